@@ -1,0 +1,199 @@
+"""Pins of the CPU MPDO oracle against the dense simulator, closed forms and
+invariants (Secs. II.C-II.D, Eqs. (1), (5)-(11), (19)-(22))."""
+import copy
+import math
+
+import numpy as np
+import pytest
+
+from oracle import channels, dense, mpdo
+from paper_2508_07610_amd import workloads as W
+
+
+def _kraus(prog):
+    return [channels.kraus_from_chi(c)[0] for c in prog.chis]
+
+
+def _lossless(n):
+    return mpdo.MPDO(n, 1 << 20, 1 << 20, 1e-15, 1e-15)
+
+
+def _ghz_prep_ops(n):
+    """H on qubit 0, then CNOT(q, q+1) compiled as RY(-pi/2)_t CZ RY(pi/2)_t."""
+    ops = [((0,), W.H)]
+    for q in range(n - 1):
+        for name, loc, U in W.cnot_compiled():
+            ops.append((tuple(q + s for s in loc), U))
+    return ops
+
+
+def _apply(sim_or_mpdo, sites, G):
+    if isinstance(sim_or_mpdo, dense.DenseSim):
+        sim_or_mpdo.apply_kraus(sites, G)
+    elif len(sites) == 1:
+        sim_or_mpdo.apply_1q(sites[0], G)
+    else:
+        sim_or_mpdo.apply_2q(sites[0], G)
+
+
+def test_untruncated_mpdo_equals_dense():
+    """Noisy RY/CZ ansatz with QPT-style channels, n = 5, one layer: the
+    lossless MPDO reproduces the dense rho entrywise."""
+    n = 5
+    prog = W.ghz_ansatz(n, 1, W.ansatz_params(n, 1, 3))
+    kr = _kraus(prog)
+    m = mpdo.run_program(prog, _lossless(n), kr)
+    sim = mpdo.run_program_dense(prog, dense.DenseSim(n), kr)
+    rho = m.to_dense()
+    assert abs(np.trace(rho) - 1) < 1e-12
+    assert np.abs(rho - sim.rho).max() < 1e-12
+    assert np.abs(rho - rho.conj().T).max() < 1e-14            # Hermitian
+    assert np.linalg.eigvalsh(rho).min() > -1e-13              # positive (Eq. (6) form)
+    for s in W.zz_strings(n) + ["XYZIX", "ZZZZZ"]:
+        assert abs(m.expect_pauli(s) - sim.expect_pauli(s)) < 1e-12
+    assert abs(m.fidelity_ghz() - sim.fidelity_pure(dense.ghz_state(n))) < 1e-12
+
+
+@pytest.mark.parametrize("n,p", [(3, 0.05), (5, 0.02), (6, 0.1)])
+def test_ghz_local_depolarizing_closed_form(n, p):
+    """GHZ_n then local depolarizing p on every qubit:
+    F = [(2-p)^n + p^n]/2^(n+1) + (1-p)^n/2,
+    purity = [(1+q)^n + (1-q)^n]/2^(n+1) + q^n/2 with q = (1-p)^2,
+    <Z_i Z_j> = (1-p)^2."""
+    dep = channels.kraus_from_chi(W.chi_from_kraus(W.kraus_depolarizing(p)))[0]
+    sim, m = dense.DenseSim(n), _lossless(n)
+    for sites, U in _ghz_prep_ops(n):
+        _apply(sim, sites, [U])
+        _apply(m, sites, [U])
+    for qb in range(n):
+        _apply(sim, (qb,), dep)
+        _apply(m, (qb,), dep)
+    F = ((2 - p) ** n + p ** n) / 2 ** (n + 1) + (1 - p) ** n / 2
+    q = (1 - p) ** 2
+    pur = ((1 + q) ** n + (1 - q) ** n) / 2 ** (n + 1) + q ** n / 2
+    assert abs(sim.fidelity_pure(dense.ghz_state(n)) - F) < 1e-14
+    assert abs(sim.purity() - pur) < 1e-14
+    assert abs(m.fidelity_ghz() - F) < 1e-13
+    for s in W.zz_strings(n):
+        assert abs(m.expect_pauli(s).real - (1 - p) ** 2) < 1e-13
+        assert abs(sim.expect_pauli(s).real - (1 - p) ** 2) < 1e-14
+    # the inner index of every site holds at most the 4 Kraus branches
+    assert max(m.inner_dims()) <= 4
+
+
+def test_amplitude_damping_on_mpdo():
+    """<Z> = 1 - 2 (1-gamma)^k after X and k amplitude-damping channels."""
+    g = 0.05
+    ad = channels.kraus_from_chi(W.chi_from_kraus(W.kraus_amplitude_damping(g)))[0]
+    m = _lossless(3)
+    m.apply_1q(1, [W.X])
+    for k in range(1, 5):
+        m.apply_1q(1, ad)
+        assert abs(m.expect_pauli("IZI").real - (1 - 2 * (1 - g) ** k)) < 1e-13
+
+
+def _qaoa_p1(edges, n, gamma, beta):
+    """Closed form of <C_uv> for p = 1 MaxCut QAOA (Wang, Hadfield, Jiang,
+    Rieffel, PRA 97, 022304): 1/2 + 1/4 sin4b sing (cos^(du-1) g + cos^(dv-1) g)
+    - 1/4 sin^2(2b) cos^(du+dv-2-2l) g (1 - cos^l 2g), l = triangles on (u,v)."""
+    adj = {i: set() for i in range(n)}
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    out = {}
+    for u, v in edges:
+        du, dv = len(adj[u]) , len(adj[v])
+        lam = len(adj[u] & adj[v])
+        g, b = gamma, beta
+        c = (0.5 + 0.25 * math.sin(4 * b) * math.sin(g) * (math.cos(g) ** (du - 1) + math.cos(g) ** (dv - 1))
+             - 0.25 * math.sin(2 * b) ** 2 * math.cos(g) ** (du + dv - 2 - 2 * lam) * (1 - math.cos(2 * g) ** lam))
+        out[(u, v)] = c
+    return out
+
+
+@pytest.mark.parametrize("n,seed", [(6, 0), (8, 1)])
+def test_qaoa_p1_closed_form(n, seed):
+    """Noiseless QAOA p = 1 through the SWAP network on a random 3-regular graph:
+    <C_uv> = (1 - <Z_u Z_v>)/2 (Eq. (20)) matches the closed form for every edge."""
+    rng = W.rng_for(100 + seed)
+    edges = W.random_3_regular(n, rng)
+    gamma, beta = 0.63, 0.27
+    prog, pos = W.qaoa_swap_network(n, edges, [gamma], [beta], noisy=False)
+    m = mpdo.run_program(prog, _lossless(n), [])
+    where = {lq: s for s, lq in enumerate(pos)}
+    want = _qaoa_p1(edges, n, gamma, beta)
+    for (u, v), c in want.items():
+        s = W.pauli_string(n, {where[u]: "Z", where[v]: "Z"})
+        got = 0.5 * (1 - m.expect_pauli(s).real)
+        assert abs(got - c) < 1e-12, (u, v, got, c)
+    # gamma = beta = 0 gives <C> = |E|/2
+    prog0, pos0 = W.qaoa_swap_network(n, edges, [0.0], [0.0], noisy=False)
+    m0 = mpdo.run_program(prog0, _lossless(n), [])
+    w0 = {lq: s for s, lq in enumerate(pos0)}
+    tot = sum(0.5 * (1 - m0.expect_pauli(W.pauli_string(n, {w0[u]: "Z", w0[v]: "Z"})).real) for u, v in edges)
+    assert abs(tot - len(edges) / 2) < 1e-12
+
+
+def _purification(m):
+    psi = np.ones((1, 1), dtype=np.complex128)
+    for T in m.T:
+        psi = np.einsum("ab,bpkr->apkr", psi, T).reshape(-1, T.shape[3])
+    return psi[:, 0]
+
+
+def test_bond_truncation_eckart_young():
+    """Eq. (10): truncating one bond of a state in canonical form to rank r
+    changes the purification by exactly the discarded weight
+    (||Psi - sqrt(kept) Psi_r||^2 = 1 - kept)."""
+    n = 4
+    prog = W.ghz_ansatz(n, 1, W.ansatz_params(n, 1, 9))
+    kr = _kraus(prog)
+    m0 = mpdo.run_program(prog, _lossless(n), kr)
+    U = W.CZ @ np.kron(W.ry(0.4), W.rx(1.1))
+    m1 = copy.deepcopy(m0)
+    m1.apply_2q(1, [U])
+    full = m1.lam[1].shape[0]
+    assert full >= 3
+    m2 = copy.deepcopy(m0)
+    m2.chi_max = full - 2
+    m2.apply_2q(1, [U])
+    s = m1.lam[1]
+    kept = float(np.sum(s[: full - 2] ** 2) / np.sum(s ** 2))
+    psi1, psi2 = _purification(m1), _purification(m2)
+    assert abs(np.vdot(psi1, psi1) - 1) < 1e-12
+    err = np.linalg.norm(psi1 - math.sqrt(kept) * psi2) ** 2
+    assert abs(err - (1 - kept)) < 1e-12
+    assert abs(m2.discarded - (1 - kept)) < 1e-12
+
+
+def test_truncate_sweep_lossless_and_canonical():
+    """The QR / SVD sweep at no truncation leaves rho unchanged and produces
+    right-orthonormal tensors whose bond weights are the Schmidt values."""
+    n = 5
+    prog = W.ghz_ansatz(n, 1, W.ansatz_params(n, 1, 4))
+    kr = _kraus(prog)
+    m = mpdo.run_program(prog, _lossless(n), kr)
+    before = m.to_dense()
+    d = m.truncate_sweep()
+    assert d < 1e-14
+    assert np.abs(m.to_dense() - before).max() < 1e-12
+    for i in range(1, n):
+        T = m.T[i]
+        M = T.reshape(T.shape[0], -1)
+        assert np.abs(M @ M.conj().T - np.eye(T.shape[0])).max() < 1e-12
+    psi = _purification(m)
+    # Schmidt values of the purification across bond 1|2 are lambda_1
+    left = 2 * m.T[0].shape[2] * 2 * m.T[1].shape[2]
+    sv = np.linalg.svd(psi.reshape(left, -1), compute_uv=False)
+    r = m.lam[1].shape[0]
+    assert np.abs(sv[:r] - m.lam[1]).max() < 1e-12
+    assert abs(np.sum(m.lam[1] ** 2) - 1) < 1e-12
+
+
+def test_rank_selection_rule():
+    eta = np.array([0.5, 0.3, 0.15, 0.04, 0.01])
+    assert mpdo.select_rank(eta, 10, 0.0) == 5
+    assert mpdo.select_rank(eta, 10, 0.01) == 4
+    assert mpdo.select_rank(eta, 10, 0.05) == 3
+    assert mpdo.select_rank(eta, 2, 0.0) == 2
+    assert mpdo.select_rank(np.array([1.0, -1e-18]), 5, 1e-14) == 1
