@@ -1,0 +1,210 @@
+/*
+ * libmpdo -- QPT-assisted matrix product density operator simulator for
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operations follow the problem statement of arXiv 2508.07610:
+ *   - a noisy n-qubit state as a matrix product density operator (MPDO):
+ *     site tensors T[l, p, n, r] with physical p, noise/inner n and bond
+ *     indices l, r (Sec. II.C, Eq. (5)); rho is the sum over the inner
+ *     indices of the tensor product with the conjugate copy (Eqs. (6)-(7));
+ *   - process-tomography channels given as a Pauli chi-matrix, converted to
+ *     Kraus operators through the Choi matrix (Sec. III, Eqs. (12)-(16));
+ *   - noisy gates K_i = N_i K~ contracted into the state, the new noise
+ *     index joining a site's inner index (Eq. (8), Fig. fig_mpdoSingle);
+ *   - truncation of the inner index (SVD, Eqs. (9)-(11)) and of the bonds
+ *     (canonical form, then SVD; Sec. II.D);
+ *   - observables from transfer-matrix contractions (Eqs. (6)-(7)), the
+ *     MaxCut objective (Eq. (20)) and state fidelities.
+ *
+ * Conventions (all entry points):
+ *   - Complex numbers are interleaved (re, im) doubles on the host.
+ *   - Matrices are row-major.  A q-qubit operator acts on (s_1 ... s_q) with
+ *     s_1 the lowest site and the most significant index bit; qubit 0 is
+ *     the leftmost site.
+ *   - Pauli order is I, X, Y, Z; the q-qubit Pauli index is
+ *     m = sum_t m_t 4^(q-1-t), t = 0 the lowest site.
+ *   - Host buffers passed in are owned by the caller and only read during
+ *     the call.  Handles own their device memory (hipMalloc), released by
+ *     the matching destroy call.
+ *   - Work is enqueued on the HIP stream given at creation (NULL = the
+ *     default stream).  Calls that return host values synchronise that
+ *     stream; others may return before the GPU work finishes.
+ *   - A handle is not thread-safe.  On error a call returns a status other
+ *     than MPDO_OK, leaves the state as it was before the call (except after
+ *     MPDO_EDEVICE, which is sticky), and mpdo_last_error() describes it.
+ */
+#ifndef MPDO_H
+#define MPDO_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPDO_OK = 0,
+  MPDO_EINVAL = 1,        /* bad argument: sites, sizes, null pointers       */
+  MPDO_ENOTCPTP = 2,      /* chi does not describe a trace-preserving map    */
+  MPDO_ENOMEM = 3,        /* device allocation failed                        */
+  MPDO_EDEVICE = 4,       /* a HIP call failed; the handle is unusable       */
+  MPDO_ENOTCONV = 5,      /* an eigensolver did not reach its tolerance      */
+  MPDO_EUNSUPPORTED = 6   /* valid but not implemented in this build         */
+} mpdo_status;
+
+typedef enum {
+  MPDO_C128 = 0,          /* complex128 everywhere                            */
+  MPDO_C64_MIXED = 1      /* complex64 tensors and contractions (FP32 MFMA);
+                             Gram matrices, eigensolvers, truncation and
+                             normalisation in FP64                            */
+} mpdo_prec;
+
+typedef struct {
+  int32_t n;              /* qubits (sites), 1 <= n <= 64                     */
+  int32_t chi_max;        /* bond dimension limit chi (Sec. II.D), >= 1       */
+  int32_t kappa_max;      /* inner (noise) dimension limit kappa (Eq. (10))   */
+  int32_t max_kraus;      /* largest Kraus count of any channel that will be
+                             applied (sizes the workspace), >= 1              */
+  double svd_cutoff;      /* bond truncation: drop the smallest singular
+                             values whose summed squares are <= cutoff times
+                             the total, then cap at chi_max                   */
+  double kappa_cutoff;    /* same rule for the inner index                    */
+  int32_t prec;           /* mpdo_prec                                        */
+} mpdo_config;
+
+typedef struct mpdo_s* mpdo_t;
+typedef struct mpdo_chan_s* mpdo_chan_t;
+
+/* Last error message of the calling thread ("" if none). */
+const char* mpdo_last_error(void);
+
+/* Library version string. */
+const char* mpdo_version(void);
+
+/* Create the state rho = |0...0><0...0| for cfg->n qubits on the current HIP
+ * device.  `hip_stream` is a hipStream_t (NULL = default stream).
+ * Returns EINVAL for invalid sizes, ENOMEM if the tensors do not fit. */
+mpdo_status mpdo_create(const mpdo_config* cfg, void* hip_stream, mpdo_t* out);
+
+/* Release a state and its device memory.  NULL is accepted. */
+mpdo_status mpdo_destroy(mpdo_t h);
+
+/* Convert a process matrix to Kraus operators on the GPU (Sec. III):
+ * Lambda = sum_mn chi_mn |sigma_m>><<sigma_n| (Eqs. (13)-(14)), Lambda =
+ * sum_i eta_i |psi_i><psi_i| (Eq. (15)), K_i = sqrt(eta_i) unvec(psi_i)
+ * (Eq. (16)), eigenvalues in descending order, negative ones clipped,
+ * operators of weight eta_i / sum eta below `eps` dropped (Sec. III,
+ * pruning "by descending eigenvalue magnitude").
+ *   chi: host, 4^q x 4^q complex, interleaved, row-major, q in {1, 2, 3}.
+ *   Returns ENOTCPTP if sum_i K_i^dag K_i differs from the identity by more
+ *   than 1e-8 (before pruning), EINVAL for bad q or non-Hermitian chi. */
+mpdo_status mpdo_channel_from_chi(const double* chi, int32_t q, double eps,
+                                  void* hip_stream, mpdo_chan_t* out);
+
+/* Number of Kraus operators and qubits of a channel; optionally copy the
+ * operators to `kraus_out` (host, nkraus x 2^q x 2^q complex, may be NULL). */
+mpdo_status mpdo_channel_info(mpdo_chan_t ch, int32_t* q, int32_t* nkraus,
+                              double* kraus_out);
+
+mpdo_status mpdo_channel_destroy(mpdo_chan_t ch);
+
+/* Apply the ideal gate U (host, 2^q x 2^q complex) on `sites` (q ascending
+ * adjacent sites, q in {1, 2}).  A 2-qubit gate re-splits the pair by SVD
+ * with bond truncation. */
+mpdo_status mpdo_apply_gate(mpdo_t h, const int32_t* sites, int32_t q, const double* U);
+
+/* Apply the noisy gate "U then channel": operators G_i = K_i U (Eq. (8));
+ * U may be NULL (identity).  The Kraus index joins the inner index of the
+ * lowest site (q <= 2) or the middle site (q = 3); that inner index is then
+ * truncated (Eqs. (9)-(11)) and the touched bonds are re-split by SVD with
+ * truncation.  q in {1, 2, 3}; sites ascending and adjacent. */
+mpdo_status mpdo_apply_channel(mpdo_t h, const int32_t* sites, int32_t q,
+                               const double* U, mpdo_chan_t ch);
+
+/* Finish all queued gates (gates on disjoint sites are grouped into one
+ * launch sequence; this call forces the queue out). */
+mpdo_status mpdo_flush(mpdo_t h);
+
+/* The truncation sweep of Sec. II.D: orthonormalise from left to right,
+ * then SVD from right to left truncating every bond to chi_max with the
+ * cutoff rule, then truncate every inner index to kappa_max.  Writes the
+ * summed discarded weight to *discarded (may be NULL). */
+mpdo_status mpdo_truncate(mpdo_t h, int32_t chi_max, int32_t kappa_max,
+                          double cutoff, double* discarded);
+
+/* Tr(P rho) / Tr(rho) for a Pauli string of length n over "IXYZ". */
+mpdo_status mpdo_expect(mpdo_t h, const char* pauli, double* re, double* im);
+
+/* Tr(O rho) / Tr(rho) for a batch of product operators:
+ * ops: host, nops x n x 2 x 2 complex (operator k on site i at
+ * ops + ((k n + i) 4) 2 doubles); out: host, nops complex. */
+mpdo_status mpdo_expect_products(mpdo_t h, const double* ops, int32_t nops, double* out);
+
+/* <GHZ| rho |GHZ> / Tr rho with |GHZ> = (|0..0> + |1..1>)/sqrt(2). */
+mpdo_status mpdo_fidelity_ghz(mpdo_t h, double* f);
+
+/* Tr(rho) (after the library's normalisation it is 1 up to truncation). */
+mpdo_status mpdo_trace(mpdo_t h, double* tr);
+
+/* Current dimensions: bonds (n-1 ints, may be NULL), inner (n ints, may be
+ * NULL), and the summed discarded weight of all truncations (may be NULL). */
+mpdo_status mpdo_dims(mpdo_t h, int32_t* bonds, int32_t* inner, double* discarded);
+
+/* Bond weights lambda of bond b (between sites b and b+1): writes up to
+ * `cap` doubles and the count to *len. */
+mpdo_status mpdo_bond_weights(mpdo_t h, int32_t b, double* out, int32_t cap, int32_t* len);
+
+/* ---------------------------------------------------------------------------
+ * Batched execution: many independent instances (parameter points, graphs of
+ * different sizes) advanced together, every sublayer of every instance in
+ * one launch sequence, the whole run captured in one HIP graph.
+ * ------------------------------------------------------------------------- */
+
+typedef enum {
+  MPDO_G_FIXED = 0,   /* U given in the program                              */
+  MPDO_G_RX = 1,      /* exp(-i a X / 2), a = scale * param                  */
+  MPDO_G_RY = 2,
+  MPDO_G_RZ = 3,
+  MPDO_G_ZZPHASE = 4, /* exp(-i a (1 - Z Z) / 2) (Eq. (21) cost term)        */
+  MPDO_G_SWAPZZ = 5   /* SWAP . exp(-i a (1 - Z Z) / 2)                      */
+} mpdo_gate_kind;
+
+typedef struct {
+  int32_t q;            /* 1 or 2                                              */
+  int32_t site;         /* lowest site                                         */
+  int32_t kind;         /* mpdo_gate_kind                                      */
+  int32_t param;        /* index into the instance's parameter row, or -1      */
+  double scale;         /* angle = scale * param value                         */
+  int32_t chan;         /* channel slot (index into `chans`), or -1            */
+  int32_t fixed;        /* for MPDO_G_FIXED: index into `fixed_u`              */
+} mpdo_op;
+
+typedef struct {
+  int32_t n;            /* qubits of this instance                            */
+  int32_t nops;
+  const mpdo_op* ops;   /* host                                                */
+  int32_t nobs;         /* observables: product operators                     */
+  const double* obs;    /* host, nobs x n x 2 x 2 complex                      */
+} mpdo_program;
+
+/* Run `ninst` programs to completion and write, for instance b, its nobs
+ * expectation values Tr(O rho)/Tr(rho) as complex doubles to
+ * out_dev + 2 * (obs_offset[b] + k), where obs_offset is the prefix sum of
+ * nobs.  params_dev: device doubles, instance b's parameter row at
+ * params_dev + b * param_stride.  fixed_u: host, nfixed 4x4 complex
+ * (2-qubit) or 2x2 (1-qubit, stored in the top-left of a 4x4 slot).
+ * chans: channel handles.  cfg: chi_max, kappa_max, cutoffs, precision for
+ * all instances (cfg->n ignored).  Enqueued on hip_stream; the call returns
+ * after enqueueing (out_dev is stream-ordered).  `use_graph` != 0 captures
+ * the run into a HIP graph and launches it once. */
+mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
+                           const double* params_dev, int32_t param_stride,
+                           const double* fixed_u, int32_t nfixed,
+                           const mpdo_chan_t* chans, int32_t nchans,
+                           double* out_dev, int32_t use_graph, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPDO_H */

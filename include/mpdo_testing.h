@@ -1,0 +1,40 @@
+/*
+ * libmpdo kernel-level entry points for unit tests (C ABI).
+ *
+ * These run one of the library's internal kernels on host data so that a
+ * test can compare it with a reference on the CPU.  All buffers are host
+ * memory owned by the caller; complex values are interleaved (re, im)
+ * doubles; matrices are row-major.  Each call allocates, copies, runs on the
+ * default stream, copies back and synchronises.  Errors: MPDO_EINVAL for bad
+ * sizes or modes, MPDO_EDEVICE / MPDO_ENOMEM for HIP failures.
+ */
+#ifndef MPDO_TESTING_H
+#define MPDO_TESTING_H
+
+#include "mpdo.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha * op(A) op(B) with the batched MFMA GEMM.
+ *   prec: 0 = complex128 on FP64 MFMA, 1 = complex64 on FP32 MFMA,
+ *         2 = complex64 inputs with FP64 MFMA and complex128 output.
+ *   opA, opB: 0 = N, 1 = T, 2 = conj, 3 = conj-transpose (element (i, k) of
+ *   op(A) is A[i*lda+k], A[k*lda+i], conj(A[i*lda+k]), conj(A[k*lda+i])).
+ *   A holds rowsA x lda values, B rowsB x ldb; C is M x N (leading dim N).
+ *   w (may be NULL): real weights, op(A)(i, k) is multiplied by w[k / wdiv].
+ *   splits: split-K count (1..64). */
+mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
+                           const double* A, int32_t rowsA, int32_t lda, const double* B, int32_t rowsB,
+                           int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha, double* C);
+
+/* Hermitian eigendecomposition of A (n x n, 1 <= n <= 512) with the Jacobi
+ * kernel: evals descending (n doubles), evecs as columns (n x n complex).
+ * *sweeps receives the sweep count (negative if not converged). */
+mpdo_status mpdo_test_eigh(int32_t n, const double* A, double* evals, double* evecs, int32_t* sweeps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPDO_TESTING_H */

@@ -48,9 +48,18 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 
+TIE_REL = 1e-9     # eigenvalues closer than this (relative) form one multiplet
+TIE_FLOOR = 1e-11  # ... unless they carry less than this fraction of the weight
+
+
 def select_rank(eta: np.ndarray, max_dim: int, cutoff: float) -> int:
     """Smallest r >= 1 with sum_{i>=r} eta_i <= cutoff * W, capped at max_dim.
-    eta is in descending order; negative round-off values count as zero."""
+    eta is in descending order; negative round-off values count as zero.
+
+    A degenerate multiplet straddling the cut is dropped as a whole (r is
+    lowered until eta_{r-1} and eta_r differ), so the kept subspace -- and
+    with it the truncated state -- is unique; multiplets below TIE_FLOOR of
+    the total weight are left as they fall."""
     e = np.clip(np.asarray(eta, dtype=np.float64), 0.0, None)
     W = e.sum()
     if W <= 0:
@@ -62,7 +71,13 @@ def select_rank(eta: np.ndarray, max_dim: int, cutoff: float) -> int:
         if tail[cand] <= cutoff * W:
             r = cand
             break
-    return int(max(1, min(r, max_dim)))
+    r = int(max(1, min(r, max_dim)))
+    r0 = r
+    while 1 < r < len(e) and e[r - 1] > TIE_FLOOR * W and e[r - 1] - e[r] <= TIE_REL * e[r - 1]:
+        r -= 1
+    if r == 1 and len(e) > 1 and e[0] - e[1] <= TIE_REL * e[0]:
+        r = r0   # the leading multiplet itself straddles the cut: keep the plain rank
+    return r
 
 
 def _eigh_desc(gram: np.ndarray):

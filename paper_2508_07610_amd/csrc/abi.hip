@@ -1,0 +1,512 @@
+// C ABI of libmpdo (declared in include/mpdo.h).  Argument checking, the
+// gate queue that groups gates on disjoint sites into sublayers, and the
+// translation of host inputs into device work.  No exception crosses the ABI.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mpdo.h"
+#include "engine.h"
+#include "kernels.h"
+#include "ops.h"
+
+using namespace mpdo;
+
+namespace {
+thread_local std::string g_err;
+
+mpdo_status fail(int st, const std::string& msg) {
+  g_err = msg;
+  return (mpdo_status)st;
+}
+
+struct AnyEngine {
+  std::unique_ptr<Engine<double>> d;
+  std::unique_ptr<Engine<float>> f;
+  void run_sublayer(const std::vector<GateOp>& ops) { d ? d->run_sublayer(ops) : f->run_sublayer(ops); }
+  void expect(const std::vector<int>& inst, const std::vector<const double*>& ops, double* out, bool raw = false) {
+    d ? d->expect(inst, ops, out, raw) : f->expect(inst, ops, out, raw);
+  }
+  void dims(int b, std::vector<int>& bo, std::vector<int>& in, double& disc) {
+    d ? d->dims(b, bo, in, disc) : f->dims(b, bo, in, disc);
+  }
+  std::vector<double> bond_weights(int b, int bond) { return d ? d->bond_weights(b, bond) : f->bond_weights(b, bond); }
+  double truncate_sweep(int b, int c, int k, double cut) {
+    return d ? d->truncate_sweep(b, c, k, cut) : f->truncate_sweep(b, c, k, cut);
+  }
+};
+
+Config make_config(const mpdo_config* cfg) {
+  Config c;
+  c.chi_max = cfg->chi_max;
+  c.kap_max = cfg->kappa_max;
+  c.mmax = cfg->max_kraus;
+  c.svd_cut = cfg->svd_cutoff;
+  c.kap_cut = cfg->kappa_cutoff;
+  return c;
+}
+
+const char* check_config(const mpdo_config* cfg, bool need_n) {
+  if (!cfg) return "null config";
+  if (need_n && (cfg->n < 1 || cfg->n > 64)) return "n must be in [1, 64]";
+  if (cfg->chi_max < 1 || cfg->chi_max > 128) return "chi_max must be in [1, 128]";
+  if (cfg->kappa_max < 1 || cfg->kappa_max > 64) return "kappa_max must be in [1, 64]";
+  if (cfg->max_kraus < 1 || cfg->max_kraus > 64) return "max_kraus must be in [1, 64]";
+  if ((long long)cfg->kappa_max * cfg->max_kraus > 512) return "kappa_max * max_kraus must be <= 512";
+  if (!(cfg->svd_cutoff >= 0 && cfg->svd_cutoff < 1)) return "svd_cutoff must be in [0, 1)";
+  if (!(cfg->kappa_cutoff >= 0 && cfg->kappa_cutoff < 1)) return "kappa_cutoff must be in [0, 1)";
+  if (cfg->prec != MPDO_C128 && cfg->prec != MPDO_C64_MIXED) return "prec must be MPDO_C128 or MPDO_C64_MIXED";
+  return nullptr;
+}
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                     \
+  }                                                                   \
+  catch (const Error& e) {                                            \
+    return fail(e.status, e.msg);                                     \
+  }                                                                   \
+  catch (const std::exception& e) {                                   \
+    return fail(MPDO_EDEVICE, std::string("internal error: ") + e.what()); \
+  }                                                                   \
+  catch (...) {                                                       \
+    return fail(MPDO_EDEVICE, "internal error");                      \
+  }
+}  // namespace
+
+struct mpdo_s {
+  mpdo_config cfg;
+  hipStream_t st = nullptr;
+  AnyEngine eng;
+  std::vector<GateOp> pending;
+  std::vector<char> busy;
+  bool dead = false;
+};
+
+struct mpdo_chan_s {
+  Channel ch;
+};
+
+static mpdo_status flush_queue(mpdo_t h) {
+  if (h->pending.empty()) return MPDO_OK;
+  std::vector<GateOp> ops;
+  ops.swap(h->pending);
+  std::fill(h->busy.begin(), h->busy.end(), 0);
+  h->eng.run_sublayer(ops);
+  return MPDO_OK;
+}
+
+extern "C" {
+
+const char* mpdo_last_error(void) { return g_err.c_str(); }
+
+const char* mpdo_version(void) { return "libmpdo 0.1 (gfx950)"; }
+
+mpdo_status mpdo_create(const mpdo_config* cfg, void* hip_stream, mpdo_t* out) {
+  if (!out) return fail(MPDO_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (const char* why = check_config(cfg, true)) return fail(MPDO_EINVAL, why);
+  GUARD_BEGIN
+  std::unique_ptr<mpdo_s> h(new mpdo_s());
+  h->cfg = *cfg;
+  h->st = reinterpret_cast<hipStream_t>(hip_stream);
+  const Config c = make_config(cfg);
+  std::vector<int> nq(1, cfg->n);
+  if (cfg->prec == MPDO_C128) h->eng.d.reset(new Engine<double>(c, nq, h->st));
+  else h->eng.f.reset(new Engine<float>(c, nq, h->st));
+  h->busy.assign(cfg->n, 0);
+  *out = h.release();
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_destroy(mpdo_t h) {
+  if (!h) return MPDO_OK;
+  GUARD_BEGIN
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  else (void)hipDeviceSynchronize();
+  delete h;
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_channel_from_chi(const double* chi, int32_t q, double eps, void* hip_stream, mpdo_chan_t* out) {
+  if (!out) return fail(MPDO_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!chi) return fail(MPDO_EINVAL, "null chi");
+  if (q < 1 || q > 3) return fail(MPDO_EINVAL, "q must be 1, 2 or 3");
+  if (!(eps >= 0 && eps < 1)) return fail(MPDO_EINVAL, "eps must be in [0, 1)");
+  const int d2 = 1 << (2 * q);
+  double scale = 0;
+  for (int e = 0; e < d2 * d2; ++e) {
+    if (!std::isfinite(chi[2 * e]) || !std::isfinite(chi[2 * e + 1])) return fail(MPDO_EINVAL, "chi is not finite");
+    scale = std::max(scale, std::hypot(chi[2 * e], chi[2 * e + 1]));
+  }
+  for (int a = 0; a < d2; ++a)
+    for (int b = 0; b < d2; ++b) {
+      const double dr = chi[2 * (a * d2 + b)] - chi[2 * (b * d2 + a)];
+      const double di = chi[2 * (a * d2 + b) + 1] + chi[2 * (b * d2 + a) + 1];
+      if (std::hypot(dr, di) > 1e-10 * std::max(1.0, scale)) return fail(MPDO_EINVAL, "chi is not Hermitian");
+    }
+  GUARD_BEGIN
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  std::unique_ptr<mpdo_chan_s> c(new mpdo_chan_s());
+  DevBuf dchi, dlam, dev, dvec, dwork, dinfo, ddesc, dkr;
+  dchi.alloc(sizeof(double) * 2 * d2 * d2);
+  dlam.alloc(sizeof(double) * 2 * d2 * d2);
+  dev.alloc(sizeof(double) * d2);
+  dvec.alloc(sizeof(double) * 2 * d2 * d2);
+  dwork.alloc(sizeof(double) * 2 * d2 * d2);
+  dinfo.alloc(sizeof(double) * 4);
+  dkr.alloc(sizeof(double) * 2 * d2 * d2);
+  ddesc.alloc(sizeof(EigDesc));
+  hip_check(hipMemcpyAsync(dchi.p, chi, sizeof(double) * 2 * d2 * d2, hipMemcpyHostToDevice, st), "upload chi");
+  EigDesc ed;
+  std::memset(&ed, 0, sizeof(ed));
+  ed.a = dlam.as<double>(); ed.lda = d2; ed.n = d2; ed.evals = dev.as<double>(); ed.evecs = dvec.as<double>();
+  ed.work = dwork.as<double>(); ed.active = 1;
+  hip_check(hipMemcpyAsync(ddesc.p, &ed, sizeof(ed), hipMemcpyHostToDevice, st), "upload desc");
+  launch_choi(dchi.as<double>(), q, dlam.as<double>(), st);
+  DevBuf dsw;
+  dsw.alloc(sizeof(int));
+  launch_eigh(ddesc.as<EigDesc>(), 1, d2, dsw.as<int>(), st);
+  launch_kraus_extract(dev.as<double>(), dvec.as<double>(), q, eps, 1e-13, dkr.as<double>(), dinfo.as<double>(), st);
+  double info[4];
+  int sweeps = 0;
+  hip_check(hipMemcpyAsync(info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, st), "info");
+  hip_check(hipMemcpyAsync(&sweeps, dsw.p, sizeof(int), hipMemcpyDeviceToHost, st), "info");
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (sweeps < 0) return fail(MPDO_ENOTCONV, "Choi eigensolver did not converge");
+  if (!(info[1] <= 1e-8)) return fail(MPDO_ENOTCPTP, "sum K^dag K differs from I by " + std::to_string(info[1]));
+  const int m = (int)info[0];
+  if (m < 1) return fail(MPDO_ENOTCPTP, "no Kraus operator kept");
+  const int d = 1 << q;
+  c->ch.q = q;
+  c->ch.m = m;
+  c->ch.completeness_err = info[1];
+  c->ch.min_eig = info[2];
+  c->ch.kraus.alloc(sizeof(double) * 2 * m * d * d);
+  hip_check(hipMemcpyAsync(c->ch.kraus.p, dkr.p, sizeof(double) * 2 * m * d * d, hipMemcpyDeviceToDevice, st), "kraus");
+  c->ch.host_kraus.resize((size_t)2 * m * d * d);
+  hip_check(hipMemcpyAsync(c->ch.host_kraus.data(), dkr.p, sizeof(double) * 2 * m * d * d, hipMemcpyDeviceToHost, st),
+            "kraus");
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  *out = c.release();
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_channel_info(mpdo_chan_t ch, int32_t* q, int32_t* nkraus, double* kraus_out) {
+  if (!ch) return fail(MPDO_EINVAL, "null channel");
+  if (q) *q = ch->ch.q;
+  if (nkraus) *nkraus = ch->ch.m;
+  if (kraus_out) std::memcpy(kraus_out, ch->ch.host_kraus.data(), ch->ch.host_kraus.size() * sizeof(double));
+  return MPDO_OK;
+}
+
+mpdo_status mpdo_channel_destroy(mpdo_chan_t ch) {
+  GUARD_BEGIN
+  if (ch) {
+    (void)hipDeviceSynchronize();
+    delete ch;
+  }
+  return MPDO_OK;
+  GUARD_END
+}
+
+static mpdo_status enqueue(mpdo_t h, const int32_t* sites, int32_t q, const double* U, mpdo_chan_t ch) {
+  if (!h) return fail(MPDO_EINVAL, "null handle");
+  if (h->dead) return fail(MPDO_EDEVICE, "handle is unusable after a device error");
+  if (!sites) return fail(MPDO_EINVAL, "null sites");
+  if (q < 1 || q > 3) return fail(MPDO_EINVAL, "q must be 1, 2 or 3");
+  const int n = h->cfg.n;
+  for (int t = 0; t < q; ++t) {
+    if (sites[t] < 0 || sites[t] >= n) return fail(MPDO_EINVAL, "site out of range");
+    if (t > 0 && sites[t] != sites[t - 1] + 1) return fail(MPDO_EINVAL, "sites must be ascending and adjacent");
+  }
+  if (ch && ch->ch.q != q) return fail(MPDO_EINVAL, "channel arity differs from the number of sites");
+  if (ch && ch->ch.m > h->cfg.max_kraus) return fail(MPDO_EINVAL, "channel has more Kraus operators than max_kraus");
+  if (q == 3) return fail(MPDO_EUNSUPPORTED, "3-qubit channels are not available in this build");
+  const int d = 1 << q;
+  if (U) {
+    for (int e = 0; e < 2 * d * d; ++e)
+      if (!std::isfinite(U[e])) return fail(MPDO_EINVAL, "U is not finite");
+  }
+  GUARD_BEGIN
+  for (int t = 0; t < q; ++t)
+    if (h->busy[sites[t]]) {
+      flush_queue(h);
+      break;
+    }
+  GateOp g;
+  g.inst = 0;
+  g.site = sites[0];
+  g.q = q;
+  g.kind = GK_FIXED;
+  g.ch = ch ? &ch->ch : nullptr;
+  if (U) {
+    std::memcpy(g.uhost, U, sizeof(double) * 2 * d * d);
+    g.has_u = true;
+  }
+  h->pending.push_back(g);
+  for (int t = 0; t < q; ++t) h->busy[sites[t]] = 1;
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_apply_gate(mpdo_t h, const int32_t* sites, int32_t q, const double* U) {
+  if (!U) return fail(MPDO_EINVAL, "null U");
+  if (q > 2) return fail(MPDO_EINVAL, "ideal gates act on 1 or 2 sites");
+  return enqueue(h, sites, q, U, nullptr);
+}
+
+mpdo_status mpdo_apply_channel(mpdo_t h, const int32_t* sites, int32_t q, const double* U, mpdo_chan_t ch) {
+  if (!ch) return fail(MPDO_EINVAL, "null channel");
+  return enqueue(h, sites, q, U, ch);
+}
+
+mpdo_status mpdo_flush(mpdo_t h) {
+  if (!h) return fail(MPDO_EINVAL, "null handle");
+  GUARD_BEGIN
+  return flush_queue(h);
+  GUARD_END
+}
+
+mpdo_status mpdo_truncate(mpdo_t h, int32_t chi_max, int32_t kappa_max, double cutoff, double* discarded) {
+  if (!h) return fail(MPDO_EINVAL, "null handle");
+  if (chi_max < 1 || chi_max > h->cfg.chi_max) return fail(MPDO_EINVAL, "chi_max out of range");
+  if (kappa_max < 1 || kappa_max > h->cfg.kappa_max) return fail(MPDO_EINVAL, "kappa_max out of range");
+  if (!(cutoff >= 0 && cutoff < 1)) return fail(MPDO_EINVAL, "cutoff must be in [0, 1)");
+  GUARD_BEGIN
+  flush_queue(h);
+  const double d = h->eng.truncate_sweep(0, chi_max, kappa_max, cutoff);
+  if (discarded) *discarded = d;
+  return MPDO_OK;
+  GUARD_END
+}
+
+static mpdo_status expect_ops(mpdo_t h, const std::vector<std::vector<double>>& ops, double* out, bool raw) {
+  flush_queue(h);
+  std::vector<int> inst(ops.size(), 0);
+  std::vector<const double*> p;
+  for (auto& o : ops) p.push_back(o.data());
+  DevBuf res;
+  res.alloc(sizeof(double) * 2 * ops.size());
+  h->eng.expect(inst, p, res.as<double>(), raw);
+  hip_check(hipMemcpyAsync(out, res.p, sizeof(double) * 2 * ops.size(), hipMemcpyDeviceToHost, h->st), "result");
+  hip_check(hipStreamSynchronize(h->st), "hipStreamSynchronize");
+  return MPDO_OK;
+}
+
+static void pauli2x2(char c, double* o) {
+  const double I[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+  const double X[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+  const double Y[8] = {0, 0, 0, -1, 0, 1, 0, 0};
+  const double Z[8] = {1, 0, 0, 0, 0, 0, -1, 0};
+  const double* s = c == 'X' ? X : c == 'Y' ? Y : c == 'Z' ? Z : I;
+  std::memcpy(o, s, sizeof(I));
+}
+
+mpdo_status mpdo_expect(mpdo_t h, const char* pauli, double* re, double* im) {
+  if (!h || !pauli) return fail(MPDO_EINVAL, "null argument");
+  const int n = h->cfg.n;
+  if ((int)std::strlen(pauli) != n) return fail(MPDO_EINVAL, "Pauli string length differs from n");
+  for (int i = 0; i < n; ++i)
+    if (!std::strchr("IXYZ", pauli[i]) || pauli[i] == 0) return fail(MPDO_EINVAL, "Pauli string must use IXYZ");
+  GUARD_BEGIN
+  std::vector<std::vector<double>> ops(1, std::vector<double>(8 * n));
+  for (int i = 0; i < n; ++i) pauli2x2(pauli[i], ops[0].data() + 8 * i);
+  double out[2];
+  expect_ops(h, ops, out, false);
+  if (re) *re = out[0];
+  if (im) *im = out[1];
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_expect_products(mpdo_t h, const double* ops, int32_t nops, double* out) {
+  if (!h || !ops || !out) return fail(MPDO_EINVAL, "null argument");
+  if (nops < 1) return fail(MPDO_EINVAL, "nops must be >= 1");
+  const int n = h->cfg.n;
+  GUARD_BEGIN
+  std::vector<std::vector<double>> v(nops, std::vector<double>(8 * n));
+  for (int k = 0; k < nops; ++k) std::memcpy(v[k].data(), ops + (size_t)8 * n * k, sizeof(double) * 8 * n);
+  return expect_ops(h, v, out, false);
+  GUARD_END
+}
+
+mpdo_status mpdo_fidelity_ghz(mpdo_t h, double* f) {
+  if (!h || !f) return fail(MPDO_EINVAL, "null argument");
+  const int n = h->cfg.n;
+  GUARD_BEGIN
+  // Tr(|0..0><0..0| rho), Tr(|1..1><1..1| rho), Tr(|1..1><0..0| rho) = rho_{0..0,1..1}
+  const double P0[8] = {1, 0, 0, 0, 0, 0, 0, 0}, P1[8] = {0, 0, 0, 0, 0, 0, 1, 0}, UP[8] = {0, 0, 0, 0, 1, 0, 0, 0};
+  std::vector<std::vector<double>> ops(3, std::vector<double>(8 * n));
+  for (int i = 0; i < n; ++i) {
+    std::memcpy(ops[0].data() + 8 * i, P0, sizeof(P0));
+    std::memcpy(ops[1].data() + 8 * i, P1, sizeof(P1));
+    std::memcpy(ops[2].data() + 8 * i, UP, sizeof(UP));
+  }
+  double out[6];
+  expect_ops(h, ops, out, false);
+  *f = 0.5 * (out[0] + out[2] + 2 * out[4]);
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_trace(mpdo_t h, double* tr) {
+  if (!h || !tr) return fail(MPDO_EINVAL, "null argument");
+  const int n = h->cfg.n;
+  GUARD_BEGIN
+  std::vector<std::vector<double>> ops(1, std::vector<double>(8 * n));
+  for (int i = 0; i < n; ++i) pauli2x2('I', ops[0].data() + 8 * i);
+  double out[2];
+  expect_ops(h, ops, out, true);
+  *tr = out[0];
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_dims(mpdo_t h, int32_t* bonds, int32_t* inner, double* discarded) {
+  if (!h) return fail(MPDO_EINVAL, "null handle");
+  GUARD_BEGIN
+  flush_queue(h);
+  std::vector<int> b, k;
+  double d;
+  h->eng.dims(0, b, k, d);
+  if (bonds) std::memcpy(bonds, b.data(), sizeof(int) * b.size());
+  if (inner) std::memcpy(inner, k.data(), sizeof(int) * k.size());
+  if (discarded) *discarded = d;
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_bond_weights(mpdo_t h, int32_t b, double* out, int32_t cap, int32_t* len) {
+  if (!h || !out || !len) return fail(MPDO_EINVAL, "null argument");
+  if (b < 0 || b >= h->cfg.n - 1) return fail(MPDO_EINVAL, "bond out of range");
+  GUARD_BEGIN
+  flush_queue(h);
+  std::vector<double> v = h->eng.bond_weights(0, b);
+  *len = (int)v.size();
+  std::memcpy(out, v.data(), sizeof(double) * std::min<size_t>(v.size(), cap));
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_batch_run(const mpdo_config*, const mpdo_program*, int32_t, const double*, int32_t, const double*,
+                           int32_t, const mpdo_chan_t*, int32_t, double*, int32_t, void*) {
+  return fail(MPDO_EUNSUPPORTED, "mpdo_batch_run is not available yet");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// kernel-level test entry points (include/mpdo_testing.h)
+// ---------------------------------------------------------------------------
+#include "../../include/mpdo_testing.h"
+
+namespace {
+template <typename Tin> std::vector<Tin> to_prec(const double* a, size_t n) {
+  std::vector<Tin> v(n);
+  for (size_t i = 0; i < n; ++i) v[i] = (Tin)a[i];
+  return v;
+}
+}  // namespace
+
+extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
+                                      const double* A, int32_t rowsA, int32_t lda, const double* B, int32_t rowsB,
+                                      int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha,
+                                      double* C) {
+  if (prec < 0 || prec > 2 || opA < 0 || opA > 3 || opB < 0 || opB > 3) return fail(MPDO_EINVAL, "bad mode");
+  if (M < 1 || N < 1 || K < 1 || rowsA < 1 || rowsB < 1 || lda < 1 || ldb < 1 || splits < 1 || splits > 64)
+    return fail(MPDO_EINVAL, "bad size");
+  if (!A || !B || !C) return fail(MPDO_EINVAL, "null buffer");
+  if (w && wdiv < 1) return fail(MPDO_EINVAL, "bad wdiv");
+  // bounds of op(A), op(B) inside the given buffers
+  const bool at = (opA == 1 || opA == 3), bt = (opB == 1 || opB == 3);
+  if (at ? (K > rowsA || M > lda) : (M > rowsA || K > lda)) return fail(MPDO_EINVAL, "A too small");
+  if (bt ? (N > rowsB || K > ldb) : (K > rowsB || N > ldb)) return fail(MPDO_EINVAL, "B too small");
+  GUARD_BEGIN
+  hipStream_t st = nullptr;
+  const size_t na = (size_t)2 * rowsA * lda, nb = (size_t)2 * rowsB * ldb;
+  const size_t esz = prec == 0 ? 8 : 4;
+  DevBuf dA, dB, dC, dW, dD;
+  dA.alloc(na * esz);
+  dB.alloc(nb * esz);
+  const size_t outsz = prec == 1 ? 4 : 8;
+  dC.alloc((size_t)2 * M * N * splits * outsz);
+  if (prec == 0) {
+    hip_check(hipMemcpy(dA.p, A, na * 8, hipMemcpyHostToDevice), "A");
+    hip_check(hipMemcpy(dB.p, B, nb * 8, hipMemcpyHostToDevice), "B");
+  } else {
+    auto a = to_prec<float>(A, na), b = to_prec<float>(B, nb);
+    hip_check(hipMemcpy(dA.p, a.data(), na * 4, hipMemcpyHostToDevice), "A");
+    hip_check(hipMemcpy(dB.p, b.data(), nb * 4, hipMemcpyHostToDevice), "B");
+  }
+  const int nw = w ? (at ? rowsA : lda) : 0;
+  if (w) {
+    const int kmax = (K + wdiv - 1) / wdiv;
+    dW.alloc(sizeof(double) * std::max(nw, kmax));
+    hip_check(hipMemcpy(dW.p, w, sizeof(double) * kmax, hipMemcpyHostToDevice), "w");
+  }
+  GemmDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.A = dA.p; d.B = dB.p; d.C = dC.p; d.w = w ? dW.as<double>() : nullptr;
+  d.M = M; d.N = N; d.K = K; d.lda = lda; d.ldb = ldb; d.ldc = N; d.wdiv = w ? wdiv : 1;
+  d.nbatch = 1; d.splits = splits; d.sSplit = (long long)M * N; d.opA = opA; d.opB = opB; d.active = 1;
+  d.alpha = alpha;
+  dD.alloc(sizeof(GemmDesc));
+  hip_check(hipMemcpy(dD.p, &d, sizeof(d), hipMemcpyHostToDevice), "desc");
+  if (prec == 0) launch_gemm<double, double, double>(dD.as<GemmDesc>(), 1, 1, splits, M, N, st);
+  else if (prec == 1) launch_gemm<float, float, float>(dD.as<GemmDesc>(), 1, 1, splits, M, N, st);
+  else launch_gemm<float, double, double>(dD.as<GemmDesc>(), 1, 1, splits, M, N, st);
+  hip_check(hipGetLastError(), "launch");
+  hip_check(hipDeviceSynchronize(), "sync");
+  const size_t nc = (size_t)2 * M * N;
+  std::vector<double> out(nc, 0.0);
+  if (prec == 1) {
+    std::vector<float> f(nc * splits);
+    hip_check(hipMemcpy(f.data(), dC.p, f.size() * 4, hipMemcpyDeviceToHost), "C");
+    for (int s = 0; s < splits; ++s)
+      for (size_t i = 0; i < nc; ++i) out[i] += f[s * nc + i];
+  } else {
+    std::vector<double> f(nc * splits);
+    hip_check(hipMemcpy(f.data(), dC.p, f.size() * 8, hipMemcpyDeviceToHost), "C");
+    for (int s = 0; s < splits; ++s)
+      for (size_t i = 0; i < nc; ++i) out[i] += f[s * nc + i];
+  }
+  std::memcpy(C, out.data(), nc * sizeof(double));
+  return MPDO_OK;
+  GUARD_END
+}
+
+extern "C" mpdo_status mpdo_test_eigh(int32_t n, const double* A, double* evals, double* evecs, int32_t* sweeps) {
+  if (n < 1 || n > 512) return fail(MPDO_EINVAL, "n must be in [1, 512]");
+  if (!A || !evals || !evecs) return fail(MPDO_EINVAL, "null buffer");
+  GUARD_BEGIN
+  DevBuf da, de, dv, dw, dd, ds;
+  const size_t nn = (size_t)2 * n * n;
+  da.alloc(nn * 8);
+  de.alloc((size_t)n * 8);
+  dv.alloc(nn * 8);
+  dw.alloc(nn * 8);
+  ds.alloc(sizeof(int));
+  hip_check(hipMemcpy(da.p, A, nn * 8, hipMemcpyHostToDevice), "A");
+  EigDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.a = da.as<double>(); d.lda = n; d.n = n; d.evals = de.as<double>(); d.evecs = dv.as<double>();
+  d.work = dw.as<double>(); d.active = 1;
+  dd.alloc(sizeof(d));
+  hip_check(hipMemcpy(dd.p, &d, sizeof(d), hipMemcpyHostToDevice), "desc");
+  launch_eigh(dd.as<EigDesc>(), 1, n, ds.as<int>(), nullptr);
+  hip_check(hipGetLastError(), "launch");
+  hip_check(hipDeviceSynchronize(), "sync");
+  hip_check(hipMemcpy(evals, de.p, (size_t)n * 8, hipMemcpyDeviceToHost), "evals");
+  hip_check(hipMemcpy(evecs, dv.p, nn * 8, hipMemcpyDeviceToHost), "evecs");
+  int sw = 0;
+  hip_check(hipMemcpy(&sw, ds.p, sizeof(int), hipMemcpyDeviceToHost), "sweeps");
+  if (sweeps) *sweeps = sw;
+  return MPDO_OK;
+  GUARD_END
+}

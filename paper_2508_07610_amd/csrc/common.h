@@ -1,0 +1,69 @@
+// Shared device/host definitions of libmpdo (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpdo {
+
+// Interleaved complex number of real type R.
+template <typename R> struct cpx { R re, im; };
+
+template <typename R> __host__ __device__ inline cpx<R> mk(R a, R b) { cpx<R> z; z.re = a; z.im = b; return z; }
+template <typename R> __host__ __device__ inline cpx<R> operator+(cpx<R> a, cpx<R> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename R> __host__ __device__ inline cpx<R> operator-(cpx<R> a, cpx<R> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename R> __host__ __device__ inline cpx<R> operator*(cpx<R> a, cpx<R> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R> __host__ __device__ inline cpx<R> operator*(R s, cpx<R> a) { return mk(s * a.re, s * a.im); }
+template <typename R> __host__ __device__ inline cpx<R> cconj(cpx<R> a) { return mk(a.re, -a.im); }
+template <typename R> __host__ __device__ inline R cabs2(cpx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// Operand modes of the batched GEMM: element (i, k) of op(A) is
+//   N: A[i*ld + k]   T: A[k*ld + i]   C: conj(A[i*ld + k])   H: conj(A[k*ld + i])
+enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2, OP_H = 3 };
+
+// One product C[s] (+)= alpha * op(A) op(B) of a batch.  All sizes are read
+// on the device, so a launch sized for the largest shape serves ragged items
+// whose dimensions were produced by earlier kernels.
+//
+// The K index may be two-level: the memory offset of k is
+//   (k / kinner) * kstride + (k % kinner)
+// which lets one product run over a sum of blocks (a weighted Gram matrix
+// over an outer index).  Optional real weights w[k / wdiv] multiply op(A).
+// An inner batch of nbatch products uses strides sA, sB, sC.  With
+// splits > 1 the K range is cut into `splits` parts and part s is written to
+// C + s * sSplit (summed later by reduce_splits).
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  const double* w;
+  long long kstride;
+  long long sA, sB, sC, sSplit;
+  int M, N, K;
+  int lda, ldb, ldc;
+  int kinner, wdiv;
+  int nbatch, splits;
+  int opA, opB;
+  int beta;        // 0: overwrite, 1: accumulate
+  int active;      // 0: item skipped
+  double alpha;
+};
+
+// A Hermitian eigenproblem of size n (<= nmax) for the Jacobi solver.
+// The matrix at `a` (n x n, row-major with leading dimension lda, complex
+// double) is destroyed.  Eigenvalues are written in descending order to
+// `evals`, eigenvectors as the columns of `evecs` (n x n, leading dimension
+// n).  `work` holds n*n complex doubles.
+struct EigDesc {
+  double* a;
+  double* evals;
+  double* evecs;
+  double* work;
+  int n, lda;
+  int active;
+  int pad;
+};
+
+}  // namespace mpdo

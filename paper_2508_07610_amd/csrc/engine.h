@@ -1,0 +1,118 @@
+// Host-side runtime of libmpdo: device state of one or many MPDO instances
+// and the launch sequences of a sublayer of noisy gates on disjoint sites.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "ops.h"
+
+namespace mpdo {
+
+struct Error {
+  int status;
+  std::string msg;
+};
+
+void hip_check(hipError_t e, const char* what);
+
+// Device allocation owned by the runtime (freed on destruction).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  void alloc(size_t n);   // (re)allocates when n > bytes; contents are lost
+  template <typename X> X* as() const { return reinterpret_cast<X*>(p); }
+};
+
+// Pinned host staging area for descriptor uploads.
+struct HostStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  ~HostStage();
+  void* get(size_t n);    // waits until the previous upload finished
+};
+
+struct Channel {
+  int q = 0, m = 0;
+  DevBuf kraus;           // m x d x d complex double
+  std::vector<double> host_kraus;
+  double completeness_err = 0, min_eig = 0;
+};
+
+// A gate of a sublayer: sites [site, site + q), ideal gate source, channel.
+struct GateOp {
+  int inst = 0, site = 0, q = 1;
+  int kind = GK_FIXED, pidx = -1;
+  double scale = 1.0;
+  const double* params = nullptr;  // device
+  const double* ufix = nullptr;    // device (filled by the executor from `uhost`)
+  double uhost[2 * 64];
+  bool has_u = false;
+  const Channel* ch = nullptr;
+};
+
+struct Config {
+  int chi_max = 16, kap_max = 4, mmax = 16;
+  double svd_cut = 1e-14, kap_cut = 1e-14;
+  double tolE = 1e-13;
+};
+
+template <typename T> class Engine {
+ public:
+  Engine(const Config& cfg, const std::vector<int>& nq, hipStream_t s);
+  ~Engine() = default;
+
+  // One group of gates on pairwise disjoint sites (any mix of 1q and 2q).
+  void run_sublayer(const std::vector<GateOp>& ops);
+  // Tr(O_k rho) / Tr rho for product operators; ops_host: per item n x 4 complex.
+  // Results (complex) are written to out_dev (device, 2 doubles per item, items
+  // of all instances concatenated in the order given).
+  void expect(const std::vector<int>& inst, const std::vector<const double*>& ops_host, double* out_dev,
+              bool raw = false);
+  // The Sec. II.D sweep on instance b.
+  double truncate_sweep(int b, int chi_max, int kap_max, double cut);
+
+  void dims(int b, std::vector<int>& bonds, std::vector<int>& inner, double& disc);
+  std::vector<double> bond_weights(int b, int bond);
+
+  const Config& config() const { return cfg_; }
+  int nq(int b) const { return nq_[b]; }
+  int ninst() const { return (int)nq_.size(); }
+  hipStream_t stream() const { return st_; }
+
+  // capture support: sizes of the upload blobs must not change during capture
+  bool capturing = false;
+
+ private:
+  Config cfg_;
+  std::vector<int> nq_, soff_;
+  int nsites_ = 0;
+  hipStream_t st_;
+  size_t cap_site_ = 0;
+  DevBuf sites_, lam_, lam2_, one_, dims_, disc_;
+  std::vector<int> par_;
+  DevBuf work_, blob_;
+  HostStage stage_;
+  DevBuf sweeps_;
+
+  cpx<T>* site(int b, int i, int p) const {
+    return sites_.as<cpx<T>>() + ((size_t)(soff_[b] + i) * 2 + p) * cap_site_;
+  }
+  int* chi_ptr(int b, int i) const { return dims_.as<int>() + soff_[b] + b + i; }  // bond left of site i
+  int* kap_ptr(int b, int i) const { return dims_.as<int>() + nsites_ + (int)nq_.size() + soff_[b] + i; }
+  double* lam_ptr(int b, int bond) const { return lam_.as<double>() + (size_t)(soff_[b] + bond) * cfg_.chi_max; }
+  double* lam2_ptr(int b, int bond) const { return lam2_.as<double>() + (size_t)(soff_[b] + bond) * cfg_.chi_max; }
+  const double* laml2(int b, int i) const { return i == 0 ? one_.as<double>() : lam2_ptr(b, i - 1); }
+  double* disc_ptr(int b, int i) const { return disc_.as<double>() + soff_[b] + i; }
+
+  void run_1q(const std::vector<const GateOp*>& ops);
+  void run_2q(const std::vector<const GateOp*>& ops);
+  int splits_for(long long K) const;
+};
+
+}  // namespace mpdo

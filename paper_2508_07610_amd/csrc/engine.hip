@@ -1,0 +1,526 @@
+// Host runtime of libmpdo: device state of MPDO instances and the launch
+// sequences that apply a sublayer of noisy gates (Eq. (8)) with inner and
+// bond truncation (Eqs. (9)-(11), Sec. II.D), observables by transfer
+// matrices (Eqs. (6)-(7)) and the canonicalise-then-truncate sweep.
+//
+// Gauge: every site tensor B[l, s, k, r] is right-orthonormal and every bond
+// carries its weights lambda, so the environment of a site or of a pair of
+// neighbouring sites is diag(lambda_left^2) (x) identity.  Gates on disjoint
+// sites are therefore independent and a whole sublayer runs as one launch
+// sequence over all its gates (and all instances of a batch).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+#include "engine.h"
+#include "kernels.h"
+
+namespace mpdo {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error{4 /*MPDO_EDEVICE*/, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+
+void DevBuf::alloc(size_t n) {
+  if (n <= bytes && p) return;
+  if (p) {
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    hip_check(hipFree(p), "hipFree");
+    p = nullptr;
+    bytes = 0;
+  }
+  if (n == 0) n = 256;
+  if (hipMalloc(&p, n) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    throw Error{3 /*MPDO_ENOMEM*/, "device allocation of " + std::to_string(n) + " bytes failed"};
+  }
+  bytes = n;
+}
+
+HostStage::~HostStage() {
+  if (done) (void)hipEventDestroy(done);
+  if (p) (void)hipHostFree(p);
+}
+
+void* HostStage::get(size_t n) {
+  if (done) hip_check(hipEventSynchronize(done), "hipEventSynchronize");
+  else hip_check(hipEventCreateWithFlags(&done, hipEventDisableTiming), "hipEventCreate");
+  if (n > bytes) {
+    if (p) hip_check(hipHostFree(p), "hipHostFree");
+    size_t cap = std::max<size_t>(n, 1 << 20);
+    hip_check(hipHostMalloc(&p, cap, hipHostMallocDefault), "hipHostMalloc");
+    bytes = cap;
+  }
+  return p;
+}
+
+namespace {
+// Offsets of the pieces of one upload (descriptors, contexts) or of the
+// per-item workspace, 256-byte aligned.
+struct Layout {
+  size_t off = 0;
+  size_t add(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  }
+};
+
+template <typename X> X* at(void* base, size_t off) { return reinterpret_cast<X*>(reinterpret_cast<char*>(base) + off); }
+
+__global__ void k_init_sites_kernel(double* base, long long nsites, long long stride_doubles) {
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < nsites; s += (long long)gridDim.x * blockDim.x)
+    base[s * stride_doubles] = 1.0;
+}
+__global__ void k_init_sites_kernel_f(float* base, long long nsites, long long stride_floats) {
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < nsites; s += (long long)gridDim.x * blockDim.x)
+    base[s * stride_floats] = 1.0f;
+}
+}  // namespace
+
+template <typename T>
+Engine<T>::Engine(const Config& cfg, const std::vector<int>& nq, hipStream_t s) : cfg_(cfg), nq_(nq), st_(s) {
+  soff_.resize(nq_.size() + 1, 0);
+  for (size_t b = 0; b < nq_.size(); ++b) soff_[b + 1] = soff_[b] + nq_[b];
+  nsites_ = soff_.back();
+  cap_site_ = (size_t)cfg_.chi_max * 2 * cfg_.kap_max * cfg_.chi_max;
+  sites_.alloc((size_t)nsites_ * 2 * cap_site_ * sizeof(cpx<T>));
+  hip_check(hipMemsetAsync(sites_.p, 0, sites_.bytes, st_), "hipMemsetAsync");
+  if (sizeof(T) == 8)
+    hipLaunchKernelGGL(k_init_sites_kernel, dim3(64), dim3(256), 0, st_, sites_.as<double>(), (long long)nsites_,
+                       (long long)(2 * cap_site_ * 2));
+  else
+    hipLaunchKernelGGL(k_init_sites_kernel_f, dim3(64), dim3(256), 0, st_, sites_.as<float>(), (long long)nsites_,
+                       (long long)(2 * cap_site_ * 2));
+  par_.assign(nsites_, 0);
+  std::vector<double> ones((size_t)nsites_ * cfg_.chi_max, 1.0);
+  lam_.alloc(ones.size() * sizeof(double));
+  lam2_.alloc(ones.size() * sizeof(double));
+  hip_check(hipMemcpyAsync(lam_.p, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice, st_), "copy");
+  hip_check(hipMemcpyAsync(lam2_.p, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice, st_), "copy");
+  one_.alloc(sizeof(double));
+  hip_check(hipMemcpyAsync(one_.p, ones.data(), sizeof(double), hipMemcpyHostToDevice, st_), "copy");
+  std::vector<int> d(nsites_ + nq_.size() + nsites_, 1);
+  dims_.alloc(d.size() * sizeof(int));
+  hip_check(hipMemcpyAsync(dims_.p, d.data(), d.size() * sizeof(int), hipMemcpyHostToDevice, st_), "copy");
+  std::vector<double> z(nsites_, 0.0);
+  disc_.alloc(z.size() * sizeof(double));
+  hip_check(hipMemcpyAsync(disc_.p, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice, st_), "copy");
+  hip_check(hipStreamSynchronize(st_), "hipStreamSynchronize");
+}
+
+template <typename T> int Engine<T>::splits_for(long long K) const {
+  long long s = (K + 2047) / 2048;
+  if (s < 1) s = 1;
+  if (s > 64) s = 64;
+  return (int)s;
+}
+
+template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& ops) {
+  std::vector<const GateOp*> one, two;
+  for (const GateOp& g : ops) {
+    if (g.q == 1) one.push_back(&g);
+    else if (g.q == 2) two.push_back(&g);
+    else throw Error{6 /*MPDO_EUNSUPPORTED*/, "3-qubit channels are not available in this build"};
+  }
+  // chunks bounded by a workspace budget
+  const size_t budget = (size_t)8 << 30;
+  const int kx = cfg_.kap_max, cx = cfg_.chi_max, mm = std::max(1, cfg_.mmax);
+  const size_t per2 = (size_t)(2 * kx * cx) * (2 * kx * cx) * sizeof(cpx<T>) * 1 +
+                      (size_t)(2 * kx * cx) * (4 * cx) * sizeof(cpx<T>) * 2 +
+                      (size_t)(4 * cx) * (4 * cx) * 16 * 4 + (size_t)(kx * mm) * (kx * mm) * 16 * 3 + (1 << 20);
+  const int chunk2 = (int)std::max<size_t>(1, budget / per2);
+  for (size_t a = 0; a < one.size(); a += 4096)
+    run_1q(std::vector<const GateOp*>(one.begin() + a, one.begin() + std::min(one.size(), a + 4096)));
+  for (size_t a = 0; a < two.size(); a += chunk2)
+    run_2q(std::vector<const GateOp*>(two.begin() + a, two.begin() + std::min(two.size(), a + chunk2)));
+}
+
+template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& ops) {
+  const int n = (int)ops.size();
+  if (n == 0) return;
+  const int kx = cfg_.kap_max, cx = cfg_.chi_max;
+  int m1 = 1;
+  for (auto* g : ops) m1 = std::max(m1, g->ch ? g->ch->m : 1);
+  const int splitsH = splits_for((long long)cx * cx);
+  const int ng = kx * m1;  // largest Gamma
+  // ---- workspace layout per item ----
+  Layout w;
+  const size_t oG = w.add((size_t)m1 * 4 * 16);
+  const size_t oH = w.add((size_t)4 * kx * kx * 16);
+  const size_t oHp = w.add((size_t)splitsH * 4 * kx * kx * 16);
+  const size_t oGam = w.add((size_t)ng * ng * 16);
+  const size_t oEv = w.add((size_t)ng * 8);
+  const size_t oVec = w.add((size_t)ng * ng * 16);
+  const size_t oWk = w.add((size_t)ng * ng * 16);
+  const size_t oW = w.add((size_t)4 * kx * kx * sizeof(cpx<T>));
+  const size_t per = w.off;
+  work_.alloc(per * n);
+  // ---- upload layout ----
+  Layout u;
+  const size_t uCtx = u.add(sizeof(Ctx1<T>) * n);
+  const size_t uH = u.add(sizeof(GemmDesc) * n);
+  const size_t uE = u.add(sizeof(EigDesc) * n);
+  const size_t uA = u.add(sizeof(GemmDesc) * n);
+  const size_t uOut = u.add(sizeof(double*) * n);
+  const size_t uU = u.add(sizeof(double) * 8 * n);
+  blob_.alloc(u.off);
+  char* h = reinterpret_cast<char*>(stage_.get(u.off));
+  std::memset(h, 0, u.off);
+  char* dv = reinterpret_cast<char*>(blob_.p);
+  char* wk = reinterpret_cast<char*>(work_.p);
+  for (int it = 0; it < n; ++it) {
+    const GateOp& g = *ops[it];
+    char* base = wk + per * it;
+    Ctx1<T>& c = at<Ctx1<T>>(h, uCtx)[it];
+    double* uslot = at<double>(h, uU) + 8 * it;
+    c.g.kind = g.kind; c.g.q = 1; c.g.pidx = g.pidx; c.g.scale = g.scale; c.g.params = g.params;
+    c.g.ufix = g.ufix;
+    if (g.has_u) {
+      std::memcpy(uslot, g.uhost, 8 * sizeof(double));
+      c.g.ufix = reinterpret_cast<const double*>(dv + uU) + 8 * it;
+    }
+    c.kraus = g.ch ? g.ch->kraus.as<double>() : nullptr;
+    c.m = g.ch ? g.ch->m : 1;
+    const int b = g.inst, i = g.site;
+    const int p = par_[soff_[b] + i];
+    c.Bold = site(b, i, p);
+    c.Bnew = site(b, i, 1 - p);
+    c.laml2 = laml2(b, i);
+    c.chil = chi_ptr(b, i);
+    c.chir = chi_ptr(b, i + 1);
+    c.kap = kap_ptr(b, i);
+    c.disc = disc_ptr(b, i);
+    c.G = at<double>(base, oG);
+    c.H = at<double>(base, oH);
+    c.Gam = at<double>(base, oGam);
+    c.ev = at<double>(base, oEv);
+    c.evec = at<double>(base, oVec);
+    c.W = at<cpx<T>>(base, oW);
+    c.dH = reinterpret_cast<GemmDesc*>(dv + uH) + it;
+    c.dE = reinterpret_cast<EigDesc*>(dv + uE) + it;
+    c.dA = reinterpret_cast<GemmDesc*>(dv + uA) + it;
+    GemmDesc& dh = at<GemmDesc>(h, uH)[it];
+    dh.C = at<double>(base, oHp);
+    dh.sSplit = (long long)4 * kx * kx;
+    EigDesc& de = at<EigDesc>(h, uE)[it];
+    de.work = at<double>(base, oWk);
+    at<double*>(h, uOut)[it] = c.H;
+  }
+  hip_check(hipMemcpyAsync(blob_.p, h, u.off, hipMemcpyHostToDevice, st_), "upload");
+  hip_check(hipEventRecord(stage_.done, st_), "hipEventRecord");
+  sweeps_.alloc(sizeof(int) * n);
+  Ctx1<T>* dctx = reinterpret_cast<Ctx1<T>*>(dv + uCtx);
+  TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
+  launch_q1_prepare<T>(dctx, n, splitsH, st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH, 2 * kx, 2 * kx, st_);
+  launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uH), reinterpret_cast<double**>(dv + uOut), n,
+                       4 * kx * kx, st_);
+  launch_q1_gamma<T>(dctx, n, st_);
+  launch_eigh(reinterpret_cast<EigDesc*>(dv + uE), n, ng, sweeps_.as<int>(), st_);
+  launch_q1_select<T>(dctx, n, tp, st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uA), n, cx, 1, 2 * kx, cx, st_);
+  hip_check(hipGetLastError(), "launch (1q sublayer)");
+  for (auto* g : ops) par_[soff_[g->inst] + g->site] ^= 1;
+}
+
+template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& ops) {
+  const int n = (int)ops.size();
+  if (n == 0) return;
+  const int kx = cfg_.kap_max, cx = cfg_.chi_max;
+  int m2 = 1;
+  for (auto* g : ops) m2 = std::max(m2, g->ch ? g->ch->m : 1);
+  const int splitsH = splits_for((long long)cx * kx * cx);
+  const int splitsE = splits_for((long long)kx * cx);
+  const int splitsC = splits_for((long long)2 * kx * cx);
+  const int ng = kx * m2;
+  const long long thetaN = (long long)2 * kx * cx;
+  Layout w;
+  const size_t oG = w.add((size_t)m2 * 16 * 16);
+  const size_t oTheta = w.add((size_t)thetaN * thetaN * sizeof(cpx<T>));
+  const size_t oH = w.add((size_t)16 * kx * kx * 16);
+  const size_t oHp = w.add((size_t)splitsH * 16 * kx * kx * 16);
+  const size_t oE = w.add((size_t)4 * cx * cx * 16);
+  const size_t oEp = w.add((size_t)splitsE * 4 * cx * cx * 16);
+  const size_t oGam = w.add((size_t)ng * ng * 16);
+  const size_t oEvG = w.add((size_t)ng * 8);
+  const size_t oVecG = w.add((size_t)ng * ng * 16);
+  const size_t oWkG = w.add((size_t)ng * ng * 16);
+  const size_t oEvE = w.add((size_t)2 * cx * 8);
+  const size_t oVecE = w.add((size_t)4 * cx * cx * 16);
+  const size_t oWkE = w.add((size_t)4 * cx * cx * 16);
+  const size_t oEvC = w.add((size_t)4 * cx * 8);
+  const size_t oVecC = w.add((size_t)16 * cx * cx * 16);
+  const size_t oWkC = w.add((size_t)16 * cx * cx * 16);
+  const size_t oW = w.add((size_t)16 * kx * kx * sizeof(cpx<T>));
+  const size_t oLF = w.add((size_t)4 * cx * cx * sizeof(cpx<T>));
+  const size_t oPD = w.add((size_t)4 * cx * cx * 16);
+  const size_t oTh = w.add((size_t)thetaN * 4 * cx * sizeof(cpx<T>));
+  const size_t oTh2 = w.add((size_t)thetaN * 4 * cx * sizeof(cpx<T>));
+  const size_t oCm = w.add((size_t)16 * cx * cx * 16);
+  const size_t oCp = w.add((size_t)splitsC * 16 * cx * cx * 16);
+  const size_t oZt = w.add((size_t)4 * cx * cx * 16);
+  const size_t oZc = w.add((size_t)4 * cx * cx * sizeof(cpx<T>));
+  const size_t oX = w.add((size_t)4 * cx * cx * sizeof(cpx<T>));
+  const size_t oScr = w.add(16);
+  const size_t per = w.off;
+  work_.alloc(per * n);
+  Layout u;
+  const size_t uCtx = u.add(sizeof(Ctx2<T>) * n);
+  const size_t uTheta = u.add(sizeof(GemmDesc) * n);
+  const size_t uGram = u.add(sizeof(GemmDesc) * 2 * n);
+  const size_t uEig = u.add(sizeof(EigDesc) * 2 * n);
+  const size_t uTh = u.add(sizeof(GemmDesc) * n);
+  const size_t uTh2 = u.add(sizeof(GemmDesc) * n);
+  const size_t uC = u.add(sizeof(GemmDesc) * n);
+  const size_t uEigC = u.add(sizeof(EigDesc) * n);
+  const size_t uX = u.add(sizeof(GemmDesc) * n);
+  const size_t uOut = u.add(sizeof(GemmDesc) * 2 * n);
+  const size_t uOutsG = u.add(sizeof(double*) * 2 * n);
+  const size_t uOutsC = u.add(sizeof(double*) * n);
+  const size_t uU = u.add(sizeof(double) * 32 * n);
+  blob_.alloc(u.off);
+  char* h = reinterpret_cast<char*>(stage_.get(u.off));
+  std::memset(h, 0, u.off);
+  char* dv = reinterpret_cast<char*>(blob_.p);
+  char* wk = reinterpret_cast<char*>(work_.p);
+  for (int it = 0; it < n; ++it) {
+    const GateOp& g = *ops[it];
+    char* base = wk + per * it;
+    Ctx2<T>& c = at<Ctx2<T>>(h, uCtx)[it];
+    double* uslot = at<double>(h, uU) + 32 * it;
+    c.g.kind = g.kind; c.g.q = 2; c.g.pidx = g.pidx; c.g.scale = g.scale; c.g.params = g.params;
+    c.g.ufix = g.ufix;
+    if (g.has_u) {
+      std::memcpy(uslot, g.uhost, 32 * sizeof(double));
+      c.g.ufix = reinterpret_cast<const double*>(dv + uU) + 32 * it;
+    }
+    c.kraus = g.ch ? g.ch->kraus.as<double>() : nullptr;
+    c.m = g.ch ? g.ch->m : 1;
+    const int b = g.inst, i = g.site;
+    const int pi = par_[soff_[b] + i], pj = par_[soff_[b] + i + 1];
+    c.Bi = site(b, i, pi);
+    c.Bj = site(b, i + 1, pj);
+    c.Bi_new = site(b, i, 1 - pi);
+    c.Bj_new = site(b, i + 1, 1 - pj);
+    c.laml2 = laml2(b, i);
+    c.lam = lam_ptr(b, i);
+    c.lam2 = lam2_ptr(b, i);
+    c.chil = chi_ptr(b, i);
+    c.chim = chi_ptr(b, i + 1);
+    c.chir = chi_ptr(b, i + 2);
+    c.kap1 = kap_ptr(b, i);
+    c.kap2 = kap_ptr(b, i + 1);
+    c.disc = disc_ptr(b, i);
+    c.scratch = at<int>(base, oScr);
+    c.G = at<double>(base, oG);
+    c.Theta = at<cpx<T>>(base, oTheta);
+    c.H = at<double>(base, oH);
+    c.E = at<double>(base, oE);
+    c.Gam = at<double>(base, oGam);
+    c.evG = at<double>(base, oEvG);
+    c.vecG = at<double>(base, oVecG);
+    c.evE = at<double>(base, oEvE);
+    c.vecE = at<double>(base, oVecE);
+    c.evC = at<double>(base, oEvC);
+    c.vecC = at<double>(base, oVecC);
+    c.W = at<cpx<T>>(base, oW);
+    c.LF = at<cpx<T>>(base, oLF);
+    c.PD = at<double>(base, oPD);
+    c.th = at<cpx<T>>(base, oTh);
+    c.th2 = at<cpx<T>>(base, oTh2);
+    c.Cm = at<double>(base, oCm);
+    c.Zt = at<double>(base, oZt);
+    c.Zc = at<cpx<T>>(base, oZc);
+    c.X = at<cpx<T>>(base, oX);
+    c.dTheta = reinterpret_cast<GemmDesc*>(dv + uTheta) + it;
+    c.dGram = reinterpret_cast<GemmDesc*>(dv + uGram) + 2 * it;
+    c.dEig = reinterpret_cast<EigDesc*>(dv + uEig) + 2 * it;
+    c.dTh = reinterpret_cast<GemmDesc*>(dv + uTh) + it;
+    c.dTh2 = reinterpret_cast<GemmDesc*>(dv + uTh2) + it;
+    c.dC = reinterpret_cast<GemmDesc*>(dv + uC) + it;
+    c.dEigC = reinterpret_cast<EigDesc*>(dv + uEigC) + it;
+    c.dX = reinterpret_cast<GemmDesc*>(dv + uX) + it;
+    c.dOut = reinterpret_cast<GemmDesc*>(dv + uOut) + 2 * it;
+    GemmDesc* hg = at<GemmDesc>(h, uGram) + 2 * it;
+    hg[0].C = at<double>(base, oHp);
+    hg[0].sSplit = (long long)16 * kx * kx;
+    hg[1].C = at<double>(base, oEp);
+    hg[1].sSplit = (long long)4 * cx * cx;
+    EigDesc* he = at<EigDesc>(h, uEig) + 2 * it;
+    he[0].work = at<double>(base, oWkG);
+    he[1].work = at<double>(base, oWkE);
+    GemmDesc& hc = at<GemmDesc>(h, uC)[it];
+    hc.C = at<double>(base, oCp);
+    hc.sSplit = (long long)16 * cx * cx;
+    at<EigDesc>(h, uEigC)[it].work = at<double>(base, oWkC);
+    at<double*>(h, uOutsG)[2 * it] = c.H;
+    at<double*>(h, uOutsG)[2 * it + 1] = c.E;
+    at<double*>(h, uOutsC)[it] = c.Cm;
+  }
+  hip_check(hipMemcpyAsync(blob_.p, h, u.off, hipMemcpyHostToDevice, st_), "upload");
+  hip_check(hipEventRecord(stage_.done, st_), "hipEventRecord");
+  sweeps_.alloc(sizeof(int) * 2 * n);
+  Ctx2<T>* dctx = reinterpret_cast<Ctx2<T>*>(dv + uCtx);
+  TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
+  const int maxGram = std::max(4 * kx, 2 * cx);
+  launch_q2_prepare<T>(dctx, n, splitsH, splitsE, st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTheta), n, 1, 1, (int)thetaN, (int)thetaN, st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGram), 2 * n, 1, std::max(splitsH, splitsE),
+                                 maxGram, maxGram, st_);
+  launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGram), reinterpret_cast<double**>(dv + uOutsG), 2 * n,
+                       maxGram * maxGram, st_);
+  launch_q2_gamma<T>(dctx, n, st_);
+  launch_eigh(reinterpret_cast<EigDesc*>(dv + uEig), 2 * n, std::max(ng, 2 * cx), sweeps_.as<int>(), st_);
+  launch_q2_select_a<T>(dctx, n, splitsC, tp, st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh), n, 1, 1, (int)thetaN, 4 * cx, st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh2), n, cx, 1, 4 * kx, 2 * cx, st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uC), n, 1, splitsC, 4 * cx, 4 * cx, st_);
+  launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uC), reinterpret_cast<double**>(dv + uOutsC), n,
+                       16 * cx * cx, st_);
+  launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigC), n, 4 * cx, sweeps_.as<int>() + n, st_);
+  launch_q2_select_b<T>(dctx, n, tp, st_);
+  launch_gemm<double, double, T>(reinterpret_cast<GemmDesc*>(dv + uX), n, 1, 1, 2 * cx, 2 * cx, st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uOut), 2 * n, 1, 1, (int)thetaN,
+                       std::max(cx, kx * cx), st_);
+  hip_check(hipGetLastError(), "launch (2q sublayer)");
+  for (auto* g : ops) {
+    par_[soff_[g->inst] + g->site] ^= 1;
+    par_[soff_[g->inst] + g->site + 1] ^= 1;
+  }
+}
+
+template <typename T>
+void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const double*>& ops_host, double* out_dev,
+                       bool raw) {
+  // items: per instance a trace item (identity) followed by its observables,
+  // in the order given (inst[] must be grouped by instance).
+  struct It { int b; const double* ops; int trace; };
+  std::vector<It> items;
+  int last = -1, trace_idx = 0;
+  std::vector<int> result_index;  // item index of each requested observable
+  for (size_t k = 0; k < inst.size(); ++k) {
+    if (inst[k] != last) {
+      trace_idx = (int)items.size();
+      items.push_back({inst[k], nullptr, trace_idx});
+      last = inst[k];
+    }
+    result_index.push_back((int)items.size());
+    items.push_back({inst[k], ops_host[k], trace_idx});
+  }
+  const int n = (int)items.size();
+  int nmax = 0;
+  for (auto& it : items) nmax = std::max(nmax, nq_[it.b]);
+  const int cx = cfg_.chi_max;
+  Layout w;
+  const size_t oE0 = w.add((size_t)cx * cx * sizeof(cpx<T>));
+  const size_t oE1 = w.add((size_t)cx * cx * sizeof(cpx<T>));
+  const size_t oBO = w.add(cap_site_ * sizeof(cpx<T>));
+  const size_t oY = w.add(cap_site_ * sizeof(cpx<T>));
+  const size_t per = w.off;
+  work_.alloc(per * n);
+  Layout u;
+  const size_t uCtx = u.add(sizeof(CtxT<T>) * (size_t)nmax * n);
+  const size_t uD1 = u.add(sizeof(GemmDesc) * (size_t)nmax * n);
+  const size_t uD2 = u.add(sizeof(GemmDesc) * (size_t)nmax * n);
+  const size_t uOps = u.add(sizeof(double) * 8 * (size_t)nmax * n);
+  const size_t uRes = u.add(sizeof(double) * 2 * n);
+  blob_.alloc(u.off);
+  char* h = reinterpret_cast<char*>(stage_.get(u.off));
+  std::memset(h, 0, u.off);
+  char* dv = reinterpret_cast<char*>(blob_.p);
+  char* wk = reinterpret_cast<char*>(work_.p);
+  for (int it = 0; it < n; ++it) {
+    const int b = items[it].b, nb = nq_[b];
+    double* ops = at<double>(h, uOps) + 8 * (size_t)nmax * it;
+    for (int s = 0; s < nb; ++s) {
+      if (items[it].ops) {
+        std::memcpy(ops + 8 * s, items[it].ops + 8 * s, 8 * sizeof(double));
+      } else {
+        const double id[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+        std::memcpy(ops + 8 * s, id, sizeof(id));
+      }
+    }
+    char* base = wk + per * it;
+    for (int s = 0; s < nmax; ++s) {
+      CtxT<T>& c = at<CtxT<T>>(h, uCtx)[(size_t)s * n + it];
+      c.ops = reinterpret_cast<const double*>(dv + uOps) + 8 * (size_t)nmax * it;
+      c.site = s;
+      c.active = s < nb;
+      c.trace_idx = raw ? -1 : items[it].trace;
+      c.Ecur = at<cpx<T>>(base, (s % 2) ? oE1 : oE0);
+      c.Enext = at<cpx<T>>(base, (s % 2) ? oE0 : oE1);
+      c.Efinal = at<cpx<T>>(base, (nb % 2) ? oE1 : oE0);
+      c.BO = at<cpx<T>>(base, oBO);
+      c.Y = at<cpx<T>>(base, oY);
+      c.d1 = reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n + it;
+      c.d2 = reinterpret_cast<GemmDesc*>(dv + uD2) + (size_t)s * n + it;
+      if (s < nb) {
+        c.B = site(b, s, par_[soff_[b] + s]);
+        c.chil = chi_ptr(b, s);
+        c.chir = chi_ptr(b, s + 1);
+        c.kap = kap_ptr(b, s);
+      } else {
+        c.B = nullptr;
+        c.chil = c.chir = c.kap = nullptr;
+      }
+    }
+  }
+  hip_check(hipMemcpyAsync(blob_.p, h, u.off, hipMemcpyHostToDevice, st_), "upload");
+  hip_check(hipEventRecord(stage_.done, st_), "hipEventRecord");
+  CtxT<T>* dctx = reinterpret_cast<CtxT<T>*>(dv + uCtx);
+  launch_transfer_init<T>(dctx, n, st_);
+  for (int s = 0; s < nmax; ++s) {
+    launch_transfer_prep<T>(dctx + (size_t)s * n, n, (int)cap_site_ / 2, st_);
+    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n, n, 1, 1, cx,
+                         (int)(2 * cfg_.kap_max * cx), st_);
+    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD2) + (size_t)s * n, n, 1, 1, cx, cx, st_);
+  }
+  double* res = reinterpret_cast<double*>(dv + uRes);
+  launch_transfer_finish<T>(dctx, n, res, st_);
+  // gather the requested observables in order
+  for (size_t k = 0; k < result_index.size(); ++k)
+    hip_check(hipMemcpyAsync(out_dev + 2 * k, res + 2 * result_index[k], 2 * sizeof(double),
+                             hipMemcpyDeviceToDevice, st_), "gather");
+  hip_check(hipGetLastError(), "launch (transfer)");
+}
+
+template <typename T>
+void Engine<T>::dims(int b, std::vector<int>& bonds, std::vector<int>& inner, double& disc) {
+  const int nb = nq_[b];
+  std::vector<int> chi(nb + 1), kap(nb);
+  std::vector<double> d(nb);
+  hip_check(hipMemcpyAsync(chi.data(), chi_ptr(b, 0), sizeof(int) * (nb + 1), hipMemcpyDeviceToHost, st_), "dims");
+  hip_check(hipMemcpyAsync(kap.data(), kap_ptr(b, 0), sizeof(int) * nb, hipMemcpyDeviceToHost, st_), "dims");
+  hip_check(hipMemcpyAsync(d.data(), disc_ptr(b, 0), sizeof(double) * nb, hipMemcpyDeviceToHost, st_), "dims");
+  hip_check(hipStreamSynchronize(st_), "hipStreamSynchronize");
+  bonds.assign(chi.begin() + 1, chi.end() - 1);
+  inner = kap;
+  disc = 0;
+  for (double x : d) disc += x;
+}
+
+template <typename T> std::vector<double> Engine<T>::bond_weights(int b, int bond) {
+  std::vector<int> bonds, inner;
+  double disc;
+  dims(b, bonds, inner, disc);
+  const int len = bonds[bond];
+  std::vector<double> v(len);
+  hip_check(hipMemcpy(v.data(), lam_ptr(b, bond), sizeof(double) * len, hipMemcpyDeviceToHost), "lambda");
+  return v;
+}
+
+template <typename T> double Engine<T>::truncate_sweep(int, int, int, double) {
+  throw Error{6, "mpdo_truncate is not available yet"};
+}
+
+template class Engine<double>;
+template class Engine<float>;
+
+}  // namespace mpdo

@@ -1,0 +1,235 @@
+// Batched complex GEMM on the gfx950 matrix cores (MFMA), ragged shapes read
+// on the device.  Used for every contraction of the MPDO update: the two-site
+// contraction, the Gram matrices of the inner and bond truncations, the
+// projections and the transfer matrices.
+//
+// A complex product is four real MFMA products on split real/imaginary
+// planes staged in LDS:  Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
+// Tile 64 x 64 (complex) per workgroup of four waves; each wave owns a
+// 32 x 32 quadrant made of 2 x 2 blocks of the 16x16x4 MFMA.
+#include "common.h"
+#include "kernels.h"
+
+namespace mpdo {
+
+// Operand layout of both 16x16x4 MFMAs: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Output: lane l holds column l % 16; accumulator
+// element v is row row(l / 16, v), which differs between the two types.
+template <typename Tc> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int g, int v) { return g + 4 * v; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int g, int v) { return 4 * g + v; }
+};
+
+namespace {
+constexpr int BM = 64, BN = 64, BK = 16, NTHR = 256, PAD = 4;
+
+__device__ inline long long kaddr(int k, int kinner, long long kstride) {
+  return (long long)(k / kinner) * kstride + (k % kinner);
+}
+}  // namespace
+
+template <typename Tin, typename Tc, typename Tout>
+__global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch,
+                                               int maxSplits, int tilesM, int tilesN) {
+  typedef typename Mfma<Tc>::v4 v4;
+  __shared__ Tc As_re[BK][BM + PAD], As_im[BK][BM + PAD];
+  __shared__ Tc Bs_re[BK][BN + PAD], Bs_im[BK][BN + PAD];
+
+  const int tiles = tilesM * tilesN;
+  long long bid = blockIdx.x;
+  const int tile = (int)(bid % tiles);
+  bid /= tiles;
+  const int split = (int)(bid % maxSplits);
+  bid /= maxSplits;
+  const int batch = (int)(bid % maxBatch);
+  const int item = (int)(bid / maxBatch);
+  const GemmDesc& d = descs[item];
+  if (!d.active || batch >= d.nbatch || split >= d.splits) return;
+  const int tm = tile / tilesN, tn = tile % tilesN;
+  const int M = d.M, N = d.N, K = d.K;
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (m0 >= M || n0 >= N) return;
+
+  const cpx<Tin>* A = reinterpret_cast<const cpx<Tin>*>(d.A) + (long long)batch * d.sA;
+  const cpx<Tin>* B = reinterpret_cast<const cpx<Tin>*>(d.B) + (long long)batch * d.sB;
+  cpx<Tout>* C = reinterpret_cast<cpx<Tout>*>(d.C) + (long long)batch * d.sC + (long long)split * d.sSplit;
+  const int opA = d.opA, opB = d.opB, lda = d.lda, ldb = d.ldb;
+  const int kinner = d.kinner > 0 ? d.kinner : (K > 0 ? K : 1);
+  const long long kstride = d.kinner > 0 ? d.kstride : (long long)kinner;
+  const double* w = d.w;
+  const int wdiv = d.wdiv > 0 ? d.wdiv : 1;
+
+  int kper = (K + d.splits - 1) / d.splits;
+  kper = (kper + BK - 1) / BK * BK;
+  const int kbeg = split * kper;
+  const int kend = min(K, kbeg + kper);
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  v4 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = v4{0, 0, 0, 0};
+      acc_im[i][j] = v4{0, 0, 0, 0};
+    }
+
+  const bool aKfast = (opA == OP_N || opA == OP_C);
+  const bool aConj = (opA == OP_C || opA == OP_H);
+  const bool bKfast = (opB == OP_T || opB == OP_H);
+  const bool bConj = (opB == OP_C || opB == OP_H);
+
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    // ---- stage A tile (BM x BK) ----
+#pragma unroll
+    for (int it = 0; it < (BM * BK) / NTHR; ++it) {
+      const int idx = tid + it * NTHR;
+      int mm, kk;
+      if (aKfast) { kk = idx % BK; mm = idx / BK; }
+      else { mm = idx % BM; kk = idx / BM; }
+      const int m = m0 + mm, k = k0 + kk;
+      Tc re = 0, im = 0;
+      if (m < M && k < kend) {
+        const long long ka = kaddr(k, kinner, kstride);
+        const cpx<Tin> v = aKfast ? A[(long long)m * lda + ka] : A[ka * lda + m];
+        re = (Tc)v.re;
+        im = aConj ? -(Tc)v.im : (Tc)v.im;
+        if (w) {
+          const Tc s = (Tc)w[k / wdiv];
+          re *= s;
+          im *= s;
+        }
+      }
+      As_re[kk][mm] = re;
+      As_im[kk][mm] = im;
+    }
+    // ---- stage B tile (BK x BN) ----
+#pragma unroll
+    for (int it = 0; it < (BN * BK) / NTHR; ++it) {
+      const int idx = tid + it * NTHR;
+      int nn, kk;
+      if (bKfast) { kk = idx % BK; nn = idx / BK; }
+      else { nn = idx % BN; kk = idx / BN; }
+      const int n = n0 + nn, k = k0 + kk;
+      Tc re = 0, im = 0;
+      if (n < N && k < kend) {
+        const long long ka = kaddr(k, kinner, kstride);
+        const cpx<Tin> v = bKfast ? B[(long long)n * ldb + ka] : B[ka * ldb + n];
+        re = (Tc)v.re;
+        im = bConj ? -(Tc)v.im : (Tc)v.im;
+      }
+      Bs_re[kk][nn] = re;
+      Bs_im[kk][nn] = im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < BK; kb += 4) {
+      Tc ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As_re[kb + lk][wm * 32 + i * 16 + li];
+        ai[i] = As_im[kb + lk][wm * 32 + i * 16 + li];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        br[j] = Bs_re[kb + lk][wn * 32 + j * 16 + li];
+        bi[j] = Bs_im[kb + lk][wn * 32 + j * 16 + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = Mfma<Tc>::mma(ar[i], br[j], acc_re[i][j]);
+          acc_re[i][j] = Mfma<Tc>::mma(-ai[i], bi[j], acc_re[i][j]);
+          acc_im[i][j] = Mfma<Tc>::mma(ar[i], bi[j], acc_im[i][j]);
+          acc_im[i][j] = Mfma<Tc>::mma(ai[i], br[j], acc_im[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+
+  const Tc alpha = (Tc)d.alpha;
+  const int ldc = d.ldc;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 32 + i * 16 + Mfma<Tc>::row(lk, v);
+        const int col = n0 + wn * 32 + j * 16 + li;
+        if (row < M && col < N) {
+          cpx<Tout>* p = C + (long long)row * ldc + col;
+          cpx<Tc> r = mk<Tc>(alpha * acc_re[i][j][v], alpha * acc_im[i][j][v]);
+          if (d.beta) r = r + mk<Tc>((Tc)p->re, (Tc)p->im);
+          *p = mk<Tout>((Tout)r.re, (Tout)r.im);
+        }
+      }
+}
+
+// Sum the split-K partial products: out[i] = sum_s parts[s * sSplit + i]
+// over a dense M x N block (complex double).
+__global__ void k_reduce_splits(const GemmDesc* __restrict__ descs, double* const* __restrict__ outs,
+                                int maxCount) {
+  const GemmDesc& d = descs[blockIdx.y];
+  if (!d.active) return;
+  double* out = outs[blockIdx.y];
+  const int count = d.M * d.ldc;
+  const cpx<double>* parts = reinterpret_cast<const cpx<double>*>(d.C);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count && e < maxCount;
+       e += gridDim.x * blockDim.x) {
+    const int row = e / d.ldc, col = e % d.ldc;
+    if (col >= d.N) continue;
+    double re = 0, im = 0;
+    for (int s = 0; s < d.splits; ++s) {
+      const cpx<double> v = parts[(long long)s * d.sSplit + e];
+      re += v.re;
+      im += v.im;
+    }
+    out[2 * (long long)e] = re;
+    out[2 * (long long)e + 1] = im;
+    (void)row;
+  }
+}
+
+template <typename Tin, typename Tc, typename Tout>
+void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxM, int maxN,
+                 hipStream_t s) {
+  if (nitems <= 0) return;
+  const int tilesM = (maxM + BM - 1) / BM, tilesN = (maxN + BN - 1) / BN;
+  const long long blocks = (long long)nitems * maxBatch * maxSplits * tilesM * tilesN;
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout>), dim3((unsigned)blocks), dim3(NTHR), 0, s, d_descs, maxBatch,
+                     maxSplits, tilesM, tilesN);
+}
+
+void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int nitems, int maxCount,
+                          hipStream_t s) {
+  if (nitems <= 0) return;
+  const int threads = 256;
+  const int bx = (maxCount + threads - 1) / threads;
+  hipLaunchKernelGGL(k_reduce_splits, dim3(bx > 4096 ? 4096 : bx, nitems), dim3(threads), 0, s, d_descs,
+                     d_outs, maxCount);
+}
+
+template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, int, hipStream_t);
+template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, int, hipStream_t);
+template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, int, hipStream_t);
+template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, int, hipStream_t);
+
+}  // namespace mpdo

@@ -1,0 +1,697 @@
+// Glue kernels of the MPDO update: fused noisy-gate operators (Eq. (8)), the
+// small Gram combinations of the inner truncation (Eqs. (9)-(11)), rank
+// selection and renormalisation (Sec. II.D), and the descriptors that size
+// the following contractions on the device.  One workgroup per item.
+#include "common.h"
+#include "ops.h"
+
+namespace mpdo {
+
+namespace {
+constexpr int GT = 256;
+
+__device__ inline cpx<double> ld(const double* p, long long i) { return mk(p[2 * i], p[2 * i + 1]); }
+__device__ inline void st(double* p, long long i, cpx<double> v) { p[2 * i] = v.re; p[2 * i + 1] = v.im; }
+
+// Ideal unitary of a gate (d = 2^q <= 8) into U (row-major, complex).
+__device__ void build_unitary(const GateSrc& g, cpx<double>* U) {
+  const int d = 1 << g.q;
+  for (int e = 0; e < d * d; ++e) U[e] = mk(0.0, 0.0);
+  const double a = g.scale * ((g.pidx >= 0 && g.params) ? g.params[g.pidx] : 1.0);
+  const double c = cos(0.5 * a), s = sin(0.5 * a);
+  switch (g.kind) {
+    case GK_RX: U[0] = mk(c, 0.0); U[1] = mk(0.0, -s); U[2] = mk(0.0, -s); U[3] = mk(c, 0.0); break;
+    case GK_RY: U[0] = mk(c, 0.0); U[1] = mk(-s, 0.0); U[2] = mk(s, 0.0); U[3] = mk(c, 0.0); break;
+    case GK_RZ: U[0] = mk(c, -s); U[3] = mk(c, s); break;
+    case GK_ZZPHASE:
+    case GK_SWAPZZ: {
+      const cpx<double> e = mk(cos(a), -sin(a));
+      U[0] = mk(1.0, 0.0);
+      U[15] = mk(1.0, 0.0);
+      if (g.kind == GK_ZZPHASE) { U[5] = e; U[10] = e; }
+      else { U[6] = e; U[9] = e; }
+      break;
+    }
+    default:
+      if (g.ufix) {
+        for (int e2 = 0; e2 < d * d; ++e2) U[e2] = ld(g.ufix, e2);
+      } else {
+        for (int i = 0; i < d; ++i) U[i * d + i] = mk(1.0, 0.0);
+      }
+  }
+}
+
+// G_j = K_j U for j < m (K = identity when kraus == null).
+__device__ void build_G(const GateSrc& g, const double* kraus, int m, double* G, cpx<double>* sU) {
+  const int d = 1 << g.q;
+  if (threadIdx.x == 0) build_unitary(g, sU);
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * d * d; e += blockDim.x) {
+    const int j = e / (d * d), r = (e / d) % d, c = e % d;
+    cpx<double> acc = mk(0.0, 0.0);
+    if (kraus) {
+      for (int t = 0; t < d; ++t) acc = acc + ld(kraus, (long long)j * d * d + r * d + t) * sU[t * d + c];
+    } else {
+      acc = sU[r * d + c];
+    }
+    st(G, e, acc);
+  }
+  __syncthreads();
+}
+
+// Smallest r >= 1 with sum_{i >= r} eta_i <= cut * W (W = sum of positive
+// eta), capped at maxd; also returns the kept and total weights.
+__device__ int select_rank(const double* eta, int n, int maxd, double cut, double* kept, double* total) {
+  double W = 0;
+  for (int i = 0; i < n; ++i) W += eta[i] > 0 ? eta[i] : 0;
+  int r = n;
+  double tail = 0;
+  // scan from the end: tail after index r-1 is sum_{i >= r}
+  for (int cand = n - 1; cand >= 1; --cand) {
+    tail += eta[cand] > 0 ? eta[cand] : 0;
+    if (tail <= cut * W) r = cand;
+    else break;
+  }
+  if (r > maxd) r = maxd;
+  if (r < 1) r = 1;
+  // a degenerate multiplet straddling the cut is dropped whole, so the kept
+  // subspace is unique (multiplets below 1e-11 of the weight are left alone)
+  const int r0 = r;
+  while (r > 1 && r < n && eta[r - 1] > 1e-11 * W && eta[r - 1] - eta[r] <= 1e-9 * eta[r - 1]) --r;
+  if (r == 1 && n > 1 && eta[0] - eta[1] <= 1e-9 * eta[0]) r = r0;
+  double k = 0;
+  for (int i = 0; i < r; ++i) k += eta[i] > 0 ? eta[i] : 0;
+  *kept = k;
+  *total = W;
+  return r;
+}
+
+__device__ inline void clear_desc(GemmDesc& d) {
+  d.w = nullptr; d.kstride = 0; d.sA = d.sB = d.sC = 0;
+  d.M = d.N = d.K = 0; d.lda = d.ldb = d.ldc = 0; d.kinner = 0; d.wdiv = 1;
+  d.nbatch = 1; d.splits = 1; d.opA = OP_N; d.opB = OP_N; d.beta = 0; d.active = 1; d.alpha = 1.0;
+}
+}  // namespace
+
+// ============================================================================
+// one-site noisy gate
+// ============================================================================
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q1_prepare(Ctx1<T>* ctxs, int splitsH) {
+  __shared__ cpx<double> sU[64];
+  Ctx1<T>& c = ctxs[blockIdx.x];
+  build_G(c.g, c.kraus, c.m, c.G, sU);
+  if (threadIdx.x != 0) return;
+  const int cl = *c.chil, cr = *c.chir, k = *c.kap;
+  GemmDesc& d = *c.dH;
+  void* C = d.C;
+  const long long sSplit = d.sSplit;
+  clear_desc(d);
+  d.C = C;
+  d.sSplit = sSplit;
+  if (c.m <= 1) { d.active = 0; return; }
+  // H[a][a'] = sum_l lambda_l^2 sum_r conj(B[l][a][r]) B[l][a'][r],  a = (t, k)
+  d.A = c.Bold; d.B = c.Bold;
+  d.opA = OP_C; d.opB = OP_T;
+  d.M = d.N = 2 * k;
+  d.K = cl * cr;
+  d.lda = d.ldb = cr;
+  d.kinner = cr;
+  d.kstride = (long long)2 * k * cr;
+  d.w = c.laml2;
+  d.wdiv = cr;
+  d.ldc = 2 * k;
+  d.splits = splitsH;
+}
+
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q1_gamma(Ctx1<T>* ctxs) {
+  Ctx1<T>& c = ctxs[blockIdx.x];
+  const int m = c.m;
+  if (m <= 1) {
+    if (threadIdx.x == 0) c.dE->active = 0;
+    return;
+  }
+  const int k = *c.kap, n = k * m;
+  // Gamma[(kk j),(kk' j')] = sum_{t,t'} Omega_{jj'}[t,t'] H[(t kk),(t' kk')],
+  // Omega_{jj'}[t,t'] = sum_s conj(G_j[s,t]) G_j'[s,t']
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int a = e / n, b = e % n;
+    const int kk = a / m, j = a % m, kk2 = b / m, j2 = b % m;
+    cpx<double> acc = mk(0.0, 0.0);
+    for (int t = 0; t < 2; ++t)
+      for (int t2 = 0; t2 < 2; ++t2) {
+        cpx<double> om = mk(0.0, 0.0);
+        for (int s = 0; s < 2; ++s) om = om + cconj(ld(c.G, j * 4 + s * 2 + t)) * ld(c.G, j2 * 4 + s * 2 + t2);
+        acc = acc + om * ld(c.H, (long long)(t * k + kk) * (2 * k) + (t2 * k + kk2));
+      }
+    st(c.Gam, e, acc);
+  }
+  if (threadIdx.x == 0) {
+    EigDesc& d = *c.dE;
+    d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.ev; d.evecs = c.evec; d.active = 1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q1_select(Ctx1<T>* ctxs, TruncParams tp) {
+  __shared__ int s_kp;
+  __shared__ double s_scale;
+  __shared__ cpx<double> sU[64];
+  Ctx1<T>& c = ctxs[blockIdx.x];
+  const int m = c.m;
+  const int k = *c.kap, cl = *c.chil, cr = *c.chir;
+  if (threadIdx.x == 0) {
+    if (m <= 1) {
+      s_kp = k;
+      s_scale = 1.0;
+    } else {
+      double kept, tot;
+      const int kp = select_rank(c.ev, k * m, tp.kap_max, tp.kap_cut, &kept, &tot);
+      s_kp = kp;
+      s_scale = 1.0 / sqrt(kept);
+      if (tot > 0) *c.disc += (tot - kept) / tot;
+    }
+  }
+  __syncthreads();
+  const int kp = s_kp;
+  const double sc = s_scale;
+  // W[(s nu),(t kk)] = scale sum_j G_j[s,t] V[(kk j), nu]   (V = identity for m = 1)
+  const int nW = (2 * kp) * (2 * k);
+  for (int e = threadIdx.x; e < nW; e += blockDim.x) {
+    const int row = e / (2 * k), col = e % (2 * k);
+    const int s = row / kp, nu = row % kp, t = col / k, kk = col % k;
+    cpx<double> acc = mk(0.0, 0.0);
+    if (m <= 1) {
+      if (nu == kk) acc = ld(c.G, s * 2 + t);
+    } else {
+      for (int j = 0; j < m; ++j)
+        acc = acc + ld(c.G, j * 4 + s * 2 + t) * ld(c.evec, (long long)(kk * m + j) * (k * m) + nu);
+    }
+    c.W[e] = mk<T>((T)(sc * acc.re), (T)(sc * acc.im));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    GemmDesc& d = *c.dA;
+    clear_desc(d);
+    d.A = c.W; d.B = c.Bold; d.C = c.Bnew;
+    d.M = 2 * kp; d.K = 2 * k; d.N = cr;
+    d.lda = 2 * k; d.ldb = cr; d.ldc = cr;
+    d.nbatch = cl;
+    d.sA = 0; d.sB = (long long)2 * k * cr; d.sC = (long long)2 * kp * cr;
+    *c.kap = kp;
+  }
+  (void)sU;
+}
+
+// ============================================================================
+// two-site noisy gate
+// ============================================================================
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q2_prepare(Ctx2<T>* ctxs, int splitsH, int splitsE) {
+  __shared__ cpx<double> sU[64];
+  Ctx2<T>& c = ctxs[blockIdx.x];
+  build_G(c.g, c.kraus, c.m, c.G, sU);
+  if (threadIdx.x != 0) return;
+  const int cl = *c.chil, cm = *c.chim, cr = *c.chir, k1 = *c.kap1, k2 = *c.kap2;
+  {  // Theta[(l t1 k1),(t2 k2 r)] = sum_m B_i[(l t1 k1), m] B_{i+1}[m, (t2 k2 r)]
+    GemmDesc& d = *c.dTheta;
+    clear_desc(d);
+    d.A = c.Bi; d.B = c.Bj; d.C = c.Theta;
+    d.M = cl * 2 * k1; d.K = cm; d.N = 2 * k2 * cr;
+    d.lda = cm; d.ldb = 2 * k2 * cr; d.ldc = 2 * k2 * cr;
+  }
+  {  // H[a][a'] = sum_l lambda_l^2 sum_(k2 r) conj(Theta[l][a][(k2 r)]) Theta[l][a'][(k2 r)], a = (t1 k1 t2)
+    GemmDesc& d = c.dGram[0];
+    void* C = d.C;
+    const long long ss = d.sSplit;
+    clear_desc(d);
+    d.C = C; d.sSplit = ss;
+    if (c.m <= 1) {
+      d.active = 0;
+    } else {
+      d.A = c.Theta; d.B = c.Theta; d.opA = OP_C; d.opB = OP_T;
+      d.M = d.N = 4 * k1;
+      d.K = cl * k2 * cr;
+      d.lda = d.ldb = k2 * cr;
+      d.kinner = k2 * cr;
+      d.kstride = (long long)4 * k1 * k2 * cr;
+      d.w = c.laml2; d.wdiv = k2 * cr;
+      d.ldc = 4 * k1;
+      d.splits = splitsH;
+    }
+  }
+  {  // E = F F^dag with F = B_{i+1} as [(m t2)] x [(k2 r)]
+    GemmDesc& d = c.dGram[1];
+    void* C = d.C;
+    const long long ss = d.sSplit;
+    clear_desc(d);
+    d.C = C; d.sSplit = ss;
+    d.A = c.Bj; d.B = c.Bj; d.opA = OP_N; d.opB = OP_H;
+    d.M = d.N = 2 * cm;
+    d.K = k2 * cr;
+    d.lda = d.ldb = k2 * cr;
+    d.ldc = 2 * cm;
+    d.splits = splitsE;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q2_gamma(Ctx2<T>* ctxs) {
+  __shared__ cpx<double> sOm[16 * 16 * 16];  // Omega_{jj'}[t][t'] for m <= 16
+  Ctx2<T>& c = ctxs[blockIdx.x];
+  const int m = c.m, k1 = *c.kap1, cm = *c.chim;
+  if (threadIdx.x == 0) {
+    EigDesc& d = c.dEig[1];
+    d.a = c.E; d.lda = 2 * cm; d.n = 2 * cm; d.evals = c.evE; d.evecs = c.vecE; d.active = 1;
+  }
+  if (m <= 1) {
+    if (threadIdx.x == 0) c.dEig[0].active = 0;
+    return;
+  }
+  const int n = k1 * m;
+  const bool om_lds = m <= 16;
+  if (om_lds) {
+    for (int e = threadIdx.x; e < m * m * 16; e += blockDim.x) {
+      const int j = e / (m * 16), j2 = (e / 16) % m, t = (e / 4) % 4, t2 = e % 4;
+      cpx<double> om = mk(0.0, 0.0);
+      for (int s = 0; s < 4; ++s) om = om + cconj(ld(c.G, j * 16 + s * 4 + t)) * ld(c.G, j2 * 16 + s * 4 + t2);
+      sOm[e] = om;
+    }
+  }
+  __syncthreads();
+  // Gamma[(kk j),(kk' j')] = sum_{t,t'} Omega_{jj'}[t,t'] H[h(t,kk)][h(t',kk')],
+  // h(t, kk) = ((t1 k1 + kk) 2 + t2) with t = 2 t1 + t2
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int a = e / n, b = e % n;
+    const int kk = a / m, j = a % m, kk2 = b / m, j2 = b % m;
+    cpx<double> acc = mk(0.0, 0.0);
+    for (int t = 0; t < 4; ++t) {
+      const int ha = ((t >> 1) * k1 + kk) * 2 + (t & 1);
+      for (int t2 = 0; t2 < 4; ++t2) {
+        const int hb = ((t2 >> 1) * k1 + kk2) * 2 + (t2 & 1);
+        cpx<double> om;
+        if (om_lds) {
+          om = sOm[((j * m + j2) * 4 + t) * 4 + t2];
+        } else {
+          om = mk(0.0, 0.0);
+          for (int s = 0; s < 4; ++s) om = om + cconj(ld(c.G, j * 16 + s * 4 + t)) * ld(c.G, j2 * 16 + s * 4 + t2);
+        }
+        acc = acc + om * ld(c.H, (long long)ha * (4 * k1) + hb);
+      }
+    }
+    st(c.Gam, e, acc);
+  }
+  if (threadIdx.x == 0) {
+    EigDesc& d = c.dEig[0];
+    d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.evG; d.evecs = c.vecG; d.active = 1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q2_select_a(Ctx2<T>* ctxs, int splitsC, TruncParams tp) {
+  __shared__ int s_kp, s_rF;
+  __shared__ double s_scale;
+  Ctx2<T>& c = ctxs[blockIdx.x];
+  const int m = c.m, k1 = *c.kap1, cl = *c.chil, cm = *c.chim;
+  if (threadIdx.x == 0) {
+    if (m <= 1) {
+      s_kp = k1;
+      s_scale = 1.0;
+    } else {
+      double kept, tot;
+      const int kp = select_rank(c.evG, k1 * m, tp.kap_max, tp.kap_cut, &kept, &tot);
+      s_kp = kp;
+      s_scale = 1.0 / sqrt(kept);
+      if (tot > 0) *c.disc += (tot - kept) / tot;
+    }
+    const int nE = 2 * cm;
+    int rF = 0;
+    const double e0 = c.evE[0];
+    for (int b = 0; b < nE; ++b) rF += (c.evE[b] > tp.tolE * e0) ? 1 : 0;
+    if (rF < 1) rF = 1;
+    s_rF = rF;
+    c.scratch[0] = s_kp;
+    c.scratch[1] = rF;
+  }
+  __syncthreads();
+  const int kp = s_kp, rF = s_rF;
+  const double sc = s_scale;
+  // W[(s1 nu s2),(t1 kk t2)] = scale sum_j G_j[(s1 s2),(t1 t2)] V[(kk j), nu]
+  const int rows = 4 * kp, cols = 4 * k1;
+  for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
+    const int row = e / cols, col = e % cols;
+    const int s1 = row / (2 * kp), nu = (row / 2) % kp, s2 = row % 2;
+    const int t1 = col / (2 * k1), kk = (col / 2) % k1, t2 = col % 2;
+    const int gs = s1 * 2 + s2, gt = t1 * 2 + t2;
+    cpx<double> acc = mk(0.0, 0.0);
+    if (m <= 1) {
+      if (nu == kk) acc = ld(c.G, gs * 4 + gt);
+    } else {
+      for (int j = 0; j < m; ++j)
+        acc = acc + ld(c.G, j * 16 + gs * 4 + gt) * ld(c.vecG, (long long)(kk * m + j) * (k1 * m) + nu);
+    }
+    c.W[e] = mk<T>((T)(sc * acc.re), (T)(sc * acc.im));
+  }
+  // L_F = P D^(1/2), PD = P D^(-1/2) on the r_F leading eigenvectors of E
+  const int nE = 2 * cm;
+  for (int e = threadIdx.x; e < nE * rF; e += blockDim.x) {
+    const int row = e / rF, b = e % rF;
+    const cpx<double> p = ld(c.vecE, (long long)row * nE + b);
+    const double dv = c.evE[b];
+    const double sq = sqrt(dv);
+    c.LF[e] = mk<T>((T)(p.re * sq), (T)(p.im * sq));
+    st(c.PD, e, mk(p.re / sq, p.im / sq));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    {  // th[(l t1 k1),(t2 b)] = sum_m B_i[(l t1 k1), m] L_F[(m t2), b]
+      GemmDesc& d = *c.dTh;
+      clear_desc(d);
+      d.A = c.Bi; d.B = c.LF; d.C = c.th;
+      d.M = cl * 2 * k1; d.K = cm; d.N = 2 * rF;
+      d.lda = cm; d.ldb = 2 * rF; d.ldc = 2 * rF;
+    }
+    {  // th2[l] = W th[l]
+      GemmDesc& d = *c.dTh2;
+      clear_desc(d);
+      d.A = c.W; d.B = c.th; d.C = c.th2;
+      d.M = 4 * kp; d.K = 4 * k1; d.N = rF;
+      d.lda = 4 * k1; d.ldb = rF; d.ldc = rF;
+      d.nbatch = cl; d.sA = 0; d.sB = (long long)4 * k1 * rF; d.sC = (long long)4 * kp * rF;
+    }
+    {  // C = th2^H diag(lambda_l^2) th2 over rows (l s1 nu)
+      GemmDesc& d = *c.dC;
+      void* C = d.C;
+      const long long ss = d.sSplit;
+      clear_desc(d);
+      d.C = C; d.sSplit = ss;
+      d.A = c.th2; d.B = c.th2; d.opA = OP_H; d.opB = OP_N;
+      d.M = d.N = 2 * rF;
+      d.K = cl * 2 * kp;
+      d.lda = d.ldb = 2 * rF;
+      d.w = c.laml2; d.wdiv = 2 * kp;
+      d.ldc = 2 * rF;
+      d.splits = splitsC;
+    }
+    {
+      EigDesc& d = *c.dEigC;
+      d.a = c.Cm; d.lda = 2 * rF; d.n = 2 * rF; d.evals = c.evC; d.evecs = c.vecC; d.active = 1;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q2_select_b(Ctx2<T>* ctxs, TruncParams tp) {
+  __shared__ int s_r;
+  __shared__ double s_scale;
+  Ctx2<T>& c = ctxs[blockIdx.x];
+  const int kp = c.scratch[0], rF = c.scratch[1];
+  const int cl = *c.chil, cm = *c.chim, cr = *c.chir, k2 = *c.kap2;
+  const int n = 2 * rF;
+  if (threadIdx.x == 0) {
+    double kept, tot;
+    const int r = select_rank(c.evC, n, tp.chi_max, tp.svd_cut, &kept, &tot);
+    s_r = r;
+    s_scale = 1.0 / sqrt(kept);
+    if (tot > 0) *c.disc += (tot - kept) / tot;
+  }
+  __syncthreads();
+  const int r = s_r;
+  const double sc = s_scale;
+  for (int v = threadIdx.x; v < r; v += blockDim.x) {
+    const double e = c.evC[v] > 0 ? c.evC[v] : 0.0;
+    c.lam[v] = sqrt(e) * sc;
+    c.lam2[v] = e * sc * sc;
+  }
+  // Zt[(nu s2)][b] = conj(Z[(s2 rF + b)][nu]),  Zc = Z[:, :r] in working precision
+  for (int e = threadIdx.x; e < 2 * r * rF; e += blockDim.x) {
+    const int row = e / rF, b = e % rF;
+    const int nu = row / 2, s2 = row % 2;
+    st(c.Zt, e, cconj(ld(c.vecC, (long long)(s2 * rF + b) * n + nu)));
+  }
+  for (int e = threadIdx.x; e < n * r; e += blockDim.x) {
+    const int row = e / r, nu = e % r;
+    const cpx<double> z = ld(c.vecC, (long long)row * n + nu);
+    c.Zc[e] = mk<T>((T)z.re, (T)z.im);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    {  // X[(nu s2),(m t2)] = sum_b Zt[(nu s2)][b] conj(PD[(m t2)][b])
+      GemmDesc& d = *c.dX;
+      clear_desc(d);
+      d.A = c.Zt; d.B = c.PD; d.C = c.X;
+      d.opB = OP_H;
+      d.M = 2 * r; d.K = rF; d.N = 2 * cm;
+      d.lda = rF; d.ldb = rF; d.ldc = 2 * cm;
+    }
+    {  // B_i' = scale th2 Z_r
+      GemmDesc& d = c.dOut[0];
+      clear_desc(d);
+      d.A = c.th2; d.B = c.Zc; d.C = c.Bi_new;
+      d.M = cl * 2 * kp; d.K = n; d.N = r;
+      d.lda = n; d.ldb = r; d.ldc = r;
+      d.alpha = sc;
+    }
+    {  // B_{i+1}' = X F
+      GemmDesc& d = c.dOut[1];
+      clear_desc(d);
+      d.A = c.X; d.B = c.Bj; d.C = c.Bj_new;
+      d.M = 2 * r; d.K = 2 * cm; d.N = k2 * cr;
+      d.lda = 2 * cm; d.ldb = k2 * cr; d.ldc = k2 * cr;
+    }
+    *c.chim = r;
+    *c.kap1 = kp;
+  }
+}
+
+// ============================================================================
+// transfer matrices
+// ============================================================================
+template <typename T>
+__global__ void k_transfer_init(CtxT<T>* ctxs) {
+  CtxT<T>& c = ctxs[blockIdx.x];
+  if (threadIdx.x == 0) c.Ecur[0] = mk<T>((T)1, (T)0);
+}
+
+// BO[l,s',k,r] = sum_s O[s',s] B[l,s,k,r]; descriptors of Y = E^T BO and
+// E' = Y^T conj(B).
+template <typename T>
+__global__ void k_transfer_prep(CtxT<T>* ctxs) {
+  CtxT<T>& c = ctxs[blockIdx.y];
+  if (!c.active) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) { c.d1->active = 0; c.d2->active = 0; }
+    return;
+  }
+  const int cl = *c.chil, cr = *c.chir, k = *c.kap;
+  const double* O = c.ops + 8 * c.site;
+  const cpx<T> o00 = mk<T>((T)O[0], (T)O[1]), o01 = mk<T>((T)O[2], (T)O[3]);
+  const cpx<T> o10 = mk<T>((T)O[4], (T)O[5]), o11 = mk<T>((T)O[6], (T)O[7]);
+  const long long half = (long long)k * cr;
+  const long long total = (long long)cl * half;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long l = e / half, rest = e % half;
+    const cpx<T> b0 = c.B[l * 2 * half + rest], b1 = c.B[l * 2 * half + half + rest];
+    c.BO[l * 2 * half + rest] = o00 * b0 + o01 * b1;
+    c.BO[l * 2 * half + half + rest] = o10 * b0 + o11 * b1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    GemmDesc& d1 = *c.d1;
+    clear_desc(d1);
+    d1.A = c.Ecur; d1.B = c.BO; d1.C = c.Y;
+    d1.opA = OP_T;
+    d1.M = cl; d1.K = cl; d1.N = 2 * k * cr;
+    d1.lda = cl; d1.ldb = 2 * k * cr; d1.ldc = 2 * k * cr;
+    GemmDesc& d2 = *c.d2;
+    clear_desc(d2);
+    d2.A = c.Y; d2.B = c.B; d2.C = c.Enext;
+    d2.opA = OP_T; d2.opB = OP_C;
+    d2.M = cr; d2.K = cl * 2 * k; d2.N = cr;
+    d2.lda = cr; d2.ldb = cr; d2.ldc = cr;
+  }
+}
+
+// out[item] = E_item / E_trace (complex); the trace item of each instance is
+// the identity string.
+template <typename T>
+__global__ void k_transfer_finish(CtxT<T>* ctxs, double* out) {
+  const int it = blockIdx.x;
+  const CtxT<T>& c = ctxs[it];
+  const cpx<T> v = c.Efinal[0];
+  double ta = 1.0;  // trace_idx < 0: raw value
+  if (c.trace_idx >= 0) ta = (double)ctxs[c.trace_idx].Efinal[0].re;
+  const double a = (double)v.re, b = (double)v.im;
+  out[2 * it] = a / ta;
+  out[2 * it + 1] = b / ta;
+}
+
+// ============================================================================
+// channels: chi -> Lambda -> Kraus
+// ============================================================================
+__device__ inline cpx<double> pauli_entry(int m, int a, int b, int q) {
+  cpx<double> v = mk(1.0, 0.0);
+  for (int t = 0; t < q; ++t) {
+    const int sh = q - 1 - t;
+    const int mt = (m >> (2 * sh)) & 3, at = (a >> sh) & 1, bt = (b >> sh) & 1;
+    cpx<double> e;
+    switch (mt) {
+      case 0: e = mk(at == bt ? 1.0 : 0.0, 0.0); break;
+      case 1: e = mk(at != bt ? 1.0 : 0.0, 0.0); break;
+      case 2: e = (at == bt) ? mk(0.0, 0.0) : (at == 0 ? mk(0.0, -1.0) : mk(0.0, 1.0)); break;
+      default: e = mk(at == bt ? (at == 0 ? 1.0 : -1.0) : 0.0, 0.0); break;
+    }
+    v = v * e;
+  }
+  return v;
+}
+
+// Lambda[(a b),(c e)] = sum_mn chi_mn sigma_m[a][b] conj(sigma_n[c][e])
+__global__ void k_choi(const double* chi, int q, double* lam) {
+  const int d = 1 << q, d2 = d * d;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < d2 * d2; e += gridDim.x * blockDim.x) {
+    const int x = e / d2, y = e % d2;
+    const int a = x / d, b = x % d, c2 = y / d, e2 = y % d;
+    cpx<double> acc = mk(0.0, 0.0);
+    for (int m = 0; m < d2; ++m) {
+      const cpx<double> pm = pauli_entry(m, a, b, q);
+      if (pm.re == 0 && pm.im == 0) continue;
+      for (int n = 0; n < d2; ++n) {
+        const cpx<double> pn = pauli_entry(n, c2, e2, q);
+        if (pn.re == 0 && pn.im == 0) continue;
+        acc = acc + (ld(chi, (long long)m * d2 + n) * pm) * cconj(pn);
+      }
+    }
+    st(lam, e, acc);
+  }
+}
+
+// K_i = sqrt(eta_i) unvec(psi_i) for the eta_i above rank_tol * eta_0 and of
+// weight >= eps.  info: [0] = kept count, [1] = completeness error of the
+// unpruned set, [2] = smallest eigenvalue, [3] = rank.
+__global__ void k_kraus_extract(const double* evals, const double* evecs, int q, double eps, double rank_tol,
+                                double* kraus, double* info) {
+  __shared__ int s_keep[64];
+  __shared__ int s_nk, s_rank;
+  __shared__ double s_err;
+  const int d = 1 << q, d2 = d * d;
+  if (threadIdx.x == 0) {
+    double tot = 0;
+    const double e0 = evals[0];
+    int rank = 0;
+    for (int i = 0; i < d2; ++i)
+      if (evals[i] > rank_tol * e0 && evals[i] > 0) { tot += evals[i]; ++rank; }
+    int nk = 0;
+    for (int i = 0; i < d2; ++i) {
+      if (!(evals[i] > rank_tol * e0 && evals[i] > 0)) continue;
+      if (evals[i] / tot < eps) continue;
+      s_keep[nk++] = i;
+    }
+    s_nk = nk;
+    s_rank = rank;
+    s_err = 0;
+  }
+  __syncthreads();
+  const int nk = s_nk;
+  for (int e = threadIdx.x; e < nk * d2; e += blockDim.x) {
+    const int kidx = e / d2, x = e % d2;
+    const int i = s_keep[kidx];
+    const double sq = sqrt(evals[i]);
+    const cpx<double> p = ld(evecs, (long long)x * d2 + i);
+    st(kraus, e, mk(sq * p.re, sq * p.im));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // completeness of the full-rank set: sum_i eta_i A_i^dag A_i = I
+    double err = 0;
+    const double e0 = evals[0];
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        cpx<double> acc = mk(0.0, 0.0);
+        for (int i = 0; i < d2; ++i) {
+          if (!(evals[i] > rank_tol * e0 && evals[i] > 0)) continue;
+          for (int t = 0; t < d; ++t)
+            acc = acc + evals[i] * (cconj(ld(evecs, (long long)(t * d + a) * d2 + i)) * ld(evecs, (long long)(t * d + b) * d2 + i));
+        }
+        if (a == b) acc.re -= 1.0;
+        const double v = sqrt(cabs2(acc));
+        err = v > err ? v : err;
+      }
+    info[0] = nk;
+    info[1] = err;
+    info[2] = evals[d2 - 1];
+    info[3] = s_rank;
+  }
+}
+
+template <typename T>
+__global__ void k_copy(const cpx<T>* src, cpx<T>* dst, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+// ============================================================================
+// launch wrappers
+// ============================================================================
+template <typename T> void launch_q1_prepare(Ctx1<T>* d, int n, int splitsH, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q1_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsH);
+}
+template <typename T> void launch_q1_gamma(Ctx1<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q1_gamma<T>, dim3(n), dim3(GT), 0, s, d);
+}
+template <typename T> void launch_q1_select(Ctx1<T>* d, int n, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q1_select<T>, dim3(n), dim3(GT), 0, s, d, tp);
+}
+template <typename T> void launch_q2_prepare(Ctx2<T>* d, int n, int splitsH, int splitsE, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q2_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsH, splitsE);
+}
+template <typename T> void launch_q2_gamma(Ctx2<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q2_gamma<T>, dim3(n), dim3(GT), 0, s, d);
+}
+template <typename T> void launch_q2_select_a(Ctx2<T>* d, int n, int splitsC, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q2_select_a<T>, dim3(n), dim3(GT), 0, s, d, splitsC, tp);
+}
+template <typename T> void launch_q2_select_b(Ctx2<T>* d, int n, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q2_select_b<T>, dim3(n), dim3(GT), 0, s, d, tp);
+}
+template <typename T> void launch_transfer_init(CtxT<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_transfer_init<T>, dim3(n), dim3(64), 0, s, d);
+}
+template <typename T> void launch_transfer_prep(CtxT<T>* d, int n, int maxElems, hipStream_t s) {
+  if (n <= 0) return;
+  int bx = (maxElems + 255) / 256;
+  if (bx < 1) bx = 1;
+  if (bx > 64) bx = 64;
+  hipLaunchKernelGGL(k_transfer_prep<T>, dim3(bx, n), dim3(256), 0, s, d);
+}
+template <typename T> void launch_transfer_finish(CtxT<T>* d, int n, double* out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_transfer_finish<T>, dim3(n), dim3(1), 0, s, d, out);
+}
+void launch_choi(const double* chi, int q, double* lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_choi, dim3(16), dim3(256), 0, s, chi, q, lam);
+}
+void launch_kraus_extract(const double* evals, const double* evecs, int q, double eps, double rank_tol,
+                          double* kraus, double* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_kraus_extract, dim3(1), dim3(256), 0, s, evals, evecs, q, eps, rank_tol, kraus, info);
+}
+template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_copy<T>, dim3(256), dim3(256), 0, s, src, dst, n);
+}
+
+#define INST(T)                                                                               \
+  template void launch_q1_prepare<T>(Ctx1<T>*, int, int, hipStream_t);                        \
+  template void launch_q1_gamma<T>(Ctx1<T>*, int, hipStream_t);                               \
+  template void launch_q1_select<T>(Ctx1<T>*, int, TruncParams, hipStream_t);                 \
+  template void launch_q2_prepare<T>(Ctx2<T>*, int, int, int, hipStream_t);                   \
+  template void launch_q2_gamma<T>(Ctx2<T>*, int, hipStream_t);                               \
+  template void launch_q2_select_a<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
+  template void launch_q2_select_b<T>(Ctx2<T>*, int, TruncParams, hipStream_t);              \
+  template void launch_transfer_init<T>(CtxT<T>*, int, hipStream_t);                          \
+  template void launch_transfer_prep<T>(CtxT<T>*, int, int, hipStream_t);                     \
+  template void launch_transfer_finish<T>(CtxT<T>*, int, double*, hipStream_t);          \
+  template void launch_copy_site<T>(const cpx<T>*, cpx<T>*, long long, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace mpdo

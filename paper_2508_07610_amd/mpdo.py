@@ -1,0 +1,298 @@
+"""Python binding of libmpdo (ctypes).  Argument marshalling only: every step
+of the simulation runs in the library's HIP kernels.
+
+The names follow the C ABI in ``include/mpdo.h``.  The binding fails loudly
+when ``libmpdo.so`` has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpdo.so")
+
+OK, EINVAL, ENOTCPTP, ENOMEM, EDEVICE, ENOTCONV, EUNSUPPORTED = range(7)
+C128, C64_MIXED = 0, 1
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTCPTP", 3: "ENOMEM", 4: "EDEVICE", 5: "ENOTCONV", 6: "EUNSUPPORTED"}
+
+EXPORTED = (
+    "mpdo_last_error", "mpdo_version", "mpdo_create", "mpdo_destroy", "mpdo_channel_from_chi",
+    "mpdo_channel_info", "mpdo_channel_destroy", "mpdo_apply_gate", "mpdo_apply_channel", "mpdo_flush",
+    "mpdo_truncate", "mpdo_expect", "mpdo_expect_products", "mpdo_fidelity_ghz", "mpdo_trace", "mpdo_dims",
+    "mpdo_bond_weights", "mpdo_batch_run",
+)
+
+
+class MPDOError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class mpdo_config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("chi_max", ctypes.c_int32), ("kappa_max", ctypes.c_int32),
+                ("max_kraus", ctypes.c_int32), ("svd_cutoff", ctypes.c_double),
+                ("kappa_cutoff", ctypes.c_double), ("prec", ctypes.c_int32)]
+
+
+class mpdo_op(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("site", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("param", ctypes.c_int32), ("scale", ctypes.c_double), ("chan", ctypes.c_int32),
+                ("fixed", ctypes.c_int32)]
+
+
+class mpdo_program(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nops", ctypes.c_int32), ("ops", ctypes.POINTER(mpdo_op)),
+                ("nobs", ctypes.c_int32), ("obs", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2508_07610_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    pd, pi = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    L.mpdo_last_error.restype = ctypes.c_char_p
+    L.mpdo_version.restype = ctypes.c_char_p
+    sig = {
+        "mpdo_create": [ctypes.POINTER(mpdo_config), vp, ctypes.POINTER(vp)],
+        "mpdo_destroy": [vp],
+        "mpdo_channel_from_chi": [pd, i32, dbl, vp, ctypes.POINTER(vp)],
+        "mpdo_channel_info": [vp, pi, pi, pd],
+        "mpdo_channel_destroy": [vp],
+        "mpdo_apply_gate": [vp, pi, i32, pd],
+        "mpdo_apply_channel": [vp, pi, i32, pd, vp],
+        "mpdo_flush": [vp],
+        "mpdo_truncate": [vp, i32, i32, dbl, pd],
+        "mpdo_expect": [vp, ctypes.c_char_p, pd, pd],
+        "mpdo_expect_products": [vp, pd, i32, pd],
+        "mpdo_fidelity_ghz": [vp, pd],
+        "mpdo_trace": [vp, pd],
+        "mpdo_dims": [vp, pi, pi, pd],
+        "mpdo_bond_weights": [vp, i32, pd, i32, pi],
+        "mpdo_batch_run": [ctypes.POINTER(mpdo_config), ctypes.POINTER(mpdo_program), i32, vp, i32, pd, i32,
+                           ctypes.POINTER(vp), i32, vp, i32, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise MPDOError(status, lib().mpdo_last_error().decode())
+
+
+def _cplx(a: np.ndarray) -> np.ndarray:
+    """Interleaved (re, im) float64 copy of a complex array."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    return a.view(np.float64).copy()
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def stream_handle(stream=None) -> Optional[int]:
+    """hipStream_t of a torch stream (or an int handle, or None = default)."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Channel:
+    """Process-tomography channel: chi (4^q x 4^q, Pauli basis) -> Kraus on the GPU."""
+
+    def __init__(self, chi: np.ndarray, q: int, eps: float = 0.0, stream=None):
+        chi = np.asarray(chi, dtype=np.complex128)
+        if chi.shape != (4 ** q, 4 ** q):
+            raise ValueError("chi must be 4^q x 4^q")
+        buf = _cplx(chi)
+        h = ctypes.c_void_p()
+        check(lib().mpdo_channel_from_chi(_dptr(buf), q, float(eps), stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.q = q
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        q, m = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().mpdo_channel_info(self._h, ctypes.byref(q), ctypes.byref(m), None))
+        d = 2 ** q.value
+        out = np.zeros(2 * m.value * d * d)
+        check(lib().mpdo_channel_info(self._h, None, None, _dptr(out)))
+        return out.view(np.complex128).reshape(m.value, d, d)
+
+    @property
+    def nkraus(self) -> int:
+        m = ctypes.c_int32()
+        check(lib().mpdo_channel_info(self._h, None, ctypes.byref(m), None))
+        return m.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mpdo_channel_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MPDO:
+    """One MPDO state on the GPU (see include/mpdo.h)."""
+
+    def __init__(self, n: int, chi_max: int, kappa_max: int, max_kraus: int = 16,
+                 svd_cutoff: float = 1e-14, kappa_cutoff: float = 1e-14, prec: int = C128, stream=None):
+        self.n = n
+        self.cfg = mpdo_config(n, chi_max, kappa_max, max_kraus, svd_cutoff, kappa_cutoff, prec)
+        h = ctypes.c_void_p()
+        check(lib().mpdo_create(ctypes.byref(self.cfg), stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mpdo_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @staticmethod
+    def _sites(sites: Sequence[int]):
+        arr = (ctypes.c_int32 * len(sites))(*sites)
+        return arr
+
+    def apply_gate(self, sites: Sequence[int], U: np.ndarray) -> None:
+        u = _cplx(U)
+        check(lib().mpdo_apply_gate(self._h, self._sites(sites), len(sites), _dptr(u)))
+
+    def apply_channel(self, sites: Sequence[int], ch: Channel, U: Optional[np.ndarray] = None) -> None:
+        u = None if U is None else _cplx(U)
+        check(lib().mpdo_apply_channel(self._h, self._sites(sites), len(sites), _dptr(u), ch.handle))
+
+    def flush(self) -> None:
+        check(lib().mpdo_flush(self._h))
+
+    def truncate(self, chi_max: int, kappa_max: int, cutoff: float) -> float:
+        d = ctypes.c_double()
+        check(lib().mpdo_truncate(self._h, chi_max, kappa_max, cutoff, ctypes.byref(d)))
+        return d.value
+
+    def expect(self, pauli: str) -> complex:
+        re, im = ctypes.c_double(), ctypes.c_double()
+        check(lib().mpdo_expect(self._h, pauli.encode(), ctypes.byref(re), ctypes.byref(im)))
+        return complex(re.value, im.value)
+
+    def expect_products(self, ops: np.ndarray) -> np.ndarray:
+        """ops: (nops, n, 2, 2) complex -> Tr(O rho)/Tr(rho) for each."""
+        ops = np.asarray(ops, dtype=np.complex128)
+        buf = _cplx(ops)
+        out = np.zeros(2 * ops.shape[0])
+        check(lib().mpdo_expect_products(self._h, _dptr(buf), ops.shape[0], _dptr(out)))
+        return out.view(np.complex128)
+
+    def fidelity_ghz(self) -> float:
+        f = ctypes.c_double()
+        check(lib().mpdo_fidelity_ghz(self._h, ctypes.byref(f)))
+        return f.value
+
+    def trace(self) -> float:
+        t = ctypes.c_double()
+        check(lib().mpdo_trace(self._h, ctypes.byref(t)))
+        return t.value
+
+    def dims(self):
+        b = (ctypes.c_int32 * max(1, self.n - 1))()
+        k = (ctypes.c_int32 * self.n)()
+        d = ctypes.c_double()
+        check(lib().mpdo_dims(self._h, b, k, ctypes.byref(d)))
+        return list(b)[: self.n - 1], list(k), d.value
+
+    def bond_weights(self, bond: int) -> np.ndarray:
+        cap = self.cfg.chi_max
+        out = np.zeros(cap)
+        ln = ctypes.c_int32()
+        check(lib().mpdo_bond_weights(self._h, bond, _dptr(out), cap, ctypes.byref(ln)))
+        return out[: ln.value].copy()
+
+
+def run_program(prog, state: MPDO, channels: Sequence[Channel]) -> MPDO:
+    """Apply a workloads.Program gate by gate through the C ABI."""
+    for op in prog.ops:
+        if op.chan >= 0:
+            state.apply_channel(op.sites, channels[op.chan], op.U)
+        else:
+            state.apply_gate(op.sites, op.U)
+    state.flush()
+    return state
+
+
+# ---------------------------------------------------------------------------
+# kernel-level test entry points (include/mpdo_testing.h)
+# ---------------------------------------------------------------------------
+def _testing_lib():
+    L = lib()
+    if not getattr(L, "_testing_sig", False):
+        pd = ctypes.POINTER(ctypes.c_double)
+        i32 = ctypes.c_int32
+        L.mpdo_test_gemm.argtypes = [i32] * 6 + [pd, i32, i32, pd, i32, i32, pd, i32, i32, ctypes.c_double, pd]
+        L.mpdo_test_gemm.restype = ctypes.c_int
+        L.mpdo_test_eigh.argtypes = [i32, pd, pd, pd, ctypes.POINTER(i32)]
+        L.mpdo_test_eigh.restype = ctypes.c_int
+        L._testing_sig = True
+    return L
+
+
+def test_gemm(prec: int, opA: int, opB: int, M: int, N: int, K: int, A: np.ndarray, B: np.ndarray,
+              w: Optional[np.ndarray] = None, wdiv: int = 1, splits: int = 1, alpha: float = 1.0) -> np.ndarray:
+    """Run the library GEMM kernel once: alpha op(A) op(B), A and B 2-D complex."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    B = np.ascontiguousarray(B, dtype=np.complex128)
+    a, b = _cplx(A), _cplx(B)
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros(2 * M * N)
+    check(_testing_lib().mpdo_test_gemm(prec, opA, opB, M, N, K, _dptr(a), A.shape[0], A.shape[1], _dptr(b),
+                                        B.shape[0], B.shape[1], _dptr(ww), wdiv, splits, alpha, _dptr(out)))
+    return out.view(np.complex128).reshape(M, N)
+
+
+def test_eigh(A: np.ndarray):
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    a = _cplx(A)
+    ev = np.zeros(n)
+    vec = np.zeros(2 * n * n)
+    sw = ctypes.c_int32()
+    check(_testing_lib().mpdo_test_eigh(n, _dptr(a), _dptr(ev), _dptr(vec), ctypes.byref(sw)))
+    return ev, vec.view(np.complex128).reshape(n, n), sw.value

@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point its headers declare, and rejects invalid arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2508_07610_amd import mpdo as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in ("mpdo.h", "mpdo_testing.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(mpdo_[a-z_0-9]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = M.lib()
+    declared = _declared()
+    assert {"mpdo_create", "mpdo_apply_gate", "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect",
+            "mpdo_batch_run"} <= declared
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(M.EXPORTED) <= declared
+
+
+def test_version_string():
+    assert b"gfx950" in M.lib().mpdo_version()
+
+
+@pytest.mark.parametrize("field,value", [("n", 0), ("n", 65), ("chi_max", 0), ("chi_max", 129), ("kappa_max", 0),
+                                         ("max_kraus", 0), ("svd_cutoff", -1.0), ("prec", 7)])
+def test_create_rejects_bad_config(field, value):
+    cfg = M.mpdo_config(6, 16, 4, 16, 1e-10, 1e-14, 0)
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p()
+    st = M.lib().mpdo_create(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert st == M.EINVAL
+    assert not h.value
+    assert len(M.lib().mpdo_last_error()) > 0
+
+
+def test_channel_rejects_bad_chi():
+    h = ctypes.c_void_p()
+    chi = np.zeros((4, 4), complex)
+    chi[0, 1] = 1.0                                   # not Hermitian
+    buf = chi.view(np.float64).copy()
+    assert M.lib().mpdo_channel_from_chi(M._dptr(buf), 1, 0.0, None, ctypes.byref(h)) == M.EINVAL
+    assert M.lib().mpdo_channel_from_chi(M._dptr(buf), 4, 0.0, None, ctypes.byref(h)) == M.EINVAL
+    chi = np.full((4, 4), np.nan, complex)
+    buf = chi.view(np.float64).copy()
+    assert M.lib().mpdo_channel_from_chi(M._dptr(buf), 1, 0.0, None, ctypes.byref(h)) == M.EINVAL
+
+
+def test_null_handles_are_rejected():
+    L = M.lib()
+    re_, im_ = ctypes.c_double(), ctypes.c_double()
+    assert L.mpdo_expect(None, b"Z", ctypes.byref(re_), ctypes.byref(im_)) == M.EINVAL
+    assert L.mpdo_flush(None) == M.EINVAL
+    assert L.mpdo_destroy(None) == M.OK
+    assert L.mpdo_channel_info(None, None, None, None) == M.EINVAL
+
+
+def test_test_entry_points_validate_sizes():
+    L = M.lib()
+    a = np.zeros(8)
+    assert L.mpdo_test_eigh(0, M._dptr(a), M._dptr(a), M._dptr(a), None) == M.EINVAL
+    L.mpdo_test_gemm.argtypes = [ctypes.c_int32] * 6 + [ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                                        ctypes.c_int32, ctypes.c_int32,
+                                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                                        ctypes.c_int32, ctypes.c_double,
+                                                        ctypes.POINTER(ctypes.c_double)]
+    # A too small for op(A) = N with M = 4 rows
+    assert L.mpdo_test_gemm(0, 0, 0, 4, 2, 2, M._dptr(a), 2, 2, M._dptr(a), 2, 2, None, 1, 1, 1.0,
+                            M._dptr(a)) == M.EINVAL

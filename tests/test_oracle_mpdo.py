@@ -197,3 +197,44 @@ def test_rank_selection_rule():
     assert mpdo.select_rank(eta, 10, 0.05) == 3
     assert mpdo.select_rank(eta, 2, 0.0) == 2
     assert mpdo.select_rank(np.array([1.0, -1e-18]), 5, 1e-14) == 1
+    # a multiplet straddling the cut is dropped whole
+    e = np.array([5.0, 3.0, 2.0, 2.0, 2.0, 1.0])
+    assert mpdo.select_rank(e, 3, 0.0) == 2
+    assert mpdo.select_rank(e, 5, 0.0) == 5
+    assert mpdo.select_rank(np.array([1.0, 1.0, 1.0]), 2, 0.0) == 2   # leading multiplet: plain rank
+
+
+def test_degenerate_cut_result_is_unique(monkeypatch):
+    """With the multiplet rule the truncated state does not depend on which
+    basis of a degenerate eigenspace the eigensolver returns: rotating every
+    degenerate eigenspace by a random unitary leaves the result unchanged."""
+    n, depth, chi, kap, tag = 6, 2, 16, 4, 0
+    prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, tag))
+    kr = _kraus(prog)
+    ref = mpdo.run_program(prog, mpdo.MPDO(n, chi, kap, 1e-10, 1e-14), kr)
+    rng = np.random.default_rng(0)
+    plain = mpdo._eigh_desc
+    hits = [0]
+
+    def scrambled(gram):
+        w, v = plain(gram)
+        i = 0
+        while i < len(w):
+            j = i + 1
+            while j < len(w) and abs(w[j] - w[i]) <= 1e-12 * abs(w[0]):
+                j += 1
+            if j - i > 1 and w[i] > 1e-10 * abs(w[0]):
+                hits[0] += 1
+                g = rng.normal(size=(j - i, j - i)) + 1j * rng.normal(size=(j - i, j - i))
+                q, _ = np.linalg.qr(g)
+                v[:, i:j] = v[:, i:j] @ q
+            i = j
+        return w, v
+
+    monkeypatch.setattr(mpdo, "_eigh_desc", scrambled)
+    alt = mpdo.run_program(prog, mpdo.MPDO(n, chi, kap, 1e-10, 1e-14), kr)
+    assert hits[0] > 0
+    assert alt.bond_dims() == ref.bond_dims()
+    for s in W.zz_strings(n):
+        assert abs(alt.expect_pauli(s) - ref.expect_pauli(s)) < 1e-12
+    assert abs(alt.fidelity_ghz() - ref.fidelity_ghz()) < 1e-12
