@@ -29,10 +29,14 @@ mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, in
                            const double* A, int32_t rowsA, int32_t lda, const double* B, int32_t rowsB,
                            int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha, double* C);
 
-/* Hermitian eigendecomposition of A (n x n, 1 <= n <= 512) with the Jacobi
- * kernel: evals descending (n doubles), evecs as columns (n x n complex).
- * *sweeps receives the sweep count (negative if not converged). */
-mpdo_status mpdo_test_eigh(int32_t n, const double* A, double* evals, double* evecs, int32_t* sweeps);
+/* Hermitian eigendecomposition of A (n x n, 1 <= n <= 512) with the
+ * library's eigensolver: the leading min(n, kvec + 1) eigenvalues in
+ * descending order in evals (the rest of the n entries zero), the
+ * eigenvectors of the leading kvec eigenvalues as the first kvec columns of
+ * evecs (n x n complex, row-major; eigenvectors of eigenvalues at or below
+ * 1e-13 times the largest are zero), and Tr(A) in *trace (may be NULL). */
+mpdo_status mpdo_test_eigh(int32_t n, int32_t kvec, const double* A, double* evals, double* evecs,
+                           double* trace);
 
 #ifdef __cplusplus
 }

@@ -50,11 +50,14 @@ import numpy as np
 
 TIE_REL = 1e-9     # eigenvalues closer than this (relative) form one multiplet
 TIE_FLOOR = 1e-11  # ... unless they carry less than this fraction of the weight
+NUM_ZERO = 1e-13   # eigenvalues at or below this fraction of the largest are zero
 
 
 def select_rank(eta: np.ndarray, max_dim: int, cutoff: float) -> int:
     """Smallest r >= 1 with sum_{i>=r} eta_i <= cutoff * W, capped at max_dim.
     eta is in descending order; negative round-off values count as zero.
+    Eigenvalues at or below NUM_ZERO times the largest are numerically zero
+    (the numerical rank of an FP64 Gram matrix) and never kept.
 
     A degenerate multiplet straddling the cut is dropped as a whole (r is
     lowered until eta_{r-1} and eta_r differ), so the kept subspace -- and
@@ -71,7 +74,8 @@ def select_rank(eta: np.ndarray, max_dim: int, cutoff: float) -> int:
         if tail[cand] <= cutoff * W:
             r = cand
             break
-    r = int(max(1, min(r, max_dim)))
+    nz = int(np.sum(e > NUM_ZERO * e[0]))
+    r = int(max(1, min(r, max_dim, nz)))
     r0 = r
     while 1 < r < len(e) and e[r - 1] > TIE_FLOOR * W and e[r - 1] - e[r] <= TIE_REL * e[r - 1]:
         r -= 1

@@ -155,9 +155,9 @@ mpdo_status mpdo_channel_from_chi(const double* chi, int32_t q, double eps, void
   DevBuf dchi, dlam, dev, dvec, dwork, dinfo, ddesc, dkr;
   dchi.alloc(sizeof(double) * 2 * d2 * d2);
   dlam.alloc(sizeof(double) * 2 * d2 * d2);
-  dev.alloc(sizeof(double) * d2);
+  dev.alloc(sizeof(double) * (d2 + 1));
   dvec.alloc(sizeof(double) * 2 * d2 * d2);
-  dwork.alloc(sizeof(double) * 2 * d2 * d2);
+  dwork.alloc(sizeof(double) * eig_work_doubles(d2));
   dinfo.alloc(sizeof(double) * 4);
   dkr.alloc(sizeof(double) * 2 * d2 * d2);
   ddesc.alloc(sizeof(EigDesc));
@@ -165,7 +165,7 @@ mpdo_status mpdo_channel_from_chi(const double* chi, int32_t q, double eps, void
   EigDesc ed;
   std::memset(&ed, 0, sizeof(ed));
   ed.a = dlam.as<double>(); ed.lda = d2; ed.n = d2; ed.evals = dev.as<double>(); ed.evecs = dvec.as<double>();
-  ed.work = dwork.as<double>(); ed.active = 1;
+  ed.work = dwork.as<double>(); ed.trace = dev.as<double>() + d2; ed.kvec = d2; ed.active = 1;
   hip_check(hipMemcpyAsync(ddesc.p, &ed, sizeof(ed), hipMemcpyHostToDevice, st), "upload desc");
   launch_choi(dchi.as<double>(), q, dlam.as<double>(), st);
   DevBuf dsw;
@@ -177,7 +177,7 @@ mpdo_status mpdo_channel_from_chi(const double* chi, int32_t q, double eps, void
   hip_check(hipMemcpyAsync(info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, st), "info");
   hip_check(hipMemcpyAsync(&sweeps, dsw.p, sizeof(int), hipMemcpyDeviceToHost, st), "info");
   hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-  if (sweeps < 0) return fail(MPDO_ENOTCONV, "Choi eigensolver did not converge");
+  if (sweeps != 1) return fail(MPDO_EDEVICE, "Choi eigensolver did not run");
   if (!(info[1] <= 1e-8)) return fail(MPDO_ENOTCPTP, "sum K^dag K differs from I by " + std::to_string(info[1]));
   const int m = (int)info[0];
   if (m < 1) return fail(MPDO_ENOTCPTP, "no Kraus operator kept");
@@ -481,22 +481,26 @@ extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, in
   GUARD_END
 }
 
-extern "C" mpdo_status mpdo_test_eigh(int32_t n, const double* A, double* evals, double* evecs, int32_t* sweeps) {
+extern "C" mpdo_status mpdo_test_eigh(int32_t n, int32_t kvec, const double* A, double* evals, double* evecs,
+                                      double* trace) {
   if (n < 1 || n > 512) return fail(MPDO_EINVAL, "n must be in [1, 512]");
+  if (kvec < 0) return fail(MPDO_EINVAL, "kvec must be >= 0");
   if (!A || !evals || !evecs) return fail(MPDO_EINVAL, "null buffer");
   GUARD_BEGIN
   DevBuf da, de, dv, dw, dd, ds;
   const size_t nn = (size_t)2 * n * n;
   da.alloc(nn * 8);
-  de.alloc((size_t)n * 8);
+  de.alloc((size_t)(n + 1) * 8);
   dv.alloc(nn * 8);
-  dw.alloc(nn * 8);
+  dw.alloc((size_t)eig_work_doubles(n) * 8);
   ds.alloc(sizeof(int));
   hip_check(hipMemcpy(da.p, A, nn * 8, hipMemcpyHostToDevice), "A");
+  hip_check(hipMemset(dv.p, 0, nn * 8), "zero");
+  hip_check(hipMemset(ds.p, 0, sizeof(int)), "zero");
   EigDesc d;
   std::memset(&d, 0, sizeof(d));
   d.a = da.as<double>(); d.lda = n; d.n = n; d.evals = de.as<double>(); d.evecs = dv.as<double>();
-  d.work = dw.as<double>(); d.active = 1;
+  d.work = dw.as<double>(); d.trace = de.as<double>() + n; d.kvec = kvec; d.active = 1;
   dd.alloc(sizeof(d));
   hip_check(hipMemcpy(dd.p, &d, sizeof(d), hipMemcpyHostToDevice), "desc");
   launch_eigh(dd.as<EigDesc>(), 1, n, ds.as<int>(), nullptr);
@@ -504,9 +508,10 @@ extern "C" mpdo_status mpdo_test_eigh(int32_t n, const double* A, double* evals,
   hip_check(hipDeviceSynchronize(), "sync");
   hip_check(hipMemcpy(evals, de.p, (size_t)n * 8, hipMemcpyDeviceToHost), "evals");
   hip_check(hipMemcpy(evecs, dv.p, nn * 8, hipMemcpyDeviceToHost), "evecs");
-  int sw = 0;
-  hip_check(hipMemcpy(&sw, ds.p, sizeof(int), hipMemcpyDeviceToHost), "sweeps");
-  if (sweeps) *sweeps = sw;
+  int ran = 0;
+  hip_check(hipMemcpy(&ran, ds.p, sizeof(int), hipMemcpyDeviceToHost), "status");
+  if (trace) hip_check(hipMemcpy(trace, de.as<double>() + n, 8, hipMemcpyDeviceToHost), "trace");
+  if (ran != 1) return fail(MPDO_EDEVICE, "eigensolver kernel did not run");
   return MPDO_OK;
   GUARD_END
 }

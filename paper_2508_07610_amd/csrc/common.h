@@ -51,19 +51,31 @@ struct GemmDesc {
   double alpha;
 };
 
-// A Hermitian eigenproblem of size n (<= nmax) for the Jacobi solver.
-// The matrix at `a` (n x n, row-major with leading dimension lda, complex
-// double) is destroyed.  Eigenvalues are written in descending order to
-// `evals`, eigenvectors as the columns of `evecs` (n x n, leading dimension
-// n).  `work` holds n*n complex doubles.
+// A Hermitian eigenproblem of size n (1 <= n <= 512).  The matrix at `a`
+// (n x n, row-major, leading dimension lda, complex double) is read only.
+// The leading kb = min(n, kvec + 1) eigenvalues are written in descending
+// order to evals[0..kb) (the rest of evals[0..n) is set to zero), *trace
+// receives Tr(A), and the eigenvectors of the leading kvec eigenvalues are
+// written as the columns of `evecs` (n x kvec used of an n x n array with
+// leading dimension n).  Eigenvectors of eigenvalues at or below
+// EIG_FLOOR * evals[0] are returned as zero (numerical null space).
+// `work` must hold eig_work_doubles(n) doubles.
 struct EigDesc {
   double* a;
   double* evals;
   double* evecs;
   double* work;
+  double* trace;
   int n, lda;
+  int kvec;
   int active;
-  int pad;
 };
+
+constexpr double EIG_FLOOR = 1e-13;
+constexpr int EIG_THREADS = 256;
+
+__host__ __device__ inline long long eig_work_doubles(int n) {
+  return 2LL * n * n + 5LL * EIG_THREADS * n + 16LL * n + 64;
+}
 
 }  // namespace mpdo

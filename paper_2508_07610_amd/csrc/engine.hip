@@ -156,9 +156,9 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
   const size_t oH = w.add((size_t)4 * kx * kx * 16);
   const size_t oHp = w.add((size_t)splitsH * 4 * kx * kx * 16);
   const size_t oGam = w.add((size_t)ng * ng * 16);
-  const size_t oEv = w.add((size_t)ng * 8);
+  const size_t oEv = w.add((size_t)(ng + 1) * 8);
   const size_t oVec = w.add((size_t)ng * ng * 16);
-  const size_t oWk = w.add((size_t)ng * ng * 16);
+  const size_t oWk = w.add((size_t)eig_work_doubles(ng) * 8);
   const size_t oW = w.add((size_t)4 * kx * kx * sizeof(cpx<T>));
   const size_t per = w.off;
   work_.alloc(per * n);
@@ -211,6 +211,7 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
     dh.sSplit = (long long)4 * kx * kx;
     EigDesc& de = at<EigDesc>(h, uE)[it];
     de.work = at<double>(base, oWk);
+    de.kvec = kx;
     at<double*>(h, uOut)[it] = c.H;
   }
   hip_check(hipMemcpyAsync(blob_.p, h, u.off, hipMemcpyHostToDevice, st_), "upload");
@@ -249,15 +250,15 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   const size_t oE = w.add((size_t)4 * cx * cx * 16);
   const size_t oEp = w.add((size_t)splitsE * 4 * cx * cx * 16);
   const size_t oGam = w.add((size_t)ng * ng * 16);
-  const size_t oEvG = w.add((size_t)ng * 8);
+  const size_t oEvG = w.add((size_t)(ng + 1) * 8);
   const size_t oVecG = w.add((size_t)ng * ng * 16);
-  const size_t oWkG = w.add((size_t)ng * ng * 16);
-  const size_t oEvE = w.add((size_t)2 * cx * 8);
+  const size_t oWkG = w.add((size_t)eig_work_doubles(ng) * 8);
+  const size_t oEvE = w.add((size_t)(2 * cx + 1) * 8);
   const size_t oVecE = w.add((size_t)4 * cx * cx * 16);
-  const size_t oWkE = w.add((size_t)4 * cx * cx * 16);
-  const size_t oEvC = w.add((size_t)4 * cx * 8);
+  const size_t oWkE = w.add((size_t)eig_work_doubles(2 * cx) * 8);
+  const size_t oEvC = w.add((size_t)(4 * cx + 1) * 8);
   const size_t oVecC = w.add((size_t)16 * cx * cx * 16);
-  const size_t oWkC = w.add((size_t)16 * cx * cx * 16);
+  const size_t oWkC = w.add((size_t)eig_work_doubles(4 * cx) * 8);
   const size_t oW = w.add((size_t)16 * kx * kx * sizeof(cpx<T>));
   const size_t oLF = w.add((size_t)4 * cx * cx * sizeof(cpx<T>));
   const size_t oPD = w.add((size_t)4 * cx * cx * 16);
@@ -355,11 +356,14 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
     hg[1].sSplit = (long long)4 * cx * cx;
     EigDesc* he = at<EigDesc>(h, uEig) + 2 * it;
     he[0].work = at<double>(base, oWkG);
+    he[0].kvec = kx;
     he[1].work = at<double>(base, oWkE);
+    he[1].kvec = 2 * cx;  // every eigenpair of the right-factor Gram
     GemmDesc& hc = at<GemmDesc>(h, uC)[it];
     hc.C = at<double>(base, oCp);
     hc.sSplit = (long long)16 * cx * cx;
     at<EigDesc>(h, uEigC)[it].work = at<double>(base, oWkC);
+    at<EigDesc>(h, uEigC)[it].kvec = cx;
     at<double*>(h, uOutsG)[2 * it] = c.H;
     at<double*>(h, uOutsG)[2 * it + 1] = c.E;
     at<double*>(h, uOutsC)[it] = c.Cm;

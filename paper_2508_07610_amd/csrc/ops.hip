@@ -61,24 +61,31 @@ __device__ void build_G(const GateSrc& g, const double* kraus, int m, double* G,
 
 // Smallest r >= 1 with sum_{i >= r} eta_i <= cut * W (W = sum of positive
 // eta), capped at maxd; also returns the kept and total weights.
-__device__ int select_rank(const double* eta, int n, int maxd, double cut, double* kept, double* total) {
-  double W = 0;
-  for (int i = 0; i < n; ++i) W += eta[i] > 0 ? eta[i] : 0;
+// eta: the leading kb eigenvalues (descending) of a Gram matrix of size n
+// and trace W.  Eigenvalues at or below EIG_FLOOR * eta_0 are numerically
+// zero and never kept.
+__device__ int select_rank(const double* eta, int kb, int n, double W, int maxd, double cut, double* kept,
+                           double* total) {
+  if (W < 0) W = 0;
+  int nz = 0;  // numerical rank among the computed eigenvalues
+  while (nz < kb && eta[nz] > EIG_FLOOR * eta[0] && eta[0] > 0) ++nz;
   int r = n;
-  double tail = 0;
-  // scan from the end: tail after index r-1 is sum_{i >= r}
-  for (int cand = n - 1; cand >= 1; --cand) {
-    tail += eta[cand] > 0 ? eta[cand] : 0;
-    if (tail <= cut * W) r = cand;
-    else break;
+  double head = 0;
+  for (int cand = 1; cand <= kb; ++cand) {
+    head += eta[cand - 1] > 0 ? eta[cand - 1] : 0;
+    if (W - head <= cut * W) {
+      r = cand;
+      break;
+    }
   }
+  if (r > nz) r = nz;
   if (r > maxd) r = maxd;
   if (r < 1) r = 1;
   // a degenerate multiplet straddling the cut is dropped whole, so the kept
   // subspace is unique (multiplets below 1e-11 of the weight are left alone)
   const int r0 = r;
-  while (r > 1 && r < n && eta[r - 1] > 1e-11 * W && eta[r - 1] - eta[r] <= 1e-9 * eta[r - 1]) --r;
-  if (r == 1 && n > 1 && eta[0] - eta[1] <= 1e-9 * eta[0]) r = r0;
+  while (r > 1 && r < kb && eta[r - 1] > 1e-11 * W && eta[r - 1] - eta[r] <= 1e-9 * eta[r - 1]) --r;
+  if (r == 1 && kb > 1 && eta[0] - eta[1] <= 1e-9 * eta[0]) r = r0;
   double k = 0;
   for (int i = 0; i < r; ++i) k += eta[i] > 0 ? eta[i] : 0;
   *kept = k;
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(GT) void k_q1_gamma(Ctx1<T>* ctxs) {
   }
   if (threadIdx.x == 0) {
     EigDesc& d = *c.dE;
-    d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.ev; d.evecs = c.evec; d.active = 1;
+    d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.ev; d.evecs = c.evec; d.trace = c.ev + n; d.active = 1;
   }
 }
 
@@ -167,7 +174,8 @@ __global__ __launch_bounds__(GT) void k_q1_select(Ctx1<T>* ctxs, TruncParams tp)
       s_scale = 1.0;
     } else {
       double kept, tot;
-      const int kp = select_rank(c.ev, k * m, tp.kap_max, tp.kap_cut, &kept, &tot);
+      const int ng = k * m;
+      const int kp = select_rank(c.ev, min(ng, tp.kap_max + 1), ng, c.ev[ng], tp.kap_max, tp.kap_cut, &kept, &tot);
       s_kp = kp;
       s_scale = 1.0 / sqrt(kept);
       if (tot > 0) *c.disc += (tot - kept) / tot;
@@ -263,7 +271,8 @@ __global__ __launch_bounds__(GT) void k_q2_gamma(Ctx2<T>* ctxs) {
   const int m = c.m, k1 = *c.kap1, cm = *c.chim;
   if (threadIdx.x == 0) {
     EigDesc& d = c.dEig[1];
-    d.a = c.E; d.lda = 2 * cm; d.n = 2 * cm; d.evals = c.evE; d.evecs = c.vecE; d.active = 1;
+    d.a = c.E; d.lda = 2 * cm; d.n = 2 * cm; d.evals = c.evE; d.evecs = c.vecE; d.trace = c.evE + 2 * cm;
+    d.active = 1;
   }
   if (m <= 1) {
     if (threadIdx.x == 0) c.dEig[0].active = 0;
@@ -304,7 +313,7 @@ __global__ __launch_bounds__(GT) void k_q2_gamma(Ctx2<T>* ctxs) {
   }
   if (threadIdx.x == 0) {
     EigDesc& d = c.dEig[0];
-    d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.evG; d.evecs = c.vecG; d.active = 1;
+    d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.evG; d.evecs = c.vecG; d.trace = c.evG + n; d.active = 1;
   }
 }
 
@@ -320,7 +329,8 @@ __global__ __launch_bounds__(GT) void k_q2_select_a(Ctx2<T>* ctxs, int splitsC, 
       s_scale = 1.0;
     } else {
       double kept, tot;
-      const int kp = select_rank(c.evG, k1 * m, tp.kap_max, tp.kap_cut, &kept, &tot);
+      const int ng = k1 * m;
+      const int kp = select_rank(c.evG, min(ng, tp.kap_max + 1), ng, c.evG[ng], tp.kap_max, tp.kap_cut, &kept, &tot);
       s_kp = kp;
       s_scale = 1.0 / sqrt(kept);
       if (tot > 0) *c.disc += (tot - kept) / tot;
@@ -396,7 +406,8 @@ __global__ __launch_bounds__(GT) void k_q2_select_a(Ctx2<T>* ctxs, int splitsC, 
     }
     {
       EigDesc& d = *c.dEigC;
-      d.a = c.Cm; d.lda = 2 * rF; d.n = 2 * rF; d.evals = c.evC; d.evecs = c.vecC; d.active = 1;
+      d.a = c.Cm; d.lda = 2 * rF; d.n = 2 * rF; d.evals = c.evC; d.evecs = c.vecC; d.trace = c.evC + 2 * rF;
+      d.active = 1;
     }
   }
 }
@@ -411,7 +422,7 @@ __global__ __launch_bounds__(GT) void k_q2_select_b(Ctx2<T>* ctxs, TruncParams t
   const int n = 2 * rF;
   if (threadIdx.x == 0) {
     double kept, tot;
-    const int r = select_rank(c.evC, n, tp.chi_max, tp.svd_cut, &kept, &tot);
+    const int r = select_rank(c.evC, min(n, tp.chi_max + 1), n, c.evC[n], tp.chi_max, tp.svd_cut, &kept, &tot);
     s_r = r;
     s_scale = 1.0 / sqrt(kept);
     if (tot > 0) *c.disc += (tot - kept) / tot;

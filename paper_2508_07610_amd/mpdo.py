@@ -268,7 +268,7 @@ def _testing_lib():
         i32 = ctypes.c_int32
         L.mpdo_test_gemm.argtypes = [i32] * 6 + [pd, i32, i32, pd, i32, i32, pd, i32, i32, ctypes.c_double, pd]
         L.mpdo_test_gemm.restype = ctypes.c_int
-        L.mpdo_test_eigh.argtypes = [i32, pd, pd, pd, ctypes.POINTER(i32)]
+        L.mpdo_test_eigh.argtypes = [i32, i32, pd, pd, pd, pd]
         L.mpdo_test_eigh.restype = ctypes.c_int
         L._testing_sig = True
     return L
@@ -287,12 +287,14 @@ def test_gemm(prec: int, opA: int, opB: int, M: int, N: int, K: int, A: np.ndarr
     return out.view(np.complex128).reshape(M, N)
 
 
-def test_eigh(A: np.ndarray):
+def test_eigh(A: np.ndarray, kvec: Optional[int] = None):
+    """Library eigensolver on host data: (leading eigenvalues, eigenvectors, trace)."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     n = A.shape[0]
+    kvec = n if kvec is None else kvec
     a = _cplx(A)
     ev = np.zeros(n)
     vec = np.zeros(2 * n * n)
-    sw = ctypes.c_int32()
-    check(_testing_lib().mpdo_test_eigh(n, _dptr(a), _dptr(ev), _dptr(vec), ctypes.byref(sw)))
-    return ev, vec.view(np.complex128).reshape(n, n), sw.value
+    tr = ctypes.c_double()
+    check(_testing_lib().mpdo_test_eigh(n, kvec, _dptr(a), _dptr(ev), _dptr(vec), ctypes.byref(tr)))
+    return ev, vec.view(np.complex128).reshape(n, n), tr.value

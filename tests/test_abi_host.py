@@ -72,7 +72,8 @@ def test_null_handles_are_rejected():
 def test_test_entry_points_validate_sizes():
     L = M.lib()
     a = np.zeros(8)
-    assert L.mpdo_test_eigh(0, M._dptr(a), M._dptr(a), M._dptr(a), None) == M.EINVAL
+    M._testing_lib()
+    assert L.mpdo_test_eigh(0, 1, M._dptr(a), M._dptr(a), M._dptr(a), None) == M.EINVAL
     L.mpdo_test_gemm.argtypes = [ctypes.c_int32] * 6 + [ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                                         ctypes.c_int32, ctypes.c_int32,

@@ -62,21 +62,40 @@ def test_gemm_split_k_and_weights():
     assert err < 1e-13, err
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 32, 64, 65, 100, 128, 256])
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 32, 64, 65, 100, 128, 256, 512])
 def test_eigh_against_numpy(n):
     require_gpu()
     rng = np.random.default_rng(n)
     X = _rand((n, n + 3), rng)
     A = X @ X.conj().T                      # Gram-like PSD
-    ev, V, sweeps = M.test_eigh(A)
-    assert sweeps >= 0
+    ev, V, tr = M.test_eigh(A)
     ref = np.sort(np.linalg.eigvalsh(A))[::-1]
     scale = float(np.abs(ref).max())
     e1 = float(np.abs(ev - ref).max()) / scale
     e2 = float(np.abs(V.conj().T @ V - np.eye(n)).max())
     e3 = float(np.abs(A @ V - V * ev).max()) / scale
-    assert e1 <= 1e-13 and e2 < 1e-12 and e3 < 1e-12, (e1, e2, e3, sweeps)
+    assert e1 <= 1e-13 and e2 < 1e-12 and e3 < 1e-12, (e1, e2, e3)
+    assert abs(tr - np.trace(A).real) < 1e-12 * scale * n
     assert bool(np.all(np.diff(ev) <= 0))
+
+
+@pytest.mark.parametrize("n,kvec", [(40, 5), (128, 16), (256, 64), (300, 100)])
+def test_eigh_leading_subset(n, kvec):
+    """Only the leading kvec eigenpairs (and kvec + 1 eigenvalues) are produced."""
+    require_gpu()
+    rng = np.random.default_rng(n + kvec)
+    X = _rand((n, n // 2), rng)              # rank-deficient
+    A = X @ X.conj().T
+    ev, V, tr = M.test_eigh(A, kvec)
+    ref = np.sort(np.linalg.eigvalsh(A))[::-1]
+    scale = float(ref[0])
+    kb = min(n, kvec + 1)
+    assert float(np.abs(ev[:kb] - ref[:kb]).max()) <= 1e-13 * scale
+    assert bool(np.all(ev[kb:] == 0))
+    Vk = V[:, :kvec]
+    e2 = float(np.abs(Vk.conj().T @ Vk - np.eye(kvec)).max())
+    e3 = float(np.abs(A @ Vk - Vk * ev[:kvec]).max()) / scale
+    assert e2 < 1e-12 and e3 < 1e-12, (e2, e3)
 
 
 def test_eigh_rank_deficient_and_degenerate():
@@ -85,8 +104,7 @@ def test_eigh_rank_deficient_and_degenerate():
     Q, _ = np.linalg.qr(_rand((40, 40), rng))
     d = np.array([5.0, 5.0, 2.0] + [1e-9] * 5 + [0.0] * 32)
     A = (Q * d) @ Q.conj().T
-    ev, V, sweeps = M.test_eigh(A)
-    assert sweeps > 0
+    ev, V, _ = M.test_eigh(A)
     e1 = float(np.abs(ev - np.sort(d)[::-1]).max())
     assert e1 < 1e-13 * 5, e1
     # the leading eigenspace (degenerate pair) is recovered exactly
@@ -94,3 +112,20 @@ def test_eigh_rank_deficient_and_degenerate():
     Pref = Q[:, :2] @ Q[:, :2].conj().T
     e2 = float(np.abs(P - Pref).max())
     assert e2 < 1e-12, e2
+    # the 1e-9 multiplet: an orthonormal basis of its eigenspace
+    P = V[:, 3:8] @ V[:, 3:8].conj().T
+    Pref = Q[:, 3:8] @ Q[:, 3:8].conj().T
+    assert float(np.abs(P - Pref).max()) < 1e-6
+    # null space (below 1e-13 of the largest eigenvalue): zero vectors
+    assert float(np.abs(V[:, 8:]).max()) == 0.0
+
+
+def test_eigh_diagonal_and_tiny():
+    """Already-diagonal input (every reflector trivial) and a 1 x 1 matrix."""
+    require_gpu()
+    d = np.array([3.0, -1.0, 2.0, 0.5])
+    ev, V, tr = M.test_eigh(np.diag(d).astype(complex))
+    assert np.allclose(ev, [3.0, 2.0, 0.5, -1.0], atol=1e-15)
+    assert abs(tr - d.sum()) < 1e-15
+    ev, V, tr = M.test_eigh(np.array([[2.5 + 0j]]))
+    assert abs(ev[0] - 2.5) < 1e-15 and abs(abs(V[0, 0]) - 1) < 1e-15
