@@ -72,10 +72,12 @@ struct EigDesc {
 };
 
 constexpr double EIG_FLOOR = 1e-13;
-constexpr int EIG_THREADS = 256;
+constexpr int EIG_THREADS = 1024;
 
+// matrix (2 n^2) + two n x np solve vectors + four n x np factor arrays
 __host__ __device__ inline long long eig_work_doubles(int n) {
-  return 2LL * n * n + 5LL * EIG_THREADS * n + 16LL * n + 64;
+  const long long np = (n + 63) / 64 * 64;
+  return 2LL * n * n + 6LL * n * np + 64;
 }
 
 }  // namespace mpdo
