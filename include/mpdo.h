@@ -195,9 +195,14 @@ typedef struct {
  * params_dev + b * param_stride.  fixed_u: host, nfixed 4x4 complex
  * (2-qubit) or 2x2 (1-qubit, stored in the top-left of a 4x4 slot).
  * chans: channel handles.  cfg: chi_max, kappa_max, cutoffs, precision for
- * all instances (cfg->n ignored).  Enqueued on hip_stream; the call returns
- * after enqueueing (out_dev is stream-ordered).  `use_graph` != 0 captures
- * the run into a HIP graph and launches it once. */
+ * all instances (cfg->n ignored).  Gates are grouped per instance into
+ * sublayers on disjoint sites (an op joins the first group after the last
+ * one touching its sites) and the k-th sublayers of all instances run as one
+ * ragged launch sequence.  `use_graph` != 0 captures the whole run (one
+ * descriptor upload, every sublayer, the observables) into one HIP graph and
+ * launches it once; with hip_stream NULL a private stream is used for the
+ * capture.  The call returns when the results are in out_dev.  Returns
+ * EINVAL for malformed programs, EUNSUPPORTED for 3-qubit ops. */
 mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
                            const double* params_dev, int32_t param_stride,
                            const double* fixed_u, int32_t nfixed,

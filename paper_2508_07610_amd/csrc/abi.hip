@@ -394,9 +394,170 @@ mpdo_status mpdo_bond_weights(mpdo_t h, int32_t b, double* out, int32_t cap, int
   GUARD_END
 }
 
-mpdo_status mpdo_batch_run(const mpdo_config*, const mpdo_program*, int32_t, const double*, int32_t, const double*,
-                           int32_t, const mpdo_chan_t*, int32_t, double*, int32_t, void*) {
-  return fail(MPDO_EUNSUPPORTED, "mpdo_batch_run is not available yet");
+}  // extern "C"
+
+namespace {
+// Runs a batch on an engine of real type T: sublayers merged across instances,
+// then the observables; with use_graph the whole sequence is one HIP graph.
+template <typename T>
+void batch_exec(const Config& c, const std::vector<int>& nq, const std::vector<std::vector<GateOp>>& layers,
+                const std::vector<int>& oinst, const std::vector<const double*>& oops, double* out_dev,
+                bool use_graph, hipStream_t user_st) {
+  // graph capture needs a real stream: use a private one when given NULL
+  struct OwnStream {
+    hipStream_t s = nullptr;
+    ~OwnStream() { if (s) (void)hipStreamDestroy(s); }
+  } own;
+  hipStream_t st = user_st;
+  if (use_graph && !st) {
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    hip_check(hipStreamCreate(&own.s), "hipStreamCreate");
+    st = own.s;
+  }
+  Engine<T> eng(c, nq, st);
+  if (!use_graph) {
+    for (const auto& L : layers) eng.run_sublayer(L);
+    if (!oinst.empty()) eng.expect(oinst, oops, out_dev);
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return;
+  }
+  Upload dry;
+  dry.dry = true;
+  for (const auto& L : layers) eng.run_sublayer(L, dry);
+  if (!oinst.empty()) eng.expect(oinst, oops, out_dev, false, dry);
+  eng.prepare_capture(dry);
+  const size_t bytes = std::max<size_t>(dry.cursor, 256);
+  void* himg = nullptr;
+  hip_check(hipHostMalloc(&himg, bytes, hipHostMallocDefault), "hipHostMalloc");
+  struct HostFree {
+    void* p;
+    ~HostFree() { if (p) (void)hipHostFree(p); }
+  } guard{himg};
+  DevBuf dimg;
+  dimg.alloc(bytes);
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  Upload real;
+  real.immediate = false;
+  real.host = reinterpret_cast<char*>(himg);
+  real.dev = reinterpret_cast<char*>(dimg.p);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  try {
+    // the image is filled below, before the graph is launched
+    hip_check(hipMemcpyAsync(dimg.p, himg, bytes, hipMemcpyHostToDevice, st), "capture upload");
+    for (const auto& L : layers) eng.run_sublayer(L, real);
+    if (!oinst.empty()) eng.expect(oinst, oops, out_dev, false, real);
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(st, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+  hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  const hipError_t le = hipGraphLaunch(exec, st);
+  const hipError_t se = hipStreamSynchronize(st);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  hip_check(le, "hipGraphLaunch");
+  hip_check(se, "hipStreamSynchronize");
+}
+}  // namespace
+
+extern "C" {
+
+mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
+                           const double* params_dev, int32_t param_stride, const double* fixed_u, int32_t nfixed,
+                           const mpdo_chan_t* chans, int32_t nchans, double* out_dev, int32_t use_graph,
+                           void* hip_stream) {
+  if (const char* why = check_config(cfg, false)) return fail(MPDO_EINVAL, why);
+  if (!progs || ninst < 1) return fail(MPDO_EINVAL, "no programs");
+  if (nfixed < 0 || nchans < 0 || param_stride < 0) return fail(MPDO_EINVAL, "negative count");
+  if (nfixed > 0 && !fixed_u) return fail(MPDO_EINVAL, "null fixed_u");
+  if (nchans > 0 && !chans) return fail(MPDO_EINVAL, "null chans");
+  for (int c = 0; c < nchans; ++c)
+    if (!chans[c]) return fail(MPDO_EINVAL, "null channel handle");
+  long long total_obs = 0;
+  for (int b = 0; b < ninst; ++b) {
+    const mpdo_program& p = progs[b];
+    if (p.n < 1 || p.n > 64) return fail(MPDO_EINVAL, "program qubit count must be in [1, 64]");
+    if (p.nops < 0 || (p.nops > 0 && !p.ops)) return fail(MPDO_EINVAL, "bad op list");
+    if (p.nobs < 0 || (p.nobs > 0 && !p.obs)) return fail(MPDO_EINVAL, "bad observable list");
+    total_obs += p.nobs;
+    for (int j = 0; j < p.nops; ++j) {
+      const mpdo_op& o = p.ops[j];
+      if (o.q < 1 || o.q > 2) return fail(o.q == 3 ? MPDO_EUNSUPPORTED : MPDO_EINVAL, "op arity must be 1 or 2");
+      if (o.site < 0 || o.site + o.q > p.n) return fail(MPDO_EINVAL, "op site out of range");
+      const bool k1 = o.kind == MPDO_G_RX || o.kind == MPDO_G_RY || o.kind == MPDO_G_RZ;
+      const bool k2 = o.kind == MPDO_G_ZZPHASE || o.kind == MPDO_G_SWAPZZ;
+      if (o.kind != MPDO_G_FIXED && !((k1 && o.q == 1) || (k2 && o.q == 2)))
+        return fail(MPDO_EINVAL, "gate kind does not match its arity");
+      if (o.kind == MPDO_G_FIXED && (o.fixed < 0 || o.fixed >= nfixed)) return fail(MPDO_EINVAL, "bad fixed index");
+      if (o.param >= 0 && (!params_dev || o.param >= param_stride)) return fail(MPDO_EINVAL, "bad parameter index");
+      if (!std::isfinite(o.scale)) return fail(MPDO_EINVAL, "scale is not finite");
+      if (o.chan >= nchans || o.chan < -1) return fail(MPDO_EINVAL, "bad channel index");
+      if (o.chan >= 0) {
+        if (chans[o.chan]->ch.q != o.q) return fail(MPDO_EINVAL, "channel arity differs from the op's");
+        if (chans[o.chan]->ch.m > cfg->max_kraus) return fail(MPDO_EINVAL, "channel exceeds max_kraus");
+      }
+    }
+  }
+  if (total_obs > 0 && !out_dev) return fail(MPDO_EINVAL, "null out_dev");
+  GUARD_BEGIN
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  // fixed gates: a 4x4 slot and its compact top-left 2x2 per entry
+  DevBuf dfix;
+  std::vector<double> hfix((size_t)std::max(1, nfixed) * 40, 0.0);
+  for (int f = 0; f < nfixed; ++f) {
+    std::memcpy(&hfix[(size_t)f * 40], fixed_u + (size_t)f * 32, 32 * sizeof(double));
+    for (int r = 0; r < 2; ++r)
+      for (int cc = 0; cc < 2; ++cc) {
+        hfix[(size_t)f * 40 + 32 + 2 * (2 * r + cc)] = fixed_u[(size_t)f * 32 + 2 * (4 * r + cc)];
+        hfix[(size_t)f * 40 + 32 + 2 * (2 * r + cc) + 1] = fixed_u[(size_t)f * 32 + 2 * (4 * r + cc) + 1];
+      }
+  }
+  dfix.alloc(hfix.size() * sizeof(double));
+  hip_check(hipMemcpy(dfix.p, hfix.data(), hfix.size() * sizeof(double), hipMemcpyHostToDevice), "fixed gates");
+  // sublayers: per instance, an op goes to the first group after the last
+  // group that touches one of its sites; groups of all instances merge
+  std::vector<std::vector<GateOp>> layers;
+  std::vector<int> nq(ninst);
+  for (int b = 0; b < ninst; ++b) {
+    const mpdo_program& p = progs[b];
+    nq[b] = p.n;
+    std::vector<int> last(p.n, -1);
+    for (int j = 0; j < p.nops; ++j) {
+      const mpdo_op& o = p.ops[j];
+      int g = 0;
+      for (int t = 0; t < o.q; ++t) g = std::max(g, last[o.site + t] + 1);
+      for (int t = 0; t < o.q; ++t) last[o.site + t] = g;
+      if ((int)layers.size() <= g) layers.resize(g + 1);
+      GateOp op;
+      op.inst = b;
+      op.site = o.site;
+      op.q = o.q;
+      op.kind = o.kind;
+      op.pidx = o.param;
+      op.scale = o.scale;
+      op.params = o.param >= 0 ? params_dev + (size_t)b * param_stride : nullptr;
+      if (o.kind == MPDO_G_FIXED) op.ufix = dfix.as<double>() + (size_t)o.fixed * 40 + (o.q == 1 ? 32 : 0);
+      op.ch = o.chan >= 0 ? &chans[o.chan]->ch : nullptr;
+      layers[g].push_back(op);
+    }
+  }
+  std::vector<int> oinst;
+  std::vector<const double*> oops;
+  for (int b = 0; b < ninst; ++b)
+    for (int k = 0; k < progs[b].nobs; ++k) {
+      oinst.push_back(b);
+      oops.push_back(progs[b].obs + (size_t)k * progs[b].n * 8);
+    }
+  const Config c = make_config(cfg);
+  if (cfg->prec == MPDO_C128) batch_exec<double>(c, nq, layers, oinst, oops, out_dev, use_graph != 0, st);
+  else batch_exec<float>(c, nq, layers, oinst, oops, out_dev, use_graph != 0, st);
+  return MPDO_OK;
+  GUARD_END
 }
 
 }  // extern "C"

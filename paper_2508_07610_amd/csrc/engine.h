@@ -62,6 +62,23 @@ struct Config {
   double tolE = 1e-13;
 };
 
+// Where the descriptors of the launch sequences go.  Immediate mode (the
+// default) copies each sequence's descriptors to the device right before
+// its kernels.  For graph capture a run is planned twice: a dry pass that
+// only measures the descriptor bytes and the workspace, then a pass that
+// writes every sequence's descriptors into one host image (`host`, pinned)
+// of one device blob (`dev`) and launches the kernels; the image is copied
+// to the device by a single copy issued before the first kernel.
+struct Upload {
+  bool dry = false;
+  bool immediate = true;
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cursor = 0;
+  size_t work_need = 0;
+  int max_items = 0;
+};
+
 template <typename T> class Engine {
  public:
   Engine(const Config& cfg, const std::vector<int>& nq, hipStream_t s);
@@ -69,11 +86,16 @@ template <typename T> class Engine {
 
   // One group of gates on pairwise disjoint sites (any mix of 1q and 2q).
   void run_sublayer(const std::vector<GateOp>& ops);
+  void run_sublayer(const std::vector<GateOp>& ops, Upload& up);
   // Tr(O_k rho) / Tr rho for product operators; ops_host: per item n x 4 complex.
   // Results (complex) are written to out_dev (device, 2 doubles per item, items
   // of all instances concatenated in the order given).
   void expect(const std::vector<int>& inst, const std::vector<const double*>& ops_host, double* out_dev,
               bool raw = false);
+  void expect(const std::vector<int>& inst, const std::vector<const double*>& ops_host, double* out_dev,
+              bool raw, Upload& up);
+  // Allocate the workspace and status buffers measured by a dry pass.
+  void prepare_capture(const Upload& dry);
   // The Sec. II.D sweep on instance b.
   double truncate_sweep(int b, int chi_max, int kap_max, double cut);
 
@@ -110,9 +132,12 @@ template <typename T> class Engine {
   const double* laml2(int b, int i) const { return i == 0 ? one_.as<double>() : lam2_ptr(b, i - 1); }
   double* disc_ptr(int b, int i) const { return disc_.as<double>() + soff_[b] + i; }
 
-  void run_1q(const std::vector<const GateOp*>& ops);
-  void run_2q(const std::vector<const GateOp*>& ops);
+  void run_1q(const std::vector<const GateOp*>& ops, Upload& up);
+  void run_2q(const std::vector<const GateOp*>& ops, Upload& up);
   int splits_for(long long K) const;
+  // descriptor space of `bytes` (host image h, device address dv); false in a dry pass
+  bool reserve(Upload& up, size_t bytes, size_t work_bytes, int items, char*& h, char*& dv);
+  void commit(Upload& up, char* h, char* dv, size_t bytes);
 };
 
 }  // namespace mpdo

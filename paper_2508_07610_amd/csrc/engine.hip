@@ -78,6 +78,13 @@ __global__ void k_init_sites_kernel(double* base, long long nsites, long long st
   for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < nsites; s += (long long)gridDim.x * blockDim.x)
     base[s * stride_doubles] = 1.0;
 }
+__global__ void k_gather_pairs(const double* src, const int* idx, int n, double* dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    dst[2 * k] = src[2 * idx[k]];
+    dst[2 * k + 1] = src[2 * idx[k] + 1];
+  }
+}
 __global__ void k_init_sites_kernel_f(float* base, long long nsites, long long stride_floats) {
   for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < nsites; s += (long long)gridDim.x * blockDim.x)
     base[s * stride_floats] = 1.0f;
@@ -122,7 +129,49 @@ template <typename T> int Engine<T>::splits_for(long long K) const {
   return (int)s;
 }
 
+template <typename T>
+bool Engine<T>::reserve(Upload& up, size_t bytes, size_t work_bytes, int items, char*& h, char*& dv) {
+  const size_t ab = (bytes + 255) & ~size_t(255);
+  if (up.dry) {
+    up.cursor += ab;
+    up.work_need = std::max(up.work_need, work_bytes);
+    up.max_items = std::max(up.max_items, items);
+    return false;
+  }
+  if (up.immediate) {
+    work_.alloc(work_bytes);
+    sweeps_.alloc(sizeof(int) * 2 * std::max(1, items));
+    blob_.alloc(bytes);
+    h = reinterpret_cast<char*>(stage_.get(bytes));
+    dv = reinterpret_cast<char*>(blob_.p);
+  } else {
+    if (work_.bytes < work_bytes || sweeps_.bytes < sizeof(int) * 2 * (size_t)items)
+      throw Error{4, "capture workspace was not prepared"};
+    h = up.host + up.cursor;
+    dv = up.dev + up.cursor;
+    up.cursor += ab;
+  }
+  std::memset(h, 0, bytes);
+  return true;
+}
+
+template <typename T> void Engine<T>::commit(Upload& up, char* h, char* dv, size_t bytes) {
+  if (!up.immediate) return;  // the whole image is copied before the first kernel
+  hip_check(hipMemcpyAsync(dv, h, bytes, hipMemcpyHostToDevice, st_), "upload");
+  hip_check(hipEventRecord(stage_.done, st_), "hipEventRecord");
+}
+
+template <typename T> void Engine<T>::prepare_capture(const Upload& dry) {
+  work_.alloc(dry.work_need);
+  sweeps_.alloc(sizeof(int) * 2 * std::max(1, dry.max_items));
+}
+
 template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& ops) {
+  Upload up;
+  run_sublayer(ops, up);
+}
+
+template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& ops, Upload& up) {
   std::vector<const GateOp*> one, two;
   for (const GateOp& g : ops) {
     if (g.q == 1) one.push_back(&g);
@@ -137,12 +186,12 @@ template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& op
                       (size_t)(4 * cx) * (4 * cx) * 16 * 4 + (size_t)(kx * mm) * (kx * mm) * 16 * 3 + (1 << 20);
   const int chunk2 = (int)std::max<size_t>(1, budget / per2);
   for (size_t a = 0; a < one.size(); a += 4096)
-    run_1q(std::vector<const GateOp*>(one.begin() + a, one.begin() + std::min(one.size(), a + 4096)));
+    run_1q(std::vector<const GateOp*>(one.begin() + a, one.begin() + std::min(one.size(), a + 4096)), up);
   for (size_t a = 0; a < two.size(); a += chunk2)
-    run_2q(std::vector<const GateOp*>(two.begin() + a, two.begin() + std::min(two.size(), a + chunk2)));
+    run_2q(std::vector<const GateOp*>(two.begin() + a, two.begin() + std::min(two.size(), a + chunk2)), up);
 }
 
-template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& ops) {
+template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up) {
   const int n = (int)ops.size();
   if (n == 0) return;
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
@@ -161,7 +210,6 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
   const size_t oWk = w.add((size_t)eig_work_doubles(ng) * 8);
   const size_t oW = w.add((size_t)4 * kx * kx * sizeof(cpx<T>));
   const size_t per = w.off;
-  work_.alloc(per * n);
   // ---- upload layout ----
   Layout u;
   const size_t uCtx = u.add(sizeof(Ctx1<T>) * n);
@@ -170,10 +218,8 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
   const size_t uA = u.add(sizeof(GemmDesc) * n);
   const size_t uOut = u.add(sizeof(double*) * n);
   const size_t uU = u.add(sizeof(double) * 8 * n);
-  blob_.alloc(u.off);
-  char* h = reinterpret_cast<char*>(stage_.get(u.off));
-  std::memset(h, 0, u.off);
-  char* dv = reinterpret_cast<char*>(blob_.p);
+  char *h = nullptr, *dv = nullptr;
+  if (!reserve(up, u.off, per * n, n, h, dv)) return;
   char* wk = reinterpret_cast<char*>(work_.p);
   for (int it = 0; it < n; ++it) {
     const GateOp& g = *ops[it];
@@ -214,9 +260,7 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
     de.kvec = kx;
     at<double*>(h, uOut)[it] = c.H;
   }
-  hip_check(hipMemcpyAsync(blob_.p, h, u.off, hipMemcpyHostToDevice, st_), "upload");
-  hip_check(hipEventRecord(stage_.done, st_), "hipEventRecord");
-  sweeps_.alloc(sizeof(int) * n);
+  commit(up, h, dv, u.off);
   Ctx1<T>* dctx = reinterpret_cast<Ctx1<T>*>(dv + uCtx);
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   launch_q1_prepare<T>(dctx, n, splitsH, st_);
@@ -231,7 +275,7 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
   for (auto* g : ops) par_[soff_[g->inst] + g->site] ^= 1;
 }
 
-template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& ops) {
+template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& ops, Upload& up) {
   const int n = (int)ops.size();
   if (n == 0) return;
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
@@ -271,7 +315,6 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   const size_t oX = w.add((size_t)4 * cx * cx * sizeof(cpx<T>));
   const size_t oScr = w.add(16);
   const size_t per = w.off;
-  work_.alloc(per * n);
   Layout u;
   const size_t uCtx = u.add(sizeof(Ctx2<T>) * n);
   const size_t uTheta = u.add(sizeof(GemmDesc) * n);
@@ -286,10 +329,8 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   const size_t uOutsG = u.add(sizeof(double*) * 2 * n);
   const size_t uOutsC = u.add(sizeof(double*) * n);
   const size_t uU = u.add(sizeof(double) * 32 * n);
-  blob_.alloc(u.off);
-  char* h = reinterpret_cast<char*>(stage_.get(u.off));
-  std::memset(h, 0, u.off);
-  char* dv = reinterpret_cast<char*>(blob_.p);
+  char *h = nullptr, *dv = nullptr;
+  if (!reserve(up, u.off, per * n, 2 * n, h, dv)) return;
   char* wk = reinterpret_cast<char*>(work_.p);
   for (int it = 0; it < n; ++it) {
     const GateOp& g = *ops[it];
@@ -368,9 +409,7 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
     at<double*>(h, uOutsG)[2 * it + 1] = c.E;
     at<double*>(h, uOutsC)[it] = c.Cm;
   }
-  hip_check(hipMemcpyAsync(blob_.p, h, u.off, hipMemcpyHostToDevice, st_), "upload");
-  hip_check(hipEventRecord(stage_.done, st_), "hipEventRecord");
-  sweeps_.alloc(sizeof(int) * 2 * n);
+  commit(up, h, dv, u.off);
   Ctx2<T>* dctx = reinterpret_cast<Ctx2<T>*>(dv + uCtx);
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   const int maxGram = std::max(4 * kx, 2 * cx);
@@ -403,6 +442,13 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
 template <typename T>
 void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const double*>& ops_host, double* out_dev,
                        bool raw) {
+  Upload up;
+  expect(inst, ops_host, out_dev, raw, up);
+}
+
+template <typename T>
+void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const double*>& ops_host, double* out_dev,
+                       bool raw, Upload& up) {
   // items: per instance a trace item (identity) followed by its observables,
   // in the order given (inst[] must be grouped by instance).
   struct It { int b; const double* ops; int trace; };
@@ -428,18 +474,17 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
   const size_t oBO = w.add(cap_site_ * sizeof(cpx<T>));
   const size_t oY = w.add(cap_site_ * sizeof(cpx<T>));
   const size_t per = w.off;
-  work_.alloc(per * n);
   Layout u;
   const size_t uCtx = u.add(sizeof(CtxT<T>) * (size_t)nmax * n);
   const size_t uD1 = u.add(sizeof(GemmDesc) * (size_t)nmax * n);
   const size_t uD2 = u.add(sizeof(GemmDesc) * (size_t)nmax * n);
   const size_t uOps = u.add(sizeof(double) * 8 * (size_t)nmax * n);
   const size_t uRes = u.add(sizeof(double) * 2 * n);
-  blob_.alloc(u.off);
-  char* h = reinterpret_cast<char*>(stage_.get(u.off));
-  std::memset(h, 0, u.off);
-  char* dv = reinterpret_cast<char*>(blob_.p);
+  const size_t uIdx = u.add(sizeof(int) * result_index.size());
+  char *h = nullptr, *dv = nullptr;
+  if (!reserve(up, u.off, per * n, 0, h, dv)) return;
   char* wk = reinterpret_cast<char*>(work_.p);
+  std::memcpy(h + uIdx, result_index.data(), sizeof(int) * result_index.size());
   for (int it = 0; it < n; ++it) {
     const int b = items[it].b, nb = nq_[b];
     double* ops = at<double>(h, uOps) + 8 * (size_t)nmax * it;
@@ -476,8 +521,7 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
       }
     }
   }
-  hip_check(hipMemcpyAsync(blob_.p, h, u.off, hipMemcpyHostToDevice, st_), "upload");
-  hip_check(hipEventRecord(stage_.done, st_), "hipEventRecord");
+  commit(up, h, dv, u.off);
   CtxT<T>* dctx = reinterpret_cast<CtxT<T>*>(dv + uCtx);
   launch_transfer_init<T>(dctx, n, st_);
   for (int s = 0; s < nmax; ++s) {
@@ -489,9 +533,9 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
   double* res = reinterpret_cast<double*>(dv + uRes);
   launch_transfer_finish<T>(dctx, n, res, st_);
   // gather the requested observables in order
-  for (size_t k = 0; k < result_index.size(); ++k)
-    hip_check(hipMemcpyAsync(out_dev + 2 * k, res + 2 * result_index[k], 2 * sizeof(double),
-                             hipMemcpyDeviceToDevice, st_), "gather");
+  const int nres = (int)result_index.size();
+  hipLaunchKernelGGL(k_gather_pairs, dim3((nres + 255) / 256), dim3(256), 0, st_, res,
+                     reinterpret_cast<const int*>(dv + uIdx), nres, out_dev);
   hip_check(hipGetLastError(), "launch (transfer)");
 }
 

@@ -247,6 +247,77 @@ class MPDO:
         return out[: ln.value].copy()
 
 
+G_FIXED, G_RX, G_RY, G_RZ, G_ZZPHASE, G_SWAPZZ = range(6)
+_PARAM_KINDS = {"ry": (G_RY, 1), "rx": (G_RX, 1), "rz": (G_RZ, 1), "swapzz": (G_SWAPZZ, 2), "mix": (G_RX, 1)}
+
+
+def program_ops(prog, fixed: List[np.ndarray], fixed_index: dict, use_params: bool = True):
+    """mpdo_op array of a workloads.Program.  Parametrised gates (kind ry, rx,
+    rz, mix, swapzz with a parameter index) read their angle from the
+    instance's parameter row on the device; every other gate is a fixed
+    matrix appended to `fixed` (deduplicated through `fixed_index`)."""
+    ops = (mpdo_op * max(1, len(prog.ops)))()
+    for j, op in enumerate(prog.ops):
+        q = len(op.sites)
+        o = ops[j]
+        o.q, o.site, o.chan, o.param, o.scale, o.fixed = q, op.sites[0], op.chan, -1, 1.0, 0
+        if use_params and op.param >= 0 and op.kind in _PARAM_KINDS:
+            o.kind = _PARAM_KINDS[op.kind][0]
+            o.param = op.param
+            o.scale = float(op.pscale)
+        else:
+            o.kind = G_FIXED
+            U = np.asarray(op.U, dtype=np.complex128)
+            slot = np.zeros((4, 4), dtype=np.complex128)
+            slot[: U.shape[0], : U.shape[1]] = U
+            key = slot.tobytes()
+            if key not in fixed_index:
+                fixed_index[key] = len(fixed)
+                fixed.append(slot)
+            o.fixed = fixed_index[key]
+    return ops
+
+
+def batch_run(programs, params, channels: Sequence[Channel], observables, chi_max: int, kappa_max: int,
+              max_kraus: int = 16, svd_cutoff: float = 1e-14, kappa_cutoff: float = 1e-14, prec: int = C128,
+              use_graph: bool = True, stream=None, out=None):
+    """Run many programs through mpdo_batch_run.
+
+    programs: workloads.Program list; params: torch float64 CUDA tensor
+    (ninst, P) of per-instance parameters (or None); observables: per program
+    a (nobs, n, 2, 2) complex array.  Returns a torch complex128 CUDA tensor
+    of all expectation values (instance-major)."""
+    import torch
+    ninst = len(programs)
+    fixed: List[np.ndarray] = []
+    fidx: dict = {}
+    keep = []
+    progs = (mpdo_program * ninst)()
+    for b, pr in enumerate(programs):
+        ops = program_ops(pr, fixed, fidx, use_params=params is not None)
+        obs = np.ascontiguousarray(np.asarray(observables[b], dtype=np.complex128))
+        obuf = obs.view(np.float64).reshape(-1).copy() if obs.size else np.zeros(8)
+        keep += [ops, obuf]
+        progs[b].n = pr.n
+        progs[b].nops = len(pr.ops)
+        progs[b].ops = ops
+        progs[b].nobs = obs.shape[0] if obs.size else 0
+        progs[b].obs = _dptr(obuf)
+    total = sum(progs[b].nobs for b in range(ninst))
+    if out is None:
+        out = torch.zeros(max(1, total), dtype=torch.complex128, device="cuda")
+    fbuf = _cplx(np.array(fixed)) if fixed else np.zeros(32)
+    chans = (ctypes.c_void_p * max(1, len(channels)))(*[c.handle.value for c in channels])
+    cfg = mpdo_config(0, chi_max, kappa_max, max_kraus, svd_cutoff, kappa_cutoff, prec)
+    pptr, pstride = None, 0
+    if params is not None:
+        assert params.is_cuda and params.dtype == torch.float64 and params.is_contiguous()
+        pptr, pstride = params.data_ptr(), params.shape[1]
+    check(lib().mpdo_batch_run(ctypes.byref(cfg), progs, ninst, pptr, pstride, _dptr(fbuf), len(fixed), chans,
+                               len(channels), out.data_ptr(), 1 if use_graph else 0, stream_handle(stream)))
+    return out[:total]
+
+
 def run_program(prog, state: MPDO, channels: Sequence[Channel]) -> MPDO:
     """Apply a workloads.Program gate by gate through the C ABI."""
     for op in prog.ops:

@@ -282,6 +282,8 @@ def qaoa_swap_network(n: int, edges: Sequence[Tuple[int, int]], gammas: Sequence
     then the mixer exp(-i beta X) on every site.  Every two-site gate is
     followed by the 2q channel, every 1q gate by the 1q channel.  Levels
     alternate the direction of the network so the logical order returns.
+    Gate angles refer to the parameter row (gamma_1, beta_1, gamma_2, ...):
+    cost gates read index 2 l, mixers index 2 l + 1 (angle 2 beta).
     Returns the program and the final map position -> logical qubit."""
     chis = [chi_1q_default(noise_scale), chi_2q_default(noise_scale)] if noisy else []
     c1, c2 = (0, 1) if noisy else (-1, -1)
@@ -295,17 +297,17 @@ def qaoa_swap_network(n: int, edges: Sequence[Tuple[int, int]], gammas: Sequence
             for s in range(start, n - 1, 2):
                 a, c = pos[s], pos[s + 1]
                 key = (min(a, c), max(a, c))
-                U = SWAP.copy()
                 if key in eset and key not in done:
-                    U = SWAP @ qaoa_cost(g)
+                    ops.append(Op((s, s + 1), SWAP @ qaoa_cost(g), c2, "swapzz", 2 * lvl, 1.0))
                     done.add(key)
-                ops.append(Op((s, s + 1), U, c2, "swapzz"))
+                else:
+                    ops.append(Op((s, s + 1), SWAP.copy(), c2, "swap"))
                 pos[s], pos[s + 1] = c, a
         missing = eset - done
         if missing:
             raise RuntimeError(f"swap network missed edges {missing}")
         for q in range(n):
-            ops.append(Op((q,), qaoa_mixer(b), c1, "mix"))
+            ops.append(Op((q,), qaoa_mixer(b), c1, "mix", 2 * lvl + 1, 2.0))
     return Program(n, ops, chis, len(gammas)), pos
 
 

@@ -1,0 +1,107 @@
+"""Batched execution (mpdo_batch_run): many instances of uneven size in one
+launch sequence / one HIP graph give, instance by instance, the results of
+the plain per-gate path and of the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import channels as OC
+from oracle import mpdo as OM
+from paper_2508_07610_amd import mpdo as M
+from paper_2508_07610_amd import workloads as W
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _zz_ops(n, pairs):
+    ops = np.zeros((len(pairs), n, 2, 2), dtype=np.complex128)
+    for k, (a, b) in enumerate(pairs):
+        for s in range(n):
+            ops[k, s] = np.diag([1.0, -1.0]) if s in (a, b) else np.eye(2)
+    return ops
+
+
+def _ghz_ops(n):
+    p0, p1 = np.diag([1.0, 0.0]), np.diag([0.0, 1.0])
+    up = np.array([[0, 0], [1, 0]], dtype=np.complex128)
+    return np.stack([np.stack([p0] * n), np.stack([p1] * n), np.stack([up] * n)]).astype(np.complex128)
+
+
+def _instances():
+    """Ansatz instances (parameter rows) and QAOA instances of different sizes."""
+    progs, params, obs = [], [], []
+    for tag, n in enumerate((6, 8, 6)):
+        th = W.ansatz_params(n, 2, 50 + tag)
+        progs.append(W.ghz_ansatz(n, 2, th))
+        params.append(th)
+        obs.append(np.concatenate([_zz_ops(n, [(i, i + 1) for i in range(n - 1)]), _ghz_ops(n)]))
+    for tag, n in enumerate((6, 8)):
+        rng = W.rng_for(300 + tag)
+        edges = W.random_3_regular(n, rng)
+        gb = rng.uniform(0, math.pi, size=4)
+        prog, pos = W.qaoa_swap_network(n, edges, gb[0::2], gb[1::2])
+        progs.append(prog)
+        params.append(gb)
+        where = {lq: s for s, lq in enumerate(pos)}
+        obs.append(_zz_ops(n, [(where[u], where[v]) for u, v in edges]))
+    width = max(len(p) for p in params)
+    P = np.zeros((len(params), width))
+    for b, p in enumerate(params):
+        P[b, : len(p)] = p
+    return progs, P, obs
+
+
+def _expect_from_products(st, ops):
+    return st.expect_products(ops)
+
+
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+def test_batch_equals_plain_and_oracle(prec):
+    require_gpu()
+    import torch
+    progs, P, obs = _instances()
+    chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
+    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
+    out = M.batch_run(progs, pdev, chans, obs, use_graph=True, **kw).cpu().numpy()
+    out_ng = M.batch_run(progs, pdev, chans, obs, use_graph=False, **kw).cpu().numpy()
+    assert np.array_equal(out, out_ng), "graph and launch-by-launch runs differ"
+    tol = 1e-10 if prec == M.C128 else 1e-5
+    kr = [OC.kraus_from_chi(c)[0] for c in (W.chi_1q_default(), W.chi_2q_default())]
+    off = 0
+    for b, pr in enumerate(progs):
+        k = obs[b].shape[0]
+        got = out[off: off + k]
+        off += k
+        st = M.MPDO(pr.n, **kw)
+        M.run_program(pr, st, chans)
+        plain = st.expect_products(obs[b])
+        assert float(np.abs(got - plain).max()) < (1e-12 if prec == M.C128 else 1e-6), b
+        o = OM.run_program(pr, OM.MPDO(pr.n, 16, 4, 1e-10, 1e-14), kr)
+        ref = np.array([o.expect_product(list(ob)) / o.trace() for ob in obs[b]])
+        assert float(np.abs(got - ref).max()) < tol, (b, float(np.abs(got - ref).max()))
+
+
+def test_batch_graph_is_deterministic():
+    require_gpu()
+    import torch
+    progs, P, obs = _instances()
+    chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
+    pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
+    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14)
+    a = M.batch_run(progs, pdev, chans, obs, **kw).cpu().numpy()
+    b = M.batch_run(progs, pdev, chans, obs, **kw).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_batch_rejects_bad_programs():
+    require_gpu()
+    import torch
+    progs, P, obs = _instances()
+    chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
+    bad = W.Program(4, [W.Op((3, 4), W.CZ, -1, "cz")], [])
+    with pytest.raises(M.MPDOError) as e:
+        M.batch_run([bad], None, chans, [np.zeros((0, 4, 2, 2))], chi_max=8, kappa_max=2)
+    assert e.value.status == M.EINVAL
