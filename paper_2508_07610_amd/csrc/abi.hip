@@ -619,9 +619,9 @@ extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, in
   d.alpha = alpha;
   dD.alloc(sizeof(GemmDesc));
   hip_check(hipMemcpy(dD.p, &d, sizeof(d), hipMemcpyHostToDevice), "desc");
-  if (prec == 0) launch_gemm<double, double, double>(dD.as<GemmDesc>(), 1, 1, splits, M, N, st);
-  else if (prec == 1) launch_gemm<float, float, float>(dD.as<GemmDesc>(), 1, 1, splits, M, N, st);
-  else launch_gemm<float, double, double>(dD.as<GemmDesc>(), 1, 1, splits, M, N, st);
+  if (prec == 0) launch_gemm<double, double, double>(dD.as<GemmDesc>(), 1, 1, splits, gemm_tiles(M, N), st);
+  else if (prec == 1) launch_gemm<float, float, float>(dD.as<GemmDesc>(), 1, 1, splits, gemm_tiles(M, N), st);
+  else launch_gemm<float, double, double>(dD.as<GemmDesc>(), 1, 1, splits, gemm_tiles(M, N), st);
   hip_check(hipGetLastError(), "launch");
   hip_check(hipDeviceSynchronize(), "sync");
   const size_t nc = (size_t)2 * M * N;

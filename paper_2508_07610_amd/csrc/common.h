@@ -72,12 +72,12 @@ struct EigDesc {
 };
 
 constexpr double EIG_FLOOR = 1e-13;
-constexpr int EIG_THREADS = 1024;
+constexpr int EIG_THREADS = 512;
 
-// matrix (2 n^2) + two n x np solve vectors + four n x np factor arrays
+// matrix (2 n^2) + two n x np solve vectors + five n x np factor arrays
 __host__ __device__ inline long long eig_work_doubles(int n) {
   const long long np = (n + 63) / 64 * 64;
-  return 2LL * n * n + 6LL * n * np + 64;
+  return 2LL * n * n + 7LL * n * np + 64;
 }
 
 }  // namespace mpdo

@@ -8,17 +8,19 @@
 //     p = A v) of step k is fused with the matrix-vector product of step k+1
 //     into one pass over the trailing block, column-parallel (Hermitian
 //     symmetry turns the row products into coalesced column reads) with
-//     eight independent loads in flight per thread.  The matrix lives in LDS
-//     for n <= 64 and in global memory (L2-resident) otherwise.
-//  2. The leading kvec + 1 eigenvalues of T by bisection on Sturm counts, one
-//     thread per eigenvalue.
+//     eight independent loads in flight per thread.  For n <= 128 the matrix
+//     is held in registers instead (16 entries per thread, see k_heev_reg);
+//     larger matrices stay in global memory (L2-resident).
+//  2. The leading kvec + 1 eigenvalues of T by multisection on Sturm counts
+//     (a group of lanes per eigenvalue, one count per lane and round).
 //  3. Their eigenvectors by inverse iteration on T (tridiagonal LU with
 //     partial pivoting, three solves from a fixed pseudo-random start), one
 //     thread per vector, the solves streaming batches of eight entries
 //     between two buffers; then Gram-Schmidt (twice) inside clusters of
 //     eigenvalues closer than 1e-6 (degenerate multiplets).
 //  4. Back-transformation z <- H_0 ... H_{n-2} z, columns in parallel with the
-//     rows of each reflector split over the remaining threads.
+//     rows of each reflector split over the remaining threads (for n <= 128
+//     the vector block stays in registers).
 //
 // Only the eigenpairs a truncation can keep are computed; the discarded
 // weight comes from Tr(A) minus the kept eigenvalues.
@@ -30,22 +32,23 @@ namespace mpdo {
 namespace {
 constexpr int NT = EIG_THREADS;
 constexpr int NW = NT / 64;
-constexpr int LDS_N = 64;
 constexpr int UB = 8;  // loads in flight per thread
 
 // Block-wide sum with one barrier: consecutive calls alternate between the
 // two halves of red[2 NW], so a half is rewritten only after the barrier of
 // the call in between.
+template <int NTH = NT>
 __device__ inline double block_sum(double v, double* red, int& parity) {
+  constexpr int NWH = NTH / 64;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* r = red + parity * NW;
+  double* r = red + parity * NWH;
   parity ^= 1;
   if (lane == 0) r[wave] = v;
   __syncthreads();
   double s = 0;
 #pragma unroll
-  for (int i = 0; i < NW; ++i) s += r[i];
+  for (int i = 0; i < NWH; ++i) s += r[i];
   return s;
 }
 
@@ -74,12 +77,13 @@ __device__ inline double start_entry(int j, int i) {
   return (double)(h & 0xFFFFFF) / (double)0x800000 - 1.0;
 }
 
-struct Shared {
+struct alignas(16) Shared {
+  alignas(16) cpx<double> tau[512];
+  alignas(16) cpx<double> v[512];              // reflector of the current step
+  alignas(16) cpx<double> vp[512];             // pending rank-2 update of the previous step
+  alignas(16) cpx<double> wp[512];
+  alignas(16) cpx<double> pp[NT];              // partial products (row chunk, column)
   double d[512], e[512], e2[512];
-  cpx<double> tau[512];
-  cpx<double> v[512];              // reflector of the current step
-  cpx<double> vp[512], wp[512];    // pending rank-2 update of the previous step
-  cpx<double> pp[NT];              // partial products (row chunk, column)
   double ev[513];
   double red[2 * NW];
   double scal[4];
@@ -154,9 +158,213 @@ __device__ void fused_pass(cpx<double>* __restrict__ A, int n, int c0, int base,
   }
 }
 
+// Steps 2, 3 and the cluster re-orthogonalisation on the tridiagonal matrix
+// (S.d, S.e, S.e2); eigenvalues to dsc.evals, real eigenvectors of T to
+// dsc.evecs.  Returns the number of vectors above the numerical-zero floor.
+template <int NTH, class SH>
+__device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
+  const int tid = threadIdx.x;
+  // ---- multisection for the leading kb = kvec + 1 eigenvalues ----
+  // A group of L lanes (a power of two, L kb <= NTH) brackets one eigenvalue;
+  // each round evaluates L Sturm counts at equally spaced interior points
+  // and keeps the sub-interval where the count passes the target, so the
+  // bracket shrinks by L + 1 per round (L = 1 is plain bisection).
+  const int kvec = dsc.kvec < n ? dsc.kvec : n;
+  const int kb = (kvec + 1 < n) ? kvec + 1 : n;
+  double lo = 1e300, hi = -1e300, emax2 = 0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(S.e[i - 1]) : 0.0) + (i + 1 < n ? fabs(S.e[i]) : 0.0);
+    lo = fmin(lo, S.d[i] - r);
+    hi = fmax(hi, S.d[i] + r);
+    if (i + 1 < n) emax2 = fmax(emax2, S.e2[i]);
+  }
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  {
+    int L = 64;
+    while (L > 1 && L * kb > NTH) L >>= 1;
+    const int groups = NTH / L;
+    const int gl = tid & (L - 1);
+    const int first = (tid & 63) & ~(L - 1);  // first lane of the group in its wave
+    const unsigned long long gmask = (L == 64) ? ~0ULL : ((1ULL << L) - 1ULL);
+    const double inv = 1.0 / (double)(L + 1);
+    for (int j = tid / L; j < kb; j += groups) {
+      const int target = n - 1 - j;  // eigenvalues strictly below lambda_j (no ties)
+      double l = lo, h = hi;
+      for (int it = 0; it < 120; ++it) {
+        if (h - l <= fmax(2.5e-16 * fmax(fabs(l), fabs(h)), 4e-17 * tnorm)) break;
+        const double w = h - l;
+        const double x = l + w * ((double)(gl + 1) * inv);
+        const bool above = sturm_count(S.d, S.e2, n, x, pivmin) > target;
+        const unsigned long long m = (__ballot(above) >> first) & gmask;
+        // first lane at or above the eigenvalue (L if none)
+        const int j0 = m ? __builtin_ctzll(m) : L;
+        const double nl = (j0 == 0) ? l : l + w * ((double)j0 * inv);
+        const double nh = (j0 == L) ? h : l + w * ((double)(j0 + 1) * inv);
+        if (nl == l && nh == h) break;
+        l = nl;
+        h = nh;
+      }
+      if (gl == 0) S.ev[j] = 0.5 * (l + h);
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += NTH) dsc.evals[j] = j < kb ? S.ev[j] : 0.0;
+  if (tid == 0 && dsc.trace) *dsc.trace = tr;
+  if (kvec <= 0) return 0;
+  const double floorv = EIG_FLOOR * S.ev[0];
+  int kz = 0;  // vectors above the numerical-zero floor (a leading block)
+  while (kz < kvec && S.ev[kz] > floorv && S.ev[0] > 0) ++kz;
+  cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
+  double* work = dsc.work;
+  // ---- 4. inverse iteration on T, one thread per vector ----
+  // T - lambda = P L U with partial pivoting; per step k the factor arrays
+  // hold 1/u_kk, u_k,k+1, u_k,k+2, the multiplier and the swap flag.
+  {
+    const long long ks = (kz + 63) / 64 * 64;  // interleave stride of the solve arrays
+    double* __restrict__ X = work + 2LL * n * n;
+    double* __restrict__ Y = X + (long long)n * ks;
+    double* __restrict__ U0 = Y + (long long)n * ks;
+    double* __restrict__ U1 = U0 + (long long)n * ks;
+    double* __restrict__ U2 = U1 + (long long)n * ks;
+    double* __restrict__ LL = U2 + (long long)n * ks;
+    double* __restrict__ PV = LL + (long long)n * ks;
+    const double pivtol = 2.2204460492503131e-16 * fmax(tnorm, 1e-300);
+    for (int j = tid; j < kvec; j += NTH) {
+      if (j >= kz) {
+        for (int i = 0; i < n; ++i) Z[(long long)i * n + j] = mk(0.0, 0.0);
+        continue;
+      }
+      const double lam = S.ev[j];
+      double u0 = S.d[0] - lam, u1 = n > 1 ? S.e[0] : 0.0, u2 = 0.0;
+      for (int k = 0; k + 1 < n; ++k) {
+        const double l = S.e[k], ak1 = S.d[k + 1] - lam, ek1 = (k + 2 < n) ? S.e[k + 1] : 0.0;
+        const long long o = (long long)k * ks + j;
+        if (fabs(u0) >= fabs(l) || fabs(l) < pivtol) {
+          double piv = u0;
+          if (fabs(piv) < pivtol) piv = piv >= 0 ? pivtol : -pivtol;
+          const double rp = 1.0 / piv;
+          const double mult = l * rp;
+          U0[o] = rp; U1[o] = u1; U2[o] = u2; LL[o] = mult; PV[o] = 0.0;
+          const double nu0 = ak1 - mult * u1, nu1 = ek1 - mult * u2;
+          u0 = nu0; u1 = nu1; u2 = 0.0;
+        } else {
+          const double rl = 1.0 / l;
+          const double mult = u0 * rl;
+          U0[o] = rl; U1[o] = ak1; U2[o] = ek1; LL[o] = mult; PV[o] = 1.0;
+          const double nu0 = u1 - mult * ak1, nu1 = u2 - mult * ek1;
+          u0 = nu0; u1 = nu1; u2 = 0.0;
+        }
+      }
+      if (fabs(u0) < pivtol) u0 = u0 >= 0 ? pivtol : -pivtol;
+      {
+        const long long o = (long long)(n - 1) * ks + j;
+        U0[o] = 1.0 / u0; U1[o] = 0; U2[o] = 0; LL[o] = 0; PV[o] = 0.0;
+      }
+      for (int i = 0; i < n; ++i) X[(long long)i * ks + j] = start_entry(j, i);
+      double scale = 1.0;
+      for (int iter = 0; iter < 3; ++iter) {
+        // forward (row swaps, L): X -> Y, the running entry carried in a register
+        double carry = X[j] * scale;
+        int k = 0;
+        for (; k + UB < n; k += UB) {
+          double nx[UB], lm[UB], pv[UB];
+#pragma unroll
+          for (int u = 0; u < UB; ++u) {
+            nx[u] = X[(long long)(k + 1 + u) * ks + j];
+            lm[u] = LL[(long long)(k + u) * ks + j];
+            pv[u] = PV[(long long)(k + u) * ks + j];
+          }
+#pragma unroll
+          for (int u = 0; u < UB; ++u) {
+            const double b1r = nx[u] * scale;
+            const bool sw = pv[u] != 0.0;
+            const double bk = sw ? b1r : carry, b1 = sw ? carry : b1r;
+            Y[(long long)(k + u) * ks + j] = bk;
+            carry = b1 - lm[u] * bk;
+          }
+        }
+        for (; k + 1 < n; ++k) {
+          const double b1r = X[(long long)(k + 1) * ks + j] * scale;
+          const bool sw = PV[(long long)k * ks + j] != 0.0;
+          const double bk = sw ? b1r : carry, b1 = sw ? carry : b1r;
+          Y[(long long)k * ks + j] = bk;
+          carry = b1 - LL[(long long)k * ks + j] * bk;
+        }
+        Y[(long long)(n - 1) * ks + j] = carry;
+        // backward (U): Y -> X
+        double xn1 = 0, xn2 = 0, mx = 0;
+        k = n - 1;
+        for (; k - UB + 1 >= 0; k -= UB) {
+          double y[UB], a0[UB], a1[UB], a2[UB];
+#pragma unroll
+          for (int u = 0; u < UB; ++u) {
+            const long long o = (long long)(k - u) * ks + j;
+            y[u] = Y[o]; a0[u] = U0[o]; a1[u] = U1[o]; a2[u] = U2[o];
+          }
+#pragma unroll
+          for (int u = 0; u < UB; ++u) {
+            const double x = (y[u] - a1[u] * xn1 - a2[u] * xn2) * a0[u];
+            X[(long long)(k - u) * ks + j] = x;
+            xn2 = xn1;
+            xn1 = x;
+            mx = fmax(mx, fabs(x));
+          }
+        }
+        for (; k >= 0; --k) {
+          const long long o = (long long)k * ks + j;
+          const double x = (Y[o] - U1[o] * xn1 - U2[o] * xn2) * U0[o];
+          X[o] = x;
+          xn2 = xn1;
+          xn1 = x;
+          mx = fmax(mx, fabs(x));
+        }
+        scale = mx > 0 ? 1.0 / mx : 1.0;
+      }
+      double nn = 0;
+      for (int i = 0; i < n; ++i) {
+        const double x = X[(long long)i * ks + j] * scale;
+        nn += x * x;
+      }
+      const double s = scale / sqrt(nn);
+      for (int i = 0; i < n; ++i) Z[(long long)i * n + j] = mk(X[(long long)i * ks + j] * s, 0.0);
+    }
+  }
+  __syncthreads();
+  // ---- 5. Gram-Schmidt (twice) inside clusters of close eigenvalues ----
+  if (tid == 0) {
+    int c = 0;
+    for (int j = 0; j < kz; ++j) {
+      if (j > 0 && S.ev[j - 1] - S.ev[j] > 1e-6 * fabs(S.ev[j - 1])) ++c;
+      S.clus[j] = c;
+    }
+  }
+  __syncthreads();
+  for (int j = 1; j < kz; ++j) {
+    if (S.clus[j] != S.clus[j - 1]) continue;  // uniform across the block
+    int i0 = j - 1;
+    while (i0 > 0 && S.clus[i0 - 1] == S.clus[j]) --i0;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = i0; i < j; ++i) {
+        double s = 0;
+        for (int r = tid; r < n; r += NTH) s += Z[(long long)r * n + i].re * Z[(long long)r * n + j].re;
+        s = block_sum<NTH>(s, S.red, par);
+        for (int r = tid; r < n; r += NTH) Z[(long long)r * n + j].re -= s * Z[(long long)r * n + i].re;
+        __syncthreads();
+      }
+      double nn = 0;
+      for (int r = tid; r < n; r += NTH) nn += Z[(long long)r * n + j].re * Z[(long long)r * n + j].re;
+      nn = block_sum<NTH>(nn, S.red, par);
+      const double sc = 1.0 / sqrt(nn);
+      for (int r = tid; r < n; r += NTH) Z[(long long)r * n + j].re *= sc;
+      __syncthreads();
+    }
+  }
+  return kz;
+}
+
 __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, Shared& S) {
   const int n = dsc.n, tid = threadIdx.x;
-  double* work = dsc.work;
   int par = 0;  // block_sum buffer parity
   // ---- 1. load (symmetrised) ----
   const cpx<double>* a = reinterpret_cast<const cpx<double>*>(dsc.a);
@@ -242,178 +450,10 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, Share
   if (tid == 0) S.d[n - 1] = A[(long long)(n - 1) * n + n - 1].re;
   for (int i = tid; i + 1 < n; i += NT) S.e2[i] = S.e[i] * S.e[i];
   __syncthreads();
-  // ---- 3. bisection for the leading kb eigenvalues ----
-  const int kvec = dsc.kvec < n ? dsc.kvec : n;
-  const int kb = (kvec + 1 < n) ? kvec + 1 : n;
-  double lo = 1e300, hi = -1e300, emax2 = 0;
-  for (int i = 0; i < n; ++i) {
-    const double r = (i > 0 ? fabs(S.e[i - 1]) : 0.0) + (i + 1 < n ? fabs(S.e[i]) : 0.0);
-    lo = fmin(lo, S.d[i] - r);
-    hi = fmax(hi, S.d[i] + r);
-    if (i + 1 < n) emax2 = fmax(emax2, S.e2[i]);
-  }
-  const double tnorm = fmax(fabs(lo), fabs(hi));
-  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-  for (int j = tid; j < kb; j += NT) {
-    const int target = n - 1 - j;  // eigenvalues strictly below lambda_j (no ties)
-    double l = lo, h = hi;
-    for (int it = 0; it < 120; ++it) {
-      const double mid = 0.5 * (l + h);
-      if (h - l <= fmax(2.5e-16 * fmax(fabs(l), fabs(h)), 4e-17 * tnorm) || mid == l || mid == h) break;
-      if (sturm_count(S.d, S.e2, n, mid, pivmin) > target) h = mid;
-      else l = mid;
-    }
-    S.ev[j] = 0.5 * (l + h);
-  }
-  __syncthreads();
-  for (int j = tid; j < n; j += NT) dsc.evals[j] = j < kb ? S.ev[j] : 0.0;
-  if (tid == 0 && dsc.trace) *dsc.trace = tr;
-  if (kvec <= 0) return;
-  const double floorv = EIG_FLOOR * S.ev[0];
-  int kz = 0;  // vectors above the numerical-zero floor (a leading block)
-  while (kz < kvec && S.ev[kz] > floorv && S.ev[0] > 0) ++kz;
-  cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
-  // ---- 4. inverse iteration on T, one thread per vector ----
-  {
-    const long long ks = (kz + 63) / 64 * 64;  // interleave stride of the solve arrays
-    double* __restrict__ X = work + 2LL * n * n;
-    double* __restrict__ Y = X + (long long)n * ks;
-    double* __restrict__ U0 = Y + (long long)n * ks;
-    double* __restrict__ U1 = U0 + (long long)n * ks;
-    double* __restrict__ U2 = U1 + (long long)n * ks;
-    double* __restrict__ LL = U2 + (long long)n * ks;
-    const double pivtol = 2.2204460492503131e-16 * fmax(tnorm, 1e-300);
-    for (int j = tid; j < kvec; j += NT) {
-      if (j >= kz) {
-        for (int i = 0; i < n; ++i) Z[(long long)i * n + j] = mk(0.0, 0.0);
-        continue;
-      }
-      const double lam = S.ev[j];
-      unsigned long long pivbits[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      double u0 = S.d[0] - lam, u1 = n > 1 ? S.e[0] : 0.0, u2 = 0.0;
-      for (int k = 0; k + 1 < n; ++k) {
-        const double l = S.e[k], ak1 = S.d[k + 1] - lam, ek1 = (k + 2 < n) ? S.e[k + 1] : 0.0;
-        const long long o = (long long)k * ks + j;
-        if (fabs(u0) >= fabs(l) || fabs(l) < pivtol) {
-          double piv = u0;
-          if (fabs(piv) < pivtol) piv = piv >= 0 ? pivtol : -pivtol;
-          const double mult = l / piv;
-          U0[o] = piv; U1[o] = u1; U2[o] = u2; LL[o] = mult;
-          const double nu0 = ak1 - mult * u1, nu1 = ek1 - mult * u2;
-          u0 = nu0; u1 = nu1; u2 = 0.0;
-        } else {
-          const double mult = u0 / l;
-          U0[o] = l; U1[o] = ak1; U2[o] = ek1; LL[o] = mult;
-          pivbits[k >> 6] |= 1ULL << (k & 63);
-          const double nu0 = u1 - mult * ak1, nu1 = u2 - mult * ek1;
-          u0 = nu0; u1 = nu1; u2 = 0.0;
-        }
-      }
-      if (fabs(u0) < pivtol) u0 = u0 >= 0 ? pivtol : -pivtol;
-      {
-        const long long o = (long long)(n - 1) * ks + j;
-        U0[o] = u0; U1[o] = 0; U2[o] = 0; LL[o] = 0;
-      }
-      for (int i = 0; i < n; ++i) X[(long long)i * ks + j] = start_entry(j, i);
-      double scale = 1.0;
-      for (int iter = 0; iter < 3; ++iter) {
-        // forward (row swaps, L): X -> Y, the running entry carried in a register
-        double carry = X[j] * scale;
-        int k = 0;
-        for (; k + UB < n; k += UB) {
-          double nx[UB], lm[UB];
-#pragma unroll
-          for (int u = 0; u < UB; ++u) {
-            nx[u] = X[(long long)(k + 1 + u) * ks + j];
-            lm[u] = LL[(long long)(k + u) * ks + j];
-          }
-#pragma unroll
-          for (int u = 0; u < UB; ++u) {
-            double bk = carry, b1 = nx[u] * scale;
-            if ((pivbits[(k + u) >> 6] >> ((k + u) & 63)) & 1ULL) { const double t = bk; bk = b1; b1 = t; }
-            b1 -= lm[u] * bk;
-            Y[(long long)(k + u) * ks + j] = bk;
-            carry = b1;
-          }
-        }
-        for (; k + 1 < n; ++k) {
-          double bk = carry, b1 = X[(long long)(k + 1) * ks + j] * scale;
-          if ((pivbits[k >> 6] >> (k & 63)) & 1ULL) { const double t = bk; bk = b1; b1 = t; }
-          b1 -= LL[(long long)k * ks + j] * bk;
-          Y[(long long)k * ks + j] = bk;
-          carry = b1;
-        }
-        Y[(long long)(n - 1) * ks + j] = carry;
-        // backward (U): Y -> X
-        double xn1 = 0, xn2 = 0, mx = 0;
-        k = n - 1;
-        for (; k - UB + 1 >= 0; k -= UB) {
-          double y[UB], a0[UB], a1[UB], a2[UB];
-#pragma unroll
-          for (int u = 0; u < UB; ++u) {
-            const long long o = (long long)(k - u) * ks + j;
-            y[u] = Y[o]; a0[u] = U0[o]; a1[u] = U1[o]; a2[u] = U2[o];
-          }
-#pragma unroll
-          for (int u = 0; u < UB; ++u) {
-            const double x = (y[u] - a1[u] * xn1 - a2[u] * xn2) / a0[u];
-            X[(long long)(k - u) * ks + j] = x;
-            xn2 = xn1;
-            xn1 = x;
-            mx = fmax(mx, fabs(x));
-          }
-        }
-        for (; k >= 0; --k) {
-          const long long o = (long long)k * ks + j;
-          const double x = (Y[o] - U1[o] * xn1 - U2[o] * xn2) / U0[o];
-          X[o] = x;
-          xn2 = xn1;
-          xn1 = x;
-          mx = fmax(mx, fabs(x));
-        }
-        scale = mx > 0 ? 1.0 / mx : 1.0;
-      }
-      double nn = 0;
-      for (int i = 0; i < n; ++i) {
-        const double x = X[(long long)i * ks + j] * scale;
-        nn += x * x;
-      }
-      const double s = scale / sqrt(nn);
-      for (int i = 0; i < n; ++i) Z[(long long)i * n + j] = mk(X[(long long)i * ks + j] * s, 0.0);
-    }
-  }
-  __syncthreads();
-  // ---- 5. Gram-Schmidt (twice) inside clusters of close eigenvalues ----
-  if (tid == 0) {
-    int c = 0;
-    for (int j = 0; j < kz; ++j) {
-      if (j > 0 && S.ev[j - 1] - S.ev[j] > 1e-6 * fabs(S.ev[j - 1])) ++c;
-      S.clus[j] = c;
-    }
-  }
-  __syncthreads();
-  for (int j = 1; j < kz; ++j) {
-    if (S.clus[j] != S.clus[j - 1]) continue;  // uniform across the block
-    int i0 = j - 1;
-    while (i0 > 0 && S.clus[i0 - 1] == S.clus[j]) --i0;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int i = i0; i < j; ++i) {
-        double s = 0;
-        for (int r = tid; r < n; r += NT) s += Z[(long long)r * n + i].re * Z[(long long)r * n + j].re;
-        s = block_sum(s, S.red, par);
-        for (int r = tid; r < n; r += NT) Z[(long long)r * n + j].re -= s * Z[(long long)r * n + i].re;
-        __syncthreads();
-      }
-      double nn = 0;
-      for (int r = tid; r < n; r += NT) nn += Z[(long long)r * n + j].re * Z[(long long)r * n + j].re;
-      nn = block_sum(nn, S.red, par);
-      const double sc = 1.0 / sqrt(nn);
-      for (int r = tid; r < n; r += NT) Z[(long long)r * n + j].re *= sc;
-      __syncthreads();
-    }
-  }
+  const int kz = eig_tail<NT>(dsc, n, tr, S, par);
   // ---- 6. back-transformation z <- H_0 ... H_{n-2} z ----
   if (kz > 0) {
+    cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
     int nq = NT / kz;
     if (nq < 1) nq = 1;
     if (nq > 16) nq = 16;
@@ -455,27 +495,286 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, Share
 }
 }  // namespace
 
-__global__ __launch_bounds__(NT) void k_heev_lds(const EigDesc* __restrict__ descs, int* __restrict__ status) {
-  __shared__ cpx<double> sA[LDS_N * LDS_N];
-  __shared__ Shared S;
-  const EigDesc& d = descs[blockIdx.x];
-  if (!d.active || d.n <= 0 || d.n > LDS_N) return;
-  heev_core(d, sA, S);
+// ---------------------------------------------------------------------------
+// n <= 128: the matrix lives in registers.  512 threads; thread t owns
+// column c = t % 128 and the 32 rows 32 (t / 128) .. 32 (t / 128) + 31 of it
+// (a wave: one row block, 64 consecutive columns).  Each tridiagonalisation step is four
+// phases between barriers: (a) the previous step's rank-2 update on the
+// owned entries and publication of column k, (b) the reflector (one wave),
+// (c) partial products of A v over the owned rows, (d) their sums and
+// w (one wave).  The reflectors go to dsc.work for the back-transformation,
+// which keeps the eigenvector block in registers in the same layout.
+// ---------------------------------------------------------------------------
+constexpr int RN = 128;
+constexpr int NTR = 512;      // threads: two waves per SIMD leave 256 VGPRs each
+constexpr int RQ = NTR / RN;  // row blocks
+constexpr int RR = RN / RQ;   // rows per thread
+
+// 16-byte alignment lets the compiler use 128-bit LDS accesses with
+// immediate offsets for the complex vectors.
+struct alignas(16) SharedR {
+  alignas(16) cpx<double> tau[RN];
+  alignas(16) cpx<double> x[RN];
+  alignas(16) cpx<double> v[2][RN];
+  alignas(16) cpx<double> vp[RN];
+  alignas(16) cpx<double> wp[RN];
+  alignas(16) cpx<double> pp[2][RQ][RN];
+  double d[RN], e[RN], e2[RN];
+  double ev[RN + 1];
+  int clus[RN + 1];
+  double red[2 * (NTR / 64)];
+  int flag[4];
+};
+
+__device__ inline double wave_allsum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ descs, int* __restrict__ status) {
+  __shared__ SharedR S;
+  const EigDesc& dsc = descs[blockIdx.x];
+  if (!dsc.active || dsc.n <= 0 || dsc.n > RN) return;
+  const int n = dsc.n, tid = threadIdx.x, lane = tid & 63;
+  const int c = tid % RN, q = tid / RN, r0 = q * RR;
+  int par = 0;
+  cpx<double>* __restrict__ Vg = reinterpret_cast<cpx<double>*>(dsc.work);  // row k: v_k, absolute index
+  // ---- load (symmetrised) ----
+  cpx<double> a[RR];
+  {
+    const cpx<double>* __restrict__ Ain = reinterpret_cast<const cpx<double>*>(dsc.a);
+    double trp = 0;
+#pragma unroll
+    for (int u = 0; u < RR; ++u) {
+      const int r = r0 + u;
+      a[u] = mk(0.0, 0.0);
+      if (r < n && c < n) {
+        const cpx<double> x = Ain[(long long)r * dsc.lda + c], y = Ain[(long long)c * dsc.lda + r];
+        a[u] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+        if (r == c) trp += a[u].re;
+      }
+    }
+    const double tr = block_sum<NTR>(trp, S.red, par);
+    if (tid == 0) S.ev[RN] = tr;  // parked until the tail
+  }
+  // ---- tridiagonalisation ----
+  // The shared vectors v, vp, wp are exactly zero outside the active range
+  // of their step, so the register updates and products run over every
+  // owned entry without predicates: out-of-range terms are exact zeros.
+  for (int i = tid; i < RN; i += NTR) {
+    S.vp[i] = mk(0.0, 0.0);
+    S.wp[i] = mk(0.0, 0.0);
+    S.v[0][i] = mk(0.0, 0.0);
+    S.v[1][i] = mk(0.0, 0.0);
+  }
+  __syncthreads();
+  bool pend = false;
+  for (int k = 0; k + 1 < n; ++k) {
+    const int c0 = k + 1;
+    // (a) rank-2 update of step k-1 on [k, n) x [k, n); publish column k
+    if (pend && r0 + RR > k) {
+      const cpx<double> wc = cconj(S.wp[c]), vc = cconj(S.vp[c]);
+#pragma unroll
+      for (int u0 = 0; u0 < RR; u0 += 8) {
+        cpx<double> vr[8], wr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          vr[u] = S.vp[r0 + u0 + u];
+          wr[u] = S.wp[r0 + u0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u0 + u] = a[u0 + u] - vr[u] * wc - wr[u] * vc;
+      }
+    }
+    if (c == k) {
+#pragma unroll
+      for (int u = 0; u < RR; ++u) S.x[r0 + u] = a[u];
+    }
+    __syncthreads();
+    // (b) reflector with H^H x = beta e_1, v[c0] = 1 (wave 0, every lane
+    // computes the same scalars)
+    if (tid < 64) {
+      double xn = 0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        const cpx<double> x = S.x[i];
+        xn += (i > c0 && i < n) ? cabs2(x) : 0.0;
+      }
+      xn = wave_allsum(xn);
+      const cpx<double> alpha = S.x[c0];
+      if (lane == 0) S.d[k] = S.x[k].re;
+      if (xn == 0.0 && alpha.im == 0.0) {
+        if (lane == 0) {
+          S.tau[k] = mk(0.0, 0.0);
+          S.e[k] = alpha.re;
+          S.flag[0] = 0;
+        }
+      } else {
+        const double nrm = sqrt(cabs2(alpha) + xn);
+        const double beta = alpha.re >= 0 ? -nrm : nrm;
+        const cpx<double> den = mk(alpha.re - beta, alpha.im);
+        const double rdd = 1.0 / cabs2(den);
+        const cpx<double> sc = mk(den.re * rdd, -den.im * rdd);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          const cpx<double> v = S.x[i] * sc;
+          S.v[0][i] = (i == c0) ? mk(1.0, 0.0) : ((i > c0 && i < n) ? v : mk(0.0, 0.0));
+        }
+        if (lane == 0) {
+          const double rb = 1.0 / beta;
+          S.tau[k] = mk((beta - alpha.re) * rb, -alpha.im * rb);
+          S.e[k] = beta;
+          S.flag[0] = 1;
+        }
+      }
+    }
+    __syncthreads();
+    const bool act = S.flag[0] != 0;
+    if (act) {
+      // (c) partial p[c] = sum_r conj(A[r][c]) v[r] over the owned rows; the
+      // owner of column k keeps v_k in its finished entries
+      const bool rows = r0 + RR > c0;
+      if (c == k) {
+#pragma unroll
+        for (int u = 0; u < RR; ++u) a[u] = S.v[0][r0 + u];
+      }
+      if (c >= c0 && c < n) {
+        double pr = 0, pi = 0;
+        if (rows) {
+#pragma unroll
+          for (int u = 0; u < RR; ++u) {
+            const cpx<double> v = S.v[0][r0 + u];
+            pr += a[u].re * v.re + a[u].im * v.im;
+            pi += a[u].re * v.im - a[u].im * v.re;
+          }
+        }
+        S.pp[0][q][c] = mk(pr, pi);
+      }
+      __syncthreads();
+      // (d) p, gamma = v^H p, w = tau p - |tau|^2 gamma / 2 v (wave 0)
+      if (tid < 64) {
+        const cpx<double> tau = S.tau[k];
+        cpx<double> ph[2], vh[2];
+        double g = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          const bool in = i >= c0 && i < n;
+          cpx<double> p = mk(0.0, 0.0);
+#pragma unroll
+          for (int qq = 0; qq < RQ; ++qq) p = p + S.pp[0][qq][i];
+          p = in ? p : mk(0.0, 0.0);
+          const cpx<double> v = S.v[0][i];
+          g += v.re * p.re + v.im * p.im;
+          ph[h] = p;
+          vh[h] = v;
+        }
+        g = wave_allsum(g);
+        const double cc = 0.5 * cabs2(tau) * g;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          S.wp[i] = tau * ph[h] - cc * vh[h];
+          S.vp[i] = vh[h];
+        }
+      }
+      __syncthreads();
+    }
+    pend = act;
+  }
+  if (c == n - 1) {
+#pragma unroll
+    for (int u = 0; u < RR; ++u) {
+      if (r0 + u == n - 1) {
+        cpx<double> x = a[u];
+        if (pend) x = x - S.vp[n - 1] * cconj(S.wp[n - 1]) - S.wp[n - 1] * cconj(S.vp[n - 1]);
+        S.d[n - 1] = x.re;
+      }
+    }
+  }
+  // reflectors to global memory for the back-transformation (column c of
+  // the register block holds v_c below the diagonal)
+  if (c + 1 < n) {
+#pragma unroll
+    for (int u = 0; u < RR; ++u) {
+      const int r = r0 + u;
+      if (r > c && r < n) Vg[(long long)c * n + r] = a[u];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i + 1 < n; i += NTR) S.e2[i] = S.e[i] * S.e[i];
+  const double tr = S.ev[RN];
+  __syncthreads();
+  const int kz = eig_tail<NTR>(dsc, n, tr, S, par);
+  // ---- back-transformation z <- H_0 ... H_{n-2} z, z in registers ----
+  if (kz > 0) {
+    cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
+    cpx<double> z[RR];
+#pragma unroll
+    for (int u = 0; u < RR; ++u) {
+      const int r = r0 + u;
+      z[u] = (c < kz && r < n) ? Z[(long long)r * n + c] : mk(0.0, 0.0);
+    }
+    if (n >= 2 && tid == n - 1) S.v[(n - 2) & 1][tid] = Vg[(long long)(n - 2) * n + tid];
+    for (int k = n - 2; k >= 0; --k) {
+      const int b = k & 1;
+      __syncthreads();  // v[b] of reflector k is visible; pp[b] is free
+      const bool pre = k >= 1 && tid >= k && tid < n;
+      cpx<double> vn = mk(0.0, 0.0);
+      if (pre) vn = Vg[(long long)(k - 1) * n + tid];  // next reflector, stored below
+      const cpx<double> t = S.tau[k];
+      const bool active = !(t.re == 0.0 && t.im == 0.0);
+      const int r1 = k + 1;
+      const bool rows = r0 + RR > r1;
+      if (active && c < kz) {
+        double yr = 0, yi = 0;
+        if (rows) {
+#pragma unroll
+          for (int u = 0; u < RR; ++u) {
+            const cpx<double> v = S.v[b][r0 + u];
+            yr += v.re * z[u].re + v.im * z[u].im;  // conj(v) z
+            yi += v.re * z[u].im - v.im * z[u].re;
+          }
+        }
+        S.pp[b][q][c] = mk(yr, yi);
+      }
+      __syncthreads();
+      if (active && c < kz && rows) {
+        cpx<double> y = mk(0.0, 0.0);
+#pragma unroll
+        for (int qq = 0; qq < RQ; ++qq) y = y + S.pp[b][qq][c];
+        const cpx<double> ty = t * y;
+#pragma unroll
+        for (int u = 0; u < RR; ++u) z[u] = z[u] - S.v[b][r0 + u] * ty;
+      }
+      if (pre) S.v[b ^ 1][tid] = vn;
+    }
+    if (c < kz) {
+#pragma unroll
+      for (int u = 0; u < RR; ++u) {
+        const int r = r0 + u;
+        if (r < n) Z[(long long)r * n + c] = z[u];
+      }
+    }
+  }
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
 
+// n in (128, 512]: the matrix in global memory (L2-resident).
 __global__ __launch_bounds__(NT) void k_heev_global(const EigDesc* __restrict__ descs, int* __restrict__ status) {
   __shared__ Shared S;
   const EigDesc& d = descs[blockIdx.x];
-  if (!d.active || d.n <= LDS_N || d.n > 512) return;
+  if (!d.active || d.n <= RN || d.n > 512) return;
   heev_core(d, reinterpret_cast<cpx<double>*>(d.work), S);
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
 
 void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hipStream_t s) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_heev_lds, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
-  if (maxn > LDS_N) hipLaunchKernelGGL(k_heev_global, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
+  hipLaunchKernelGGL(k_heev_reg, dim3(nitems), dim3(NTR), 0, s, d_descs, d_status);
+  if (maxn > RN) hipLaunchKernelGGL(k_heev_global, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
 }
 
 }  // namespace mpdo

@@ -181,8 +181,7 @@ template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& op
   // chunks bounded by a workspace budget
   const size_t budget = (size_t)8 << 30;
   const int kx = cfg_.kap_max, cx = cfg_.chi_max, mm = std::max(1, cfg_.mmax);
-  const size_t per2 = (size_t)(2 * kx * cx) * (2 * kx * cx) * sizeof(cpx<T>) * 1 +
-                      (size_t)(2 * kx * cx) * (4 * cx) * sizeof(cpx<T>) * 2 +
+  const size_t per2 = (size_t)(2 * kx * cx) * (4 * cx) * sizeof(cpx<T>) * 2 +
                       (size_t)(4 * cx) * (4 * cx) * 16 * 4 + (size_t)(kx * mm) * (kx * mm) * 16 * 3 + (1 << 20);
   const int chunk2 = (int)std::max<size_t>(1, budget / per2);
   for (size_t a = 0; a < one.size(); a += 4096)
@@ -264,13 +263,14 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
   Ctx1<T>* dctx = reinterpret_cast<Ctx1<T>*>(dv + uCtx);
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   launch_q1_prepare<T>(dctx, n, splitsH, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH, 2 * kx, 2 * kx, st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH, gemm_tiles(2 * kx, 2 * kx),
+                                 st_);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uH), reinterpret_cast<double**>(dv + uOut), n,
                        4 * kx * kx, st_);
   launch_q1_gamma<T>(dctx, n, st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uE), n, ng, sweeps_.as<int>(), st_);
   launch_q1_select<T>(dctx, n, tp, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uA), n, cx, 1, 2 * kx, cx, st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uA), n, cx, 1, gemm_tiles(2 * kx, cx), st_);
   hip_check(hipGetLastError(), "launch (1q sublayer)");
   for (auto* g : ops) par_[soff_[g->inst] + g->site] ^= 1;
 }
@@ -281,14 +281,13 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
   int m2 = 1;
   for (auto* g : ops) m2 = std::max(m2, g->ch ? g->ch->m : 1);
-  const int splitsH = splits_for((long long)cx * kx * cx);
+  const int splitsH = splits_for((long long)cx * 2 * cx);
   const int splitsE = splits_for((long long)kx * cx);
   const int splitsC = splits_for((long long)2 * kx * cx);
   const int ng = kx * m2;
   const long long thetaN = (long long)2 * kx * cx;
   Layout w;
   const size_t oG = w.add((size_t)m2 * 16 * 16);
-  const size_t oTheta = w.add((size_t)thetaN * thetaN * sizeof(cpx<T>));
   const size_t oH = w.add((size_t)16 * kx * kx * 16);
   const size_t oHp = w.add((size_t)splitsH * 16 * kx * kx * 16);
   const size_t oE = w.add((size_t)4 * cx * cx * 16);
@@ -317,16 +316,18 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   const size_t per = w.off;
   Layout u;
   const size_t uCtx = u.add(sizeof(Ctx2<T>) * n);
-  const size_t uTheta = u.add(sizeof(GemmDesc) * n);
-  const size_t uGram = u.add(sizeof(GemmDesc) * 2 * n);
-  const size_t uEig = u.add(sizeof(EigDesc) * 2 * n);
+  const size_t uGramE = u.add(sizeof(GemmDesc) * n);
+  const size_t uEigE = u.add(sizeof(EigDesc) * n);
+  const size_t uGramH = u.add(sizeof(GemmDesc) * n);
+  const size_t uEigG = u.add(sizeof(EigDesc) * n);
   const size_t uTh = u.add(sizeof(GemmDesc) * n);
   const size_t uTh2 = u.add(sizeof(GemmDesc) * n);
   const size_t uC = u.add(sizeof(GemmDesc) * n);
   const size_t uEigC = u.add(sizeof(EigDesc) * n);
   const size_t uX = u.add(sizeof(GemmDesc) * n);
   const size_t uOut = u.add(sizeof(GemmDesc) * 2 * n);
-  const size_t uOutsG = u.add(sizeof(double*) * 2 * n);
+  const size_t uOutsE = u.add(sizeof(double*) * n);
+  const size_t uOutsH = u.add(sizeof(double*) * n);
   const size_t uOutsC = u.add(sizeof(double*) * n);
   const size_t uU = u.add(sizeof(double) * 32 * n);
   char *h = nullptr, *dv = nullptr;
@@ -362,7 +363,6 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
     c.disc = disc_ptr(b, i);
     c.scratch = at<int>(base, oScr);
     c.G = at<double>(base, oG);
-    c.Theta = at<cpx<T>>(base, oTheta);
     c.H = at<double>(base, oH);
     c.E = at<double>(base, oE);
     c.Gam = at<double>(base, oGam);
@@ -381,57 +381,66 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
     c.Zt = at<double>(base, oZt);
     c.Zc = at<cpx<T>>(base, oZc);
     c.X = at<cpx<T>>(base, oX);
-    c.dTheta = reinterpret_cast<GemmDesc*>(dv + uTheta) + it;
-    c.dGram = reinterpret_cast<GemmDesc*>(dv + uGram) + 2 * it;
-    c.dEig = reinterpret_cast<EigDesc*>(dv + uEig) + 2 * it;
+    c.dGramE = reinterpret_cast<GemmDesc*>(dv + uGramE) + it;
+    c.dEigE = reinterpret_cast<EigDesc*>(dv + uEigE) + it;
+    c.dGramH = reinterpret_cast<GemmDesc*>(dv + uGramH) + it;
+    c.dEigG = reinterpret_cast<EigDesc*>(dv + uEigG) + it;
     c.dTh = reinterpret_cast<GemmDesc*>(dv + uTh) + it;
     c.dTh2 = reinterpret_cast<GemmDesc*>(dv + uTh2) + it;
     c.dC = reinterpret_cast<GemmDesc*>(dv + uC) + it;
     c.dEigC = reinterpret_cast<EigDesc*>(dv + uEigC) + it;
     c.dX = reinterpret_cast<GemmDesc*>(dv + uX) + it;
     c.dOut = reinterpret_cast<GemmDesc*>(dv + uOut) + 2 * it;
-    GemmDesc* hg = at<GemmDesc>(h, uGram) + 2 * it;
-    hg[0].C = at<double>(base, oHp);
-    hg[0].sSplit = (long long)16 * kx * kx;
-    hg[1].C = at<double>(base, oEp);
-    hg[1].sSplit = (long long)4 * cx * cx;
-    EigDesc* he = at<EigDesc>(h, uEig) + 2 * it;
-    he[0].work = at<double>(base, oWkG);
-    he[0].kvec = kx;
-    he[1].work = at<double>(base, oWkE);
-    he[1].kvec = 2 * cx;  // every eigenpair of the right-factor Gram
+    GemmDesc& hgE = at<GemmDesc>(h, uGramE)[it];
+    hgE.C = at<double>(base, oEp);
+    hgE.sSplit = (long long)4 * cx * cx;
+    GemmDesc& hgH = at<GemmDesc>(h, uGramH)[it];
+    hgH.C = at<double>(base, oHp);
+    hgH.sSplit = (long long)16 * kx * kx;
+    EigDesc& heE = at<EigDesc>(h, uEigE)[it];
+    heE.work = at<double>(base, oWkE);
+    heE.kvec = 2 * cx;  // every eigenpair of the right-factor Gram
+    EigDesc& heG = at<EigDesc>(h, uEigG)[it];
+    heG.work = at<double>(base, oWkG);
+    heG.kvec = kx;
     GemmDesc& hc = at<GemmDesc>(h, uC)[it];
     hc.C = at<double>(base, oCp);
     hc.sSplit = (long long)16 * cx * cx;
     at<EigDesc>(h, uEigC)[it].work = at<double>(base, oWkC);
     at<EigDesc>(h, uEigC)[it].kvec = cx;
-    at<double*>(h, uOutsG)[2 * it] = c.H;
-    at<double*>(h, uOutsG)[2 * it + 1] = c.E;
+    at<double*>(h, uOutsE)[it] = c.E;
+    at<double*>(h, uOutsH)[it] = c.H;
     at<double*>(h, uOutsC)[it] = c.Cm;
   }
   commit(up, h, dv, u.off);
   Ctx2<T>* dctx = reinterpret_cast<Ctx2<T>*>(dv + uCtx);
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
-  const int maxGram = std::max(4 * kx, 2 * cx);
-  launch_q2_prepare<T>(dctx, n, splitsH, splitsE, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTheta), n, 1, 1, (int)thetaN, (int)thetaN, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGram), 2 * n, 1, std::max(splitsH, splitsE),
-                                 maxGram, maxGram, st_);
-  launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGram), reinterpret_cast<double**>(dv + uOutsG), 2 * n,
-                       maxGram * maxGram, st_);
+  int* status = sweeps_.as<int>();
+  launch_q2_prepare<T>(dctx, n, splitsE, st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGramE), n, 1, splitsE, gemm_tiles(2 * cx, 2 * cx),
+                                 st_);
+  launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramE), reinterpret_cast<double**>(dv + uOutsE), n,
+                       4 * cx * cx, st_);
+  launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigE), n, 2 * cx, status, st_);
+  launch_q2_select_e<T>(dctx, n, splitsH, tp, st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh), n, 1, 1, gemm_tiles((int)thetaN, 4 * cx), st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGramH), n, 1, splitsH, gemm_tiles(4 * kx, 4 * kx),
+                                 st_);
+  launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramH), reinterpret_cast<double**>(dv + uOutsH), n,
+                       16 * kx * kx, st_);
   launch_q2_gamma<T>(dctx, n, st_);
-  launch_eigh(reinterpret_cast<EigDesc*>(dv + uEig), 2 * n, std::max(ng, 2 * cx), sweeps_.as<int>(), st_);
-  launch_q2_select_a<T>(dctx, n, splitsC, tp, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh), n, 1, 1, (int)thetaN, 4 * cx, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh2), n, cx, 1, 4 * kx, 2 * cx, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uC), n, 1, splitsC, 4 * cx, 4 * cx, st_);
+  launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigG), n, ng, status + n, st_);
+  launch_q2_select_g<T>(dctx, n, splitsC, tp, st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh2), n, cx, 1, gemm_tiles(4 * kx, 2 * cx), st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uC), n, 1, splitsC, gemm_tiles(4 * cx, 4 * cx), st_);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uC), reinterpret_cast<double**>(dv + uOutsC), n,
                        16 * cx * cx, st_);
-  launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigC), n, 4 * cx, sweeps_.as<int>() + n, st_);
+  launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigC), n, 4 * cx, status + 2 * n, st_);
   launch_q2_select_b<T>(dctx, n, tp, st_);
-  launch_gemm<double, double, T>(reinterpret_cast<GemmDesc*>(dv + uX), n, 1, 1, 2 * cx, 2 * cx, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uOut), 2 * n, 1, 1, (int)thetaN,
-                       std::max(cx, kx * cx), st_);
+  launch_gemm<double, double, T>(reinterpret_cast<GemmDesc*>(dv + uX), n, 1, 1, gemm_tiles(2 * cx, 2 * cx), st_);
+  // B_i' (at most thetaN x cx) and B_{i+1}' (at most 2 cx x kx cx) share a launch
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uOut), 2 * n, 1, 1,
+                       std::max(gemm_tiles((int)thetaN, cx), gemm_tiles(2 * cx, kx * cx)), st_);
   hip_check(hipGetLastError(), "launch (2q sublayer)");
   for (auto* g : ops) {
     par_[soff_[g->inst] + g->site] ^= 1;
@@ -526,9 +535,9 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
   launch_transfer_init<T>(dctx, n, st_);
   for (int s = 0; s < nmax; ++s) {
     launch_transfer_prep<T>(dctx + (size_t)s * n, n, (int)cap_site_ / 2, st_);
-    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n, n, 1, 1, cx,
-                         (int)(2 * cfg_.kap_max * cx), st_);
-    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD2) + (size_t)s * n, n, 1, 1, cx, cx, st_);
+    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n, n, 1, 1,
+                         gemm_tiles(cx, (int)(2 * cfg_.kap_max * cx)), st_);
+    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD2) + (size_t)s * n, n, 1, 1, gemm_tiles(cx, cx), st_);
   }
   double* res = reinterpret_cast<double*>(dv + uRes);
   launch_transfer_finish<T>(dctx, n, res, st_);

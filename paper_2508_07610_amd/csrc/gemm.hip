@@ -33,6 +33,7 @@ template <> struct Mfma<float> {
 
 namespace {
 constexpr int BM = 64, BN = 64, BK = 16, NTHR = 256, PAD = 4;
+constexpr int NXCD = 8;  // accelerator complex dies of the MI355X
 
 __device__ inline long long kaddr(int k, int kinner, long long kstride) {
   return (long long)(k / kinner) * kstride + (k % kinner);
@@ -41,25 +42,31 @@ __device__ inline long long kaddr(int k, int kinner, long long kstride) {
 
 template <typename Tin, typename Tc, typename Tout>
 __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch,
-                                               int maxSplits, int tilesM, int tilesN) {
+                                               int maxSplits, int maxTiles, long long nblocks) {
   typedef typename Mfma<Tc>::v4 v4;
   __shared__ Tc As_re[BK][BM + PAD], As_im[BK][BM + PAD];
   __shared__ Tc Bs_re[BK][BN + PAD], Bs_im[BK][BN + PAD];
 
-  const int tiles = tilesM * tilesN;
-  long long bid = blockIdx.x;
-  const int tile = (int)(bid % tiles);
-  bid /= tiles;
+  // Workgroups are dealt to the XCDs round-robin (block b runs on XCD b % 8);
+  // renumber so that each XCD takes a contiguous range of (item, batch,
+  // split, tile), keeping the tiles that share operands in one L2.
+  const long long per_xcd = (nblocks + NXCD - 1) / NXCD;
+  long long bid = (long long)(blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
+  if (bid >= nblocks) return;
+  const int tile = (int)(bid % maxTiles);
+  bid /= maxTiles;
   const int split = (int)(bid % maxSplits);
   bid /= maxSplits;
   const int batch = (int)(bid % maxBatch);
   const int item = (int)(bid / maxBatch);
   const GemmDesc& d = descs[item];
   if (!d.active || batch >= d.nbatch || split >= d.splits) return;
-  const int tm = tile / tilesN, tn = tile % tilesN;
   const int M = d.M, N = d.N, K = d.K;
+  // this item's tiles are a prefix of the tile range
+  const int tilesN = (N + BN - 1) / BN;
+  if (tile >= ((M + BM - 1) / BM) * tilesN) return;
+  const int tm = tile / tilesN, tn = tile % tilesN;
   const int m0 = tm * BM, n0 = tn * BN;
-  if (m0 >= M || n0 >= N) return;
 
   const cpx<Tin>* A = reinterpret_cast<const cpx<Tin>*>(d.A) + (long long)batch * d.sA;
   const cpx<Tin>* B = reinterpret_cast<const cpx<Tin>*>(d.B) + (long long)batch * d.sB;
@@ -207,15 +214,16 @@ __global__ void k_reduce_splits(const GemmDesc* __restrict__ descs, double* cons
   }
 }
 
+int gemm_tiles(int maxM, int maxN) { return ((maxM + BM - 1) / BM) * ((maxN + BN - 1) / BN); }
+
 template <typename Tin, typename Tc, typename Tout>
-void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxM, int maxN,
-                 hipStream_t s) {
-  if (nitems <= 0) return;
-  const int tilesM = (maxM + BM - 1) / BM, tilesN = (maxN + BN - 1) / BN;
-  const long long blocks = (long long)nitems * maxBatch * maxSplits * tilesM * tilesN;
+void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s) {
+  if (nitems <= 0 || maxTiles <= 0) return;
+  const long long blocks = (long long)nitems * maxBatch * maxSplits * maxTiles;
   if (blocks <= 0) return;
-  hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout>), dim3((unsigned)blocks), dim3(NTHR), 0, s, d_descs, maxBatch,
-                     maxSplits, tilesM, tilesN);
+  const long long grid = (blocks + NXCD - 1) / NXCD * NXCD;
+  hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs, maxBatch,
+                     maxSplits, maxTiles, blocks);
 }
 
 void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int nitems, int maxCount,
@@ -227,9 +235,9 @@ void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int ni
                      d_outs, maxCount);
 }
 
-template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, int, hipStream_t);
-template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, int, hipStream_t);
-template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, int, hipStream_t);
-template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, int, hipStream_t);
+template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, hipStream_t);
+template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, hipStream_t);
+template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, hipStream_t);
+template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, hipStream_t);
 
 }  // namespace mpdo

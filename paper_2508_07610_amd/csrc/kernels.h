@@ -5,19 +5,22 @@
 namespace mpdo {
 
 // Batched complex GEMM (see GemmDesc).  The grid covers nitems x maxBatch x
-// maxSplits x tiles of a maxM x maxN output; items with smaller shapes exit
-// early.  Tin: input precision, Tc: MFMA precision, Tout: output precision.
+// maxSplits x maxTiles output tiles of 64 x 64; an item uses the first
+// ceil(M/64) ceil(N/64) tiles of its range, so maxTiles must bound that
+// count for every item (gemm_tiles of the largest M and N).  Tin: input
+// precision, Tc: MFMA precision, Tout: output precision.
+int gemm_tiles(int maxM, int maxN);
 template <typename Tin, typename Tc, typename Tout>
-void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxM, int maxN,
-                 hipStream_t s);
+void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s);
 
 // out[item] = sum over splits of the partial products of descs[item]
 // (complex double, dense M x ldc).
 void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int nitems, int maxCount,
                           hipStream_t s);
 
-// Batched Hermitian eigensolver (Jacobi, FP64), one workgroup per problem.
-// d_sweeps[item] receives the sweep count (negative: not converged).
-void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_sweeps, hipStream_t s);
+// Batched Hermitian eigensolver (FP64, Householder tridiagonalisation,
+// multisection, inverse iteration), one workgroup per problem; maxn bounds
+// every item's n.  d_status[item] is set to 1 when the item's workgroup ran.
+void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hipStream_t s);
 
 }  // namespace mpdo

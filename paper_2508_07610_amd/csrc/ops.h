@@ -59,7 +59,6 @@ template <typename T> struct Ctx2 {
   double* disc;
   int* scratch;           // [0] = kappa', [1] = r_F
   double* G;              // m x 4 x 4
-  cpx<T>* Theta;          // (2 k1 chil) x (2 k2 chir)
   double* H;              // (4 k1)^2
   double* E;              // (2 chim)^2
   double* Gam;            // (k1 m)^2
@@ -75,9 +74,10 @@ template <typename T> struct Ctx2 {
   double* Zt;             // (2 r) x r_F
   cpx<T>* Zc;             // (2 r_F) x r
   cpx<T>* X;              // (2 r) x (2 chim)
-  GemmDesc* dTheta;       // 1
-  GemmDesc* dGram;        // 2: H, E
-  EigDesc* dEig;          // 2: Gamma, E
+  GemmDesc* dGramE;       // E = F F^dag
+  EigDesc* dEigE;
+  GemmDesc* dGramH;       // H from th (lambda^2-weighted)
+  EigDesc* dEigG;         // Gamma
   GemmDesc* dTh;
   GemmDesc* dTh2;
   GemmDesc* dC;
@@ -113,9 +113,10 @@ template <typename T> void launch_q1_prepare(Ctx1<T>* d_ctx, int n, int splitsH,
 template <typename T> void launch_q1_gamma(Ctx1<T>* d_ctx, int n, hipStream_t s);
 template <typename T> void launch_q1_select(Ctx1<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
 
-template <typename T> void launch_q2_prepare(Ctx2<T>* d_ctx, int n, int splitsH, int splitsE, hipStream_t s);
+template <typename T> void launch_q2_prepare(Ctx2<T>* d_ctx, int n, int splitsE, hipStream_t s);
+template <typename T> void launch_q2_select_e(Ctx2<T>* d_ctx, int n, int splitsH, TruncParams tp, hipStream_t s);
 template <typename T> void launch_q2_gamma(Ctx2<T>* d_ctx, int n, hipStream_t s);
-template <typename T> void launch_q2_select_a(Ctx2<T>* d_ctx, int n, int splitsC, TruncParams tp, hipStream_t s);
+template <typename T> void launch_q2_select_g(Ctx2<T>* d_ctx, int n, int splitsC, TruncParams tp, hipStream_t s);
 template <typename T> void launch_q2_select_b(Ctx2<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
 
 template <typename T> void launch_transfer_prep(CtxT<T>* d_ctx, int n, int maxElems, hipStream_t s);

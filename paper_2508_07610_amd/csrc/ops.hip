@@ -215,42 +215,25 @@ __global__ __launch_bounds__(GT) void k_q1_select(Ctx1<T>* ctxs, TruncParams tp)
 // ============================================================================
 // two-site noisy gate
 // ============================================================================
+// Order of the two-site update (B_i, B_{i+1} right-canonical, weights lambda
+// on the bond left of i):
+//   E = F F^dag, F = B_{i+1} as [(m t2)] x [(k2 r)]  -> E = P D P^dag,
+//   L_F = P D^(1/2) on the r_F numerically non-zero eigenvalues,
+//   th = B_i L_F  (so that the two-site block is th applied to F's row space),
+//   H  = lambda^2-weighted Gram of th over (l, beta)  (the inner-index Gram of
+//        the gate input, Eq. (9), expressed in the F basis),
+//   Gamma from H and the fused operators G_j -> eig -> W (inner truncation,
+//        Eqs. (10)-(11)),
+//   th2 = W th, C = weighted Gram of th2 -> eig -> new bond (SVD, Sec. II.D).
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q2_prepare(Ctx2<T>* ctxs, int splitsH, int splitsE) {
+__global__ __launch_bounds__(GT) void k_q2_prepare(Ctx2<T>* ctxs, int splitsE) {
   __shared__ cpx<double> sU[64];
   Ctx2<T>& c = ctxs[blockIdx.x];
   build_G(c.g, c.kraus, c.m, c.G, sU);
   if (threadIdx.x != 0) return;
-  const int cl = *c.chil, cm = *c.chim, cr = *c.chir, k1 = *c.kap1, k2 = *c.kap2;
-  {  // Theta[(l t1 k1),(t2 k2 r)] = sum_m B_i[(l t1 k1), m] B_{i+1}[m, (t2 k2 r)]
-    GemmDesc& d = *c.dTheta;
-    clear_desc(d);
-    d.A = c.Bi; d.B = c.Bj; d.C = c.Theta;
-    d.M = cl * 2 * k1; d.K = cm; d.N = 2 * k2 * cr;
-    d.lda = cm; d.ldb = 2 * k2 * cr; d.ldc = 2 * k2 * cr;
-  }
-  {  // H[a][a'] = sum_l lambda_l^2 sum_(k2 r) conj(Theta[l][a][(k2 r)]) Theta[l][a'][(k2 r)], a = (t1 k1 t2)
-    GemmDesc& d = c.dGram[0];
-    void* C = d.C;
-    const long long ss = d.sSplit;
-    clear_desc(d);
-    d.C = C; d.sSplit = ss;
-    if (c.m <= 1) {
-      d.active = 0;
-    } else {
-      d.A = c.Theta; d.B = c.Theta; d.opA = OP_C; d.opB = OP_T;
-      d.M = d.N = 4 * k1;
-      d.K = cl * k2 * cr;
-      d.lda = d.ldb = k2 * cr;
-      d.kinner = k2 * cr;
-      d.kstride = (long long)4 * k1 * k2 * cr;
-      d.w = c.laml2; d.wdiv = k2 * cr;
-      d.ldc = 4 * k1;
-      d.splits = splitsH;
-    }
-  }
+  const int cm = *c.chim, cr = *c.chir, k2 = *c.kap2;
   {  // E = F F^dag with F = B_{i+1} as [(m t2)] x [(k2 r)]
-    GemmDesc& d = c.dGram[1];
+    GemmDesc& d = *c.dGramE;
     void* C = d.C;
     const long long ss = d.sSplit;
     clear_desc(d);
@@ -262,20 +245,77 @@ __global__ __launch_bounds__(GT) void k_q2_prepare(Ctx2<T>* ctxs, int splitsH, i
     d.ldc = 2 * cm;
     d.splits = splitsE;
   }
+  {
+    EigDesc& d = *c.dEigE;
+    d.a = c.E; d.lda = 2 * cm; d.n = 2 * cm; d.evals = c.evE; d.evecs = c.vecE; d.trace = c.evE + 2 * cm;
+    d.active = 1;
+  }
+}
+
+// r_F, L_F = P D^(1/2), PD = P D^(-1/2); descriptors of th = B_i L_F and of
+// the Gram H of th.
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q2_select_e(Ctx2<T>* ctxs, int splitsH, TruncParams tp) {
+  __shared__ int s_rF;
+  Ctx2<T>& c = ctxs[blockIdx.x];
+  const int k1 = *c.kap1, cl = *c.chil, cm = *c.chim;
+  const int nE = 2 * cm;
+  if (threadIdx.x == 0) {
+    int rF = 0;
+    const double e0 = c.evE[0];
+    for (int b = 0; b < nE; ++b) rF += (c.evE[b] > tp.tolE * e0) ? 1 : 0;
+    if (rF < 1) rF = 1;
+    s_rF = rF;
+    c.scratch[1] = rF;
+  }
+  __syncthreads();
+  const int rF = s_rF;
+  for (int e = threadIdx.x; e < nE * rF; e += blockDim.x) {
+    const int row = e / rF, b = e % rF;
+    const cpx<double> p = ld(c.vecE, (long long)row * nE + b);
+    const double sq = sqrt(c.evE[b]);
+    c.LF[e] = mk<T>((T)(p.re * sq), (T)(p.im * sq));
+    st(c.PD, e, mk(p.re / sq, p.im / sq));
+  }
+  if (threadIdx.x == 0) {
+    {  // th[(l t1 k1),(t2 b)] = sum_m B_i[(l t1 k1), m] L_F[(m t2), b]
+      GemmDesc& d = *c.dTh;
+      clear_desc(d);
+      d.A = c.Bi; d.B = c.LF; d.C = c.th;
+      d.M = cl * 2 * k1; d.K = cm; d.N = 2 * rF;
+      d.lda = cm; d.ldb = 2 * rF; d.ldc = 2 * rF;
+    }
+    {  // H[a][a'] = sum_l lambda_l^2 sum_b conj(th[l][a][b]) th[l][a'][b],
+       // a = (t1 k1 t2): th[l] viewed as (4 k1) rows of r_F
+      GemmDesc& d = *c.dGramH;
+      void* C = d.C;
+      const long long ss = d.sSplit;
+      clear_desc(d);
+      d.C = C; d.sSplit = ss;
+      if (c.m <= 1) {
+        d.active = 0;
+      } else {
+        d.A = c.th; d.B = c.th; d.opA = OP_C; d.opB = OP_T;
+        d.M = d.N = 4 * k1;
+        d.K = cl * rF;
+        d.lda = d.ldb = rF;
+        d.kinner = rF;
+        d.kstride = (long long)4 * k1 * rF;
+        d.w = c.laml2; d.wdiv = rF;
+        d.ldc = 4 * k1;
+        d.splits = splitsH;
+      }
+    }
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(GT) void k_q2_gamma(Ctx2<T>* ctxs) {
   __shared__ cpx<double> sOm[16 * 16 * 16];  // Omega_{jj'}[t][t'] for m <= 16
   Ctx2<T>& c = ctxs[blockIdx.x];
-  const int m = c.m, k1 = *c.kap1, cm = *c.chim;
-  if (threadIdx.x == 0) {
-    EigDesc& d = c.dEig[1];
-    d.a = c.E; d.lda = 2 * cm; d.n = 2 * cm; d.evals = c.evE; d.evecs = c.vecE; d.trace = c.evE + 2 * cm;
-    d.active = 1;
-  }
+  const int m = c.m, k1 = *c.kap1;
   if (m <= 1) {
-    if (threadIdx.x == 0) c.dEig[0].active = 0;
+    if (threadIdx.x == 0) c.dEigG->active = 0;
     return;
   }
   const int n = k1 * m;
@@ -312,17 +352,19 @@ __global__ __launch_bounds__(GT) void k_q2_gamma(Ctx2<T>* ctxs) {
     st(c.Gam, e, acc);
   }
   if (threadIdx.x == 0) {
-    EigDesc& d = c.dEig[0];
+    EigDesc& d = *c.dEigG;
     d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.evG; d.evecs = c.vecG; d.trace = c.evG + n; d.active = 1;
   }
 }
 
+// kappa' and W; descriptors of th2 = W th, its Gram C and C's eigensolver.
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q2_select_a(Ctx2<T>* ctxs, int splitsC, TruncParams tp) {
-  __shared__ int s_kp, s_rF;
+__global__ __launch_bounds__(GT) void k_q2_select_g(Ctx2<T>* ctxs, int splitsC, TruncParams tp) {
+  __shared__ int s_kp;
   __shared__ double s_scale;
   Ctx2<T>& c = ctxs[blockIdx.x];
-  const int m = c.m, k1 = *c.kap1, cl = *c.chil, cm = *c.chim;
+  const int m = c.m, k1 = *c.kap1, cl = *c.chil;
+  const int rF = c.scratch[1];
   if (threadIdx.x == 0) {
     if (m <= 1) {
       s_kp = k1;
@@ -335,17 +377,10 @@ __global__ __launch_bounds__(GT) void k_q2_select_a(Ctx2<T>* ctxs, int splitsC, 
       s_scale = 1.0 / sqrt(kept);
       if (tot > 0) *c.disc += (tot - kept) / tot;
     }
-    const int nE = 2 * cm;
-    int rF = 0;
-    const double e0 = c.evE[0];
-    for (int b = 0; b < nE; ++b) rF += (c.evE[b] > tp.tolE * e0) ? 1 : 0;
-    if (rF < 1) rF = 1;
-    s_rF = rF;
     c.scratch[0] = s_kp;
-    c.scratch[1] = rF;
   }
   __syncthreads();
-  const int kp = s_kp, rF = s_rF;
+  const int kp = s_kp;
   const double sc = s_scale;
   // W[(s1 nu s2),(t1 kk t2)] = scale sum_j G_j[(s1 s2),(t1 t2)] V[(kk j), nu]
   const int rows = 4 * kp, cols = 4 * k1;
@@ -363,25 +398,7 @@ __global__ __launch_bounds__(GT) void k_q2_select_a(Ctx2<T>* ctxs, int splitsC, 
     }
     c.W[e] = mk<T>((T)(sc * acc.re), (T)(sc * acc.im));
   }
-  // L_F = P D^(1/2), PD = P D^(-1/2) on the r_F leading eigenvectors of E
-  const int nE = 2 * cm;
-  for (int e = threadIdx.x; e < nE * rF; e += blockDim.x) {
-    const int row = e / rF, b = e % rF;
-    const cpx<double> p = ld(c.vecE, (long long)row * nE + b);
-    const double dv = c.evE[b];
-    const double sq = sqrt(dv);
-    c.LF[e] = mk<T>((T)(p.re * sq), (T)(p.im * sq));
-    st(c.PD, e, mk(p.re / sq, p.im / sq));
-  }
-  __syncthreads();
   if (threadIdx.x == 0) {
-    {  // th[(l t1 k1),(t2 b)] = sum_m B_i[(l t1 k1), m] L_F[(m t2), b]
-      GemmDesc& d = *c.dTh;
-      clear_desc(d);
-      d.A = c.Bi; d.B = c.LF; d.C = c.th;
-      d.M = cl * 2 * k1; d.K = cm; d.N = 2 * rF;
-      d.lda = cm; d.ldb = 2 * rF; d.ldc = 2 * rF;
-    }
     {  // th2[l] = W th[l]
       GemmDesc& d = *c.dTh2;
       clear_desc(d);
@@ -653,14 +670,17 @@ template <typename T> void launch_q1_gamma(Ctx1<T>* d, int n, hipStream_t s) {
 template <typename T> void launch_q1_select(Ctx1<T>* d, int n, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q1_select<T>, dim3(n), dim3(GT), 0, s, d, tp);
 }
-template <typename T> void launch_q2_prepare(Ctx2<T>* d, int n, int splitsH, int splitsE, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q2_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsH, splitsE);
+template <typename T> void launch_q2_prepare(Ctx2<T>* d, int n, int splitsE, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q2_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsE);
+}
+template <typename T> void launch_q2_select_e(Ctx2<T>* d, int n, int splitsH, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q2_select_e<T>, dim3(n), dim3(GT), 0, s, d, splitsH, tp);
 }
 template <typename T> void launch_q2_gamma(Ctx2<T>* d, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_gamma<T>, dim3(n), dim3(GT), 0, s, d);
 }
-template <typename T> void launch_q2_select_a(Ctx2<T>* d, int n, int splitsC, TruncParams tp, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q2_select_a<T>, dim3(n), dim3(GT), 0, s, d, splitsC, tp);
+template <typename T> void launch_q2_select_g(Ctx2<T>* d, int n, int splitsC, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q2_select_g<T>, dim3(n), dim3(GT), 0, s, d, splitsC, tp);
 }
 template <typename T> void launch_q2_select_b(Ctx2<T>* d, int n, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_select_b<T>, dim3(n), dim3(GT), 0, s, d, tp);
@@ -693,9 +713,10 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_q1_prepare<T>(Ctx1<T>*, int, int, hipStream_t);                        \
   template void launch_q1_gamma<T>(Ctx1<T>*, int, hipStream_t);                               \
   template void launch_q1_select<T>(Ctx1<T>*, int, TruncParams, hipStream_t);                 \
-  template void launch_q2_prepare<T>(Ctx2<T>*, int, int, int, hipStream_t);                   \
+  template void launch_q2_prepare<T>(Ctx2<T>*, int, int, hipStream_t);                        \
+  template void launch_q2_select_e<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_gamma<T>(Ctx2<T>*, int, hipStream_t);                               \
-  template void launch_q2_select_a<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
+  template void launch_q2_select_g<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_select_b<T>(Ctx2<T>*, int, TruncParams, hipStream_t);              \
   template void launch_transfer_init<T>(CtxT<T>*, int, hipStream_t);                          \
   template void launch_transfer_prep<T>(CtxT<T>*, int, int, hipStream_t);                     \
