@@ -1,16 +1,27 @@
 """Benchmark: MPDO gate-layers/s on the n=16, chi=64, kappa=8 noisy ansatz.
 
 One step = one pass of the whole simulation over one batch of synthetic
-input: the depth-10 noisy RY/CZ ansatz (2 RY sublayers + 2 CZ sublayers per
-layer, a synthetic QPT channel after every gate) from |0...0>, followed by
-the GHZ fidelity and all <Z_i Z_{i+1}>.  gate-layers/s = instances x layers
-per second of wall time, inputs resident on the GPU.
+input: the depth-10 noisy RY/CZ ansatz (per layer two RY sublayers and two CZ
+sublayers, the synthetic process-tomography channel after every gate) from
+|0...0>, followed by the GHZ-fidelity terms and every <Z_i Z_i+1>.
 
-Prints one JSON line (see the design doc for the fields).
+  batched (default): B parameter points advanced together by one
+      mpdo_batch_run call per step;
+  plain: one instance through per-gate C-ABI calls.
+
+gate-layers/s = instances x layers / wall time of the timed steps, with the
+inputs already resident on the GPU.  During the timed steps the library's
+profiler brackets every compute launch with HIP events on its stream and
+accumulates the launches' algorithmic work; the kernel class with the largest
+summed time is reported as the roofline kernel.  The CPU oracle (the plain
+NumPy/LAPACK MPDO) is timed on a bounded sample of the same circuit.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +33,8 @@ if ROOT not in sys.path:
 
 N_QUBITS, DEPTH, CHI, KAPPA = 16, 10, 64, 8
 SVD_CUT, KAP_CUT = 1e-10, 1e-14
+# MI355X published peaks
+PEAK = {"f64_mfma": 78.6, "f32_mfma": 157.3, "f64_valu": 78.6, "hbm": 8000.0}
 
 
 def parse():
@@ -34,8 +47,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-layers", type=int, default=5)
     ap.add_argument("--mode", choices=["batched", "plain"], default="batched")
-    ap.add_argument("--batch", type=int, default=32, help="parameter points per step (batched mode)")
-    ap.add_argument("--no-graph", action="store_true", help="batched mode without HIP graph capture")
+    ap.add_argument("--batch", type=int, default=64, help="parameter points per step (batched mode)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each batched step into one HIP graph (the roofline then comes from one "
+                         "extra profiled step outside the timed region)")
     return ap.parse_args()
 
 
@@ -49,24 +64,34 @@ def gpu_step(M, W, prog, chans, prec):
     return f, zz
 
 
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d.get("num_threads", 0) for d in threadpool_info() if d.get("user_api") == "blas"]
+        if n:
+            return max(n)
+    except Exception:
+        pass
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+
 def cpu_baseline(W, layers):
-    """The oracle MPDO as it stands on the first `layers` layers of the same circuit."""
-    import numpy as np
+    """The oracle MPDO as it stands, on the first `layers` layers of the same circuit."""
     from oracle import channels as OC
     from oracle import mpdo as OM
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     prog = W.ghz_ansatz(N_QUBITS, layers, W.ansatz_params(N_QUBITS, DEPTH, 0))
     kr = [OC.kraus_from_chi(c)[0] for c in prog.chis]
     t0 = time.perf_counter()
     OM.run_program(prog, OM.MPDO(N_QUBITS, CHI, KAPPA, SVD_CUT, KAP_CUT), kr)
     dt = time.perf_counter() - t0
-    return {"value": layers / dt, "unit": "gate-layers/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {layers} of {DEPTH} layers of the same circuit, one instance, complex128 "
-                      f"NumPy/LAPACK ({dt:.1f} s)"}
+    return {"value": layers / dt, "unit": "gate-layers/s", "cores": blas_threads(), "kind": "oracle",
+            "sample": f"first {layers} of {DEPTH} layers of the same circuit (parameter point 0), one instance, "
+                      f"complex128 NumPy/LAPACK, {dt:.1f} s; the early layers have smaller bonds, so this "
+                      f"overstates the CPU rate on the full circuit"}
 
 
-def observables(W, n):
-    """GHZ-fidelity terms and the <Z_i Z_i+1> as product operators."""
+def observables(n):
+    """<Z_i Z_i+1> and the GHZ-fidelity terms as product operators."""
     import numpy as np
     ops = []
     for i in range(n - 1):
@@ -76,6 +101,55 @@ def observables(W, n):
     for m in (np.diag([1.0, 0.0]), np.diag([0.0, 1.0]), np.array([[0.0, 1.0], [0.0, 0.0]])):
         ops.append(np.stack([m.astype(np.complex128)] * n))
     return np.stack(ops)
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2508_07610_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, launches_per_step):
+    """HBM bytes per launch from the committed PMC summary of this kernel, if it
+    was taken from the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel)
+    if not e or e.get("sources") != kernel_sources_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def roofline(M, prec_c128, steps):
+    classes = {}
+    for c, name in M.PROF_NAMES.items():
+        classes[c] = M.profile_read(c)
+    dom = max(classes, key=lambda c: classes[c]["ms"])
+    r = classes[dom]
+    if dom == M.PROF_GEMM_F64:
+        bound, peak = "mfma", PEAK["f64_mfma"]
+    elif dom == M.PROF_GEMM_F32:
+        bound, peak = "mfma", PEAK["f32_mfma"]
+    else:
+        bound, peak = "alu", PEAK["f64_valu"]
+    achieved = r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["ms"] > 0 else 0.0
+    out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+           "traffic": traffic_for(M.PROF_NAMES[dom], r["launches"] / max(1, steps)),
+           "kernel": M.PROF_NAMES[dom], "launches": r["launches"], "avg_launch_ms": r["ms"] / max(1, r["launches"]),
+           "flops_per_launch": r["flops"] / max(1, r["launches"]),
+           "algorithmic_bytes_per_launch": r["bytes"] / max(1, r["launches"])}
+    share = {M.PROF_NAMES[c]: {"ms": v["ms"], "launches": v["launches"],
+                               "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0}
+             for c, v in classes.items()}
+    return out, share
 
 
 def main():
@@ -94,46 +168,58 @@ def main():
     if a.mode == "plain":
         ninst = 1
 
-        def step():
+        def step(graph=False):
             return gpu_step(M, W, prog, chans, prec)
     else:
         ninst = a.batch
         P = np.stack([W.ansatz_params(N_QUBITS, DEPTH, t) for t in range(ninst)])
         progs = [W.ghz_ansatz(N_QUBITS, a.depth, P[b]) for b in range(ninst)]
         pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
-        obs = observables(W, N_QUBITS)
+        obs = observables(N_QUBITS)
         nobs = obs.shape[0]
 
-        def step():
+        def step(graph=a.graph):
             r = M.batch_run(progs, pdev, chans, [obs] * ninst, chi_max=CHI, kappa_max=KAPPA, max_kraus=16,
-                            svd_cutoff=SVD_CUT, kappa_cutoff=KAP_CUT, prec=prec, use_graph=not a.no_graph)
+                            svd_cutoff=SVD_CUT, kappa_cutoff=KAP_CUT, prec=prec, use_graph=graph)
             r = r.view(ninst, nobs)
             f = 0.5 * (r[0, -3] + r[0, -2] + 2 * r[0, -1]).real.item()
             return f, r[0, : N_QUBITS - 1].real.cpu().tolist()
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
+    profiled_timed = not (a.mode == "batched" and a.graph)
+    if profiled_timed:
+        M.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(a.steps):
         f, zz = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if not profiled_timed:
+        M.profile_enable(True)
+        step(graph=False)
+        torch.cuda.synchronize()
+    roof, share = roofline(M, prec == M.C128, a.steps if profiled_timed else 1)
+    M.profile_enable(False)
     ms = 1e3 * dt / a.steps
     value = ninst * a.depth * a.steps / dt
     if a.mode == "plain":
         wl = (f"plain MPDO, noisy RY/CZ ansatz n={N_QUBITS} depth={a.depth} chi={CHI} kappa={KAPPA} "
-              f"svd_cutoff={SVD_CUT}, per-gate ABI calls, one instance")
+              f"svd_cutoff={SVD_CUT}, per-gate C-ABI calls, one instance")
     else:
         wl = (f"batched MPDO, {ninst} parameter points of the noisy RY/CZ ansatz n={N_QUBITS} depth={a.depth} "
               f"chi={CHI} kappa={KAPPA} svd_cutoff={SVD_CUT}, one mpdo_batch_run per step"
-              + ("" if a.no_graph else " captured in one HIP graph"))
+              + (" captured in one HIP graph" if a.graph else ""))
     out = {
         "metric": "MPDO gate-layers/s (n=16,chi=64,kappa=8) plain vs batched; surrogate time-to-fidelity",
         "value": value, "unit": "gate-layers/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c128" if prec == M.C128 else "c64+f64", "data": "synthetic",
-        "config": {"workload": wl, "instances": ninst, "ghz_fidelity": f, "zz0": zz[0]},
-        "roofline": None,
+        "config": {"workload": wl, "instances": ninst, "mode": a.mode, "ghz_fidelity_instance0": f,
+                   "zz01_instance0": zz[0], "roofline_from": "timed steps" if profiled_timed
+                   else "one extra profiled step (graph launches are not profiled)"},
+        "roofline": roof,
+        "kernel_time_ms": share,
         "cpu_baseline": None if a.no_cpu else cpu_baseline(W, a.cpu_layers),
     }
     print(json.dumps(out))

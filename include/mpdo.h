@@ -209,6 +209,35 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
                            const mpdo_chan_t* chans, int32_t nchans,
                            double* out_dev, int32_t use_graph, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Kernel profiling (process-wide, not thread-safe).  While enabled, every
+ * launch of the library's compute kernels on a stream that is not being
+ * captured into a graph is bracketed by two HIP events recorded on that
+ * stream, and the launch's algorithmic work, computed on the device from the
+ * shapes its descriptors hold when it runs, is added to per-class counters:
+ *   GEMM classes: 8 M N K flops per complex product; bytes of reading op(A)
+ *     and op(B) and writing C once;
+ *   eigensolver classes: 16/3 n^3 + 8 n^2 k flops (Householder
+ *     tridiagonalisation, back-transformation of k vectors); bytes of reading
+ *     the matrix and writing k vectors.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  MPDO_PROF_GEMM_F64 = 0,   /* complex GEMMs on FP64 MFMA                     */
+  MPDO_PROF_GEMM_F32 = 1,   /* complex GEMMs on FP32 MFMA (mixed precision)   */
+  MPDO_PROF_EIG_REG = 2,    /* eigensolver, n <= 128 (register-resident)      */
+  MPDO_PROF_EIG_GLOBAL = 3, /* eigensolver, 128 < n <= 512                    */
+  MPDO_PROF_NCLASS = 4
+} mpdo_prof_class;
+
+/* Reset the counters (synchronises the device) and switch profiling on
+ * (on != 0) or off. */
+mpdo_status mpdo_profile_enable(int32_t on);
+
+/* Totals of one class since the last reset: launches, summed event time in
+ * milliseconds, algorithmic flops and bytes (any pointer may be NULL).
+ * Synchronises the device.  EINVAL for an unknown class. */
+mpdo_status mpdo_profile_read(int32_t cls, int32_t* launches, double* ms, double* flops, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@
 #include "engine.h"
 #include "kernels.h"
 #include "ops.h"
+#include "profile.h"
 
 using namespace mpdo;
 
@@ -556,6 +557,25 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
   const Config c = make_config(cfg);
   if (cfg->prec == MPDO_C128) batch_exec<double>(c, nq, layers, oinst, oops, out_dev, use_graph != 0, st);
   else batch_exec<float>(c, nq, layers, oinst, oops, out_dev, use_graph != 0, st);
+  return MPDO_OK;
+  GUARD_END
+}
+
+}  // extern "C"
+
+extern "C" {
+
+mpdo_status mpdo_profile_enable(int32_t on) {
+  GUARD_BEGIN
+  prof_reset(on != 0);
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_profile_read(int32_t cls, int32_t* launches, double* ms, double* flops, double* bytes) {
+  if (cls < 0 || cls >= PC_NCLASS) return fail(MPDO_EINVAL, "unknown profile class");
+  GUARD_BEGIN
+  prof_read(cls, launches, ms, flops, bytes);
   return MPDO_OK;
   GUARD_END
 }

@@ -26,6 +26,7 @@
 // weight comes from Tr(A) minus the kept eigenvalues.
 #include "common.h"
 #include "kernels.h"
+#include "profile.h"
 
 namespace mpdo {
 
@@ -773,8 +774,14 @@ __global__ __launch_bounds__(NT) void k_heev_global(const EigDesc* __restrict__ 
 
 void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hipStream_t s) {
   if (nitems <= 0) return;
+  int tok = prof_begin(PC_EIG_REG, s);
   hipLaunchKernelGGL(k_heev_reg, dim3(nitems), dim3(NTR), 0, s, d_descs, d_status);
-  if (maxn > RN) hipLaunchKernelGGL(k_heev_global, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
+  prof_end_eig(tok, PC_EIG_REG, d_descs, nitems, 1, RN, s);
+  if (maxn > RN) {
+    tok = prof_begin(PC_EIG_GLOBAL, s);
+    hipLaunchKernelGGL(k_heev_global, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
+    prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, RN + 1, 512, s);
+  }
 }
 
 }  // namespace mpdo

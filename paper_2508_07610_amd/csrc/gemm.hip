@@ -9,6 +9,7 @@
 // 32 x 32 quadrant made of 2 x 2 blocks of the 16x16x4 MFMA.
 #include "common.h"
 #include "kernels.h"
+#include "profile.h"
 
 namespace mpdo {
 
@@ -222,8 +223,11 @@ void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplit
   const long long blocks = (long long)nitems * maxBatch * maxSplits * maxTiles;
   if (blocks <= 0) return;
   const long long grid = (blocks + NXCD - 1) / NXCD * NXCD;
+  const int cls = sizeof(Tc) == 8 ? PC_GEMM_F64 : PC_GEMM_F32;
+  const int tok = prof_begin(cls, s);
   hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs, maxBatch,
                      maxSplits, maxTiles, blocks);
+  prof_end_gemm(tok, cls, d_descs, nitems, (int)sizeof(cpx<Tin>), (int)sizeof(cpx<Tout>), s);
 }
 
 void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int nitems, int maxCount,

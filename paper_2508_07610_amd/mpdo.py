@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
         "mpdo_bond_weights": [vp, i32, pd, i32, pi],
         "mpdo_batch_run": [ctypes.POINTER(mpdo_config), ctypes.POINTER(mpdo_program), i32, vp, i32, pd, i32,
                            ctypes.POINTER(vp), i32, vp, i32, vp],
+        "mpdo_profile_enable": [i32],
+        "mpdo_profile_read": [i32, pi, pd, pd, pd],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -316,6 +318,24 @@ def batch_run(programs, params, channels: Sequence[Channel], observables, chi_ma
     check(lib().mpdo_batch_run(ctypes.byref(cfg), progs, ninst, pptr, pstride, _dptr(fbuf), len(fixed), chans,
                                len(channels), out.data_ptr(), 1 if use_graph else 0, stream_handle(stream)))
     return out[:total]
+
+
+PROF_GEMM_F64, PROF_GEMM_F32, PROF_EIG_REG, PROF_EIG_GLOBAL = range(4)
+PROF_NAMES = {PROF_GEMM_F64: "k_gemm (FP64 MFMA)", PROF_GEMM_F32: "k_gemm (FP32 MFMA)",
+              PROF_EIG_REG: "k_heev_reg", PROF_EIG_GLOBAL: "k_heev_global"}
+
+
+def profile_enable(on: bool = True) -> None:
+    """Reset the kernel profile counters and switch profiling on or off."""
+    check(lib().mpdo_profile_enable(1 if on else 0))
+
+
+def profile_read(cls: int) -> dict:
+    """Launches, summed HIP-event time (ms), algorithmic flops and bytes of one class."""
+    n = ctypes.c_int32()
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    check(lib().mpdo_profile_read(cls, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)))
+    return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
 
 
 def run_program(prog, state: MPDO, channels: Sequence[Channel]) -> MPDO:

@@ -83,3 +83,9 @@ def test_test_entry_points_validate_sizes():
     # A too small for op(A) = N with M = 4 rows
     assert L.mpdo_test_gemm(0, 0, 0, 4, 2, 2, M._dptr(a), 2, 2, M._dptr(a), 2, 2, None, 1, 1, 1.0,
                             M._dptr(a)) == M.EINVAL
+
+
+def test_profile_read_rejects_unknown_class():
+    L = M.lib()
+    assert L.mpdo_profile_read(-1, None, None, None, None) == M.EINVAL
+    assert L.mpdo_profile_read(4, None, None, None, None) == M.EINVAL

@@ -1,6 +1,7 @@
 """Kernel unit tests on the GPU: the MFMA complex GEMM (every operand mode,
-ragged shapes, split-K, weights, all precisions) and the Jacobi eigensolver,
-each against NumPy."""
+ragged shapes, split-K, weights, all precisions) and the Hermitian
+eigensolver (register-resident and global-memory variants), each against
+NumPy; and the profiler's launch and work accounting."""
 import numpy as np
 import pytest
 
@@ -131,3 +132,24 @@ def test_eigh_diagonal_and_tiny():
     assert abs(tr - d.sum()) < 1e-15
     ev, V, tr = M.test_eigh(np.array([[2.5 + 0j]]))
     assert abs(ev[0] - 2.5) < 1e-15 and abs(abs(V[0, 0]) - 1) < 1e-15
+
+
+def test_profiler_counts_gemm_and_eig_work():
+    require_gpu()
+    rng = np.random.default_rng(5)
+    A, B = _rand((70, 33), rng), _rand((33, 90), rng)
+    M.profile_enable(True)
+    M.test_gemm(0, 0, 0, 70, 90, 33, A, B)
+    g = M.profile_read(M.PROF_GEMM_F64)
+    X = _rand((100, 100), rng)
+    M.test_eigh(X @ X.conj().T, 10)
+    e = M.profile_read(M.PROF_EIG_REG)
+    Y = _rand((200, 200), rng)
+    M.test_eigh(Y @ Y.conj().T, 20)
+    e2 = M.profile_read(M.PROF_EIG_GLOBAL)
+    M.profile_enable(False)
+    assert g["launches"] == 1 and g["ms"] > 0
+    assert g["flops"] == 8.0 * 70 * 90 * 33
+    assert g["bytes"] == 16.0 * (70 * 33 + 33 * 90 + 70 * 90)
+    assert e["launches"] == 1 and abs(e["flops"] - (16.0 / 3.0 * 100 ** 3 + 8.0 * 100 ** 2 * 10)) < 1.0
+    assert e2["launches"] == 1 and abs(e2["flops"] - (16.0 / 3.0 * 200 ** 3 + 8.0 * 200 ** 2 * 20)) < 1.0
