@@ -132,7 +132,11 @@ template <typename T> class Engine {
   const double* laml2(int b, int i) const { return i == 0 ? one_.as<double>() : lam2_ptr(b, i - 1); }
   double* disc_ptr(int b, int i) const { return disc_.as<double>() + soff_[b] + i; }
 
-  void run_1q(const std::vector<const GateOp*>& ops, Upload& up);
+  // force: truncate the inner index even for unitary ops; tpo overrides the
+  // truncation parameters of the configuration.
+  void run_1q(const std::vector<const GateOp*>& ops, Upload& up, bool force = false,
+              const TruncParams* tpo = nullptr);
+  void sweep_step(const std::vector<int>& inst, int pass, int site, const TruncParams& tp);
   void run_2q(const std::vector<const GateOp*>& ops, Upload& up);
   int splits_for(long long K) const;
   // descriptor space of `bytes` (host image h, device address dv); false in a dry pass

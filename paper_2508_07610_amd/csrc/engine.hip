@@ -190,7 +190,8 @@ template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& op
     run_2q(std::vector<const GateOp*>(two.begin() + a, two.begin() + std::min(two.size(), a + chunk2)), up);
 }
 
-template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up) {
+template <typename T>
+void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up, bool force, const TruncParams* tpo) {
   const int n = (int)ops.size();
   if (n == 0) return;
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
@@ -233,6 +234,7 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
     }
     c.kraus = g.ch ? g.ch->kraus.as<double>() : nullptr;
     c.m = g.ch ? g.ch->m : 1;
+    c.force = force ? 1 : 0;
     const int b = g.inst, i = g.site;
     const int p = par_[soff_[b] + i];
     c.Bold = site(b, i, p);
@@ -262,6 +264,7 @@ template <typename T> void Engine<T>::run_1q(const std::vector<const GateOp*>& o
   commit(up, h, dv, u.off);
   Ctx1<T>* dctx = reinterpret_cast<Ctx1<T>*>(dv + uCtx);
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
+  if (tpo) tp = *tpo;
   launch_q1_prepare<T>(dctx, n, splitsH, st_);
   launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH, gemm_tiles(2 * kx, 2 * kx),
                                  st_);
@@ -573,8 +576,134 @@ template <typename T> std::vector<double> Engine<T>::bond_weights(int b, int bon
   return v;
 }
 
-template <typename T> double Engine<T>::truncate_sweep(int, int, int, double) {
-  throw Error{6, "mpdo_truncate is not available yet"};
+// One sweep step (pass 0: site -> site + 1, pass 1: site -> site - 1) on the
+// instances `inst`.
+template <typename T>
+void Engine<T>::sweep_step(const std::vector<int>& inst, int pass, int si, const TruncParams& tp) {
+  const int n = (int)inst.size();
+  if (n == 0) return;
+  const int kx = cfg_.kap_max, cx = cfg_.chi_max;
+  const int splits = splits_for((long long)2 * kx * cx);
+  Layout w;
+  const size_t oG = w.add((size_t)cx * cx * 16);
+  const size_t oGp = w.add((size_t)splits * cx * cx * 16);
+  const size_t oEv = w.add((size_t)(cx + 1) * 8);
+  const size_t oVec = w.add((size_t)cx * cx * 16);
+  const size_t oWk = w.add((size_t)eig_work_doubles(cx) * 8);
+  const size_t oP1 = w.add((size_t)cx * cx * sizeof(cpx<T>));
+  const size_t oP2 = w.add((size_t)cx * cx * sizeof(cpx<T>));
+  const size_t per = w.off;
+  Layout u;
+  const size_t uCtx = u.add(sizeof(CtxS<T>) * n);
+  const size_t uG = u.add(sizeof(GemmDesc) * n);
+  const size_t uE = u.add(sizeof(EigDesc) * n);
+  const size_t uA = u.add(sizeof(GemmDesc) * 2 * n);
+  const size_t uOut = u.add(sizeof(double*) * n);
+  Upload up;
+  char *h = nullptr, *dv = nullptr;
+  if (!reserve(up, u.off, per * n, n, h, dv)) return;
+  char* wk = reinterpret_cast<char*>(work_.p);
+  const int nb = pass == 0 ? si + 1 : si - 1;
+  for (int it = 0; it < n; ++it) {
+    const int b = inst[it];
+    char* base = wk + per * it;
+    CtxS<T>& c = at<CtxS<T>>(h, uCtx)[it];
+    const int pi = par_[soff_[b] + si], pn = par_[soff_[b] + nb];
+    c.pass = pass;
+    c.A = site(b, si, pi);
+    c.Anew = site(b, si, 1 - pi);
+    c.Bn = site(b, nb, pn);
+    c.Bnnew = site(b, nb, 1 - pn);
+    c.chil = chi_ptr(b, si);
+    c.chir = chi_ptr(b, si + 1);
+    c.kap = kap_ptr(b, si);
+    c.chib = pass == 0 ? chi_ptr(b, si + 1) : chi_ptr(b, si);
+    c.chio = pass == 0 ? chi_ptr(b, si + 2) : chi_ptr(b, si - 1);
+    c.kapn = kap_ptr(b, nb);
+    c.lam = pass == 1 ? lam_ptr(b, si - 1) : nullptr;
+    c.lam2 = pass == 1 ? lam2_ptr(b, si - 1) : nullptr;
+    c.disc = disc_ptr(b, si);
+    c.ev = at<double>(base, oEv);
+    c.evec = at<double>(base, oVec);
+    c.P1 = at<cpx<T>>(base, oP1);
+    c.P2 = at<cpx<T>>(base, oP2);
+    c.dG = reinterpret_cast<GemmDesc*>(dv + uG) + it;
+    c.dE = reinterpret_cast<EigDesc*>(dv + uE) + it;
+    c.dA = reinterpret_cast<GemmDesc*>(dv + uA) + 2 * it;
+    c.dB = c.dA + 1;
+    GemmDesc& g = at<GemmDesc>(h, uG)[it];
+    g.C = at<double>(base, oGp);
+    g.sSplit = (long long)cx * cx;
+    EigDesc& e = at<EigDesc>(h, uE)[it];
+    e.a = at<double>(base, oG);
+    e.work = at<double>(base, oWk);
+    e.kvec = cx;
+    at<double*>(h, uOut)[it] = at<double>(base, oG);
+  }
+  commit(up, h, dv, u.off);
+  CtxS<T>* dctx = reinterpret_cast<CtxS<T>*>(dv + uCtx);
+  launch_sw_prepare<T>(dctx, n, splits, st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uG), n, 1, splits, gemm_tiles(cx, cx), st_);
+  launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uG), reinterpret_cast<double**>(dv + uOut), n, cx * cx,
+                       st_);
+  launch_eigh(reinterpret_cast<EigDesc*>(dv + uE), n, cx, sweeps_.as<int>(), st_);
+  launch_sw_select<T>(dctx, n, tp, st_);
+  const int tiles = std::max(gemm_tiles(2 * kx * cx, cx), gemm_tiles(cx, 2 * kx * cx));
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uA), 2 * n, 1, 1, tiles, st_);
+  hip_check(hipGetLastError(), "launch (truncation sweep)");
+  for (int b : inst) {
+    par_[soff_[b] + si] ^= 1;
+    par_[soff_[b] + nb] ^= 1;
+  }
+}
+
+// The truncation sweep of Sec. II.D on instance b: orthonormalise from left
+// to right, SVD from right to left with the bond rule (chi_max, cut), then
+// truncate every inner index to kap_max.  Returns the discarded weight.
+template <typename T> double Engine<T>::truncate_sweep(int b, int chi_max, int kap_max, double cut) {
+  std::vector<int> b0, b1;
+  double d0 = 0, d1 = 0;
+  dims(b, b0, b1, d0);
+  const int n = nq_[b];
+  const std::vector<int> one{b};
+  TruncParams tp{chi_max, kap_max, cut, cfg_.kap_cut, cfg_.tolE};
+  for (int i = 0; i + 1 < n; ++i) sweep_step(one, 0, i, tp);
+  for (int i = n - 1; i >= 1; --i) sweep_step(one, 1, i, tp);
+  {  // normalise the first site
+    Upload up;
+    char *h = nullptr, *dv = nullptr;
+    if (reserve(up, sizeof(CtxS<T>), 0, 1, h, dv)) {
+      CtxS<T>& c = *reinterpret_cast<CtxS<T>*>(h);
+      c.Anew = site(b, 0, par_[soff_[b]]);
+      c.chil = chi_ptr(b, 0);
+      c.chir = chi_ptr(b, 1);
+      c.kap = kap_ptr(b, 0);
+      commit(up, h, dv, sizeof(CtxS<T>));
+      launch_sw_normalize<T>(reinterpret_cast<CtxS<T>*>(dv), 1, st_);
+      hip_check(hipGetLastError(), "launch (normalise)");
+    }
+  }
+  {  // inner truncation of every site (identity operators, forced)
+    std::vector<GateOp> ops(n);
+    std::vector<const GateOp*> ptrs;
+    for (int i = 0; i < n; ++i) {
+      ops[i].inst = b;
+      ops[i].site = i;
+      ops[i].q = 1;
+      ops[i].kind = 0;
+      ops[i].pidx = -1;
+      ops[i].scale = 1.0;
+      ops[i].params = nullptr;
+      ops[i].ufix = nullptr;
+      ops[i].has_u = false;
+      ops[i].ch = nullptr;
+      ptrs.push_back(&ops[i]);
+    }
+    Upload up;
+    run_1q(ptrs, up, true, &tp);
+  }
+  dims(b, b0, b1, d1);
+  return d1 - d0;
 }
 
 template class Engine<double>;

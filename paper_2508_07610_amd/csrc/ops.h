@@ -20,7 +20,8 @@ struct GateSrc {
 template <typename T> struct Ctx1 {
   GateSrc g;
   const double* kraus;    // m x 2 x 2 complex (device) or null (m = 1)
-  int m, pad;
+  int m;
+  int force;              // truncate the inner index even when m = 1
   const cpx<T>* Bold;
   cpx<T>* Bnew;
   const double* laml2;    // squared weights of the left bond
@@ -86,6 +87,38 @@ template <typename T> struct Ctx2 {
   GemmDesc* dOut;         // 2: B_i, B_{i+1}
 };
 
+// One step of the truncation sweep (Sec. II.D) on one instance.
+//  pass 0, left to right: A = T_i as (l s k) x r; A^H A = V D V^H on the
+//    eigenvalues above the numerical floor; T_i <- A V D^(-1/2) (orthonormal
+//    columns), T_{i+1} <- D^(1/2) V^H T_{i+1}.
+//  pass 1, right to left: A = T_i as l x (s k r); A A^H = U S^2 U^H, rank r
+//    by the truncation rule; T_i <- S^(-1) U_r^H A (orthonormal rows),
+//    T_{i-1} <- T_{i-1} U_r S_r, bond weights S_r / sqrt(kept weight).
+template <typename T> struct CtxS {
+  int pass, pad;
+  const cpx<T>* A;        // T_i
+  cpx<T>* Anew;
+  const cpx<T>* Bn;       // the neighbour: T_{i+1} (pass 0) or T_{i-1} (pass 1)
+  cpx<T>* Bnnew;
+  const int* chil;        // bonds and inner dimension of site i
+  const int* chir;
+  const int* kap;
+  int* chib;              // the bond shared with the neighbour (rewritten)
+  const int* chio;        // the neighbour's other bond
+  const int* kapn;        // the neighbour's inner dimension
+  double* lam;            // weights of the shared bond (pass 1)
+  double* lam2;
+  double* disc;
+  double* ev;
+  double* evec;
+  cpx<T>* P1;             // pass 0: V D^(-1/2);  pass 1: U_r S_r^(-1)
+  cpx<T>* P2;             // pass 0: D^(1/2) V^H; pass 1: U_r S_r
+  GemmDesc* dG;
+  EigDesc* dE;
+  GemmDesc* dA;
+  GemmDesc* dB;
+};
+
 // Transfer-matrix item: E'[r, r'] = sum E[l, l'] B[l,s,k,r] O[s',s] conj(B[l',s',k,r']).
 template <typename T> struct CtxT {
   const double* ops;      // n x 2 x 2 complex of this item's product operator
@@ -118,6 +151,11 @@ template <typename T> void launch_q2_select_e(Ctx2<T>* d_ctx, int n, int splitsH
 template <typename T> void launch_q2_gamma(Ctx2<T>* d_ctx, int n, hipStream_t s);
 template <typename T> void launch_q2_select_g(Ctx2<T>* d_ctx, int n, int splitsC, TruncParams tp, hipStream_t s);
 template <typename T> void launch_q2_select_b(Ctx2<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
+
+template <typename T> void launch_sw_prepare(CtxS<T>* d_ctx, int n, int splits, hipStream_t s);
+template <typename T> void launch_sw_select(CtxS<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
+// T_0 <- T_0 / ||T_0|| (Anew of each item is the instance's T_0)
+template <typename T> void launch_sw_normalize(CtxS<T>* d_ctx, int n, hipStream_t s);
 
 template <typename T> void launch_transfer_prep(CtxT<T>* d_ctx, int n, int maxElems, hipStream_t s);
 template <typename T> void launch_transfer_init(CtxT<T>* d_ctx, int n, hipStream_t s);

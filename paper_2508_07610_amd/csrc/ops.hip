@@ -116,7 +116,7 @@ __global__ __launch_bounds__(GT) void k_q1_prepare(Ctx1<T>* ctxs, int splitsH) {
   clear_desc(d);
   d.C = C;
   d.sSplit = sSplit;
-  if (c.m <= 1) { d.active = 0; return; }
+  if (c.m <= 1 && !c.force) { d.active = 0; return; }
   // H[a][a'] = sum_l lambda_l^2 sum_r conj(B[l][a][r]) B[l][a'][r],  a = (t, k)
   d.A = c.Bold; d.B = c.Bold;
   d.opA = OP_C; d.opB = OP_T;
@@ -135,7 +135,7 @@ template <typename T>
 __global__ __launch_bounds__(GT) void k_q1_gamma(Ctx1<T>* ctxs) {
   Ctx1<T>& c = ctxs[blockIdx.x];
   const int m = c.m;
-  if (m <= 1) {
+  if (m <= 1 && !c.force) {
     if (threadIdx.x == 0) c.dE->active = 0;
     return;
   }
@@ -168,8 +168,9 @@ __global__ __launch_bounds__(GT) void k_q1_select(Ctx1<T>* ctxs, TruncParams tp)
   Ctx1<T>& c = ctxs[blockIdx.x];
   const int m = c.m;
   const int k = *c.kap, cl = *c.chil, cr = *c.chir;
+  const bool trunc = m > 1 || c.force;
   if (threadIdx.x == 0) {
-    if (m <= 1) {
+    if (!trunc) {
       s_kp = k;
       s_scale = 1.0;
     } else {
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(GT) void k_q1_select(Ctx1<T>* ctxs, TruncParams tp)
     const int row = e / (2 * k), col = e % (2 * k);
     const int s = row / kp, nu = row % kp, t = col / k, kk = col % k;
     cpx<double> acc = mk(0.0, 0.0);
-    if (m <= 1) {
+    if (!trunc) {
       if (nu == kk) acc = ld(c.G, s * 2 + t);
     } else {
       for (int j = 0; j < m; ++j)
@@ -494,6 +495,135 @@ __global__ __launch_bounds__(GT) void k_q2_select_b(Ctx2<T>* ctxs, TruncParams t
 }
 
 // ============================================================================
+// truncation sweep (Sec. II.D)
+// ============================================================================
+template <typename T>
+__global__ __launch_bounds__(GT) void k_sw_prepare(CtxS<T>* ctxs, int splits) {
+  CtxS<T>& c = ctxs[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const int l = *c.chil, k = *c.kap, r = *c.chir;
+  GemmDesc& d = *c.dG;
+  void* C = d.C;
+  const long long ss = d.sSplit;
+  clear_desc(d);
+  d.C = C; d.sSplit = ss;
+  d.A = c.A; d.B = c.A;
+  d.splits = splits;
+  int n;
+  if (c.pass == 0) {  // A^H A over rows (l s k): r x r
+    n = r;
+    d.opA = OP_H; d.opB = OP_N;
+    d.M = d.N = r; d.K = l * 2 * k;
+    d.lda = d.ldb = r;
+  } else {            // A A^H over columns (s k r): l x l
+    n = l;
+    d.opA = OP_N; d.opB = OP_H;
+    d.M = d.N = l; d.K = 2 * k * r;
+    d.lda = d.ldb = 2 * k * r;
+  }
+  d.ldc = n;
+  EigDesc& e = *c.dE;  // a, work and kvec are set by the host (a = the reduced Gram)
+  e.lda = n; e.n = n; e.evals = c.ev; e.evecs = c.evec; e.trace = c.ev + n; e.active = 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(GT) void k_sw_select(CtxS<T>* ctxs, TruncParams tp) {
+  __shared__ int s_r;
+  __shared__ double s_kept;
+  CtxS<T>& c = ctxs[blockIdx.x];
+  const int l = *c.chil, k = *c.kap, r = *c.chir;
+  const int n = c.pass == 0 ? r : l;
+  if (threadIdx.x == 0) {
+    if (c.pass == 0) {
+      int rr = 0;
+      while (rr < n && c.ev[rr] > EIG_FLOOR * c.ev[0] && c.ev[0] > 0) ++rr;
+      s_r = rr < 1 ? 1 : rr;
+      s_kept = 1.0;
+    } else {
+      double kept, tot;
+      const int rr = select_rank(c.ev, min(n, tp.chi_max + 1), n, c.ev[n], tp.chi_max, tp.svd_cut, &kept, &tot);
+      s_r = rr;
+      s_kept = kept;
+      if (tot > 0) *c.disc += (tot - kept) / tot;
+    }
+  }
+  __syncthreads();
+  const int rr = s_r;
+  const double kept = s_kept;
+  // P1 (n x rr): V / sqrt(D);  P2: pass 0 (rr x n) sqrt(D) V^H, pass 1 (n x rr) U sqrt(S^2)
+  for (int e = threadIdx.x; e < n * rr; e += blockDim.x) {
+    const int a = e / rr, b = e % rr;
+    const cpx<double> v = ld(c.evec, (long long)a * n + b);
+    const double dv = c.ev[b] > 0 ? c.ev[b] : 0.0;
+    const double sq = sqrt(dv), is = sq > 0 ? 1.0 / sq : 0.0;
+    c.P1[e] = mk<T>((T)(v.re * is), (T)(v.im * is));
+    if (c.pass == 0) {
+      c.P2[(long long)b * n + a] = mk<T>((T)(v.re * sq), (T)(-v.im * sq));
+    } else {
+      c.P2[e] = mk<T>((T)(v.re * sq), (T)(v.im * sq));
+    }
+  }
+  if (c.pass == 1) {
+    for (int v = threadIdx.x; v < rr; v += blockDim.x) {
+      const double e = c.ev[v] > 0 ? c.ev[v] : 0.0;
+      c.lam[v] = sqrt(e / kept);
+      c.lam2[v] = e / kept;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int o = *c.chio, kn = *c.kapn;
+    GemmDesc& a = *c.dA;
+    GemmDesc& b = *c.dB;
+    clear_desc(a);
+    clear_desc(b);
+    if (c.pass == 0) {
+      // T_i <- A P1: (l s k) x r times r x rr
+      a.A = c.A; a.B = c.P1; a.C = c.Anew;
+      a.M = l * 2 * k; a.K = r; a.N = rr;
+      a.lda = r; a.ldb = rr; a.ldc = rr;
+      // T_{i+1} <- P2 T_{i+1}: rr x r times r x (s kn o)
+      b.A = c.P2; b.B = c.Bn; b.C = c.Bnnew;
+      b.M = rr; b.K = r; b.N = 2 * kn * o;
+      b.lda = r; b.ldb = 2 * kn * o; b.ldc = 2 * kn * o;
+    } else {
+      // T_i <- P1^H A: rr x l times l x (s k r)
+      a.A = c.P1; a.B = c.A; a.C = c.Anew;
+      a.opA = OP_H;
+      a.M = rr; a.K = l; a.N = 2 * k * r;
+      a.lda = rr; a.ldb = 2 * k * r; a.ldc = 2 * k * r;
+      // T_{i-1} <- T_{i-1} P2: (o s kn) x l times l x rr
+      b.A = c.Bn; b.B = c.P2; b.C = c.Bnnew;
+      b.M = o * 2 * kn; b.K = l; b.N = rr;
+      b.lda = l; b.ldb = rr; b.ldc = rr;
+    }
+    *c.chib = rr;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(GT) void k_sw_normalize(CtxS<T>* ctxs) {
+  __shared__ double red[GT / 64];
+  CtxS<T>& c = ctxs[blockIdx.x];
+  const long long cnt = (long long)(*c.chil) * 2 * (*c.kap) * (*c.chir);
+  double s = 0;
+  for (long long e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const cpx<T> v = c.Anew[e];
+    s += (double)v.re * v.re + (double)v.im * v.im;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double tot = 0;
+  for (int i = 0; i < GT / 64; ++i) tot += red[i];
+  const double sc = tot > 0 ? 1.0 / sqrt(tot) : 1.0;
+  for (long long e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const cpx<T> v = c.Anew[e];
+    c.Anew[e] = mk<T>((T)(v.re * sc), (T)(v.im * sc));
+  }
+}
+
+// ============================================================================
 // transfer matrices
 // ============================================================================
 template <typename T>
@@ -685,6 +815,15 @@ template <typename T> void launch_q2_select_g(Ctx2<T>* d, int n, int splitsC, Tr
 template <typename T> void launch_q2_select_b(Ctx2<T>* d, int n, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_select_b<T>, dim3(n), dim3(GT), 0, s, d, tp);
 }
+template <typename T> void launch_sw_prepare(CtxS<T>* d, int n, int splits, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_sw_prepare<T>, dim3(n), dim3(GT), 0, s, d, splits);
+}
+template <typename T> void launch_sw_select(CtxS<T>* d, int n, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_sw_select<T>, dim3(n), dim3(GT), 0, s, d, tp);
+}
+template <typename T> void launch_sw_normalize(CtxS<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_sw_normalize<T>, dim3(n), dim3(GT), 0, s, d);
+}
 template <typename T> void launch_transfer_init(CtxT<T>* d, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_transfer_init<T>, dim3(n), dim3(64), 0, s, d);
 }
@@ -718,6 +857,9 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_q2_gamma<T>(Ctx2<T>*, int, hipStream_t);                               \
   template void launch_q2_select_g<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_select_b<T>(Ctx2<T>*, int, TruncParams, hipStream_t);              \
+  template void launch_sw_prepare<T>(CtxS<T>*, int, int, hipStream_t);                        \
+  template void launch_sw_select<T>(CtxS<T>*, int, TruncParams, hipStream_t);                 \
+  template void launch_sw_normalize<T>(CtxS<T>*, int, hipStream_t);                           \
   template void launch_transfer_init<T>(CtxT<T>*, int, hipStream_t);                          \
   template void launch_transfer_prep<T>(CtxT<T>*, int, int, hipStream_t);                     \
   template void launch_transfer_finish<T>(CtxT<T>*, int, double*, hipStream_t);          \
