@@ -238,6 +238,43 @@ mpdo_status mpdo_profile_enable(int32_t on);
  * Synchronises the device.  EINVAL for an unknown class. */
 mpdo_status mpdo_profile_read(int32_t cls, int32_t* launches, double* ms, double* flops, double* bytes);
 
+/* ---------------------------------------------------------------------------
+ * Surrogate network: a multilayer perceptron trained on MPDO-generated
+ * (parameters, noise) -> observables data.  Widths d_0 .. d_L; hidden
+ * layers z_l = W_l h_{l-1} + b_l, h_l = GELU(z_l) = z Phi(z) (exact erf
+ * form); output y = W_L h_{L-1} + b_L; loss = mean over batch and outputs of
+ * (y - t)^2.  Operands of every matrix product (inputs, activations, weights,
+ * gradients with respect to z) are bfloat16 (round to nearest even), the
+ * products accumulate in FP32 on the matrix cores; biases, pre-activations,
+ * gradients, master weights and Adam moments are FP32.
+ * Parameters are packed as W_1 (d_1 x d_0, row-major), b_1, W_2, b_2, ...
+ * All x / t / y / gradient buffers are device pointers (FP32, row-major,
+ * one sample per row) and the work is ordered on the network's stream.
+ * ------------------------------------------------------------------------- */
+typedef struct mpdo_mlp_s* mpdo_mlp_t;
+
+/* widths: nlayers + 1 ints in [1, 8192]; max_batch in [1, 2^20] sizes the
+ * activation buffers.  Parameters start at zero. */
+mpdo_status mpdo_mlp_create(const int32_t* widths, int32_t nlayers, int32_t max_batch, void* hip_stream,
+                            mpdo_mlp_t* out);
+mpdo_status mpdo_mlp_destroy(mpdo_mlp_t h);
+mpdo_status mpdo_mlp_info(mpdo_mlp_t h, int64_t* nparams);
+/* host FP32 arrays of nparams; set also resets the Adam state. */
+mpdo_status mpdo_mlp_set_params(mpdo_mlp_t h, const float* host);
+mpdo_status mpdo_mlp_get_params(mpdo_mlp_t h, float* host);
+/* y_dev (batch x d_L) = network(x_dev (batch x d_0)). */
+mpdo_status mpdo_mlp_forward(mpdo_mlp_t h, const float* x_dev, int32_t batch, float* y_dev);
+/* Forward into y_dev, then back-propagate either the MSE loss against
+ * targets t_dev, or a given output cotangent gy_dev (exactly one of the two
+ * non-NULL).  Parameter gradients are kept for mpdo_mlp_adam and copied to
+ * grad_dev (nparams) if non-NULL; the input gradient goes to dx_dev
+ * (batch x d_0) if non-NULL; *loss (if non-NULL) receives the MSE (0 with
+ * gy_dev) and makes the call synchronous. */
+mpdo_status mpdo_mlp_backward(mpdo_mlp_t h, const float* x_dev, const float* t_dev, const float* gy_dev,
+                              int32_t batch, float* y_dev, float* grad_dev, float* dx_dev, float* loss);
+/* One Adam step (bias-corrected) with the gradients of the last backward. */
+mpdo_status mpdo_mlp_adam(mpdo_mlp_t h, float lr, float beta1, float beta2, float eps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,14 @@ mpdo_status fail(int st, const std::string& msg) {
   g_err = msg;
   return (mpdo_status)st;
 }
+}  // namespace
+
+int mpdo::set_last_error(int st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+namespace {
 
 struct AnyEngine {
   std::unique_ptr<Engine<double>> d;

@@ -15,6 +15,8 @@ struct Error {
 };
 
 void hip_check(hipError_t e, const char* what);
+// Records the message returned by mpdo_last_error() and passes the status through.
+int set_last_error(int status, const std::string& msg);
 
 // Device allocation owned by the runtime (freed on destruction).
 struct DevBuf {

@@ -1,0 +1,457 @@
+// Surrogate multilayer perceptron: forward, backward and Adam on the gfx950
+// matrix cores in bfloat16 with FP32 accumulation.
+//
+// Network (widths d_0 .. d_L): z_l = W_l h_{l-1} + b_l, h_l = GELU(z_l) for
+// hidden layers (exact erf form), y = z_L; loss = mean (y - t)^2.  Operands
+// of every matrix product (inputs, hidden activations, weights, gradients
+// with respect to z) are bfloat16, rounded to nearest-even from FP32; biases,
+// pre-activations, gradients and the Adam state are FP32, with FP32 master
+// weights.  Matrix products use v_mfma_f32_16x16x16_bf16: 64 x 64 tiles per
+// workgroup of four waves, each wave a 32 x 32 quadrant of 2 x 2 MFMA blocks,
+// operand tiles staged in LDS with the K index contiguous, and the bias /
+// activation / rounding epilogues fused into the product kernel.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpdo.h"
+#include "engine.h"
+
+namespace mpdo {
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int MT = 64, KT = 16, MTH = 256, KP = KT + 4;
+
+__device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+enum Epi : int {
+  EPI_STORE = 0,   // C = acc
+  EPI_HIDDEN = 1,  // z = acc + bias[col] -> Z (FP32), h = GELU(z) -> Hb (bf16)
+  EPI_OUT = 2,     // y = acc + bias[col] -> C
+  EPI_ACTGRAD = 3  // g = acc * GELU'(aux[row][col]) -> C (FP32) and Hb (bf16)
+};
+
+struct MlpGemm {
+  const uint16_t* A;
+  const uint16_t* B;
+  int M, N, K, lda, ldb, transA, transB;
+  float* C;
+  int ldc;
+  uint16_t* Hb;
+  const float* bias;
+  const float* aux;
+};
+
+// C[M x N] = op(A)[M x K] op(B)[K x N]: op(A)[i][k] = transA ? A[k lda + i] : A[i lda + k],
+// op(B)[k][j] = transB ? B[j ldb + k] : B[k ldb + j].
+template <int EPI>
+__global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[MT][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[MT][KP];  // [n][k]
+  const int tilesN = (g.N + MT - 1) / MT;
+  const int m0 = (blockIdx.x / tilesN) * MT, n0 = (blockIdx.x % tilesN) * MT;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1, li = lane & 15, lg = lane >> 4;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < g.K; k0 += KT) {
+#pragma unroll
+    for (int it = 0; it < (MT * KT) / MTH; ++it) {
+      const int idx = tid + it * MTH;
+      int mm, kk;
+      if (g.transA) { mm = idx % MT; kk = idx / MT; }
+      else { kk = idx % KT; mm = idx / KT; }
+      const int m = m0 + mm, k = k0 + kk;
+      uint16_t v = 0;
+      if (m < g.M && k < g.K) v = g.transA ? g.A[(long long)k * g.lda + m] : g.A[(long long)m * g.lda + k];
+      As[mm][kk] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < (MT * KT) / MTH; ++it) {
+      const int idx = tid + it * MTH;
+      int nn, kk;
+      if (g.transB) { kk = idx % KT; nn = idx / KT; }
+      else { nn = idx % MT; kk = idx / MT; }
+      const int n = n0 + nn, k = k0 + kk;
+      uint16_t v = 0;
+      if (n < g.N && k < g.K) v = g.transB ? g.B[(long long)n * g.ldb + k] : g.B[(long long)k * g.ldb + n];
+      Bs[nn][kk] = v;
+    }
+    __syncthreads();
+    s4 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const s4*>(&As[wm * 32 + i * 16 + li][4 * lg]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const s4*>(&Bs[wn * 32 + j * 16 + li][4 * lg]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 32 + i * 16 + 4 * lg + v;
+        const int col = n0 + wn * 32 + j * 16 + li;
+        if (row >= g.M || col >= g.N) continue;
+        const float x = acc[i][j][v];
+        const long long o = (long long)row * g.ldc + col;
+        if (EPI == EPI_STORE) {
+          g.C[o] = x;
+        } else if (EPI == EPI_HIDDEN) {
+          const float z = x + g.bias[col];
+          g.C[o] = z;
+          g.Hb[o] = f2bf(gelu(z));
+        } else if (EPI == EPI_OUT) {
+          g.C[o] = x + g.bias[col];
+        } else {
+          const float gz = x * gelu_grad(g.aux[o]);
+          g.C[o] = gz;
+          g.Hb[o] = f2bf(gz);
+        }
+      }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = f2bf(x[i]);
+}
+
+// g = 2 (y - t) / count; loss partials per block
+__global__ void k_out_grad(const float* __restrict__ y, const float* __restrict__ t, long long n, float inv,
+                           float* __restrict__ g, uint16_t* __restrict__ gb, float* __restrict__ part) {
+  __shared__ float red[256];
+  float s = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float d = y[i] - t[i];
+    s += d * d;
+    const float v = 2.0f * d * inv;
+    g[i] = v;
+    gb[i] = f2bf(v);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// copies a given output cotangent into the gradient buffers
+__global__ void k_set_grad(const float* __restrict__ gy, long long n, float* __restrict__ g,
+                           uint16_t* __restrict__ gb) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    g[i] = gy[i];
+    gb[i] = f2bf(gy[i]);
+  }
+}
+
+// db[j] = sum_b g[b][j]
+__global__ void k_colsum(const float* __restrict__ g, int rows, int cols, float* __restrict__ db) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0;
+  for (int r = 0; r < rows; ++r) s += g[(long long)r * cols + j];
+  db[j] = s;
+}
+
+// Adam on the FP32 master parameters; refreshes the bf16 weight copies.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ grad, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float gr = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gr;
+    const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  }
+}
+
+template <int EPI> void gemm(const MlpGemm& g, hipStream_t s) {
+  const int tiles = ((g.M + MT - 1) / MT) * ((g.N + MT - 1) / MT);
+  if (tiles > 0 && g.K > 0) hipLaunchKernelGGL(k_mlp_gemm<EPI>, dim3(tiles), dim3(MTH), 0, s, g);
+}
+
+int grid_for(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+}  // namespace
+}  // namespace mpdo
+
+using namespace mpdo;
+
+struct mpdo_mlp_s {
+  std::vector<int> w;            // widths d_0 .. d_L
+  int L = 0, max_batch = 0;
+  long long np = 0;
+  std::vector<long long> woff, boff;
+  hipStream_t st = nullptr;
+  DevBuf p, g, m, v, pb;         // FP32 params / grads / Adam moments; bf16 params
+  DevBuf xb;                     // input, bf16
+  DevBuf z, hb, gz, gzb, dx, part;
+  std::vector<long long> zoff;   // per layer offsets into z / hb / gz / gzb (max_batch x d_l)
+  long long step = 0;
+};
+
+namespace {
+mpdo_status mfail(int st, const std::string& msg) { return (mpdo_status)set_last_error(st, msg); }
+
+// Forward pass for `batch` rows of x (FP32, device) into y (FP32, device).
+void mlp_forward(mpdo_mlp_s* h, const float* x, int batch, float* y) {
+  const int L = h->L;
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for((long long)batch * h->w[0])), dim3(256), 0, h->st, x,
+                     h->xb.as<uint16_t>(), (long long)batch * h->w[0]);
+  const uint16_t* in = h->xb.as<uint16_t>();
+  for (int l = 0; l < L; ++l) {
+    MlpGemm g{};
+    g.A = in; g.lda = h->w[l];
+    g.B = h->pb.as<uint16_t>() + h->woff[l]; g.ldb = h->w[l]; g.transB = 1;  // W_l^T
+    g.M = batch; g.N = h->w[l + 1]; g.K = h->w[l];
+    g.bias = h->p.as<float>() + h->boff[l];
+    g.ldc = h->w[l + 1];
+    if (l + 1 < L) {
+      g.C = h->z.as<float>() + h->zoff[l];
+      g.Hb = h->hb.as<uint16_t>() + h->zoff[l];
+      gemm<EPI_HIDDEN>(g, h->st);
+      in = g.Hb;
+    } else {
+      g.C = y;
+      gemm<EPI_OUT>(g, h->st);
+    }
+  }
+}
+
+// Backward pass from the output cotangent already in gz/gzb of the last
+// layer: weight and bias gradients into h->g, input gradient into dx (if set).
+void mlp_backward(mpdo_mlp_s* h, int batch, float* dx) {
+  const int L = h->L;
+  for (int l = L - 1; l >= 0; --l) {
+    const uint16_t* gb = h->gzb.as<uint16_t>() + h->zoff[l];
+    const float* gf = h->gz.as<float>() + h->zoff[l];
+    const uint16_t* hin = l == 0 ? h->xb.as<uint16_t>() : h->hb.as<uint16_t>() + h->zoff[l - 1];
+    {  // dW_l = G^T H_{l-1}: (d_l x B)(B x d_{l-1})
+      MlpGemm g{};
+      g.A = gb; g.lda = h->w[l + 1]; g.transA = 1;
+      g.B = hin; g.ldb = h->w[l];
+      g.M = h->w[l + 1]; g.N = h->w[l]; g.K = batch;
+      g.C = h->g.as<float>() + h->woff[l]; g.ldc = h->w[l];
+      gemm<EPI_STORE>(g, h->st);
+    }
+    hipLaunchKernelGGL(k_colsum, dim3((h->w[l + 1] + 255) / 256), dim3(256), 0, h->st, gf, batch, h->w[l + 1],
+                       h->g.as<float>() + h->boff[l]);
+    // dA = G W_l: (B x d_l)(d_l x d_{l-1}); times GELU'(z_{l-1}) for hidden inputs
+    MlpGemm g{};
+    g.A = gb; g.lda = h->w[l + 1];
+    g.B = h->pb.as<uint16_t>() + h->woff[l]; g.ldb = h->w[l];
+    g.M = batch; g.N = h->w[l]; g.K = h->w[l + 1];
+    g.ldc = h->w[l];
+    if (l > 0) {
+      g.C = h->gz.as<float>() + h->zoff[l - 1];
+      g.Hb = h->gzb.as<uint16_t>() + h->zoff[l - 1];
+      g.aux = h->z.as<float>() + h->zoff[l - 1];
+      gemm<EPI_ACTGRAD>(g, h->st);
+    } else if (dx) {
+      g.C = dx;
+      gemm<EPI_STORE>(g, h->st);
+    }
+  }
+}
+
+void refresh_bf16(mpdo_mlp_s* h) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(h->np)), dim3(256), 0, h->st, h->p.as<float>(),
+                     h->pb.as<uint16_t>(), h->np);
+}
+
+#define MGUARD_BEGIN try {
+#define MGUARD_END                                                    \
+  }                                                                   \
+  catch (const Error& e) {                                            \
+    return mfail(e.status, e.msg);                                    \
+  }                                                                   \
+  catch (...) {                                                       \
+    return mfail(MPDO_EDEVICE, "internal error");                     \
+  }
+
+const char* check_batch(mpdo_mlp_s* h, int batch) {
+  if (!h) return "null network";
+  if (batch < 1 || batch > h->max_batch) return "batch must be in [1, max_batch]";
+  return nullptr;
+}
+}  // namespace
+
+extern "C" {
+
+mpdo_status mpdo_mlp_create(const int32_t* widths, int32_t nlayers, int32_t max_batch, void* hip_stream,
+                            mpdo_mlp_t* out) {
+  if (!out) return mfail(MPDO_EINVAL, "null out");
+  *out = nullptr;
+  if (!widths || nlayers < 1 || nlayers > 16) return mfail(MPDO_EINVAL, "nlayers must be in [1, 16]");
+  if (max_batch < 1 || max_batch > (1 << 20)) return mfail(MPDO_EINVAL, "max_batch must be in [1, 2^20]");
+  for (int l = 0; l <= nlayers; ++l)
+    if (widths[l] < 1 || widths[l] > 8192) return mfail(MPDO_EINVAL, "widths must be in [1, 8192]");
+  MGUARD_BEGIN
+  auto* h = new mpdo_mlp_s();
+  h->L = nlayers;
+  h->max_batch = max_batch;
+  h->st = reinterpret_cast<hipStream_t>(hip_stream);
+  h->w.assign(widths, widths + nlayers + 1);
+  long long off = 0, zo = 0;
+  for (int l = 0; l < nlayers; ++l) {
+    h->woff.push_back(off);
+    off += (long long)h->w[l + 1] * h->w[l];
+    h->boff.push_back(off);
+    off += h->w[l + 1];
+    h->zoff.push_back(zo);
+    zo += (long long)max_batch * h->w[l + 1];
+  }
+  h->np = off;
+  try {
+    h->p.alloc(off * 4);
+    h->g.alloc(off * 4);
+    h->m.alloc(off * 4);
+    h->v.alloc(off * 4);
+    h->pb.alloc(off * 2);
+    h->xb.alloc((size_t)max_batch * h->w[0] * 2);
+    h->z.alloc(zo * 4);
+    h->hb.alloc(zo * 2);
+    h->gz.alloc(zo * 4);
+    h->gzb.alloc(zo * 2);
+    h->part.alloc(1024 * 4);
+    hip_check(hipMemsetAsync(h->p.p, 0, off * 4, h->st), "memset");
+    hip_check(hipMemsetAsync(h->m.p, 0, off * 4, h->st), "memset");
+    hip_check(hipMemsetAsync(h->v.p, 0, off * 4, h->st), "memset");
+    refresh_bf16(h);
+    hip_check(hipStreamSynchronize(h->st), "sync");
+  } catch (...) {
+    delete h;
+    throw;
+  }
+  *out = h;
+  return MPDO_OK;
+  MGUARD_END
+}
+
+mpdo_status mpdo_mlp_destroy(mpdo_mlp_t h) {
+  if (!h) return MPDO_OK;
+  (void)hipStreamSynchronize(h->st);
+  delete h;
+  return MPDO_OK;
+}
+
+mpdo_status mpdo_mlp_info(mpdo_mlp_t h, int64_t* nparams) {
+  if (!h || !nparams) return mfail(MPDO_EINVAL, "null argument");
+  *nparams = h->np;
+  return MPDO_OK;
+}
+
+mpdo_status mpdo_mlp_set_params(mpdo_mlp_t h, const float* host) {
+  if (!h || !host) return mfail(MPDO_EINVAL, "null argument");
+  MGUARD_BEGIN
+  hip_check(hipMemcpyAsync(h->p.p, host, h->np * 4, hipMemcpyHostToDevice, h->st), "params");
+  hip_check(hipMemsetAsync(h->m.p, 0, h->np * 4, h->st), "memset");
+  hip_check(hipMemsetAsync(h->v.p, 0, h->np * 4, h->st), "memset");
+  h->step = 0;
+  refresh_bf16(h);
+  hip_check(hipStreamSynchronize(h->st), "sync");
+  return MPDO_OK;
+  MGUARD_END
+}
+
+mpdo_status mpdo_mlp_get_params(mpdo_mlp_t h, float* host) {
+  if (!h || !host) return mfail(MPDO_EINVAL, "null argument");
+  MGUARD_BEGIN
+  hip_check(hipMemcpyAsync(host, h->p.p, h->np * 4, hipMemcpyDeviceToHost, h->st), "params");
+  hip_check(hipStreamSynchronize(h->st), "sync");
+  return MPDO_OK;
+  MGUARD_END
+}
+
+mpdo_status mpdo_mlp_forward(mpdo_mlp_t h, const float* x_dev, int32_t batch, float* y_dev) {
+  if (const char* why = check_batch(h, batch)) return mfail(MPDO_EINVAL, why);
+  if (!x_dev || !y_dev) return mfail(MPDO_EINVAL, "null buffer");
+  MGUARD_BEGIN
+  mlp_forward(h, x_dev, batch, y_dev);
+  hip_check(hipGetLastError(), "launch (mlp forward)");
+  return MPDO_OK;
+  MGUARD_END
+}
+
+mpdo_status mpdo_mlp_backward(mpdo_mlp_t h, const float* x_dev, const float* t_dev, const float* gy_dev,
+                              int32_t batch, float* y_dev, float* grad_dev, float* dx_dev, float* loss) {
+  if (const char* why = check_batch(h, batch)) return mfail(MPDO_EINVAL, why);
+  if (!x_dev || !y_dev) return mfail(MPDO_EINVAL, "null buffer");
+  if ((t_dev == nullptr) == (gy_dev == nullptr)) return mfail(MPDO_EINVAL, "give exactly one of t_dev, gy_dev");
+  MGUARD_BEGIN
+  mlp_forward(h, x_dev, batch, y_dev);
+  const int L = h->L;
+  const long long n = (long long)batch * h->w[L];
+  float* gl = h->gz.as<float>() + h->zoff[L - 1];
+  uint16_t* glb = h->gzb.as<uint16_t>() + h->zoff[L - 1];
+  const int blocks = grid_for(n);
+  if (t_dev) {
+    hipLaunchKernelGGL(k_out_grad, dim3(blocks), dim3(256), 0, h->st, y_dev, t_dev, n, 1.0f / (float)n, gl, glb,
+                       h->part.as<float>());
+  } else {
+    hipLaunchKernelGGL(k_set_grad, dim3(blocks), dim3(256), 0, h->st, gy_dev, n, gl, glb);
+  }
+  mlp_backward(h, batch, dx_dev);
+  if (grad_dev)
+    hip_check(hipMemcpyAsync(grad_dev, h->g.p, h->np * 4, hipMemcpyDeviceToDevice, h->st), "grad copy");
+  hip_check(hipGetLastError(), "launch (mlp backward)");
+  if (loss) {
+    *loss = 0;
+    if (t_dev) {
+      std::vector<float> part(blocks);
+      hip_check(hipMemcpyAsync(part.data(), h->part.p, blocks * 4, hipMemcpyDeviceToHost, h->st), "loss");
+      hip_check(hipStreamSynchronize(h->st), "sync");
+      double s = 0;
+      for (float x : part) s += x;
+      *loss = (float)(s / (double)n);
+    }
+  }
+  return MPDO_OK;
+  MGUARD_END
+}
+
+mpdo_status mpdo_mlp_adam(mpdo_mlp_t h, float lr, float beta1, float beta2, float eps) {
+  if (!h) return mfail(MPDO_EINVAL, "null network");
+  if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return mfail(MPDO_EINVAL, "bad Adam hyper-parameters");
+  MGUARD_BEGIN
+  h->step += 1;
+  const float c1 = 1.0f / (1.0f - std::pow(beta1, (float)h->step));
+  const float c2 = 1.0f / (1.0f - std::pow(beta2, (float)h->step));
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(h->np)), dim3(256), 0, h->st, h->p.as<float>(), h->g.as<float>(),
+                     h->m.as<float>(), h->v.as<float>(), h->np, lr, beta1, beta2, eps, c1, c2);
+  refresh_bf16(h);
+  hip_check(hipGetLastError(), "launch (adam)");
+  return MPDO_OK;
+  MGUARD_END
+}
+
+}  // extern "C"

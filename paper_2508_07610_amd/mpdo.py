@@ -84,6 +84,14 @@ def lib() -> ctypes.CDLL:
                            ctypes.POINTER(vp), i32, vp, i32, vp],
         "mpdo_profile_enable": [i32],
         "mpdo_profile_read": [i32, pi, pd, pd, pd],
+        "mpdo_mlp_create": [pi, i32, i32, vp, ctypes.POINTER(vp)],
+        "mpdo_mlp_destroy": [vp],
+        "mpdo_mlp_info": [vp, ctypes.POINTER(ctypes.c_int64)],
+        "mpdo_mlp_set_params": [vp, ctypes.POINTER(ctypes.c_float)],
+        "mpdo_mlp_get_params": [vp, ctypes.POINTER(ctypes.c_float)],
+        "mpdo_mlp_forward": [vp, vp, i32, vp],
+        "mpdo_mlp_backward": [vp, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_float)],
+        "mpdo_mlp_adam": [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
     }
     for name, args in sig.items():
         f = getattr(L, name)
