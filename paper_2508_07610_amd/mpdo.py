@@ -59,6 +59,10 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2508_07610_amd.build`")
+    # torch ships its own HIP runtime under the same soname as the system one
+    # the library links against; importing torch first makes the process load
+    # exactly one runtime (torch's), so device buffers are shared between them.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     pd, pi = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)

@@ -360,3 +360,49 @@ def pauli_string(n: int, terms: dict) -> str:
 
 def zz_strings(n: int) -> List[str]:
     return [pauli_string(n, {i: "Z", i + 1: "Z"}) for i in range(n - 1)]
+
+
+# ----------------------------------------------------------------------------
+# per-gate noise strengths (surrogate inputs)
+# ----------------------------------------------------------------------------
+NOISE_LEVELS = 33
+_LOG_LO, _LOG_HI = math.log(0.25), math.log(4.0)
+
+
+def noise_level_scale(i: int) -> float:
+    """Channel strength multiplier of level i: a log grid on [1/4, 4]; level 16 is exactly 1."""
+    return math.exp(_LOG_LO + (_LOG_HI - _LOG_LO) * i / (NOISE_LEVELS - 1))
+
+
+def noise_levels(s: np.ndarray) -> np.ndarray:
+    """Nearest level of each strength multiplier (clipped to [1/4, 4])."""
+    x = (np.log(np.clip(s, 0.25, 4.0)) - _LOG_LO) / (_LOG_HI - _LOG_LO) * (NOISE_LEVELS - 1)
+    return np.clip(np.rint(x), 0, NOISE_LEVELS - 1).astype(np.int32)
+
+
+def gate_noise_levels(n: int, noise: Optional[np.ndarray]) -> Tuple[np.ndarray, np.ndarray]:
+    """The 2n noise inputs -- n per-qubit scales of the 1q channel, n - 1
+    per-bond scales of the 2q channel, one global scale -- as channel levels
+    of every qubit's 1q gates and every bond's CZ."""
+    if noise is None:
+        noise = np.ones(2 * n)
+    noise = np.asarray(noise, dtype=np.float64)
+    return noise_levels(noise[:n] * noise[-1]), noise_levels(noise[n:2 * n - 1] * noise[-1])
+
+
+def ghz_ansatz_noise(n: int, depth: int, theta: np.ndarray, noise: Optional[np.ndarray]) -> Program:
+    """ghz_ansatz with per-gate channel strengths: chis holds the 1q channels of
+    all levels, then the 2q channels of all levels; op.chan selects them."""
+    l1, l2 = gate_noise_levels(n, noise)
+    chis = ([chi_1q_default(noise_level_scale(i)) for i in range(NOISE_LEVELS)]
+            + [chi_2q_default(noise_level_scale(i)) for i in range(NOISE_LEVELS)])
+    ops: List[Op] = []
+    k = 0
+    for _ in range(depth):
+        for parity in (0, 1):
+            for q in range(n):
+                ops.append(Op((q,), ry(float(theta[k])), int(l1[q]), "ry", k))
+                k += 1
+            for q in range(parity, n - 1, 2):
+                ops.append(Op((q, q + 1), CZ.copy(), NOISE_LEVELS + int(l2[q]), "cz"))
+    return Program(n, ops, chis, depth)
