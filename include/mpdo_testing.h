@@ -24,10 +24,12 @@ extern "C" {
  *   op(A) is A[i*lda+k], A[k*lda+i], conj(A[i*lda+k]), conj(A[k*lda+i])).
  *   A holds rowsA x lda values, B rowsB x ldb; C is M x N (leading dim N).
  *   w (may be NULL): real weights, op(A)(i, k) is multiplied by w[k / wdiv].
- *   splits: split-K count (1..64). */
+ *   splits: split-K count (1..64).
+ *   tile: output tile edge of the kernel variant, 64 or 32. */
 mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
                            const double* A, int32_t rowsA, int32_t lda, const double* B, int32_t rowsB,
-                           int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha, double* C);
+                           int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha, double* C,
+                           int32_t tile);
 
 /* Hermitian eigendecomposition of A (n x n, 1 <= n <= 512) with the
  * library's eigensolver: the leading min(n, kvec + 1) eigenvalues in

@@ -606,8 +606,9 @@ template <typename Tin> std::vector<Tin> to_prec(const double* a, size_t n) {
 extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
                                       const double* A, int32_t rowsA, int32_t lda, const double* B, int32_t rowsB,
                                       int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha,
-                                      double* C) {
+                                      double* C, int32_t tile) {
   if (prec < 0 || prec > 2 || opA < 0 || opA > 3 || opB < 0 || opB > 3) return fail(MPDO_EINVAL, "bad mode");
+  if (tile != 64 && tile != 32) return fail(MPDO_EINVAL, "tile must be 64 or 32");
   if (M < 1 || N < 1 || K < 1 || rowsA < 1 || rowsB < 1 || lda < 1 || ldb < 1 || splits < 1 || splits > 64)
     return fail(MPDO_EINVAL, "bad size");
   if (!A || !B || !C) return fail(MPDO_EINVAL, "null buffer");
@@ -647,9 +648,10 @@ extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, in
   d.alpha = alpha;
   dD.alloc(sizeof(GemmDesc));
   hip_check(hipMemcpy(dD.p, &d, sizeof(d), hipMemcpyHostToDevice), "desc");
-  if (prec == 0) launch_gemm<double, double, double>(dD.as<GemmDesc>(), 1, 1, splits, gemm_tiles(M, N), st);
-  else if (prec == 1) launch_gemm<float, float, float>(dD.as<GemmDesc>(), 1, 1, splits, gemm_tiles(M, N), st);
-  else launch_gemm<float, double, double>(dD.as<GemmDesc>(), 1, 1, splits, gemm_tiles(M, N), st);
+  const int tiles = gemm_tiles(M, N, tile);
+  if (prec == 0) launch_gemm<double, double, double>(dD.as<GemmDesc>(), 1, 1, splits, tiles, st, tile);
+  else if (prec == 1) launch_gemm<float, float, float>(dD.as<GemmDesc>(), 1, 1, splits, tiles, st, tile);
+  else launch_gemm<float, double, double>(dD.as<GemmDesc>(), 1, 1, splits, tiles, st, tile);
   hip_check(hipGetLastError(), "launch");
   hip_check(hipDeviceSynchronize(), "sync");
   const size_t nc = (size_t)2 * M * N;

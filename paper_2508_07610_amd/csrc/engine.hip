@@ -197,7 +197,9 @@ void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up, bool f
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
   int m1 = 1;
   for (auto* g : ops) m1 = std::max(m1, g->ch ? g->ch->m : 1);
-  const int splitsH = splits_for((long long)cx * cx);
+  // (2k)^2 Gram over chi^2 terms: small output, long K -> 32 x 32 tiles, more splits
+  const int tileH = 2 * kx <= 32 ? 32 : 64;
+  const int splitsH = splits_for((long long)cx * cx * (tileH == 32 ? 4 : 1));
   const int ng = kx * m1;  // largest Gamma
   // ---- workspace layout per item ----
   Layout w;
@@ -266,8 +268,8 @@ void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up, bool f
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   if (tpo) tp = *tpo;
   launch_q1_prepare<T>(dctx, n, splitsH, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH, gemm_tiles(2 * kx, 2 * kx),
-                                 st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH,
+                                 gemm_tiles(2 * kx, 2 * kx, tileH), st_, tileH);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uH), reinterpret_cast<double**>(dv + uOut), n,
                        4 * kx * kx, st_);
   launch_q1_gamma<T>(dctx, n, st_);
@@ -284,7 +286,8 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
   int m2 = 1;
   for (auto* g : ops) m2 = std::max(m2, g->ch ? g->ch->m : 1);
-  const int splitsH = splits_for((long long)cx * 2 * cx);
+  const int tileH = 4 * kx <= 32 ? 32 : 64;
+  const int splitsH = splits_for((long long)cx * 2 * cx * (tileH == 32 ? 4 : 1));
   const int splitsE = splits_for((long long)kx * cx);
   const int splitsC = splits_for((long long)2 * kx * cx);
   const int ng = kx * m2;
@@ -427,14 +430,14 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigE), n, 2 * cx, status, st_);
   launch_q2_select_e<T>(dctx, n, splitsH, tp, st_);
   launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh), n, 1, 1, gemm_tiles((int)thetaN, 4 * cx), st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGramH), n, 1, splitsH, gemm_tiles(4 * kx, 4 * kx),
-                                 st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGramH), n, 1, splitsH,
+                                 gemm_tiles(4 * kx, 4 * kx, tileH), st_, tileH);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramH), reinterpret_cast<double**>(dv + uOutsH), n,
                        16 * kx * kx, st_);
   launch_q2_gamma<T>(dctx, n, st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigG), n, ng, status + n, st_);
   launch_q2_select_g<T>(dctx, n, splitsC, tp, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh2), n, cx, 1, gemm_tiles(4 * kx, 2 * cx), st_);
+  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh2), n, cx, 1, gemm_tiles(4 * kx, 2 * cx, tileH), st_, tileH);
   launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uC), n, 1, splitsC, gemm_tiles(4 * cx, 4 * cx), st_);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uC), reinterpret_cast<double**>(dv + uOutsC), n,
                        16 * cx * cx, st_);

@@ -5,8 +5,10 @@
 //
 // A complex product is four real MFMA products on split real/imaginary
 // planes staged in LDS:  Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
-// Tile 64 x 64 (complex) per workgroup of four waves; each wave owns a
-// 32 x 32 quadrant made of 2 x 2 blocks of the 16x16x4 MFMA.
+// Tiles of 64 x 64 (or 32 x 32 for products with small outputs and long K)
+// per workgroup of four waves; each wave owns a quadrant made of 16 x 16
+// MFMA blocks; the next K slice is fetched into registers while the current
+// one is multiplied.
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
@@ -33,20 +35,71 @@ template <> struct Mfma<float> {
 };
 
 namespace {
-constexpr int BM = 64, BN = 64, BK = 16, NTHR = 256, PAD = 4;
+constexpr int BK = 16, NTHR = 256, PAD = 4;
 constexpr int NXCD = 8;  // accelerator complex dies of the MI355X
 
 __device__ inline long long kaddr(int k, int kinner, long long kstride) {
   return (long long)(k / kinner) * kstride + (k % kinner);
 }
+
+// Staging of one BK-deep slice of op(A) (T x BK) or op(B) (BK x T): each
+// thread holds E = T * BK / NTHR elements in registers between the global
+// loads (issued one slice ahead) and the LDS stores.
+template <typename Tin, typename Tc, int T> struct Slice {
+  static constexpr int E = T * BK / NTHR;
+  Tc re[E], im[E];
+  // kfast: the K index is contiguous in memory for this operand
+  __device__ void load(const cpx<Tin>* X, int ld, bool kfast, bool conj, int r0, int R, int k0, int kend,
+                       int kinner, long long kstride, const double* w, int wdiv) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < E; ++it) {
+      const int idx = tid + it * NTHR;
+      int rr, kk;
+      if (kfast) { kk = idx % BK; rr = idx / BK; }
+      else { rr = idx % T; kk = idx / T; }
+      const int r = r0 + rr, k = k0 + kk;
+      Tc vr = 0, vi = 0;
+      if (r < R && k < kend) {
+        const long long ka = kaddr(k, kinner, kstride);
+        const cpx<Tin> v = kfast ? X[(long long)r * ld + ka] : X[ka * ld + r];
+        vr = (Tc)v.re;
+        vi = conj ? -(Tc)v.im : (Tc)v.im;
+        if (w) {
+          const Tc sw = (Tc)w[k / wdiv];
+          vr *= sw;
+          vi *= sw;
+        }
+      }
+      re[it] = vr;
+      im[it] = vi;
+    }
+  }
+  __device__ void store(Tc (*Sre)[T + PAD], Tc (*Sim)[T + PAD], bool kfast) const {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < E; ++it) {
+      const int idx = tid + it * NTHR;
+      int rr, kk;
+      if (kfast) { kk = idx % BK; rr = idx / BK; }
+      else { rr = idx % T; kk = idx / T; }
+      Sre[kk][rr] = re[it];
+      Sim[kk][rr] = im[it];
+    }
+  }
+};
 }  // namespace
 
-template <typename Tin, typename Tc, typename Tout>
+// Tile TM x TN per workgroup of four waves in a 2 x 2 arrangement; each wave
+// computes (TM/2) x (TN/2) from 16 x 16 MFMA blocks.  The next K slice is
+// loaded into registers while the current one is multiplied from LDS.
+template <typename Tin, typename Tc, typename Tout, int TM, int TN>
 __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch,
                                                int maxSplits, int maxTiles, long long nblocks) {
   typedef typename Mfma<Tc>::v4 v4;
-  __shared__ Tc As_re[BK][BM + PAD], As_im[BK][BM + PAD];
-  __shared__ Tc Bs_re[BK][BN + PAD], Bs_im[BK][BN + PAD];
+  constexpr int FM = TM / 32, FN = TN / 32;  // 16 x 16 blocks per wave and dimension
+  __shared__ Tc As_re[BK][TM + PAD], As_im[BK][TM + PAD];
+  __shared__ Tc Bs_re[BK][TN + PAD], Bs_im[BK][TN + PAD];
 
   // Workgroups are dealt to the XCDs round-robin (block b runs on XCD b % 8);
   // renumber so that each XCD takes a contiguous range of (item, batch,
@@ -64,10 +117,10 @@ __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ desc
   if (!d.active || batch >= d.nbatch || split >= d.splits) return;
   const int M = d.M, N = d.N, K = d.K;
   // this item's tiles are a prefix of the tile range
-  const int tilesN = (N + BN - 1) / BN;
-  if (tile >= ((M + BM - 1) / BM) * tilesN) return;
+  const int tilesN = (N + TN - 1) / TN;
+  if (tile >= ((M + TM - 1) / TM) * tilesN) return;
   const int tm = tile / tilesN, tn = tile % tilesN;
-  const int m0 = tm * BM, n0 = tn * BN;
+  const int m0 = tm * TM, n0 = tn * TN;
 
   const cpx<Tin>* A = reinterpret_cast<const cpx<Tin>*>(d.A) + (long long)batch * d.sA;
   const cpx<Tin>* B = reinterpret_cast<const cpx<Tin>*>(d.B) + (long long)batch * d.sB;
@@ -88,11 +141,11 @@ __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ desc
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
 
-  v4 acc_re[2][2], acc_im[2][2];
+  v4 acc_re[FM][FN], acc_im[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < FN; ++j) {
       acc_re[i][j] = v4{0, 0, 0, 0};
       acc_im[i][j] = v4{0, 0, 0, 0};
     }
@@ -102,66 +155,37 @@ __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ desc
   const bool bKfast = (opB == OP_T || opB == OP_H);
   const bool bConj = (opB == OP_C || opB == OP_H);
 
+  Slice<Tin, Tc, TM> sa;
+  Slice<Tin, Tc, TN> sb;
+  if (kbeg < kend) {
+    sa.load(A, lda, aKfast, aConj, m0, M, kbeg, kend, kinner, kstride, w, wdiv);
+    sb.load(B, ldb, bKfast, bConj, n0, N, kbeg, kend, kinner, kstride, nullptr, 1);
+  }
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // ---- stage A tile (BM x BK) ----
-#pragma unroll
-    for (int it = 0; it < (BM * BK) / NTHR; ++it) {
-      const int idx = tid + it * NTHR;
-      int mm, kk;
-      if (aKfast) { kk = idx % BK; mm = idx / BK; }
-      else { mm = idx % BM; kk = idx / BM; }
-      const int m = m0 + mm, k = k0 + kk;
-      Tc re = 0, im = 0;
-      if (m < M && k < kend) {
-        const long long ka = kaddr(k, kinner, kstride);
-        const cpx<Tin> v = aKfast ? A[(long long)m * lda + ka] : A[ka * lda + m];
-        re = (Tc)v.re;
-        im = aConj ? -(Tc)v.im : (Tc)v.im;
-        if (w) {
-          const Tc s = (Tc)w[k / wdiv];
-          re *= s;
-          im *= s;
-        }
-      }
-      As_re[kk][mm] = re;
-      As_im[kk][mm] = im;
-    }
-    // ---- stage B tile (BK x BN) ----
-#pragma unroll
-    for (int it = 0; it < (BN * BK) / NTHR; ++it) {
-      const int idx = tid + it * NTHR;
-      int nn, kk;
-      if (bKfast) { kk = idx % BK; nn = idx / BK; }
-      else { nn = idx % BN; kk = idx / BN; }
-      const int n = n0 + nn, k = k0 + kk;
-      Tc re = 0, im = 0;
-      if (n < N && k < kend) {
-        const long long ka = kaddr(k, kinner, kstride);
-        const cpx<Tin> v = bKfast ? B[(long long)n * ldb + ka] : B[ka * ldb + n];
-        re = (Tc)v.re;
-        im = bConj ? -(Tc)v.im : (Tc)v.im;
-      }
-      Bs_re[kk][nn] = re;
-      Bs_im[kk][nn] = im;
-    }
+    sa.store(As_re, As_im, aKfast);
+    sb.store(Bs_re, Bs_im, bKfast);
     __syncthreads();
+    if (k0 + BK < kend) {  // next slice in flight during the products below
+      sa.load(A, lda, aKfast, aConj, m0, M, k0 + BK, kend, kinner, kstride, w, wdiv);
+      sb.load(B, ldb, bKfast, bConj, n0, N, k0 + BK, kend, kinner, kstride, nullptr, 1);
+    }
 #pragma unroll
     for (int kb = 0; kb < BK; kb += 4) {
-      Tc ar[2], ai[2], br[2], bi[2];
+      Tc ar[FM], ai[FM], br[FN], bi[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = As_re[kb + lk][wm * 32 + i * 16 + li];
-        ai[i] = As_im[kb + lk][wm * 32 + i * 16 + li];
+      for (int i = 0; i < FM; ++i) {
+        ar[i] = As_re[kb + lk][wm * (TM / 2) + i * 16 + li];
+        ai[i] = As_im[kb + lk][wm * (TM / 2) + i * 16 + li];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        br[j] = Bs_re[kb + lk][wn * 32 + j * 16 + li];
-        bi[j] = Bs_im[kb + lk][wn * 32 + j * 16 + li];
+      for (int j = 0; j < FN; ++j) {
+        br[j] = Bs_re[kb + lk][wn * (TN / 2) + j * 16 + li];
+        bi[j] = Bs_im[kb + lk][wn * (TN / 2) + j * 16 + li];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < FN; ++j) {
           acc_re[i][j] = Mfma<Tc>::mma(ar[i], br[j], acc_re[i][j]);
           acc_re[i][j] = Mfma<Tc>::mma(-ai[i], bi[j], acc_re[i][j]);
           acc_im[i][j] = Mfma<Tc>::mma(ar[i], bi[j], acc_im[i][j]);
@@ -174,13 +198,13 @@ __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ desc
   const Tc alpha = (Tc)d.alpha;
   const int ldc = d.ldc;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 32 + i * 16 + Mfma<Tc>::row(lk, v);
-        const int col = n0 + wn * 32 + j * 16 + li;
+        const int row = m0 + wm * (TM / 2) + i * 16 + Mfma<Tc>::row(lk, v);
+        const int col = n0 + wn * (TN / 2) + j * 16 + li;
         if (row < M && col < N) {
           cpx<Tout>* p = C + (long long)row * ldc + col;
           cpx<Tc> r = mk<Tc>(alpha * acc_re[i][j][v], alpha * acc_im[i][j][v]);
@@ -215,18 +239,23 @@ __global__ void k_reduce_splits(const GemmDesc* __restrict__ descs, double* cons
   }
 }
 
-int gemm_tiles(int maxM, int maxN) { return ((maxM + BM - 1) / BM) * ((maxN + BN - 1) / BN); }
+int gemm_tiles(int maxM, int maxN, int tile) { return ((maxM + tile - 1) / tile) * ((maxN + tile - 1) / tile); }
 
 template <typename Tin, typename Tc, typename Tout>
-void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s) {
+void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s,
+                 int tile) {
   if (nitems <= 0 || maxTiles <= 0) return;
   const long long blocks = (long long)nitems * maxBatch * maxSplits * maxTiles;
   if (blocks <= 0) return;
   const long long grid = (blocks + NXCD - 1) / NXCD * NXCD;
   const int cls = sizeof(Tc) == 8 ? PC_GEMM_F64 : PC_GEMM_F32;
   const int tok = prof_begin(cls, s);
-  hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs, maxBatch,
-                     maxSplits, maxTiles, blocks);
+  if (tile == 32)
+    hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 32, 32>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs, maxBatch,
+                       maxSplits, maxTiles, blocks);
+  else
+    hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 64, 64>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs, maxBatch,
+                       maxSplits, maxTiles, blocks);
   prof_end_gemm(tok, cls, d_descs, nitems, (int)sizeof(cpx<Tin>), (int)sizeof(cpx<Tout>), s);
 }
 
@@ -239,9 +268,9 @@ void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int ni
                      d_outs, maxCount);
 }
 
-template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, hipStream_t);
-template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, hipStream_t);
-template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, hipStream_t);
-template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, hipStream_t);
+template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int);
+template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, hipStream_t, int);
+template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int);
+template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, hipStream_t, int);
 
 }  // namespace mpdo

@@ -5,13 +5,14 @@
 namespace mpdo {
 
 // Batched complex GEMM (see GemmDesc).  The grid covers nitems x maxBatch x
-// maxSplits x maxTiles output tiles of 64 x 64; an item uses the first
-// ceil(M/64) ceil(N/64) tiles of its range, so maxTiles must bound that
-// count for every item (gemm_tiles of the largest M and N).  Tin: input
-// precision, Tc: MFMA precision, Tout: output precision.
-int gemm_tiles(int maxM, int maxN);
+// maxSplits x maxTiles output tiles of tile x tile (tile = 64 or 32); an item
+// uses the first ceil(M/tile) ceil(N/tile) tiles of its range, so maxTiles
+// must bound that count for every item (gemm_tiles of the largest M and N).
+// Tin: input precision, Tc: MFMA precision, Tout: output precision.
+int gemm_tiles(int maxM, int maxN, int tile = 64);
 template <typename Tin, typename Tc, typename Tout>
-void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s);
+void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s,
+                 int tile = 64);
 
 // out[item] = sum over splits of the partial products of descs[item]
 // (complex double, dense M x ldc).

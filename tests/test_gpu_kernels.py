@@ -22,12 +22,13 @@ def _rand(shape, rng):
 @pytest.mark.parametrize("M_,N_,K_", [(1, 1, 1), (16, 16, 4), (64, 64, 16), (65, 70, 33), (130, 37, 257),
                                       (5, 300, 9)])
 @pytest.mark.parametrize("opA,opB", [(0, 0), (1, 0), (2, 1), (3, 3), (0, 3), (3, 0)])
-def test_gemm_fp64(M_, N_, K_, opA, opB):
+@pytest.mark.parametrize("tile", [64, 32])
+def test_gemm_fp64(M_, N_, K_, opA, opB, tile):
     require_gpu()
     rng = np.random.default_rng(M_ * 1000 + N_ * 10 + K_)
     A = _rand((K_, M_) if opA in (1, 3) else (M_, K_), rng)
     B = _rand((N_, K_) if opB in (1, 3) else (K_, N_), rng)
-    C = M.test_gemm(0, opA, opB, M_, N_, K_, A, B, alpha=0.75)
+    C = M.test_gemm(0, opA, opB, M_, N_, K_, A, B, alpha=0.75, tile=tile)
     ref = 0.75 * _op(A, opA) @ _op(B, opB)
     err = float(np.abs(C - ref).max())
     bad = np.argwhere(np.abs(C - ref) > 1e-9)[:8].tolist()
@@ -35,12 +36,13 @@ def test_gemm_fp64(M_, N_, K_, opA, opB):
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-def test_gemm_fp32_paths(prec):
+@pytest.mark.parametrize("tile", [64, 32])
+def test_gemm_fp32_paths(prec, tile):
     require_gpu()
     rng = np.random.default_rng(3)
     A = _rand((200, 96), rng)
     B = _rand((96, 150), rng)
-    C = M.test_gemm(prec, 0, 0, 200, 150, 96, A, B)
+    C = M.test_gemm(prec, 0, 0, 200, 150, 96, A, B, tile=tile)
     A32, B32 = A.astype(np.complex64), B.astype(np.complex64)
     ref = A32.astype(np.complex128) @ B32.astype(np.complex128)
     tol = 1e-5 if prec == 1 else 1e-12
@@ -49,14 +51,15 @@ def test_gemm_fp32_paths(prec):
     assert err < tol, (err, bad)
 
 
-def test_gemm_split_k_and_weights():
+@pytest.mark.parametrize("tile", [64, 32])
+def test_gemm_split_k_and_weights(tile):
     """Weighted Gram with split-K: C = A^H diag(w[k / wdiv]) A."""
     require_gpu()
     rng = np.random.default_rng(4)
     K_, N_ = 4100, 48
     A = _rand((K_, N_), rng)
     w = rng.uniform(0.1, 2.0, size=(K_ + 3) // 4)
-    C = M.test_gemm(0, 3, 0, N_, N_, K_, A, A, w=w, wdiv=4, splits=7)
+    C = M.test_gemm(0, 3, 0, N_, N_, K_, A, A, w=w, wdiv=4, splits=7, tile=tile)
     wk = np.repeat(w, 4)[:K_]
     ref = A.conj().T @ (wk[:, None] * A)
     err = float(np.abs(C - ref).max() / np.abs(ref).max())
