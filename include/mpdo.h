@@ -110,8 +110,9 @@ mpdo_status mpdo_channel_info(mpdo_chan_t ch, int32_t* q, int32_t* nkraus,
 mpdo_status mpdo_channel_destroy(mpdo_chan_t ch);
 
 /* Apply the ideal gate U (host, 2^q x 2^q complex) on `sites` (q ascending
- * adjacent sites, q in {1, 2}).  A 2-qubit gate re-splits the pair by SVD
- * with bond truncation. */
+ * adjacent sites, q in {1, 2, 3}).  A 2- or 3-qubit gate re-splits the block
+ * by SVD with bond truncation.  3-site gates (ideal or noisy) need
+ * 2 kappa_max chi_max <= 512, else MPDO_EUNSUPPORTED. */
 mpdo_status mpdo_apply_gate(mpdo_t h, const int32_t* sites, int32_t q, const double* U);
 
 /* Apply the noisy gate "U then channel": operators G_i = K_i U (Eq. (8));
@@ -171,13 +172,15 @@ typedef enum {
 } mpdo_gate_kind;
 
 typedef struct {
-  int32_t q;            /* 1 or 2                                              */
+  int32_t q;            /* 1, 2 or 3 (3: kind MPDO_G_FIXED with fixed = -1,
+                           i.e. a three-site channel without a gate)          */
   int32_t site;         /* lowest site                                         */
   int32_t kind;         /* mpdo_gate_kind                                      */
   int32_t param;        /* index into the instance's parameter row, or -1      */
   double scale;         /* angle = scale * param value                         */
   int32_t chan;         /* channel slot (index into `chans`), or -1            */
-  int32_t fixed;        /* for MPDO_G_FIXED: index into `fixed_u`              */
+  int32_t fixed;        /* for MPDO_G_FIXED: index into `fixed_u`, or -1 for
+                           the identity                                        */
 } mpdo_op;
 
 typedef struct {
@@ -202,7 +205,8 @@ typedef struct {
  * descriptor upload, every sublayer, the observables) into one HIP graph and
  * launches it once; with hip_stream NULL a private stream is used for the
  * capture.  The call returns when the results are in out_dev.  Returns
- * EINVAL for malformed programs, EUNSUPPORTED for 3-qubit ops. */
+ * EINVAL for malformed programs, EUNSUPPORTED for 3-site ops when
+ * 2 kappa_max chi_max > 512. */
 mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
                            const double* params_dev, int32_t param_stride,
                            const double* fixed_u, int32_t nfixed,

@@ -236,7 +236,8 @@ static mpdo_status enqueue(mpdo_t h, const int32_t* sites, int32_t q, const doub
   }
   if (ch && ch->ch.q != q) return fail(MPDO_EINVAL, "channel arity differs from the number of sites");
   if (ch && ch->ch.m > h->cfg.max_kraus) return fail(MPDO_EINVAL, "channel has more Kraus operators than max_kraus");
-  if (q == 3) return fail(MPDO_EUNSUPPORTED, "3-qubit channels are not available in this build");
+  if (q == 3 && 2LL * h->cfg.kappa_max * h->cfg.chi_max > 512)
+    return fail(MPDO_EUNSUPPORTED, "3-site gates need 2 kappa_max chi_max <= 512");
   const int d = 1 << q;
   if (U) {
     for (int e = 0; e < 2 * d * d; ++e)
@@ -266,7 +267,6 @@ static mpdo_status enqueue(mpdo_t h, const int32_t* sites, int32_t q, const doub
 
 mpdo_status mpdo_apply_gate(mpdo_t h, const int32_t* sites, int32_t q, const double* U) {
   if (!U) return fail(MPDO_EINVAL, "null U");
-  if (q > 2) return fail(MPDO_EINVAL, "ideal gates act on 1 or 2 sites");
   return enqueue(h, sites, q, U, nullptr);
 }
 
@@ -496,13 +496,17 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
     total_obs += p.nobs;
     for (int j = 0; j < p.nops; ++j) {
       const mpdo_op& o = p.ops[j];
-      if (o.q < 1 || o.q > 2) return fail(o.q == 3 ? MPDO_EUNSUPPORTED : MPDO_EINVAL, "op arity must be 1 or 2");
+      if (o.q < 1 || o.q > 3) return fail(MPDO_EINVAL, "op arity must be 1, 2 or 3");
+      if (o.q == 3 && (o.kind != MPDO_G_FIXED || o.fixed != -1))
+        return fail(MPDO_EINVAL, "3-site ops carry no gate matrix (kind MPDO_G_FIXED, fixed = -1)");
+      if (o.q == 3 && 2LL * cfg->kappa_max * cfg->chi_max > 512)
+        return fail(MPDO_EUNSUPPORTED, "3-site ops need 2 kappa_max chi_max <= 512");
       if (o.site < 0 || o.site + o.q > p.n) return fail(MPDO_EINVAL, "op site out of range");
       const bool k1 = o.kind == MPDO_G_RX || o.kind == MPDO_G_RY || o.kind == MPDO_G_RZ;
       const bool k2 = o.kind == MPDO_G_ZZPHASE || o.kind == MPDO_G_SWAPZZ;
       if (o.kind != MPDO_G_FIXED && !((k1 && o.q == 1) || (k2 && o.q == 2)))
         return fail(MPDO_EINVAL, "gate kind does not match its arity");
-      if (o.kind == MPDO_G_FIXED && (o.fixed < 0 || o.fixed >= nfixed)) return fail(MPDO_EINVAL, "bad fixed index");
+      if (o.kind == MPDO_G_FIXED && (o.fixed < -1 || o.fixed >= nfixed)) return fail(MPDO_EINVAL, "bad fixed index");
       if (o.param >= 0 && (!params_dev || o.param >= param_stride)) return fail(MPDO_EINVAL, "bad parameter index");
       if (!std::isfinite(o.scale)) return fail(MPDO_EINVAL, "scale is not finite");
       if (o.chan >= nchans || o.chan < -1) return fail(MPDO_EINVAL, "bad channel index");
@@ -550,7 +554,8 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
       op.pidx = o.param;
       op.scale = o.scale;
       op.params = o.param >= 0 ? params_dev + (size_t)b * param_stride : nullptr;
-      if (o.kind == MPDO_G_FIXED) op.ufix = dfix.as<double>() + (size_t)o.fixed * 40 + (o.q == 1 ? 32 : 0);
+      if (o.kind == MPDO_G_FIXED && o.fixed >= 0)
+        op.ufix = dfix.as<double>() + (size_t)o.fixed * 40 + (o.q == 1 ? 32 : 0);
       op.ch = o.chan >= 0 ? &chans[o.chan]->ch : nullptr;
       layers[g].push_back(op);
     }

@@ -140,6 +140,7 @@ template <typename T> class Engine {
               const TruncParams* tpo = nullptr);
   void sweep_step(const std::vector<int>& inst, int pass, int site, const TruncParams& tp);
   void run_2q(const std::vector<const GateOp*>& ops, Upload& up);
+  void run_3q(const std::vector<const GateOp*>& ops, Upload& up);
   int splits_for(long long K) const;
   // descriptor space of `bytes` (host image h, device address dv); false in a dry pass
   bool reserve(Upload& up, size_t bytes, size_t work_bytes, int items, char*& h, char*& dv);

@@ -172,11 +172,11 @@ template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& op
 }
 
 template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& ops, Upload& up) {
-  std::vector<const GateOp*> one, two;
+  std::vector<const GateOp*> one, two, three;
   for (const GateOp& g : ops) {
     if (g.q == 1) one.push_back(&g);
     else if (g.q == 2) two.push_back(&g);
-    else throw Error{6 /*MPDO_EUNSUPPORTED*/, "3-qubit channels are not available in this build"};
+    else three.push_back(&g);
   }
   // chunks bounded by a workspace budget
   const size_t budget = (size_t)8 << 30;
@@ -188,6 +188,8 @@ template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& op
     run_1q(std::vector<const GateOp*>(one.begin() + a, one.begin() + std::min(one.size(), a + 4096)), up);
   for (size_t a = 0; a < two.size(); a += chunk2)
     run_2q(std::vector<const GateOp*>(two.begin() + a, two.begin() + std::min(two.size(), a + chunk2)), up);
+  for (size_t a = 0; a < three.size(); a += 8)
+    run_3q(std::vector<const GateOp*>(three.begin() + a, three.begin() + std::min(three.size(), a + 8)), up);
 }
 
 template <typename T>
@@ -577,6 +579,170 @@ template <typename T> std::vector<double> Engine<T>::bond_weights(int b, int bon
   std::vector<double> v(len);
   hip_check(hipMemcpy(v.data(), lam_ptr(b, bond), sizeof(double) * len, hipMemcpyDeviceToHost), "lambda");
   return v;
+}
+
+// Three-site noisy gates (see Ctx3).  Requires 2 kap_max chi_max <= 512 (the
+// Gram matrices of the two splits) and kap_max max_kraus <= 512.
+template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& ops, Upload& up) {
+  const int n = (int)ops.size();
+  if (n == 0) return;
+  const int kx = cfg_.kap_max, cx = cfg_.chi_max;
+  int m3 = 1;
+  for (auto* g : ops) m3 = std::max(m3, g->ch ? g->ch->m : 1);
+  const int rowsL = 2 * kx * cx;             // (l t k) and (r1 s nu) bound
+  const long long innerX = (long long)2 * kx * cx;
+  const int kmm = kx * m3;
+  if (rowsL > 512 || kmm > 512)
+    throw Error{6 /*MPDO_EUNSUPPORTED*/, "3-site channels need 2 kappa_max chi_max <= 512 and kappa_max m <= 512"};
+  const int splitsH = splits_for((long long)cx * 4 * kx * innerX);
+  const int splitsG = splits_for((long long)2 * kx * innerX);
+  Layout w;
+  const size_t oG = w.add((size_t)m3 * 64 * 16);
+  const size_t oX = w.add((size_t)rowsL * innerX * sizeof(cpx<T>));
+  const size_t oPhi = w.add((size_t)rowsL * 2 * kx * innerX * sizeof(cpx<T>));
+  const size_t oPsi = w.add((size_t)rowsL * 2 * kmm * innerX * sizeof(cpx<T>));
+  const size_t oPsi2 = w.add((size_t)rowsL * 2 * kx * innerX * sizeof(cpx<T>));
+  const size_t oH = w.add((size_t)kmm * kmm * 16);
+  const size_t oHp = w.add((size_t)splitsH * kmm * kmm * 16);
+  const size_t oEvH = w.add((size_t)(kmm + 1) * 8);
+  const size_t oVecH = w.add((size_t)kmm * kmm * 16);
+  const size_t oWkH = w.add((size_t)eig_work_doubles(kmm) * 8);
+  const size_t oP = w.add((size_t)kmm * kx * sizeof(cpx<T>));
+  const size_t oG1 = w.add((size_t)rowsL * rowsL * 16);
+  const size_t oG1p = w.add((size_t)splitsG * rowsL * rowsL * 16);
+  const size_t oEv1 = w.add((size_t)(rowsL + 1) * 8);
+  const size_t oVec1 = w.add((size_t)rowsL * rowsL * 16);
+  const size_t oWk1 = w.add((size_t)eig_work_doubles(rowsL) * 8);
+  const size_t oQ1 = w.add((size_t)rowsL * cx * sizeof(cpx<T>));
+  const size_t oV1 = w.add((size_t)cx * 2 * kx * innerX * sizeof(cpx<T>));
+  const size_t oG2 = w.add((size_t)rowsL * rowsL * 16);
+  const size_t oG2p = w.add((size_t)splitsG * rowsL * rowsL * 16);
+  const size_t oEv2 = w.add((size_t)(rowsL + 1) * 8);
+  const size_t oVec2 = w.add((size_t)rowsL * rowsL * 16);
+  const size_t oWk2 = w.add((size_t)eig_work_doubles(rowsL) * 8);
+  const size_t oQ2 = w.add((size_t)rowsL * cx * sizeof(cpx<T>));
+  const size_t oScr = w.add(16);
+  const size_t per = w.off;
+  if (n > 1 && per * n > ((size_t)8 << 30)) {  // workspace budget: split the group
+    const int h = n / 2;
+    run_3q(std::vector<const GateOp*>(ops.begin(), ops.begin() + h), up);
+    run_3q(std::vector<const GateOp*>(ops.begin() + h, ops.end()), up);
+    return;
+  }
+  Layout u;
+  const size_t uCtx = u.add(sizeof(Ctx3<T>) * n);
+  const size_t uG = u.add(sizeof(GemmDesc) * 8 * n);  // X Phi H Proj G1 V1 G2 Tk
+  const size_t uE = u.add(sizeof(EigDesc) * 3 * n);    // H G1 G2
+  const size_t uOuts = u.add(sizeof(double*) * 3 * n);
+  const size_t uU = u.add(sizeof(double) * 128 * n);
+  char *h = nullptr, *dv = nullptr;
+  if (!reserve(up, u.off, per * n, 3 * n, h, dv)) return;
+  char* wk = reinterpret_cast<char*>(work_.p);
+  GemmDesc* dG = reinterpret_cast<GemmDesc*>(dv + uG);
+  EigDesc* dE = reinterpret_cast<EigDesc*>(dv + uE);
+  for (int it = 0; it < n; ++it) {
+    const GateOp& g = *ops[it];
+    char* base = wk + per * it;
+    Ctx3<T>& c = at<Ctx3<T>>(h, uCtx)[it];
+    double* uslot = at<double>(h, uU) + 128 * it;
+    c.g.kind = g.kind; c.g.q = 3; c.g.pidx = g.pidx; c.g.scale = g.scale; c.g.params = g.params;
+    c.g.ufix = g.ufix;
+    if (g.has_u) {
+      std::memcpy(uslot, g.uhost, 128 * sizeof(double));
+      c.g.ufix = reinterpret_cast<const double*>(dv + uU) + 128 * it;
+    }
+    c.kraus = g.ch ? g.ch->kraus.as<double>() : nullptr;
+    c.m = g.ch ? g.ch->m : 1;
+    const int b = g.inst, i = g.site;
+    const int p0 = par_[soff_[b] + i], p1 = par_[soff_[b] + i + 1], p2 = par_[soff_[b] + i + 2];
+    c.Bi = site(b, i, p0);
+    c.Bj = site(b, i + 1, p1);
+    c.Bk = site(b, i + 2, p2);
+    c.Bi_new = site(b, i, 1 - p0);
+    c.Bj_new = site(b, i + 1, 1 - p1);
+    c.Bk_new = site(b, i + 2, 1 - p2);
+    c.laml2 = laml2(b, i);
+    c.lam1 = lam_ptr(b, i);
+    c.lam1sq = lam2_ptr(b, i);
+    c.lam2 = lam_ptr(b, i + 1);
+    c.lam2sq = lam2_ptr(b, i + 1);
+    c.chil = chi_ptr(b, i);
+    c.chim1 = chi_ptr(b, i + 1);
+    c.chim2 = chi_ptr(b, i + 2);
+    c.chir = chi_ptr(b, i + 3);
+    c.kap1 = kap_ptr(b, i);
+    c.kap2 = kap_ptr(b, i + 1);
+    c.kap3 = kap_ptr(b, i + 2);
+    c.disc = disc_ptr(b, i);
+    c.scratch = at<int>(base, oScr);
+    c.G = at<double>(base, oG);
+    c.X = at<cpx<T>>(base, oX);
+    c.Phi = at<cpx<T>>(base, oPhi);
+    c.Psi = at<cpx<T>>(base, oPsi);
+    c.Psi2 = at<cpx<T>>(base, oPsi2);
+    c.H = at<double>(base, oH);
+    c.evH = at<double>(base, oEvH);
+    c.vecH = at<double>(base, oVecH);
+    c.P = at<cpx<T>>(base, oP);
+    c.G1 = at<double>(base, oG1);
+    c.ev1 = at<double>(base, oEv1);
+    c.vec1 = at<double>(base, oVec1);
+    c.Q1 = at<cpx<T>>(base, oQ1);
+    c.V1 = at<cpx<T>>(base, oV1);
+    c.G2 = at<double>(base, oG2);
+    c.ev2 = at<double>(base, oEv2);
+    c.vec2 = at<double>(base, oVec2);
+    c.Q2 = at<cpx<T>>(base, oQ2);
+    // descriptor kind k of item it lives at dG[k n + it] (launches take one kind)
+    c.dX = dG + it; c.dPhi = dG + n + it; c.dH = dG + 2 * n + it; c.dProj = dG + 3 * n + it;
+    c.dG1 = dG + 4 * n + it; c.dV1 = dG + 5 * n + it; c.dG2 = dG + 6 * n + it; c.dTk = dG + 7 * n + it;
+    c.dEH = dE + it; c.dE1 = dE + n + it; c.dE2 = dE + 2 * n + it;
+    GemmDesc* hd = at<GemmDesc>(h, uG);
+    hd[2 * n + it].C = at<double>(base, oHp);
+    hd[2 * n + it].sSplit = (long long)kmm * kmm;
+    hd[4 * n + it].C = at<double>(base, oG1p);
+    hd[4 * n + it].sSplit = (long long)rowsL * rowsL;
+    hd[6 * n + it].C = at<double>(base, oG2p);
+    hd[6 * n + it].sSplit = (long long)rowsL * rowsL;
+    EigDesc* he = at<EigDesc>(h, uE);
+    he[it].a = c.H; he[it].work = at<double>(base, oWkH); he[it].kvec = kx;
+    he[n + it].a = c.G1; he[n + it].work = at<double>(base, oWk1); he[n + it].kvec = cx;
+    he[2 * n + it].a = c.G2; he[2 * n + it].work = at<double>(base, oWk2); he[2 * n + it].kvec = cx;
+    double** outs = at<double*>(h, uOuts);
+    outs[it] = c.H;
+    outs[n + it] = c.G1;
+    outs[2 * n + it] = c.G2;
+  }
+  commit(up, h, dv, u.off);
+  Ctx3<T>* dctx = reinterpret_cast<Ctx3<T>*>(dv + uCtx);
+  double** douts = reinterpret_cast<double**>(dv + uOuts);
+  TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
+  int* status = sweeps_.as<int>();
+  const int tX = gemm_tiles(rowsL, (int)innerX), tPhi = gemm_tiles(rowsL, 2 * kx * (int)innerX);
+  launch_q3_prepare<T>(dctx, n, splitsH, st_);
+  launch_gemm<T, T, T>(dG, n, 1, 1, tX, st_);
+  launch_gemm<T, T, T>(dG + n, n, 1, 1, tPhi, st_);
+  launch_q3_apply<T>(dctx, n, st_);
+  launch_gemm<T, double, double>(dG + 2 * n, n, 1, splitsH, gemm_tiles(kmm, kmm), st_);
+  launch_reduce_splits(dG + 2 * n, douts, n, kmm * kmm, st_);
+  launch_eigh(dE, n, kmm, status, st_);
+  launch_q3_select_h<T>(dctx, n, splitsG, tp, st_);
+  launch_gemm<T, T, T>(dG + 3 * n, n, cx * 4 * kx, 1, gemm_tiles(kx, (int)innerX), st_);
+  launch_gemm<T, double, double>(dG + 4 * n, n, 1, splitsG, gemm_tiles(rowsL, rowsL), st_);
+  launch_reduce_splits(dG + 4 * n, douts + n, n, rowsL * rowsL, st_);
+  launch_q3_scale1<T>(dctx, n, st_);
+  launch_eigh(dE + n, n, rowsL, status + n, st_);
+  launch_q3_select_1<T>(dctx, n, splitsG, tp, st_);
+  launch_gemm<T, T, T>(dG + 5 * n, n, 1, 1, gemm_tiles(cx, 2 * kx * (int)innerX), st_);
+  launch_gemm<T, double, double>(dG + 6 * n, n, 1, splitsG, gemm_tiles(rowsL, rowsL), st_);
+  launch_reduce_splits(dG + 6 * n, douts + 2 * n, n, rowsL * rowsL, st_);
+  launch_q3_scale2<T>(dctx, n, st_);
+  launch_eigh(dE + 2 * n, n, rowsL, status + 2 * n, st_);
+  launch_q3_select_2<T>(dctx, n, tp, st_);
+  launch_gemm<T, T, T>(dG + 7 * n, n, 1, 1, gemm_tiles(cx, (int)innerX), st_);
+  hip_check(hipGetLastError(), "launch (3-site sublayer)");
+  for (auto* g : ops)
+    for (int t = 0; t < 3; ++t) par_[soff_[g->inst] + g->site + t] ^= 1;
 }
 
 // One sweep step (pass 0: site -> site + 1, pass 1: site -> site - 1) on the

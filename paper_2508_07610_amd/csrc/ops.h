@@ -87,6 +87,51 @@ template <typename T> struct Ctx2 {
   GemmDesc* dOut;         // 2: B_i, B_{i+1}
 };
 
+// Three-site noisy gate on (i, i+1, i+2), the Kraus index joining the inner
+// index of the middle site: the three-site block is contracted, the fused
+// operators applied, the middle inner index truncated, and the block split
+// twice (bond i, then bond i+1) by Gram eigendecompositions.
+template <typename T> struct Ctx3 {
+  GateSrc g;
+  const double* kraus;    // m x 8 x 8 complex or null
+  int m, pad;
+  const cpx<T>* Bi;
+  const cpx<T>* Bj;
+  const cpx<T>* Bk;
+  cpx<T>* Bi_new;
+  cpx<T>* Bj_new;
+  cpx<T>* Bk_new;
+  const double* laml2;    // squared weights of bond i-1
+  double* lam1;           // weights of bond i (output)
+  double* lam1sq;
+  double* lam2;           // weights of bond i+1 (output)
+  double* lam2sq;
+  const int* chil;
+  int* chim1;
+  int* chim2;
+  const int* chir;
+  const int* kap1;
+  int* kap2;
+  const int* kap3;
+  double* disc;
+  int* scratch;           // [0] kappa', [1] bond i, [2] bond i+1
+  double* G;              // m x 8 x 8
+  cpx<T>* X;              // B_{i+1} B_{i+2}
+  cpx<T>* Phi;            // (l t1 k1) x (t2 k2 t3 k3 r)
+  cpx<T>* Psi;            // (l s1 k1) x (s2 (k2 j) s3 k3 r)
+  cpx<T>* Psi2;           // (l s1 k1) x (s2 nu s3 k3 r)
+  double* H;  double* evH; double* vecH;
+  cpx<T>* P;              // (k2 m) x kappa'
+  double* G1; double* ev1; double* vec1;
+  cpx<T>* Q1;             // (l s1 k1) x r1
+  cpx<T>* V1;             // r1 x (s2 nu s3 k3 r)
+  double* G2; double* ev2; double* vec2;
+  cpx<T>* Q2;             // (r1 s2 nu) x r2
+  GemmDesc* dX; GemmDesc* dPhi; GemmDesc* dH; GemmDesc* dProj; GemmDesc* dG1; GemmDesc* dV1;
+  GemmDesc* dG2; GemmDesc* dTk;
+  EigDesc* dEH; EigDesc* dE1; EigDesc* dE2;
+};
+
 // One step of the truncation sweep (Sec. II.D) on one instance.
 //  pass 0, left to right: A = T_i as (l s k) x r; A^H A = V D V^H on the
 //    eigenvalues above the numerical floor; T_i <- A V D^(-1/2) (orthonormal
@@ -151,6 +196,14 @@ template <typename T> void launch_q2_select_e(Ctx2<T>* d_ctx, int n, int splitsH
 template <typename T> void launch_q2_gamma(Ctx2<T>* d_ctx, int n, hipStream_t s);
 template <typename T> void launch_q2_select_g(Ctx2<T>* d_ctx, int n, int splitsC, TruncParams tp, hipStream_t s);
 template <typename T> void launch_q2_select_b(Ctx2<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
+
+template <typename T> void launch_q3_prepare(Ctx3<T>* d_ctx, int n, int splitsH, hipStream_t s);
+template <typename T> void launch_q3_apply(Ctx3<T>* d_ctx, int n, hipStream_t s);
+template <typename T> void launch_q3_select_h(Ctx3<T>* d_ctx, int n, int splitsG, TruncParams tp, hipStream_t s);
+template <typename T> void launch_q3_scale1(Ctx3<T>* d_ctx, int n, hipStream_t s);
+template <typename T> void launch_q3_select_1(Ctx3<T>* d_ctx, int n, int splitsG, TruncParams tp, hipStream_t s);
+template <typename T> void launch_q3_scale2(Ctx3<T>* d_ctx, int n, hipStream_t s);
+template <typename T> void launch_q3_select_2(Ctx3<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
 
 template <typename T> void launch_sw_prepare(CtxS<T>* d_ctx, int n, int splits, hipStream_t s);
 template <typename T> void launch_sw_select(CtxS<T>* d_ctx, int n, TruncParams tp, hipStream_t s);

@@ -495,6 +495,296 @@ __global__ __launch_bounds__(GT) void k_q2_select_b(Ctx2<T>* ctxs, TruncParams t
 }
 
 // ============================================================================
+// three-site noisy gate
+// ============================================================================
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_prepare(Ctx3<T>* ctxs, int splitsH) {
+  __shared__ cpx<double> sU[64];
+  Ctx3<T>& c = ctxs[blockIdx.x];
+  build_G(c.g, c.kraus, c.m, c.G, sU);
+  if (threadIdx.x != 0) return;
+  const int cl = *c.chil, c1 = *c.chim1, c2 = *c.chim2, cr = *c.chir;
+  const int k1 = *c.kap1, k2 = *c.kap2, k3 = *c.kap3;
+  const int inner = 2 * k3 * cr;
+  {  // X[(c1 t2 k2), (t3 k3 r)] = B_{i+1} B_{i+2}
+    GemmDesc& d = *c.dX;
+    clear_desc(d);
+    d.A = c.Bj; d.B = c.Bk; d.C = c.X;
+    d.M = c1 * 2 * k2; d.K = c2; d.N = inner;
+    d.lda = c2; d.ldb = inner; d.ldc = inner;
+  }
+  {  // Phi[(l t1 k1), (t2 k2 t3 k3 r)] = B_i X
+    GemmDesc& d = *c.dPhi;
+    clear_desc(d);
+    d.A = c.Bi; d.B = c.X; d.C = c.Phi;
+    d.M = cl * 2 * k1; d.K = c1; d.N = 2 * k2 * inner;
+    d.lda = c1; d.ldb = 2 * k2 * inner; d.ldc = 2 * k2 * inner;
+  }
+  {  // H[a][b] = sum_{l s1 k1 s2, s3 k3 r} lambda_l^2 conj(Psi) Psi, a = (k2 j)
+    GemmDesc& d = *c.dH;
+    void* C = d.C;
+    const long long ss = d.sSplit;
+    clear_desc(d);
+    d.C = C; d.sSplit = ss;
+    const int n = k2 * c.m;
+    if (c.m <= 1) {
+      d.active = 0;
+      c.dEH->active = 0;
+    } else {
+      d.A = c.Psi; d.B = c.Psi; d.opA = OP_C; d.opB = OP_T;
+      d.M = d.N = n;
+      d.K = cl * 4 * k1 * inner;
+      d.lda = d.ldb = inner;
+      d.kinner = inner;
+      d.kstride = (long long)n * inner;
+      d.w = c.laml2; d.wdiv = 4 * k1 * inner;
+      d.ldc = n;
+      d.splits = splitsH;
+      EigDesc& e = *c.dEH;
+      e.lda = n; e.n = n; e.evals = c.evH; e.evecs = c.vecH; e.trace = c.evH + n; e.active = 1;
+    }
+  }
+}
+
+// Psi[(l s1 k1), (s2 (k2 j) s3 k3 r)] = sum_t G_j[(s1 s2 s3), (t1 t2 t3)] Phi[(l t1 k1), (t2 k2 t3 k3 r)]
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_apply(Ctx3<T>* ctxs) {
+  Ctx3<T>& c = ctxs[blockIdx.y];
+  const int cl = *c.chil, cr = *c.chir, k1 = *c.kap1, k2 = *c.kap2, k3 = *c.kap3, m = c.m;
+  const int kr = k3 * cr, inner = 2 * kr, km = k2 * m;
+  const long long total = (long long)cl * 2 * k1 * 2 * km * inner;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    long long rest = e;
+    const int in = (int)(rest % inner); rest /= inner;
+    const int a = (int)(rest % km); rest /= km;
+    const int s2 = (int)(rest % 2); rest /= 2;
+    const int kk1 = (int)(rest % k1); rest /= k1;
+    const int s1 = (int)(rest % 2);
+    const long long l = rest / 2;
+    const int kk2 = a / m, j = a % m;
+    const int s3 = in / kr, krr = in % kr;
+    const int srow = s1 * 4 + s2 * 2 + s3;
+    cpx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int t1 = t >> 2, t2 = (t >> 1) & 1, t3 = t & 1;
+      const long long pi = ((l * 2 + t1) * k1 + kk1) * (2LL * k2 * inner) + (long long)(t2 * k2 + kk2) * inner +
+                           t3 * kr + krr;
+      const cpx<T> ph = c.Phi[pi];
+      acc = acc + ld(c.G, ((long long)j * 8 + srow) * 8 + t) * mk((double)ph.re, (double)ph.im);
+    }
+    c.Psi[e] = mk<T>((T)acc.re, (T)acc.im);
+  }
+}
+
+// kappa' and the projection of the middle inner index; descriptor of the Gram G1
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_select_h(Ctx3<T>* ctxs, int splitsG, TruncParams tp) {
+  __shared__ int s_kp;
+  __shared__ double s_scale;
+  Ctx3<T>& c = ctxs[blockIdx.x];
+  const int cl = *c.chil, cr = *c.chir, k1 = *c.kap1, k2 = *c.kap2, k3 = *c.kap3, m = c.m;
+  const int inner = 2 * k3 * cr, n = k2 * m;
+  if (threadIdx.x == 0) {
+    if (m <= 1) {
+      s_kp = k2;
+      s_scale = 1.0;
+    } else {
+      double kept, tot;
+      const int kp = select_rank(c.evH, min(n, tp.kap_max + 1), n, c.evH[n], tp.kap_max, tp.kap_cut, &kept, &tot);
+      s_kp = kp;
+      s_scale = 1.0 / sqrt(kept);
+      if (tot > 0) *c.disc += (tot - kept) / tot;
+    }
+    c.scratch[0] = s_kp;
+  }
+  __syncthreads();
+  const int kp = s_kp;
+  const double sc = s_scale;
+  for (int e = threadIdx.x; e < n * kp; e += blockDim.x) {
+    const int a = e / kp, nu = e % kp;
+    cpx<double> v = mk(0.0, 0.0);
+    if (m <= 1) {
+      if (a == nu) v = mk(1.0, 0.0);
+    } else {
+      v = ld(c.vecH, (long long)a * n + nu);
+    }
+    c.P[e] = mk<T>((T)(v.re * sc), (T)(v.im * sc));
+  }
+  if (threadIdx.x == 0) {
+    {  // Psi2[o] = P^T Psi[o] for every o = (l s1 k1 s2)
+      GemmDesc& d = *c.dProj;
+      clear_desc(d);
+      d.A = c.P; d.B = c.Psi; d.C = c.Psi2;
+      d.opA = OP_T;
+      d.M = kp; d.K = n; d.N = inner;
+      d.lda = kp; d.ldb = inner; d.ldc = inner;
+      d.nbatch = cl * 4 * k1;
+      d.sA = 0; d.sB = (long long)n * inner; d.sC = (long long)kp * inner;
+    }
+    {  // G1 = Psi2 Psi2^H over rows (l s1 k1)
+      GemmDesc& d = *c.dG1;
+      void* C = d.C;
+      const long long ss = d.sSplit;
+      clear_desc(d);
+      d.C = C; d.sSplit = ss;
+      d.A = c.Psi2; d.B = c.Psi2; d.opA = OP_N; d.opB = OP_H;
+      d.M = d.N = cl * 2 * k1;
+      d.K = 2 * kp * inner;
+      d.lda = d.ldb = 2 * kp * inner;
+      d.ldc = cl * 2 * k1;
+      d.splits = splitsG;
+    }
+  }
+}
+
+// G1[x][y] *= lambda_l(x) lambda_l(y); eigensolver descriptor
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_scale1(Ctx3<T>* ctxs) {
+  Ctx3<T>& c = ctxs[blockIdx.x];
+  const int k1 = *c.kap1, n = *c.chil * 2 * k1;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int x = e / n, y = e % n;
+    const double f = sqrt(c.laml2[x / (2 * k1)] * c.laml2[y / (2 * k1)]);
+    c.G1[2 * e] *= f;
+    c.G1[2 * e + 1] *= f;
+  }
+  if (threadIdx.x == 0) {
+    EigDesc& e = *c.dE1;
+    e.a = c.G1; e.lda = n; e.n = n; e.evals = c.ev1; e.evecs = c.vec1; e.trace = c.ev1 + n; e.active = 1;
+  }
+}
+
+// bond i: rank, weights, T_i = lambda^-1 U S / sqrt(kept), V1 = S^-1 U^H (lambda Psi2); descriptor of G2
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_select_1(Ctx3<T>* ctxs, int splitsG, TruncParams tp) {
+  __shared__ int s_r;
+  __shared__ double s_kept;
+  Ctx3<T>& c = ctxs[blockIdx.x];
+  const int k1 = *c.kap1, n = *c.chil * 2 * k1;
+  const int kp = c.scratch[0], inner = 2 * (*c.kap3) * (*c.chir);
+  if (threadIdx.x == 0) {
+    double kept, tot;
+    const int r = select_rank(c.ev1, min(n, tp.chi_max + 1), n, c.ev1[n], tp.chi_max, tp.svd_cut, &kept, &tot);
+    s_r = r;
+    s_kept = kept;
+    if (tot > 0) *c.disc += (tot - kept) / tot;
+    c.scratch[1] = r;
+  }
+  __syncthreads();
+  const int r = s_r;
+  const double kept = s_kept;
+  for (int v = threadIdx.x; v < r; v += blockDim.x) {
+    const double e = c.ev1[v] > 0 ? c.ev1[v] : 0.0;
+    c.lam1[v] = sqrt(e / kept);
+    c.lam1sq[v] = e / kept;
+  }
+  // Q1 = Lambda U S^-1 (for V1) and T_i = Lambda^-1 U S / sqrt(kept), both from
+  // the FP64 eigenvectors: forming T_i as Psi2 V1^H would carry the rounding of
+  // V1's small-sigma rows (relative eps / sigma) into unweighted columns.
+  const double isk = 1.0 / sqrt(kept);
+  for (int e = threadIdx.x; e < n * r; e += blockDim.x) {
+    const int x = e / r, rho = e % r;
+    const cpx<double> u = ld(c.vec1, (long long)x * n + rho);
+    const double ll = sqrt(c.laml2[x / (2 * k1)]), s = sqrt(c.ev1[rho]);
+    const double f = ll / s, g = s / ll * isk;
+    c.Q1[e] = mk<T>((T)(u.re * f), (T)(u.im * f));
+    c.Bi_new[e] = mk<T>((T)(u.re * g), (T)(u.im * g));
+  }
+  if (threadIdx.x == 0) {
+    const int n2cols = 2 * kp * inner;
+    {
+      GemmDesc& d = *c.dV1;
+      clear_desc(d);
+      d.A = c.Q1; d.B = c.Psi2; d.C = c.V1;
+      d.opA = OP_H;
+      d.M = r; d.K = n; d.N = n2cols;
+      d.lda = r; d.ldb = n2cols; d.ldc = n2cols;
+    }
+    {
+      GemmDesc& d = *c.dG2;
+      void* C = d.C;
+      const long long ss = d.sSplit;
+      clear_desc(d);
+      d.C = C; d.sSplit = ss;
+      d.A = c.V1; d.B = c.V1; d.opA = OP_N; d.opB = OP_H;
+      d.M = d.N = r * 2 * kp;
+      d.K = inner;
+      d.lda = d.ldb = inner;
+      d.ldc = r * 2 * kp;
+      d.splits = splitsG;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_scale2(Ctx3<T>* ctxs) {
+  Ctx3<T>& c = ctxs[blockIdx.x];
+  const int kp = c.scratch[0], r = c.scratch[1], n = r * 2 * kp;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int x = e / n, y = e % n;
+    const double f = c.lam1[x / (2 * kp)] * c.lam1[y / (2 * kp)];
+    c.G2[2 * e] *= f;
+    c.G2[2 * e + 1] *= f;
+  }
+  if (threadIdx.x == 0) {
+    EigDesc& e = *c.dE2;
+    e.a = c.G2; e.lda = n; e.n = n; e.evals = c.ev2; e.evecs = c.vec2; e.trace = c.ev2 + n; e.active = 1;
+  }
+}
+
+// bond i+1: rank, weights, T_{i+1} = lambda'^-1 U2 S2 / sqrt(kept), T_{i+2} = S2^-1 U2^H (lambda' V1)
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_select_2(Ctx3<T>* ctxs, TruncParams tp) {
+  __shared__ int s_r;
+  __shared__ double s_kept;
+  Ctx3<T>& c = ctxs[blockIdx.x];
+  const int kp = c.scratch[0], r1 = c.scratch[1], n = r1 * 2 * kp;
+  const int inner = 2 * (*c.kap3) * (*c.chir);
+  if (threadIdx.x == 0) {
+    double kept, tot;
+    const int r = select_rank(c.ev2, min(n, tp.chi_max + 1), n, c.ev2[n], tp.chi_max, tp.svd_cut, &kept, &tot);
+    s_r = r;
+    s_kept = kept;
+    if (tot > 0) *c.disc += (tot - kept) / tot;
+    c.scratch[2] = r;
+  }
+  __syncthreads();
+  const int r = s_r;
+  const double kept = s_kept;
+  for (int v = threadIdx.x; v < r; v += blockDim.x) {
+    const double e = c.ev2[v] > 0 ? c.ev2[v] : 0.0;
+    c.lam2[v] = sqrt(e / kept);
+    c.lam2sq[v] = e / kept;
+  }
+  // Q2 = lambda' U2 S2^-1 (for T_{i+2}) and T_{i+1} = lambda'^-1 U2 S2 / sqrt(kept)
+  const double isk = 1.0 / sqrt(kept);
+  for (int e = threadIdx.x; e < n * r; e += blockDim.x) {
+    const int y = e / r, rho = e % r;
+    const cpx<double> u = ld(c.vec2, (long long)y * n + rho);
+    const double l1 = c.lam1[y / (2 * kp)], s = sqrt(c.ev2[rho]);
+    const double f = l1 / s, g = s / l1 * isk;
+    c.Q2[e] = mk<T>((T)(u.re * f), (T)(u.im * f));
+    c.Bj_new[e] = mk<T>((T)(u.re * g), (T)(u.im * g));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    {
+      GemmDesc& d = *c.dTk;
+      clear_desc(d);
+      d.A = c.Q2; d.B = c.V1; d.C = c.Bk_new;
+      d.opA = OP_H;
+      d.M = r; d.K = n; d.N = inner;
+      d.lda = r; d.ldb = inner; d.ldc = inner;
+    }
+    *c.chim1 = r1;
+    *c.chim2 = r;
+    *c.kap2 = kp;
+  }
+}
+
+// ============================================================================
 // truncation sweep (Sec. II.D)
 // ============================================================================
 template <typename T>
@@ -815,6 +1105,27 @@ template <typename T> void launch_q2_select_g(Ctx2<T>* d, int n, int splitsC, Tr
 template <typename T> void launch_q2_select_b(Ctx2<T>* d, int n, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_select_b<T>, dim3(n), dim3(GT), 0, s, d, tp);
 }
+template <typename T> void launch_q3_prepare(Ctx3<T>* d, int n, int splitsH, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsH);
+}
+template <typename T> void launch_q3_apply(Ctx3<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_apply<T>, dim3(1024, n), dim3(GT), 0, s, d);
+}
+template <typename T> void launch_q3_select_h(Ctx3<T>* d, int n, int splitsG, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_select_h<T>, dim3(n), dim3(GT), 0, s, d, splitsG, tp);
+}
+template <typename T> void launch_q3_scale1(Ctx3<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_scale1<T>, dim3(n), dim3(GT), 0, s, d);
+}
+template <typename T> void launch_q3_select_1(Ctx3<T>* d, int n, int splitsG, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_select_1<T>, dim3(n), dim3(GT), 0, s, d, splitsG, tp);
+}
+template <typename T> void launch_q3_scale2(Ctx3<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_scale2<T>, dim3(n), dim3(GT), 0, s, d);
+}
+template <typename T> void launch_q3_select_2(Ctx3<T>* d, int n, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_select_2<T>, dim3(n), dim3(GT), 0, s, d, tp);
+}
 template <typename T> void launch_sw_prepare(CtxS<T>* d, int n, int splits, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_sw_prepare<T>, dim3(n), dim3(GT), 0, s, d, splits);
 }
@@ -857,6 +1168,13 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_q2_gamma<T>(Ctx2<T>*, int, hipStream_t);                               \
   template void launch_q2_select_g<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_select_b<T>(Ctx2<T>*, int, TruncParams, hipStream_t);              \
+  template void launch_q3_prepare<T>(Ctx3<T>*, int, int, hipStream_t);                        \
+  template void launch_q3_apply<T>(Ctx3<T>*, int, hipStream_t);                               \
+  template void launch_q3_select_h<T>(Ctx3<T>*, int, int, TruncParams, hipStream_t);          \
+  template void launch_q3_scale1<T>(Ctx3<T>*, int, hipStream_t);                              \
+  template void launch_q3_select_1<T>(Ctx3<T>*, int, int, TruncParams, hipStream_t);          \
+  template void launch_q3_scale2<T>(Ctx3<T>*, int, hipStream_t);                              \
+  template void launch_q3_select_2<T>(Ctx3<T>*, int, TruncParams, hipStream_t);               \
   template void launch_sw_prepare<T>(CtxS<T>*, int, int, hipStream_t);                        \
   template void launch_sw_select<T>(CtxS<T>*, int, TruncParams, hipStream_t);                 \
   template void launch_sw_normalize<T>(CtxS<T>*, int, hipStream_t);                           \

@@ -279,6 +279,10 @@ def program_ops(prog, fixed: List[np.ndarray], fixed_index: dict, use_params: bo
             o.kind = _PARAM_KINDS[op.kind][0]
             o.param = op.param
             o.scale = float(op.pscale)
+        elif q == 3:  # three-site ops in batch runs: the channel alone
+            if not np.allclose(op.U, np.eye(8)):
+                raise ValueError("batch runs take 3-site ops without a gate matrix")
+            o.kind, o.fixed = G_FIXED, -1
         else:
             o.kind = G_FIXED
             U = np.asarray(op.U, dtype=np.complex128)

@@ -91,3 +91,20 @@ def test_profile_read_rejects_unknown_class():
     L = M.lib()
     assert L.mpdo_profile_read(-1, None, None, None, None) == M.EINVAL
     assert L.mpdo_profile_read(4, None, None, None, None) == M.EINVAL
+
+
+@pytest.mark.parametrize("q,kind,fixed,chi,status", [(3, 0, 0, 16, M.EINVAL), (3, 1, -1, 16, M.EINVAL),
+                                                     (4, 0, -1, 16, M.EINVAL), (3, 0, -1, 128, M.EUNSUPPORTED),
+                                                     (2, 0, -2, 16, M.EINVAL)])
+def test_batch_run_validates_op_arity(q, kind, fixed, chi, status):
+    """Three-site ops in batch runs are channels without a gate matrix; the
+    call fails before touching the device."""
+    cfg = M.mpdo_config(6, chi, 4, 16, 1e-10, 1e-14, 0)
+    ops = (M.mpdo_op * 1)()
+    ops[0].q, ops[0].site, ops[0].kind, ops[0].param, ops[0].scale, ops[0].chan, ops[0].fixed = (
+        q, 0, kind, -1, 1.0, -1, fixed)
+    prog = (M.mpdo_program * 1)()
+    prog[0].n, prog[0].nops, prog[0].ops, prog[0].nobs = 6, 1, ops, 0
+    u = np.eye(4, dtype=complex).view(np.float64).copy()
+    st = M.lib().mpdo_batch_run(ctypes.byref(cfg), prog, 1, None, 0, M._dptr(u), 1, None, 0, None, 0, None)
+    assert st == status, M.lib().mpdo_last_error()
