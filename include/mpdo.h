@@ -62,10 +62,12 @@ typedef enum {
 
 typedef struct {
   int32_t n;              /* qubits (sites), 1 <= n <= 64                     */
-  int32_t chi_max;        /* bond dimension limit chi (Sec. II.D), >= 1       */
-  int32_t kappa_max;      /* inner (noise) dimension limit kappa (Eq. (10))   */
+  int32_t chi_max;        /* bond dimension limit chi (Sec. II.D), 1..128     */
+  int32_t kappa_max;      /* inner (noise) dimension limit kappa (Eq. (10)),
+                             1..64                                            */
   int32_t max_kraus;      /* largest Kraus count of any channel that will be
-                             applied (sizes the workspace), >= 1              */
+                             applied (sizes the workspace), >= 1;
+                             kappa_max * max_kraus <= 1024                    */
   double svd_cutoff;      /* bond truncation: drop the smallest singular
                              values whose summed squares are <= cutoff times
                              the total, then cap at chi_max                   */
@@ -111,8 +113,7 @@ mpdo_status mpdo_channel_destroy(mpdo_chan_t ch);
 
 /* Apply the ideal gate U (host, 2^q x 2^q complex) on `sites` (q ascending
  * adjacent sites, q in {1, 2, 3}).  A 2- or 3-qubit gate re-splits the block
- * by SVD with bond truncation.  3-site gates (ideal or noisy) need
- * 2 kappa_max chi_max <= 512, else MPDO_EUNSUPPORTED. */
+ * by SVD with bond truncation. */
 mpdo_status mpdo_apply_gate(mpdo_t h, const int32_t* sites, int32_t q, const double* U);
 
 /* Apply the noisy gate "U then channel": operators G_i = K_i U (Eq. (8));
@@ -205,8 +206,7 @@ typedef struct {
  * descriptor upload, every sublayer, the observables) into one HIP graph and
  * launches it once; with hip_stream NULL a private stream is used for the
  * capture.  The call returns when the results are in out_dev.  Returns
- * EINVAL for malformed programs, EUNSUPPORTED for 3-site ops when
- * 2 kappa_max chi_max > 512. */
+ * EINVAL for malformed programs. */
 mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
                            const double* params_dev, int32_t param_stride,
                            const double* fixed_u, int32_t nfixed,

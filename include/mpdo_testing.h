@@ -31,7 +31,7 @@ mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, in
                            int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha, double* C,
                            int32_t tile);
 
-/* Hermitian eigendecomposition of A (n x n, 1 <= n <= 512) with the
+/* Hermitian eigendecomposition of A (n x n, 1 <= n <= 1024) with the
  * library's eigensolver: the leading min(n, kvec + 1) eigenvalues in
  * descending order in evals (the rest of the n entries zero), the
  * eigenvectors of the leading kvec eigenvalues as the first kvec columns of

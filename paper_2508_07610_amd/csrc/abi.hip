@@ -63,7 +63,7 @@ const char* check_config(const mpdo_config* cfg, bool need_n) {
   if (cfg->chi_max < 1 || cfg->chi_max > 128) return "chi_max must be in [1, 128]";
   if (cfg->kappa_max < 1 || cfg->kappa_max > 64) return "kappa_max must be in [1, 64]";
   if (cfg->max_kraus < 1 || cfg->max_kraus > 64) return "max_kraus must be in [1, 64]";
-  if ((long long)cfg->kappa_max * cfg->max_kraus > 512) return "kappa_max * max_kraus must be <= 512";
+  if ((long long)cfg->kappa_max * cfg->max_kraus > EIG_NMAX) return "kappa_max * max_kraus must be <= 1024";
   if (!(cfg->svd_cutoff >= 0 && cfg->svd_cutoff < 1)) return "svd_cutoff must be in [0, 1)";
   if (!(cfg->kappa_cutoff >= 0 && cfg->kappa_cutoff < 1)) return "kappa_cutoff must be in [0, 1)";
   if (cfg->prec != MPDO_C128 && cfg->prec != MPDO_C64_MIXED) return "prec must be MPDO_C128 or MPDO_C64_MIXED";
@@ -236,8 +236,6 @@ static mpdo_status enqueue(mpdo_t h, const int32_t* sites, int32_t q, const doub
   }
   if (ch && ch->ch.q != q) return fail(MPDO_EINVAL, "channel arity differs from the number of sites");
   if (ch && ch->ch.m > h->cfg.max_kraus) return fail(MPDO_EINVAL, "channel has more Kraus operators than max_kraus");
-  if (q == 3 && 2LL * h->cfg.kappa_max * h->cfg.chi_max > 512)
-    return fail(MPDO_EUNSUPPORTED, "3-site gates need 2 kappa_max chi_max <= 512");
   const int d = 1 << q;
   if (U) {
     for (int e = 0; e < 2 * d * d; ++e)
@@ -499,8 +497,6 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
       if (o.q < 1 || o.q > 3) return fail(MPDO_EINVAL, "op arity must be 1, 2 or 3");
       if (o.q == 3 && (o.kind != MPDO_G_FIXED || o.fixed != -1))
         return fail(MPDO_EINVAL, "3-site ops carry no gate matrix (kind MPDO_G_FIXED, fixed = -1)");
-      if (o.q == 3 && 2LL * cfg->kappa_max * cfg->chi_max > 512)
-        return fail(MPDO_EUNSUPPORTED, "3-site ops need 2 kappa_max chi_max <= 512");
       if (o.site < 0 || o.site + o.q > p.n) return fail(MPDO_EINVAL, "op site out of range");
       const bool k1 = o.kind == MPDO_G_RX || o.kind == MPDO_G_RY || o.kind == MPDO_G_RZ;
       const bool k2 = o.kind == MPDO_G_ZZPHASE || o.kind == MPDO_G_SWAPZZ;
@@ -679,7 +675,7 @@ extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, in
 
 extern "C" mpdo_status mpdo_test_eigh(int32_t n, int32_t kvec, const double* A, double* evals, double* evecs,
                                       double* trace) {
-  if (n < 1 || n > 512) return fail(MPDO_EINVAL, "n must be in [1, 512]");
+  if (n < 1 || n > EIG_NMAX) return fail(MPDO_EINVAL, "n must be in [1, 1024]");
   if (kvec < 0) return fail(MPDO_EINVAL, "kvec must be >= 0");
   if (!A || !evals || !evecs) return fail(MPDO_EINVAL, "null buffer");
   GUARD_BEGIN

@@ -51,14 +51,15 @@ struct GemmDesc {
   double alpha;
 };
 
-// A Hermitian eigenproblem of size n (1 <= n <= 512).  The matrix at `a`
+// A Hermitian eigenproblem of size n (1 <= n <= EIG_NMAX).  The matrix at `a`
 // (n x n, row-major, leading dimension lda, complex double) is read only.
 // The leading kb = min(n, kvec + 1) eigenvalues are written in descending
 // order to evals[0..kb) (the rest of evals[0..n) is set to zero), *trace
 // receives Tr(A), and the eigenvectors of the leading kvec eigenvalues are
 // written as the columns of `evecs` (n x kvec used of an n x n array with
 // leading dimension n).  Eigenvectors of eigenvalues at or below
-// EIG_FLOOR * evals[0] are returned as zero (numerical null space).
+// vfloor * evals[0] (EIG_FLOOR when vfloor is 0) are returned as zero
+// (numerical null space).
 // `work` must hold eig_work_doubles(n) doubles.
 struct EigDesc {
   double* a;
@@ -66,12 +67,14 @@ struct EigDesc {
   double* evecs;
   double* work;
   double* trace;
+  double vfloor;  // relative floor of the returned vectors; 0: EIG_FLOOR
   int n, lda;
   int kvec;
   int active;
 };
 
 constexpr double EIG_FLOOR = 1e-13;
+constexpr int EIG_NMAX = 1024;
 constexpr int EIG_THREADS = 512;
 
 // matrix (2 n^2) + two n x np solve vectors + five n x np factor arrays

@@ -78,24 +78,25 @@ __device__ inline double start_entry(int j, int i) {
   return (double)(h & 0xFFFFFF) / (double)0x800000 - 1.0;
 }
 
-struct alignas(16) Shared {
-  alignas(16) cpx<double> tau[512];
-  alignas(16) cpx<double> v[512];              // reflector of the current step
-  alignas(16) cpx<double> vp[512];             // pending rank-2 update of the previous step
-  alignas(16) cpx<double> wp[512];
-  alignas(16) cpx<double> pp[NT];              // partial products (row chunk, column)
-  double d[512], e[512], e2[512];
-  double ev[513];
+// Workgroup state of the global-memory solver for n <= NMAX.
+template <int NMAX> struct alignas(16) SharedG {
+  alignas(16) cpx<double> tau[NMAX];
+  alignas(16) cpx<double> v[NMAX];             // reflector of the current step
+  alignas(16) cpx<double> vp[NMAX];            // pending rank-2 update of the previous step
+  alignas(16) cpx<double> wp[NMAX];
+  alignas(16) cpx<double> pp[NMAX > NT ? NMAX : NT];  // partial products (row chunk, column)
+  double d[NMAX], e[NMAX], e2[NMAX];
+  double ev[NMAX + 1];
   double red[2 * NW];
   double scal[4];
   int flag[4];
-  int clus[513];
+  int clus[NMAX + 1];
 };
 
 // Pending update (vp, wp; index 0 = row `base`) on rows/cols [c0, n) and,
 // if `act`, p = A22 v (v indexed from c0) into S.pp[0..m).
-__device__ void fused_pass(cpx<double>* __restrict__ A, int n, int c0, int base, bool pend, bool act,
-                           Shared& S) {
+template <class SH>
+__device__ void fused_pass(cpx<double>* __restrict__ A, int n, int c0, int base, bool pend, bool act, SH& S) {
   const int m = n - c0;
   if (m <= 0) return;
   int nq = NT / m;
@@ -148,7 +149,7 @@ __device__ void fused_pass(cpx<double>* __restrict__ A, int n, int c0, int base,
   __syncthreads();
   if (act && nq > 1) {
     cpx<double> s[1];
-    for (int cl = tid; cl < m; cl += NT) {  // m <= 512 < NT: one column per thread
+    for (int cl = tid; cl < m; cl += NT) {  // nq > 1 means m <= NT / 2: one column per thread
       cpx<double> a = S.pp[cl];
       for (int q = 1; q < nq; ++q) a = a + S.pp[q * m + cl];
       s[0] = a;
@@ -213,7 +214,7 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   for (int j = tid; j < n; j += NTH) dsc.evals[j] = j < kb ? S.ev[j] : 0.0;
   if (tid == 0 && dsc.trace) *dsc.trace = tr;
   if (kvec <= 0) return 0;
-  const double floorv = EIG_FLOOR * S.ev[0];
+  const double floorv = (dsc.vfloor > 0 ? dsc.vfloor : EIG_FLOOR) * S.ev[0];
   int kz = 0;  // vectors above the numerical-zero floor (a leading block)
   while (kz < kvec && S.ev[kz] > floorv && S.ev[0] > 0) ++kz;
   cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
@@ -333,24 +334,42 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   }
   __syncthreads();
   // ---- 5. Gram-Schmidt (twice) inside clusters of close eigenvalues ----
+  // Inverse iteration leaves vectors of eigenvalues closer than about
+  // eps ||T|| / gap non-orthogonal, so a cluster joins eigenvalues whose gap
+  // is below 1e-6 of their size or below 1e-10 of the largest.  Each vector
+  // is orthogonalised against the earlier members of its cluster in two
+  // blocked passes (one dot product per wave, then one update per row).
   if (tid == 0) {
     int c = 0;
+    const double agap = 1e-10 * fabs(S.ev[0]);
     for (int j = 0; j < kz; ++j) {
-      if (j > 0 && S.ev[j - 1] - S.ev[j] > 1e-6 * fabs(S.ev[j - 1])) ++c;
+      if (j > 0 && S.ev[j - 1] - S.ev[j] > fmax(1e-6 * fabs(S.ev[j - 1]), agap)) ++c;
       S.clus[j] = c;
     }
   }
   __syncthreads();
-  for (int j = 1; j < kz; ++j) {
-    if (S.clus[j] != S.clus[j - 1]) continue;  // uniform across the block
-    int i0 = j - 1;
-    while (i0 > 0 && S.clus[i0 - 1] == S.clus[j]) --i0;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int i = i0; i < j; ++i) {
-        double s = 0;
-        for (int r = tid; r < n; r += NTH) s += Z[(long long)r * n + i].re * Z[(long long)r * n + j].re;
-        s = block_sum<NTH>(s, S.red, par);
-        for (int r = tid; r < n; r += NTH) Z[(long long)r * n + j].re -= s * Z[(long long)r * n + i].re;
+  {
+    double* dots = reinterpret_cast<double*>(&S.pp);  // free after the tridiagonalisation
+    constexpr int NWV = NTH / 64;
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int j = 1; j < kz; ++j) {
+      if (S.clus[j] != S.clus[j - 1]) continue;  // uniform across the block
+      int i0 = j - 1;
+      while (i0 > 0 && S.clus[i0 - 1] == S.clus[j]) --i0;
+      const int cnt = j - i0;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int ib = wave; ib < cnt; ib += NWV) {
+          double s = 0;
+          for (int r = lane; r < n; r += 64) s += Z[(long long)r * n + i0 + ib].re * Z[(long long)r * n + j].re;
+          for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+          if (lane == 0) dots[ib] = s;
+        }
+        __syncthreads();
+        for (int r = tid; r < n; r += NTH) {
+          double a = Z[(long long)r * n + j].re;
+          for (int i = 0; i < cnt; ++i) a -= dots[i] * Z[(long long)r * n + i0 + i].re;
+          Z[(long long)r * n + j].re = a;
+        }
         __syncthreads();
       }
       double nn = 0;
@@ -364,7 +383,8 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   return kz;
 }
 
-__device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, Shared& S) {
+template <class SH>
+__device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S) {
   const int n = dsc.n, tid = threadIdx.x;
   int par = 0;  // block_sum buffer parity
   // ---- 1. load (symmetrised) ----
@@ -765,9 +785,18 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
 
 // n in (128, 512]: the matrix in global memory (L2-resident).
 __global__ __launch_bounds__(NT) void k_heev_global(const EigDesc* __restrict__ descs, int* __restrict__ status) {
-  __shared__ Shared S;
+  __shared__ SharedG<512> S;
   const EigDesc& d = descs[blockIdx.x];
   if (!d.active || d.n <= RN || d.n > 512) return;
+  heev_core(d, reinterpret_cast<cpx<double>*>(d.work), S);
+  if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
+}
+
+// n in (512, 1024]: as above with the larger workgroup state.
+__global__ __launch_bounds__(NT) void k_heev_big(const EigDesc* __restrict__ descs, int* __restrict__ status) {
+  __shared__ SharedG<EIG_NMAX> S;
+  const EigDesc& d = descs[blockIdx.x];
+  if (!d.active || d.n <= 512 || d.n > EIG_NMAX) return;
   heev_core(d, reinterpret_cast<cpx<double>*>(d.work), S);
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
@@ -781,6 +810,11 @@ void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hi
     tok = prof_begin(PC_EIG_GLOBAL, s);
     hipLaunchKernelGGL(k_heev_global, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
     prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, RN + 1, 512, s);
+  }
+  if (maxn > 512) {
+    tok = prof_begin(PC_EIG_GLOBAL, s);
+    hipLaunchKernelGGL(k_heev_big, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
+    prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, 513, EIG_NMAX, s);
   }
 }
 

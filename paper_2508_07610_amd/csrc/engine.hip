@@ -581,47 +581,54 @@ template <typename T> std::vector<double> Engine<T>::bond_weights(int b, int bon
   return v;
 }
 
-// Three-site noisy gates (see Ctx3).  Requires 2 kap_max chi_max <= 512 (the
-// Gram matrices of the two splits) and kap_max max_kraus <= 512.
+// Three-site noisy gates (see Ctx3).  Requires kap_max m <= EIG_NMAX (the
+// Gamma eigenproblem of the middle inner index); every other eigenproblem has
+// size at most 4 chi_max.
 template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& ops, Upload& up) {
   const int n = (int)ops.size();
   if (n == 0) return;
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
   int m3 = 1;
   for (auto* g : ops) m3 = std::max(m3, g->ch ? g->ch->m : 1);
-  const int rowsL = 2 * kx * cx;             // (l t k) and (r1 s nu) bound
-  const long long innerX = (long long)2 * kx * cx;
-  const int kmm = kx * m3;
-  if (rowsL > 512 || kmm > 512)
-    throw Error{6 /*MPDO_EUNSUPPORTED*/, "3-site channels need 2 kappa_max chi_max <= 512 and kappa_max m <= 512"};
-  const int splitsH = splits_for((long long)cx * 4 * kx * innerX);
-  const int splitsG = splits_for((long long)2 * kx * innerX);
+  const int ng = kx * m3;
+  if (ng > EIG_NMAX)
+    throw Error{6 /*MPDO_EUNSUPPORTED*/, "3-site channels need kappa_max * (Kraus operators) <= 1024"};
+  const int n2 = 2 * cx, n4 = 4 * cx, nh = 8 * kx;
+  const size_t sT = sizeof(cpx<T>);
+  const int spN = splits_for((long long)cx * kx), spE = splits_for((long long)kx * cx);
+  const int spH = splits_for((long long)n2 * n2), spC1 = splits_for((long long)nh * n2);
+  const int spC2 = splits_for((long long)cx * 2 * kx);
   Layout w;
   const size_t oG = w.add((size_t)m3 * 64 * 16);
-  const size_t oX = w.add((size_t)rowsL * innerX * sizeof(cpx<T>));
-  const size_t oPhi = w.add((size_t)rowsL * 2 * kx * innerX * sizeof(cpx<T>));
-  const size_t oPsi = w.add((size_t)rowsL * 2 * kmm * innerX * sizeof(cpx<T>));
-  const size_t oPsi2 = w.add((size_t)rowsL * 2 * kx * innerX * sizeof(cpx<T>));
-  const size_t oH = w.add((size_t)kmm * kmm * 16);
-  const size_t oHp = w.add((size_t)splitsH * kmm * kmm * 16);
-  const size_t oEvH = w.add((size_t)(kmm + 1) * 8);
-  const size_t oVecH = w.add((size_t)kmm * kmm * 16);
-  const size_t oWkH = w.add((size_t)eig_work_doubles(kmm) * 8);
-  const size_t oP = w.add((size_t)kmm * kx * sizeof(cpx<T>));
-  const size_t oG1 = w.add((size_t)rowsL * rowsL * 16);
-  const size_t oG1p = w.add((size_t)splitsG * rowsL * rowsL * 16);
-  const size_t oEv1 = w.add((size_t)(rowsL + 1) * 8);
-  const size_t oVec1 = w.add((size_t)rowsL * rowsL * 16);
-  const size_t oWk1 = w.add((size_t)eig_work_doubles(rowsL) * 8);
-  const size_t oQ1 = w.add((size_t)rowsL * cx * sizeof(cpx<T>));
-  const size_t oV1 = w.add((size_t)cx * 2 * kx * innerX * sizeof(cpx<T>));
-  const size_t oG2 = w.add((size_t)rowsL * rowsL * 16);
-  const size_t oG2p = w.add((size_t)splitsG * rowsL * rowsL * 16);
-  const size_t oEv2 = w.add((size_t)(rowsL + 1) * 8);
-  const size_t oVec2 = w.add((size_t)rowsL * rowsL * 16);
-  const size_t oWk2 = w.add((size_t)eig_work_doubles(rowsL) * 8);
-  const size_t oQ2 = w.add((size_t)rowsL * cx * sizeof(cpx<T>));
-  const size_t oScr = w.add(16);
+  const size_t oBp = w.add((size_t)cx * kx * n2 * sT);
+  const size_t oN = w.add((size_t)n2 * n2 * 16), oNp = w.add((size_t)spN * n2 * n2 * 16);
+  const size_t oEvN = w.add((size_t)(n2 + 1) * 8), oVecN = w.add((size_t)n2 * n2 * 16);
+  const size_t oWkN = w.add((size_t)eig_work_doubles(n2) * 8);
+  const size_t oE3 = w.add((size_t)n2 * n2 * 16), oE3p = w.add((size_t)spE * n2 * n2 * 16);
+  const size_t oEvE = w.add((size_t)(n2 + 1) * 8), oVecE = w.add((size_t)n2 * n2 * 16);
+  const size_t oWkE = w.add((size_t)eig_work_doubles(n2) * 8);
+  const size_t oL1 = w.add((size_t)n2 * n2 * sT), oPND = w.add((size_t)n2 * n2 * 16);
+  const size_t oL3 = w.add((size_t)n2 * n2 * sT), oPD3 = w.add((size_t)n2 * n2 * 16);
+  const size_t oXt = w.add((size_t)cx * 2 * kx * n4 * sT);
+  const size_t oPsi = w.add((size_t)n2 * nh * n2 * sT);
+  const size_t oHin = w.add((size_t)nh * nh * 16), oHinp = w.add((size_t)spH * nh * nh * 16);
+  const size_t oGam = w.add((size_t)ng * ng * 16), oEvG = w.add((size_t)(ng + 1) * 8);
+  const size_t oVecG = w.add((size_t)ng * ng * 16), oWkG = w.add((size_t)eig_work_doubles(ng) * 8);
+  const size_t oQop = w.add((size_t)nh * nh * sT);
+  const size_t oPsi2 = w.add((size_t)n2 * nh * n2 * sT);
+  const size_t oC1 = w.add((size_t)n4 * n4 * 16), oC1p = w.add((size_t)spC1 * n4 * n4 * 16);
+  const size_t oEv1 = w.add((size_t)(n4 + 1) * 8), oVec1 = w.add((size_t)n4 * n4 * 16);
+  const size_t oWk1 = w.add((size_t)eig_work_doubles(n4) * 8);
+  const size_t oU1 = w.add((size_t)n4 * cx * sT), oU1s = w.add((size_t)n4 * cx * 16);
+  const size_t oW1 = w.add((size_t)cx * 4 * kx * n2 * sT);
+  const size_t oY1 = w.add((size_t)n2 * n2 * sT);
+  const size_t oBiP = w.add((size_t)cx * kx * n2 * sT);
+  const size_t oC2 = w.add((size_t)n4 * n4 * 16), oC2p = w.add((size_t)spC2 * n4 * n4 * 16);
+  const size_t oEv2 = w.add((size_t)(n4 + 1) * 8), oVec2 = w.add((size_t)n4 * n4 * 16);
+  const size_t oWk2 = w.add((size_t)eig_work_doubles(n4) * 8);
+  const size_t oZt3 = w.add((size_t)n2 * n2 * 16), oZ2c = w.add((size_t)n4 * cx * sT);
+  const size_t oY3 = w.add((size_t)n2 * n2 * sT);
+  const size_t oScr = w.add(64), oKept = w.add(16);
   const size_t per = w.off;
   if (n > 1 && per * n > ((size_t)8 << 30)) {  // workspace budget: split the group
     const int h = n / 2;
@@ -629,17 +636,23 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
     run_3q(std::vector<const GateOp*>(ops.begin() + h, ops.end()), up);
     return;
   }
+  // descriptor kinds (item it of kind k at k n + it; kinds launched together are adjacent)
+  enum { gN, gE3, gXt, gPsi, gHin, gPsi2, gC1, gY1, gW1, gBiP, gC2, gY3, gBk, gBj, gCount };
+  enum { eN, eE3, eG, e1, e2, eCount };
   Layout u;
   const size_t uCtx = u.add(sizeof(Ctx3<T>) * n);
-  const size_t uG = u.add(sizeof(GemmDesc) * 8 * n);  // X Phi H Proj G1 V1 G2 Tk
-  const size_t uE = u.add(sizeof(EigDesc) * 3 * n);    // H G1 G2
-  const size_t uOuts = u.add(sizeof(double*) * 3 * n);
+  const size_t uG = u.add(sizeof(GemmDesc) * gCount * n);
+  const size_t uE = u.add(sizeof(EigDesc) * eCount * n);
+  const size_t uOuts = u.add(sizeof(double*) * 5 * n);  // N E3 | Hin | C1 | C2
   const size_t uU = u.add(sizeof(double) * 128 * n);
   char *h = nullptr, *dv = nullptr;
   if (!reserve(up, u.off, per * n, 3 * n, h, dv)) return;
   char* wk = reinterpret_cast<char*>(work_.p);
   GemmDesc* dG = reinterpret_cast<GemmDesc*>(dv + uG);
   EigDesc* dE = reinterpret_cast<EigDesc*>(dv + uE);
+  GemmDesc* hd = at<GemmDesc>(h, uG);
+  EigDesc* he = at<EigDesc>(h, uE);
+  double** outs = at<double*>(h, uOuts);
   for (int it = 0; it < n; ++it) {
     const GateOp& g = *ops[it];
     char* base = wk + per * it;
@@ -675,71 +688,91 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
     c.kap3 = kap_ptr(b, i + 2);
     c.disc = disc_ptr(b, i);
     c.scratch = at<int>(base, oScr);
+    c.kept = at<double>(base, oKept);
     c.G = at<double>(base, oG);
-    c.X = at<cpx<T>>(base, oX);
-    c.Phi = at<cpx<T>>(base, oPhi);
+    c.Bp = at<cpx<T>>(base, oBp);
+    c.N = at<double>(base, oN); c.evN = at<double>(base, oEvN); c.vecN = at<double>(base, oVecN);
+    c.E3 = at<double>(base, oE3); c.evE3 = at<double>(base, oEvE); c.vecE3 = at<double>(base, oVecE);
+    c.L1 = at<cpx<T>>(base, oL1); c.PND = at<double>(base, oPND);
+    c.L3 = at<cpx<T>>(base, oL3); c.PD3 = at<double>(base, oPD3);
+    c.Xt = at<cpx<T>>(base, oXt);
     c.Psi = at<cpx<T>>(base, oPsi);
+    c.Hin = at<double>(base, oHin);
+    c.Gam = at<double>(base, oGam); c.evG = at<double>(base, oEvG); c.vecG = at<double>(base, oVecG);
+    c.Qop = at<cpx<T>>(base, oQop);
     c.Psi2 = at<cpx<T>>(base, oPsi2);
-    c.H = at<double>(base, oH);
-    c.evH = at<double>(base, oEvH);
-    c.vecH = at<double>(base, oVecH);
-    c.P = at<cpx<T>>(base, oP);
-    c.G1 = at<double>(base, oG1);
-    c.ev1 = at<double>(base, oEv1);
-    c.vec1 = at<double>(base, oVec1);
-    c.Q1 = at<cpx<T>>(base, oQ1);
-    c.V1 = at<cpx<T>>(base, oV1);
-    c.G2 = at<double>(base, oG2);
-    c.ev2 = at<double>(base, oEv2);
-    c.vec2 = at<double>(base, oVec2);
-    c.Q2 = at<cpx<T>>(base, oQ2);
-    // descriptor kind k of item it lives at dG[k n + it] (launches take one kind)
-    c.dX = dG + it; c.dPhi = dG + n + it; c.dH = dG + 2 * n + it; c.dProj = dG + 3 * n + it;
-    c.dG1 = dG + 4 * n + it; c.dV1 = dG + 5 * n + it; c.dG2 = dG + 6 * n + it; c.dTk = dG + 7 * n + it;
-    c.dEH = dE + it; c.dE1 = dE + n + it; c.dE2 = dE + 2 * n + it;
-    GemmDesc* hd = at<GemmDesc>(h, uG);
-    hd[2 * n + it].C = at<double>(base, oHp);
-    hd[2 * n + it].sSplit = (long long)kmm * kmm;
-    hd[4 * n + it].C = at<double>(base, oG1p);
-    hd[4 * n + it].sSplit = (long long)rowsL * rowsL;
-    hd[6 * n + it].C = at<double>(base, oG2p);
-    hd[6 * n + it].sSplit = (long long)rowsL * rowsL;
-    EigDesc* he = at<EigDesc>(h, uE);
-    he[it].a = c.H; he[it].work = at<double>(base, oWkH); he[it].kvec = kx;
-    he[n + it].a = c.G1; he[n + it].work = at<double>(base, oWk1); he[n + it].kvec = cx;
-    he[2 * n + it].a = c.G2; he[2 * n + it].work = at<double>(base, oWk2); he[2 * n + it].kvec = cx;
-    double** outs = at<double*>(h, uOuts);
-    outs[it] = c.H;
-    outs[n + it] = c.G1;
-    outs[2 * n + it] = c.G2;
+    c.C1 = at<double>(base, oC1); c.ev1 = at<double>(base, oEv1); c.vec1 = at<double>(base, oVec1);
+    c.U1 = at<cpx<T>>(base, oU1); c.U1s = at<double>(base, oU1s);
+    c.W1 = at<cpx<T>>(base, oW1);
+    c.Y1 = at<cpx<T>>(base, oY1);
+    c.BiP = at<cpx<T>>(base, oBiP);
+    c.C2 = at<double>(base, oC2); c.ev2 = at<double>(base, oEv2); c.vec2 = at<double>(base, oVec2);
+    c.Zt3 = at<double>(base, oZt3); c.Z2c = at<cpx<T>>(base, oZ2c);
+    c.Y3 = at<cpx<T>>(base, oY3);
+    c.dN = dG + gN * n + it; c.dE3 = dG + gE3 * n + it; c.dXt = dG + gXt * n + it; c.dPsi = dG + gPsi * n + it;
+    c.dHin = dG + gHin * n + it; c.dPsi2 = dG + gPsi2 * n + it; c.dC1 = dG + gC1 * n + it;
+    c.dY1 = dG + gY1 * n + it; c.dW1 = dG + gW1 * n + it; c.dBiP = dG + gBiP * n + it;
+    c.dC2 = dG + gC2 * n + it; c.dY3 = dG + gY3 * n + it; c.dBk = dG + gBk * n + it; c.dBj = dG + gBj * n + it;
+    c.eN = dE + eN * n + it; c.eE3 = dE + eE3 * n + it; c.eG = dE + eG * n + it;
+    c.e1 = dE + e1 * n + it; c.e2 = dE + e2 * n + it;
+    // split-K partial buffers of the Gram products (kept by the device-side descriptor setup)
+    hd[gN * n + it].C = at<double>(base, oNp);    hd[gN * n + it].sSplit = (long long)n2 * n2;
+    hd[gE3 * n + it].C = at<double>(base, oE3p);  hd[gE3 * n + it].sSplit = (long long)n2 * n2;
+    hd[gHin * n + it].C = at<double>(base, oHinp); hd[gHin * n + it].sSplit = (long long)nh * nh;
+    hd[gC1 * n + it].C = at<double>(base, oC1p);  hd[gC1 * n + it].sSplit = (long long)n4 * n4;
+    hd[gC2 * n + it].C = at<double>(base, oC2p);  hd[gC2 * n + it].sSplit = (long long)n4 * n4;
+    he[eN * n + it].a = c.N;   he[eN * n + it].work = at<double>(base, oWkN);  he[eN * n + it].kvec = n2;
+    he[eE3 * n + it].a = c.E3; he[eE3 * n + it].work = at<double>(base, oWkE); he[eE3 * n + it].kvec = n2;
+    he[eN * n + it].vfloor = Q3_BASIS_FLOOR;
+    he[eE3 * n + it].vfloor = Q3_BASIS_FLOOR;
+    he[eG * n + it].a = c.Gam; he[eG * n + it].work = at<double>(base, oWkG);  he[eG * n + it].kvec = kx;
+    he[e1 * n + it].a = c.C1;  he[e1 * n + it].work = at<double>(base, oWk1);  he[e1 * n + it].kvec = cx;
+    he[e2 * n + it].a = c.C2;  he[e2 * n + it].work = at<double>(base, oWk2);  he[e2 * n + it].kvec = cx;
+    outs[it] = c.N;
+    outs[n + it] = c.E3;
+    outs[2 * n + it] = c.Hin;
+    outs[3 * n + it] = c.C1;
+    outs[4 * n + it] = c.C2;
   }
   commit(up, h, dv, u.off);
   Ctx3<T>* dctx = reinterpret_cast<Ctx3<T>*>(dv + uCtx);
   double** douts = reinterpret_cast<double**>(dv + uOuts);
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   int* status = sweeps_.as<int>();
-  const int tX = gemm_tiles(rowsL, (int)innerX), tPhi = gemm_tiles(rowsL, 2 * kx * (int)innerX);
-  launch_q3_prepare<T>(dctx, n, splitsH, st_);
-  launch_gemm<T, T, T>(dG, n, 1, 1, tX, st_);
-  launch_gemm<T, T, T>(dG + n, n, 1, 1, tPhi, st_);
-  launch_q3_apply<T>(dctx, n, st_);
-  launch_gemm<T, double, double>(dG + 2 * n, n, 1, splitsH, gemm_tiles(kmm, kmm), st_);
-  launch_reduce_splits(dG + 2 * n, douts, n, kmm * kmm, st_);
-  launch_eigh(dE, n, kmm, status, st_);
-  launch_q3_select_h<T>(dctx, n, splitsG, tp, st_);
-  launch_gemm<T, T, T>(dG + 3 * n, n, cx * 4 * kx, 1, gemm_tiles(kx, (int)innerX), st_);
-  launch_gemm<T, double, double>(dG + 4 * n, n, 1, splitsG, gemm_tiles(rowsL, rowsL), st_);
-  launch_reduce_splits(dG + 4 * n, douts + n, n, rowsL * rowsL, st_);
-  launch_q3_scale1<T>(dctx, n, st_);
-  launch_eigh(dE + n, n, rowsL, status + n, st_);
-  launch_q3_select_1<T>(dctx, n, splitsG, tp, st_);
-  launch_gemm<T, T, T>(dG + 5 * n, n, 1, 1, gemm_tiles(cx, 2 * kx * (int)innerX), st_);
-  launch_gemm<T, double, double>(dG + 6 * n, n, 1, splitsG, gemm_tiles(rowsL, rowsL), st_);
-  launch_reduce_splits(dG + 6 * n, douts + 2 * n, n, rowsL * rowsL, st_);
-  launch_q3_scale2<T>(dctx, n, st_);
-  launch_eigh(dE + 2 * n, n, rowsL, status + 2 * n, st_);
-  launch_q3_select_2<T>(dctx, n, tp, st_);
-  launch_gemm<T, T, T>(dG + 7 * n, n, 1, 1, gemm_tiles(cx, (int)innerX), st_);
+  // outer bases
+  launch_q3_prepare<T>(dctx, n, spN, spE, st_);
+  launch_q3_perm_in<T>(dctx, n, st_);
+  launch_gemm<T, double, double>(dG + gN * n, 2 * n, 1, std::max(spN, spE), gemm_tiles(n2, n2), st_);
+  launch_reduce_splits(dG + gN * n, douts, 2 * n, n2 * n2, st_);
+  launch_eigh(dE + eN * n, 2 * n, n2, status, st_);
+  launch_q3_sel_env<T>(dctx, n, spH, Q3_BASIS_FLOOR, st_);
+  // reduced block, middle inner truncation
+  launch_gemm<T, T, T>(dG + gXt * n, n, 1, 1, gemm_tiles(cx * 2 * kx, n4), st_);
+  launch_gemm<T, T, T>(dG + gPsi * n, n, 2, 1, gemm_tiles(n2, 4 * kx * n2), st_);
+  launch_gemm<T, double, double>(dG + gHin * n, n, 1, spH, gemm_tiles(nh, nh), st_);
+  launch_reduce_splits(dG + gHin * n, douts + 2 * n, n, nh * nh, st_);
+  launch_q3_gamma<T>(dctx, n, m3, st_);
+  launch_eigh(dE + eG * n, n, ng, status + 2 * n, st_);
+  launch_q3_sel_h<T>(dctx, n, spC1, tp, st_);
+  launch_gemm<T, T, T>(dG + gPsi2 * n, n, n2, 1, gemm_tiles(nh, n2), st_);
+  // bond i
+  launch_gemm<T, double, double>(dG + gC1 * n, n, 1, spC1, gemm_tiles(n4, n4), st_);
+  launch_reduce_splits(dG + gC1 * n, douts + 3 * n, n, n4 * n4, st_);
+  launch_eigh(dE + e1 * n, n, n4, status + 3 * n, st_);
+  launch_q3_sel_1<T>(dctx, n, spC2, tp, st_);
+  launch_gemm<double, double, T>(dG + gY1 * n, n, 1, 1, gemm_tiles(n2, n2), st_);
+  launch_gemm<T, T, T>(dG + gW1 * n, 2 * n, 1, 1,
+                       std::max(gemm_tiles(cx, 4 * kx * n2), gemm_tiles(cx * kx, n2)), st_);
+  launch_q3_perm_out<T>(dctx, n, st_);
+  // bond i+1
+  launch_gemm<T, double, double>(dG + gC2 * n, n, 1, spC2, gemm_tiles(n4, n4), st_);
+  launch_reduce_splits(dG + gC2 * n, douts + 4 * n, n, n4 * n4, st_);
+  launch_eigh(dE + e2 * n, n, n4, status + 4 * n, st_);
+  launch_q3_sel_2<T>(dctx, n, tp, st_);
+  launch_gemm<double, double, T>(dG + gY3 * n, n, 1, 1, gemm_tiles(n2, n2), st_);
+  launch_gemm<T, T, T>(dG + gBk * n, 2 * n, 1, 1,
+                       std::max(gemm_tiles(n2, kx * cx), gemm_tiles(2 * kx * cx, cx)), st_);
+  launch_q3_finish<T>(dctx, n, st_);
   hip_check(hipGetLastError(), "launch (3-site sublayer)");
   for (auto* g : ops)
     for (int t = 0; t < 3; ++t) par_[soff_[g->inst] + g->site + t] ^= 1;

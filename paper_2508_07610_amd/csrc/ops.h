@@ -88,9 +88,30 @@ template <typename T> struct Ctx2 {
 };
 
 // Three-site noisy gate on (i, i+1, i+2), the Kraus index joining the inner
-// index of the middle site: the three-site block is contracted, the fused
-// operators applied, the middle inner index truncated, and the block split
-// twice (bond i, then bond i+1) by Gram eigendecompositions.
+// index of the middle site.  The passive indices of the outer sites, (l k1)
+// of site i (weighted by lambda_l) and (k3 r) of site i+2, are replaced by
+// orthonormal bases of their spans, taken from the Gram eigendecompositions
+//   N  = (Lambda B_i)^H (Lambda B_i) over (l k1), columns (t1 a):  P D P^H,
+//   E3 = F F^H with F = B_{i+2} as [(b t3)] x [(k3 r)]:            P3 D3 P3^H,
+// so that Lambda Psi = Q1 Psi^ Q3 with Q1, Q3 isometries and the reduced block
+//   Psi^[alpha, (t1 t2 k2 t3), beta] = sum_a L1[alpha, (t1 a)] Xt[(a t2 k2), (t3 beta)],
+//   L1 = sqrt(D) P^H,  Xt = B_{i+1} L3,  L3 = P3 sqrt(D3)
+// (at most 2 chi_a x 8 kappa x 2 chi_b).  Every Gram matrix of the gate output
+// is then a Gram matrix of the reduced block:
+//   Hin = Gram of Psi^ over (alpha, beta) with the middle indices open -> Gamma
+//         (fused operators, Eqs. (9)-(11)) -> kappa' and the operator Qop;
+//   Psi2 = Qop Psi^;  C1 = Psi2 Psi2^H over rows (alpha s1): bond i, at most
+//         4 chi; W1 = U1^H Psi2 / sqrt(kept) = lambda' V1;
+//   C2 = W1^H W1 over columns (s3 beta): bond i+1, at most 4 chi.
+// New tensors:  B_i' = Bp (P D^-1/2 U1 S1) / sqrt(kept1),
+//   B_{i+1}' = lambda'^-1 W1 Z2 / sqrt(kept2),  B_{i+2}' = (Z2^H D3^-1/2 P3^H) F,
+// the small factors in parentheses formed in FP64.
+// N is weighted by lambda^2, so its spectrum spans that of the bond weights:
+// its basis keeps every direction above this fraction of the largest
+// eigenvalue (the factors P D^-1/2 and sqrt(D) P^H enter only as balanced
+// products), where the Gram floor of the truncation rule would drop weight.
+constexpr double Q3_BASIS_FLOOR = 1e-18;
+
 template <typename T> struct Ctx3 {
   GateSrc g;
   const double* kraus;    // m x 8 x 8 complex or null
@@ -114,22 +135,36 @@ template <typename T> struct Ctx3 {
   int* kap2;
   const int* kap3;
   double* disc;
-  int* scratch;           // [0] kappa', [1] bond i, [2] bond i+1
+  int* scratch;           // [0] kappa', [1] r_N, [2] r_3, [3] bond i, [4] bond i+1
+  double* kept;           // [0] kept weight at bond i, [1] at bond i+1
   double* G;              // m x 8 x 8
-  cpx<T>* X;              // B_{i+1} B_{i+2}
-  cpx<T>* Phi;            // (l t1 k1) x (t2 k2 t3 k3 r)
-  cpx<T>* Psi;            // (l s1 k1) x (s2 (k2 j) s3 k3 r)
-  cpx<T>* Psi2;           // (l s1 k1) x (s2 nu s3 k3 r)
-  double* H;  double* evH; double* vecH;
-  cpx<T>* P;              // (k2 m) x kappa'
-  double* G1; double* ev1; double* vec1;
-  cpx<T>* Q1;             // (l s1 k1) x r1
-  cpx<T>* V1;             // r1 x (s2 nu s3 k3 r)
-  double* G2; double* ev2; double* vec2;
-  cpx<T>* Q2;             // (r1 s2 nu) x r2
-  GemmDesc* dX; GemmDesc* dPhi; GemmDesc* dH; GemmDesc* dProj; GemmDesc* dG1; GemmDesc* dV1;
-  GemmDesc* dG2; GemmDesc* dTk;
-  EigDesc* dEH; EigDesc* dE1; EigDesc* dE2;
+  cpx<T>* Bp;             // B_i as (l k1) x (t1 a)
+  double* N;  double* evN;  double* vecN;
+  double* E3; double* evE3; double* vecE3;
+  cpx<T>* L1;             // r_N x (t1 a)
+  double* PND;            // (t1 a) x r_N: P D^-1/2
+  cpx<T>* L3;             // (b t3) x r_3
+  double* PD3;            // (b t3) x r_3: P3 D3^-1/2
+  cpx<T>* Xt;             // (a t2 k2) x (t3 beta)
+  cpx<T>* Psi;            // alpha x (t1 t2 k2 t3) x beta
+  double* Hin;            // (8 k2)^2
+  double* Gam; double* evG; double* vecG;
+  cpx<T>* Qop;            // (s1 s2 nu s3) x (t1 t2 k2 t3)
+  cpx<T>* Psi2;           // alpha x (s1 s2 nu s3) x beta
+  double* C1; double* ev1; double* vec1;
+  cpx<T>* U1;             // (alpha s1) x r1
+  double* U1s;            // (alpha s1) x r1, columns scaled by sqrt(eta / kept)
+  cpx<T>* W1;             // r1 x (s2 nu s3 beta)
+  cpx<T>* Y1;             // (t1 a) x (s1 r1)
+  cpx<T>* BiP;            // (l k1) x (s1 r1)
+  double* C2; double* ev2; double* vec2;
+  double* Zt3;            // (r2 s3) x beta
+  cpx<T>* Z2c;            // (s3 beta) x r2
+  cpx<T>* Y3;             // (r2 s3) x (b t3)
+  GemmDesc* dN; GemmDesc* dE3; GemmDesc* dXt; GemmDesc* dPsi; GemmDesc* dHin; GemmDesc* dPsi2;
+  GemmDesc* dC1; GemmDesc* dY1; GemmDesc* dW1; GemmDesc* dBiP; GemmDesc* dC2; GemmDesc* dY3;
+  GemmDesc* dBk; GemmDesc* dBj;
+  EigDesc* eN; EigDesc* eE3; EigDesc* eG; EigDesc* e1; EigDesc* e2;
 };
 
 // One step of the truncation sweep (Sec. II.D) on one instance.
@@ -197,13 +232,15 @@ template <typename T> void launch_q2_gamma(Ctx2<T>* d_ctx, int n, hipStream_t s)
 template <typename T> void launch_q2_select_g(Ctx2<T>* d_ctx, int n, int splitsC, TruncParams tp, hipStream_t s);
 template <typename T> void launch_q2_select_b(Ctx2<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
 
-template <typename T> void launch_q3_prepare(Ctx3<T>* d_ctx, int n, int splitsH, hipStream_t s);
-template <typename T> void launch_q3_apply(Ctx3<T>* d_ctx, int n, hipStream_t s);
-template <typename T> void launch_q3_select_h(Ctx3<T>* d_ctx, int n, int splitsG, TruncParams tp, hipStream_t s);
-template <typename T> void launch_q3_scale1(Ctx3<T>* d_ctx, int n, hipStream_t s);
-template <typename T> void launch_q3_select_1(Ctx3<T>* d_ctx, int n, int splitsG, TruncParams tp, hipStream_t s);
-template <typename T> void launch_q3_scale2(Ctx3<T>* d_ctx, int n, hipStream_t s);
-template <typename T> void launch_q3_select_2(Ctx3<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
+template <typename T> void launch_q3_prepare(Ctx3<T>* d_ctx, int n, int splitsN, int splitsE, hipStream_t s);
+template <typename T> void launch_q3_perm_in(Ctx3<T>* d_ctx, int n, hipStream_t s);
+template <typename T> void launch_q3_sel_env(Ctx3<T>* d_ctx, int n, int splitsH, double floor, hipStream_t s);
+template <typename T> void launch_q3_gamma(Ctx3<T>* d_ctx, int n, int mmax, hipStream_t s);
+template <typename T> void launch_q3_sel_h(Ctx3<T>* d_ctx, int n, int splitsC, TruncParams tp, hipStream_t s);
+template <typename T> void launch_q3_sel_1(Ctx3<T>* d_ctx, int n, int splitsC, TruncParams tp, hipStream_t s);
+template <typename T> void launch_q3_perm_out(Ctx3<T>* d_ctx, int n, hipStream_t s);
+template <typename T> void launch_q3_sel_2(Ctx3<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
+template <typename T> void launch_q3_finish(Ctx3<T>* d_ctx, int n, hipStream_t s);
 
 template <typename T> void launch_sw_prepare(CtxS<T>* d_ctx, int n, int splits, hipStream_t s);
 template <typename T> void launch_sw_select(CtxS<T>* d_ctx, int n, TruncParams tp, hipStream_t s);

@@ -495,104 +495,192 @@ __global__ __launch_bounds__(GT) void k_q2_select_b(Ctx2<T>* ctxs, TruncParams t
 }
 
 // ============================================================================
-// three-site noisy gate
+// three-site noisy gate (see Ctx3)
 // ============================================================================
+// Gate operators and the Gram descriptors of the two outer sites.
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q3_prepare(Ctx3<T>* ctxs, int splitsH) {
+__global__ __launch_bounds__(GT) void k_q3_prepare(Ctx3<T>* ctxs, int splitsN, int splitsE) {
   __shared__ cpx<double> sU[64];
   Ctx3<T>& c = ctxs[blockIdx.x];
   build_G(c.g, c.kraus, c.m, c.G, sU);
   if (threadIdx.x != 0) return;
-  const int cl = *c.chil, c1 = *c.chim1, c2 = *c.chim2, cr = *c.chir;
-  const int k1 = *c.kap1, k2 = *c.kap2, k3 = *c.kap3;
-  const int inner = 2 * k3 * cr;
-  {  // X[(c1 t2 k2), (t3 k3 r)] = B_{i+1} B_{i+2}
-    GemmDesc& d = *c.dX;
-    clear_desc(d);
-    d.A = c.Bj; d.B = c.Bk; d.C = c.X;
-    d.M = c1 * 2 * k2; d.K = c2; d.N = inner;
-    d.lda = c2; d.ldb = inner; d.ldc = inner;
-  }
-  {  // Phi[(l t1 k1), (t2 k2 t3 k3 r)] = B_i X
-    GemmDesc& d = *c.dPhi;
-    clear_desc(d);
-    d.A = c.Bi; d.B = c.X; d.C = c.Phi;
-    d.M = cl * 2 * k1; d.K = c1; d.N = 2 * k2 * inner;
-    d.lda = c1; d.ldb = 2 * k2 * inner; d.ldc = 2 * k2 * inner;
-  }
-  {  // H[a][b] = sum_{l s1 k1 s2, s3 k3 r} lambda_l^2 conj(Psi) Psi, a = (k2 j)
-    GemmDesc& d = *c.dH;
+  const int cl = *c.chil, ca = *c.chim1, cb = *c.chim2, cr = *c.chir;
+  const int k1 = *c.kap1, k3 = *c.kap3;
+  {  // N[(t1 a),(t1' a')] = sum_{l k1} lambda_l^2 conj(Bp) Bp
+    GemmDesc& d = *c.dN;
     void* C = d.C;
     const long long ss = d.sSplit;
     clear_desc(d);
     d.C = C; d.sSplit = ss;
-    const int n = k2 * c.m;
-    if (c.m <= 1) {
-      d.active = 0;
-      c.dEH->active = 0;
-    } else {
-      d.A = c.Psi; d.B = c.Psi; d.opA = OP_C; d.opB = OP_T;
-      d.M = d.N = n;
-      d.K = cl * 4 * k1 * inner;
-      d.lda = d.ldb = inner;
-      d.kinner = inner;
-      d.kstride = (long long)n * inner;
-      d.w = c.laml2; d.wdiv = 4 * k1 * inner;
-      d.ldc = n;
-      d.splits = splitsH;
-      EigDesc& e = *c.dEH;
-      e.lda = n; e.n = n; e.evals = c.evH; e.evecs = c.vecH; e.trace = c.evH + n; e.active = 1;
-    }
+    d.A = c.Bp; d.B = c.Bp; d.opA = OP_H; d.opB = OP_N;
+    d.M = d.N = 2 * ca;
+    d.K = cl * k1;
+    d.lda = d.ldb = 2 * ca;
+    d.w = c.laml2; d.wdiv = k1;
+    d.ldc = 2 * ca;
+    d.splits = splitsN;
+    EigDesc& e = *c.eN;
+    e.lda = 2 * ca; e.n = 2 * ca; e.evals = c.evN; e.evecs = c.vecN; e.trace = c.evN + 2 * ca; e.active = 1;
+  }
+  {  // E3 = F F^H, F = B_{i+2} as [(b t3)] x [(k3 r)]
+    GemmDesc& d = *c.dE3;
+    void* C = d.C;
+    const long long ss = d.sSplit;
+    clear_desc(d);
+    d.C = C; d.sSplit = ss;
+    d.A = c.Bk; d.B = c.Bk; d.opA = OP_N; d.opB = OP_H;
+    d.M = d.N = 2 * cb;
+    d.K = k3 * cr;
+    d.lda = d.ldb = k3 * cr;
+    d.ldc = 2 * cb;
+    d.splits = splitsE;
+    EigDesc& e = *c.eE3;
+    e.lda = 2 * cb; e.n = 2 * cb; e.evals = c.evE3; e.evecs = c.vecE3; e.trace = c.evE3 + 2 * cb; e.active = 1;
   }
 }
 
-// Psi[(l s1 k1), (s2 (k2 j) s3 k3 r)] = sum_t G_j[(s1 s2 s3), (t1 t2 t3)] Phi[(l t1 k1), (t2 k2 t3 k3 r)]
+// Bp[(l k1), (t1 a)] = B_i[l, t1, k1, a]
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q3_apply(Ctx3<T>* ctxs) {
+__global__ __launch_bounds__(GT) void k_q3_perm_in(Ctx3<T>* ctxs) {
   Ctx3<T>& c = ctxs[blockIdx.y];
-  const int cl = *c.chil, cr = *c.chir, k1 = *c.kap1, k2 = *c.kap2, k3 = *c.kap3, m = c.m;
-  const int kr = k3 * cr, inner = 2 * kr, km = k2 * m;
-  const long long total = (long long)cl * 2 * k1 * 2 * km * inner;
+  const int cl = *c.chil, ca = *c.chim1, k1 = *c.kap1;
+  const long long total = (long long)cl * 2 * k1 * ca;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    long long rest = e;
-    const int in = (int)(rest % inner); rest /= inner;
-    const int a = (int)(rest % km); rest /= km;
-    const int s2 = (int)(rest % 2); rest /= 2;
-    const int kk1 = (int)(rest % k1); rest /= k1;
-    const int s1 = (int)(rest % 2);
-    const long long l = rest / 2;
-    const int kk2 = a / m, j = a % m;
-    const int s3 = in / kr, krr = in % kr;
-    const int srow = s1 * 4 + s2 * 2 + s3;
-    cpx<double> acc = mk(0.0, 0.0);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int t1 = t >> 2, t2 = (t >> 1) & 1, t3 = t & 1;
-      const long long pi = ((l * 2 + t1) * k1 + kk1) * (2LL * k2 * inner) + (long long)(t2 * k2 + kk2) * inner +
-                           t3 * kr + krr;
-      const cpx<T> ph = c.Phi[pi];
-      acc = acc + ld(c.G, ((long long)j * 8 + srow) * 8 + t) * mk((double)ph.re, (double)ph.im);
-    }
-    c.Psi[e] = mk<T>((T)acc.re, (T)acc.im);
+    const int a = (int)(e % ca);
+    long long rest = e / ca;
+    const int t1 = (int)(rest % 2);
+    rest /= 2;
+    const int kk = (int)(rest % k1);
+    const int l = (int)(rest / k1);
+    c.Bp[e] = c.Bi[(((long long)l * 2 + t1) * k1 + kk) * ca + a];
   }
 }
 
-// kappa' and the projection of the middle inner index; descriptor of the Gram G1
+// Ranks of N and E3 (eigenvalues above Q3_BASIS_FLOOR times the largest),
+// the basis factors, and the descriptors of Xt, Psi and Hin.
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q3_select_h(Ctx3<T>* ctxs, int splitsG, TruncParams tp) {
+__global__ __launch_bounds__(GT) void k_q3_sel_env(Ctx3<T>* ctxs, int splitsH, double floor) {
+  __shared__ int s_r[2];
+  Ctx3<T>& c = ctxs[blockIdx.x];
+  const int ca = *c.chim1, cb = *c.chim2, k2 = *c.kap2;
+  const int nN = 2 * ca, nE = 2 * cb;
+  if (threadIdx.x == 0) {
+    int rN = 0, r3 = 0;
+    for (int b = 0; b < nN; ++b) rN += (c.evN[b] > floor * c.evN[0]) ? 1 : 0;
+    for (int b = 0; b < nE; ++b) r3 += (c.evE3[b] > floor * c.evE3[0]) ? 1 : 0;
+    s_r[0] = rN < 1 ? 1 : rN;
+    s_r[1] = r3 < 1 ? 1 : r3;
+    c.scratch[1] = s_r[0];
+    c.scratch[2] = s_r[1];
+  }
+  __syncthreads();
+  const int rN = s_r[0], r3 = s_r[1];
+  for (int e = threadIdx.x; e < nN * rN; e += blockDim.x) {
+    const int x = e / rN, al = e % rN;
+    const cpx<double> p = ld(c.vecN, (long long)x * nN + al);
+    const double sq = sqrt(c.evN[al]);
+    c.L1[(long long)al * nN + x] = mk<T>((T)(p.re * sq), (T)(-p.im * sq));
+    st(c.PND, e, mk(p.re / sq, p.im / sq));
+  }
+  for (int e = threadIdx.x; e < nE * r3; e += blockDim.x) {
+    const int y = e / r3, be = e % r3;
+    const cpx<double> p = ld(c.vecE3, (long long)y * nE + be);
+    const double sq = sqrt(c.evE3[be]);
+    c.L3[e] = mk<T>((T)(p.re * sq), (T)(p.im * sq));
+    st(c.PD3, e, mk(p.re / sq, p.im / sq));
+  }
+  if (threadIdx.x == 0) {
+    {  // Xt[(a t2 k2), (t3 beta)] = sum_b B_{i+1}[(a t2 k2), b] L3[(b t3), beta]
+      GemmDesc& d = *c.dXt;
+      clear_desc(d);
+      d.A = c.Bj; d.B = c.L3; d.C = c.Xt;
+      d.M = ca * 2 * k2; d.K = cb; d.N = 2 * r3;
+      d.lda = cb; d.ldb = 2 * r3; d.ldc = 2 * r3;
+    }
+    {  // Psi[alpha, t1, :] = sum_a L1[alpha, (t1 a)] Xt[a, :], one batch per t1
+      GemmDesc& d = *c.dPsi;
+      clear_desc(d);
+      d.A = c.L1; d.B = c.Xt; d.C = c.Psi;
+      d.M = rN; d.K = ca; d.N = 4 * k2 * r3;
+      d.lda = nN; d.ldb = 4 * k2 * r3; d.ldc = 8 * k2 * r3;
+      d.nbatch = 2; d.sA = ca; d.sB = 0; d.sC = (long long)4 * k2 * r3;
+    }
+    {  // Hin[x][x'] = sum_{alpha beta} conj(Psi[alpha][x][beta]) Psi[alpha][x'][beta]
+      GemmDesc& d = *c.dHin;
+      void* C = d.C;
+      const long long ss = d.sSplit;
+      clear_desc(d);
+      d.C = C; d.sSplit = ss;
+      if (c.m <= 1) {
+        d.active = 0;
+      } else {
+        d.A = c.Psi; d.B = c.Psi; d.opA = OP_C; d.opB = OP_T;
+        d.M = d.N = 8 * k2;
+        d.K = rN * r3;
+        d.lda = d.ldb = r3;
+        d.kinner = r3;
+        d.kstride = (long long)8 * k2 * r3;
+        d.ldc = 8 * k2;
+        d.splits = splitsH;
+      }
+    }
+  }
+}
+
+// Gamma[(k j),(k' j')] = sum_{t,t'} Omega_{jj'}[t,t'] Hin[x(t,k)][x(t',k')],
+// Omega_{jj'} = G_j^H G_j' (the 8 x 8 blocks of one (j, j') pair per block),
+// x(t, k) = ((t1 2 + t2) k2 + k) 2 + t3.
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_gamma(Ctx3<T>* ctxs) {
+  __shared__ cpx<double> sOm[64];
+  Ctx3<T>& c = ctxs[blockIdx.y];
+  const int m = c.m, k2 = *c.kap2, n = k2 * m;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    EigDesc& d = *c.eG;
+    d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.evG; d.evecs = c.vecG; d.trace = c.evG + n;
+    d.active = m > 1 ? 1 : 0;
+  }
+  if (m <= 1 || (int)blockIdx.x >= m * m) return;
+  const int j = blockIdx.x / m, j2 = blockIdx.x % m;
+  if (threadIdx.x < 64) {
+    const int t = threadIdx.x / 8, t2 = threadIdx.x % 8;
+    cpx<double> om = mk(0.0, 0.0);
+    for (int s = 0; s < 8; ++s) om = om + cconj(ld(c.G, j * 64 + s * 8 + t)) * ld(c.G, j2 * 64 + s * 8 + t2);
+    sOm[threadIdx.x] = om;
+  }
+  __syncthreads();
+  const int nh = 8 * k2;
+  for (int e = threadIdx.x; e < k2 * k2; e += blockDim.x) {
+    const int kk = e / k2, kk2 = e % k2;
+    cpx<double> acc = mk(0.0, 0.0);
+    for (int t = 0; t < 8; ++t) {
+      const int xa = (((t >> 2) * 2 + ((t >> 1) & 1)) * k2 + kk) * 2 + (t & 1);
+      for (int t2 = 0; t2 < 8; ++t2) {
+        const int xb = (((t2 >> 2) * 2 + ((t2 >> 1) & 1)) * k2 + kk2) * 2 + (t2 & 1);
+        acc = acc + sOm[t * 8 + t2] * ld(c.Hin, (long long)xa * nh + xb);
+      }
+    }
+    st(c.Gam, (long long)(kk * m + j) * n + (kk2 * m + j2), acc);
+  }
+}
+
+// kappa' (Eqs. (10)-(11)) and Qop[(s1 s2 nu s3), (t1 t2 k t3)] =
+// sum_j G_j[s, t] V[(k j), nu] / sqrt(kept); descriptors of Psi2 and C1.
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_sel_h(Ctx3<T>* ctxs, int splitsC, TruncParams tp) {
   __shared__ int s_kp;
   __shared__ double s_scale;
   Ctx3<T>& c = ctxs[blockIdx.x];
-  const int cl = *c.chil, cr = *c.chir, k1 = *c.kap1, k2 = *c.kap2, k3 = *c.kap3, m = c.m;
-  const int inner = 2 * k3 * cr, n = k2 * m;
+  const int m = c.m, k2 = *c.kap2, n = k2 * m;
+  const int rN = c.scratch[1], r3 = c.scratch[2];
   if (threadIdx.x == 0) {
     if (m <= 1) {
       s_kp = k2;
       s_scale = 1.0;
     } else {
       double kept, tot;
-      const int kp = select_rank(c.evH, min(n, tp.kap_max + 1), n, c.evH[n], tp.kap_max, tp.kap_cut, &kept, &tot);
+      const int kp = select_rank(c.evG, min(n, tp.kap_max + 1), n, c.evG[n], tp.kap_max, tp.kap_cut, &kept, &tot);
       s_kp = kp;
       s_scale = 1.0 / sqrt(kept);
       if (tot > 0) *c.disc += (tot - kept) / tot;
@@ -602,153 +690,162 @@ __global__ __launch_bounds__(GT) void k_q3_select_h(Ctx3<T>* ctxs, int splitsG, 
   __syncthreads();
   const int kp = s_kp;
   const double sc = s_scale;
-  for (int e = threadIdx.x; e < n * kp; e += blockDim.x) {
-    const int a = e / kp, nu = e % kp;
-    cpx<double> v = mk(0.0, 0.0);
+  const int rows = 8 * kp, cols = 8 * k2;
+  for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
+    const int row = e / cols, col = e % cols;
+    const int s1 = row / (4 * kp), s2 = (row / (2 * kp)) % 2, nu = (row / 2) % kp, s3 = row % 2;
+    const int t1 = col / (4 * k2), t2 = (col / (2 * k2)) % 2, kk = (col / 2) % k2, t3 = col % 2;
+    const int gs = s1 * 4 + s2 * 2 + s3, gt = t1 * 4 + t2 * 2 + t3;
+    cpx<double> acc = mk(0.0, 0.0);
     if (m <= 1) {
-      if (a == nu) v = mk(1.0, 0.0);
+      if (nu == kk) acc = ld(c.G, gs * 8 + gt);
     } else {
-      v = ld(c.vecH, (long long)a * n + nu);
+      for (int j = 0; j < m; ++j)
+        acc = acc + ld(c.G, j * 64 + gs * 8 + gt) * ld(c.vecG, (long long)(kk * m + j) * n + nu);
     }
-    c.P[e] = mk<T>((T)(v.re * sc), (T)(v.im * sc));
+    c.Qop[e] = mk<T>((T)(sc * acc.re), (T)(sc * acc.im));
   }
   if (threadIdx.x == 0) {
-    {  // Psi2[o] = P^T Psi[o] for every o = (l s1 k1 s2)
-      GemmDesc& d = *c.dProj;
+    {  // Psi2[alpha] = Qop Psi[alpha]
+      GemmDesc& d = *c.dPsi2;
       clear_desc(d);
-      d.A = c.P; d.B = c.Psi; d.C = c.Psi2;
-      d.opA = OP_T;
-      d.M = kp; d.K = n; d.N = inner;
-      d.lda = kp; d.ldb = inner; d.ldc = inner;
-      d.nbatch = cl * 4 * k1;
-      d.sA = 0; d.sB = (long long)n * inner; d.sC = (long long)kp * inner;
+      d.A = c.Qop; d.B = c.Psi; d.C = c.Psi2;
+      d.M = rows; d.K = cols; d.N = r3;
+      d.lda = cols; d.ldb = r3; d.ldc = r3;
+      d.nbatch = rN; d.sA = 0; d.sB = (long long)cols * r3; d.sC = (long long)rows * r3;
     }
-    {  // G1 = Psi2 Psi2^H over rows (l s1 k1)
-      GemmDesc& d = *c.dG1;
+    {  // C1 = Psi2 Psi2^H over rows (alpha s1)
+      GemmDesc& d = *c.dC1;
       void* C = d.C;
       const long long ss = d.sSplit;
       clear_desc(d);
       d.C = C; d.sSplit = ss;
       d.A = c.Psi2; d.B = c.Psi2; d.opA = OP_N; d.opB = OP_H;
-      d.M = d.N = cl * 2 * k1;
-      d.K = 2 * kp * inner;
-      d.lda = d.ldb = 2 * kp * inner;
-      d.ldc = cl * 2 * k1;
-      d.splits = splitsG;
+      d.M = d.N = 2 * rN;
+      d.K = 4 * kp * r3;
+      d.lda = d.ldb = 4 * kp * r3;
+      d.ldc = 2 * rN;
+      d.splits = splitsC;
     }
+    EigDesc& e = *c.e1;
+    e.lda = 2 * rN; e.n = 2 * rN; e.evals = c.ev1; e.evecs = c.vec1; e.trace = c.ev1 + 2 * rN; e.active = 1;
   }
 }
 
-// G1[x][y] *= lambda_l(x) lambda_l(y); eigensolver descriptor
+// bond i: rank r1, weights, U1 and U1 S1 / sqrt(kept); descriptors of
+// Y1 = P D^-1/2 U1 S1 / sqrt(kept) (FP64), W1 = U1^H Psi2 / sqrt(kept),
+// BiP = Bp Y1 and C2 = W1^H W1 over rows (r1 s2 nu).
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q3_scale1(Ctx3<T>* ctxs) {
-  Ctx3<T>& c = ctxs[blockIdx.x];
-  const int k1 = *c.kap1, n = *c.chil * 2 * k1;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int x = e / n, y = e % n;
-    const double f = sqrt(c.laml2[x / (2 * k1)] * c.laml2[y / (2 * k1)]);
-    c.G1[2 * e] *= f;
-    c.G1[2 * e + 1] *= f;
-  }
-  if (threadIdx.x == 0) {
-    EigDesc& e = *c.dE1;
-    e.a = c.G1; e.lda = n; e.n = n; e.evals = c.ev1; e.evecs = c.vec1; e.trace = c.ev1 + n; e.active = 1;
-  }
-}
-
-// bond i: rank, weights, T_i = lambda^-1 U S / sqrt(kept), V1 = S^-1 U^H (lambda Psi2); descriptor of G2
-template <typename T>
-__global__ __launch_bounds__(GT) void k_q3_select_1(Ctx3<T>* ctxs, int splitsG, TruncParams tp) {
+__global__ __launch_bounds__(GT) void k_q3_sel_1(Ctx3<T>* ctxs, int splitsC, TruncParams tp) {
   __shared__ int s_r;
   __shared__ double s_kept;
   Ctx3<T>& c = ctxs[blockIdx.x];
-  const int k1 = *c.kap1, n = *c.chil * 2 * k1;
-  const int kp = c.scratch[0], inner = 2 * (*c.kap3) * (*c.chir);
+  const int cl = *c.chil, ca = *c.chim1, k1 = *c.kap1;
+  const int kp = c.scratch[0], rN = c.scratch[1], r3 = c.scratch[2];
+  const int n = 2 * rN;
   if (threadIdx.x == 0) {
     double kept, tot;
     const int r = select_rank(c.ev1, min(n, tp.chi_max + 1), n, c.ev1[n], tp.chi_max, tp.svd_cut, &kept, &tot);
     s_r = r;
     s_kept = kept;
     if (tot > 0) *c.disc += (tot - kept) / tot;
-    c.scratch[1] = r;
+    c.scratch[3] = r;
+    c.kept[0] = kept;
   }
   __syncthreads();
   const int r = s_r;
-  const double kept = s_kept;
+  const double kept = s_kept, isk = 1.0 / sqrt(kept);
   for (int v = threadIdx.x; v < r; v += blockDim.x) {
     const double e = c.ev1[v] > 0 ? c.ev1[v] : 0.0;
     c.lam1[v] = sqrt(e / kept);
     c.lam1sq[v] = e / kept;
   }
-  // Q1 = Lambda U S^-1 (for V1) and T_i = Lambda^-1 U S / sqrt(kept), both from
-  // the FP64 eigenvectors: forming T_i as Psi2 V1^H would carry the rounding of
-  // V1's small-sigma rows (relative eps / sigma) into unweighted columns.
-  const double isk = 1.0 / sqrt(kept);
   for (int e = threadIdx.x; e < n * r; e += blockDim.x) {
     const int x = e / r, rho = e % r;
     const cpx<double> u = ld(c.vec1, (long long)x * n + rho);
-    const double ll = sqrt(c.laml2[x / (2 * k1)]), s = sqrt(c.ev1[rho]);
-    const double f = ll / s, g = s / ll * isk;
-    c.Q1[e] = mk<T>((T)(u.re * f), (T)(u.im * f));
-    c.Bi_new[e] = mk<T>((T)(u.re * g), (T)(u.im * g));
+    const double g = sqrt(c.ev1[rho] > 0 ? c.ev1[rho] : 0.0) * isk;
+    c.U1[e] = mk<T>((T)u.re, (T)u.im);
+    st(c.U1s, e, mk(u.re * g, u.im * g));
   }
   if (threadIdx.x == 0) {
-    const int n2cols = 2 * kp * inner;
-    {
-      GemmDesc& d = *c.dV1;
+    {  // Y1[(t1 a), (s1 rho)] = sum_alpha PND[(t1 a), alpha] U1s[(alpha s1), rho]
+      GemmDesc& d = *c.dY1;
       clear_desc(d);
-      d.A = c.Q1; d.B = c.Psi2; d.C = c.V1;
-      d.opA = OP_H;
-      d.M = r; d.K = n; d.N = n2cols;
-      d.lda = r; d.ldb = n2cols; d.ldc = n2cols;
+      d.A = c.PND; d.B = c.U1s; d.C = c.Y1;
+      d.M = 2 * ca; d.K = rN; d.N = 2 * r;
+      d.lda = rN; d.ldb = 2 * r; d.ldc = 2 * r;
     }
-    {
-      GemmDesc& d = *c.dG2;
+    {  // W1 = U1^H Psi2 / sqrt(kept)
+      GemmDesc& d = *c.dW1;
+      clear_desc(d);
+      d.A = c.U1; d.B = c.Psi2; d.C = c.W1;
+      d.opA = OP_H;
+      d.M = r; d.K = n; d.N = 4 * kp * r3;
+      d.lda = r; d.ldb = 4 * kp * r3; d.ldc = 4 * kp * r3;
+      d.alpha = isk;
+    }
+    {  // BiP[(l k1), (s1 rho)] = Bp Y1
+      GemmDesc& d = *c.dBiP;
+      clear_desc(d);
+      d.A = c.Bp; d.B = c.Y1; d.C = c.BiP;
+      d.M = cl * k1; d.K = 2 * ca; d.N = 2 * r;
+      d.lda = 2 * ca; d.ldb = 2 * r; d.ldc = 2 * r;
+    }
+    {  // C2[(s3 beta), (s3' beta')] = sum_{(rho s2 nu)} conj(W1) W1
+      GemmDesc& d = *c.dC2;
       void* C = d.C;
       const long long ss = d.sSplit;
       clear_desc(d);
       d.C = C; d.sSplit = ss;
-      d.A = c.V1; d.B = c.V1; d.opA = OP_N; d.opB = OP_H;
-      d.M = d.N = r * 2 * kp;
-      d.K = inner;
-      d.lda = d.ldb = inner;
-      d.ldc = r * 2 * kp;
-      d.splits = splitsG;
+      d.A = c.W1; d.B = c.W1; d.opA = OP_H; d.opB = OP_N;
+      d.M = d.N = 2 * r3;
+      d.K = r * 2 * kp;
+      d.lda = d.ldb = 2 * r3;
+      d.ldc = 2 * r3;
+      d.splits = splitsC;
     }
+    EigDesc& e = *c.e2;
+    e.lda = 2 * r3; e.n = 2 * r3; e.evals = c.ev2; e.evecs = c.vec2; e.trace = c.ev2 + 2 * r3; e.active = 1;
   }
 }
 
+// B_i'[l, s1, k1, rho] = BiP[(l k1), (s1 rho)]
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q3_scale2(Ctx3<T>* ctxs) {
-  Ctx3<T>& c = ctxs[blockIdx.x];
-  const int kp = c.scratch[0], r = c.scratch[1], n = r * 2 * kp;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int x = e / n, y = e % n;
-    const double f = c.lam1[x / (2 * kp)] * c.lam1[y / (2 * kp)];
-    c.G2[2 * e] *= f;
-    c.G2[2 * e + 1] *= f;
-  }
-  if (threadIdx.x == 0) {
-    EigDesc& e = *c.dE2;
-    e.a = c.G2; e.lda = n; e.n = n; e.evals = c.ev2; e.evecs = c.vec2; e.trace = c.ev2 + n; e.active = 1;
+__global__ __launch_bounds__(GT) void k_q3_perm_out(Ctx3<T>* ctxs) {
+  Ctx3<T>& c = ctxs[blockIdx.y];
+  const int cl = *c.chil, k1 = *c.kap1, r = c.scratch[3];
+  const long long total = (long long)cl * 2 * k1 * r;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int rho = (int)(e % r);
+    long long rest = e / r;
+    const int kk = (int)(rest % k1);
+    rest /= k1;
+    const int s1 = (int)(rest % 2);
+    const int l = (int)(rest / 2);
+    c.Bi_new[e] = c.BiP[(((long long)l * k1 + kk) * 2 + s1) * r + rho];
   }
 }
 
-// bond i+1: rank, weights, T_{i+1} = lambda'^-1 U2 S2 / sqrt(kept), T_{i+2} = S2^-1 U2^H (lambda' V1)
+// bond i+1: rank r2, weights, Z2; descriptors of Y3 = Z2^H (P3 D3^-1/2)^H
+// (FP64), B_{i+2}' = Y3 F and B_{i+1}' = W1 Z2 / sqrt(kept) (rows rescaled by
+// 1 / lambda' afterwards).
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q3_select_2(Ctx3<T>* ctxs, TruncParams tp) {
+__global__ __launch_bounds__(GT) void k_q3_sel_2(Ctx3<T>* ctxs, TruncParams tp) {
   __shared__ int s_r;
   __shared__ double s_kept;
   Ctx3<T>& c = ctxs[blockIdx.x];
-  const int kp = c.scratch[0], r1 = c.scratch[1], n = r1 * 2 * kp;
-  const int inner = 2 * (*c.kap3) * (*c.chir);
+  const int cb = *c.chim2, cr = *c.chir, k3 = *c.kap3;
+  const int kp = c.scratch[0], r3 = c.scratch[2], r1 = c.scratch[3];
+  const int n = 2 * r3;
   if (threadIdx.x == 0) {
     double kept, tot;
     const int r = select_rank(c.ev2, min(n, tp.chi_max + 1), n, c.ev2[n], tp.chi_max, tp.svd_cut, &kept, &tot);
     s_r = r;
     s_kept = kept;
     if (tot > 0) *c.disc += (tot - kept) / tot;
-    c.scratch[2] = r;
+    c.scratch[4] = r;
+    c.kept[1] = kept;
   }
   __syncthreads();
   const int r = s_r;
@@ -758,28 +855,60 @@ __global__ __launch_bounds__(GT) void k_q3_select_2(Ctx3<T>* ctxs, TruncParams t
     c.lam2[v] = sqrt(e / kept);
     c.lam2sq[v] = e / kept;
   }
-  // Q2 = lambda' U2 S2^-1 (for T_{i+2}) and T_{i+1} = lambda'^-1 U2 S2 / sqrt(kept)
-  const double isk = 1.0 / sqrt(kept);
+  // Zt3[(rho s3), beta] = conj(Z2[(s3 beta), rho]),  Z2c = Z2[:, :r]
+  for (int e = threadIdx.x; e < 2 * r * r3; e += blockDim.x) {
+    const int row = e / r3, be = e % r3;
+    const int rho = row / 2, s3 = row % 2;
+    st(c.Zt3, e, cconj(ld(c.vec2, (long long)(s3 * r3 + be) * n + rho)));
+  }
   for (int e = threadIdx.x; e < n * r; e += blockDim.x) {
     const int y = e / r, rho = e % r;
-    const cpx<double> u = ld(c.vec2, (long long)y * n + rho);
-    const double l1 = c.lam1[y / (2 * kp)], s = sqrt(c.ev2[rho]);
-    const double f = l1 / s, g = s / l1 * isk;
-    c.Q2[e] = mk<T>((T)(u.re * f), (T)(u.im * f));
-    c.Bj_new[e] = mk<T>((T)(u.re * g), (T)(u.im * g));
+    const cpx<double> z = ld(c.vec2, (long long)y * n + rho);
+    c.Z2c[e] = mk<T>((T)z.re, (T)z.im);
   }
-  __syncthreads();
   if (threadIdx.x == 0) {
-    {
-      GemmDesc& d = *c.dTk;
+    {  // Y3[(rho s3), (b t3)] = sum_beta Zt3[(rho s3), beta] conj(PD3[(b t3), beta])
+      GemmDesc& d = *c.dY3;
       clear_desc(d);
-      d.A = c.Q2; d.B = c.V1; d.C = c.Bk_new;
-      d.opA = OP_H;
-      d.M = r; d.K = n; d.N = inner;
-      d.lda = r; d.ldb = inner; d.ldc = inner;
+      d.A = c.Zt3; d.B = c.PD3; d.C = c.Y3;
+      d.opB = OP_H;
+      d.M = 2 * r; d.K = r3; d.N = 2 * cb;
+      d.lda = r3; d.ldb = r3; d.ldc = 2 * cb;
     }
+    {  // B_{i+2}'[(rho s3), (k3 r)] = Y3 F
+      GemmDesc& d = *c.dBk;
+      clear_desc(d);
+      d.A = c.Y3; d.B = c.Bk; d.C = c.Bk_new;
+      d.M = 2 * r; d.K = 2 * cb; d.N = k3 * cr;
+      d.lda = 2 * cb; d.ldb = k3 * cr; d.ldc = k3 * cr;
+    }
+    {  // B_{i+1}'[(rho1 s2 nu), rho] = W1[(rho1 s2 nu), (s3 beta)] Z2[(s3 beta), rho] / sqrt(kept)
+      GemmDesc& d = *c.dBj;
+      clear_desc(d);
+      d.A = c.W1; d.B = c.Z2c; d.C = c.Bj_new;
+      d.M = r1 * 2 * kp; d.K = n; d.N = r;
+      d.lda = n; d.ldb = r; d.ldc = r;
+      d.alpha = 1.0 / sqrt(kept);
+    }
+  }
+}
+
+// B_{i+1}' rows (rho1, s2, nu) divided by lambda'_rho1; the new dimensions.
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q3_finish(Ctx3<T>* ctxs) {
+  Ctx3<T>& c = ctxs[blockIdx.y];
+  const int kp = c.scratch[0], r1 = c.scratch[3], r2 = c.scratch[4];
+  const long long row = 2LL * kp * r2;
+  const long long total = (long long)r1 * row;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double f = 1.0 / c.lam1[e / row];
+    const cpx<T> v = c.Bj_new[e];
+    c.Bj_new[e] = mk<T>((T)(v.re * f), (T)(v.im * f));
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     *c.chim1 = r1;
-    *c.chim2 = r;
+    *c.chim2 = r2;
     *c.kap2 = kp;
   }
 }
@@ -1105,26 +1234,33 @@ template <typename T> void launch_q2_select_g(Ctx2<T>* d, int n, int splitsC, Tr
 template <typename T> void launch_q2_select_b(Ctx2<T>* d, int n, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_select_b<T>, dim3(n), dim3(GT), 0, s, d, tp);
 }
-template <typename T> void launch_q3_prepare(Ctx3<T>* d, int n, int splitsH, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q3_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsH);
+template <typename T> void launch_q3_prepare(Ctx3<T>* d, int n, int splitsN, int splitsE, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsN, splitsE);
 }
-template <typename T> void launch_q3_apply(Ctx3<T>* d, int n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q3_apply<T>, dim3(1024, n), dim3(GT), 0, s, d);
+template <typename T> void launch_q3_perm_in(Ctx3<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_perm_in<T>, dim3(256, n), dim3(GT), 0, s, d);
 }
-template <typename T> void launch_q3_select_h(Ctx3<T>* d, int n, int splitsG, TruncParams tp, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q3_select_h<T>, dim3(n), dim3(GT), 0, s, d, splitsG, tp);
+template <typename T> void launch_q3_sel_env(Ctx3<T>* d, int n, int splitsH, double floor, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_sel_env<T>, dim3(n), dim3(GT), 0, s, d, splitsH, floor);
 }
-template <typename T> void launch_q3_scale1(Ctx3<T>* d, int n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q3_scale1<T>, dim3(n), dim3(GT), 0, s, d);
+template <typename T> void launch_q3_gamma(Ctx3<T>* d, int n, int mmax, hipStream_t s) {
+  const int pairs = mmax > 1 ? mmax * mmax : 1;
+  if (n > 0) hipLaunchKernelGGL(k_q3_gamma<T>, dim3(pairs, n), dim3(GT), 0, s, d);
 }
-template <typename T> void launch_q3_select_1(Ctx3<T>* d, int n, int splitsG, TruncParams tp, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q3_select_1<T>, dim3(n), dim3(GT), 0, s, d, splitsG, tp);
+template <typename T> void launch_q3_sel_h(Ctx3<T>* d, int n, int splitsC, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_sel_h<T>, dim3(n), dim3(GT), 0, s, d, splitsC, tp);
 }
-template <typename T> void launch_q3_scale2(Ctx3<T>* d, int n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q3_scale2<T>, dim3(n), dim3(GT), 0, s, d);
+template <typename T> void launch_q3_sel_1(Ctx3<T>* d, int n, int splitsC, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_sel_1<T>, dim3(n), dim3(GT), 0, s, d, splitsC, tp);
 }
-template <typename T> void launch_q3_select_2(Ctx3<T>* d, int n, TruncParams tp, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q3_select_2<T>, dim3(n), dim3(GT), 0, s, d, tp);
+template <typename T> void launch_q3_perm_out(Ctx3<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_perm_out<T>, dim3(256, n), dim3(GT), 0, s, d);
+}
+template <typename T> void launch_q3_sel_2(Ctx3<T>* d, int n, TruncParams tp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_sel_2<T>, dim3(n), dim3(GT), 0, s, d, tp);
+}
+template <typename T> void launch_q3_finish(Ctx3<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q3_finish<T>, dim3(128, n), dim3(GT), 0, s, d);
 }
 template <typename T> void launch_sw_prepare(CtxS<T>* d, int n, int splits, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_sw_prepare<T>, dim3(n), dim3(GT), 0, s, d, splits);
@@ -1168,13 +1304,15 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_q2_gamma<T>(Ctx2<T>*, int, hipStream_t);                               \
   template void launch_q2_select_g<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_select_b<T>(Ctx2<T>*, int, TruncParams, hipStream_t);              \
-  template void launch_q3_prepare<T>(Ctx3<T>*, int, int, hipStream_t);                        \
-  template void launch_q3_apply<T>(Ctx3<T>*, int, hipStream_t);                               \
-  template void launch_q3_select_h<T>(Ctx3<T>*, int, int, TruncParams, hipStream_t);          \
-  template void launch_q3_scale1<T>(Ctx3<T>*, int, hipStream_t);                              \
-  template void launch_q3_select_1<T>(Ctx3<T>*, int, int, TruncParams, hipStream_t);          \
-  template void launch_q3_scale2<T>(Ctx3<T>*, int, hipStream_t);                              \
-  template void launch_q3_select_2<T>(Ctx3<T>*, int, TruncParams, hipStream_t);               \
+  template void launch_q3_prepare<T>(Ctx3<T>*, int, int, int, hipStream_t);                   \
+  template void launch_q3_perm_in<T>(Ctx3<T>*, int, hipStream_t);                             \
+  template void launch_q3_sel_env<T>(Ctx3<T>*, int, int, double, hipStream_t);                \
+  template void launch_q3_gamma<T>(Ctx3<T>*, int, int, hipStream_t);                          \
+  template void launch_q3_sel_h<T>(Ctx3<T>*, int, int, TruncParams, hipStream_t);             \
+  template void launch_q3_sel_1<T>(Ctx3<T>*, int, int, TruncParams, hipStream_t);             \
+  template void launch_q3_perm_out<T>(Ctx3<T>*, int, hipStream_t);                            \
+  template void launch_q3_sel_2<T>(Ctx3<T>*, int, TruncParams, hipStream_t);                  \
+  template void launch_q3_finish<T>(Ctx3<T>*, int, hipStream_t);                              \
   template void launch_sw_prepare<T>(CtxS<T>*, int, int, hipStream_t);                        \
   template void launch_sw_select<T>(CtxS<T>*, int, TruncParams, hipStream_t);                 \
   template void launch_sw_normalize<T>(CtxS<T>*, int, hipStream_t);                           \

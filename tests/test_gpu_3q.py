@@ -1,7 +1,9 @@
 """Three-site noisy gates (crosstalk channels on neighbouring triples) on the
 GPU against the oracle MPDO: observables, bond and inner dimensions, bond
 weights and discarded weight; a unitary three-site gate; Kraus pruning by
-weight against the oracle's counts."""
+weight against the oracle's counts; batched runs.  The cases include
+kappa_max chi_max = 512 (the bond Grams at 4 chi) and a middle inner index of
+16 x 64 Kraus operators (a Gamma eigenproblem of size 1024)."""
 import math
 
 import numpy as np
@@ -32,7 +34,8 @@ def _run_both(prog, chi, kap, eps, prec, max_kraus):
 
 @pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
 @pytest.mark.parametrize("n,depth,chi,kap,eps,tag", [(6, 2, 16, 4, 1e-4, 1), (5, 2, 8, 4, 0.0, 2),
-                                                      (7, 3, 16, 8, 1e-3, 3)])
+                                                      (7, 3, 16, 8, 1e-3, 3), (5, 2, 64, 8, 1e-4, 4),
+                                                      (4, 2, 16, 16, 0.0, 5), (6, 4, 64, 8, 1e-4, 6)])
 def test_crosstalk_circuit_matches_oracle(prec, n, depth, chi, kap, eps, tag):
     require_gpu()
     rng = W.rng_for(400 + tag)
@@ -73,15 +76,6 @@ def test_kraus_pruning_counts(eps):
     ch = M.Channel(chi, 3, eps=eps)
     ko = OC.kraus_from_chi(chi, eps)[0]
     assert ch.nkraus == len(ko)
-
-
-def test_three_site_limits_are_reported():
-    require_gpu()
-    st = M.MPDO(4, chi_max=128, kappa_max=4, max_kraus=16)
-    ch = M.Channel(W.random_cptp_near_identity_3q(W.rng_for(1)), 3, eps=1e-3)
-    with pytest.raises(M.MPDOError) as e:
-        st.apply_channel([0, 1, 2], ch)
-    assert e.value.status == M.EUNSUPPORTED
 
 
 @pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])

@@ -66,7 +66,7 @@ def test_gemm_split_k_and_weights(tile):
     assert err < 1e-13, err
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 32, 64, 65, 100, 128, 256, 512])
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 32, 64, 65, 100, 128, 256, 512, 513, 1024])
 def test_eigh_against_numpy(n):
     require_gpu()
     rng = np.random.default_rng(n)
@@ -79,13 +79,14 @@ def test_eigh_against_numpy(n):
     e2 = float(np.abs(V.conj().T @ V - np.eye(n)).max())
     e3 = float(np.abs(A @ V - V * ev).max()) / scale
     # inverse iteration: orthogonality ~ eps ||A|| / gap for the dense
-    # Wishart spectrum near zero, residuals at eps
-    assert e1 <= 1e-13 and e2 < 1e-11 and e3 < 1e-12, (e1, e2, e3)
+    # Wishart spectrum near zero (the gaps there shrink as n grows), residuals
+    # at eps
+    assert e1 <= 1e-13 and e2 < 2e-14 * max(n, 500) and e3 < 1e-12, (e1, e2, e3)
     assert abs(tr - np.trace(A).real) < 1e-12 * scale * n
     assert bool(np.all(np.diff(ev) <= 0))
 
 
-@pytest.mark.parametrize("n,kvec", [(40, 5), (128, 16), (256, 64), (300, 100)])
+@pytest.mark.parametrize("n,kvec", [(40, 5), (128, 16), (256, 64), (300, 100), (700, 17), (1024, 16)])
 def test_eigh_leading_subset(n, kvec):
     """Only the leading kvec eigenpairs (and kvec + 1 eigenvalues) are produced."""
     require_gpu()
