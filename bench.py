@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=64, help="parameter points per step (batched mode)")
     ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-fidelity leg (C5 variational loop)")
     ap.add_argument("--ttf-steps", type=int, default=30)
+    ap.add_argument("--no-crosstalk", action="store_true",
+                    help="skip the crosstalk leg (three-site channels, Kraus pruning thresholds)")
     ap.add_argument("--graph", action="store_true",
                     help="capture each batched step into one HIP graph (the roofline then comes from one "
                          "extra profiled step outside the timed region)")
@@ -187,6 +189,20 @@ def ttf_leg(steps):
             "note": "surrogate seconds include its online training; no pre-training data"}
 
 
+def crosstalk_leg():
+    """Three-site crosstalk channels with Kraus pruning: the random circuit n=24,
+    depth 12, chi=128, kappa=16, mixed precision, once per pruning threshold;
+    observables <Z_i>, <Z_i Z_i+1> of every run against the eps = 0 run."""
+    from paper_2508_07610_amd import crosstalk as X
+    res = X.run(n=24, depth=12, chi_max=128, kappa_max=16, eps_list=(0.0, 1e-4, 1e-3))
+    return {"workload": "random RX/RY/RZ + CZ-brick circuit n=24 depth=12, 2q channel after every CZ and a random "
+                        "CPTP 3-site channel on the neighbouring triple, chi=128 kappa=16 svd_cutoff=1e-10, "
+                        "c64 contractions with FP64 Grams/eigensolvers, per-gate C-ABI calls",
+            "runs": [{"eps": r["eps"], "kraus_counts": r["kraus"], "seconds": r["seconds"],
+                      "discarded_weight": r["discarded"], "trace": r["trace"], "max_bond": r["max_bond"],
+                      "max_obs_dev_vs_eps0": r["max_dev_vs_eps0"]} for r in res]}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -257,6 +273,7 @@ def main():
         "kernel_time_ms": share,
         "cpu_baseline": None if a.no_cpu else cpu_baseline(W, a.cpu_layers),
         "time_to_fidelity": None if a.no_ttf else ttf_leg(a.ttf_steps),
+        "crosstalk": None if a.no_crosstalk else crosstalk_leg(),
     }
     print(json.dumps(out))
 

@@ -109,3 +109,22 @@ def test_batch_run_with_crosstalk(prec):
         got = out[off: off + len(ob)]
         off += len(ob)
         assert float(np.abs(got - ref).max()) < tol, (pr.n, float(np.abs(got - ref).max()))
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-4])
+def test_crosstalk_workload_at_full_bond_and_inner_limits(eps):
+    """The crosstalk workload at chi=128, kappa=16 (n=24): both precisions give
+    a normalised state (trace 1) and agree on every <Z_i>, <Z_i Z_i+1> to the
+    tolerance of the mixed path; bonds and inner indices respect their limits
+    (no oracle at this size: the properties hold at any size)."""
+    require_gpu()
+    from paper_2508_07610_amd import crosstalk as X
+    n, depth = 24, 4
+    r64 = X.run(n=n, depth=depth, chi_max=128, kappa_max=16, eps_list=(eps,), prec=M.C64_MIXED)[0]
+    r128 = X.run(n=n, depth=depth, chi_max=128, kappa_max=16, eps_list=(eps,), prec=M.C128)[0]
+    assert abs(r128["trace"] - 1) < 1e-10
+    assert abs(r64["trace"] - 1) < 1e-4
+    assert r128["max_bond"] <= 128 and r128["max_inner"] <= 16
+    assert float(np.abs(r64["obs"] - r128["obs"]).max()) < 1e-5
+    assert float(np.abs(r128["obs"]).max()) <= 1 + 1e-12
+    assert r128["max_bond"] > 32
