@@ -107,13 +107,20 @@ def observables(n):
     return np.stack(ops)
 
 
-def kernel_sources_hash():
+# sources that decide a kernel class's code and the shapes it is launched with
+KERNEL_SOURCES = {
+    "k_gemm": ("gemm.hip", "common.h", "ops.hip", "ops.h", "engine.hip", "engine.h", "kernels.h"),
+    "k_heev": ("eigh.hip", "common.h", "ops.hip", "engine.hip", "kernels.h"),
+}
+
+
+def kernel_sources_hash(kernel):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2508_07610_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    key = "k_gemm" if kernel.startswith("k_gemm") else "k_heev"
+    for f in KERNEL_SOURCES[key]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -127,7 +134,7 @@ def traffic_for(kernel, launches_per_step):
     except (OSError, ValueError):
         return None
     e = t.get(kernel)
-    if not e or e.get("sources") != kernel_sources_hash():
+    if not e or e.get("sources") != kernel_sources_hash(kernel):
         return None
     return e.get("bytes_per_launch")
 
@@ -275,7 +282,7 @@ def main():
         "time_to_fidelity": None if a.no_ttf else ttf_leg(a.ttf_steps),
         "crosstalk": None if a.no_crosstalk else crosstalk_leg(),
     }
-    print(json.dumps(out))
+    print(json.dumps(out, default=lambda o: o.item() if hasattr(o, "item") else str(o)))
 
 
 if __name__ == "__main__":
