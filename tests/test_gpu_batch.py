@@ -105,3 +105,29 @@ def test_batch_rejects_bad_programs():
     with pytest.raises(M.MPDOError) as e:
         M.batch_run([bad], None, chans, [np.zeros((0, 4, 2, 2))], chi_max=8, kappa_max=2)
     assert e.value.status == M.EINVAL
+
+
+def test_mixed_ghz_and_maxcut_batch_at_full_size():
+    """256 ansatz points (n=12, depth 6) and 128 QAOA p=2 MaxCut instances
+    (n in 8..20) in one graph-captured batch (chi=32, kappa=4, mixed
+    precision): a sample of instances equals the plain per-gate path of the
+    same precision to the mixed path's accuracy target (both are FP32
+    contractions, summed in different orders by different launch shapes), and
+    every <H_cut> lies in [0, |E|]."""
+    require_gpu()
+    from paper_2508_07610_amd import maxcut as MC
+    r = MC.run(n_ghz=256, n_qaoa=128, repeats=1)
+    per, progs, obs = r["instances"], r["programs"], r["observables"]
+    assert len(per) == 384
+    for p in per:
+        if p["kind"] == "qaoa":
+            assert -1e-6 <= p["h_cut"] <= p["edges"] + 1e-6
+        else:
+            assert -1e-6 <= p["ghz_fidelity"] <= 1 + 1e-6
+    kw = r["config"]
+    for b in (0, 255, 256, 300, 383):
+        st = M.MPDO(progs[b].n, **kw)
+        M.run_program(progs[b], st, r["channels"])
+        plain = st.expect_products(obs[b]).real
+        got = np.array(per[b]["zz"] if per[b]["kind"] == "ghz" else per[b]["zz_edges"])
+        assert float(np.abs(got - plain[: len(got)]).max()) < 1e-5, b
