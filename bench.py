@@ -222,12 +222,17 @@ def crosstalk_leg():
     observables <Z_i>, <Z_i Z_i+1> of every run against the eps = 0 run."""
     from paper_2508_07610_amd import crosstalk as X
     res = X.run(n=24, depth=12, chi_max=128, kappa_max=16, eps_list=(0.0, 1e-4, 1e-3))
+    small = X.run(n=8, depth=12, chi_max=64, kappa_max=16, eps_list=(0.0, 1e-4, 1e-3), dense=True)
     return {"workload": "random RX/RY/RZ + CZ-brick circuit n=24 depth=12, 2q channel after every CZ and a random "
                         "CPTP 3-site channel on the neighbouring triple, chi=128 kappa=16 svd_cutoff=1e-10, "
                         "c64 contractions with FP64 Grams/eigensolvers, per-gate C-ABI calls",
             "runs": [{"eps": r["eps"], "kraus_counts": r["kraus"], "seconds": r["seconds"],
                       "discarded_weight": r["discarded"], "trace": r["trace"], "max_bond": r["max_bond"],
-                      "max_obs_dev_vs_eps0": r["max_dev_vs_eps0"]} for r in res]}
+                      "max_obs_dev_vs_eps0": r["max_dev_vs_eps0"]} for r in res],
+            "slice_n8": {"note": "same construction at n=8, chi=64 (dense states from mpdo_to_dense); Uhlmann fidelity "
+                                 "F(rho_eps0, rho_eps) computed on the host from the two dense matrices",
+                         "fidelity_vs_eps0": {str(r["eps"]): r["fidelity_vs_eps0"] for r in small},
+                         "seconds": {str(r["eps"]): r["seconds"] for r in small}}}
 
 
 def main():

@@ -157,6 +157,15 @@ mpdo_status mpdo_dims(mpdo_t h, int32_t* bonds, int32_t* inner, double* discarde
  * `cap` doubles and the count to *len. */
 mpdo_status mpdo_bond_weights(mpdo_t h, int32_t b, double* out, int32_t cap, int32_t* len);
 
+/* The dense density matrix (Eqs. (6)-(7): the per-site tensors summed over
+ * the inner index, contracted along the chain) for n <= 12: rho is host
+ * memory of 2^n x 2^n complex doubles, row-major, qubit 0 the most
+ * significant bit of the row and column indices.  For verification: the
+ * contraction runs on the device in FP64 (in both precisions) and needs
+ * about 5 x 16 x max(4^(n/2) chi^2, 4 chi^4, 4^n) bytes of scratch;
+ * EUNSUPPORTED above 16 GiB, EINVAL for n > 12. */
+mpdo_status mpdo_to_dense(mpdo_t h, double* rho);
+
 /* ---------------------------------------------------------------------------
  * Batched execution: many independent instances (parameter points, graphs of
  * different sizes) advanced together, every sublayer of every instance in

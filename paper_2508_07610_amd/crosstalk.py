@@ -42,12 +42,27 @@ def z_products(n: int) -> np.ndarray:
     return np.stack(ops)
 
 
+def uhlmann_fidelity(rho: np.ndarray, sigma: np.ndarray) -> float:
+    """F(rho, sigma) = (Tr sqrt(sqrt(rho) sigma sqrt(rho)))^2 (the fidelity the
+    paper uses to compare truncated and untruncated states), for two dense
+    density matrices of unit trace; a host-side measurement of results."""
+    w, v = np.linalg.eigh((rho + rho.conj().T) / 2)
+    w = np.where(w > 1e-12 * w.max(), w, 0.0)          # rounding-level eigenvalues are zero
+    sq = (v * np.sqrt(w)) @ v.conj().T
+    mid = sq @ ((sigma + sigma.conj().T) / 2) @ sq
+    ev = np.linalg.eigvalsh((mid + mid.conj().T) / 2)
+    ev = np.where(ev > 1e-12 * ev.max(), ev, 0.0)
+    return float(np.sum(np.sqrt(ev)) ** 2)
+
+
 def run(n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,
         eps_list: Sequence[float] = (0.0, 1e-4, 1e-3), prec: int = M.C64_MIXED,
-        seed_tag: int = 0) -> List[Dict]:
+        seed_tag: int = 0, dense: bool = False) -> List[Dict]:
     """One run per eps; returns per eps the Kraus counts of the channels, the
     wall time, the summed discarded weight, the observables and their largest
-    deviation from the eps = 0 run (the first entry of eps_list)."""
+    deviation from the eps = 0 run (the first entry of eps_list).  With
+    `dense` (n <= 12) also the dense state of each run (trace-normalised) and
+    its fidelity with the first run's."""
     import torch
     prog = circuit(n, depth, seed_tag)
     qs = [int(round(np.log(c.shape[0]) / np.log(4))) for c in prog.chis]
@@ -68,9 +83,15 @@ def run(n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,
         bonds, inner, disc = st.dims()
         rec = {"eps": eps, "kraus": [ch.nkraus for ch in chans], "seconds": dt, "discarded": disc,
                "max_bond": max(bonds), "max_inner": max(inner), "trace": st.trace(), "obs": vals}
+        if dense:
+            rho = st.to_dense()
+            rec["rho"] = rho / np.trace(rho).real
         if ref is None:
             ref = vals
+            rho0 = rec.get("rho")
         rec["max_dev_vs_eps0"] = float(np.abs(vals - ref).max())
+        if dense:
+            rec["fidelity_vs_eps0"] = uhlmann_fidelity(rho0, rec["rho"])
         out.append(rec)
         st.close()
         for ch in chans:

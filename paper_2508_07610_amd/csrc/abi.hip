@@ -42,6 +42,7 @@ struct AnyEngine {
     d ? d->dims(b, bo, in, disc) : f->dims(b, bo, in, disc);
   }
   std::vector<double> bond_weights(int b, int bond) { return d ? d->bond_weights(b, bond) : f->bond_weights(b, bond); }
+  void to_dense(int b, double* host) { d ? d->to_dense(b, host) : f->to_dense(b, host); }
   double truncate_sweep(int b, int c, int k, double cut) {
     return d ? d->truncate_sweep(b, c, k, cut) : f->truncate_sweep(b, c, k, cut);
   }
@@ -385,6 +386,17 @@ mpdo_status mpdo_dims(mpdo_t h, int32_t* bonds, int32_t* inner, double* discarde
   if (bonds) std::memcpy(bonds, b.data(), sizeof(int) * b.size());
   if (inner) std::memcpy(inner, k.data(), sizeof(int) * k.size());
   if (discarded) *discarded = d;
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_to_dense(mpdo_t h, double* rho) {
+  if (!h || !rho) return fail(MPDO_EINVAL, "null argument");
+  if (h->dead) return fail(MPDO_EDEVICE, "handle is unusable after a device error");
+  if (h->cfg.n > 12) return fail(MPDO_EINVAL, "dense state needs n <= 12");
+  GUARD_BEGIN
+  flush_queue(h);
+  h->eng.to_dense(0, rho);
   return MPDO_OK;
   GUARD_END
 }

@@ -103,6 +103,8 @@ template <typename T> class Engine {
 
   void dims(int b, std::vector<int>& bonds, std::vector<int>& inner, double& disc);
   std::vector<double> bond_weights(int b, int bond);
+  // rho of instance b (n <= 12) as 2^n x 2^n complex doubles into `host`
+  void to_dense(int b, double* host);
 
   const Config& config() const { return cfg_; }
   int nq(int b) const { return nq_[b]; }

@@ -23,7 +23,7 @@ EXPORTED = (
     "mpdo_last_error", "mpdo_version", "mpdo_create", "mpdo_destroy", "mpdo_channel_from_chi",
     "mpdo_channel_info", "mpdo_channel_destroy", "mpdo_apply_gate", "mpdo_apply_channel", "mpdo_flush",
     "mpdo_truncate", "mpdo_expect", "mpdo_expect_products", "mpdo_fidelity_ghz", "mpdo_trace", "mpdo_dims",
-    "mpdo_bond_weights", "mpdo_batch_run",
+    "mpdo_bond_weights", "mpdo_to_dense", "mpdo_batch_run",
 )
 
 
@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
         "mpdo_trace": [vp, pd],
         "mpdo_dims": [vp, pi, pi, pd],
         "mpdo_bond_weights": [vp, i32, pd, i32, pi],
+        "mpdo_to_dense": [vp, pd],
         "mpdo_batch_run": [ctypes.POINTER(mpdo_config), ctypes.POINTER(mpdo_program), i32, vp, i32, pd, i32,
                            ctypes.POINTER(vp), i32, vp, i32, vp],
         "mpdo_profile_enable": [i32],
@@ -252,6 +253,13 @@ class MPDO:
         d = ctypes.c_double()
         check(lib().mpdo_dims(self._h, b, k, ctypes.byref(d)))
         return list(b)[: self.n - 1], list(k), d.value
+
+    def to_dense(self) -> np.ndarray:
+        """rho as a (2^n, 2^n) complex array (n <= 12)."""
+        d = 1 << self.n
+        out = np.zeros(2 * d * d)
+        check(lib().mpdo_to_dense(self._h, _dptr(out)))
+        return out.view(np.complex128).reshape(d, d)
 
     def bond_weights(self, bond: int) -> np.ndarray:
         cap = self.cfg.chi_max

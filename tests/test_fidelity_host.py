@@ -1,0 +1,38 @@
+"""The Uhlmann fidelity used by the crosstalk report (host-side measurement),
+pinned by closed forms: pure states, commuting states, and invariance."""
+import numpy as np
+
+from paper_2508_07610_amd.crosstalk import uhlmann_fidelity
+
+
+def _rand_rho(d, rank, rng):
+    X = rng.normal(size=(d, rank)) + 1j * rng.normal(size=(d, rank))
+    r = X @ X.conj().T
+    return r / np.trace(r).real
+
+
+def test_pure_states_give_the_squared_overlap():
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=8) + 1j * rng.normal(size=8)
+    b = rng.normal(size=8) + 1j * rng.normal(size=8)
+    a /= np.linalg.norm(a)
+    b /= np.linalg.norm(b)
+    f = uhlmann_fidelity(np.outer(a, a.conj()), np.outer(b, b.conj()))
+    assert abs(f - abs(np.vdot(a, b)) ** 2) < 1e-10
+
+
+def test_commuting_states_give_the_classical_fidelity():
+    p = np.array([0.5, 0.3, 0.2, 0.0])
+    q = np.array([0.1, 0.1, 0.4, 0.4])
+    f = uhlmann_fidelity(np.diag(p).astype(complex), np.diag(q).astype(complex))
+    assert abs(f - np.sum(np.sqrt(p * q)) ** 2) < 1e-12
+
+
+def test_identity_symmetry_and_unitary_invariance():
+    rng = np.random.default_rng(2)
+    r, s = _rand_rho(6, 3, rng), _rand_rho(6, 6, rng)
+    assert abs(uhlmann_fidelity(r, r) - 1) < 1e-9
+    assert abs(uhlmann_fidelity(r, s) - uhlmann_fidelity(s, r)) < 1e-9
+    U, _ = np.linalg.qr(rng.normal(size=(6, 6)) + 1j * rng.normal(size=(6, 6)))
+    assert abs(uhlmann_fidelity(U @ r @ U.conj().T, U @ s @ U.conj().T) - uhlmann_fidelity(r, s)) < 1e-9
+    assert 0 < uhlmann_fidelity(r, s) < 1

@@ -1,0 +1,97 @@
+"""Dense density matrix of the MPDO (mpdo_to_dense, Eqs. (6)-(7)) against the
+oracle's dense contraction of the same truncated state, and its properties
+at the largest supported size."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import channels as OC
+from oracle import mpdo as OM
+from paper_2508_07610_amd import mpdo as M
+from paper_2508_07610_amd import workloads as W
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+TOL = {M.C128: 1e-10, M.C64_MIXED: 1e-5}
+
+
+def _both(prog, chi, kap, prec, eps=0.0):
+    qs = [int(round(math.log(c.shape[0], 4))) for c in prog.chis]
+    kr = [OC.kraus_from_chi(c, eps if q == 3 else 0.0)[0] for c, q in zip(prog.chis, qs)]
+    o = OM.run_program(prog, OM.MPDO(prog.n, chi, kap, 1e-10, 1e-14), kr)
+    chans = [M.Channel(c, q, eps=eps if q == 3 else 0.0) for c, q in zip(prog.chis, qs)]
+    st = M.MPDO(prog.n, chi_max=chi, kappa_max=kap, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    M.run_program(prog, st, chans)
+    return o, st
+
+
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+@pytest.mark.parametrize("n,depth,chi,kap", [(1, 1, 4, 4), (2, 1, 4, 4), (5, 2, 16, 4), (6, 3, 16, 4)])
+def test_dense_matches_oracle_ansatz(prec, n, depth, chi, kap):
+    require_gpu()
+    prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, 11 + n))
+    o, st = _both(prog, chi, kap, prec)
+    rho, ref = st.to_dense(), o.to_dense()
+    assert rho.shape == (1 << n, 1 << n)
+    assert float(np.abs(rho - ref).max()) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+def test_dense_matches_oracle_crosstalk(prec):
+    require_gpu()
+    rng = W.rng_for(620)
+    chi3 = [W.random_cptp_near_identity_3q(rng) for _ in range(2)]
+    prog = W.random_circuit(6, 2, rng, chi2=W.chi_2q_default(), chi3=chi3)
+    o, st = _both(prog, 16, 8, prec, eps=1e-4)
+    assert float(np.abs(st.to_dense() - o.to_dense()).max()) < TOL[prec]
+
+
+def test_dense_at_twelve_qubits():
+    """n = 12: unit trace, Hermitian, positive semidefinite to rounding, and
+    <Z_i Z_i+1> from the dense matrix equal the transfer-matrix values."""
+    require_gpu()
+    n = 12
+    prog = W.ghz_ansatz(n, 2, W.ansatz_params(n, 2, 5))
+    st = M.MPDO(n, chi_max=32, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14)
+    M.run_program(prog, st, [M.Channel(c, 1 if c.shape[0] == 4 else 2) for c in prog.chis])
+    rho = st.to_dense()
+    assert abs(np.trace(rho) - st.trace()) < 1e-10
+    assert float(np.abs(rho - rho.conj().T).max()) < 1e-12
+    assert float(np.linalg.eigvalsh((rho + rho.conj().T) / 2).min()) > -1e-10
+    idx = np.arange(1 << n)
+    diag = np.real(np.diag(rho)) / np.real(np.trace(rho))
+    for i in range(n - 1):
+        bi = (idx >> (n - 1 - i)) & 1
+        bj = (idx >> (n - 2 - i)) & 1
+        zz = float(np.sum(diag * (1 - 2 * (bi ^ bj))))
+        assert abs(zz - st.expect("I" * i + "ZZ" + "I" * (n - 2 - i)).real) < 1e-10, i
+
+
+def test_dense_rejects_more_than_twelve_qubits():
+    require_gpu()
+    st = M.MPDO(13, chi_max=4, kappa_max=2, max_kraus=4)
+    with pytest.raises(M.MPDOError) as e:
+        st.to_dense()
+    assert e.value.status == M.EINVAL
+
+
+def test_uhlmann_fidelity_of_pruned_crosstalk_runs():
+    """The crosstalk workload's fidelity between the eps = 0 and pruned runs
+    (n = 6): 1 for identical states, within (0, 1], and equal to the oracle's
+    dense states' fidelity."""
+    require_gpu()
+    from paper_2508_07610_amd import crosstalk as X
+    res = X.run(n=6, depth=3, chi_max=32, kappa_max=8, eps_list=(0.0, 1e-3), prec=M.C128, dense=True)
+    assert abs(res[0]["fidelity_vs_eps0"] - 1) < 1e-9
+    f = res[1]["fidelity_vs_eps0"]
+    assert 0 < f <= 1 + 1e-9
+    prog = X.circuit(6, 3)
+    qs = [int(round(math.log(c.shape[0], 4))) for c in prog.chis]
+    dens = []
+    for eps in (0.0, 1e-3):
+        kr = [OC.kraus_from_chi(c, eps if q == 3 else 0.0)[0] for c, q in zip(prog.chis, qs)]
+        o = OM.run_program(prog, OM.MPDO(6, 32, 8, 1e-10, 1e-14), kr)
+        r = o.to_dense()
+        dens.append(r / np.trace(r).real)
+    assert abs(X.uhlmann_fidelity(dens[0], dens[1]) - f) < 1e-8
