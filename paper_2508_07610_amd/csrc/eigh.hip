@@ -383,7 +383,136 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   return kz;
 }
 
+// Z <- H_0 H_1 ... H_{n-2} Z for the kz leading columns of Z (ld n), the
+// reflectors H_k = I - tau_k v_k v_k^H stored below the diagonal in column k
+// of A (v_k(k+1) = 1).  Blocks of BTB reflectors, from the last, are applied
+// in compact form Q = H_k0 ... H_k1-1 = I - V T V^H (T upper triangular,
+// T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^H v_j):
+// W = V^H Z, W <- T W, Z <- Z - V W, so Z is read twice and written once per
+// block instead of once per reflector.
+constexpr int BTB = 8;
+constexpr int TRB = 8;  // tridiagonalisation panel width
 template <class SH>
+__device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict__ A, int n, int kz, SH& S) {
+  cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
+  // scratch after the matrix: free once the inverse iteration is done
+  cpx<double>* __restrict__ Vb = reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n);  // n x BTB
+  cpx<double>* __restrict__ part = Vb + (long long)n * BTB;                              // nq x BTB x kz
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nq = kz < NT ? NT / kz : 1;          // row chunks per column
+  cpx<double>* __restrict__ Wt = part + (long long)nq * BTB * kz;                       // BTB x kz
+  cpx<double>* G = S.v;                          // BTB x BTB (LDS, free here)
+  cpx<double>* T = S.vp;
+  for (int kend = n - 1; kend > 0; kend -= BTB) {
+    const int k0 = kend > BTB ? kend - BTB : 0, nb = kend - k0;
+    const int r0 = k0 + 1, m = n - r0;
+    // V block, row r0 + i: v_{k0+j}(row) for j < nb (zero above v's first row
+    // and for tau = 0)
+    for (int e = tid; e < m * BTB; e += NT) {
+      const int i = e / BTB, j = e % BTB, r = r0 + i, k = k0 + j;
+      cpx<double> v = mk(0.0, 0.0);
+      if (j < nb && r >= k + 1 && (S.tau[k].re != 0.0 || S.tau[k].im != 0.0))
+        v = (r == k + 1) ? mk(1.0, 0.0) : A[(long long)r * n + k];
+      Vb[e] = v;
+    }
+    __syncthreads();
+    // G(i, j) = v_i^H v_j for i < j, one wave per pair
+    for (int pr = wave; pr < BTB * BTB; pr += NT / 64) {
+      const int i = pr / BTB, j = pr % BTB;
+      if (i >= j || j >= nb) continue;  // uniform per wave
+      double gr = 0, gi = 0;
+      for (int r = lane; r < m; r += 64) {
+        const cpx<double> a = Vb[(long long)r * BTB + i], b = Vb[(long long)r * BTB + j];
+        gr += a.re * b.re + a.im * b.im;
+        gi += a.re * b.im - a.im * b.re;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        gr += __shfl_xor(gr, off, 64);
+        gi += __shfl_xor(gi, off, 64);
+      }
+      if (lane == 0) G[i * BTB + j] = mk(gr, gi);
+    }
+    __syncthreads();
+    // T, one lane per row (row i of T depends only on its own earlier
+    // entries, which the same lane wrote)
+    if (wave == 0 && lane < BTB) {
+      const int i = lane;
+      for (int j = 0; j < BTB; ++j) {
+        cpx<double> x = mk(0.0, 0.0);
+        if (j < nb) {
+          const cpx<double> t = S.tau[k0 + j];
+          if (i == j) {
+            x = t;
+          } else if (i < j) {
+            cpx<double> acc = mk(0.0, 0.0);
+            for (int q = i; q < j; ++q) acc = acc + T[i * BTB + q] * G[q * BTB + j];
+            x = mk(0.0, 0.0) - t * acc;
+          }
+        }
+        T[i * BTB + j] = x;
+      }
+    }
+    // partial W = V^H Z over row chunks: thread (column c, chunk q)
+    const int rows_per = (m + nq - 1) / nq;
+    for (int u = tid; u < kz * nq; u += NT) {
+      const int c = u % kz, q = u / kz;
+      cpx<double> acc[BTB];
+#pragma unroll
+      for (int j = 0; j < BTB; ++j) acc[j] = mk(0.0, 0.0);
+      const int i1 = min(m, (q + 1) * rows_per);
+      for (int i = q * rows_per; i < i1; ++i) {
+        const cpx<double> z = Z[(long long)(r0 + i) * n + c];
+#pragma unroll
+        for (int j = 0; j < BTB; ++j) {
+          const cpx<double> v = Vb[(long long)i * BTB + j];
+          acc[j] = acc[j] + mk(v.re * z.re + v.im * z.im, v.re * z.im - v.im * z.re);  // conj(v) z
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < BTB; ++j) part[((long long)q * BTB + j) * kz + c] = acc[j];
+    }
+    __syncthreads();
+    // Wt = T (sum of the partials), one thread per column
+    for (int c = tid; c < kz; c += NT) {
+      cpx<double> w[BTB];
+#pragma unroll
+      for (int j = 0; j < BTB; ++j) {
+        cpx<double> x = mk(0.0, 0.0);
+        for (int q = 0; q < nq; ++q) x = x + part[((long long)q * BTB + j) * kz + c];
+        w[j] = x;
+      }
+#pragma unroll
+      for (int i = 0; i < BTB; ++i) {
+        cpx<double> x = mk(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < BTB; ++j)
+          if (j >= i) x = x + T[i * BTB + j] * w[j];
+        Wt[(long long)i * kz + c] = x;
+      }
+    }
+    __syncthreads();
+    // Z <- Z - V Wt
+    for (int u = tid; u < kz * nq; u += NT) {
+      const int c = u % kz, q = u / kz;
+      cpx<double> w[BTB];
+#pragma unroll
+      for (int j = 0; j < BTB; ++j) w[j] = Wt[(long long)j * kz + c];
+      const int i1 = min(m, (q + 1) * rows_per);
+      for (int i = q * rows_per; i < i1; ++i) {
+        cpx<double> z = Z[(long long)(r0 + i) * n + c];
+#pragma unroll
+        for (int j = 0; j < BTB; ++j) z = z - Vb[(long long)i * BTB + j] * w[j];
+        Z[(long long)(r0 + i) * n + c] = z;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// PANEL: the panel-blocked reduction (less memory traffic per step, more
+// work per step: faster when many matrices share the memory system);
+// otherwise one fused pass per step (lower latency for a lone matrix).
+template <bool PANEL, class SH>
 __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S) {
   const int n = dsc.n, tid = threadIdx.x;
   int par = 0;  // block_sum buffer parity
@@ -398,121 +527,206 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
   double tr = 0;
   for (int i = tid; i < n; i += NT) tr += A[i * n + i].re;
   tr = block_sum(tr, S.red, par);
-  // ---- 2. tridiagonalisation ----
-  bool pend = false;  // a rank-2 update (vp, wp; index 0 = row k) is pending
-  for (int k = 0; k + 1 < n; ++k) {
-    const int m = n - k - 1;
-    const int c0 = k + 1;
-    if (pend) {  // bring column k (rows k..n-1) up to date first
-      const cpx<double> wk = cconj(S.wp[0]), vk = cconj(S.vp[0]);
-      for (int i = k + tid; i < n; i += NT) {
-        cpx<double> x = A[(long long)i * n + k];
-        x = x - S.vp[i - k] * wk - S.wp[i - k] * vk;
-        A[(long long)i * n + k] = x;
+  if constexpr (PANEL) {
+    // ---- 2. tridiagonalisation, in panels of TRB columns ----
+    // Within a panel the trailing block is not updated: after j steps it is
+    // A - V W^H - W V^H with the panel's reflectors v_q and w_q = tau p -
+    // (|tau|^2 / 2)(v^H p) v (zero above their first row), so a step reads the
+    // trailing block once (p = A v - V (W^H v) - W (V^H v)) and the block is
+    // written once per panel.
+    cpx<double>* __restrict__ Vp = reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n);  // n x TRB
+    cpx<double>* __restrict__ Wp = Vp + (long long)n * TRB;
+    cpx<double>* xk = S.wp;     // current column k (rows k..n-1)
+    cpx<double>* y12 = S.vp;    // W^H v (0..TRB) and V^H v (TRB..2 TRB)
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int p0 = 0; p0 + 1 < n; p0 += TRB) {
+      const int np = min(TRB, n - 1 - p0);
+      for (int j = 0; j < np; ++j) {
+        const int k = p0 + j, m = n - k - 1, c0 = k + 1;
+        // current column k from row k of the stored matrix and the panel so far
+        for (int i = k + tid; i < n; i += NT) {
+          cpx<double> x = cconj(A[(long long)k * n + i]);
+          for (int q = 0; q < j; ++q)
+            x = x - Vp[(long long)i * TRB + q] * cconj(Wp[(long long)k * TRB + q]) -
+                Wp[(long long)i * TRB + q] * cconj(Vp[(long long)k * TRB + q]);
+          xk[i - k] = x;
+        }
+        __syncthreads();
+        if (tid == 0) S.d[k] = xk[0].re;
+        double xn = 0;
+        for (int i = 2 + tid; i <= m; i += NT) xn += cabs2(xk[i]);
+        xn = block_sum(xn, S.red, par);
+        if (tid == 0) {
+          const cpx<double> alpha = xk[1];
+          if (xn == 0.0 && alpha.im == 0.0) {
+            S.tau[k] = mk(0.0, 0.0);
+            S.e[k] = alpha.re;
+            S.flag[0] = 0;
+          } else {
+            const double nrm = sqrt(cabs2(alpha) + xn);
+            const double beta = alpha.re >= 0 ? -nrm : nrm;
+            S.tau[k] = mk((beta - alpha.re) / beta, -alpha.im / beta);
+            const cpx<double> den = mk(alpha.re - beta, alpha.im);  // scal = 1 / (alpha - beta)
+            const double dd = cabs2(den);
+            S.scal[0] = den.re / dd;
+            S.scal[1] = -den.im / dd;
+            S.e[k] = beta;
+            S.flag[0] = 1;
+          }
+        }
+        __syncthreads();
+        const bool act = S.flag[0] != 0;
+        const cpx<double> tau = S.tau[k];
+        const cpx<double> sc = mk(S.scal[0], S.scal[1]);
+        for (int i = tid; i < m; i += NT) {
+          const cpx<double> v = !act ? mk(0.0, 0.0) : (i == 0) ? mk(1.0, 0.0) : xk[1 + i] * sc;
+          S.v[i] = v;
+          if (act) A[(long long)(c0 + i) * n + k] = v;  // kept for the back-transformation
+          Vp[(long long)(c0 + i) * TRB + j] = v;
+        }
+        __syncthreads();
+        if (!act) {
+          for (int i = tid; i < m; i += NT) Wp[(long long)(c0 + i) * TRB + j] = mk(0.0, 0.0);
+          __syncthreads();
+          continue;
+        }
+        fused_pass(A, n, c0, k, false, true, S);  // S.pp = A22 v (stored block)
+        // y1 = W^H v, y2 = V^H v over rows c0..n-1, one wave per dot product
+        for (int d = wave; d < 2 * j; d += NT / 64) {
+          const cpx<double>* Y = d < j ? Wp : Vp;
+          const int q = d < j ? d : d - j;
+          double yr = 0, yi = 0;
+          for (int i = lane; i < m; i += 64) {
+            const cpx<double> a = Y[(long long)(c0 + i) * TRB + q], v = S.v[i];
+            yr += a.re * v.re + a.im * v.im;  // conj(a) v
+            yi += a.re * v.im - a.im * v.re;
+          }
+          for (int off = 32; off > 0; off >>= 1) {
+            yr += __shfl_xor(yr, off, 64);
+            yi += __shfl_xor(yi, off, 64);
+          }
+          if (lane == 0) y12[(d < j ? 0 : TRB) + q] = mk(yr, yi);
+        }
+        __syncthreads();
+        double g = 0;  // gamma = v^H p with p corrected for the panel
+        for (int i = tid; i < m; i += NT) {
+          cpx<double> pv = S.pp[i];
+          for (int q = 0; q < j; ++q)
+            pv = pv - Vp[(long long)(c0 + i) * TRB + q] * y12[q] - Wp[(long long)(c0 + i) * TRB + q] * y12[TRB + q];
+          S.pp[i] = pv;
+          g += S.v[i].re * pv.re + S.v[i].im * pv.im;
+        }
+        g = block_sum(g, S.red, par);
+        const double cc = 0.5 * cabs2(tau) * g;
+        for (int i = tid; i < m; i += NT) Wp[(long long)(c0 + i) * TRB + j] = tau * S.pp[i] - cc * S.v[i];
+        __syncthreads();
+      }
+      // trailing block [p1, n)^2 <- A - V W^H - W V^H
+      const int p1 = p0 + np;
+      const int mt = n - p1;
+      if (mt > 0) {
+        int nq = NT / mt;
+        if (nq < 1) nq = 1;
+        const int rows_per = (mt + nq - 1) / nq;
+        for (int u = tid; u < mt * nq; u += NT) {
+          const int c = p1 + u % mt, q = u / mt;
+          cpx<double> vc[TRB], wc[TRB];
+  #pragma unroll
+          for (int t = 0; t < TRB; ++t) {
+            vc[t] = t < np ? cconj(Vp[(long long)c * TRB + t]) : mk(0.0, 0.0);
+            wc[t] = t < np ? cconj(Wp[(long long)c * TRB + t]) : mk(0.0, 0.0);
+          }
+          const int r1 = min(n, p1 + (q + 1) * rows_per);
+          for (int r = p1 + q * rows_per; r < r1; ++r) {
+            cpx<double> x = A[(long long)r * n + c];
+  #pragma unroll
+            for (int t = 0; t < TRB; ++t)
+              if (t < np) x = x - Vp[(long long)r * TRB + t] * wc[t] - Wp[(long long)r * TRB + t] * vc[t];
+            A[(long long)r * n + c] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    // ---- 2. tridiagonalisation, one column per step: the previous step's
+    // rank-2 update is fused with this step's matrix-vector pass ----
+    bool pend = false;  // a rank-2 update (vp, wp; index 0 = row k) is pending
+    for (int k = 0; k + 1 < n; ++k) {
+      const int m = n - k - 1;
+      const int c0 = k + 1;
+      if (pend) {  // bring column k (rows k..n-1) up to date first
+        const cpx<double> wk = cconj(S.wp[0]), vk = cconj(S.vp[0]);
+        for (int i = k + tid; i < n; i += NT) {
+          cpx<double> x = A[(long long)i * n + k];
+          x = x - S.vp[i - k] * wk - S.wp[i - k] * vk;
+          A[(long long)i * n + k] = x;
+        }
+        __syncthreads();
+      }
+      if (tid == 0) S.d[k] = A[(long long)k * n + k].re;
+      double xn = 0;
+      for (int i = 1 + tid; i < m; i += NT) xn += cabs2(A[(long long)(c0 + i) * n + k]);
+      xn = block_sum(xn, S.red, par);
+      if (tid == 0) {
+        const cpx<double> alpha = A[(long long)c0 * n + k];
+        if (xn == 0.0 && alpha.im == 0.0) {
+          S.tau[k] = mk(0.0, 0.0);
+          S.e[k] = alpha.re;
+          S.flag[0] = 0;
+        } else {
+          const double nrm = sqrt(cabs2(alpha) + xn);
+          const double beta = alpha.re >= 0 ? -nrm : nrm;
+          S.tau[k] = mk((beta - alpha.re) / beta, -alpha.im / beta);
+          const cpx<double> den = mk(alpha.re - beta, alpha.im);  // scal = 1 / (alpha - beta)
+          const double dd = cabs2(den);
+          S.scal[0] = den.re / dd;
+          S.scal[1] = -den.im / dd;
+          S.e[k] = beta;
+          S.flag[0] = 1;
+        }
+      }
+      __syncthreads();
+      const bool act = S.flag[0] != 0;
+      const cpx<double> tau = S.tau[k];
+      if (act) {
+        const cpx<double> sc = mk(S.scal[0], S.scal[1]);
+        for (int i = tid; i < m; i += NT) {
+          const cpx<double> v = (i == 0) ? mk(1.0, 0.0) : A[(long long)(c0 + i) * n + k] * sc;
+          S.v[i] = v;
+          A[(long long)(c0 + i) * n + k] = v;  // kept for the back-transformation
+        }
+      }
+      __syncthreads();
+      fused_pass(A, n, c0, k, pend, act, S);
+      if (act) {
+        double g = 0;  // gamma = v^H p
+        for (int i = tid; i < m; i += NT) g += S.v[i].re * S.pp[i].re + S.v[i].im * S.pp[i].im;
+        g = block_sum(g, S.red, par);
+        const double cc = 0.5 * cabs2(tau) * g;
+        for (int i = tid; i < m; i += NT) {
+          S.wp[i] = tau * S.pp[i] - cc * S.v[i];
+          S.vp[i] = S.v[i];
+        }
+        __syncthreads();
+      }
+      pend = act;
+    }
+    if (pend) {  // the last pending update touches only A[n-1][n-1]
+      if (tid == 0) {
+        cpx<double> x = A[(long long)(n - 1) * n + n - 1];
+        x = x - S.vp[0] * cconj(S.wp[0]) - S.wp[0] * cconj(S.vp[0]);
+        A[(long long)(n - 1) * n + n - 1] = x;
       }
       __syncthreads();
     }
-    if (tid == 0) S.d[k] = A[(long long)k * n + k].re;
-    double xn = 0;
-    for (int i = 1 + tid; i < m; i += NT) xn += cabs2(A[(long long)(c0 + i) * n + k]);
-    xn = block_sum(xn, S.red, par);
-    if (tid == 0) {
-      const cpx<double> alpha = A[(long long)c0 * n + k];
-      if (xn == 0.0 && alpha.im == 0.0) {
-        S.tau[k] = mk(0.0, 0.0);
-        S.e[k] = alpha.re;
-        S.flag[0] = 0;
-      } else {
-        const double nrm = sqrt(cabs2(alpha) + xn);
-        const double beta = alpha.re >= 0 ? -nrm : nrm;
-        S.tau[k] = mk((beta - alpha.re) / beta, -alpha.im / beta);
-        const cpx<double> den = mk(alpha.re - beta, alpha.im);  // scal = 1 / (alpha - beta)
-        const double dd = cabs2(den);
-        S.scal[0] = den.re / dd;
-        S.scal[1] = -den.im / dd;
-        S.e[k] = beta;
-        S.flag[0] = 1;
-      }
-    }
-    __syncthreads();
-    const bool act = S.flag[0] != 0;
-    const cpx<double> tau = S.tau[k];
-    if (act) {
-      const cpx<double> sc = mk(S.scal[0], S.scal[1]);
-      for (int i = tid; i < m; i += NT) {
-        const cpx<double> v = (i == 0) ? mk(1.0, 0.0) : A[(long long)(c0 + i) * n + k] * sc;
-        S.v[i] = v;
-        A[(long long)(c0 + i) * n + k] = v;  // kept for the back-transformation
-      }
-    }
-    __syncthreads();
-    fused_pass(A, n, c0, k, pend, act, S);
-    if (act) {
-      double g = 0;  // gamma = v^H p
-      for (int i = tid; i < m; i += NT) g += S.v[i].re * S.pp[i].re + S.v[i].im * S.pp[i].im;
-      g = block_sum(g, S.red, par);
-      const double cc = 0.5 * cabs2(tau) * g;
-      for (int i = tid; i < m; i += NT) {
-        S.wp[i] = tau * S.pp[i] - cc * S.v[i];
-        S.vp[i] = S.v[i];
-      }
-      __syncthreads();
-    }
-    pend = act;
-  }
-  if (pend) {  // the last pending update touches only A[n-1][n-1]
-    if (tid == 0) {
-      cpx<double> x = A[(long long)(n - 1) * n + n - 1];
-      x = x - S.vp[0] * cconj(S.wp[0]) - S.wp[0] * cconj(S.vp[0]);
-      A[(long long)(n - 1) * n + n - 1] = x;
-    }
-    __syncthreads();
   }
   if (tid == 0) S.d[n - 1] = A[(long long)(n - 1) * n + n - 1].re;
   for (int i = tid; i + 1 < n; i += NT) S.e2[i] = S.e[i] * S.e[i];
   __syncthreads();
   const int kz = eig_tail<NT>(dsc, n, tr, S, par);
-  // ---- 6. back-transformation z <- H_0 ... H_{n-2} z ----
-  if (kz > 0) {
-    cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
-    int nq = NT / kz;
-    if (nq < 1) nq = 1;
-    if (nq > 16) nq = 16;
-    for (int k = n - 2; k >= 0; --k) {
-      const cpx<double> t = S.tau[k];
-      if (t.re == 0.0 && t.im == 0.0) continue;
-      const int m = n - k - 1, r0 = k + 1;
-      for (int i = tid; i < m; i += NT) S.v[i] = (i == 0) ? mk(1.0, 0.0) : A[(long long)(r0 + i) * n + k];
-      __syncthreads();
-      const int rows_per = (m + nq - 1) / nq;
-      for (int u = tid; u < kz * nq; u += NT) {
-        const int c = u % kz, q = u / kz;
-        const int i0 = q * rows_per, i1 = min(m, i0 + rows_per);
-        double yr = 0, yi = 0;
-        for (int i = i0; i < i1; ++i) {
-          const cpx<double> v = S.v[i];
-          const cpx<double> z = Z[(long long)(r0 + i) * n + c];
-          yr += v.re * z.re + v.im * z.im;  // conj(v) z
-          yi += v.re * z.im - v.im * z.re;
-        }
-        S.pp[q * kz + c] = mk(yr, yi);
-      }
-      __syncthreads();
-      for (int u = tid; u < kz * nq; u += NT) {
-        const int c = u % kz, q = u / kz;
-        cpx<double> y = S.pp[c];
-        for (int qq = 1; qq < nq; ++qq) y = y + S.pp[qq * kz + c];
-        const cpx<double> ty = t * y;
-        const int i0 = q * rows_per, i1 = min(m, i0 + rows_per);
-        for (int i = i0; i < i1; ++i) {
-          cpx<double> z = Z[(long long)(r0 + i) * n + c];
-          z = z - S.v[i] * ty;
-          Z[(long long)(r0 + i) * n + c] = z;
-        }
-      }
-      __syncthreads();
-    }
-  }
+  // ---- 6. back-transformation z <- H_0 ... H_{n-2} z, in blocks ----
+  if (kz > 0) back_transform(dsc, A, n, kz, S);
 }
 }  // namespace
 
@@ -788,7 +1002,7 @@ __global__ __launch_bounds__(NT) void k_heev_global(const EigDesc* __restrict__ 
   __shared__ SharedG<512> S;
   const EigDesc& d = descs[blockIdx.x];
   if (!d.active || d.n <= RN || d.n > 512) return;
-  heev_core(d, reinterpret_cast<cpx<double>*>(d.work), S);
+  heev_core<true>(d, reinterpret_cast<cpx<double>*>(d.work), S);
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
 
@@ -797,7 +1011,7 @@ __global__ __launch_bounds__(NT) void k_heev_big(const EigDesc* __restrict__ des
   __shared__ SharedG<EIG_NMAX> S;
   const EigDesc& d = descs[blockIdx.x];
   if (!d.active || d.n <= 512 || d.n > EIG_NMAX) return;
-  heev_core(d, reinterpret_cast<cpx<double>*>(d.work), S);
+  heev_core<false>(d, reinterpret_cast<cpx<double>*>(d.work), S);
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
 
