@@ -48,6 +48,9 @@ struct GemmDesc {
   int opA, opB;
   int beta;        // 0: overwrite, 1: accumulate
   int active;      // 0: item skipped
+  int herm;        // 1: C is Hermitian (a Gram matrix): only its upper
+                   // triangle of tiles is computed (and reduced)
+  int hpad;
   double alpha;
 };
 
@@ -71,6 +74,8 @@ struct EigDesc {
   int n, lda;
   int kvec;
   int active;
+  int upper;      // 1: only the upper triangle of `a` is valid (lower = conj)
+  int upad;
 };
 
 constexpr double EIG_FLOOR = 1e-13;

@@ -520,8 +520,13 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
   const cpx<double>* a = reinterpret_cast<const cpx<double>*>(dsc.a);
   for (int e = tid; e < n * n; e += NT) {
     const int i = e / n, j = e % n;
-    const cpx<double> x = a[(long long)i * dsc.lda + j], y = a[(long long)j * dsc.lda + i];
-    A[e] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+    if (dsc.upper) {  // only the upper triangle is valid
+      const cpx<double> x = i <= j ? a[(long long)i * dsc.lda + j] : a[(long long)j * dsc.lda + i];
+      A[e] = i < j ? x : i > j ? cconj(x) : mk(x.re, 0.0);
+    } else {
+      const cpx<double> x = a[(long long)i * dsc.lda + j], y = a[(long long)j * dsc.lda + i];
+      A[e] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+    }
   }
   __syncthreads();
   double tr = 0;
@@ -784,8 +789,13 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
       const int r = r0 + u;
       a[u] = mk(0.0, 0.0);
       if (r < n && c < n) {
-        const cpx<double> x = Ain[(long long)r * dsc.lda + c], y = Ain[(long long)c * dsc.lda + r];
-        a[u] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+        if (dsc.upper) {  // only the upper triangle is valid
+          const cpx<double> x = r <= c ? Ain[(long long)r * dsc.lda + c] : Ain[(long long)c * dsc.lda + r];
+          a[u] = r < c ? x : r > c ? cconj(x) : mk(x.re, 0.0);
+        } else {
+          const cpx<double> x = Ain[(long long)r * dsc.lda + c], y = Ain[(long long)c * dsc.lda + r];
+          a[u] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+        }
         if (r == c) trp += a[u].re;
       }
     }

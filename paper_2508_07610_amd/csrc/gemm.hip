@@ -120,6 +120,7 @@ __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ desc
   const int tilesN = (N + TN - 1) / TN;
   if (tile >= ((M + TM - 1) / TM) * tilesN) return;
   const int tm = tile / tilesN, tn = tile % tilesN;
+  if (d.herm && tm > tn) return;  // Hermitian C: the lower tiles are not needed
   const int m0 = tm * TM, n0 = tn * TN;
 
   const cpx<Tin>* A = reinterpret_cast<const cpx<Tin>*>(d.A) + (long long)batch * d.sA;
@@ -226,7 +227,7 @@ __global__ void k_reduce_splits(const GemmDesc* __restrict__ descs, double* cons
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count && e < maxCount;
        e += gridDim.x * blockDim.x) {
     const int row = e / d.ldc, col = e % d.ldc;
-    if (col >= d.N) continue;
+    if (col >= d.N || (d.herm && row > col)) continue;
     double re = 0, im = 0;
     for (int s = 0; s < d.splits; ++s) {
       const cpx<double> v = parts[(long long)s * d.sSplit + e];

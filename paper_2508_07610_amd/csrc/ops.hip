@@ -97,6 +97,7 @@ __device__ inline void clear_desc(GemmDesc& d) {
   d.w = nullptr; d.kstride = 0; d.sA = d.sB = d.sC = 0;
   d.M = d.N = d.K = 0; d.lda = d.ldb = d.ldc = 0; d.kinner = 0; d.wdiv = 1;
   d.nbatch = 1; d.splits = 1; d.opA = OP_N; d.opB = OP_N; d.beta = 0; d.active = 1; d.alpha = 1.0;
+  d.herm = 0;
 }
 }  // namespace
 
@@ -245,11 +246,12 @@ __global__ __launch_bounds__(GT) void k_q2_prepare(Ctx2<T>* ctxs, int splitsE) {
     d.lda = d.ldb = k2 * cr;
     d.ldc = 2 * cm;
     d.splits = splitsE;
+    d.herm = 1;
   }
   {
     EigDesc& d = *c.dEigE;
     d.a = c.E; d.lda = 2 * cm; d.n = 2 * cm; d.evals = c.evE; d.evecs = c.vecE; d.trace = c.evE + 2 * cm;
-    d.active = 1;
+    d.active = 1; d.upper = 1;
   }
 }
 
@@ -421,11 +423,12 @@ __global__ __launch_bounds__(GT) void k_q2_select_g(Ctx2<T>* ctxs, int splitsC, 
       d.w = c.laml2; d.wdiv = 2 * kp;
       d.ldc = 2 * rF;
       d.splits = splitsC;
+      d.herm = 1;
     }
     {
       EigDesc& d = *c.dEigC;
       d.a = c.Cm; d.lda = 2 * rF; d.n = 2 * rF; d.evals = c.evC; d.evecs = c.vecC; d.trace = c.evC + 2 * rF;
-      d.active = 1;
+      d.active = 1; d.upper = 1;
     }
   }
 }
@@ -519,8 +522,10 @@ __global__ __launch_bounds__(GT) void k_q3_prepare(Ctx3<T>* ctxs, int splitsN, i
     d.w = c.laml2; d.wdiv = k1;
     d.ldc = 2 * ca;
     d.splits = splitsN;
+    d.herm = 1;
     EigDesc& e = *c.eN;
     e.lda = 2 * ca; e.n = 2 * ca; e.evals = c.evN; e.evecs = c.vecN; e.trace = c.evN + 2 * ca; e.active = 1;
+    e.upper = 1;
   }
   {  // E3 = F F^H, F = B_{i+2} as [(b t3)] x [(k3 r)]
     GemmDesc& d = *c.dE3;
@@ -534,8 +539,10 @@ __global__ __launch_bounds__(GT) void k_q3_prepare(Ctx3<T>* ctxs, int splitsN, i
     d.lda = d.ldb = k3 * cr;
     d.ldc = 2 * cb;
     d.splits = splitsE;
+    d.herm = 1;
     EigDesc& e = *c.eE3;
     e.lda = 2 * cb; e.n = 2 * cb; e.evals = c.evE3; e.evecs = c.vecE3; e.trace = c.evE3 + 2 * cb; e.active = 1;
+    e.upper = 1;
   }
 }
 
@@ -726,9 +733,11 @@ __global__ __launch_bounds__(GT) void k_q3_sel_h(Ctx3<T>* ctxs, int splitsC, Tru
       d.lda = d.ldb = 4 * kp * r3;
       d.ldc = 2 * rN;
       d.splits = splitsC;
+      d.herm = 1;
     }
     EigDesc& e = *c.e1;
     e.lda = 2 * rN; e.n = 2 * rN; e.evals = c.ev1; e.evecs = c.vec1; e.trace = c.ev1 + 2 * rN; e.active = 1;
+    e.upper = 1;
   }
 }
 
@@ -803,9 +812,11 @@ __global__ __launch_bounds__(GT) void k_q3_sel_1(Ctx3<T>* ctxs, int splitsC, Tru
       d.lda = d.ldb = 2 * r3;
       d.ldc = 2 * r3;
       d.splits = splitsC;
+      d.herm = 1;
     }
     EigDesc& e = *c.e2;
     e.lda = 2 * r3; e.n = 2 * r3; e.evals = c.ev2; e.evecs = c.vec2; e.trace = c.ev2 + 2 * r3; e.active = 1;
+    e.upper = 1;
   }
 }
 
@@ -941,8 +952,9 @@ __global__ __launch_bounds__(GT) void k_sw_prepare(CtxS<T>* ctxs, int splits) {
     d.lda = d.ldb = 2 * k * r;
   }
   d.ldc = n;
+  d.herm = 1;
   EigDesc& e = *c.dE;  // a, work and kvec are set by the host (a = the reduced Gram)
-  e.lda = n; e.n = n; e.evals = c.ev; e.evecs = c.evec; e.trace = c.ev + n; e.active = 1;
+  e.lda = n; e.n = n; e.evals = c.ev; e.evecs = c.evec; e.trace = c.ev + n; e.active = 1; e.upper = 1;
 }
 
 template <typename T>

@@ -63,8 +63,9 @@ __global__ __launch_bounds__(AT) void k_account_gemm(const GemmDesc* __restrict_
     if (!d[i].active) continue;
     const double nb = d[i].nbatch > 0 ? d[i].nbatch : 1;
     const double M = d[i].M, N = d[i].N, K = d[i].K;
-    f += 8.0 * M * N * K * nb;
-    b += nb * (in_bytes * (M * K + K * N) + out_bytes * M * N);
+    const double MN = d[i].herm ? 0.5 * M * (M + 1) : M * N;  // Hermitian C: its upper triangle
+    f += 8.0 * MN * K * nb;
+    b += nb * (in_bytes * (M * K + K * N) + out_bytes * MN);
   }
   block_add(f, b, flops, bytes);
 }
