@@ -8,7 +8,9 @@
 // Tiles of 64 x 64 (or 32 x 32 for products with small outputs and long K)
 // per workgroup of four waves; each wave owns a quadrant made of 16 x 16
 // MFMA blocks; the next K slice is fetched into registers while the current
-// one is multiplied.
+// one is multiplied.  At these sizes the products are latency-bound rather
+// than MFMA-bound, so the design favours occupancy: short K slices and a
+// register budget of four waves per SIMD.
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
@@ -34,8 +36,14 @@ template <> struct Mfma<float> {
   __device__ static inline int row(int g, int v) { return 4 * g + v; }
 };
 
+// Operands are read through global-address-space pointers (the descriptors
+// hold generic ones), so their loads are not tied to the LDS wait counter.
+#define GLB __attribute__((address_space(1)))
+
 namespace {
-constexpr int BK = 16, NTHR = 256, PAD = 4;
+// K slice of 8: the kernel is latency-bound at small tiles, so the slice is
+// kept short to fit four waves per SIMD (four workgroups per CU).
+constexpr int BK = 8, NTHR = 256, PAD = 4;
 constexpr int NXCD = 8;  // accelerator complex dies of the MI355X
 
 __device__ inline long long kaddr(int k, int kinner, long long kstride) {
@@ -49,8 +57,8 @@ template <typename Tin, typename Tc, int T> struct Slice {
   static constexpr int E = T * BK / NTHR;
   Tc re[E], im[E];
   // kfast: the K index is contiguous in memory for this operand
-  __device__ void load(const cpx<Tin>* X, int ld, bool kfast, bool conj, int r0, int R, int k0, int kend,
-                       int kinner, long long kstride, const double* w, int wdiv) {
+  __device__ void load(const GLB cpx<Tin>* X, int ld, bool kfast, bool conj, int r0, int R, int k0, int kend,
+                       int kinner, long long kstride, const GLB double* w, int wdiv, bool two) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int it = 0; it < E; ++it) {
@@ -61,12 +69,13 @@ template <typename Tin, typename Tc, int T> struct Slice {
       const int r = r0 + rr, k = k0 + kk;
       Tc vr = 0, vi = 0;
       if (r < R && k < kend) {
-        const long long ka = kaddr(k, kinner, kstride);
-        const cpx<Tin> v = kfast ? X[(long long)r * ld + ka] : X[ka * ld + r];
+        const long long ka = two ? kaddr(k, kinner, kstride) : (long long)k;  // uniform branch
+        const GLB cpx<Tin>* px = kfast ? X + ((long long)r * ld + ka) : X + (ka * ld + r);
+        const cpx<Tin> v = mk<Tin>(px->re, px->im);
         vr = (Tc)v.re;
         vi = conj ? -(Tc)v.im : (Tc)v.im;
         if (w) {
-          const Tc sw = (Tc)w[k / wdiv];
+          const Tc sw = (Tc)w[wdiv == 1 ? k : k / wdiv];
           vr *= sw;
           vi *= sw;
         }
@@ -94,8 +103,8 @@ template <typename Tin, typename Tc, int T> struct Slice {
 // computes (TM/2) x (TN/2) from 16 x 16 MFMA blocks.  The next K slice is
 // loaded into registers while the current one is multiplied from LDS.
 template <typename Tin, typename Tc, typename Tout, int TM, int TN>
-__global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch,
-                                               int maxSplits, int maxTiles, long long nblocks) {
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int maxTiles, long long nblocks) {
   typedef typename Mfma<Tc>::v4 v4;
   constexpr int FM = TM / 32, FN = TN / 32;  // 16 x 16 blocks per wave and dimension
   __shared__ Tc As_re[BK][TM + PAD], As_im[BK][TM + PAD];
@@ -123,13 +132,14 @@ __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ desc
   if (d.herm && tm > tn) return;  // Hermitian C: the lower tiles are not needed
   const int m0 = tm * TM, n0 = tn * TN;
 
-  const cpx<Tin>* A = reinterpret_cast<const cpx<Tin>*>(d.A) + (long long)batch * d.sA;
-  const cpx<Tin>* B = reinterpret_cast<const cpx<Tin>*>(d.B) + (long long)batch * d.sB;
-  cpx<Tout>* C = reinterpret_cast<cpx<Tout>*>(d.C) + (long long)batch * d.sC + (long long)split * d.sSplit;
+  const GLB cpx<Tin>* A = (const GLB cpx<Tin>*)(d.A) + (long long)batch * d.sA;
+  const GLB cpx<Tin>* B = (const GLB cpx<Tin>*)(d.B) + (long long)batch * d.sB;
+  GLB cpx<Tout>* C = (GLB cpx<Tout>*)(d.C) + (long long)batch * d.sC + (long long)split * d.sSplit;
   const int opA = d.opA, opB = d.opB, lda = d.lda, ldb = d.ldb;
   const int kinner = d.kinner > 0 ? d.kinner : (K > 0 ? K : 1);
   const long long kstride = d.kinner > 0 ? d.kstride : (long long)kinner;
-  const double* w = d.w;
+  const GLB double* w = (const GLB double*)d.w;
+  const bool two = d.kinner > 0 && d.kinner < K;
   const int wdiv = d.wdiv > 0 ? d.wdiv : 1;
 
   int kper = (K + d.splits - 1) / d.splits;
@@ -159,18 +169,18 @@ __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ desc
   Slice<Tin, Tc, TM> sa;
   Slice<Tin, Tc, TN> sb;
   if (kbeg < kend) {
-    sa.load(A, lda, aKfast, aConj, m0, M, kbeg, kend, kinner, kstride, w, wdiv);
-    sb.load(B, ldb, bKfast, bConj, n0, N, kbeg, kend, kinner, kstride, nullptr, 1);
+    sa.load(A, lda, aKfast, aConj, m0, M, kbeg, kend, kinner, kstride, w, wdiv, two);
+    sb.load(B, ldb, bKfast, bConj, n0, N, kbeg, kend, kinner, kstride, nullptr, 1, two);
   }
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     sa.store(As_re, As_im, aKfast);
     sb.store(Bs_re, Bs_im, bKfast);
     __syncthreads();
     if (k0 + BK < kend) {  // next slice in flight during the products below
-      sa.load(A, lda, aKfast, aConj, m0, M, k0 + BK, kend, kinner, kstride, w, wdiv);
-      sb.load(B, ldb, bKfast, bConj, n0, N, k0 + BK, kend, kinner, kstride, nullptr, 1);
+      sa.load(A, lda, aKfast, aConj, m0, M, k0 + BK, kend, kinner, kstride, w, wdiv, two);
+      sb.load(B, ldb, bKfast, bConj, n0, N, k0 + BK, kend, kinner, kstride, nullptr, 1, two);
     }
-#pragma unroll
+#pragma unroll 1
     for (int kb = 0; kb < BK; kb += 4) {
       Tc ar[FM], ai[FM], br[FN], bi[FN];
 #pragma unroll
@@ -207,10 +217,12 @@ __global__ __launch_bounds__(NTHR) void k_gemm(const GemmDesc* __restrict__ desc
         const int row = m0 + wm * (TM / 2) + i * 16 + Mfma<Tc>::row(lk, v);
         const int col = n0 + wn * (TN / 2) + j * 16 + li;
         if (row < M && col < N) {
-          cpx<Tout>* p = C + (long long)row * ldc + col;
+          GLB cpx<Tout>* p = C + (long long)row * ldc + col;
           cpx<Tc> r = mk<Tc>(alpha * acc_re[i][j][v], alpha * acc_im[i][j][v]);
           if (d.beta) r = r + mk<Tc>((Tc)p->re, (Tc)p->im);
-          *p = mk<Tout>((Tout)r.re, (Tout)r.im);
+          const cpx<Tout> o = mk<Tout>((Tout)r.re, (Tout)r.im);
+          p->re = o.re;
+          p->im = o.im;
         }
       }
 }
