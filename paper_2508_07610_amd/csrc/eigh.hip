@@ -91,6 +91,9 @@ template <int NMAX> struct alignas(16) SharedG {
   double scal[4];
   int flag[4];
   int clus[NMAX + 1];
+  // panel form, n <= 256: conj(V), conj(W) of the panel, transposed (t, column)
+  alignas(16) cpx<double> vcT[NMAX <= 512 ? 8 * 256 : 1];
+  alignas(16) cpx<double> wcT[NMAX <= 512 ? 8 * 256 : 1];
 };
 
 // Pending update (vp, wp; index 0 = row `base`) on rows/cols [c0, n) and,
@@ -629,7 +632,49 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
       // trailing block [p1, n)^2 <- A - V W^H - W V^H
       const int p1 = p0 + np;
       const int mt = n - p1;
-      if (mt > 0) {
+      if (mt > 0 && n <= 256) {
+        // 4 x 4 blocks per thread, all loads of a block independent; the
+        // panel factors come from LDS, transposed (t, row)
+        static_assert(TRB == 8, "LDS panel factors hold eight columns");
+        for (int e = tid; e < np * mt; e += NT) {
+          const int t = e / mt, c = e % mt;
+          S.vcT[t * 256 + c] = cconj(Vp[(long long)(p1 + c) * TRB + t]);
+          S.wcT[t * 256 + c] = cconj(Wp[(long long)(p1 + c) * TRB + t]);
+        }
+        __syncthreads();
+        const int nb = (mt + 3) >> 2;
+        for (int u = tid; u < nb * nb; u += NT) {
+          const int r0 = 4 * (u / nb), q0 = 4 * (u % nb);  // relative to p1
+          cpx<double> x[4][4];
+  #pragma unroll
+          for (int i = 0; i < 4; ++i)
+  #pragma unroll
+            for (int j = 0; j < 4; ++j)
+              x[i][j] = (r0 + i < mt && q0 + j < mt) ? A[(long long)(p1 + r0 + i) * n + p1 + q0 + j] : mk(0.0, 0.0);
+  #pragma unroll
+          for (int t = 0; t < TRB; ++t) {
+            if (t >= np) break;
+            cpx<double> vr[4], wr[4], vc[4], wc[4];
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) {  // r0 + i, q0 + i < 256: entries past mt are not stored back
+              vr[i] = cconj(S.vcT[t * 256 + r0 + i]);
+              wr[i] = cconj(S.wcT[t * 256 + r0 + i]);
+              vc[i] = S.vcT[t * 256 + q0 + i];
+              wc[i] = S.wcT[t * 256 + q0 + i];
+            }
+  #pragma unroll
+            for (int i = 0; i < 4; ++i)
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) x[i][j] = x[i][j] - vr[i] * wc[j] - wr[i] * vc[j];
+          }
+  #pragma unroll
+          for (int i = 0; i < 4; ++i)
+  #pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (r0 + i < mt && q0 + j < mt) A[(long long)(p1 + r0 + i) * n + p1 + q0 + j] = x[i][j];
+        }
+        __syncthreads();
+      } else if (mt > 0) {
         int nq = NT / mt;
         if (nq < 1) nq = 1;
         const int rows_per = (mt + nq - 1) / nq;

@@ -66,7 +66,7 @@ def test_gemm_split_k_and_weights(tile):
     assert err < 1e-13, err
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 32, 64, 65, 100, 128, 256, 512, 513, 1024])
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 32, 64, 65, 100, 128, 129, 255, 256, 257, 512, 513, 1024])
 def test_eigh_against_numpy(n):
     require_gpu()
     rng = np.random.default_rng(n)
