@@ -53,14 +53,21 @@ __device__ inline double block_sum(double v, double* red, int& parity) {
   return s;
 }
 
-// number of eigenvalues of T (diag d, squared off-diagonal e2) below x
+// number of eigenvalues of T (diag d, squared off-diagonal e2) below x.
+// e2 / q is formed as e2 times the hardware reciprocal estimate of q refined
+// by two Newton steps (relative error at the rounding level; the IEEE divide
+// sequence is several times longer on this dependent chain).  |q| >= pivmin
+// keeps the reciprocal finite, and the count stays backward stable.
 __device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0;
   for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
+    double r = __builtin_amdgcn_rcp(q);
+    r = r * (2.0 - q * r);
+    r = r * (2.0 - q * r);
+    q = (d[i] - x) - e2[i - 1] * r;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0;
   }
