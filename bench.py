@@ -54,6 +54,9 @@ def parse():
                     help="skip the mixed GHZ-ansatz / QAOA MaxCut batch leg")
     ap.add_argument("--no-crosstalk", action="store_true",
                     help="skip the crosstalk leg (three-site channels, Kraus pruning thresholds)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB three times (b.copy_(a), 2^28 float32): the reference run that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
     ap.add_argument("--graph", action="store_true",
                     help="capture each batched step into one HIP graph (the roofline then comes from one "
                          "extra profiled step outside the timed region)")
@@ -242,6 +245,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if a.copy_calibration:
+        x = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("copied 1 GiB x 3", flush=True)
+        return
     from paper_2508_07610_amd import mpdo as M
     from paper_2508_07610_amd import workloads as W
     torch.cuda.set_device(0)

@@ -869,10 +869,14 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
   for (int k = 0; k + 1 < n; ++k) {
     const int c0 = k + 1;
     // (a) rank-2 update of step k-1 on [k, n) x [k, n); publish column k
-    if (pend && r0 + RR > k) {
+    // (the update is zero outside rows and columns [k, n): finished rows are
+    // skipped per group of eight, uniformly across the wave, and finished
+    // columns per thread)
+    if (pend && r0 + RR > k && c >= k) {
       const cpx<double> wc = cconj(S.wp[c]), vc = cconj(S.vp[c]);
 #pragma unroll
       for (int u0 = 0; u0 < RR; u0 += 8) {
+        if (r0 + u0 + 8 <= k) continue;
         cpx<double> vr[8], wr[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -941,10 +945,14 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
         double pr = 0, pi = 0;
         if (rows) {
 #pragma unroll
-          for (int u = 0; u < RR; ++u) {
-            const cpx<double> v = S.v[0][r0 + u];
-            pr += a[u].re * v.re + a[u].im * v.im;
-            pi += a[u].re * v.im - a[u].im * v.re;
+          for (int u0 = 0; u0 < RR; u0 += 8) {
+            if (r0 + u0 + 8 <= c0) continue;  // v is zero there
+#pragma unroll
+            for (int u = u0; u < u0 + 8; ++u) {
+              const cpx<double> v = S.v[0][r0 + u];
+              pr += a[u].re * v.re + a[u].im * v.im;
+              pi += a[u].re * v.im - a[u].im * v.re;
+            }
           }
         }
         S.pp[0][q][c] = mk(pr, pi);
