@@ -224,14 +224,27 @@ def crosstalk_leg():
     depth 12, chi=128, kappa=16, mixed precision, once per pruning threshold;
     observables <Z_i>, <Z_i Z_i+1> of every run against the eps = 0 run."""
     from paper_2508_07610_amd import crosstalk as X
+    from paper_2508_07610_amd import mpdo as M
+    M.profile_enable(True)
     res = X.run(n=24, depth=12, chi_max=128, kappa_max=16, eps_list=(0.0, 1e-4, 1e-3))
+    prof = {M.PROF_NAMES[c]: M.profile_read(c) for c in M.PROF_NAMES}
+    M.profile_enable(False)
     small = X.run(n=8, depth=12, chi_max=64, kappa_max=16, eps_list=(0.0, 1e-4, 1e-3), dense=True)
+    g32 = prof[M.PROF_NAMES[M.PROF_GEMM_F32]]
+    tf32 = g32["flops"] / (g32["ms"] * 1e-3) / 1e12 if g32["ms"] > 0 else 0.0
     return {"workload": "random RX/RY/RZ + CZ-brick circuit n=24 depth=12, 2q channel after every CZ and a random "
                         "CPTP 3-site channel on the neighbouring triple, chi=128 kappa=16 svd_cutoff=1e-10, "
                         "c64 contractions with FP64 Grams/eigensolvers, per-gate C-ABI calls",
             "runs": [{"eps": r["eps"], "kraus_counts": r["kraus"], "seconds": r["seconds"],
                       "discarded_weight": r["discarded"], "trace": r["trace"], "max_bond": r["max_bond"],
                       "max_obs_dev_vs_eps0": r["max_dev_vs_eps0"]} for r in res],
+            "kernel_time_ms": {k: {"ms": v["ms"], "launches": v["launches"],
+                                   "tflops": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0}
+                               for k, v in prof.items()},
+            "fp32_contractions": {"achieved": tf32, "peak": PEAK["f32_mfma"], "unit": "TFLOP/s", "frac": tf32 / PEAK["f32_mfma"],
+                                  "launches": g32["launches"], "avg_launch_ms": g32["ms"] / max(1, g32["launches"]),
+                                  "note": "the chi=128 FP32 MFMA contractions of the three runs, algorithmic flops "
+                                          "over HIP-event time per launch (per-gate calls: one item per launch)"},
             "slice_n8": {"note": "same construction at n=8, chi=64 (dense states from mpdo_to_dense); Uhlmann fidelity "
                                  "F(rho_eps0, rho_eps) computed on the host from the two dense matrices",
                          "fidelity_vs_eps0": {str(r["eps"]): r["fidelity_vs_eps0"] for r in small},

@@ -166,6 +166,25 @@ mpdo_status mpdo_bond_weights(mpdo_t h, int32_t b, double* out, int32_t cap, int
  * EUNSUPPORTED above 16 GiB, EINVAL for n > 12. */
 mpdo_status mpdo_to_dense(mpdo_t h, double* rho);
 
+/* Computational-basis measurement (the bitstring distributions compared in
+ * Sec. IV.A, whose distance there is the Jensen-Shannon divergence, Eq. (18)).
+ *
+ * mpdo_probabilities: p[z] = <z| rho |z> / Tr rho for nz bitstrings.
+ * bits: host, nz x n bytes, each 0 or 1 (bits[z n + i] is qubit i of string
+ * z, qubit 0 first); p: host, nz doubles.  EINVAL for a byte above 1.
+ *
+ * mpdo_sample: nshots bitstrings drawn by sequential conditionals: qubit i
+ * of shot t is 0 when u[t n + i] < P(z_i = 0 | z_0 .. z_{i-1}), else 1.  The
+ * random numbers are the caller's: u is host memory of nshots x n uniforms
+ * in [0, 1) (EINVAL otherwise), so a draw is reproducible.  bits: host,
+ * nshots x n bytes (output); pz: host, nshots doubles, the probability
+ * P(z) / Tr rho of each drawn string (the product of its conditionals), or
+ * NULL.  The conditionals come from left environments of the shots and right
+ * environments of the state, contracted on the device in the handle's
+ * precision; ENOTCONV if a prefix has no weight. */
+mpdo_status mpdo_probabilities(mpdo_t h, const uint8_t* bits, int32_t nz, double* p);
+mpdo_status mpdo_sample(mpdo_t h, const double* u, int32_t nshots, uint8_t* bits, double* pz);
+
 /* ---------------------------------------------------------------------------
  * Batched execution: many independent instances (parameter points, graphs of
  * different sizes) advanced together, every sublayer of every instance in

@@ -43,6 +43,9 @@ struct AnyEngine {
   }
   std::vector<double> bond_weights(int b, int bond) { return d ? d->bond_weights(b, bond) : f->bond_weights(b, bond); }
   void to_dense(int b, double* host) { d ? d->to_dense(b, host) : f->to_dense(b, host); }
+  void sample(int b, const double* u, int ns, unsigned char* bits, double* pz) {
+    d ? d->sample(b, u, ns, bits, pz) : f->sample(b, u, ns, bits, pz);
+  }
   double truncate_sweep(int b, int c, int k, double cut) {
     return d ? d->truncate_sweep(b, c, k, cut) : f->truncate_sweep(b, c, k, cut);
   }
@@ -397,6 +400,39 @@ mpdo_status mpdo_to_dense(mpdo_t h, double* rho) {
   GUARD_BEGIN
   flush_queue(h);
   h->eng.to_dense(0, rho);
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_probabilities(mpdo_t h, const uint8_t* bits, int32_t nz, double* p) {
+  if (!h || !bits || !p) return fail(MPDO_EINVAL, "null argument");
+  if (nz < 1) return fail(MPDO_EINVAL, "nz must be >= 1");
+  const int n = h->cfg.n;
+  for (long long e = 0; e < (long long)nz * n; ++e)
+    if (bits[e] > 1) return fail(MPDO_EINVAL, "bits must be 0 or 1");
+  GUARD_BEGIN
+  // <z| rho |z> / Tr rho: the product of the projectors |z_i><z_i|
+  const double P0[8] = {1, 0, 0, 0, 0, 0, 0, 0}, P1[8] = {0, 0, 0, 0, 0, 0, 1, 0};
+  std::vector<std::vector<double>> ops(nz, std::vector<double>(8 * n));
+  for (int z = 0; z < nz; ++z)
+    for (int i = 0; i < n; ++i) std::memcpy(ops[z].data() + 8 * i, bits[(size_t)z * n + i] ? P1 : P0, sizeof(P0));
+  std::vector<double> out(2 * (size_t)nz);
+  expect_ops(h, ops, out.data(), false);
+  for (int z = 0; z < nz; ++z) p[z] = out[2 * (size_t)z];
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_sample(mpdo_t h, const double* u, int32_t nshots, uint8_t* bits, double* pz) {
+  if (!h || !u || !bits) return fail(MPDO_EINVAL, "null argument");
+  if (h->dead) return fail(MPDO_EDEVICE, "handle is unusable after a device error");
+  if (nshots < 1) return fail(MPDO_EINVAL, "nshots must be >= 1");
+  const int n = h->cfg.n;
+  for (long long e = 0; e < (long long)nshots * n; ++e)
+    if (!(u[e] >= 0.0 && u[e] < 1.0)) return fail(MPDO_EINVAL, "uniforms must lie in [0, 1)");
+  GUARD_BEGIN
+  flush_queue(h);
+  h->eng.sample(0, u, nshots, bits, pz);
   return MPDO_OK;
   GUARD_END
 }

@@ -105,6 +105,9 @@ template <typename T> class Engine {
   std::vector<double> bond_weights(int b, int bond);
   // rho of instance b (n <= 12) as 2^n x 2^n complex doubles into `host`
   void to_dense(int b, double* host);
+  // nshots bitstrings by sequential conditionals (u: nshots x n uniforms,
+  // host; bits: nshots x n, host; pz: probability of each, host or null)
+  void sample(int b, const double* u_host, int nshots, unsigned char* bits_host, double* pz_host);
 
   const Config& config() const { return cfg_; }
   int nq(int b) const { return nq_[b]; }

@@ -23,7 +23,7 @@ EXPORTED = (
     "mpdo_last_error", "mpdo_version", "mpdo_create", "mpdo_destroy", "mpdo_channel_from_chi",
     "mpdo_channel_info", "mpdo_channel_destroy", "mpdo_apply_gate", "mpdo_apply_channel", "mpdo_flush",
     "mpdo_truncate", "mpdo_expect", "mpdo_expect_products", "mpdo_fidelity_ghz", "mpdo_trace", "mpdo_dims",
-    "mpdo_bond_weights", "mpdo_to_dense", "mpdo_batch_run",
+    "mpdo_bond_weights", "mpdo_to_dense", "mpdo_probabilities", "mpdo_sample", "mpdo_batch_run",
 )
 
 
@@ -85,6 +85,8 @@ def lib() -> ctypes.CDLL:
         "mpdo_dims": [vp, pi, pi, pd],
         "mpdo_bond_weights": [vp, i32, pd, i32, pi],
         "mpdo_to_dense": [vp, pd],
+        "mpdo_probabilities": [vp, ctypes.POINTER(ctypes.c_uint8), i32, pd],
+        "mpdo_sample": [vp, pd, i32, ctypes.POINTER(ctypes.c_uint8), pd],
         "mpdo_batch_run": [ctypes.POINTER(mpdo_config), ctypes.POINTER(mpdo_program), i32, vp, i32, pd, i32,
                            ctypes.POINTER(vp), i32, vp, i32, vp],
         "mpdo_profile_enable": [i32],
@@ -260,6 +262,23 @@ class MPDO:
         out = np.zeros(2 * d * d)
         check(lib().mpdo_to_dense(self._h, _dptr(out)))
         return out.view(np.complex128).reshape(d, d)
+
+    def probabilities(self, bits: np.ndarray) -> np.ndarray:
+        """bits: (nz, n) of 0/1 -> <z|rho|z> / Tr(rho) for each row."""
+        b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint8).reshape(-1, self.n))
+        out = np.zeros(b.shape[0])
+        check(lib().mpdo_probabilities(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), b.shape[0],
+                                       _dptr(out)))
+        return out
+
+    def sample(self, u: np.ndarray):
+        """u: (nshots, n) uniforms in [0, 1) -> (bits (nshots, n) uint8, P(z) of each draw)."""
+        uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1, self.n))
+        bits = np.zeros(uu.shape, dtype=np.uint8)
+        pz = np.zeros(uu.shape[0])
+        check(lib().mpdo_sample(self._h, _dptr(uu), uu.shape[0], bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                _dptr(pz)))
+        return bits, pz
 
     def bond_weights(self, bond: int) -> np.ndarray:
         cap = self.cfg.chi_max

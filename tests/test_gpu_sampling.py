@@ -1,0 +1,130 @@
+"""Computational-basis measurement on the device (mpdo_probabilities,
+mpdo_sample) against the oracle's dense state of the same truncated MPDO,
+and self-consistency at the benchmark size."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import channels as OC
+from oracle import dense as OD
+from oracle import mpdo as OM
+from oracle import sampling as OS
+from paper_2508_07610_amd import mpdo as M
+from paper_2508_07610_amd import workloads as W
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+TOL = {M.C128: 1e-10, M.C64_MIXED: 1e-5}
+# a uniform this close to the conditional decides differently under rounding
+MARGIN = {M.C128: 1e-9, M.C64_MIXED: 1e-4}
+
+
+def _both(prog, chi, kap, prec, eps=0.0):
+    qs = [int(round(math.log(c.shape[0], 4))) for c in prog.chis]
+    kr = [OC.kraus_from_chi(c, eps if q == 3 else 0.0)[0] for c, q in zip(prog.chis, qs)]
+    o = OM.run_program(prog, OM.MPDO(prog.n, chi, kap, 1e-10, 1e-14), kr)
+    chans = [M.Channel(c, q, eps=eps if q == 3 else 0.0) for c, q in zip(prog.chis, qs)]
+    st = M.MPDO(prog.n, chi_max=chi, kappa_max=kap, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    M.run_program(prog, st, chans)
+    return o, st
+
+
+def _all_bits(n):
+    return np.array([OS.bits_of(z, n) for z in range(1 << n)], dtype=np.uint8)
+
+
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+@pytest.mark.parametrize("n,depth,chi,kap", [(1, 1, 4, 4), (5, 2, 16, 4), (7, 3, 16, 4)])
+def test_probabilities_match_oracle(prec, n, depth, chi, kap):
+    require_gpu()
+    prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, 31 + n))
+    o, st = _both(prog, chi, kap, prec)
+    ref = OS.basis_probabilities(o.to_dense())
+    got = st.probabilities(_all_bits(n))
+    assert float(np.abs(got - ref).max()) < TOL[prec]
+    assert abs(got.sum() - 1) < TOL[prec] * (1 << n)
+
+
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+def test_samples_match_oracle_draws(prec):
+    """The same uniforms give the same bits as the oracle's sequential
+    conditionals on the dense state (compared up to the first qubit whose
+    uniform lies within rounding of its conditional), and the returned
+    probability of each draw is its oracle probability."""
+    require_gpu()
+    n, shots = 6, 300
+    rng = W.rng_for(640)
+    chi3 = [W.random_cptp_near_identity_3q(rng) for _ in range(2)]
+    prog = W.random_circuit(n, 2, rng, chi2=W.chi_2q_default(), chi3=chi3)
+    o, st = _both(prog, 16, 8, prec, eps=1e-4)
+    P = OS.basis_probabilities(o.to_dense())
+    u = np.random.default_rng(641).random((shots, n))
+    bits, pz = st.sample(u)
+    assert bits.shape == (shots, n) and bits.dtype == np.uint8
+    full = 0
+    for t in range(shots):
+        ob, opz, q0 = OS.conditional_sample(P, n, u[t])
+        tie = [i for i in range(n) if abs(u[t, i] - q0[i]) < MARGIN[prec]]
+        k = tie[0] if tie else n  # bits before a near-tie must agree
+        assert list(bits[t, :k]) == ob[:k], t
+        if not tie:
+            full += 1
+            assert abs(pz[t] - opz) < TOL[prec] * max(1.0, 1e3 * opz), t
+    assert full > shots - 5
+
+
+def test_sample_reproducible_and_consistent_at_benchmark_size():
+    """n = 16, chi = 64, kappa = 8 (the benchmark circuit): a draw replays
+    bit for bit, the probability returned with each drawn string equals
+    mpdo_probabilities of it (no string of probability 0 is drawn), and the
+    frequency of z_0 = 0 agrees with <Z_0> = 2 P(z_0 = 0) - 1 within five
+    standard errors."""
+    require_gpu()
+    n, depth = 16, 10
+    prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, 0))
+    st = M.MPDO(n, chi_max=64, kappa_max=8, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14)
+    M.run_program(prog, st, [M.Channel(c, 1 if c.shape[0] == 4 else 2) for c in prog.chis])
+    u = np.random.default_rng(16).random((512, n))
+    bits, pz = st.sample(u)
+    bits2, pz2 = st.sample(u)
+    assert np.array_equal(bits, bits2) and np.array_equal(pz, pz2)
+    p = st.probabilities(bits)
+    assert np.all(pz > 0)
+    assert float(np.abs(pz / p - 1).max()) < 1e-9
+    z0 = st.expect("Z" + "I" * (n - 1)).real
+    f0 = float(np.mean(bits[:, 0] == 0))
+    assert abs((2 * f0 - 1) - z0) < 5 * 2 * math.sqrt(0.25 / len(bits))
+
+
+def test_sampling_rejects_bad_input():
+    require_gpu()
+    st = M.MPDO(3, chi_max=4, kappa_max=2, max_kraus=4)
+    with pytest.raises(M.MPDOError) as e:
+        st.sample(np.full((2, 3), 1.0))
+    assert e.value.status == M.EINVAL
+    with pytest.raises(M.MPDOError) as e:
+        st.probabilities(np.full((1, 3), 2, dtype=np.uint8))
+    assert e.value.status == M.EINVAL
+    # |000>: every draw is 000 with probability 1
+    bits, pz = st.sample(np.random.default_rng(1).random((4, 3)))
+    assert not bits.any() and np.allclose(pz, 1.0)
+    assert np.allclose(st.probabilities(np.array([[0, 0, 0], [1, 0, 0]], dtype=np.uint8)), [1.0, 0.0])
+
+
+def test_jsd_between_device_and_oracle_distributions():
+    """Eq. (18) between the device distribution and the oracle's dense one is
+    at rounding level, and between the ideal and the noisy circuit it is
+    positive (the paper's comparison metric)."""
+    require_gpu()
+    n, depth = 5, 2
+    prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, 77))
+    o, st = _both(prog, 16, 4, M.C128)
+    P = OS.basis_probabilities(o.to_dense())
+    Q = st.probabilities(_all_bits(n))
+    assert OD.jsd(P, Q) < 1e-12
+    ideal = M.MPDO(n, chi_max=16, kappa_max=4, max_kraus=4)
+    for op in prog.ops:  # every op is a gate followed by its channel: keep the gates
+        ideal.apply_gate(op.sites, op.U)
+    ideal.flush()
+    assert OD.jsd(P, ideal.probabilities(_all_bits(n))) > 1e-6
