@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--ttf-steps", type=int, default=30)
     ap.add_argument("--no-maxcut", action="store_true",
                     help="skip the mixed GHZ-ansatz / QAOA MaxCut batch leg")
+    ap.add_argument("--no-sampling", action="store_true", help="skip the bitstring sampling leg")
     ap.add_argument("--no-crosstalk", action="store_true",
                     help="skip the crosstalk leg (three-site channels, Kraus pruning thresholds)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -219,6 +220,31 @@ def maxcut_leg():
             "ghz_fidelity_point0": r["instances"][0]["ghz_fidelity"]}
 
 
+def sampling_leg(shots=4096):
+    """Computational-basis sampling of the benchmark state (parameter point 0
+    of the noisy RY/CZ ansatz, n=16, depth 10, chi=64, kappa=8, c128): shots
+    per second of mpdo_sample, the right environments included."""
+    import numpy as np
+    import torch
+    from paper_2508_07610_amd import mpdo as M
+    from paper_2508_07610_amd import workloads as W
+    prog = W.ghz_ansatz(N_QUBITS, DEPTH, W.ansatz_params(N_QUBITS, DEPTH, 0))
+    st = M.MPDO(N_QUBITS, chi_max=CHI, kappa_max=KAPPA, max_kraus=16, svd_cutoff=SVD_CUT, kappa_cutoff=1e-14)
+    M.run_program(prog, st, [M.Channel(c, 1 if c.shape[0] == 4 else 2) for c in prog.chis])
+    u = np.random.default_rng(7616).random((shots, N_QUBITS))
+    st.sample(u[:64])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bits, pz = st.sample(u)
+    dt = time.perf_counter() - t0
+    distinct = len({b.tobytes() for b in bits})
+    st.close()
+    return {"workload": f"mpdo_sample of the benchmark state (parameter point 0, n={N_QUBITS} depth={DEPTH} "
+                        f"chi={CHI} kappa={KAPPA}, c128), caller uniforms, one call",
+            "shots": shots, "seconds": dt, "shots_per_s": shots / dt, "distinct_strings": distinct,
+            "max_p_drawn": float(pz.max())}
+
+
 def crosstalk_leg():
     """Three-site crosstalk channels with Kraus pruning: the random circuit n=24,
     depth 12, chi=128, kappa=16, mixed precision, once per pruning threshold;
@@ -248,6 +274,7 @@ def crosstalk_leg():
             "slice_n8": {"note": "same construction at n=8, chi=64 (dense states from mpdo_to_dense); Uhlmann fidelity "
                                  "F(rho_eps0, rho_eps) computed on the host from the two dense matrices",
                          "fidelity_vs_eps0": {str(r["eps"]): r["fidelity_vs_eps0"] for r in small},
+                         "jsd_vs_eps0": {str(r["eps"]): r["jsd_vs_eps0"] for r in small},
                          "seconds": {str(r["eps"]): r["seconds"] for r in small}}}
 
 
@@ -331,6 +358,7 @@ def main():
         "cpu_baseline": None if a.no_cpu else cpu_baseline(W, a.cpu_layers),
         "time_to_fidelity": None if a.no_ttf else ttf_leg(a.ttf_steps),
         "maxcut_batch": None if a.no_maxcut else maxcut_leg(),
+        "sampling": None if a.no_sampling else sampling_leg(),
         "crosstalk": None if a.no_crosstalk else crosstalk_leg(),
     }
     print(json.dumps(out, default=lambda o: o.item() if hasattr(o, "item") else str(o)))

@@ -55,14 +55,36 @@ def uhlmann_fidelity(rho: np.ndarray, sigma: np.ndarray) -> float:
     return float(np.sum(np.sqrt(ev)) ** 2)
 
 
+def jsd(p: np.ndarray, q: np.ndarray) -> float:
+    """Jensen-Shannon divergence of two bitstring distributions, Eq. (18):
+    half the summed Kullback-Leibler divergences (natural logarithm) of P and
+    Q from their midpoint M = (P + Q) / 2, empty bins contributing nothing."""
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    mid = 0.5 * (p + q)
+    out = 0.0
+    for a in (p, q):
+        keep = a > 0
+        out += 0.5 * float(np.dot(a[keep], np.log(a[keep] / mid[keep])))
+    return out
+
+
+def all_bitstrings(n: int) -> np.ndarray:
+    """(2^n, n) uint8, row z = the bits of z with qubit 0 the most significant."""
+    z = np.arange(1 << n)
+    return ((z[:, None] >> (n - 1 - np.arange(n))[None, :]) & 1).astype(np.uint8)
+
+
 def run(n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,
         eps_list: Sequence[float] = (0.0, 1e-4, 1e-3), prec: int = M.C64_MIXED,
         seed_tag: int = 0, dense: bool = False) -> List[Dict]:
     """One run per eps; returns per eps the Kraus counts of the channels, the
     wall time, the summed discarded weight, the observables and their largest
     deviation from the eps = 0 run (the first entry of eps_list).  With
-    `dense` (n <= 12) also the dense state of each run (trace-normalised) and
-    its fidelity with the first run's."""
+    `dense` (n <= 12) also the dense state of each run (trace-normalised), its
+    fidelity with the first run's, the bitstring distribution
+    (mpdo_probabilities) and its Jensen-Shannon divergence from the first
+    run's."""
     import torch
     prog = circuit(n, depth, seed_tag)
     qs = [int(round(np.log(c.shape[0]) / np.log(4))) for c in prog.chis]
@@ -86,12 +108,15 @@ def run(n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,
         if dense:
             rho = st.to_dense()
             rec["rho"] = rho / np.trace(rho).real
+            rec["probs"] = st.probabilities(all_bitstrings(n))
         if ref is None:
             ref = vals
             rho0 = rec.get("rho")
+            p0 = rec.get("probs")
         rec["max_dev_vs_eps0"] = float(np.abs(vals - ref).max())
         if dense:
             rec["fidelity_vs_eps0"] = uhlmann_fidelity(rho0, rec["rho"])
+            rec["jsd_vs_eps0"] = jsd(p0, rec["probs"])
         out.append(rec)
         st.close()
         for ch in chans:

@@ -36,3 +36,25 @@ def test_identity_symmetry_and_unitary_invariance():
     U, _ = np.linalg.qr(rng.normal(size=(6, 6)) + 1j * rng.normal(size=(6, 6)))
     assert abs(uhlmann_fidelity(U @ r @ U.conj().T, U @ s @ U.conj().T) - uhlmann_fidelity(r, s)) < 1e-9
     assert 0 < uhlmann_fidelity(r, s) < 1
+
+
+def test_host_jsd_and_bitstrings_match_the_oracle():
+    """crosstalk.jsd (Eq. (18)) against the oracle's, on random and disjoint
+    distributions; crosstalk.all_bitstrings against the oracle's bit order."""
+    import numpy as np
+    from oracle import dense as OD
+    from oracle import sampling as OS
+    from paper_2508_07610_amd import crosstalk as X
+    rng = np.random.default_rng(18)
+    for _ in range(20):
+        p = rng.random(32) * (rng.random(32) > 0.3)
+        q = rng.random(32) * (rng.random(32) > 0.3)
+        p /= p.sum()
+        q /= q.sum()
+        assert abs(X.jsd(p, q) - OD.jsd(p, q)) < 1e-15
+    assert abs(X.jsd([1.0, 0.0], [0.0, 1.0]) - np.log(2)) < 1e-15
+    assert X.jsd([0.25] * 4, [0.25] * 4) == 0.0
+    b = X.all_bitstrings(5)
+    assert b.dtype == np.uint8 and b.shape == (32, 5)
+    for z in range(32):
+        assert list(b[z]) == OS.bits_of(z, 5)
