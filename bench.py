@@ -256,6 +256,10 @@ def crosstalk_leg():
     prof = {M.PROF_NAMES[c]: M.profile_read(c) for c in M.PROF_NAMES}
     M.profile_enable(False)
     small = X.run(n=8, depth=12, chi_max=64, kappa_max=16, eps_list=(0.0, 1e-4, 1e-3), dense=True)
+    nb = 8
+    bat = X.run_batch(nb=nb, n=24, depth=12, chi_max=128, kappa_max=16, eps=1e-4)
+    b32 = bat["profile"][M.PROF_NAMES[M.PROF_GEMM_F32]]
+    tb32 = b32["flops"] / (b32["ms"] * 1e-3) / 1e12 if b32["ms"] > 0 else 0.0
     g32 = prof[M.PROF_NAMES[M.PROF_GEMM_F32]]
     tf32 = g32["flops"] / (g32["ms"] * 1e-3) / 1e12 if g32["ms"] > 0 else 0.0
     return {"workload": "random RX/RY/RZ + CZ-brick circuit n=24 depth=12, 2q channel after every CZ and a random "
@@ -271,6 +275,14 @@ def crosstalk_leg():
                                   "launches": g32["launches"], "avg_launch_ms": g32["ms"] / max(1, g32["launches"]),
                                   "note": "the chi=128 FP32 MFMA contractions of the three runs, algorithmic flops "
                                           "over HIP-event time per launch (per-gate calls: one item per launch)"},
+            "batched": {"workload": f"{nb} seeded instances of the same construction (own 3-site channels each), "
+                                    "eps=1e-4, one mpdo_batch_run (launch by launch, after one sizing run)",
+                        "seconds": bat["seconds"], "seconds_per_instance": bat["seconds"] / nb,
+                        "kernel_time_ms": {k: {"ms": v["ms"], "launches": v["launches"],
+                                               "tflops": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0}
+                                           for k, v in bat["profile"].items()},
+                        "fp32_contractions": {"achieved": tb32, "peak": PEAK["f32_mfma"], "unit": "TFLOP/s",
+                                              "frac": tb32 / PEAK["f32_mfma"], "launches": b32["launches"]}},
             "slice_n8": {"note": "same construction at n=8, chi=64 (dense states from mpdo_to_dense); Uhlmann fidelity "
                                  "F(rho_eps0, rho_eps) computed on the host from the two dense matrices",
                          "fidelity_vs_eps0": {str(r["eps"]): r["fidelity_vs_eps0"] for r in small},

@@ -11,6 +11,7 @@ results are compared with the eps = 0 run.  Everything runs through the C ABI
 """
 from __future__ import annotations
 
+import dataclasses
 import time
 from typing import Dict, List, Sequence
 
@@ -122,3 +123,42 @@ def run(n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,
         for ch in chans:
             ch.close()
     return out
+
+
+def run_batch(nb: int = 16, n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,
+              eps: float = 1e-4, prec: int = M.C64_MIXED) -> Dict:
+    """nb seeded instances of the crosstalk circuit (seed tags 0 .. nb-1, each
+    with its own pair of three-site channels) in one mpdo_batch_run: the
+    two-site channel is shared, the three-site channels of instance b are
+    channels 1 + 2b and 2 + 2b.  Returns the wall time, the observables
+    (<Z_i>, <Z_i Z_i+1> per instance) and the library's per-class kernel
+    profile of the run."""
+    import torch
+    circs = [circuit(n, depth, t) for t in range(nb)]
+    chis = [circs[0].chis[0]]
+    progs = []
+    for b, pr in enumerate(circs):
+        assert np.array_equal(pr.chis[0], chis[0])
+        chis.extend(pr.chis[1:])
+        ops = [dataclasses.replace(o, chan=-1 if o.chan < 0 else (0 if o.chan == 0 else o.chan + 2 * b))
+               for o in pr.ops]
+        progs.append(W.Program(pr.n, ops, [], pr.layers))
+    qs = [int(round(np.log(c.shape[0]) / np.log(4))) for c in chis]
+    chans = [M.Channel(c, q, eps=eps if q == 3 else 0.0) for c, q in zip(chis, qs)]
+    mk = max(ch.nkraus for ch in chans)
+    obs = [z_products(n)] * nb
+    kw = dict(chi_max=chi_max, kappa_max=kappa_max, max_kraus=mk, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    M.batch_run(progs, None, chans, obs, use_graph=False, **kw)  # warm-up (workspace sizing)
+    torch.cuda.synchronize()
+    M.profile_enable(True)
+    t0 = time.perf_counter()
+    out = M.batch_run(progs, None, chans, obs, use_graph=False, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {M.PROF_NAMES[c]: M.profile_read(c) for c in M.PROF_NAMES}
+    M.profile_enable(False)
+    vals = out.cpu().numpy().real.reshape(nb, -1)
+    kraus = [ch.nkraus for ch in chans[:3]]
+    for ch in chans:
+        ch.close()
+    return {"seconds": dt, "obs": vals, "profile": prof, "kraus": kraus}

@@ -131,3 +131,16 @@ def test_crosstalk_workload_at_full_bond_and_inner_limits(eps):
     assert float(np.abs(r64["obs"] - r128["obs"]).max()) < 2e-5
     assert float(np.abs(r128["obs"]).max()) <= 1 + 1e-12
     assert r128["max_bond"] > 32
+
+
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+def test_crosstalk_batch_equals_per_gate_runs(prec):
+    """Seeded crosstalk instances with their own three-site channels in one
+    mpdo_batch_run give each instance's per-gate observables."""
+    require_gpu()
+    from paper_2508_07610_amd import crosstalk as X
+    r = X.run_batch(nb=3, n=10, depth=3, chi_max=32, kappa_max=8, eps=1e-4, prec=prec)
+    assert r["obs"].shape == (3, 2 * 10 - 1)
+    for t in range(3):
+        single = X.run(n=10, depth=3, chi_max=32, kappa_max=8, eps_list=(1e-4,), prec=prec, seed_tag=t)[0]["obs"]
+        assert float(np.abs(r["obs"][t] - single).max()) < 1e-12, t
