@@ -220,6 +220,21 @@ def maxcut_leg():
             "ghz_fidelity_point0": r["instances"][0]["ghz_fidelity"]}
 
 
+def gemm_tiles_leg():
+    """The GEMM kernel on full tiles (mpdo_test_gemm_rate: device operands,
+    HIP events around 10 launches): one 2048^3 complex product and 16
+    batched 512 x 1024 x 512 products (the size of the chi = 128 contractions),
+    in both MFMA precisions, as context for the workloads' ragged mixes."""
+    from paper_2508_07610_amd import mpdo as M
+    out = {}
+    for prec, name, peak in ((0, "fp64", PEAK["f64_mfma"]), (1, "fp32", PEAK["f32_mfma"])):
+        for (m, n, k, items) in ((2048, 2048, 2048, 1), (512, 512, 1024, 16)):
+            ms = M.test_gemm_rate(prec, m, n, k, items, 10)
+            tf = 8.0 * m * n * k * items / (ms * 1e-3) / 1e12
+            out[f"{name}_{items}x{m}x{n}x{k}"] = {"ms": ms, "tflops": tf, "frac": tf / peak}
+    return out
+
+
 def sampling_leg(shots=4096):
     """Computational-basis sampling of the benchmark state (parameter point 0
     of the noisy RY/CZ ansatz, n=16, depth 10, chi=64, kappa=8, c128): shots
@@ -370,6 +385,7 @@ def main():
         "cpu_baseline": None if a.no_cpu else cpu_baseline(W, a.cpu_layers),
         "time_to_fidelity": None if a.no_ttf else ttf_leg(a.ttf_steps),
         "maxcut_batch": None if a.no_maxcut else maxcut_leg(),
+        "gemm_full_tiles": gemm_tiles_leg(),
         "sampling": None if a.no_sampling else sampling_leg(),
         "crosstalk": None if a.no_crosstalk else crosstalk_leg(),
     }

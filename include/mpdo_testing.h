@@ -31,6 +31,15 @@ mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, in
                            int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha, double* C,
                            int32_t tile);
 
+/* Throughput of the batched MFMA GEMM on full tiles: items independent
+ * products C = A B (op N, N; M x K times K x N, complex128 on FP64 MFMA for
+ * prec 0, complex64 on FP32 MFMA for prec 1) on device operands the call
+ * allocates and fills; one warm-up launch, then reps launches (1..1000)
+ * between HIP events; *ms = average milliseconds per launch.  EINVAL when
+ * the operands would exceed 32 GiB. */
+mpdo_status mpdo_test_gemm_rate(int32_t prec, int32_t M, int32_t N, int32_t K, int32_t items, int32_t reps,
+                                double* ms);
+
 /* Hermitian eigendecomposition of A (n x n, 1 <= n <= 1024) with the
  * library's eigensolver: the leading min(n, kvec + 1) eigenvalues in
  * descending order in evals (the rest of the n entries zero), the

@@ -721,6 +721,69 @@ extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, in
   GUARD_END
 }
 
+namespace {
+template <typename T> __global__ void k_fill_test(T* p, size_t n, unsigned seed) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    unsigned h = (unsigned)i * 2654435761u ^ seed;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    p[i] = (T)((double)(h & 0xFFFF) / 65536.0 - 0.5);
+  }
+}
+
+template <typename T>
+void gemm_rate(int M, int N, int K, int items, int reps, double* ms) {
+  const size_t ea = (size_t)2 * M * K, eb = (size_t)2 * K * N, ec = (size_t)2 * M * N;
+  DevBuf dA, dB, dC, dD;
+  dA.alloc(ea * items * sizeof(T));
+  dB.alloc(eb * items * sizeof(T));
+  dC.alloc(ec * items * sizeof(T));
+  hipLaunchKernelGGL(k_fill_test<T>, dim3(4096), dim3(256), 0, nullptr, dA.as<T>(), ea * items, 11u);
+  hipLaunchKernelGGL(k_fill_test<T>, dim3(4096), dim3(256), 0, nullptr, dB.as<T>(), eb * items, 23u);
+  std::vector<GemmDesc> hd(items);
+  for (int i = 0; i < items; ++i) {
+    GemmDesc& d = hd[i];
+    std::memset(&d, 0, sizeof(d));
+    d.A = reinterpret_cast<const double*>(dA.as<T>() + ea * i);
+    d.B = reinterpret_cast<const double*>(dB.as<T>() + eb * i);
+    d.C = reinterpret_cast<double*>(dC.as<T>() + ec * i);
+    d.M = M; d.N = N; d.K = K; d.lda = K; d.ldb = N; d.ldc = N;
+    d.nbatch = 1; d.splits = 1; d.wdiv = 1; d.active = 1; d.alpha = 1.0;
+  }
+  dD.alloc(sizeof(GemmDesc) * items);
+  hip_check(hipMemcpy(dD.p, hd.data(), sizeof(GemmDesc) * items, hipMemcpyHostToDevice), "descriptors");
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  const int tiles = gemm_tiles(M, N, 64);
+  launch_gemm<T, T, T>(dD.as<GemmDesc>(), items, 1, 1, tiles, nullptr);
+  hip_check(hipEventRecord(e0, nullptr), "event");
+  for (int r = 0; r < reps; ++r) launch_gemm<T, T, T>(dD.as<GemmDesc>(), items, 1, 1, tiles, nullptr);
+  hip_check(hipEventRecord(e1, nullptr), "event");
+  hip_check(hipEventSynchronize(e1), "event");
+  hip_check(hipGetLastError(), "launch");
+  float t = 0;
+  hip_check(hipEventElapsedTime(&t, e0, e1), "event");
+  hip_check(hipEventDestroy(e0), "event");
+  hip_check(hipEventDestroy(e1), "event");
+  *ms = (double)t / reps;
+}
+}  // namespace
+
+extern "C" mpdo_status mpdo_test_gemm_rate(int32_t prec, int32_t M, int32_t N, int32_t K, int32_t items, int32_t reps,
+                                           double* ms) {
+  if (prec < 0 || prec > 1) return fail(MPDO_EINVAL, "prec must be 0 or 1");
+  if (M < 1 || N < 1 || K < 1 || items < 1 || reps < 1 || reps > 1000 || !ms) return fail(MPDO_EINVAL, "bad size");
+  const double bytes = 2.0 * (prec == 0 ? 8 : 4) * items * ((double)M * K + (double)K * N + (double)M * N);
+  if (bytes > 32.0 * (1ULL << 30)) return fail(MPDO_EINVAL, "operands above 32 GiB");
+  GUARD_BEGIN
+  if (prec == 0) gemm_rate<double>(M, N, K, items, reps, ms);
+  else gemm_rate<float>(M, N, K, items, reps, ms);
+  return MPDO_OK;
+  GUARD_END
+}
+
 extern "C" mpdo_status mpdo_test_eigh(int32_t n, int32_t kvec, const double* A, double* evals, double* evecs,
                                       double* trace) {
   if (n < 1 || n > EIG_NMAX) return fail(MPDO_EINVAL, "n must be in [1, 1024]");

@@ -403,6 +403,8 @@ def _testing_lib():
         L.mpdo_test_gemm.argtypes = [i32] * 6 + [pd, i32, i32, pd, i32, i32, pd, i32, i32, ctypes.c_double, pd, i32]
         L.mpdo_test_gemm.restype = ctypes.c_int
         L.mpdo_test_eigh.argtypes = [i32, i32, pd, pd, pd, pd]
+        L.mpdo_test_gemm_rate.argtypes = [i32] * 6 + [pd]
+        L.mpdo_test_gemm_rate.restype = ctypes.c_int
         L.mpdo_test_eigh.restype = ctypes.c_int
         L._testing_sig = True
     return L
@@ -433,3 +435,11 @@ def test_eigh(A: np.ndarray, kvec: Optional[int] = None):
     tr = ctypes.c_double()
     check(_testing_lib().mpdo_test_eigh(n, kvec, _dptr(a), _dptr(ev), _dptr(vec), ctypes.byref(tr)))
     return ev, vec.view(np.complex128).reshape(n, n), tr.value
+
+
+def test_gemm_rate(prec: int, M: int, N: int, K: int, items: int = 1, reps: int = 10) -> float:
+    """Average milliseconds per launch of `items` complex M x K by K x N
+    products on full tiles (prec 0: FP64 MFMA, 1: FP32 MFMA)."""
+    ms = ctypes.c_double()
+    check(_testing_lib().mpdo_test_gemm_rate(prec, M, N, K, items, reps, ctypes.byref(ms)))
+    return ms.value

@@ -157,3 +157,16 @@ def test_profiler_counts_gemm_and_eig_work():
     assert g["bytes"] == 16.0 * (70 * 33 + 33 * 90 + 70 * 90)
     assert e["launches"] == 1 and abs(e["flops"] - (16.0 / 3.0 * 100 ** 3 + 8.0 * 100 ** 2 * 10)) < 1.0
     assert e2["launches"] == 1 and abs(e2["flops"] - (16.0 / 3.0 * 200 ** 3 + 8.0 * 200 ** 2 * 20)) < 1.0
+
+
+def test_gemm_rate_entry_point():
+    """mpdo_test_gemm_rate times launches on device operands; bad sizes are
+    rejected before any allocation."""
+    require_gpu()
+    ms = M.test_gemm_rate(0, 256, 256, 256, 2, 3)
+    assert 0 < ms < 1000
+    assert 0 < M.test_gemm_rate(1, 128, 64, 32, 1, 1) < 1000
+    for bad in ((2, 64, 64, 64, 1, 1), (0, 0, 64, 64, 1, 1), (0, 64, 64, 64, 1, 0), (0, 65536, 65536, 4096, 1, 1)):
+        with pytest.raises(M.MPDOError) as e:
+            M.test_gemm_rate(*bad)
+        assert e.value.status == M.EINVAL
