@@ -639,70 +639,62 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
       // trailing block [p1, n)^2 <- A - V W^H - W V^H
       const int p1 = p0 + np;
       const int mt = n - p1;
-      if (mt > 0 && n <= 256) {
-        // 4 x 4 blocks per thread, all loads of a block independent; the
-        // panel factors come from LDS, transposed (t, row)
+      if (mt > 0) {
+        // 4 x 4 blocks per thread, all loads of a block independent.  The
+        // column factors conj(V), conj(W) come from LDS, transposed (t,
+        // column), in windows of 256 columns; the row factors too when one
+        // window holds the whole block (mt <= 256), else from the panel in
+        // global memory (one row block per wave: a broadcast).
         static_assert(TRB == 8, "LDS panel factors hold eight columns");
-        for (int e = tid; e < np * mt; e += NT) {
-          const int t = e / mt, c = e % mt;
-          S.vcT[t * 256 + c] = cconj(Vp[(long long)(p1 + c) * TRB + t]);
-          S.wcT[t * 256 + c] = cconj(Wp[(long long)(p1 + c) * TRB + t]);
-        }
-        __syncthreads();
-        const int nb = (mt + 3) >> 2;
-        for (int u = tid; u < nb * nb; u += NT) {
-          const int r0 = 4 * (u / nb), q0 = 4 * (u % nb);  // relative to p1
-          cpx<double> x[4][4];
+        const bool one = mt <= 256;
+        for (int cw = 0; cw < mt; cw += 256) {
+          const int wn = min(256, mt - cw);
+          for (int e = tid; e < np * wn; e += NT) {
+            const int t = e / wn, c = e % wn;
+            S.vcT[t * 256 + c] = cconj(Vp[(long long)(p1 + cw + c) * TRB + t]);
+            S.wcT[t * 256 + c] = cconj(Wp[(long long)(p1 + cw + c) * TRB + t]);
+          }
+          __syncthreads();
+          const int nbr = (mt + 3) >> 2, nbc = (wn + 3) >> 2;
+          for (int u = tid; u < nbr * nbc; u += NT) {
+            const int r0 = 4 * (u / nbc), q0 = 4 * (u % nbc);  // rows from p1, columns from p1 + cw
+            cpx<double> x[4][4];
   #pragma unroll
-          for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i)
   #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              x[i][j] = (r0 + i < mt && q0 + j < mt) ? A[(long long)(p1 + r0 + i) * n + p1 + q0 + j] : mk(0.0, 0.0);
+              for (int j = 0; j < 4; ++j)
+                x[i][j] = (r0 + i < mt && q0 + j < wn) ? A[(long long)(p1 + r0 + i) * n + p1 + cw + q0 + j]
+                                                        : mk(0.0, 0.0);
   #pragma unroll
-          for (int t = 0; t < TRB; ++t) {
-            if (t >= np) break;
-            cpx<double> vr[4], wr[4], vc[4], wc[4];
+            for (int t = 0; t < TRB; ++t) {
+              if (t >= np) break;
+              cpx<double> vr[4], wr[4], vc[4], wc[4];
   #pragma unroll
-            for (int i = 0; i < 4; ++i) {  // r0 + i, q0 + i < 256: entries past mt are not stored back
-              vr[i] = cconj(S.vcT[t * 256 + r0 + i]);
-              wr[i] = cconj(S.wcT[t * 256 + r0 + i]);
-              vc[i] = S.vcT[t * 256 + q0 + i];
-              wc[i] = S.wcT[t * 256 + q0 + i];
+              for (int i = 0; i < 4; ++i) {  // indices below 256; entries past mt, wn are not stored back
+                if (one) {
+                  vr[i] = cconj(S.vcT[t * 256 + r0 + i]);
+                  wr[i] = cconj(S.wcT[t * 256 + r0 + i]);
+                } else {
+                  const bool ok = r0 + i < mt;
+                  vr[i] = ok ? Vp[(long long)(p1 + r0 + i) * TRB + t] : mk(0.0, 0.0);
+                  wr[i] = ok ? Wp[(long long)(p1 + r0 + i) * TRB + t] : mk(0.0, 0.0);
+                }
+                vc[i] = S.vcT[t * 256 + q0 + i];
+                wc[i] = S.wcT[t * 256 + q0 + i];
+              }
+  #pragma unroll
+              for (int i = 0; i < 4; ++i)
+  #pragma unroll
+                for (int j = 0; j < 4; ++j) x[i][j] = x[i][j] - vr[i] * wc[j] - wr[i] * vc[j];
             }
   #pragma unroll
             for (int i = 0; i < 4; ++i)
   #pragma unroll
-              for (int j = 0; j < 4; ++j) x[i][j] = x[i][j] - vr[i] * wc[j] - wr[i] * vc[j];
+              for (int j = 0; j < 4; ++j)
+                if (r0 + i < mt && q0 + j < wn) A[(long long)(p1 + r0 + i) * n + p1 + cw + q0 + j] = x[i][j];
           }
-  #pragma unroll
-          for (int i = 0; i < 4; ++i)
-  #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if (r0 + i < mt && q0 + j < mt) A[(long long)(p1 + r0 + i) * n + p1 + q0 + j] = x[i][j];
+          __syncthreads();
         }
-        __syncthreads();
-      } else if (mt > 0) {
-        int nq = NT / mt;
-        if (nq < 1) nq = 1;
-        const int rows_per = (mt + nq - 1) / nq;
-        for (int u = tid; u < mt * nq; u += NT) {
-          const int c = p1 + u % mt, q = u / mt;
-          cpx<double> vc[TRB], wc[TRB];
-  #pragma unroll
-          for (int t = 0; t < TRB; ++t) {
-            vc[t] = t < np ? cconj(Vp[(long long)c * TRB + t]) : mk(0.0, 0.0);
-            wc[t] = t < np ? cconj(Wp[(long long)c * TRB + t]) : mk(0.0, 0.0);
-          }
-          const int r1 = min(n, p1 + (q + 1) * rows_per);
-          for (int r = p1 + q * rows_per; r < r1; ++r) {
-            cpx<double> x = A[(long long)r * n + c];
-  #pragma unroll
-            for (int t = 0; t < TRB; ++t)
-              if (t < np) x = x - Vp[(long long)r * TRB + t] * wc[t] - Wp[(long long)r * TRB + t] * vc[t];
-            A[(long long)r * n + c] = x;
-          }
-        }
-        __syncthreads();
       }
     }
   } else {
