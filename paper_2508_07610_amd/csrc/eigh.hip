@@ -99,8 +99,9 @@ template <int NMAX> struct alignas(16) SharedG {
   int flag[4];
   int clus[NMAX + 1];
   // panel form, n <= 256: conj(V), conj(W) of the panel, transposed (t, column)
-  alignas(16) cpx<double> vcT[NMAX <= 512 ? 8 * 256 : 1];
-  alignas(16) cpx<double> wcT[NMAX <= 512 ? 8 * 256 : 1];
+  // (conj(W) follows at offset 8 * 256; the back-transformation reuses the
+  // whole array for its block of reflectors, n <= 512 rows of 8)
+  alignas(16) cpx<double> pf[NMAX <= 512 ? 2 * 8 * 256 : 1];
 };
 
 // Pending update (vp, wp; index 0 = row `base`) on rows/cols [c0, n) and,
@@ -406,8 +407,11 @@ template <class SH>
 __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict__ A, int n, int kz, SH& S) {
   cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
   // scratch after the matrix: free once the inverse iteration is done
-  cpx<double>* __restrict__ Vb = reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n);  // n x BTB
-  cpx<double>* __restrict__ part = Vb + (long long)n * BTB;                              // nq x BTB x kz
+  cpx<double>* const Vg = reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n);  // n x BTB
+  cpx<double>* __restrict__ part = Vg + (long long)n * BTB;                        // nq x BTB x kz
+  // the block of reflectors in LDS when the panel factors' array holds it
+  constexpr int LV = sizeof(S.pf) / sizeof(S.pf[0]);
+  cpx<double>* __restrict__ Vb = n * BTB <= LV ? S.pf : Vg;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nq = kz < NT ? NT / kz : 1;          // row chunks per column
   cpx<double>* __restrict__ Wt = part + (long long)nq * BTB * kz;                       // BTB x kz
@@ -651,8 +655,8 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
           const int wn = min(256, mt - cw);
           for (int e = tid; e < np * wn; e += NT) {
             const int t = e / wn, c = e % wn;
-            S.vcT[t * 256 + c] = cconj(Vp[(long long)(p1 + cw + c) * TRB + t]);
-            S.wcT[t * 256 + c] = cconj(Wp[(long long)(p1 + cw + c) * TRB + t]);
+            S.pf[t * 256 + c] = cconj(Vp[(long long)(p1 + cw + c) * TRB + t]);
+            S.pf[2048 + t * 256 + c] = cconj(Wp[(long long)(p1 + cw + c) * TRB + t]);
           }
           __syncthreads();
           const int nbr = (mt + 3) >> 2, nbc = (wn + 3) >> 2;
@@ -672,15 +676,15 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
   #pragma unroll
               for (int i = 0; i < 4; ++i) {  // indices below 256; entries past mt, wn are not stored back
                 if (one) {
-                  vr[i] = cconj(S.vcT[t * 256 + r0 + i]);
-                  wr[i] = cconj(S.wcT[t * 256 + r0 + i]);
+                  vr[i] = cconj(S.pf[t * 256 + r0 + i]);
+                  wr[i] = cconj(S.pf[2048 + t * 256 + r0 + i]);
                 } else {
                   const bool ok = r0 + i < mt;
                   vr[i] = ok ? Vp[(long long)(p1 + r0 + i) * TRB + t] : mk(0.0, 0.0);
                   wr[i] = ok ? Wp[(long long)(p1 + r0 + i) * TRB + t] : mk(0.0, 0.0);
                 }
-                vc[i] = S.vcT[t * 256 + q0 + i];
-                wc[i] = S.wcT[t * 256 + q0 + i];
+                vc[i] = S.pf[t * 256 + q0 + i];
+                wc[i] = S.pf[2048 + t * 256 + q0 + i];
               }
   #pragma unroll
               for (int i = 0; i < 4; ++i)
