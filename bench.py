@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-maxcut", action="store_true",
                     help="skip the mixed GHZ-ansatz / QAOA MaxCut batch leg")
     ap.add_argument("--no-sampling", action="store_true", help="skip the bitstring sampling leg")
+    ap.add_argument("--no-gemm-tiles", action="store_true", help="skip the full-tile GEMM throughput leg")
     ap.add_argument("--no-crosstalk", action="store_true",
                     help="skip the crosstalk leg (three-site channels, Kraus pruning thresholds)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -385,7 +386,7 @@ def main():
         "cpu_baseline": None if a.no_cpu else cpu_baseline(W, a.cpu_layers),
         "time_to_fidelity": None if a.no_ttf else ttf_leg(a.ttf_steps),
         "maxcut_batch": None if a.no_maxcut else maxcut_leg(),
-        "gemm_full_tiles": gemm_tiles_leg(),
+        "gemm_full_tiles": None if a.no_gemm_tiles else gemm_tiles_leg(),
         "sampling": None if a.no_sampling else sampling_leg(),
         "crosstalk": None if a.no_crosstalk else crosstalk_leg(),
     }
