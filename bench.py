@@ -54,6 +54,7 @@ def parse():
                     help="skip the mixed GHZ-ansatz / QAOA MaxCut batch leg")
     ap.add_argument("--no-sampling", action="store_true", help="skip the bitstring sampling leg")
     ap.add_argument("--no-gemm-tiles", action="store_true", help="skip the full-tile GEMM throughput leg")
+    ap.add_argument("--no-noise-models", action="store_true", help="skip the standard noise model comparison")
     ap.add_argument("--no-crosstalk", action="store_true",
                     help="skip the crosstalk leg (three-site channels, Kraus pruning thresholds)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -261,6 +262,43 @@ def sampling_leg(shots=4096):
             "max_p_drawn": float(pz.max())}
 
 
+def noise_models_leg(shots=4096):
+    """Bitstring distributions of the noisy RY/CZ ansatz (n=8, depth 4,
+    parameter point 0) under the QPT-style channels and the two standard
+    models (Fig. fig_unifiedNoise: thermal relaxation T1 = 30 us, T2 = 20 us
+    over 30 / 300 ns gates, depolarizing 1e-3 / 1e-2 on the target only or on
+    both qubits, read-out flips 2 %); the Jensen-Shannon divergence (Eq. (18))
+    of each from the QPT-style one, and of a sampled histogram from its exact
+    distribution."""
+    import numpy as np
+    from paper_2508_07610_amd import distributions as D
+    from paper_2508_07610_amd import mpdo as M
+    from paper_2508_07610_amd import workloads as W
+    n, depth = 8, 4
+    base = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, 0))
+    c1 = W.chi_standard_1q(1e-3, 0.03, 30.0, 20.0)
+    models = {"qpt": base,
+              "unified": W.with_channels(base, c1, W.chi_unified_2q(1e-2, 0.3, 30.0, 20.0)),
+              "ideal_noisy": W.with_channels(base, c1, W.chi_ideal_noisy_2q(1e-2, 0.3, 30.0, 20.0))}
+    probs, hist = {}, None
+    for name, prog in models.items():
+        st = M.MPDO(n, chi_max=32, kappa_max=8, max_kraus=64, svd_cutoff=SVD_CUT, kappa_cutoff=KAP_CUT)
+        M.run_program(prog, st, [M.Channel(c, 1 if c.shape[0] == 4 else 2) for c in prog.chis])
+        probs[name] = st.probabilities(D.all_bitstrings(n))
+        if name == "qpt":
+            bits, _ = st.sample(np.random.default_rng(7617).random((shots, n)))
+            idx = bits.astype(np.int64) @ (1 << np.arange(n - 1, -1, -1))
+            hist = np.bincount(idx, minlength=1 << n) / shots
+        st.close()
+    q = probs["qpt"]
+    return {"workload": f"noisy RY/CZ ansatz n={n} depth={depth}, chi=32 kappa=8, c128, full distributions "
+                        "from mpdo_probabilities",
+            "jsd_vs_qpt": {k: D.jsd(q, v) for k, v in probs.items() if k != "qpt"},
+            "jsd_vs_qpt_with_readout_flips": {k: D.jsd(q, D.measurement_flip(v, n, 0.02))
+                                              for k, v in probs.items() if k != "qpt"},
+            "jsd_sampled_vs_exact": {"shots": shots, "jsd": D.jsd(q, hist)}}
+
+
 def crosstalk_leg():
     """Three-site crosstalk channels with Kraus pruning: the random circuit n=24,
     depth 12, chi=128, kappa=16, mixed precision, once per pruning threshold;
@@ -388,6 +426,7 @@ def main():
         "maxcut_batch": None if a.no_maxcut else maxcut_leg(),
         "gemm_full_tiles": None if a.no_gemm_tiles else gemm_tiles_leg(),
         "sampling": None if a.no_sampling else sampling_leg(),
+        "noise_models": None if a.no_noise_models else noise_models_leg(),
         "crosstalk": None if a.no_crosstalk else crosstalk_leg(),
     }
     print(json.dumps(out, default=lambda o: o.item() if hasattr(o, "item") else str(o)))

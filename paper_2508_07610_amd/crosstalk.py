@@ -18,6 +18,7 @@ from typing import Dict, List, Sequence
 import numpy as np
 
 from . import mpdo as M
+from .distributions import all_bitstrings, jsd  # noqa: F401 (re-exported)
 from . import workloads as W
 
 
@@ -54,26 +55,6 @@ def uhlmann_fidelity(rho: np.ndarray, sigma: np.ndarray) -> float:
     ev = np.linalg.eigvalsh((mid + mid.conj().T) / 2)
     ev = np.where(ev > 1e-12 * ev.max(), ev, 0.0)
     return float(np.sum(np.sqrt(ev)) ** 2)
-
-
-def jsd(p: np.ndarray, q: np.ndarray) -> float:
-    """Jensen-Shannon divergence of two bitstring distributions, Eq. (18):
-    half the summed Kullback-Leibler divergences (natural logarithm) of P and
-    Q from their midpoint M = (P + Q) / 2, empty bins contributing nothing."""
-    p = np.asarray(p, dtype=np.float64)
-    q = np.asarray(q, dtype=np.float64)
-    mid = 0.5 * (p + q)
-    out = 0.0
-    for a in (p, q):
-        keep = a > 0
-        out += 0.5 * float(np.dot(a[keep], np.log(a[keep] / mid[keep])))
-    return out
-
-
-def all_bitstrings(n: int) -> np.ndarray:
-    """(2^n, n) uint8, row z = the bits of z with qubit 0 the most significant."""
-    z = np.arange(1 << n)
-    return ((z[:, None] >> (n - 1 - np.arange(n))[None, :]) & 1).astype(np.uint8)
 
 
 def run(n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,

@@ -159,6 +159,74 @@ def chi_2q_default(scale: float = 1.0) -> np.ndarray:
     return chi_from_kraus(ks)
 
 
+# ----------------------------------------------------------------------------
+# standard (non-QPT) noise models of the circuit model (Sec. II.B, Fig.
+# `fig_unifiedNoise`): thermal relaxation over a gate duration, depolarizing
+# after the gate, state-preparation and measurement flips; emitted as the same
+# Pauli chi-matrices the QPT channels use, so either kind drives the simulator.
+# ----------------------------------------------------------------------------
+
+def kraus_phase_damping(lam: float) -> List[np.ndarray]:
+    """Pure dephasing: diag(1, sqrt(1-lam)) and diag(0, sqrt(lam)); the
+    coherence rho_01 shrinks by sqrt(1-lam)."""
+    return [np.diag([1.0, math.sqrt(1 - lam)]).astype(np.complex128),
+            np.diag([0.0, math.sqrt(lam)]).astype(np.complex128)]
+
+
+def kraus_bit_flip(p: float) -> List[np.ndarray]:
+    """X with probability p (the SPAM preparation error of the unified model)."""
+    return [math.sqrt(1 - p) * I2, math.sqrt(p) * X]
+
+
+def kraus_thermal_relaxation(t: float, T1: float, T2: float) -> List[np.ndarray]:
+    """Thermal relaxation over a duration t (T2 <= 2 T1): amplitude damping
+    gamma = 1 - exp(-t/T1), then pure dephasing with exp(-t/T_phi),
+    1/T_phi = 1/T2 - 1/(2 T1), so that P(1) decays as exp(-t/T1) and the
+    coherence as exp(-t/T2)."""
+    if T2 > 2 * T1:
+        raise ValueError("thermal relaxation needs T2 <= 2 T1")
+    gamma = 1 - math.exp(-t / T1)
+    rphi = 1 / T2 - 1 / (2 * T1)
+    lam = 1 - math.exp(-2 * t * rphi)
+    return compose(kraus_amplitude_damping(gamma), kraus_phase_damping(lam))
+
+
+def kron_kraus(a: Sequence[np.ndarray], b: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Kraus set of the product channel a (x) b (a on the first qubit)."""
+    return [np.kron(x, y) for x in a for y in b]
+
+
+def chi_standard_1q(p_dep: float, t: float, T1: float, T2: float) -> np.ndarray:
+    """One-qubit gate noise of the standard models: thermal relaxation over
+    the gate time t, then depolarizing p_dep after the gate."""
+    return chi_from_kraus(compose(kraus_thermal_relaxation(t, T1, T2), kraus_depolarizing(p_dep)))
+
+
+def chi_unified_2q(p_dep: float, t: float, T1: float, T2: float, target: int = 1) -> np.ndarray:
+    """Two-qubit gate noise of the unified model (Fig. `fig_unifiedNoise`(b)):
+    thermal relaxation on both qubits over the gate time t, then depolarizing
+    p_dep on the target qubit only (target 0 or 1 of the pair)."""
+    trc = kraus_thermal_relaxation(t, T1, T2)
+    dep = kraus_depolarizing(p_dep)
+    idk = [I2.copy()]
+    dep2 = kron_kraus(idk, dep) if target == 1 else kron_kraus(dep, idk)
+    return chi_from_kraus(compose(kron_kraus(trc, trc), dep2))
+
+
+def chi_ideal_noisy_2q(p_dep: float, t: float, T1: float, T2: float) -> np.ndarray:
+    """Two-qubit gate noise of the general model (Fig. `fig_unifiedNoise`(c)):
+    thermal relaxation over t, then depolarizing p_dep, on both qubits."""
+    one = compose(kraus_thermal_relaxation(t, T1, T2), kraus_depolarizing(p_dep))
+    return chi_from_kraus(kron_kraus(one, one))
+
+
+def with_channels(prog: "Program", chi1: np.ndarray, chi2: np.ndarray) -> "Program":
+    """The same gates with every one-qubit gate followed by chi1 and every
+    two-qubit gate by chi2 (channels 0 and 1 of the returned program)."""
+    ops = [dataclasses.replace(o, chan=-1 if o.chan < 0 else (0 if len(o.sites) == 1 else 1)) for o in prog.ops]
+    return Program(prog.n, ops, [chi1, chi2], prog.layers)
+
+
 def random_cptp_near_identity_3q(rng: np.random.Generator, spread: float = 1e-2) -> np.ndarray:
     """3-qubit CPTP map close to the identity, as a Pauli chi-matrix (64x64).
     A0 = exp(-i eps H) with H a GUE matrix of scale 1e-2; A_1..A_63 Ginibre
