@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-sampling", action="store_true", help="skip the bitstring sampling leg")
     ap.add_argument("--no-gemm-tiles", action="store_true", help="skip the full-tile GEMM throughput leg")
     ap.add_argument("--no-noise-models", action="store_true", help="skip the standard noise model comparison")
+    ap.add_argument("--no-truncation-study", action="store_true", help="skip the truncation study leg")
     ap.add_argument("--no-crosstalk", action="store_true",
                     help="skip the crosstalk leg (three-site channels, Kraus pruning thresholds)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -299,6 +300,21 @@ def noise_models_leg(shots=4096):
             "jsd_sampled_vs_exact": {"shots": shots, "jsd": D.jsd(q, hist)}}
 
 
+def truncation_study_leg(ncirc=16):
+    """Sec. IV.C: mean Uhlmann fidelity between lossless and truncated states
+    of random circuits with RZ crosstalk (Q = 3 and 6, depth 4) over a grid
+    of (chi, kappa), ncirc circuits each, per-gate calls, FP64."""
+    from paper_2508_07610_amd import truncation_study as TS
+    limits = [(2, 2), (4, 4), (8, 8), (16, 4), (16, 16)]
+    out = {}
+    for q in (3, 6):
+        t0 = time.perf_counter()
+        r = TS.run(q, 4, limits, ncirc=ncirc)
+        out[f"Q={q},depth=4"] = {"fidelity": r, "seconds": time.perf_counter() - t0}
+    return {"workload": f"{ncirc} random RX/RY/RZ + CNOT circuits per Q, RZ(alpha) crosstalk on the neighbour of "
+                        "every CNOT, QPT-style channels, lossless reference at chi=64 kappa=64", "results": out}
+
+
 def crosstalk_leg():
     """Three-site crosstalk channels with Kraus pruning: the random circuit n=24,
     depth 12, chi=128, kappa=16, mixed precision, once per pruning threshold;
@@ -427,6 +443,7 @@ def main():
         "gemm_full_tiles": None if a.no_gemm_tiles else gemm_tiles_leg(),
         "sampling": None if a.no_sampling else sampling_leg(),
         "noise_models": None if a.no_noise_models else noise_models_leg(),
+        "truncation_study": None if a.no_truncation_study else truncation_study_leg(),
         "crosstalk": None if a.no_crosstalk else crosstalk_leg(),
     }
     print(json.dumps(out, default=lambda o: o.item() if hasattr(o, "item") else str(o)))
