@@ -7,7 +7,7 @@ Steps, in the paper's order and notation:
 1. The process matrix chi is given in an operator basis {sigma_m}
    (Eq. (12)): eps(rho) = sum_mn chi_mn sigma_m rho sigma_n^dagger.  Here the
    basis is the unnormalised Pauli products, order I, X, Y, Z, site 0 most
-   significant (the reading listed in the design doc).
+   significant (a reading: the paper does not fix the normalisation or order).
 2. Change of basis to the "Choi" matrix Lambda = sum_mn chi_mn
    |sigma_m>><<sigma_n| (Eqs. (13)-(14)), with |A>> the row-major
    vectorisation of A.

@@ -34,7 +34,7 @@ split by an SVD of lambda_left * Theta; the right factor V^dagger becomes the
 new right tensor, the singular values the new bond weights, and Theta V the
 new left tensor.
 
-Truncation rule for both kinds of index (a reading, listed in the design doc):
+Truncation rule for both kinds of index (a reading: the paper fixes no rule):
 with eigenvalues eta (descending) of the relevant Gram matrix and total
 weight W, keep the smallest r >= 1 with sum_{i >= r} eta_i <= cutoff * W,
 capped at the maximum dimension; then rescale so the kept weight is 1
