@@ -1,26 +1,29 @@
-// Hermitian eigensolver for the truncations (FP64), one workgroup of 1024
+// Hermitian eigensolver for the truncations (FP64), one workgroup of 512
 // threads per matrix:
 //
 //  1. Householder reduction to real symmetric tridiagonal form
 //     T = Q^H A Q,  Q = H_0 H_1 ... H_{n-2},  H_k = I - tau_k v_k v_k^H,
-//     with the reflector chosen so that H_k^H x = beta e_1, beta real.  The
-//     trailing update A <- A - v w^H - w v^H (w = tau p - |tau|^2 (v^H p)/2 v,
-//     p = A v) of step k is fused with the matrix-vector product of step k+1
-//     into one pass over the trailing block, column-parallel (Hermitian
-//     symmetry turns the row products into coalesced column reads) with
-//     eight independent loads in flight per thread.  For n <= 128 the matrix
-//     is held in registers instead (16 entries per thread, see k_heev_reg);
-//     larger matrices stay in global memory (L2-resident).
+//     with the reflector chosen so that H_k^H x = beta e_1, beta real, and
+//     w = tau p - |tau|^2 (v^H p)/2 v, p = A v, for the rank-2 update
+//     A <- A - v w^H - w v^H.  Three forms:
+//     - n <= 128: the matrix is held in registers (k_heev_reg);
+//     - n <= 512: panels of eight columns (k_heev_global): each step reads
+//       the trailing block once and corrects p for the panel's pending
+//       updates; the block is written once per panel, in 4 x 4 register
+//       blocks with the panel factors staged in LDS;
+//     - n <= 1024: one column per step, the update of step k fused with the
+//       matrix-vector pass of step k+1 (k_heev_big; lowest latency for a
+//       lone matrix).
 //  2. The leading kvec + 1 eigenvalues of T by multisection on Sturm counts
 //     (a group of lanes per eigenvalue, one count per lane and round).
 //  3. Their eigenvectors by inverse iteration on T (tridiagonal LU with
 //     partial pivoting, three solves from a fixed pseudo-random start), one
-//     thread per vector, the solves streaming batches of eight entries
-//     between two buffers; then Gram-Schmidt (twice) inside clusters of
-//     eigenvalues closer than 1e-6 (degenerate multiplets).
-//  4. Back-transformation z <- H_0 ... H_{n-2} z, columns in parallel with the
-//     rows of each reflector split over the remaining threads (for n <= 128
-//     the vector block stays in registers).
+//     thread per vector; then Gram-Schmidt (twice) inside clusters of
+//     eigenvalues closer than 1e-6 of their size or 1e-10 of the largest
+//     (degenerate multiplets).
+//  4. Back-transformation z <- H_0 ... H_{n-2} z: with the vector block in
+//     registers for n <= 128 and, in the panel form, for n <= 256 with at
+//     most 64 vectors; otherwise in blocks of eight reflectors (compact WY).
 //
 // Only the eigenpairs a truncation can keep are computed; the discarded
 // weight comes from Tr(A) minus the kept eigenvalues.
@@ -523,6 +526,69 @@ __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict
   }
 }
 
+// Z <- H_0 ... H_{n-2} Z with the vector block in registers, for n <= 256
+// and kz <= 64 (the panel form's LDS holds the reflectors): thread t owns
+// column t % 64 and rows 32 (t / 64) .. 32 (t / 64) + 31 of Z.  Per
+// reflector, from the last: partial y = v^H z over each thread's rows, the
+// eight row chunks summed by every thread of a column, then z -= tau v y;
+// one barrier per reflector (reflector buffers rotate over three slots and
+// the partial sums over two, so a slot is rewritten only after every thread
+// has passed the barrier that follows its last read).
+template <class SH>
+__device__ void back_transform_reg(const EigDesc& dsc, const cpx<double>* __restrict__ A, int n, int kz, SH& S) {
+  constexpr int RB = 32;  // rows per thread
+  cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
+  const int tid = threadIdx.x, c = tid & 63, q = tid >> 6, r0 = q * RB;
+  cpx<double>* vb[3] = {S.pf, S.pf + 256, S.pf + 512};  // reflector k in vb[k % 3]
+  cpx<double>* pw[2] = {S.pf + 1024, S.pf + 1536};      // 8 chunks x 64 columns
+  cpx<double> z[RB];
+#pragma unroll
+  for (int u = 0; u < RB; ++u) {
+    const int r = r0 + u;
+    z[u] = (c < kz && r < n) ? Z[(long long)r * n + c] : mk(0.0, 0.0);
+  }
+  auto load_v = [&](int k, cpx<double>* dst) {  // v_k over all 256 rows (zero outside k+1 .. n-1)
+    for (int i = tid; i < 256; i += NT)
+      dst[i] = (i == k + 1) ? mk(1.0, 0.0) : (i > k + 1 && i < n) ? A[(long long)i * n + k] : mk(0.0, 0.0);
+  };
+  if (n >= 2) load_v(n - 2, vb[(n - 2) % 3]);
+  __syncthreads();
+  for (int k = n - 2; k >= 0; --k) {
+    const cpx<double>* v = vb[k % 3];
+    const cpx<double> t = S.tau[k];
+    const bool act = !(t.re == 0.0 && t.im == 0.0);
+    if (act) {
+      double yr = 0, yi = 0;
+      if (r0 + RB > k + 1) {
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          const cpx<double> vv = v[r0 + u];
+          yr += vv.re * z[u].re + vv.im * z[u].im;  // conj(v) z
+          yi += vv.re * z[u].im - vv.im * z[u].re;
+        }
+      }
+      pw[k & 1][q * 64 + c] = mk(yr, yi);
+    }
+    if (k >= 1) load_v(k - 1, vb[(k - 1) % 3]);
+    __syncthreads();
+    if (act && r0 + RB > k + 1) {
+      cpx<double> y = mk(0.0, 0.0);
+#pragma unroll
+      for (int qq = 0; qq < NT / 64; ++qq) y = y + pw[k & 1][qq * 64 + c];
+      const cpx<double> ty = t * y;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) z[u] = z[u] - v[r0 + u] * ty;
+    }
+  }
+  if (c < kz) {
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int r = r0 + u;
+      if (r < n) Z[(long long)r * n + c] = z[u];
+    }
+  }
+}
+
 // PANEL: the panel-blocked reduction (less memory traffic per step, more
 // work per step: faster when many matrices share the memory system);
 // otherwise one fused pass per step (lower latency for a lone matrix).
@@ -779,7 +845,12 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
   __syncthreads();
   const int kz = eig_tail<NT>(dsc, n, tr, S, par);
   // ---- 6. back-transformation z <- H_0 ... H_{n-2} z, in blocks ----
-  if (kz > 0) back_transform(dsc, A, n, kz, S);
+  if constexpr (PANEL) {
+    if (kz > 0 && n <= 256 && kz <= 64) back_transform_reg(dsc, A, n, kz, S);
+    else if (kz > 0) back_transform(dsc, A, n, kz, S);
+  } else if (kz > 0) {
+    back_transform(dsc, A, n, kz, S);
+  }
 }
 }  // namespace
 
