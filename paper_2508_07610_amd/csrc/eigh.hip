@@ -589,6 +589,183 @@ __device__ void back_transform_reg(const EigDesc& dsc, const cpx<double>* __rest
   }
 }
 
+// Step 2 in the panel form (see heev_core); LV: the panel's V and W live in
+// LDS (n <= 256), else in the work array after the matrix.
+template <bool LV, class SH>
+__device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, int n, SH& S, int& par) {
+  const int tid = threadIdx.x;
+  // ---- 2. tridiagonalisation, in panels of TRB columns ----
+  // Within a panel the trailing block is not updated: after j steps it is
+  // A - V W^H - W V^H with the panel's reflectors v_q and w_q = tau p -
+  // (|tau|^2 / 2)(v^H p) v (zero above their first row), so a step reads the
+  // trailing block once (p = A v - V (W^H v) - W (V^H v)) and the block is
+  // written once per panel.
+  cpx<double>* __restrict__ Vp = reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n);  // n x TRB
+  cpx<double>* __restrict__ Wp = Vp + (long long)n * TRB;
+  // n <= 256: V and W of the panel live in LDS, transposed (t, row)
+  constexpr bool lv = LV;
+  auto vp = [&](int row, int t) -> cpx<double>& { return lv ? S.pf[t * 256 + row] : Vp[(long long)row * TRB + t]; };
+  auto wp = [&](int row, int t) -> cpx<double>& {
+    return lv ? S.pf[2048 + t * 256 + row] : Wp[(long long)row * TRB + t];
+  };
+  cpx<double>* xk = S.wp;     // current column k (rows k..n-1)
+  cpx<double>* y12 = S.vp;    // W^H v (0..TRB) and V^H v (TRB..2 TRB)
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int p0 = 0; p0 + 1 < n; p0 += TRB) {
+    const int np = min(TRB, n - 1 - p0);
+    for (int j = 0; j < np; ++j) {
+      const int k = p0 + j, m = n - k - 1, c0 = k + 1;
+      // current column k from row k of the stored matrix and the panel so far
+      for (int i = k + tid; i < n; i += NT) {
+        cpx<double> x = cconj(A[(long long)k * n + i]);
+        for (int q = 0; q < j; ++q)
+          x = x - vp(i, q) * cconj(wp(k, q)) - wp(i, q) * cconj(vp(k, q));
+        xk[i - k] = x;
+      }
+      __syncthreads();
+      if (tid == 0) S.d[k] = xk[0].re;
+      double xn = 0;
+      for (int i = 2 + tid; i <= m; i += NT) xn += cabs2(xk[i]);
+      xn = block_sum(xn, S.red, par);
+      if (tid == 0) {
+        const cpx<double> alpha = xk[1];
+        if (xn == 0.0 && alpha.im == 0.0) {
+          S.tau[k] = mk(0.0, 0.0);
+          S.e[k] = alpha.re;
+          S.flag[0] = 0;
+        } else {
+          const double nrm = sqrt(cabs2(alpha) + xn);
+          const double beta = alpha.re >= 0 ? -nrm : nrm;
+          S.tau[k] = mk((beta - alpha.re) / beta, -alpha.im / beta);
+          const cpx<double> den = mk(alpha.re - beta, alpha.im);  // scal = 1 / (alpha - beta)
+          const double dd = cabs2(den);
+          S.scal[0] = den.re / dd;
+          S.scal[1] = -den.im / dd;
+          S.e[k] = beta;
+          S.flag[0] = 1;
+        }
+      }
+      __syncthreads();
+      const bool act = S.flag[0] != 0;
+      const cpx<double> tau = S.tau[k];
+      const cpx<double> sc = mk(S.scal[0], S.scal[1]);
+      for (int i = tid; i < m; i += NT) {
+        const cpx<double> v = !act ? mk(0.0, 0.0) : (i == 0) ? mk(1.0, 0.0) : xk[1 + i] * sc;
+        S.v[i] = v;
+        if (act) A[(long long)(c0 + i) * n + k] = v;  // kept for the back-transformation
+        vp(c0 + i, j) = v;
+      }
+      __syncthreads();
+      if (!act) {
+        for (int i = tid; i < m; i += NT) wp(c0 + i, j) = mk(0.0, 0.0);
+        __syncthreads();
+        continue;
+      }
+      fused_pass(A, n, c0, k, false, true, S);  // S.pp = A22 v (stored block)
+      // y1 = W^H v, y2 = V^H v over rows c0..n-1, one wave per dot product
+      for (int d = wave; d < 2 * j; d += NT / 64) {
+        const bool isw = d < j;
+        const int q = isw ? d : d - j;
+        double yr = 0, yi = 0;
+        for (int i = lane; i < m; i += 64) {
+          const cpx<double> a = isw ? wp(c0 + i, q) : vp(c0 + i, q), v = S.v[i];
+          yr += a.re * v.re + a.im * v.im;  // conj(a) v
+          yi += a.re * v.im - a.im * v.re;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          yr += __shfl_xor(yr, off, 64);
+          yi += __shfl_xor(yi, off, 64);
+        }
+        if (lane == 0) y12[(d < j ? 0 : TRB) + q] = mk(yr, yi);
+      }
+      __syncthreads();
+      double g = 0;  // gamma = v^H p with p corrected for the panel
+      for (int i = tid; i < m; i += NT) {
+        cpx<double> pv = S.pp[i];
+        for (int q = 0; q < j; ++q)
+          pv = pv - vp(c0 + i, q) * y12[q] - wp(c0 + i, q) * y12[TRB + q];
+        S.pp[i] = pv;
+        g += S.v[i].re * pv.re + S.v[i].im * pv.im;
+      }
+      g = block_sum(g, S.red, par);
+      const double cc = 0.5 * cabs2(tau) * g;
+      for (int i = tid; i < m; i += NT) wp(c0 + i, j) = tau * S.pp[i] - cc * S.v[i];
+      __syncthreads();
+    }
+    // trailing block [p1, n)^2 <- A - V W^H - W V^H
+    const int p1 = p0 + np;
+    const int mt = n - p1;
+    if (mt > 0) {
+      // 4 x 4 blocks per thread, all loads of a block independent.  For
+      // n <= 256 the factors are read where they live (LDS); otherwise the
+      // column factors conj(V), conj(W) are staged in LDS, transposed (t,
+      // column), in windows of 256 columns, and the row factors come from
+      // LDS too when one window holds the whole block (mt <= 256), else from
+      // the panel in global memory (one row block per wave: a broadcast).
+      static_assert(TRB == 8, "LDS panel factors hold eight columns");
+      const bool one = mt <= 256;
+      for (int cw = 0; cw < mt; cw += 256) {
+        const int wn = min(256, mt - cw);
+        if (!lv) {
+          for (int e = tid; e < np * wn; e += NT) {
+            const int t = e / wn, c = e % wn;
+            S.pf[t * 256 + c] = cconj(Vp[(long long)(p1 + cw + c) * TRB + t]);
+            S.pf[2048 + t * 256 + c] = cconj(Wp[(long long)(p1 + cw + c) * TRB + t]);
+          }
+          __syncthreads();
+        }
+        const int nbr = (mt + 3) >> 2, nbc = (wn + 3) >> 2;
+        for (int u = tid; u < nbr * nbc; u += NT) {
+          const int r0 = 4 * (u / nbc), q0 = 4 * (u % nbc);  // rows from p1, columns from p1 + cw
+          cpx<double> x[4][4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              x[i][j] = (r0 + i < mt && q0 + j < wn) ? A[(long long)(p1 + r0 + i) * n + p1 + cw + q0 + j]
+                                                      : mk(0.0, 0.0);
+#pragma unroll
+          for (int t = 0; t < TRB; ++t) {
+            if (t >= np) break;
+            cpx<double> vr[4], wr[4], vc[4], wc[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {  // indices below 256; entries past mt, wn are not stored back
+              if (lv) {
+                const int rr = min(p1 + r0 + i, 255), cc = min(p1 + q0 + i, 255);
+                vr[i] = S.pf[t * 256 + rr];
+                wr[i] = S.pf[2048 + t * 256 + rr];
+                vc[i] = cconj(S.pf[t * 256 + cc]);
+                wc[i] = cconj(S.pf[2048 + t * 256 + cc]);
+                continue;
+              }
+              if (one) {
+                vr[i] = cconj(S.pf[t * 256 + r0 + i]);
+                wr[i] = cconj(S.pf[2048 + t * 256 + r0 + i]);
+              } else {
+                const bool ok = r0 + i < mt;
+                vr[i] = ok ? Vp[(long long)(p1 + r0 + i) * TRB + t] : mk(0.0, 0.0);
+                wr[i] = ok ? Wp[(long long)(p1 + r0 + i) * TRB + t] : mk(0.0, 0.0);
+              }
+              vc[i] = S.pf[t * 256 + q0 + i];
+              wc[i] = S.pf[2048 + t * 256 + q0 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) x[i][j] = x[i][j] - vr[i] * wc[j] - wr[i] * vc[j];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (r0 + i < mt && q0 + j < wn) A[(long long)(p1 + r0 + i) * n + p1 + cw + q0 + j] = x[i][j];
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 // PANEL: the panel-blocked reduction (less memory traffic per step, more
 // work per step: faster when many matrices share the memory system);
 // otherwise one fused pass per step (lower latency for a lone matrix).
@@ -613,160 +790,8 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
   for (int i = tid; i < n; i += NT) tr += A[i * n + i].re;
   tr = block_sum(tr, S.red, par);
   if constexpr (PANEL) {
-    // ---- 2. tridiagonalisation, in panels of TRB columns ----
-    // Within a panel the trailing block is not updated: after j steps it is
-    // A - V W^H - W V^H with the panel's reflectors v_q and w_q = tau p -
-    // (|tau|^2 / 2)(v^H p) v (zero above their first row), so a step reads the
-    // trailing block once (p = A v - V (W^H v) - W (V^H v)) and the block is
-    // written once per panel.
-    cpx<double>* __restrict__ Vp = reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n);  // n x TRB
-    cpx<double>* __restrict__ Wp = Vp + (long long)n * TRB;
-    cpx<double>* xk = S.wp;     // current column k (rows k..n-1)
-    cpx<double>* y12 = S.vp;    // W^H v (0..TRB) and V^H v (TRB..2 TRB)
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int p0 = 0; p0 + 1 < n; p0 += TRB) {
-      const int np = min(TRB, n - 1 - p0);
-      for (int j = 0; j < np; ++j) {
-        const int k = p0 + j, m = n - k - 1, c0 = k + 1;
-        // current column k from row k of the stored matrix and the panel so far
-        for (int i = k + tid; i < n; i += NT) {
-          cpx<double> x = cconj(A[(long long)k * n + i]);
-          for (int q = 0; q < j; ++q)
-            x = x - Vp[(long long)i * TRB + q] * cconj(Wp[(long long)k * TRB + q]) -
-                Wp[(long long)i * TRB + q] * cconj(Vp[(long long)k * TRB + q]);
-          xk[i - k] = x;
-        }
-        __syncthreads();
-        if (tid == 0) S.d[k] = xk[0].re;
-        double xn = 0;
-        for (int i = 2 + tid; i <= m; i += NT) xn += cabs2(xk[i]);
-        xn = block_sum(xn, S.red, par);
-        if (tid == 0) {
-          const cpx<double> alpha = xk[1];
-          if (xn == 0.0 && alpha.im == 0.0) {
-            S.tau[k] = mk(0.0, 0.0);
-            S.e[k] = alpha.re;
-            S.flag[0] = 0;
-          } else {
-            const double nrm = sqrt(cabs2(alpha) + xn);
-            const double beta = alpha.re >= 0 ? -nrm : nrm;
-            S.tau[k] = mk((beta - alpha.re) / beta, -alpha.im / beta);
-            const cpx<double> den = mk(alpha.re - beta, alpha.im);  // scal = 1 / (alpha - beta)
-            const double dd = cabs2(den);
-            S.scal[0] = den.re / dd;
-            S.scal[1] = -den.im / dd;
-            S.e[k] = beta;
-            S.flag[0] = 1;
-          }
-        }
-        __syncthreads();
-        const bool act = S.flag[0] != 0;
-        const cpx<double> tau = S.tau[k];
-        const cpx<double> sc = mk(S.scal[0], S.scal[1]);
-        for (int i = tid; i < m; i += NT) {
-          const cpx<double> v = !act ? mk(0.0, 0.0) : (i == 0) ? mk(1.0, 0.0) : xk[1 + i] * sc;
-          S.v[i] = v;
-          if (act) A[(long long)(c0 + i) * n + k] = v;  // kept for the back-transformation
-          Vp[(long long)(c0 + i) * TRB + j] = v;
-        }
-        __syncthreads();
-        if (!act) {
-          for (int i = tid; i < m; i += NT) Wp[(long long)(c0 + i) * TRB + j] = mk(0.0, 0.0);
-          __syncthreads();
-          continue;
-        }
-        fused_pass(A, n, c0, k, false, true, S);  // S.pp = A22 v (stored block)
-        // y1 = W^H v, y2 = V^H v over rows c0..n-1, one wave per dot product
-        for (int d = wave; d < 2 * j; d += NT / 64) {
-          const cpx<double>* Y = d < j ? Wp : Vp;
-          const int q = d < j ? d : d - j;
-          double yr = 0, yi = 0;
-          for (int i = lane; i < m; i += 64) {
-            const cpx<double> a = Y[(long long)(c0 + i) * TRB + q], v = S.v[i];
-            yr += a.re * v.re + a.im * v.im;  // conj(a) v
-            yi += a.re * v.im - a.im * v.re;
-          }
-          for (int off = 32; off > 0; off >>= 1) {
-            yr += __shfl_xor(yr, off, 64);
-            yi += __shfl_xor(yi, off, 64);
-          }
-          if (lane == 0) y12[(d < j ? 0 : TRB) + q] = mk(yr, yi);
-        }
-        __syncthreads();
-        double g = 0;  // gamma = v^H p with p corrected for the panel
-        for (int i = tid; i < m; i += NT) {
-          cpx<double> pv = S.pp[i];
-          for (int q = 0; q < j; ++q)
-            pv = pv - Vp[(long long)(c0 + i) * TRB + q] * y12[q] - Wp[(long long)(c0 + i) * TRB + q] * y12[TRB + q];
-          S.pp[i] = pv;
-          g += S.v[i].re * pv.re + S.v[i].im * pv.im;
-        }
-        g = block_sum(g, S.red, par);
-        const double cc = 0.5 * cabs2(tau) * g;
-        for (int i = tid; i < m; i += NT) Wp[(long long)(c0 + i) * TRB + j] = tau * S.pp[i] - cc * S.v[i];
-        __syncthreads();
-      }
-      // trailing block [p1, n)^2 <- A - V W^H - W V^H
-      const int p1 = p0 + np;
-      const int mt = n - p1;
-      if (mt > 0) {
-        // 4 x 4 blocks per thread, all loads of a block independent.  The
-        // column factors conj(V), conj(W) come from LDS, transposed (t,
-        // column), in windows of 256 columns; the row factors too when one
-        // window holds the whole block (mt <= 256), else from the panel in
-        // global memory (one row block per wave: a broadcast).
-        static_assert(TRB == 8, "LDS panel factors hold eight columns");
-        const bool one = mt <= 256;
-        for (int cw = 0; cw < mt; cw += 256) {
-          const int wn = min(256, mt - cw);
-          for (int e = tid; e < np * wn; e += NT) {
-            const int t = e / wn, c = e % wn;
-            S.pf[t * 256 + c] = cconj(Vp[(long long)(p1 + cw + c) * TRB + t]);
-            S.pf[2048 + t * 256 + c] = cconj(Wp[(long long)(p1 + cw + c) * TRB + t]);
-          }
-          __syncthreads();
-          const int nbr = (mt + 3) >> 2, nbc = (wn + 3) >> 2;
-          for (int u = tid; u < nbr * nbc; u += NT) {
-            const int r0 = 4 * (u / nbc), q0 = 4 * (u % nbc);  // rows from p1, columns from p1 + cw
-            cpx<double> x[4][4];
-  #pragma unroll
-            for (int i = 0; i < 4; ++i)
-  #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                x[i][j] = (r0 + i < mt && q0 + j < wn) ? A[(long long)(p1 + r0 + i) * n + p1 + cw + q0 + j]
-                                                        : mk(0.0, 0.0);
-  #pragma unroll
-            for (int t = 0; t < TRB; ++t) {
-              if (t >= np) break;
-              cpx<double> vr[4], wr[4], vc[4], wc[4];
-  #pragma unroll
-              for (int i = 0; i < 4; ++i) {  // indices below 256; entries past mt, wn are not stored back
-                if (one) {
-                  vr[i] = cconj(S.pf[t * 256 + r0 + i]);
-                  wr[i] = cconj(S.pf[2048 + t * 256 + r0 + i]);
-                } else {
-                  const bool ok = r0 + i < mt;
-                  vr[i] = ok ? Vp[(long long)(p1 + r0 + i) * TRB + t] : mk(0.0, 0.0);
-                  wr[i] = ok ? Wp[(long long)(p1 + r0 + i) * TRB + t] : mk(0.0, 0.0);
-                }
-                vc[i] = S.pf[t * 256 + q0 + i];
-                wc[i] = S.pf[2048 + t * 256 + q0 + i];
-              }
-  #pragma unroll
-              for (int i = 0; i < 4; ++i)
-  #pragma unroll
-                for (int j = 0; j < 4; ++j) x[i][j] = x[i][j] - vr[i] * wc[j] - wr[i] * vc[j];
-            }
-  #pragma unroll
-            for (int i = 0; i < 4; ++i)
-  #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                if (r0 + i < mt && q0 + j < wn) A[(long long)(p1 + r0 + i) * n + p1 + cw + q0 + j] = x[i][j];
-          }
-          __syncthreads();
-        }
-      }
-    }
+    if (n <= 256) panel_tridiag<true>(dsc, A, n, S, par);
+    else panel_tridiag<false>(dsc, A, n, S, par);
   } else {
     // ---- 2. tridiagonalisation, one column per step: the previous step's
     // rank-2 update is fused with this step's matrix-vector pass ----
