@@ -899,7 +899,7 @@ constexpr int RR = RN / RQ;   // rows per thread
 struct alignas(16) SharedR {
   alignas(16) cpx<double> tau[RN];
   alignas(16) cpx<double> x[RN];
-  alignas(16) cpx<double> v[2][RN];
+  alignas(16) cpx<double> v[3][RN];
   alignas(16) cpx<double> vp[RN];
   alignas(16) cpx<double> wp[RN];
   alignas(16) cpx<double> pp[2][RQ][RN];
@@ -1114,10 +1114,15 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
       const int r = r0 + u;
       z[u] = (c < kz && r < n) ? Z[(long long)r * n + c] : mk(0.0, 0.0);
     }
-    if (n >= 2 && tid == n - 1) S.v[(n - 2) & 1][tid] = Vg[(long long)(n - 2) * n + tid];
+    // reflector k in S.v[k % 3] (zero outside rows k+1 .. n-1), partial sums
+    // in S.pp[k & 1]: one barrier per reflector, since a slot is rewritten
+    // only after every thread has passed the barrier that follows its last read
+    for (int i = tid; i < 3 * RN; i += NTR) S.v[i / RN][i % RN] = mk(0.0, 0.0);
+    __syncthreads();
+    if (n >= 2 && tid == n - 1) S.v[(n - 2) % 3][tid] = Vg[(long long)(n - 2) * n + tid];
+    __syncthreads();
     for (int k = n - 2; k >= 0; --k) {
-      const int b = k & 1;
-      __syncthreads();  // v[b] of reflector k is visible; pp[b] is free
+      const cpx<double>* __restrict__ vk = S.v[k % 3];
       const bool pre = k >= 1 && tid >= k && tid < n;
       cpx<double> vn = mk(0.0, 0.0);
       if (pre) vn = Vg[(long long)(k - 1) * n + tid];  // next reflector, stored below
@@ -1130,23 +1135,23 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
         if (rows) {
 #pragma unroll
           for (int u = 0; u < RR; ++u) {
-            const cpx<double> v = S.v[b][r0 + u];
+            const cpx<double> v = vk[r0 + u];
             yr += v.re * z[u].re + v.im * z[u].im;  // conj(v) z
             yi += v.re * z[u].im - v.im * z[u].re;
           }
         }
-        S.pp[b][q][c] = mk(yr, yi);
+        S.pp[k & 1][q][c] = mk(yr, yi);
       }
+      if (pre) S.v[(k - 1) % 3][tid] = vn;
       __syncthreads();
       if (active && c < kz && rows) {
         cpx<double> y = mk(0.0, 0.0);
 #pragma unroll
-        for (int qq = 0; qq < RQ; ++qq) y = y + S.pp[b][qq][c];
+        for (int qq = 0; qq < RQ; ++qq) y = y + S.pp[k & 1][qq][c];
         const cpx<double> ty = t * y;
 #pragma unroll
-        for (int u = 0; u < RR; ++u) z[u] = z[u] - S.v[b][r0 + u] * ty;
+        for (int u = 0; u < RR; ++u) z[u] = z[u] - vk[r0 + u] * ty;
       }
-      if (pre) S.v[b ^ 1][tid] = vn;
     }
     if (c < kz) {
 #pragma unroll
