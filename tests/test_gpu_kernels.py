@@ -86,7 +86,7 @@ def test_eigh_against_numpy(n):
     assert bool(np.all(np.diff(ev) <= 0))
 
 
-@pytest.mark.parametrize("n,kvec", [(40, 5), (128, 16), (256, 64), (300, 100), (700, 17), (1024, 16)])
+@pytest.mark.parametrize("n,kvec", [(40, 5), (128, 16), (129, 64), (200, 40), (256, 1), (256, 64), (256, 65), (300, 100), (700, 17), (1024, 16)])
 def test_eigh_leading_subset(n, kvec):
     """Only the leading kvec eigenpairs (and kvec + 1 eigenvalues) are produced."""
     require_gpu()
