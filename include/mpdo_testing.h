@@ -25,11 +25,15 @@ extern "C" {
  *   A holds rowsA x lda values, B rowsB x ldb; C is M x N (leading dim N).
  *   w (may be NULL): real weights, op(A)(i, k) is multiplied by w[k / wdiv].
  *   splits: split-K count (1..64).
- *   tile: output tile edge of the kernel variant, 64 or 32. */
+ *   tile: output tile edge of the kernel variant, 64 or 32.
+ *   herm: 1 = C is Hermitian (M == N, e.g. a Gram matrix A^H A): only the
+ *   tiles on and above the diagonal are computed, the entries of the tiles
+ *   below it are returned as 0; 0 = the full product.  EINVAL for herm = 1
+ *   with M != N or any other value. */
 mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
                            const double* A, int32_t rowsA, int32_t lda, const double* B, int32_t rowsB,
                            int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha, double* C,
-                           int32_t tile);
+                           int32_t tile, int32_t herm);
 
 /* Throughput of the batched MFMA GEMM on full tiles: items independent
  * products C = A B (op N, N; M x K times K x N, complex128 on FP64 MFMA for

@@ -655,9 +655,10 @@ template <typename Tin> std::vector<Tin> to_prec(const double* a, size_t n) {
 extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
                                       const double* A, int32_t rowsA, int32_t lda, const double* B, int32_t rowsB,
                                       int32_t ldb, const double* w, int32_t wdiv, int32_t splits, double alpha,
-                                      double* C, int32_t tile) {
+                                      double* C, int32_t tile, int32_t herm) {
   if (prec < 0 || prec > 2 || opA < 0 || opA > 3 || opB < 0 || opB > 3) return fail(MPDO_EINVAL, "bad mode");
   if (tile != 64 && tile != 32) return fail(MPDO_EINVAL, "tile must be 64 or 32");
+  if (herm != 0 && (herm != 1 || M != N)) return fail(MPDO_EINVAL, "herm needs a square C");
   if (M < 1 || N < 1 || K < 1 || rowsA < 1 || rowsB < 1 || lda < 1 || ldb < 1 || splits < 1 || splits > 64)
     return fail(MPDO_EINVAL, "bad size");
   if (!A || !B || !C) return fail(MPDO_EINVAL, "null buffer");
@@ -675,6 +676,7 @@ extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, in
   dB.alloc(nb * esz);
   const size_t outsz = prec == 1 ? 4 : 8;
   dC.alloc((size_t)2 * M * N * splits * outsz);
+  if (herm) hip_check(hipMemset(dC.p, 0, (size_t)2 * M * N * splits * outsz), "C");  // tiles left unwritten
   if (prec == 0) {
     hip_check(hipMemcpy(dA.p, A, na * 8, hipMemcpyHostToDevice), "A");
     hip_check(hipMemcpy(dB.p, B, nb * 8, hipMemcpyHostToDevice), "B");
@@ -695,9 +697,10 @@ extern "C" mpdo_status mpdo_test_gemm(int32_t prec, int32_t opA, int32_t opB, in
   d.M = M; d.N = N; d.K = K; d.lda = lda; d.ldb = ldb; d.ldc = N; d.wdiv = w ? wdiv : 1;
   d.nbatch = 1; d.splits = splits; d.sSplit = (long long)M * N; d.opA = opA; d.opB = opB; d.active = 1;
   d.alpha = alpha;
+  d.herm = herm;
   dD.alloc(sizeof(GemmDesc));
   hip_check(hipMemcpy(dD.p, &d, sizeof(d), hipMemcpyHostToDevice), "desc");
-  const int tiles = gemm_tiles(M, N, tile);
+  const int tiles = herm ? gemm_tiles_herm(N, tile) : gemm_tiles(M, N, tile);
   if (prec == 0) launch_gemm<double, double, double>(dD.as<GemmDesc>(), 1, 1, splits, tiles, st, tile);
   else if (prec == 1) launch_gemm<float, float, float>(dD.as<GemmDesc>(), 1, 1, splits, tiles, st, tile);
   else launch_gemm<float, double, double>(dD.as<GemmDesc>(), 1, 1, splits, tiles, st, tile);

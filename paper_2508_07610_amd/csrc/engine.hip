@@ -425,7 +425,7 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   int* status = sweeps_.as<int>();
   launch_q2_prepare<T>(dctx, n, splitsE, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGramE), n, 1, splitsE, gemm_tiles(2 * cx, 2 * cx),
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGramE), n, 1, splitsE, gemm_tiles_herm(2 * cx),
                                  st_);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramE), reinterpret_cast<double**>(dv + uOutsE), n,
                        4 * cx * cx, st_);
@@ -440,7 +440,7 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigG), n, ng, status + n, st_);
   launch_q2_select_g<T>(dctx, n, splitsC, tp, st_);
   launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh2), n, cx, 1, gemm_tiles(4 * kx, 2 * cx, tileH), st_, tileH);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uC), n, 1, splitsC, gemm_tiles(4 * cx, 4 * cx), st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uC), n, 1, splitsC, gemm_tiles_herm(4 * cx), st_);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uC), reinterpret_cast<double**>(dv + uOutsC), n,
                        16 * cx * cx, st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigC), n, 4 * cx, status + 2 * n, st_);
@@ -742,7 +742,7 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
   // outer bases
   launch_q3_prepare<T>(dctx, n, spN, spE, st_);
   launch_q3_perm_in<T>(dctx, n, st_);
-  launch_gemm<T, double, double>(dG + gN * n, 2 * n, 1, std::max(spN, spE), gemm_tiles(n2, n2), st_);
+  launch_gemm<T, double, double>(dG + gN * n, 2 * n, 1, std::max(spN, spE), gemm_tiles_herm(n2), st_);
   launch_reduce_splits(dG + gN * n, douts, 2 * n, n2 * n2, st_);
   launch_eigh(dE + eN * n, 2 * n, n2, status, st_);
   launch_q3_sel_env<T>(dctx, n, spH, Q3_BASIS_FLOOR, st_);
@@ -756,7 +756,7 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
   launch_q3_sel_h<T>(dctx, n, spC1, tp, st_);
   launch_gemm<T, T, T>(dG + gPsi2 * n, n, n2, 1, gemm_tiles(nh, n2), st_);
   // bond i
-  launch_gemm<T, double, double>(dG + gC1 * n, n, 1, spC1, gemm_tiles(n4, n4), st_);
+  launch_gemm<T, double, double>(dG + gC1 * n, n, 1, spC1, gemm_tiles_herm(n4), st_);
   launch_reduce_splits(dG + gC1 * n, douts + 3 * n, n, n4 * n4, st_);
   launch_eigh(dE + e1 * n, n, n4, status + 3 * n, st_);
   launch_q3_sel_1<T>(dctx, n, spC2, tp, st_);
@@ -765,7 +765,7 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
                        std::max(gemm_tiles(cx, 4 * kx * n2), gemm_tiles(cx * kx, n2)), st_);
   launch_q3_perm_out<T>(dctx, n, st_);
   // bond i+1
-  launch_gemm<T, double, double>(dG + gC2 * n, n, 1, spC2, gemm_tiles(n4, n4), st_);
+  launch_gemm<T, double, double>(dG + gC2 * n, n, 1, spC2, gemm_tiles_herm(n4), st_);
   launch_reduce_splits(dG + gC2 * n, douts + 4 * n, n, n4 * n4, st_);
   launch_eigh(dE + e2 * n, n, n4, status + 4 * n, st_);
   launch_q3_sel_2<T>(dctx, n, tp, st_);
@@ -845,7 +845,7 @@ void Engine<T>::sweep_step(const std::vector<int>& inst, int pass, int si, const
   commit(up, h, dv, u.off);
   CtxS<T>* dctx = reinterpret_cast<CtxS<T>*>(dv + uCtx);
   launch_sw_prepare<T>(dctx, n, splits, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uG), n, 1, splits, gemm_tiles(cx, cx), st_);
+  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uG), n, 1, splits, gemm_tiles_herm(cx), st_);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uG), reinterpret_cast<double**>(dv + uOut), n, cx * cx,
                        st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uE), n, cx, sweeps_.as<int>(), st_);

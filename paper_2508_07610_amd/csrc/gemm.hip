@@ -116,8 +116,14 @@ void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int
   const long long per_xcd = (nblocks + NXCD - 1) / NXCD;
   long long bid = (long long)(blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
   if (bid >= nblocks) return;
-  const int tile = (int)(bid % maxTiles);
-  bid /= maxTiles;
+  // Items with fewer tiles than maxTiles leave blocks with nothing to do.
+  // Workgroups reach the CUs of an XCD in a fixed rotation, so a block
+  // position that is idle in every group would leave the same CUs idle for
+  // the whole launch; rotating the tile order by the group index spreads the
+  // idle positions over all CUs.
+  const long long grp = bid / maxTiles;
+  const int tile = (int)((bid + grp) % maxTiles);
+  bid = grp;
   const int split = (int)(bid % maxSplits);
   bid /= maxSplits;
   const int batch = (int)(bid % maxBatch);
@@ -127,9 +133,23 @@ void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int
   const int M = d.M, N = d.N, K = d.K;
   // this item's tiles are a prefix of the tile range
   const int tilesN = (N + TN - 1) / TN;
-  if (tile >= ((M + TM - 1) / TM) * tilesN) return;
-  const int tm = tile / tilesN, tn = tile % tilesN;
-  if (d.herm && tm > tn) return;  // Hermitian C: the lower tiles are not needed
+  int tm, tn;
+  if (d.herm) {
+    // Hermitian (square) C: only the tiles on and above the diagonal, numbered
+    // row by row, so no block of the launch is spent on the lower triangle
+    if (tile >= tilesN * (tilesN + 1) / 2) return;
+    tm = 0;
+    int rest = tile;
+    while (rest >= tilesN - tm) {
+      rest -= tilesN - tm;
+      ++tm;
+    }
+    tn = tm + rest;
+  } else {
+    if (tile >= ((M + TM - 1) / TM) * tilesN) return;
+    tm = tile / tilesN;
+    tn = tile % tilesN;
+  }
   const int m0 = tm * TM, n0 = tn * TN;
 
   const GLB cpx<Tin>* A = (const GLB cpx<Tin>*)(d.A) + (long long)batch * d.sA;
@@ -253,6 +273,11 @@ __global__ void k_reduce_splits(const GemmDesc* __restrict__ descs, double* cons
 }
 
 int gemm_tiles(int maxM, int maxN, int tile) { return ((maxM + tile - 1) / tile) * ((maxN + tile - 1) / tile); }
+
+int gemm_tiles_herm(int maxN, int tile) {
+  const int t = (maxN + tile - 1) / tile;
+  return t * (t + 1) / 2;
+}
 
 template <typename Tin, typename Tc, typename Tout>
 void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s,

@@ -8,8 +8,12 @@ namespace mpdo {
 // maxSplits x maxTiles output tiles of tile x tile (tile = 64 or 32); an item
 // uses the first ceil(M/tile) ceil(N/tile) tiles of its range, so maxTiles
 // must bound that count for every item (gemm_tiles of the largest M and N).
+// An item with herm set (square, Hermitian C) computes only the tiles on and
+// above the diagonal, ceil(N/tile) (ceil(N/tile) + 1) / 2 of them: a launch
+// of such items needs only gemm_tiles_herm of the largest N.
 // Tin: input precision, Tc: MFMA precision, Tout: output precision.
 int gemm_tiles(int maxM, int maxN, int tile = 64);
+int gemm_tiles_herm(int maxN, int tile = 64);
 template <typename Tin, typename Tc, typename Tout>
 void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s,
                  int tile = 64);

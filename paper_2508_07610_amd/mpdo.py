@@ -400,7 +400,8 @@ def _testing_lib():
     if not getattr(L, "_testing_sig", False):
         pd = ctypes.POINTER(ctypes.c_double)
         i32 = ctypes.c_int32
-        L.mpdo_test_gemm.argtypes = [i32] * 6 + [pd, i32, i32, pd, i32, i32, pd, i32, i32, ctypes.c_double, pd, i32]
+        L.mpdo_test_gemm.argtypes = [i32] * 6 + [pd, i32, i32, pd, i32, i32, pd, i32, i32, ctypes.c_double, pd, i32,
+                                                 i32]
         L.mpdo_test_gemm.restype = ctypes.c_int
         L.mpdo_test_eigh.argtypes = [i32, i32, pd, pd, pd, pd]
         L.mpdo_test_gemm_rate.argtypes = [i32] * 6 + [pd]
@@ -412,15 +413,18 @@ def _testing_lib():
 
 def test_gemm(prec: int, opA: int, opB: int, M: int, N: int, K: int, A: np.ndarray, B: np.ndarray,
               w: Optional[np.ndarray] = None, wdiv: int = 1, splits: int = 1, alpha: float = 1.0,
-              tile: int = 64) -> np.ndarray:
-    """Run the library GEMM kernel once: alpha op(A) op(B), A and B 2-D complex."""
+              tile: int = 64, herm: bool = False) -> np.ndarray:
+    """Run the library GEMM kernel once: alpha op(A) op(B), A and B 2-D complex.
+    herm: C is Hermitian; only its tiles on and above the diagonal are
+    computed (those below are returned as 0)."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     B = np.ascontiguousarray(B, dtype=np.complex128)
     a, b = _cplx(A), _cplx(B)
     ww = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
     out = np.zeros(2 * M * N)
     check(_testing_lib().mpdo_test_gemm(prec, opA, opB, M, N, K, _dptr(a), A.shape[0], A.shape[1], _dptr(b),
-                                        B.shape[0], B.shape[1], _dptr(ww), wdiv, splits, alpha, _dptr(out), tile))
+                                        B.shape[0], B.shape[1], _dptr(ww), wdiv, splits, alpha, _dptr(out), tile,
+                                        int(herm)))
     return out.view(np.complex128).reshape(M, N)
 
 

@@ -79,12 +79,18 @@ def test_test_entry_points_validate_sizes():
                                                         ctypes.c_int32, ctypes.c_int32,
                                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                                         ctypes.c_int32, ctypes.c_double,
-                                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+                                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                                        ctypes.c_int32]
     # A too small for op(A) = N with M = 4 rows
     assert L.mpdo_test_gemm(0, 0, 0, 4, 2, 2, M._dptr(a), 2, 2, M._dptr(a), 2, 2, None, 1, 1, 1.0,
-                            M._dptr(a), 64) == M.EINVAL
+                            M._dptr(a), 64, 0) == M.EINVAL
     assert L.mpdo_test_gemm(0, 0, 0, 2, 2, 2, M._dptr(a), 2, 2, M._dptr(a), 2, 2, None, 1, 1, 1.0,
-                            M._dptr(a), 48) == M.EINVAL
+                            M._dptr(a), 48, 0) == M.EINVAL
+    # a Hermitian C must be square; herm is 0 or 1
+    assert L.mpdo_test_gemm(0, 0, 0, 2, 1, 2, M._dptr(a), 2, 2, M._dptr(a), 2, 2, None, 1, 1, 1.0,
+                            M._dptr(a), 64, 1) == M.EINVAL
+    assert L.mpdo_test_gemm(0, 0, 0, 2, 2, 2, M._dptr(a), 2, 2, M._dptr(a), 2, 2, None, 1, 1, 1.0,
+                            M._dptr(a), 64, 2) == M.EINVAL
 
 
 def test_profile_read_rejects_unknown_class():

@@ -66,6 +66,31 @@ def test_gemm_split_k_and_weights(tile):
     assert err < 1e-13, err
 
 
+@pytest.mark.parametrize("N_,K_,splits", [(1, 3, 1), (48, 70, 1), (64, 33, 2), (100, 257, 3), (130, 40, 1),
+                                           (257, 96, 5), (300, 128, 1)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("tile", [64, 32])
+def test_gemm_hermitian_tiles(N_, K_, splits, prec, tile):
+    """Hermitian C = A^H diag(w) A with only the tiles on and above the
+    diagonal launched (numbered along the upper triangle): every entry of
+    those tiles equals the full product, every tile below the diagonal is
+    left untouched (0)."""
+    require_gpu()
+    rng = np.random.default_rng(N_ * 7 + K_ + splits)
+    A = _rand((K_, N_), rng)
+    w = rng.uniform(0.5, 1.5, size=K_)
+    C = M.test_gemm(prec, 3, 0, N_, N_, K_, A, A, w=w, splits=splits, tile=tile, herm=True)
+    Ar = A.astype(np.complex64).astype(np.complex128) if prec else A
+    ref = Ar.conj().T @ (w[:, None] * Ar)
+    tm = np.arange(N_)[:, None] // tile
+    tn = np.arange(N_)[None, :] // tile
+    upper = tm <= tn
+    tol = (1e-4 if prec == 1 else 1e-12) * float(np.abs(ref).max())
+    err = float(np.abs(np.where(upper, C - ref, 0)).max())
+    assert err < tol, (err, np.argwhere(upper & (np.abs(C - ref) > tol))[:8].tolist())
+    assert not np.any(C[~upper]), "a tile below the diagonal was written"
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 32, 64, 65, 100, 128, 129, 255, 256, 257, 512, 513, 1024])
 def test_eigh_against_numpy(n):
     require_gpu()
