@@ -38,6 +38,38 @@ constexpr int NT = EIG_THREADS;
 constexpr int NW = NT / 64;
 constexpr int UB = 8;  // loads in flight per thread
 
+// Complex multiply-adds written as real FMAs (a complex product followed by
+// a subtraction would round the product first and take half again as many
+// instructions).
+// a - x y - u w
+__device__ inline cpx<double> sub2prod(cpx<double> a, cpx<double> x, cpx<double> y, cpx<double> u,
+                                       cpx<double> w) {
+  double re = fma(-x.re, y.re, a.re);
+  re = fma(x.im, y.im, re);
+  re = fma(-u.re, w.re, re);
+  re = fma(u.im, w.im, re);
+  double im = fma(-x.re, y.im, a.im);
+  im = fma(-x.im, y.re, im);
+  im = fma(-u.re, w.im, im);
+  im = fma(-u.im, w.re, im);
+  return mk(re, im);
+}
+// a - x y
+__device__ inline cpx<double> subprod(cpx<double> a, cpx<double> x, cpx<double> y) {
+  double re = fma(-x.re, y.re, a.re);
+  re = fma(x.im, y.im, re);
+  double im = fma(-x.re, y.im, a.im);
+  im = fma(-x.im, y.re, im);
+  return mk(re, im);
+}
+// (re, im) += conj(x) y
+__device__ inline void dotacc(double& re, double& im, cpx<double> x, cpx<double> y) {
+  re = fma(x.re, y.re, re);
+  re = fma(x.im, y.im, re);
+  im = fma(x.re, y.im, im);
+  im = fma(-x.im, y.re, im);
+}
+
 // Block-wide sum with one barrier: consecutive calls alternate between the
 // two halves of red[2 NW], so a half is rewritten only after the barrier of
 // the call in between.
@@ -105,6 +137,8 @@ template <int NMAX> struct alignas(16) SharedG {
   // (conj(W) follows at offset 8 * 256; the back-transformation reuses the
   // whole array for its block of reflectors, n <= 512 rows of 8)
   alignas(16) cpx<double> pf[NMAX <= 512 ? 2 * 8 * 256 : 1];
+  static constexpr int SOLVE_CAP = 0;  // no LDS room for the inverse-iteration arrays
+  __device__ double* solve() { return nullptr; }
 };
 
 // Pending update (vp, wp; index 0 = row `base`) on rows/cols [c0, n) and,
@@ -133,30 +167,22 @@ __device__ void fused_pass(cpx<double>* __restrict__ A, int n, int c0, int base,
       if (pend) {
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
-          a[u] = a[u] - S.vp[i + u - base] * wpc - S.wp[i + u - base] * vpc;
+          a[u] = sub2prod(a[u], S.vp[i + u - base], wpc, S.wp[i + u - base], vpc);
           A[(long long)(i + u) * n + c] = a[u];
         }
       }
       if (act) {
 #pragma unroll
-        for (int u = 0; u < UB; ++u) {
-          const cpx<double> v = S.v[i + u - c0];
-          ar += a[u].re * v.re + a[u].im * v.im;  // conj(a) v
-          ai += a[u].re * v.im - a[u].im * v.re;
-        }
+        for (int u = 0; u < UB; ++u) dotacc(ar, ai, a[u], S.v[i + u - c0]);  // conj(a) v
       }
     }
     for (; i < i1; ++i) {
       cpx<double> a = A[(long long)i * n + c];
       if (pend) {
-        a = a - S.vp[i - base] * wpc - S.wp[i - base] * vpc;
+        a = sub2prod(a, S.vp[i - base], wpc, S.wp[i - base], vpc);
         A[(long long)i * n + c] = a;
       }
-      if (act) {
-        const cpx<double> v = S.v[i - c0];
-        ar += a.re * v.re + a.im * v.im;
-        ai += a.re * v.im - a.im * v.re;
-      }
+      if (act) dotacc(ar, ai, a, S.v[i - c0]);
     }
     S.pp[q * m + cl] = mk(ar, ai);
   }
@@ -235,10 +261,13 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   double* work = dsc.work;
   // ---- 4. inverse iteration on T, one thread per vector ----
   // T - lambda = P L U with partial pivoting; per step k the factor arrays
-  // hold 1/u_kk, u_k,k+1, u_k,k+2, the multiplier and the swap flag.
+  // hold 1/u_kk, u_k,k+1, u_k,k+2, the multiplier and the swap flag.  The
+  // arrays live in LDS when the workgroup has room for them (the sweeps are
+  // latency-bound), else in the work array.
   {
-    const long long ks = (kz + 63) / 64 * 64;  // interleave stride of the solve arrays
-    double* __restrict__ X = work + 2LL * n * n;
+    const bool lds = SH::SOLVE_CAP > 0 && 7LL * n * kz <= SH::SOLVE_CAP;
+    const long long ks = lds ? kz : (kz + 63) / 64 * 64;  // interleave stride of the solve arrays
+    double* __restrict__ X = lds ? S.solve() : work + 2LL * n * n;
     double* __restrict__ Y = X + (long long)n * ks;
     double* __restrict__ U0 = Y + (long long)n * ks;
     double* __restrict__ U1 = U0 + (long long)n * ks;
@@ -547,29 +576,31 @@ __device__ void back_transform_reg(const EigDesc& dsc, const cpx<double>* __rest
     const int r = r0 + u;
     z[u] = (c < kz && r < n) ? Z[(long long)r * n + c] : mk(0.0, 0.0);
   }
-  auto load_v = [&](int k, cpx<double>* dst) {  // v_k over all 256 rows (zero outside k+1 .. n-1)
-    for (int i = tid; i < 256; i += NT)
-      dst[i] = (i == k + 1) ? mk(1.0, 0.0) : (i > k + 1 && i < n) ? A[(long long)i * n + k] : mk(0.0, 0.0);
+  static_assert(NT >= 256, "one reflector entry per thread");
+  // entry i of v_k over all 256 rows (zero outside k+1 .. n-1); the entries
+  // of reflector k - 1 are read during step k + 1, a step before they are
+  // stored for use
+  auto vent = [&](int k, int i) {
+    return (i == k + 1) ? mk(1.0, 0.0) : (i > k + 1 && i < n) ? A[(long long)i * n + k] : mk(0.0, 0.0);
   };
-  if (n >= 2) load_v(n - 2, vb[(n - 2) % 3]);
+  if (n >= 2 && tid < 256) vb[(n - 2) % 3][tid] = vent(n - 2, tid);
+  cpx<double> vq = (n >= 3 && tid < 256) ? vent(n - 3, tid) : mk(0.0, 0.0);
   __syncthreads();
   for (int k = n - 2; k >= 0; --k) {
     const cpx<double>* v = vb[k % 3];
+    const cpx<double> vq2 = (k >= 2 && tid < 256) ? vent(k - 2, tid) : mk(0.0, 0.0);
     const cpx<double> t = S.tau[k];
     const bool act = !(t.re == 0.0 && t.im == 0.0);
     if (act) {
-      double yr = 0, yi = 0;
+      double yr[4] = {0, 0, 0, 0}, yi[4] = {0, 0, 0, 0};  // four chains for latency
       if (r0 + RB > k + 1) {
 #pragma unroll
-        for (int u = 0; u < RB; ++u) {
-          const cpx<double> vv = v[r0 + u];
-          yr += vv.re * z[u].re + vv.im * z[u].im;  // conj(v) z
-          yi += vv.re * z[u].im - vv.im * z[u].re;
-        }
+        for (int u = 0; u < RB; ++u) dotacc(yr[u & 3], yi[u & 3], v[r0 + u], z[u]);  // conj(v) z
       }
-      pw[k & 1][q * 64 + c] = mk(yr, yi);
+      pw[k & 1][q * 64 + c] = mk((yr[0] + yr[1]) + (yr[2] + yr[3]), (yi[0] + yi[1]) + (yi[2] + yi[3]));
     }
-    if (k >= 1) load_v(k - 1, vb[(k - 1) % 3]);
+    if (k >= 1 && tid < 256) vb[(k - 1) % 3][tid] = vq;
+    vq = vq2;
     __syncthreads();
     if (act && r0 + RB > k + 1) {
       cpx<double> y = mk(0.0, 0.0);
@@ -577,7 +608,7 @@ __device__ void back_transform_reg(const EigDesc& dsc, const cpx<double>* __rest
       for (int qq = 0; qq < NT / 64; ++qq) y = y + pw[k & 1][qq * 64 + c];
       const cpx<double> ty = t * y;
 #pragma unroll
-      for (int u = 0; u < RB; ++u) z[u] = z[u] - v[r0 + u] * ty;
+      for (int u = 0; u < RB; ++u) z[u] = subprod(z[u], v[r0 + u], ty);
     }
   }
   if (c < kz) {
@@ -619,7 +650,7 @@ __device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, i
       for (int i = k + tid; i < n; i += NT) {
         cpx<double> x = cconj(A[(long long)k * n + i]);
         for (int q = 0; q < j; ++q)
-          x = x - vp(i, q) * cconj(wp(k, q)) - wp(i, q) * cconj(vp(k, q));
+          x = sub2prod(x, vp(i, q), cconj(wp(k, q)), wp(i, q), cconj(vp(k, q)));
         xk[i - k] = x;
       }
       __syncthreads();
@@ -668,9 +699,7 @@ __device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, i
         const int q = isw ? d : d - j;
         double yr = 0, yi = 0;
         for (int i = lane; i < m; i += 64) {
-          const cpx<double> a = isw ? wp(c0 + i, q) : vp(c0 + i, q), v = S.v[i];
-          yr += a.re * v.re + a.im * v.im;  // conj(a) v
-          yi += a.re * v.im - a.im * v.re;
+          dotacc(yr, yi, isw ? wp(c0 + i, q) : vp(c0 + i, q), S.v[i]);  // conj(a) v
         }
         for (int off = 32; off > 0; off >>= 1) {
           yr += __shfl_xor(yr, off, 64);
@@ -683,7 +712,7 @@ __device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, i
       for (int i = tid; i < m; i += NT) {
         cpx<double> pv = S.pp[i];
         for (int q = 0; q < j; ++q)
-          pv = pv - vp(c0 + i, q) * y12[q] - wp(c0 + i, q) * y12[TRB + q];
+          pv = sub2prod(pv, vp(c0 + i, q), y12[q], wp(c0 + i, q), y12[TRB + q]);
         S.pp[i] = pv;
         g += S.v[i].re * pv.re + S.v[i].im * pv.im;
       }
@@ -752,7 +781,7 @@ __device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, i
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-              for (int j = 0; j < 4; ++j) x[i][j] = x[i][j] - vr[i] * wc[j] - wr[i] * vc[j];
+              for (int j = 0; j < 4; ++j) x[i][j] = sub2prod(x[i][j], vr[i], wc[j], wr[i], vc[j]);
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -803,7 +832,7 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
         const cpx<double> wk = cconj(S.wp[0]), vk = cconj(S.vp[0]);
         for (int i = k + tid; i < n; i += NT) {
           cpx<double> x = A[(long long)i * n + k];
-          x = x - S.vp[i - k] * wk - S.wp[i - k] * vk;
+          x = sub2prod(x, S.vp[i - k], wk, S.wp[i - k], vk);
           A[(long long)i * n + k] = x;
         }
         __syncthreads();
@@ -908,6 +937,10 @@ struct alignas(16) SharedR {
   int clus[RN + 1];
   double red[2 * (NTR / 64)];
   int flag[4];
+  // the seven inverse-iteration arrays (n x kz each) when n kz <= 1024
+  static constexpr int SOLVE_CAP = 7 * 1024;
+  double sv[SOLVE_CAP];
+  __device__ double* solve() { return sv; }
 };
 
 __device__ inline double wave_allsum(double v) {
@@ -961,14 +994,14 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
   for (int k = 0; k + 1 < n; ++k) {
     const int c0 = k + 1;
     // (a) rank-2 update of step k-1 on [k, n) x [k, n); publish column k
-    // (the update is zero outside rows and columns [k, n): finished rows are
-    // skipped per group of eight, uniformly across the wave, and finished
-    // columns per thread)
-    if (pend && r0 + RR > k && c >= k) {
+    // (the update is zero outside rows and columns [k, n): finished rows and
+    // rows beyond n are skipped per group of eight, uniformly across the
+    // wave, finished columns and columns beyond n per thread)
+    if (pend && r0 + RR > k && r0 < n && c >= k && c < n) {
       const cpx<double> wc = cconj(S.wp[c]), vc = cconj(S.vp[c]);
 #pragma unroll
       for (int u0 = 0; u0 < RR; u0 += 8) {
-        if (r0 + u0 + 8 <= k) continue;
+        if (r0 + u0 + 8 <= k || r0 + u0 >= n) continue;
         cpx<double> vr[8], wr[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -976,7 +1009,7 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
           wr[u] = S.wp[r0 + u0 + u];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u0 + u] = a[u0 + u] - vr[u] * wc - wr[u] * vc;
+        for (int u = 0; u < 8; ++u) a[u0 + u] = sub2prod(a[u0 + u], vr[u], wc, wr[u], vc);
       }
     }
     if (c == k) {
@@ -1028,26 +1061,22 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
     if (act) {
       // (c) partial p[c] = sum_r conj(A[r][c]) v[r] over the owned rows; the
       // owner of column k keeps v_k in its finished entries
-      const bool rows = r0 + RR > c0;
+      const bool rows = r0 + RR > c0 && r0 < n;
       if (c == k) {
 #pragma unroll
         for (int u = 0; u < RR; ++u) a[u] = S.v[0][r0 + u];
       }
       if (c >= c0 && c < n) {
-        double pr = 0, pi = 0;
+        double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};  // four chains for latency
         if (rows) {
 #pragma unroll
           for (int u0 = 0; u0 < RR; u0 += 8) {
-            if (r0 + u0 + 8 <= c0) continue;  // v is zero there
+            if (r0 + u0 + 8 <= c0 || r0 + u0 >= n) continue;  // v is zero there
 #pragma unroll
-            for (int u = u0; u < u0 + 8; ++u) {
-              const cpx<double> v = S.v[0][r0 + u];
-              pr += a[u].re * v.re + a[u].im * v.im;
-              pi += a[u].re * v.im - a[u].im * v.re;
-            }
+            for (int u = u0; u < u0 + 8; ++u) dotacc(pr[u & 3], pi[u & 3], a[u], S.v[0][r0 + u]);
           }
         }
-        S.pp[0][q][c] = mk(pr, pi);
+        S.pp[0][q][c] = mk((pr[0] + pr[1]) + (pr[2] + pr[3]), (pi[0] + pi[1]) + (pi[2] + pi[3]));
       }
       __syncthreads();
       // (d) p, gamma = v^H p, w = tau p - |tau|^2 gamma / 2 v (wave 0)
@@ -1117,32 +1146,32 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
     // reflector k in S.v[k % 3] (zero outside rows k+1 .. n-1), partial sums
     // in S.pp[k & 1]: one barrier per reflector, since a slot is rewritten
     // only after every thread has passed the barrier that follows its last read
+    // The entries of reflector k - 1 are read from global memory during step
+    // k + 1, so the load has a whole step to arrive before they are stored.
     for (int i = tid; i < 3 * RN; i += NTR) S.v[i / RN][i % RN] = mk(0.0, 0.0);
     __syncthreads();
     if (n >= 2 && tid == n - 1) S.v[(n - 2) % 3][tid] = Vg[(long long)(n - 2) * n + tid];
+    cpx<double> vq = mk(0.0, 0.0);  // reflector k - 1, row tid
+    if (n >= 3 && tid >= n - 2 && tid < n) vq = Vg[(long long)(n - 3) * n + tid];
     __syncthreads();
     for (int k = n - 2; k >= 0; --k) {
       const cpx<double>* __restrict__ vk = S.v[k % 3];
-      const bool pre = k >= 1 && tid >= k && tid < n;
-      cpx<double> vn = mk(0.0, 0.0);
-      if (pre) vn = Vg[(long long)(k - 1) * n + tid];  // next reflector, stored below
+      cpx<double> vq2 = mk(0.0, 0.0);  // reflector k - 2, row tid
+      if (k >= 2 && tid >= k - 1 && tid < n) vq2 = Vg[(long long)(k - 2) * n + tid];
       const cpx<double> t = S.tau[k];
       const bool active = !(t.re == 0.0 && t.im == 0.0);
       const int r1 = k + 1;
-      const bool rows = r0 + RR > r1;
+      const bool rows = r0 + RR > r1 && r0 < n;
       if (active && c < kz) {
-        double yr = 0, yi = 0;
+        double yr[4] = {0, 0, 0, 0}, yi[4] = {0, 0, 0, 0};  // four chains for latency
         if (rows) {
 #pragma unroll
-          for (int u = 0; u < RR; ++u) {
-            const cpx<double> v = vk[r0 + u];
-            yr += v.re * z[u].re + v.im * z[u].im;  // conj(v) z
-            yi += v.re * z[u].im - v.im * z[u].re;
-          }
+          for (int u = 0; u < RR; ++u) dotacc(yr[u & 3], yi[u & 3], vk[r0 + u], z[u]);  // conj(v) z
         }
-        S.pp[k & 1][q][c] = mk(yr, yi);
+        S.pp[k & 1][q][c] = mk((yr[0] + yr[1]) + (yr[2] + yr[3]), (yi[0] + yi[1]) + (yi[2] + yi[3]));
       }
-      if (pre) S.v[(k - 1) % 3][tid] = vn;
+      if (k >= 1 && tid >= k && tid < n) S.v[(k - 1) % 3][tid] = vq;
+      vq = vq2;
       __syncthreads();
       if (active && c < kz && rows) {
         cpx<double> y = mk(0.0, 0.0);
@@ -1150,7 +1179,7 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
         for (int qq = 0; qq < RQ; ++qq) y = y + S.pp[k & 1][qq][c];
         const cpx<double> ty = t * y;
 #pragma unroll
-        for (int u = 0; u < RR; ++u) z[u] = z[u] - vk[r0 + u] * ty;
+        for (int u = 0; u < RR; ++u) z[u] = subprod(z[u], vk[r0 + u], ty);
       }
     }
     if (c < kz) {
