@@ -1063,7 +1063,7 @@ __global__ void k_transfer_init(CtxT<T>* ctxs) {
   if (threadIdx.x == 0) c.Ecur[0] = mk<T>((T)1, (T)0);
 }
 
-// BO[l,s',k,r] = sum_s O[s',s] B[l,s,k,r]; descriptors of Y = E^T BO and
+// BO[l,s',k,r] = sum_s O[s',s] B[l,s,k,r] (B itself when O is the identity); descriptors of Y = E^T BO and
 // E' = Y^T conj(B).
 template <typename T>
 __global__ void k_transfer_prep(CtxT<T>* ctxs) {
@@ -1077,7 +1077,10 @@ __global__ void k_transfer_prep(CtxT<T>* ctxs) {
   const cpx<T> o00 = mk<T>((T)O[0], (T)O[1]), o01 = mk<T>((T)O[2], (T)O[3]);
   const cpx<T> o10 = mk<T>((T)O[4], (T)O[5]), o11 = mk<T>((T)O[6], (T)O[7]);
   const long long half = (long long)k * cr;
-  const long long total = (long long)cl * half;
+  // an identity factor leaves B as it is: the product reads B itself
+  const bool ident = O[0] == 1.0 && O[1] == 0.0 && O[2] == 0.0 && O[3] == 0.0 && O[4] == 0.0 && O[5] == 0.0 &&
+                     O[6] == 1.0 && O[7] == 0.0;
+  const long long total = ident ? 0 : (long long)cl * half;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const long long l = e / half, rest = e % half;
@@ -1088,7 +1091,7 @@ __global__ void k_transfer_prep(CtxT<T>* ctxs) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     GemmDesc& d1 = *c.d1;
     clear_desc(d1);
-    d1.A = c.Ecur; d1.B = c.BO; d1.C = c.Y;
+    d1.A = c.Ecur; d1.B = ident ? c.B : c.BO; d1.C = c.Y;
     d1.opA = OP_T;
     d1.M = cl; d1.K = cl; d1.N = 2 * k * cr;
     d1.lda = cl; d1.ldb = 2 * k * cr; d1.ldc = 2 * k * cr;
