@@ -918,14 +918,17 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
 // w (one wave).  The reflectors go to dsc.work for the back-transformation,
 // which keeps the eigenvector block in registers in the same layout.
 // ---------------------------------------------------------------------------
-constexpr int RN = 128;
-constexpr int NTR = 512;      // threads: two waves per SIMD leave 256 VGPRs each
-constexpr int RQ = NTR / RN;  // row blocks
-constexpr int RR = RN / RQ;   // rows per thread
+// Two variants share the code below (RN_: largest n, NTR_: threads, NLO:
+// smaller n are left to the other variant):
+//   <128, 512, 32>: 32 < n <= 128, two waves per SIMD (256 VGPRs each);
+//   <32, 64, 0>: n <= 32, one wave per matrix, so its barriers cost little
+//   and many matrices share a CU.
+constexpr int REG_NMAX = 128, SMALL_NMAX = 32;
 
 // 16-byte alignment lets the compiler use 128-bit LDS accesses with
 // immediate offsets for the complex vectors.
-struct alignas(16) SharedR {
+template <int RN, int NTR, int SCAP> struct alignas(16) SharedR {
+  static constexpr int RQ = NTR / RN;
   alignas(16) cpx<double> tau[RN];
   alignas(16) cpx<double> x[RN];
   alignas(16) cpx<double> v[3][RN];
@@ -937,8 +940,8 @@ struct alignas(16) SharedR {
   int clus[RN + 1];
   double red[2 * (NTR / 64)];
   int flag[4];
-  // the seven inverse-iteration arrays (n x kz each) when n kz <= 1024
-  static constexpr int SOLVE_CAP = 7 * 1024;
+  // the seven inverse-iteration arrays (n x kz each) when 7 n kz <= SCAP
+  static constexpr int SOLVE_CAP = SCAP;
   double sv[SOLVE_CAP];
   __device__ double* solve() { return sv; }
 };
@@ -948,10 +951,15 @@ __device__ inline double wave_allsum(double v) {
   return v;
 }
 
+template <int RN, int NTR, int NLO>
 __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ descs, int* __restrict__ status) {
-  __shared__ SharedR S;
+  constexpr int RQ = NTR / RN;  // row blocks
+  constexpr int RR = RN / RQ;   // rows per thread
+  constexpr int NH = (RN + 63) / 64;  // vector entries per lane of wave 0
+  static_assert(RR % 8 == 0, "rows are updated in groups of eight");
+  __shared__ SharedR<RN, NTR, RN == REG_NMAX ? 7 * 1024 : 7 * 256> S;
   const EigDesc& dsc = descs[blockIdx.x];
-  if (!dsc.active || dsc.n <= 0 || dsc.n > RN) return;
+  if (!dsc.active || dsc.n <= NLO || dsc.n > RN) return;
   const int n = dsc.n, tid = threadIdx.x, lane = tid & 63;
   const int c = tid % RN, q = tid / RN, r0 = q * RR;
   int par = 0;
@@ -1022,10 +1030,12 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
     if (tid < 64) {
       double xn = 0;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < NH; ++h) {
         const int i = lane + 64 * h;
-        const cpx<double> x = S.x[i];
-        xn += (i > c0 && i < n) ? cabs2(x) : 0.0;
+        if (i < RN) {
+          const cpx<double> x = S.x[i];
+          xn += (i > c0 && i < n) ? cabs2(x) : 0.0;
+        }
       }
       xn = wave_allsum(xn);
       const cpx<double> alpha = S.x[c0];
@@ -1043,10 +1053,12 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
         const double rdd = 1.0 / cabs2(den);
         const cpx<double> sc = mk(den.re * rdd, -den.im * rdd);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < NH; ++h) {
           const int i = lane + 64 * h;
-          const cpx<double> v = S.x[i] * sc;
-          S.v[0][i] = (i == c0) ? mk(1.0, 0.0) : ((i > c0 && i < n) ? v : mk(0.0, 0.0));
+          if (i < RN) {
+            const cpx<double> v = S.x[i] * sc;
+            S.v[0][i] = (i == c0) ? mk(1.0, 0.0) : ((i > c0 && i < n) ? v : mk(0.0, 0.0));
+          }
         }
         if (lane == 0) {
           const double rb = 1.0 / beta;
@@ -1082,17 +1094,19 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
       // (d) p, gamma = v^H p, w = tau p - |tau|^2 gamma / 2 v (wave 0)
       if (tid < 64) {
         const cpx<double> tau = S.tau[k];
-        cpx<double> ph[2], vh[2];
+        cpx<double> ph[NH], vh[NH];
         double g = 0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < NH; ++h) {
           const int i = lane + 64 * h;
           const bool in = i >= c0 && i < n;
-          cpx<double> p = mk(0.0, 0.0);
+          cpx<double> p = mk(0.0, 0.0), v = mk(0.0, 0.0);
+          if (i < RN) {
 #pragma unroll
-          for (int qq = 0; qq < RQ; ++qq) p = p + S.pp[0][qq][i];
+            for (int qq = 0; qq < RQ; ++qq) p = p + S.pp[0][qq][i];
+            v = S.v[0][i];
+          }
           p = in ? p : mk(0.0, 0.0);
-          const cpx<double> v = S.v[0][i];
           g += v.re * p.re + v.im * p.im;
           ph[h] = p;
           vh[h] = v;
@@ -1100,10 +1114,12 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
         g = wave_allsum(g);
         const double cc = 0.5 * cabs2(tau) * g;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < NH; ++h) {
           const int i = lane + 64 * h;
-          S.wp[i] = tau * ph[h] - cc * vh[h];
-          S.vp[i] = vh[h];
+          if (i < RN) {
+            S.wp[i] = tau * ph[h] - cc * vh[h];
+            S.vp[i] = vh[h];
+          }
         }
       }
       __syncthreads();
@@ -1197,7 +1213,7 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
 __global__ __launch_bounds__(NT) void k_heev_global(const EigDesc* __restrict__ descs, int* __restrict__ status) {
   __shared__ SharedG<512> S;
   const EigDesc& d = descs[blockIdx.x];
-  if (!d.active || d.n <= RN || d.n > 512) return;
+  if (!d.active || d.n <= REG_NMAX || d.n > 512) return;
   heev_core<true>(d, reinterpret_cast<cpx<double>*>(d.work), S);
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
@@ -1213,13 +1229,16 @@ __global__ __launch_bounds__(NT) void k_heev_big(const EigDesc* __restrict__ des
 
 void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hipStream_t s) {
   if (nitems <= 0) return;
+  // the register variants (n <= 32 and n <= 128) count as one profiled call
   int tok = prof_begin(PC_EIG_REG, s);
-  hipLaunchKernelGGL(k_heev_reg, dim3(nitems), dim3(NTR), 0, s, d_descs, d_status);
-  prof_end_eig(tok, PC_EIG_REG, d_descs, nitems, 1, RN, s);
-  if (maxn > RN) {
+  hipLaunchKernelGGL((k_heev_reg<SMALL_NMAX, 64, 0>), dim3(nitems), dim3(64), 0, s, d_descs, d_status);
+  if (maxn > SMALL_NMAX)
+    hipLaunchKernelGGL((k_heev_reg<REG_NMAX, 512, SMALL_NMAX>), dim3(nitems), dim3(512), 0, s, d_descs, d_status);
+  prof_end_eig(tok, PC_EIG_REG, d_descs, nitems, 1, REG_NMAX, s);
+  if (maxn > REG_NMAX) {
     tok = prof_begin(PC_EIG_GLOBAL, s);
     hipLaunchKernelGGL(k_heev_global, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
-    prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, RN + 1, 512, s);
+    prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, REG_NMAX + 1, 512, s);
   }
   if (maxn > 512) {
     tok = prof_begin(PC_EIG_GLOBAL, s);
