@@ -484,26 +484,67 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
   const int n = (int)items.size();
   int nmax = 0;
   for (auto& it : items) nmax = std::max(nmax, nq_[it.b]);
+  // Each observable only needs the sites between its first and last
+  // non-identity factor: the left environment before the first comes from
+  // the instance's identity (trace) sweep, which keeps every L_s, and the
+  // environment after the last is the right environment R_{last+1} of the
+  // instance, from one right sweep.
+  std::vector<int> fst(n), lst(n), slot(n);  // non-identity range of each item
+  int ninst = 0;
+  for (int it = 0; it < n; ++it) {
+    const int nb = nq_[items[it].b];
+    if (!items[it].ops) {  // the trace item: every site, recorded
+      slot[it] = ninst++;
+      fst[it] = 0;
+      lst[it] = nb - 1;
+      continue;
+    }
+    slot[it] = slot[items[it].trace];
+    fst[it] = nb;
+    lst[it] = -1;
+    for (int s = 0; s < nb; ++s) {
+      const double* o = items[it].ops + 8 * s;
+      const bool id = o[0] == 1.0 && o[1] == 0.0 && o[2] == 0.0 && o[3] == 0.0 && o[4] == 0.0 && o[5] == 0.0 &&
+                      o[6] == 1.0 && o[7] == 0.0;
+      if (!id) {
+        fst[it] = std::min(fst[it], s);
+        lst[it] = s;
+      }
+    }
+  }
   const int cx = cfg_.chi_max;
-  Layout w;
+  Layout w;  // per item
   const size_t oE0 = w.add((size_t)cx * cx * sizeof(cpx<T>));
   const size_t oE1 = w.add((size_t)cx * cx * sizeof(cpx<T>));
   const size_t oBO = w.add(cap_site_ * sizeof(cpx<T>));
   const size_t oY = w.add(cap_site_ * sizeof(cpx<T>));
   const size_t per = w.off;
+  Layout v;  // per instance: L_0 .. L_nmax, R_0 .. R_nmax, W
+  const size_t oL = v.add((size_t)(nmax + 1) * cx * cx * sizeof(cpx<T>));
+  const size_t oR = v.add((size_t)(nmax + 1) * cx * cx * sizeof(cpx<T>));
+  const size_t oW = v.add(cap_site_ * sizeof(cpx<T>));
+  const size_t env = v.off;
+  const int nr = std::max(1, nmax - 1);  // right-sweep steps
   Layout u;
   const size_t uCtx = u.add(sizeof(CtxT<T>) * (size_t)nmax * n);
   const size_t uD1 = u.add(sizeof(GemmDesc) * (size_t)nmax * n);
   const size_t uD2 = u.add(sizeof(GemmDesc) * (size_t)nmax * n);
+  const size_t uCtxR = u.add(sizeof(CtxR<T>) * (size_t)nr * ninst);
+  const size_t uD3 = u.add(sizeof(GemmDesc) * (size_t)nr * ninst);
+  const size_t uD4 = u.add(sizeof(GemmDesc) * (size_t)nr * ninst);
   const size_t uOps = u.add(sizeof(double) * 8 * (size_t)nmax * n);
   const size_t uRes = u.add(sizeof(double) * 2 * n);
   const size_t uIdx = u.add(sizeof(int) * result_index.size());
   char *h = nullptr, *dv = nullptr;
-  if (!reserve(up, u.off, per * n, 0, h, dv)) return;
+  if (!reserve(up, u.off, per * n + env * ninst, 0, h, dv)) return;
   char* wk = reinterpret_cast<char*>(work_.p);
+  char* ebase = wk + per * n;
+  auto Lp = [&](int it, int s) { return at<cpx<T>>(ebase + env * slot[it], oL) + (size_t)s * cx * cx; };
+  auto Rp = [&](int it, int s) { return at<cpx<T>>(ebase + env * slot[it], oR) + (size_t)s * cx * cx; };
   std::memcpy(h + uIdx, result_index.data(), sizeof(int) * result_index.size());
   for (int it = 0; it < n; ++it) {
     const int b = items[it].b, nb = nq_[b];
+    const bool rec = !items[it].ops, any = fst[it] <= lst[it];
     double* ops = at<double>(h, uOps) + 8 * (size_t)nmax * it;
     for (int s = 0; s < nb; ++s) {
       if (items[it].ops) {
@@ -514,15 +555,25 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
       }
     }
     char* base = wk + per * it;
+    cpx<T>* E[2] = {at<cpx<T>>(base, oE0), at<cpx<T>>(base, oE1)};
+    cpx<T>* efin = rec || !any ? Lp(it, nb) : E[(lst[it] - fst[it]) & 1];
+    const bool rfin = !rec && any && lst[it] + 1 < nb;
     for (int s = 0; s < nmax; ++s) {
       CtxT<T>& c = at<CtxT<T>>(h, uCtx)[(size_t)s * n + it];
       c.ops = reinterpret_cast<const double*>(dv + uOps) + 8 * (size_t)nmax * it;
       c.site = s;
-      c.active = s < nb;
+      c.active = s < nb && s >= fst[it] && s <= lst[it];
       c.trace_idx = raw ? -1 : items[it].trace;
-      c.Ecur = at<cpx<T>>(base, (s % 2) ? oE1 : oE0);
-      c.Enext = at<cpx<T>>(base, (s % 2) ? oE0 : oE1);
-      c.Efinal = at<cpx<T>>(base, (nb % 2) ? oE1 : oE0);
+      if (rec) {
+        c.Ecur = Lp(it, s);
+        c.Enext = Lp(it, s + 1);
+      } else {
+        c.Ecur = s == fst[it] ? Lp(it, s) : (s > fst[it] ? E[(s - 1 - fst[it]) & 1] : E[0]);
+        c.Enext = E[(s - fst[it]) & 1];
+      }
+      c.Efinal = efin;
+      c.Rfin = rfin ? Rp(it, lst[it] + 1) : nullptr;
+      c.chif = rfin ? chi_ptr(b, lst[it] + 1) : nullptr;
       c.BO = at<cpx<T>>(base, oBO);
       c.Y = at<cpx<T>>(base, oY);
       c.d1 = reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n + it;
@@ -537,10 +588,37 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
         c.chil = c.chir = c.kap = nullptr;
       }
     }
+    if (!rec) continue;
+    // right sweep of this instance: step t builds R_s, s = nb - 1 - t (s >= 1)
+    for (int t = 0; t < nr; ++t) {
+      CtxR<T>& r = at<CtxR<T>>(h, uCtxR)[(size_t)t * ninst + slot[it]];
+      const int s = nb - 1 - t;
+      r.d3 = reinterpret_cast<GemmDesc*>(dv + uD3) + (size_t)t * ninst + slot[it];
+      r.d4 = reinterpret_cast<GemmDesc*>(dv + uD4) + (size_t)t * ninst + slot[it];
+      r.active = s >= 1;
+      r.last = t == 0;
+      if (s >= 1) {
+        r.B = site(b, s, par_[soff_[b] + s]);
+        r.chil = chi_ptr(b, s);
+        r.chir = chi_ptr(b, s + 1);
+        r.kap = kap_ptr(b, s);
+        r.Rn = Rp(it, s + 1);
+        r.Rs = Rp(it, s);
+        r.W = at<cpx<T>>(ebase + env * slot[it], oW);
+      }
+    }
   }
   commit(up, h, dv, u.off);
   CtxT<T>* dctx = reinterpret_cast<CtxT<T>*>(dv + uCtx);
+  CtxR<T>* rctx = reinterpret_cast<CtxR<T>*>(dv + uCtxR);
   launch_transfer_init<T>(dctx, n, st_);
+  for (int t = 0; t < nmax - 1; ++t) {
+    launch_rtransfer_prep<T>(rctx + (size_t)t * ninst, ninst, st_);
+    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD3) + (size_t)t * ninst, ninst, 1, 1,
+                         gemm_tiles((int)(2 * cfg_.kap_max * cx), cx), st_);
+    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD4) + (size_t)t * ninst, ninst, 1, 1, gemm_tiles(cx, cx),
+                         st_);
+  }
   for (int s = 0; s < nmax; ++s) {
     launch_transfer_prep<T>(dctx + (size_t)s * n, n, (int)cap_site_ / 2, st_);
     launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n, n, 1, 1,

@@ -210,10 +210,27 @@ template <typename T> struct CtxT {
   cpx<T>* Enext;
   cpx<T>* BO;
   cpx<T>* Y;
-  cpx<T>* Efinal;         // where the 1 x 1 result ends up
+  cpx<T>* Efinal;         // the item's last left environment
+  const cpx<T>* Rfin;     // right environment Efinal is contracted with (null: Efinal is 1 x 1)
+  const int* chif;        // bond dimension of Efinal and Rfin
   GemmDesc* d1;
   GemmDesc* d2;
   int site, active, trace_idx, pad;
+};
+
+// Right environment R_s[l, l'] = sum B_s[l, x] W[l', x] with
+// W[(l' s k), r] = sum_r' conj(B_s[(l' s k), r']) R_{s+1}[r, r'] (R_n = [1]).
+template <typename T> struct CtxR {
+  const cpx<T>* B;
+  const int* chil;
+  const int* chir;
+  const int* kap;
+  cpx<T>* Rn;  // R_{s+1}
+  cpx<T>* Rs;  // R_s
+  cpx<T>* W;
+  GemmDesc* d3;
+  GemmDesc* d4;
+  int active, last;  // last: s is the last site (R_{s+1} = [1] is written here)
 };
 
 struct TruncParams {
@@ -250,6 +267,7 @@ template <typename T> void launch_sw_normalize(CtxS<T>* d_ctx, int n, hipStream_
 template <typename T> void launch_transfer_prep(CtxT<T>* d_ctx, int n, int maxElems, hipStream_t s);
 template <typename T> void launch_transfer_init(CtxT<T>* d_ctx, int n, hipStream_t s);
 template <typename T> void launch_transfer_finish(CtxT<T>* d_ctx, int n, double* out, hipStream_t s);
+template <typename T> void launch_rtransfer_prep(CtxR<T>* d_ctx, int n, hipStream_t s);
 
 // chi -> Lambda (Eqs. (13)-(14)) and Kraus extraction (Eq. (16)).
 void launch_choi(const double* chi, int q, double* lam, hipStream_t s);

@@ -1104,18 +1104,73 @@ __global__ void k_transfer_prep(CtxT<T>* ctxs) {
   }
 }
 
-// out[item] = E_item / E_trace (complex); the trace item of each instance is
-// the identity string.
+// Descriptors of one right-environment step (one thread per instance).
 template <typename T>
-__global__ void k_transfer_finish(CtxT<T>* ctxs, double* out) {
+__global__ void k_rtransfer_prep(CtxR<T>* ctxs, int n) {
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= n) return;
+  CtxR<T>& c = ctxs[it];
+  if (!c.active) {
+    c.d3->active = 0;
+    c.d4->active = 0;
+    return;
+  }
+  if (c.last) c.Rn[0] = mk<T>((T)1, (T)0);
+  const int cl = *c.chil, cr = *c.chir, k = *c.kap;
+  GemmDesc& d3 = *c.d3;  // W = conj(B) R_{s+1}^T, (cl 2k) x cr
+  clear_desc(d3);
+  d3.A = c.B; d3.B = c.Rn; d3.C = c.W;
+  d3.opA = OP_C; d3.opB = OP_T;
+  d3.M = cl * 2 * k; d3.K = cr; d3.N = cr;
+  d3.lda = cr; d3.ldb = cr; d3.ldc = cr;
+  GemmDesc& d4 = *c.d4;  // R_s = B W^T over (s k r), cl x cl
+  clear_desc(d4);
+  d4.A = c.B; d4.B = c.W; d4.C = c.Rs;
+  d4.opA = OP_N; d4.opB = OP_T;
+  d4.M = cl; d4.K = 2 * k * cr; d4.N = cl;
+  d4.lda = 2 * k * cr; d4.ldb = 2 * k * cr; d4.ldc = cl;
+}
+
+// out[item] = <E_item, R_item> / E_trace (complex): the left environment
+// after the item's last non-identity site contracted with the right
+// environment of the same bond (E itself when that bond is the last); the
+// trace item of each instance is the identity string.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transfer_finish(CtxT<T>* ctxs, double* out) {
+  __shared__ double sre[256], sim[256];
   const int it = blockIdx.x;
   const CtxT<T>& c = ctxs[it];
-  const cpx<T> v = c.Efinal[0];
-  double ta = 1.0;  // trace_idx < 0: raw value
-  if (c.trace_idx >= 0) ta = (double)ctxs[c.trace_idx].Efinal[0].re;
-  const double a = (double)v.re, b = (double)v.im;
-  out[2 * it] = a / ta;
-  out[2 * it + 1] = b / ta;
+  double a, b;
+  if (!c.Rfin) {
+    a = (double)c.Efinal[0].re;
+    b = (double)c.Efinal[0].im;
+  } else {
+    const int ch = *c.chif;
+    double pr = 0, pi = 0;
+    for (int e = threadIdx.x; e < ch * ch; e += blockDim.x) {
+      const cpx<T> x = c.Efinal[e], y = c.Rfin[e];
+      pr += (double)x.re * (double)y.re - (double)x.im * (double)y.im;
+      pi += (double)x.re * (double)y.im + (double)x.im * (double)y.re;
+    }
+    sre[threadIdx.x] = pr;
+    sim[threadIdx.x] = pi;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        sre[threadIdx.x] += sre[threadIdx.x + h];
+        sim[threadIdx.x] += sim[threadIdx.x + h];
+      }
+      __syncthreads();
+    }
+    a = sre[0];
+    b = sim[0];
+  }
+  if (threadIdx.x == 0) {
+    double ta = 1.0;  // trace_idx < 0: raw value
+    if (c.trace_idx >= 0) ta = (double)ctxs[c.trace_idx].Efinal[0].re;
+    out[2 * it] = a / ta;
+    out[2 * it + 1] = b / ta;
+  }
 }
 
 // ============================================================================
@@ -1297,7 +1352,10 @@ template <typename T> void launch_transfer_prep(CtxT<T>* d, int n, int maxElems,
   hipLaunchKernelGGL(k_transfer_prep<T>, dim3(bx, n), dim3(256), 0, s, d);
 }
 template <typename T> void launch_transfer_finish(CtxT<T>* d, int n, double* out, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_transfer_finish<T>, dim3(n), dim3(1), 0, s, d, out);
+  if (n > 0) hipLaunchKernelGGL(k_transfer_finish<T>, dim3(n), dim3(256), 0, s, d, out);
+}
+template <typename T> void launch_rtransfer_prep(CtxR<T>* d, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_rtransfer_prep<T>, dim3((n + 63) / 64), dim3(64), 0, s, d, n);
 }
 void launch_choi(const double* chi, int q, double* lam, hipStream_t s) {
   hipLaunchKernelGGL(k_choi, dim3(16), dim3(256), 0, s, chi, q, lam);
@@ -1334,6 +1392,7 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_transfer_init<T>(CtxT<T>*, int, hipStream_t);                          \
   template void launch_transfer_prep<T>(CtxT<T>*, int, int, hipStream_t);                     \
   template void launch_transfer_finish<T>(CtxT<T>*, int, double*, hipStream_t);          \
+  template void launch_rtransfer_prep<T>(CtxR<T>*, int, hipStream_t);                      \
   template void launch_copy_site<T>(const cpx<T>*, cpx<T>*, long long, hipStream_t);
 INST(double)
 INST(float)
