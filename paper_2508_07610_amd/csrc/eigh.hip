@@ -918,17 +918,19 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
 // w (one wave).  The reflectors go to dsc.work for the back-transformation,
 // which keeps the eigenvector block in registers in the same layout.
 // ---------------------------------------------------------------------------
-// Two variants share the code below (RN_: largest n, NTR_: threads, NLO:
-// smaller n are left to the other variant):
-//   <128, 512, 32>: 32 < n <= 128, two waves per SIMD (256 VGPRs each);
-//   <32, 64, 0>: n <= 32, one wave per matrix, so its barriers cost little
+// Two variants share the code below (RN: largest n, NTR: threads, NLO:
+// smaller n are left to the other variant, CPT: columns per thread):
+//   <128, 512, 32, 2>: 32 < n <= 128, two waves per SIMD (256 VGPRs each);
+//   each thread holds 16 rows of two columns, so a row value read from LDS
+//   serves both (the rank-2 updates are bound by these broadcast reads);
+//   <32, 64, 0, 1>: n <= 32, one wave per matrix, so its barriers cost little
 //   and many matrices share a CU.
 constexpr int REG_NMAX = 128, SMALL_NMAX = 32;
 
 // 16-byte alignment lets the compiler use 128-bit LDS accesses with
 // immediate offsets for the complex vectors.
-template <int RN, int NTR, int SCAP> struct alignas(16) SharedR {
-  static constexpr int RQ = NTR / RN;
+template <int RN, int NTR, int CPT, int SCAP> struct alignas(16) SharedR {
+  static constexpr int RQ = NTR / (RN / CPT);
   alignas(16) cpx<double> tau[RN];
   alignas(16) cpx<double> x[RN];
   alignas(16) cpx<double> v[3][RN];
@@ -951,39 +953,42 @@ __device__ inline double wave_allsum(double v) {
   return v;
 }
 
-template <int RN, int NTR, int NLO>
+template <int RN, int NTR, int NLO, int CPT>
 __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ descs, int* __restrict__ status) {
-  constexpr int RQ = NTR / RN;  // row blocks
+  constexpr int CW = RN / CPT;  // thread c holds columns c + CW j, j < CPT
+  constexpr int RQ = NTR / CW;  // row blocks
   constexpr int RR = RN / RQ;   // rows per thread
   constexpr int NH = (RN + 63) / 64;  // vector entries per lane of wave 0
   static_assert(RR % 8 == 0, "rows are updated in groups of eight");
-  __shared__ SharedR<RN, NTR, RN == REG_NMAX ? 7 * 1024 : 7 * 256> S;
+  __shared__ SharedR<RN, NTR, CPT, RN == REG_NMAX ? 7 * 1024 : 7 * 256> S;
   const EigDesc& dsc = descs[blockIdx.x];
   if (!dsc.active || dsc.n <= NLO || dsc.n > RN) return;
   const int n = dsc.n, tid = threadIdx.x, lane = tid & 63;
-  const int c = tid % RN, q = tid / RN, r0 = q * RR;
+  const int c = tid % CW, q = tid / CW, r0 = q * RR;
   int par = 0;
   cpx<double>* __restrict__ Vg = reinterpret_cast<cpx<double>*>(dsc.work);  // row k: v_k, absolute index
   // ---- load (symmetrised) ----
-  cpx<double> a[RR];
+  cpx<double> a[CPT][RR];
   {
     const cpx<double>* __restrict__ Ain = reinterpret_cast<const cpx<double>*>(dsc.a);
     double trp = 0;
 #pragma unroll
-    for (int u = 0; u < RR; ++u) {
-      const int r = r0 + u;
-      a[u] = mk(0.0, 0.0);
-      if (r < n && c < n) {
-        if (dsc.upper) {  // only the upper triangle is valid
-          const cpx<double> x = r <= c ? Ain[(long long)r * dsc.lda + c] : Ain[(long long)c * dsc.lda + r];
-          a[u] = r < c ? x : r > c ? cconj(x) : mk(x.re, 0.0);
-        } else {
-          const cpx<double> x = Ain[(long long)r * dsc.lda + c], y = Ain[(long long)c * dsc.lda + r];
-          a[u] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+    for (int j = 0; j < CPT; ++j)
+#pragma unroll
+      for (int u = 0; u < RR; ++u) {
+        const int r = r0 + u, cj = c + CW * j;
+        a[j][u] = mk(0.0, 0.0);
+        if (r < n && cj < n) {
+          if (dsc.upper) {  // only the upper triangle is valid
+            const cpx<double> x = r <= cj ? Ain[(long long)r * dsc.lda + cj] : Ain[(long long)cj * dsc.lda + r];
+            a[j][u] = r < cj ? x : r > cj ? cconj(x) : mk(x.re, 0.0);
+          } else {
+            const cpx<double> x = Ain[(long long)r * dsc.lda + cj], y = Ain[(long long)cj * dsc.lda + r];
+            a[j][u] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+          }
+          if (r == cj) trp += a[j][u].re;
         }
-        if (r == c) trp += a[u].re;
       }
-    }
     const double tr = block_sum<NTR>(trp, S.red, par);
     if (tid == 0) S.ev[RN] = tr;  // parked until the tail
   }
@@ -1005,8 +1010,19 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
     // (the update is zero outside rows and columns [k, n): finished rows and
     // rows beyond n are skipped per group of eight, uniformly across the
     // wave, finished columns and columns beyond n per thread)
-    if (pend && r0 + RR > k && r0 < n && c >= k && c < n) {
-      const cpx<double> wc = cconj(S.wp[c]), vc = cconj(S.vp[c]);
+    bool on[CPT], any = false;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      on[j] = c + CW * j >= k && c + CW * j < n;
+      any = any || on[j];
+    }
+    if (pend && r0 + RR > k && r0 < n && any) {
+      cpx<double> wc[CPT], vc[CPT];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        wc[j] = cconj(S.wp[c + CW * j]);
+        vc[j] = cconj(S.vp[c + CW * j]);
+      }
 #pragma unroll
       for (int u0 = 0; u0 < RR; u0 += 8) {
         if (r0 + u0 + 8 <= k || r0 + u0 >= n) continue;
@@ -1017,13 +1033,19 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
           wr[u] = S.wp[r0 + u0 + u];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u0 + u] = sub2prod(a[u0 + u], vr[u], wc, wr[u], vc);
+        for (int j = 0; j < CPT; ++j)
+          if (on[j]) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[j][u0 + u] = sub2prod(a[j][u0 + u], vr[u], wc[j], wr[u], vc[j]);
+          }
       }
     }
-    if (c == k) {
 #pragma unroll
-      for (int u = 0; u < RR; ++u) S.x[r0 + u] = a[u];
-    }
+    for (int j = 0; j < CPT; ++j)
+      if (c + CW * j == k) {
+#pragma unroll
+        for (int u = 0; u < RR; ++u) S.x[r0 + u] = a[j][u];
+      }
     __syncthreads();
     // (b) reflector with H^H x = beta e_1, v[c0] = 1 (wave 0, every lane
     // computes the same scalars)
@@ -1074,21 +1096,49 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
       // (c) partial p[c] = sum_r conj(A[r][c]) v[r] over the owned rows; the
       // owner of column k keeps v_k in its finished entries
       const bool rows = r0 + RR > c0 && r0 < n;
-      if (c == k) {
 #pragma unroll
-        for (int u = 0; u < RR; ++u) a[u] = S.v[0][r0 + u];
+      for (int j = 0; j < CPT; ++j)
+        if (c + CW * j == k) {
+#pragma unroll
+          for (int u = 0; u < RR; ++u) a[j][u] = S.v[0][r0 + u];
+        }
+      bool in[CPT], anyin = false;
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        in[j] = c + CW * j >= c0 && c + CW * j < n;
+        anyin = anyin || in[j];
       }
-      if (c >= c0 && c < n) {
-        double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};  // four chains for latency
+      if (anyin) {
+        constexpr int NC = CPT == 1 ? 4 : 2;  // independent chains per column
+        double pr[CPT][NC], pi[CPT][NC];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+#pragma unroll
+          for (int h = 0; h < NC; ++h) pr[j][h] = pi[j][h] = 0.0;
         if (rows) {
 #pragma unroll
           for (int u0 = 0; u0 < RR; u0 += 8) {
             if (r0 + u0 + 8 <= c0 || r0 + u0 >= n) continue;  // v is zero there
+            cpx<double> vv[8];
 #pragma unroll
-            for (int u = u0; u < u0 + 8; ++u) dotacc(pr[u & 3], pi[u & 3], a[u], S.v[0][r0 + u]);
+            for (int u = 0; u < 8; ++u) vv[u] = S.v[0][r0 + u0 + u];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+#pragma unroll
+              for (int u = 0; u < 8; ++u) dotacc(pr[j][u % NC], pi[j][u % NC], a[j][u0 + u], vv[u]);
           }
         }
-        S.pp[0][q][c] = mk((pr[0] + pr[1]) + (pr[2] + pr[3]), (pi[0] + pi[1]) + (pi[2] + pi[3]));
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+          if (in[j]) {
+            double sr = 0, si = 0;
+#pragma unroll
+            for (int h = 0; h < NC; ++h) {
+              sr += pr[j][h];
+              si += pi[j][h];
+            }
+            S.pp[0][q][c + CW * j] = mk(sr, si);
+          }
       }
       __syncthreads();
       // (d) p, gamma = v^H p, w = tau p - |tau|^2 gamma / 2 v (wave 0)
@@ -1126,23 +1176,29 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
     }
     pend = act;
   }
-  if (c == n - 1) {
 #pragma unroll
-    for (int u = 0; u < RR; ++u) {
-      if (r0 + u == n - 1) {
-        cpx<double> x = a[u];
-        if (pend) x = x - S.vp[n - 1] * cconj(S.wp[n - 1]) - S.wp[n - 1] * cconj(S.vp[n - 1]);
-        S.d[n - 1] = x.re;
+  for (int j = 0; j < CPT; ++j)
+    if (c + CW * j == n - 1) {
+#pragma unroll
+      for (int u = 0; u < RR; ++u) {
+        if (r0 + u == n - 1) {
+          cpx<double> x = a[j][u];
+          if (pend) x = x - S.vp[n - 1] * cconj(S.wp[n - 1]) - S.wp[n - 1] * cconj(S.vp[n - 1]);
+          S.d[n - 1] = x.re;
+        }
       }
     }
-  }
-  // reflectors to global memory for the back-transformation (column c of
-  // the register block holds v_c below the diagonal)
-  if (c + 1 < n) {
+  // reflectors to global memory for the back-transformation (column cj of
+  // the register block holds v_cj below the diagonal)
 #pragma unroll
-    for (int u = 0; u < RR; ++u) {
-      const int r = r0 + u;
-      if (r > c && r < n) Vg[(long long)c * n + r] = a[u];
+  for (int j = 0; j < CPT; ++j) {
+    const int cj = c + CW * j;
+    if (cj + 1 < n) {
+#pragma unroll
+      for (int u = 0; u < RR; ++u) {
+        const int r = r0 + u;
+        if (r > cj && r < n) Vg[(long long)cj * n + r] = a[j][u];
+      }
     }
   }
   __syncthreads();
@@ -1153,12 +1209,14 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
   // ---- back-transformation z <- H_0 ... H_{n-2} z, z in registers ----
   if (kz > 0) {
     cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
-    cpx<double> z[RR];
+    cpx<double> z[CPT][RR];  // vectors c + CW j
 #pragma unroll
-    for (int u = 0; u < RR; ++u) {
-      const int r = r0 + u;
-      z[u] = (c < kz && r < n) ? Z[(long long)r * n + c] : mk(0.0, 0.0);
-    }
+    for (int j = 0; j < CPT; ++j)
+#pragma unroll
+      for (int u = 0; u < RR; ++u) {
+        const int r = r0 + u, cj = c + CW * j;
+        z[j][u] = (cj < kz && r < n) ? Z[(long long)r * n + cj] : mk(0.0, 0.0);
+      }
     // reflector k in S.v[k % 3] (zero outside rows k+1 .. n-1), partial sums
     // in S.pp[k & 1]: one barrier per reflector, since a slot is rewritten
     // only after every thread has passed the barrier that follows its last read
@@ -1179,32 +1237,63 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
       const int r1 = k + 1;
       const bool rows = r0 + RR > r1 && r0 < n;
       if (active && c < kz) {
-        double yr[4] = {0, 0, 0, 0}, yi[4] = {0, 0, 0, 0};  // four chains for latency
+        constexpr int NC = CPT == 1 ? 4 : 2;  // independent chains per vector
+        double yr[CPT][NC], yi[CPT][NC];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+#pragma unroll
+          for (int h = 0; h < NC; ++h) yr[j][h] = yi[j][h] = 0.0;
         if (rows) {
 #pragma unroll
-          for (int u = 0; u < RR; ++u) dotacc(yr[u & 3], yi[u & 3], vk[r0 + u], z[u]);  // conj(v) z
+          for (int u = 0; u < RR; ++u) {
+            const cpx<double> vv = vk[r0 + u];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) dotacc(yr[j][u % NC], yi[j][u % NC], vv, z[j][u]);  // conj(v) z
+          }
         }
-        S.pp[k & 1][q][c] = mk((yr[0] + yr[1]) + (yr[2] + yr[3]), (yi[0] + yi[1]) + (yi[2] + yi[3]));
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+          if (c + CW * j < kz) {
+            double sr = 0, si = 0;
+#pragma unroll
+            for (int h = 0; h < NC; ++h) {
+              sr += yr[j][h];
+              si += yi[j][h];
+            }
+            S.pp[k & 1][q][c + CW * j] = mk(sr, si);
+          }
       }
       if (k >= 1 && tid >= k && tid < n) S.v[(k - 1) % 3][tid] = vq;
       vq = vq2;
       __syncthreads();
       if (active && c < kz && rows) {
-        cpx<double> y = mk(0.0, 0.0);
+        cpx<double> ty[CPT];
 #pragma unroll
-        for (int qq = 0; qq < RQ; ++qq) y = y + S.pp[k & 1][qq][c];
-        const cpx<double> ty = t * y;
+        for (int j = 0; j < CPT; ++j) {
+          cpx<double> y = mk(0.0, 0.0);
+          if (c + CW * j < kz) {
 #pragma unroll
-        for (int u = 0; u < RR; ++u) z[u] = subprod(z[u], vk[r0 + u], ty);
+            for (int qq = 0; qq < RQ; ++qq) y = y + S.pp[k & 1][qq][c + CW * j];
+          }
+          ty[j] = t * y;
+        }
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+          const cpx<double> vv = vk[r0 + u];
+#pragma unroll
+          for (int j = 0; j < CPT; ++j) z[j][u] = subprod(z[j][u], vv, ty[j]);
+        }
       }
     }
-    if (c < kz) {
 #pragma unroll
-      for (int u = 0; u < RR; ++u) {
-        const int r = r0 + u;
-        if (r < n) Z[(long long)r * n + c] = z[u];
+    for (int j = 0; j < CPT; ++j)
+      if (c + CW * j < kz) {
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+          const int r = r0 + u;
+          if (r < n) Z[(long long)r * n + c + CW * j] = z[j][u];
+        }
       }
-    }
   }
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
@@ -1231,9 +1320,9 @@ void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hi
   if (nitems <= 0) return;
   // the register variants (n <= 32 and n <= 128) count as one profiled call
   int tok = prof_begin(PC_EIG_REG, s);
-  hipLaunchKernelGGL((k_heev_reg<SMALL_NMAX, 64, 0>), dim3(nitems), dim3(64), 0, s, d_descs, d_status);
+  hipLaunchKernelGGL((k_heev_reg<SMALL_NMAX, 64, 0, 1>), dim3(nitems), dim3(64), 0, s, d_descs, d_status);
   if (maxn > SMALL_NMAX)
-    hipLaunchKernelGGL((k_heev_reg<REG_NMAX, 512, SMALL_NMAX>), dim3(nitems), dim3(512), 0, s, d_descs, d_status);
+    hipLaunchKernelGGL((k_heev_reg<REG_NMAX, 512, SMALL_NMAX, 2>), dim3(nitems), dim3(512), 0, s, d_descs, d_status);
   prof_end_eig(tok, PC_EIG_REG, d_descs, nitems, 1, REG_NMAX, s);
   if (maxn > REG_NMAX) {
     tok = prof_begin(PC_EIG_GLOBAL, s);
