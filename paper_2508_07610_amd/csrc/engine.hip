@@ -616,14 +616,16 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
     launch_rtransfer_prep<T>(rctx + (size_t)t * ninst, ninst, st_);
     launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD3) + (size_t)t * ninst, ninst, 1, 1,
                          gemm_tiles((int)(2 * cfg_.kap_max * cx), cx), st_);
-    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD4) + (size_t)t * ninst, ninst, 1, 1, gemm_tiles(cx, cx),
-                         st_);
+    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD4) + (size_t)t * ninst, ninst, 1, 1,
+                         gemm_tiles(cx, cx, 32), st_, 32);
   }
   for (int s = 0; s < nmax; ++s) {
     launch_transfer_prep<T>(dctx + (size_t)s * n, n, (int)cap_site_ / 2, st_);
     launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n, n, 1, 1,
                          gemm_tiles(cx, (int)(2 * cfg_.kap_max * cx)), st_);
-    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD2) + (size_t)s * n, n, 1, 1, gemm_tiles(cx, cx), st_);
+    // one cx x cx output over a long K per item: 32 x 32 tiles fill the CUs
+    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD2) + (size_t)s * n, n, 1, 1, gemm_tiles(cx, cx, 32), st_,
+                         32);
   }
   double* res = reinterpret_cast<double*>(dv + uRes);
   launch_transfer_finish<T>(dctx, n, res, st_);

@@ -318,7 +318,7 @@ __global__ __launch_bounds__(GT) void k_q2_gamma(Ctx2<T>* ctxs) {
   Ctx2<T>& c = ctxs[blockIdx.x];
   const int m = c.m, k1 = *c.kap1;
   if (m <= 1) {
-    if (threadIdx.x == 0) c.dEigG->active = 0;
+    if (threadIdx.x == 0 && blockIdx.y == 0) c.dEigG->active = 0;
     return;
   }
   const int n = k1 * m;
@@ -333,9 +333,11 @@ __global__ __launch_bounds__(GT) void k_q2_gamma(Ctx2<T>* ctxs) {
   }
   __syncthreads();
   // Gamma[(kk j),(kk' j')] = sum_{t,t'} Omega_{jj'}[t,t'] H[h(t,kk)][h(t',kk')],
-  // h(t, kk) = ((t1 k1 + kk) 2 + t2) with t = 2 t1 + t2
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+  // h(t, kk) = ((t1 k1 + kk) 2 + t2) with t = 2 t1 + t2; the upper triangle
+  // only (the eigensolver reads no more), spread over gridDim.y blocks
+  for (int e = threadIdx.x + blockIdx.y * blockDim.x; e < n * n; e += blockDim.x * gridDim.y) {
     const int a = e / n, b = e % n;
+    if (b < a) continue;
     const int kk = a / m, j = a % m, kk2 = b / m, j2 = b % m;
     cpx<double> acc = mk(0.0, 0.0);
     for (int t = 0; t < 4; ++t) {
@@ -354,9 +356,10 @@ __global__ __launch_bounds__(GT) void k_q2_gamma(Ctx2<T>* ctxs) {
     }
     st(c.Gam, e, acc);
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
     EigDesc& d = *c.dEigG;
     d.a = c.Gam; d.lda = n; d.n = n; d.evals = c.evG; d.evecs = c.vecG; d.trace = c.evG + n; d.active = 1;
+    d.upper = 1;
   }
 }
 
@@ -1296,7 +1299,7 @@ template <typename T> void launch_q2_select_e(Ctx2<T>* d, int n, int splitsH, Tr
   if (n > 0) hipLaunchKernelGGL(k_q2_select_e<T>, dim3(n), dim3(GT), 0, s, d, splitsH, tp);
 }
 template <typename T> void launch_q2_gamma(Ctx2<T>* d, int n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q2_gamma<T>, dim3(n), dim3(GT), 0, s, d);
+  if (n > 0) hipLaunchKernelGGL(k_q2_gamma<T>, dim3(n, 4), dim3(GT), 0, s, d);
 }
 template <typename T> void launch_q2_select_g(Ctx2<T>* d, int n, int splitsC, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_select_g<T>, dim3(n), dim3(GT), 0, s, d, splitsC, tp);
