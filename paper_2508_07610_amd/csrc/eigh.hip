@@ -920,9 +920,10 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
 // ---------------------------------------------------------------------------
 // Two variants share the code below (RN: largest n, NTR: threads, NLO:
 // smaller n are left to the other variant, CPT: columns per thread):
-//   <128, 512, 32, 2>: 32 < n <= 128, two waves per SIMD (256 VGPRs each);
-//   each thread holds 16 rows of two columns, so a row value read from LDS
-//   serves both (the rank-2 updates are bound by these broadcast reads);
+//   <128, 512, 32, 4>: 32 < n <= 128, two waves per SIMD (256 VGPRs each);
+//   each thread holds 8 rows of four columns, so a row value read from LDS
+//   serves four columns (the rank-2 updates are bound by these broadcast
+//   reads: 1.79 -> 1.70 ms for 512 matrices of n = 128 against two columns);
 //   <32, 64, 0, 1>: n <= 32, one wave per matrix, so its barriers cost little
 //   and many matrices share a CU.
 constexpr int REG_NMAX = 128, SMALL_NMAX = 32;
@@ -1207,14 +1208,19 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
   __syncthreads();
   const int kz = eig_tail<NTR>(dsc, n, tr, S, par);
   // ---- back-transformation z <- H_0 ... H_{n-2} z, z in registers ----
+  // (its own layout: two vectors per thread at most; with more, each thread
+  // would sum more partial products than the shared reads save)
+  constexpr int CPTB = CPT < 2 ? CPT : 2, CWB = RN / CPTB, RQB = NTR / CWB, RRB = RN / RQB;
+  static_assert(RQB <= RQ, "partial sums fit the tridiagonalisation's array");
+  const int cb = tid % CWB, qb = tid / CWB, rb0 = qb * RRB;
   if (kz > 0) {
     cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
-    cpx<double> z[CPT][RR];  // vectors c + CW j
+    cpx<double> z[CPTB][RRB];  // vectors cb + CWB j
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
+    for (int j = 0; j < CPTB; ++j)
 #pragma unroll
-      for (int u = 0; u < RR; ++u) {
-        const int r = r0 + u, cj = c + CW * j;
+      for (int u = 0; u < RRB; ++u) {
+        const int r = rb0 + u, cj = cb + CWB * j;
         z[j][u] = (cj < kz && r < n) ? Z[(long long)r * n + cj] : mk(0.0, 0.0);
       }
     // reflector k in S.v[k % 3] (zero outside rows k+1 .. n-1), partial sums
@@ -1235,63 +1241,63 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
       const cpx<double> t = S.tau[k];
       const bool active = !(t.re == 0.0 && t.im == 0.0);
       const int r1 = k + 1;
-      const bool rows = r0 + RR > r1 && r0 < n;
-      if (active && c < kz) {
-        constexpr int NC = CPT == 1 ? 4 : 2;  // independent chains per vector
-        double yr[CPT][NC], yi[CPT][NC];
+      const bool rows = rb0 + RRB > r1 && rb0 < n;
+      if (active && cb < kz) {
+        constexpr int NC = CPTB == 1 ? 4 : 2;  // independent chains per vector
+        double yr[CPTB][NC], yi[CPTB][NC];
 #pragma unroll
-        for (int j = 0; j < CPT; ++j)
+        for (int j = 0; j < CPTB; ++j)
 #pragma unroll
           for (int h = 0; h < NC; ++h) yr[j][h] = yi[j][h] = 0.0;
         if (rows) {
 #pragma unroll
-          for (int u = 0; u < RR; ++u) {
-            const cpx<double> vv = vk[r0 + u];
+          for (int u = 0; u < RRB; ++u) {
+            const cpx<double> vv = vk[rb0 + u];
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) dotacc(yr[j][u % NC], yi[j][u % NC], vv, z[j][u]);  // conj(v) z
+            for (int j = 0; j < CPTB; ++j) dotacc(yr[j][u % NC], yi[j][u % NC], vv, z[j][u]);  // conj(v) z
           }
         }
 #pragma unroll
-        for (int j = 0; j < CPT; ++j)
-          if (c + CW * j < kz) {
+        for (int j = 0; j < CPTB; ++j)
+          if (cb + CWB * j < kz) {
             double sr = 0, si = 0;
 #pragma unroll
             for (int h = 0; h < NC; ++h) {
               sr += yr[j][h];
               si += yi[j][h];
             }
-            S.pp[k & 1][q][c + CW * j] = mk(sr, si);
+            S.pp[k & 1][qb][cb + CWB * j] = mk(sr, si);
           }
       }
       if (k >= 1 && tid >= k && tid < n) S.v[(k - 1) % 3][tid] = vq;
       vq = vq2;
       __syncthreads();
-      if (active && c < kz && rows) {
-        cpx<double> ty[CPT];
+      if (active && cb < kz && rows) {
+        cpx<double> ty[CPTB];
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) {
+        for (int j = 0; j < CPTB; ++j) {
           cpx<double> y = mk(0.0, 0.0);
-          if (c + CW * j < kz) {
+          if (cb + CWB * j < kz) {
 #pragma unroll
-            for (int qq = 0; qq < RQ; ++qq) y = y + S.pp[k & 1][qq][c + CW * j];
+            for (int qq = 0; qq < RQB; ++qq) y = y + S.pp[k & 1][qq][cb + CWB * j];
           }
           ty[j] = t * y;
         }
 #pragma unroll
-        for (int u = 0; u < RR; ++u) {
-          const cpx<double> vv = vk[r0 + u];
+        for (int u = 0; u < RRB; ++u) {
+          const cpx<double> vv = vk[rb0 + u];
 #pragma unroll
-          for (int j = 0; j < CPT; ++j) z[j][u] = subprod(z[j][u], vv, ty[j]);
+          for (int j = 0; j < CPTB; ++j) z[j][u] = subprod(z[j][u], vv, ty[j]);
         }
       }
     }
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
-      if (c + CW * j < kz) {
+    for (int j = 0; j < CPTB; ++j)
+      if (cb + CWB * j < kz) {
 #pragma unroll
-        for (int u = 0; u < RR; ++u) {
-          const int r = r0 + u;
-          if (r < n) Z[(long long)r * n + c + CW * j] = z[j][u];
+        for (int u = 0; u < RRB; ++u) {
+          const int r = rb0 + u;
+          if (r < n) Z[(long long)r * n + cb + CWB * j] = z[j][u];
         }
       }
   }
@@ -1322,7 +1328,7 @@ void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hi
   int tok = prof_begin(PC_EIG_REG, s);
   hipLaunchKernelGGL((k_heev_reg<SMALL_NMAX, 64, 0, 1>), dim3(nitems), dim3(64), 0, s, d_descs, d_status);
   if (maxn > SMALL_NMAX)
-    hipLaunchKernelGGL((k_heev_reg<REG_NMAX, 512, SMALL_NMAX, 2>), dim3(nitems), dim3(512), 0, s, d_descs, d_status);
+    hipLaunchKernelGGL((k_heev_reg<REG_NMAX, 512, SMALL_NMAX, 4>), dim3(nitems), dim3(512), 0, s, d_descs, d_status);
   prof_end_eig(tok, PC_EIG_REG, d_descs, nitems, 1, REG_NMAX, s);
   if (maxn > REG_NMAX) {
     tok = prof_begin(PC_EIG_GLOBAL, s);
