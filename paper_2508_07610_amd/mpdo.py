@@ -323,42 +323,58 @@ def program_ops(prog, fixed: List[np.ndarray], fixed_index: dict, use_params: bo
     return ops
 
 
+class BatchPlan:
+    """The host-side form of a batch of programs and their observables
+    (mpdo_program records, operation arrays, fixed gate matrices), built once
+    and reusable across batch_run calls that vary only the device parameters."""
+
+    def __init__(self, programs, observables, use_params: bool):
+        ninst = len(programs)
+        fixed: List[np.ndarray] = []
+        fidx: dict = {}
+        self.keep = []
+        self.progs = (mpdo_program * ninst)()
+        for b, pr in enumerate(programs):
+            ops = program_ops(pr, fixed, fidx, use_params=use_params)
+            obs = np.ascontiguousarray(np.asarray(observables[b], dtype=np.complex128))
+            obuf = obs.view(np.float64).reshape(-1).copy() if obs.size else np.zeros(8)
+            self.keep += [ops, obuf]
+            self.progs[b].n = pr.n
+            self.progs[b].nops = len(pr.ops)
+            self.progs[b].ops = ops
+            self.progs[b].nobs = obs.shape[0] if obs.size else 0
+            self.progs[b].obs = _dptr(obuf)
+        self.ninst = ninst
+        self.use_params = use_params
+        self.total = sum(self.progs[b].nobs for b in range(ninst))
+        self.nfixed = len(fixed)
+        self.fbuf = _cplx(np.array(fixed)) if fixed else np.zeros(32)
+
+
 def batch_run(programs, params, channels: Sequence[Channel], observables, chi_max: int, kappa_max: int,
               max_kraus: int = 16, svd_cutoff: float = 1e-14, kappa_cutoff: float = 1e-14, prec: int = C128,
               use_graph: bool = True, stream=None, out=None):
     """Run many programs through mpdo_batch_run.
 
-    programs: workloads.Program list; params: torch float64 CUDA tensor
-    (ninst, P) of per-instance parameters (or None); observables: per program
-    a (nobs, n, 2, 2) complex array.  Returns a torch complex128 CUDA tensor
+    programs: workloads.Program list, or a BatchPlan built from them (then
+    observables is ignored); params: torch float64 CUDA tensor (ninst, P) of
+    per-instance parameters (or None); observables: per program a
+    (nobs, n, 2, 2) complex array.  Returns a torch complex128 CUDA tensor
     of all expectation values (instance-major)."""
     import torch
-    ninst = len(programs)
-    fixed: List[np.ndarray] = []
-    fidx: dict = {}
-    keep = []
-    progs = (mpdo_program * ninst)()
-    for b, pr in enumerate(programs):
-        ops = program_ops(pr, fixed, fidx, use_params=params is not None)
-        obs = np.ascontiguousarray(np.asarray(observables[b], dtype=np.complex128))
-        obuf = obs.view(np.float64).reshape(-1).copy() if obs.size else np.zeros(8)
-        keep += [ops, obuf]
-        progs[b].n = pr.n
-        progs[b].nops = len(pr.ops)
-        progs[b].ops = ops
-        progs[b].nobs = obs.shape[0] if obs.size else 0
-        progs[b].obs = _dptr(obuf)
-    total = sum(progs[b].nobs for b in range(ninst))
+    plan = programs if isinstance(programs, BatchPlan) else BatchPlan(programs, observables, params is not None)
+    if plan.use_params != (params is not None):
+        raise ValueError("the plan was built for a different parameter mode")
+    ninst, progs, total = plan.ninst, plan.progs, plan.total
     if out is None:
         out = torch.zeros(max(1, total), dtype=torch.complex128, device="cuda")
-    fbuf = _cplx(np.array(fixed)) if fixed else np.zeros(32)
     chans = (ctypes.c_void_p * max(1, len(channels)))(*[c.handle.value for c in channels])
     cfg = mpdo_config(0, chi_max, kappa_max, max_kraus, svd_cutoff, kappa_cutoff, prec)
     pptr, pstride = None, 0
     if params is not None:
         assert params.is_cuda and params.dtype == torch.float64 and params.is_contiguous()
         pptr, pstride = params.data_ptr(), params.shape[1]
-    check(lib().mpdo_batch_run(ctypes.byref(cfg), progs, ninst, pptr, pstride, _dptr(fbuf), len(fixed), chans,
+    check(lib().mpdo_batch_run(ctypes.byref(cfg), progs, ninst, pptr, pstride, _dptr(plan.fbuf), plan.nfixed, chans,
                                len(channels), out.data_ptr(), 1 if use_graph else 0, stream_handle(stream)))
     return out[:total]
 

@@ -96,6 +96,25 @@ def test_batch_graph_is_deterministic():
     assert np.array_equal(a, b)
 
 
+def test_batch_plan_reuse_matches_fresh_calls():
+    """A BatchPlan built once and reused (with new device parameters in
+    between) gives bit-identical results to calls that rebuild it."""
+    require_gpu()
+    import torch
+    progs, P, obs = _instances()
+    chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
+    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14)
+    plan = M.BatchPlan(progs, obs, use_params=True)
+    for scale in (1.0, 0.5, 1.0):
+        pdev = torch.tensor(P * scale, dtype=torch.float64, device="cuda")
+        for graph in (True, False):
+            fresh = M.batch_run(progs, pdev, chans, obs, use_graph=graph, **kw).cpu().numpy()
+            again = M.batch_run(plan, pdev, chans, None, use_graph=graph, **kw).cpu().numpy()
+            assert np.array_equal(fresh, again), (scale, graph)
+    with pytest.raises(ValueError):
+        M.batch_run(plan, None, chans, None, **kw)
+
+
 def test_batch_rejects_bad_programs():
     require_gpu()
     import torch
