@@ -207,7 +207,7 @@ template <int NTH, class SH>
 __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   const int tid = threadIdx.x;
   // ---- multisection for the leading kb = kvec + 1 eigenvalues ----
-  // A group of L lanes (a power of two, L kb <= NTH) brackets one eigenvalue;
+  // A group of L lanes (inside one wave) brackets one eigenvalue;
   // each round evaluates L Sturm counts at equally spaced interior points
   // and keeps the sub-interval where the count passes the target, so the
   // bracket shrinks by L + 1 per round (L = 1 is plain bisection).
@@ -223,14 +223,17 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   const double tnorm = fmax(fabs(lo), fabs(hi));
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   {
+    // groups stay inside a wave: the widest L that still gives every
+    // eigenvalue a group (the last 64 mod L lanes of each wave sit out)
     int L = 64;
-    while (L > 1 && L * kb > NTH) L >>= 1;
-    const int groups = NTH / L;
-    const int gl = tid & (L - 1);
-    const int first = (tid & 63) & ~(L - 1);  // first lane of the group in its wave
+    while (L > 1 && (64 / L) * (NTH / 64) < kb) --L;
+    const int gpw = 64 / L, groups = gpw * (NTH / 64);
+    const int gi = (tid & 63) / L;  // group within the wave
+    const int gl = (tid & 63) - gi * L;
+    const int first = gi * L;  // first lane of the group in its wave
     const unsigned long long gmask = (L == 64) ? ~0ULL : ((1ULL << L) - 1ULL);
     const double inv = 1.0 / (double)(L + 1);
-    for (int j = tid / L; j < kb; j += groups) {
+    for (int j = gi < gpw ? (tid >> 6) * gpw + gi : kb; j < kb; j += groups) {
       const int target = n - 1 - j;  // eigenvalues strictly below lambda_j (no ties)
       double l = lo, h = hi;
       for (int it = 0; it < 120; ++it) {
