@@ -568,18 +568,24 @@ __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict
 // has passed the barrier that follows its last read).
 template <class SH>
 __device__ void back_transform_reg(const EigDesc& dsc, const cpx<double>* __restrict__ A, int n, int kz, SH& S) {
-  constexpr int RB = 32;  // rows per thread
+  // Thread t holds vectors c and c + 32 (c = t mod 32) over 16 rows, so each
+  // reflector entry read from LDS serves two vectors; the two row blocks of a
+  // wave are summed with one lane exchange before the partial sums go to LDS.
+  constexpr int RB = 16;  // rows per thread
   cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
-  const int tid = threadIdx.x, c = tid & 63, q = tid >> 6, r0 = q * RB;
+  const int tid = threadIdx.x, c = tid & 31, q = tid >> 5, r0 = q * RB, wave = tid >> 6;
   cpx<double>* vb[3] = {S.pf, S.pf + 256, S.pf + 512};  // reflector k in vb[k % 3]
-  cpx<double>* pw[2] = {S.pf + 1024, S.pf + 1536};      // 8 chunks x 64 columns
-  cpx<double> z[RB];
+  cpx<double>* pw[2] = {S.pf + 1024, S.pf + 1536};      // 8 waves x 64 vectors
+  cpx<double> z[2][RB];
 #pragma unroll
-  for (int u = 0; u < RB; ++u) {
-    const int r = r0 + u;
-    z[u] = (c < kz && r < n) ? Z[(long long)r * n + c] : mk(0.0, 0.0);
-  }
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int r = r0 + u, cj = c + 32 * j;
+      z[j][u] = (cj < kz && r < n) ? Z[(long long)r * n + cj] : mk(0.0, 0.0);
+    }
   static_assert(NT >= 256, "one reflector entry per thread");
+  static_assert(NT / 32 * RB == 256, "16 row blocks of 16 rows");
   // entry i of v_k over all 256 rows (zero outside k+1 .. n-1); the entries
   // of reflector k - 1 are read during step k + 1, a step before they are
   // stored for use
@@ -593,34 +599,55 @@ __device__ void back_transform_reg(const EigDesc& dsc, const cpx<double>* __rest
     const cpx<double>* v = vb[k % 3];
     const cpx<double> vq2 = (k >= 2 && tid < 256) ? vent(k - 2, tid) : mk(0.0, 0.0);
     const cpx<double> t = S.tau[k];
-    const bool act = !(t.re == 0.0 && t.im == 0.0);
+    const bool act = !(t.re == 0.0 && t.im == 0.0);  // uniform across the block
+    const bool rows = r0 + RB > k + 1;
     if (act) {
-      double yr[4] = {0, 0, 0, 0}, yi[4] = {0, 0, 0, 0};  // four chains for latency
-      if (r0 + RB > k + 1) {
+      double yr[2][2] = {{0, 0}, {0, 0}}, yi[2][2] = {{0, 0}, {0, 0}};
+      if (rows) {
 #pragma unroll
-        for (int u = 0; u < RB; ++u) dotacc(yr[u & 3], yi[u & 3], v[r0 + u], z[u]);  // conj(v) z
+        for (int u = 0; u < RB; ++u) {
+          const cpx<double> vv = v[r0 + u];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) dotacc(yr[j][u & 1], yi[j][u & 1], vv, z[j][u]);  // conj(v) z
+        }
       }
-      pw[k & 1][q * 64 + c] = mk((yr[0] + yr[1]) + (yr[2] + yr[3]), (yi[0] + yi[1]) + (yi[2] + yi[3]));
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        double sr = yr[j][0] + yr[j][1], si = yi[j][0] + yi[j][1];
+        sr += __shfl_xor(sr, 32, 64);  // the other row block of this wave
+        si += __shfl_xor(si, 32, 64);
+        if ((tid & 32) == 0) pw[k & 1][wave * 64 + c + 32 * j] = mk(sr, si);
+      }
     }
     if (k >= 1 && tid < 256) vb[(k - 1) % 3][tid] = vq;
     vq = vq2;
     __syncthreads();
-    if (act && r0 + RB > k + 1) {
-      cpx<double> y = mk(0.0, 0.0);
+    if (act && rows) {
+      cpx<double> ty[2];
 #pragma unroll
-      for (int qq = 0; qq < NT / 64; ++qq) y = y + pw[k & 1][qq * 64 + c];
-      const cpx<double> ty = t * y;
+      for (int j = 0; j < 2; ++j) {
+        cpx<double> y = mk(0.0, 0.0);
 #pragma unroll
-      for (int u = 0; u < RB; ++u) z[u] = subprod(z[u], v[r0 + u], ty);
+        for (int w = 0; w < NT / 64; ++w) y = y + pw[k & 1][w * 64 + c + 32 * j];
+        ty[j] = t * y;
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const cpx<double> vv = v[r0 + u];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) z[j][u] = subprod(z[j][u], vv, ty[j]);
+      }
     }
   }
-  if (c < kz) {
 #pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const int r = r0 + u;
-      if (r < n) Z[(long long)r * n + c] = z[u];
+  for (int j = 0; j < 2; ++j)
+    if (c + 32 * j < kz) {
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int r = r0 + u;
+        if (r < n) Z[(long long)r * n + c + 32 * j] = z[j][u];
+      }
     }
-  }
 }
 
 // Step 2 in the panel form (see heev_core); LV: the panel's V and W live in
