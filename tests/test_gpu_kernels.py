@@ -111,7 +111,9 @@ def test_eigh_against_numpy(n):
     assert bool(np.all(np.diff(ev) <= 0))
 
 
-@pytest.mark.parametrize("n,kvec", [(40, 5), (128, 16), (129, 64), (200, 40), (256, 1), (256, 64), (256, 65), (300, 100), (700, 17), (1024, 16)])
+@pytest.mark.parametrize("n,kvec", [(20, 3), (32, 8), (32, 15), (33, 8), (40, 5), (64, 9), (100, 8), (128, 8), (128, 9),
+                                    (128, 16), (129, 64), (200, 40), (256, 1), (256, 64), (256, 65), (300, 100),
+                                    (700, 17), (1024, 16)])
 def test_eigh_leading_subset(n, kvec):
     """Only the leading kvec eigenpairs (and kvec + 1 eigenvalues) are produced."""
     require_gpu()
@@ -130,11 +132,13 @@ def test_eigh_leading_subset(n, kvec):
     assert e2 < 1e-12 and e3 < 1e-12, (e2, e3)
 
 
-def test_eigh_rank_deficient_and_degenerate():
+@pytest.mark.parametrize("n", [24, 40, 200])
+def test_eigh_rank_deficient_and_degenerate(n):
+    """One case per eigensolver variant (n <= 32, n <= 128, n <= 256)."""
     require_gpu()
-    rng = np.random.default_rng(9)
-    Q, _ = np.linalg.qr(_rand((40, 40), rng))
-    d = np.array([5.0, 5.0, 2.0] + [1e-9] * 5 + [0.0] * 32)
+    rng = np.random.default_rng(9 + n)
+    Q, _ = np.linalg.qr(_rand((n, n), rng))
+    d = np.array([5.0, 5.0, 2.0] + [1e-9] * 5 + [0.0] * (n - 8))
     A = (Q * d) @ Q.conj().T
     ev, V, _ = M.test_eigh(A)
     e1 = float(np.abs(ev - np.sort(d)[::-1]).max())
