@@ -1,12 +1,13 @@
-// Hermitian eigensolver for the truncations (FP64), one workgroup of 512
-// threads per matrix:
+// Hermitian eigensolver for the truncations (FP64), one workgroup per matrix
+// (512 threads; 64 for n <= 32):
 //
 //  1. Householder reduction to real symmetric tridiagonal form
 //     T = Q^H A Q,  Q = H_0 H_1 ... H_{n-2},  H_k = I - tau_k v_k v_k^H,
 //     with the reflector chosen so that H_k^H x = beta e_1, beta real, and
 //     w = tau p - |tau|^2 (v^H p)/2 v, p = A v, for the rank-2 update
 //     A <- A - v w^H - w v^H.  Three forms:
-//     - n <= 128: the matrix is held in registers (k_heev_reg);
+//     - n <= 128: the matrix is held in registers (k_heev_reg; n <= 32 with
+//       one wave per matrix);
 //     - n <= 512: panels of eight columns (k_heev_global): each step reads
 //       the trailing block once and corrects p for the panel's pending
 //       updates; the block is written once per panel, in 4 x 4 register
@@ -560,9 +561,10 @@ __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict
 
 // Z <- H_0 ... H_{n-2} Z with the vector block in registers, for n <= 256
 // and kz <= 64 (the panel form's LDS holds the reflectors): thread t owns
-// column t % 64 and rows 32 (t / 64) .. 32 (t / 64) + 31 of Z.  Per
-// reflector, from the last: partial y = v^H z over each thread's rows, the
-// eight row chunks summed by every thread of a column, then z -= tau v y;
+// columns t % 32 and t % 32 + 32 over rows 16 (t / 32) .. 16 (t / 32) + 15
+// of Z.  Per reflector, from the last: partial y = v^H z over each thread's
+// rows, summed over the wave's two row blocks by a lane exchange and then
+// over the eight waves by every thread of a column, then z -= tau v y;
 // one barrier per reflector (reflector buffers rotate over three slots and
 // the partial sums over two, so a slot is rewritten only after every thread
 // has passed the barrier that follows its last read).
@@ -939,14 +941,15 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// n <= 128: the matrix lives in registers.  512 threads; thread t owns
-// column c = t % 128 and the 32 rows 32 (t / 128) .. 32 (t / 128) + 31 of it
-// (a wave: one row block, 64 consecutive columns).  Each tridiagonalisation step is four
+// n <= 128: the matrix lives in registers.  Thread t owns columns
+// c + (RN / CPT) j, j < CPT, c = t mod (RN / CPT), over one block of rows
+// (the variants below).  Each tridiagonalisation step is four
 // phases between barriers: (a) the previous step's rank-2 update on the
 // owned entries and publication of column k, (b) the reflector (one wave),
 // (c) partial products of A v over the owned rows, (d) their sums and
 // w (one wave).  The reflectors go to dsc.work for the back-transformation,
-// which keeps the eigenvector block in registers in the same layout.
+// which keeps the eigenvector block in registers (at most two vectors per
+// thread).
 // ---------------------------------------------------------------------------
 // Two variants share the code below (RN: largest n, NTR: threads, NLO:
 // smaller n are left to the other variant, CPT: columns per thread):
