@@ -101,9 +101,11 @@ template <typename Tin, typename Tc, int T> struct Slice {
 
 // Tile TM x TN per workgroup of four waves in a 2 x 2 arrangement; each wave
 // computes (TM/2) x (TN/2) from 16 x 16 MFMA blocks.  The next K slice is
-// loaded into registers while the current one is multiplied from LDS.
+// loaded into registers while the current one is multiplied from LDS.  The
+// 32 x 32 tiles (small outputs, long K) fit eight waves per SIMD, the 64 x 64
+// tiles four.
 template <typename Tin, typename Tc, typename Tout, int TM, int TN>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(TM == 32 ? 8 : 4, TM == 32 ? 8 : 4)))
 void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int maxTiles, long long nblocks) {
   typedef typename Mfma<Tc>::v4 v4;
   constexpr int FM = TM / 32, FN = TN / 32;  // 16 x 16 blocks per wave and dimension
