@@ -17,17 +17,20 @@ neighbouring sites is then diag(lambda_{left}^2) on the left and the identity
 on the right, which is the canonical form Sec. II.D asks for before an SVD
 truncation, maintained gate by gate.  ``truncate_sweep`` performs the
 paper's explicit procedure -- QR from left to right, then SVD from right to
-left -- and restores an exact canonical form.
+left.  It leaves every tensor but the first right-orthonormal; each bond's
+weights are its singular values when it was cut, which are the Schmidt
+values of the result when nothing further left is cut (always for bond 0).
 
 Noisy gates (Eq. (8), Fig. fig_mpdoSingle).  A gate on q adjacent sites with
 ideal unitary U and channel {K_j} acts through the fused operators
 G_j = K_j U.  The new noise index j is attached to the inner index of the
-leftmost site (q = 1, 2); a 3-site channel is split into a 3-site operator
-string first.
+leftmost site (q = 1, 2) or of the middle site (q = 3).
 
-Inner truncation (Eqs. (9)-(11)).  T ~= U Sigma V^dagger over (p, l, r) x n;
-V, Sigma^2 come from the eigendecomposition of the Gram matrix over the
-inner index with the left bond weighted by lambda^2; the new tensor is T V_kappa.
+Inner truncation (Eqs. (9)-(11)).  T ~= U Sigma V^dagger over (p, l, r) x n,
+the SVD taken of T with its left bond weighted by lambda (the environment of
+the site in canonical form); the new tensor is T V_kappa.  The SVD is taken
+of the matrix itself, not of a Gram matrix, so weights far below the
+largest are resolved.
 
 Bond truncation (Sec. II.D, Fig. fig_svdTruncate (b)).  The two-site block is
 split by an SVD of lambda_left * Theta; the right factor V^dagger becomes the
@@ -35,10 +38,10 @@ new right tensor, the singular values the new bond weights, and Theta V the
 new left tensor.
 
 Truncation rule for both kinds of index (a reading: the paper fixes no rule):
-with eigenvalues eta (descending) of the relevant Gram matrix and total
-weight W, keep the smallest r >= 1 with sum_{i >= r} eta_i <= cutoff * W,
-capped at the maximum dimension; then rescale so the kept weight is 1
-(Tr rho = 1).
+with eta the squared singular values (descending) and W their sum, keep the
+smallest r >= 1 with sum_{i >= r} eta_i <= cutoff * W, capped at the maximum
+dimension; then rescale so the kept weight is 1 (Tr rho = 1).  There is no
+other floor: the cutoff alone decides what is numerically zero.
 """
 from __future__ import annotations
 
@@ -48,16 +51,14 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 
-TIE_REL = 1e-9     # eigenvalues closer than this (relative) form one multiplet
-TIE_FLOOR = 1e-11  # ... unless they carry less than this fraction of the weight
-NUM_ZERO = 1e-13   # eigenvalues at or below this fraction of the largest are zero
+TIE_REL = 1e-9     # weights closer than this (relative) form one multiplet
+TIE_FLOOR = 1e-11  # ... unless they carry less than this fraction of the total
 
 
 def select_rank(eta: np.ndarray, max_dim: int, cutoff: float) -> int:
     """Smallest r >= 1 with sum_{i>=r} eta_i <= cutoff * W, capped at max_dim.
-    eta is in descending order; negative round-off values count as zero.
-    Eigenvalues at or below NUM_ZERO times the largest are numerically zero
-    (the numerical rank of an FP64 Gram matrix) and never kept.
+    eta (squared singular values) is in descending order; negative values
+    count as zero.
 
     A degenerate multiplet straddling the cut is dropped as a whole (r is
     lowered until eta_{r-1} and eta_r differ), so the kept subspace -- and
@@ -74,8 +75,7 @@ def select_rank(eta: np.ndarray, max_dim: int, cutoff: float) -> int:
         if tail[cand] <= cutoff * W:
             r = cand
             break
-    nz = int(np.sum(e > NUM_ZERO * e[0]))
-    r = int(max(1, min(r, max_dim, nz)))
+    r = int(max(1, min(r, max_dim)))
     r0 = r
     while 1 < r < len(e) and e[r - 1] > TIE_FLOOR * W and e[r - 1] - e[r] <= TIE_REL * e[r - 1]:
         r -= 1
@@ -84,11 +84,9 @@ def select_rank(eta: np.ndarray, max_dim: int, cutoff: float) -> int:
     return r
 
 
-def _eigh_desc(gram: np.ndarray):
-    gram = (gram + gram.conj().T) / 2
-    w, v = np.linalg.eigh(gram)
-    order = np.argsort(-w, kind="stable")
-    return w[order], v[:, order]
+def _svd(M: np.ndarray):
+    """Thin SVD M = U diag(S) Vh, singular values descending."""
+    return np.linalg.svd(M, full_matrices=False)
 
 
 class MPDO:
@@ -106,6 +104,7 @@ class MPDO:
             self.T.append(t)
         self.lam: List[np.ndarray] = [np.ones(1) for _ in range(n - 1)]
         self.discarded = 0.0   # summed discarded weight of all truncations
+        self.cuts: List[float] = []   # discarded fraction of every bond cut, in order
 
     # -- helpers ----------------------------------------------------------------
     def lam_left(self, i: int) -> np.ndarray:
@@ -120,16 +119,17 @@ class MPDO:
     # -- inner (noise) truncation, Eqs. (9)-(11) ---------------------------------
     def _compress_inner(self, Tp: np.ndarray, inner_axis: int, lam_l: np.ndarray):
         """Tp has the left bond on axis 0 and the inner index on `inner_axis`.
-        Returns (Tp V_kappa with the inner axis replaced, kept weight fraction)."""
+        Returns Tp V_kappa (the inner axis replaced by the kept directions),
+        rescaled so the kept weight is 1."""
         moved = np.moveaxis(Tp, inner_axis, -1)
         shape = moved.shape
         M = (lam_l.reshape((-1,) + (1,) * (moved.ndim - 1)) * moved).reshape(-1, shape[-1])
-        gram = M.conj().T @ M
-        eta, V = _eigh_desc(gram)
+        _, S, Vh = _svd(M)
+        eta = S ** 2
         k = select_rank(eta, self.kappa_max, self.kappa_cutoff)
-        W = np.clip(eta, 0, None).sum()
-        kept = np.clip(eta[:k], 0, None).sum()
-        out = moved.reshape(-1, shape[-1]) @ V[:, :k]
+        W = eta.sum()
+        kept = eta[:k].sum()
+        out = moved.reshape(-1, shape[-1]) @ Vh[:k].conj().T
         out = out.reshape(shape[:-1] + (k,)) / math.sqrt(kept)
         self.discarded += float((W - kept) / W) if W > 0 else 0.0
         return np.moveaxis(out, -1, inner_axis)
@@ -168,23 +168,25 @@ class MPDO:
     def _split(self, i: int, theta: np.ndarray, lshape, rshape, lam_l: np.ndarray) -> None:
         """SVD of lambda_left * Theta; right factor -> T_{i+1}, Theta V -> T_i."""
         wl = np.repeat(lam_l, theta.shape[0] // lam_l.shape[0])
-        U, S, Vh = np.linalg.svd(wl[:, None] * theta, full_matrices=False)
+        U, S, Vh = _svd(wl[:, None] * theta)
         eta = S ** 2
         rr = select_rank(eta, self.chi_max, self.svd_cutoff)
         W = eta.sum()
         kept = eta[:rr].sum()
         self.discarded += float((W - kept) / W) if W > 0 else 0.0
+        self.cuts.append(float((W - kept) / W) if W > 0 else 0.0)
         s = 1.0 / math.sqrt(kept)
         self.T[i + 1] = Vh[:rr].reshape((rr,) + tuple(rshape))
         self.T[i] = (theta @ Vh[:rr].conj().T).reshape(tuple(lshape) + (rr,)) * s
         self.lam[i] = S[:rr] * s
 
     def apply_3q(self, i: int, G: Sequence[np.ndarray]) -> None:
-        """Three-site noisy gate on (i, i+1, i+2): the operators G_j are written
-        as a string W1[a] W2[a, b, j] W3[b] by two SVDs (the noise index j on the
-        middle site), applied to the three sites, then the middle inner index and
-        both grown bonds are truncated.  Implemented as contract-apply-split on
-        the full three-site block."""
+        """Three-site noisy gate on (i, i+1, i+2), written as contract-apply-split
+        on the full three-site block: the three tensors are contracted, every
+        G_j is applied to the physical indices with the new noise index j joined
+        to the inner index of the middle site, that inner index is truncated
+        (Eqs. (9)-(11)), and the block is split by two SVDs, first at bond i
+        (left site off), then at bond i+1 with the new weights of bond i."""
         G = np.asarray(G, dtype=np.complex128).reshape(-1, 8, 8)
         A, B, C = self.T[i], self.T[i + 1], self.T[i + 2]
         l, _, k1, _ = A.shape
@@ -218,6 +220,20 @@ class MPDO:
         kappa_max = self.kappa_max if kappa_max is None else kappa_max
         cutoff = self.svd_cutoff if cutoff is None else cutoff
         before = self.discarded
+        self.bond_sweep(chi_max, cutoff)
+        saved = self.kappa_max
+        self.kappa_max = kappa_max
+        for i in range(self.n):
+            T = self.T[i]
+            if T.shape[2] > 1:
+                self.T[i] = self._compress_inner(T, 2, self.lam_left(i))
+        self.kappa_max = saved
+        return self.discarded - before
+
+    def bond_sweep(self, chi_max: int, cutoff: float) -> None:
+        """The bond part of the sweep: QR left to right, then SVD right to left
+        with every bond truncated by the rank rule; the state is renormalised
+        once at the end, each cut's discarded fraction is logged in ``cuts``."""
         n = self.n
         for i in range(n - 1):
             T = self.T[i]
@@ -233,19 +249,12 @@ class MPDO:
             rr = select_rank(eta, chi_max, cutoff)
             W, kept = eta.sum(), eta[:rr].sum()
             self.discarded += float((W - kept) / W) if W > 0 else 0.0
+            self.cuts.append(float((W - kept) / W) if W > 0 else 0.0)
             self.T[i] = Vh[:rr].reshape(rr, 2, k, r)
             self.T[i - 1] = np.einsum("lskb,bc->lskc", self.T[i - 1], U[:, :rr] * S[:rr])
             self.lam[i - 1] = S[:rr] / math.sqrt(kept)
         t0 = self.T[0]
         self.T[0] = t0 / np.linalg.norm(t0)
-        saved = self.kappa_max
-        self.kappa_max = kappa_max
-        for i in range(n):
-            T = self.T[i]
-            if T.shape[2] > 1:
-                self.T[i] = self._compress_inner(T, 2, self.lam_left(i))
-        self.kappa_max = saved
-        return self.discarded - before
 
     # -- observables (Eqs. (6)-(7)) -------------------------------------------------
     def expect_product(self, ops: Sequence[np.ndarray]) -> complex:
