@@ -77,7 +77,7 @@ def run(n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,
         chans = [M.Channel(c, q, eps=eps if q == 3 else 0.0) for c, q in zip(prog.chis, qs)]
         mk = max(ch.nkraus for ch in chans)
         st = M.MPDO(n, chi_max=chi_max, kappa_max=kappa_max, max_kraus=mk, svd_cutoff=1e-10,
-                    kappa_cutoff=1e-14, prec=prec)
+                    kappa_cutoff=1e-10, prec=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         M.run_program(prog, st, chans)
@@ -128,7 +128,7 @@ def run_batch(nb: int = 16, n: int = 24, depth: int = 12, chi_max: int = 128, ka
     chans = [M.Channel(c, q, eps=eps if q == 3 else 0.0) for c, q in zip(chis, qs)]
     mk = max(ch.nkraus for ch in chans)
     obs = [z_products(n)] * nb
-    kw = dict(chi_max=chi_max, kappa_max=kappa_max, max_kraus=mk, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    kw = dict(chi_max=chi_max, kappa_max=kappa_max, max_kraus=mk, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     M.batch_run(progs, None, chans, obs, use_graph=False, **kw)  # warm-up (workspace sizing)
     torch.cuda.synchronize()
     M.profile_enable(True)

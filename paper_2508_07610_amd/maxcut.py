@@ -73,7 +73,7 @@ def run(n_ghz: int = 256, n_qaoa: int = 128, depth: int = 6, chi_max: int = 32, 
     progs, P, obs, info = instances(n_ghz, n_qaoa, depth, seed_tag)
     chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
     pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
-    kw = dict(chi_max=chi_max, kappa_max=kappa_max, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    kw = dict(chi_max=chi_max, kappa_max=kappa_max, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     plan = M.BatchPlan(progs, obs, use_params=True)  # the host-side form, built once
     out = M.batch_run(plan, pdev, chans, None, use_graph=use_graph, **kw)
     torch.cuda.synchronize()

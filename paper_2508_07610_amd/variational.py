@@ -41,7 +41,7 @@ class AnsatzEvaluator:
     """GHZ fidelity and <Z_i Z_i+1> of the noisy ansatz for many (theta, noise) rows, one batch_run per call."""
 
     def __init__(self, n: int, depth: int, chi_max: int = 32, kappa_max: int = 4, prec: int = M.C128,
-                 svd_cutoff: float = 1e-10, kappa_cutoff: float = 1e-14):
+                 svd_cutoff: float = 1e-10, kappa_cutoff: float = 1e-10):
         self.n, self.depth = n, depth
         self.P = 2 * n * depth
         self.kw = dict(chi_max=chi_max, kappa_max=kappa_max, max_kraus=16, svd_cutoff=svd_cutoff,

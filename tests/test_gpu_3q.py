@@ -24,9 +24,9 @@ def _run_both(prog, chi, kap, eps, prec, max_kraus):
     """eps prunes the Kraus sets of the three-site channels only."""
     qs = [int(round(math.log(c.shape[0], 4))) for c in prog.chis]
     kr = [OC.kraus_from_chi(c, eps if q == 3 else 0.0)[0] for c, q in zip(prog.chis, qs)]
-    o = OM.run_program(prog, OM.MPDO(prog.n, chi, kap, 1e-10, 1e-14), kr)
+    o = OM.run_program(prog, OM.MPDO(prog.n, chi, kap, 1e-10, 1e-10), kr)
     chans = [M.Channel(c, q, eps=eps if q == 3 else 0.0) for c, q in zip(prog.chis, qs)]
-    st = M.MPDO(prog.n, chi_max=chi, kappa_max=kap, max_kraus=max_kraus, svd_cutoff=1e-10, kappa_cutoff=1e-14,
+    st = M.MPDO(prog.n, chi_max=chi, kappa_max=kap, max_kraus=max_kraus, svd_cutoff=1e-10, kappa_cutoff=1e-10,
                 prec=prec)
     M.run_program(prog, st, chans)
     return o, st
@@ -96,7 +96,7 @@ def test_batch_run_with_crosstalk(prec):
                 z[k, s] = np.diag([1.0, -1.0]) if s in (k, k + 1) else np.eye(2)
         obs.append(z)
     chans = [M.Channel(chis[0], 2), M.Channel(chi3[0], 3), M.Channel(chi3[1], 3)]
-    kw = dict(chi_max=16, kappa_max=4, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    kw = dict(chi_max=16, kappa_max=4, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     out = M.batch_run(progs, None, chans, obs, use_graph=True, **kw).cpu().numpy()
     out_ng = M.batch_run(progs, None, chans, obs, use_graph=False, **kw).cpu().numpy()
     assert np.array_equal(out, out_ng)
@@ -104,7 +104,7 @@ def test_batch_run_with_crosstalk(prec):
     tol = TOL[prec]
     off = 0
     for pr, ob in zip(progs, obs):
-        o = OM.run_program(pr, OM.MPDO(pr.n, 16, 4, 1e-10, 1e-14), kr)
+        o = OM.run_program(pr, OM.MPDO(pr.n, 16, 4, 1e-10, 1e-10), kr)
         ref = np.array([o.expect_product(list(x)) / o.trace() for x in ob])
         got = out[off: off + len(ob)]
         off += len(ob)

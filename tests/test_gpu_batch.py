@@ -63,7 +63,7 @@ def test_batch_equals_plain_and_oracle(prec):
     import torch
     progs, P, obs = _instances()
     chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
-    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
     out = M.batch_run(progs, pdev, chans, obs, use_graph=True, **kw).cpu().numpy()
     out_ng = M.batch_run(progs, pdev, chans, obs, use_graph=False, **kw).cpu().numpy()
@@ -79,7 +79,7 @@ def test_batch_equals_plain_and_oracle(prec):
         M.run_program(pr, st, chans)
         plain = st.expect_products(obs[b])
         assert float(np.abs(got - plain).max()) < (1e-12 if prec == M.C128 else 1e-6), b
-        o = OM.run_program(pr, OM.MPDO(pr.n, 16, 4, 1e-10, 1e-14), kr)
+        o = OM.run_program(pr, OM.MPDO(pr.n, 16, 4, 1e-10, 1e-10), kr)
         ref = np.array([o.expect_product(list(ob)) / o.trace() for ob in obs[b]])
         assert float(np.abs(got - ref).max()) < tol, (b, float(np.abs(got - ref).max()))
 
@@ -90,7 +90,7 @@ def test_batch_graph_is_deterministic():
     progs, P, obs = _instances()
     chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
     pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
-    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14)
+    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10)
     a = M.batch_run(progs, pdev, chans, obs, **kw).cpu().numpy()
     b = M.batch_run(progs, pdev, chans, obs, **kw).cpu().numpy()
     assert np.array_equal(a, b)
@@ -103,7 +103,7 @@ def test_batch_plan_reuse_matches_fresh_calls():
     import torch
     progs, P, obs = _instances()
     chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
-    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14)
+    kw = dict(chi_max=16, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10)
     plan = M.BatchPlan(progs, obs, use_params=True)
     for scale in (1.0, 0.5, 1.0):
         pdev = torch.tensor(P * scale, dtype=torch.float64, device="cuda")

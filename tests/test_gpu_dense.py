@@ -19,9 +19,9 @@ TOL = {M.C128: 1e-10, M.C64_MIXED: 1e-5}
 def _both(prog, chi, kap, prec, eps=0.0):
     qs = [int(round(math.log(c.shape[0], 4))) for c in prog.chis]
     kr = [OC.kraus_from_chi(c, eps if q == 3 else 0.0)[0] for c, q in zip(prog.chis, qs)]
-    o = OM.run_program(prog, OM.MPDO(prog.n, chi, kap, 1e-10, 1e-14), kr)
+    o = OM.run_program(prog, OM.MPDO(prog.n, chi, kap, 1e-10, 1e-10), kr)
     chans = [M.Channel(c, q, eps=eps if q == 3 else 0.0) for c, q in zip(prog.chis, qs)]
-    st = M.MPDO(prog.n, chi_max=chi, kappa_max=kap, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    st = M.MPDO(prog.n, chi_max=chi, kappa_max=kap, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     M.run_program(prog, st, chans)
     return o, st
 
@@ -53,7 +53,7 @@ def test_dense_at_twelve_qubits():
     require_gpu()
     n = 12
     prog = W.ghz_ansatz(n, 2, W.ansatz_params(n, 2, 5))
-    st = M.MPDO(n, chi_max=32, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14)
+    st = M.MPDO(n, chi_max=32, kappa_max=4, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10)
     M.run_program(prog, st, [M.Channel(c, 1 if c.shape[0] == 4 else 2) for c in prog.chis])
     rho = st.to_dense()
     assert abs(np.trace(rho) - st.trace()) < 1e-10
@@ -91,7 +91,7 @@ def test_uhlmann_fidelity_of_pruned_crosstalk_runs():
     dens = []
     for eps in (0.0, 1e-3):
         kr = [OC.kraus_from_chi(c, eps if q == 3 else 0.0)[0] for c, q in zip(prog.chis, qs)]
-        o = OM.run_program(prog, OM.MPDO(6, 32, 8, 1e-10, 1e-14), kr)
+        o = OM.run_program(prog, OM.MPDO(6, 32, 8, 1e-10, 1e-10), kr)
         r = o.to_dense()
         dens.append(r / np.trace(r).real)
     assert abs(X.uhlmann_fidelity(dens[0], dens[1]) - f) < 1e-8

@@ -22,7 +22,7 @@ T1, T2, T_1Q, T_2Q, P1, P2 = 30.0, 20.0, 0.03, 0.3, 1e-3, 1e-2  # microseconds
 
 def _probs(prog, prec=M.C128):
     qs = [int(round(math.log(c.shape[0], 4))) for c in prog.chis]
-    st = M.MPDO(prog.n, chi_max=32, kappa_max=8, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    st = M.MPDO(prog.n, chi_max=32, kappa_max=8, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     M.run_program(prog, st, [M.Channel(c, q) for c, q in zip(prog.chis, qs)])
     p = st.probabilities(D.all_bitstrings(prog.n))
     st.close()
@@ -37,7 +37,7 @@ def test_standard_models_match_oracle(model):
     c2 = W.chi_unified_2q(P2, T_2Q, T1, T2) if model == "unified" else W.chi_ideal_noisy_2q(P2, T_2Q, T1, T2)
     prog = W.with_channels(base, W.chi_standard_1q(P1, T_1Q, T1, T2), c2)
     kr = [OC.kraus_from_chi(c)[0] for c in prog.chis]
-    o = OM.run_program(prog, OM.MPDO(n, 32, 8, 1e-10, 1e-14), kr)
+    o = OM.run_program(prog, OM.MPDO(n, 32, 8, 1e-10, 1e-10), kr)
     ref = OS.basis_probabilities(o.to_dense())
     got = _probs(prog)
     assert float(np.abs(got - ref).max()) < 1e-10

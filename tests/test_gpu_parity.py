@@ -122,8 +122,8 @@ def test_truncated_ansatz_matches_oracle(prec, n, depth, chi, kap, tag):
     agree (observables to the tolerance of the precision)."""
     require_gpu()
     prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, tag))
-    o = _oracle_run(prog, chi, kap, 1e-10, 1e-14)
-    st = _gpu_run(prog, chi_max=chi, kappa_max=kap, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    o = _oracle_run(prog, chi, kap, 1e-10, 1e-10)
+    st = _gpu_run(prog, chi_max=chi, kappa_max=kap, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     bonds, inner, disc = st.dims()
     tol = TOL[prec]
     if prec == M.C128:

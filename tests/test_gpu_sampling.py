@@ -23,9 +23,9 @@ MARGIN = {M.C128: 1e-9, M.C64_MIXED: 1e-4}
 def _both(prog, chi, kap, prec, eps=0.0):
     qs = [int(round(math.log(c.shape[0], 4))) for c in prog.chis]
     kr = [OC.kraus_from_chi(c, eps if q == 3 else 0.0)[0] for c, q in zip(prog.chis, qs)]
-    o = OM.run_program(prog, OM.MPDO(prog.n, chi, kap, 1e-10, 1e-14), kr)
+    o = OM.run_program(prog, OM.MPDO(prog.n, chi, kap, 1e-10, 1e-10), kr)
     chans = [M.Channel(c, q, eps=eps if q == 3 else 0.0) for c, q in zip(prog.chis, qs)]
-    st = M.MPDO(prog.n, chi_max=chi, kappa_max=kap, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-14, prec=prec)
+    st = M.MPDO(prog.n, chi_max=chi, kappa_max=kap, max_kraus=64, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     M.run_program(prog, st, chans)
     return o, st
 
@@ -83,7 +83,7 @@ def test_sample_reproducible_and_consistent_at_benchmark_size():
     require_gpu()
     n, depth = 16, 10
     prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, 0))
-    st = M.MPDO(n, chi_max=64, kappa_max=8, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-14)
+    st = M.MPDO(n, chi_max=64, kappa_max=8, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10)
     M.run_program(prog, st, [M.Channel(c, 1 if c.shape[0] == 4 else 2) for c in prog.chis])
     u = np.random.default_rng(16).random((512, n))
     bits, pz = st.sample(u)

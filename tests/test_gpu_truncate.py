@@ -21,9 +21,9 @@ TOL = {M.C128: 1e-10, M.C64_MIXED: 1e-5}
 def _pair(n, depth, chi, kap, tag, prec):
     prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, tag))
     kr = [OC.kraus_from_chi(c)[0] for c in prog.chis]
-    o = OM.run_program(prog, OM.MPDO(n, chi, kap, 1e-12, 1e-14), kr)
+    o = OM.run_program(prog, OM.MPDO(n, chi, kap, 1e-10, 1e-10), kr)
     chans = [M.Channel(c, int(round(math.log(c.shape[0], 4)))) for c in prog.chis]
-    st = M.MPDO(n, chi_max=chi, kappa_max=kap, max_kraus=16, svd_cutoff=1e-12, kappa_cutoff=1e-14, prec=prec)
+    st = M.MPDO(n, chi_max=chi, kappa_max=kap, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
     M.run_program(prog, st, chans)
     return o, st
 
@@ -36,7 +36,7 @@ def _observables(n):
 @pytest.mark.parametrize("n,depth,chi,kap,chi2,kap2,cut,tag", [
     (6, 2, 16, 8, 4, 2, 1e-8, 1),
     (8, 3, 32, 8, 6, 3, 1e-6, 2),
-    (7, 2, 16, 4, 16, 1, 0.0, 3),
+    (7, 2, 16, 4, 16, 1, 1e-10, 3),
 ])
 def test_truncate_matches_oracle(prec, n, depth, chi, kap, chi2, kap2, cut, tag):
     require_gpu()

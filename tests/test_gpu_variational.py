@@ -27,7 +27,7 @@ def test_evaluator_matches_oracle():
     for b in range(3):
         prog = W.ghz_ansatz_noise(n, depth, th[b], nz[b])
         kr = [OC.kraus_from_chi(c)[0] for c in prog.chis]
-        o = OM.run_program(prog, OM.MPDO(n, 16, 4, 1e-10, 1e-14), kr)
+        o = OM.run_program(prog, OM.MPDO(n, 16, 4, 1e-10, 1e-10), kr)
         assert abs(out[b, 0] - o.fidelity_ghz()) < 1e-10
         for i, s in enumerate(W.zz_strings(n)):
             assert abs(out[b, 1 + i] - o.expect_pauli(s).real) < 1e-10
