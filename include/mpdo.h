@@ -24,14 +24,31 @@
  *   - Pauli order is I, X, Y, Z; the q-qubit Pauli index is
  *     m = sum_t m_t 4^(q-1-t), t = 0 the lowest site.
  *   - Host buffers passed in are owned by the caller and only read during
- *     the call.  Handles own their device memory (hipMalloc), released by
- *     the matching destroy call.
+ *     the call.  Handles own their device memory, released by the matching
+ *     destroy call.  It comes from the caller's allocator when the config
+ *     supplies one (alloc/free hooks, e.g. a framework's caching allocator),
+ *     else from the library's cache of device blocks: a released block is
+ *     kept and reused by later requests of up to its size (so repeated
+ *     mpdo_batch_run calls of the same shapes allocate nothing after the
+ *     first); mpdo_release_cached_memory() returns the cache to the driver.
  *   - Work is enqueued on the HIP stream given at creation (NULL = the
  *     default stream).  Calls that return host values synchronise that
  *     stream; others may return before the GPU work finishes.
- *   - A handle is not thread-safe.  On error a call returns a status other
- *     than MPDO_OK, leaves the state as it was before the call (except after
- *     MPDO_EDEVICE, which is sticky), and mpdo_last_error() describes it.
+ *   - A handle is not thread-safe.
+ *   - Errors.  Argument errors (EINVAL, ENOTCPTP) are detected before any
+ *     work starts: the call changes nothing.  Any error after work on the
+ *     device has started (EDEVICE: a HIP call failed; ENOMEM; ENOTCONV: a
+ *     numerical failure, see below) makes the handle unusable: that call and
+ *     every later call on the handle except mpdo_destroy, mpdo_stats and
+ *     mpdo_dims return an error (EDEVICE after the first).  Queued gates run
+ *     when a call needs the state, so a failure in a queued gate is reported
+ *     by the next call that synchronises (expect, trace, dims, truncate,
+ *     to_dense, probabilities, sample, bond_weights, stats).
+ *     mpdo_last_error() describes the last error of the calling thread.
+ *   - Numerical failures (ENOTCONV) are detected on the device and checked
+ *     at every synchronising call: a non-finite weight in a truncation, an
+ *     eigenpair of a Gram matrix whose tridiagonal residual exceeds
+ *     1e-9 ||T||, a non-finite or non-positive Tr(rho).
  */
 #ifndef MPDO_H
 #define MPDO_H
@@ -49,7 +66,8 @@ typedef enum {
   MPDO_ENOTCPTP = 2,      /* chi does not describe a trace-preserving map    */
   MPDO_ENOMEM = 3,        /* device allocation failed                        */
   MPDO_EDEVICE = 4,       /* a HIP call failed; the handle is unusable       */
-  MPDO_ENOTCONV = 5,      /* an eigensolver did not reach its tolerance      */
+  MPDO_ENOTCONV = 5,      /* a numerical failure: an eigenpair above its
+                             residual bound, non-finite weights or trace    */
   MPDO_EUNSUPPORTED = 6   /* valid but not implemented in this build         */
 } mpdo_status;
 
@@ -73,6 +91,14 @@ typedef struct {
                              the total, then cap at chi_max                   */
   double kappa_cutoff;    /* same rule for the inner index                    */
   int32_t prec;           /* mpdo_prec                                        */
+  /* Optional device allocator for every allocation the call or the handle
+   * makes (both hooks set, or alloc NULL for the library's cache).  alloc
+   * returns device memory of at least `bytes` bytes on the current device,
+   * or NULL (the call then fails with ENOMEM); free releases it.  Memory is
+   * released only after the device has finished the work that uses it. */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* alloc_ctx;
 } mpdo_config;
 
 typedef struct mpdo_s* mpdo_t;
@@ -157,6 +183,40 @@ mpdo_status mpdo_dims(mpdo_t h, int32_t* bonds, int32_t* inner, double* discarde
  * `cap` doubles and the count to *len. */
 mpdo_status mpdo_bond_weights(mpdo_t h, int32_t b, double* out, int32_t cap, int32_t* len);
 
+/* Truncation statistics of a state (metrics for diagnosing truncated
+ * results; the rule is the one of mpdo_config):
+ *   truncations: inner and bond truncations applied so far;
+ *   discarded: summed discarded weight, each truncation's dropped fraction
+ *     of its Gram trace (Eq. (10): the squared Frobenius error of the
+ *     truncated site, relative);
+ *   max_discarded: the largest single one;
+ *   min_gap: smallest relative gap eta_{r-1} / eta_r - 1 between the last
+ *     kept and the first dropped eigenvalue over all truncations that
+ *     dropped weight (1e300 if none): a cut inside a near-degenerate
+ *     multiplet makes a truncated result depend on rounding;
+ *   trace: Tr(rho) of the current state, unnormalised (its drift from 1
+ *     measures accumulated rounding and pruning);
+ *   failures: numerical failures detected on the device (nonzero means the
+ *     handle has reported ENOTCONV);
+ *   max_bond, max_inner: largest bond and inner dimension.
+ * Works on an unusable handle too (then trace is NaN). */
+typedef struct {
+  int64_t truncations;
+  int64_t failures;
+  double discarded;
+  double max_discarded;
+  double min_gap;
+  double trace;
+  int32_t max_bond;
+  int32_t max_inner;
+} mpdo_stats_t;
+mpdo_status mpdo_stats(mpdo_t h, mpdo_stats_t* out);
+
+/* Return the library's cache of released device and pinned host blocks to
+ * the driver (blocks held by live handles stay).  *cached (may be NULL)
+ * receives the device bytes the cache held. */
+mpdo_status mpdo_release_cached_memory(size_t* cached);
+
 /* The dense density matrix (Eqs. (6)-(7): the per-site tensors summed over
  * the inner index, contracted along the chain) for n <= 12: rho is host
  * memory of 2^n x 2^n complex doubles, row-major, qubit 0 the most
@@ -234,7 +294,10 @@ typedef struct {
  * descriptor upload, every sublayer, the observables) into one HIP graph and
  * launches it once; with hip_stream NULL a private stream is used for the
  * capture.  The call returns when the results are in out_dev.  Returns
- * EINVAL for malformed programs. */
+ * EINVAL for malformed programs, ENOTCONV (after writing the results) when
+ * a numerical failure was detected in any instance.  Device memory comes
+ * from cfg's allocator or the library's cache (no driver allocation once
+ * a run of the same shapes has been made). */
 mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
                            const double* params_dev, int32_t param_stride,
                            const double* fixed_u, int32_t nfixed,

@@ -53,6 +53,17 @@ mpdo_status mpdo_test_gemm_rate(int32_t prec, int32_t M, int32_t N, int32_t K, i
 mpdo_status mpdo_test_eigh(int32_t n, int32_t kvec, const double* A, double* evals, double* evecs,
                            double* trace);
 
+/* Failure injection for the tests of error handling (forced from the host;
+ * every kernel still runs to its normal end):
+ *   mpdo_test_eig_residual_bound: residual bound of the eigensolver on the
+ *     current device, relative to ||T|| (0 restores 1e-9; a negative bound
+ *     makes every eigenpair fail its check, which the library reports as
+ *     ENOTCONV);
+ *   mpdo_test_fail_next_update: the next sublayer of gates of any handle
+ *     fails with `status` before launching anything (0 cancels). */
+mpdo_status mpdo_test_eig_residual_bound(double rtol);
+mpdo_status mpdo_test_fail_next_update(int32_t status);
+
 #ifdef __cplusplus
 }
 #endif

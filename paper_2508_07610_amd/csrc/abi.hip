@@ -1,6 +1,7 @@
 // C ABI of libmpdo (declared in include/mpdo.h).  Argument checking, the
 // gate queue that groups gates on disjoint sites into sublayers, and the
 // translation of host inputs into device work.  No exception crosses the ABI.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -49,6 +50,8 @@ struct AnyEngine {
   double truncate_sweep(int b, int c, int k, double cut) {
     return d ? d->truncate_sweep(b, c, k, cut) : f->truncate_sweep(b, c, k, cut);
   }
+  InstStats stats(int b) { return d ? d->stats(b) : f->stats(b); }
+  long long failures() { return d ? d->failures() : f->failures(); }
 };
 
 Config make_config(const mpdo_config* cfg) {
@@ -74,6 +77,16 @@ const char* check_config(const mpdo_config* cfg, bool need_n) {
   return nullptr;
 }
 
+DeviceAllocator hooks_of(const mpdo_config* cfg) {
+  DeviceAllocator a;
+  if (cfg && cfg->alloc && cfg->free) {
+    a.alloc = cfg->alloc;
+    a.free = cfg->free;
+    a.ctx = cfg->alloc_ctx;
+  }
+  return a;
+}
+
 #define GUARD_BEGIN try {
 #define GUARD_END                                                     \
   }                                                                   \
@@ -86,20 +99,48 @@ const char* check_config(const mpdo_config* cfg, bool need_n) {
   catch (...) {                                                       \
     return fail(MPDO_EDEVICE, "internal error");                      \
   }
+
+// Handle entry points: allocations go through the handle's allocator, and
+// an error once work has started makes the handle unusable.
+#define HANDLE_CHECK(h)                                                      \
+  if (!(h)) return fail(MPDO_EINVAL, "null handle");                         \
+  if ((h)->dead) return fail(MPDO_EDEVICE, "handle is unusable after an earlier error: " + (h)->why);
+#define GUARD_BEGIN_H(h)                                                     \
+  AllocScope alloc_scope_((h)->alloc.alloc ? &(h)->alloc : nullptr);         \
+  try {
+#define GUARD_END_H(h)                                                       \
+  }                                                                          \
+  catch (const Error& e) {                                                   \
+    return mark_dead((h), e.status, e.msg);                                  \
+  }                                                                          \
+  catch (const std::exception& e) {                                          \
+    return mark_dead((h), MPDO_EDEVICE, std::string("internal error: ") + e.what()); \
+  }                                                                          \
+  catch (...) {                                                              \
+    return mark_dead((h), MPDO_EDEVICE, "internal error");                   \
+  }
 }  // namespace
 
 struct mpdo_s {
   mpdo_config cfg;
+  DeviceAllocator alloc;
   hipStream_t st = nullptr;
   AnyEngine eng;
   std::vector<GateOp> pending;
   std::vector<char> busy;
-  bool dead = false;
+  bool dead = false;        // an error after device work started
+  std::string why;
 };
 
 struct mpdo_chan_s {
   Channel ch;
 };
+
+static mpdo_status mark_dead(mpdo_t h, int st, const std::string& msg) {
+  h->dead = true;
+  h->why = msg;
+  return fail(st, msg);
+}
 
 static mpdo_status flush_queue(mpdo_t h) {
   if (h->pending.empty()) return MPDO_OK;
@@ -108,6 +149,16 @@ static mpdo_status flush_queue(mpdo_t h) {
   std::fill(h->busy.begin(), h->busy.end(), 0);
   h->eng.run_sublayer(ops);
   return MPDO_OK;
+}
+
+// After a synchronising call: a numerical failure recorded on the device
+// (see mpdo.h) is an error of this call.
+static void check_health(mpdo_t h) {
+  const long long f = h->eng.failures();
+  if (f > 0)
+    throw Error{MPDO_ENOTCONV, std::to_string(f) +
+                                   " numerical failure(s) in truncations (non-finite weights, an eigenpair above its "
+                                   "residual bound, or a non-positive trace)"};
 }
 
 extern "C" {
@@ -120,9 +171,12 @@ mpdo_status mpdo_create(const mpdo_config* cfg, void* hip_stream, mpdo_t* out) {
   if (!out) return fail(MPDO_EINVAL, "null output pointer");
   *out = nullptr;
   if (const char* why = check_config(cfg, true)) return fail(MPDO_EINVAL, why);
-  GUARD_BEGIN
+  if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return fail(MPDO_EINVAL, "set both allocator hooks or none");
   std::unique_ptr<mpdo_s> h(new mpdo_s());
   h->cfg = *cfg;
+  h->alloc = hooks_of(cfg);
+  AllocScope scope(h->alloc.alloc ? &h->alloc : nullptr);
+  GUARD_BEGIN
   h->st = reinterpret_cast<hipStream_t>(hip_stream);
   const Config c = make_config(cfg);
   std::vector<int> nq(1, cfg->n);
@@ -229,8 +283,7 @@ mpdo_status mpdo_channel_destroy(mpdo_chan_t ch) {
 }
 
 static mpdo_status enqueue(mpdo_t h, const int32_t* sites, int32_t q, const double* U, mpdo_chan_t ch) {
-  if (!h) return fail(MPDO_EINVAL, "null handle");
-  if (h->dead) return fail(MPDO_EDEVICE, "handle is unusable after a device error");
+  HANDLE_CHECK(h)
   if (!sites) return fail(MPDO_EINVAL, "null sites");
   if (q < 1 || q > 3) return fail(MPDO_EINVAL, "q must be 1, 2 or 3");
   const int n = h->cfg.n;
@@ -245,7 +298,7 @@ static mpdo_status enqueue(mpdo_t h, const int32_t* sites, int32_t q, const doub
     for (int e = 0; e < 2 * d * d; ++e)
       if (!std::isfinite(U[e])) return fail(MPDO_EINVAL, "U is not finite");
   }
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   for (int t = 0; t < q; ++t)
     if (h->busy[sites[t]]) {
       flush_queue(h);
@@ -264,7 +317,7 @@ static mpdo_status enqueue(mpdo_t h, const int32_t* sites, int32_t q, const doub
   h->pending.push_back(g);
   for (int t = 0; t < q; ++t) h->busy[sites[t]] = 1;
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_apply_gate(mpdo_t h, const int32_t* sites, int32_t q, const double* U) {
@@ -278,23 +331,24 @@ mpdo_status mpdo_apply_channel(mpdo_t h, const int32_t* sites, int32_t q, const 
 }
 
 mpdo_status mpdo_flush(mpdo_t h) {
-  if (!h) return fail(MPDO_EINVAL, "null handle");
-  GUARD_BEGIN
+  HANDLE_CHECK(h)
+  GUARD_BEGIN_H(h)
   return flush_queue(h);
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_truncate(mpdo_t h, int32_t chi_max, int32_t kappa_max, double cutoff, double* discarded) {
-  if (!h) return fail(MPDO_EINVAL, "null handle");
+  HANDLE_CHECK(h)
   if (chi_max < 1 || chi_max > h->cfg.chi_max) return fail(MPDO_EINVAL, "chi_max out of range");
   if (kappa_max < 1 || kappa_max > h->cfg.kappa_max) return fail(MPDO_EINVAL, "kappa_max out of range");
   if (!(cutoff >= 0 && cutoff < 1)) return fail(MPDO_EINVAL, "cutoff must be in [0, 1)");
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   flush_queue(h);
   const double d = h->eng.truncate_sweep(0, chi_max, kappa_max, cutoff);
+  check_health(h);
   if (discarded) *discarded = d;
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 static mpdo_status expect_ops(mpdo_t h, const std::vector<std::vector<double>>& ops, double* out, bool raw) {
@@ -307,6 +361,7 @@ static mpdo_status expect_ops(mpdo_t h, const std::vector<std::vector<double>>& 
   h->eng.expect(inst, p, res.as<double>(), raw);
   hip_check(hipMemcpyAsync(out, res.p, sizeof(double) * 2 * ops.size(), hipMemcpyDeviceToHost, h->st), "result");
   hip_check(hipStreamSynchronize(h->st), "hipStreamSynchronize");
+  check_health(h);
   return MPDO_OK;
 }
 
@@ -320,12 +375,13 @@ static void pauli2x2(char c, double* o) {
 }
 
 mpdo_status mpdo_expect(mpdo_t h, const char* pauli, double* re, double* im) {
-  if (!h || !pauli) return fail(MPDO_EINVAL, "null argument");
+  HANDLE_CHECK(h)
+  if (!pauli) return fail(MPDO_EINVAL, "null argument");
   const int n = h->cfg.n;
   if ((int)std::strlen(pauli) != n) return fail(MPDO_EINVAL, "Pauli string length differs from n");
   for (int i = 0; i < n; ++i)
     if (!std::strchr("IXYZ", pauli[i]) || pauli[i] == 0) return fail(MPDO_EINVAL, "Pauli string must use IXYZ");
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   std::vector<std::vector<double>> ops(1, std::vector<double>(8 * n));
   for (int i = 0; i < n; ++i) pauli2x2(pauli[i], ops[0].data() + 8 * i);
   double out[2];
@@ -333,24 +389,26 @@ mpdo_status mpdo_expect(mpdo_t h, const char* pauli, double* re, double* im) {
   if (re) *re = out[0];
   if (im) *im = out[1];
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_expect_products(mpdo_t h, const double* ops, int32_t nops, double* out) {
-  if (!h || !ops || !out) return fail(MPDO_EINVAL, "null argument");
+  HANDLE_CHECK(h)
+  if (!ops || !out) return fail(MPDO_EINVAL, "null argument");
   if (nops < 1) return fail(MPDO_EINVAL, "nops must be >= 1");
   const int n = h->cfg.n;
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   std::vector<std::vector<double>> v(nops, std::vector<double>(8 * n));
   for (int k = 0; k < nops; ++k) std::memcpy(v[k].data(), ops + (size_t)8 * n * k, sizeof(double) * 8 * n);
   return expect_ops(h, v, out, false);
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_fidelity_ghz(mpdo_t h, double* f) {
-  if (!h || !f) return fail(MPDO_EINVAL, "null argument");
+  HANDLE_CHECK(h)
+  if (!f) return fail(MPDO_EINVAL, "null argument");
   const int n = h->cfg.n;
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   // Tr(|0..0><0..0| rho), Tr(|1..1><1..1| rho), Tr(|1..1><0..0| rho) = rho_{0..0,1..1}
   const double P0[8] = {1, 0, 0, 0, 0, 0, 0, 0}, P1[8] = {0, 0, 0, 0, 0, 0, 1, 0}, UP[8] = {0, 0, 0, 0, 1, 0, 0, 0};
   std::vector<std::vector<double>> ops(3, std::vector<double>(8 * n));
@@ -363,54 +421,108 @@ mpdo_status mpdo_fidelity_ghz(mpdo_t h, double* f) {
   expect_ops(h, ops, out, false);
   *f = 0.5 * (out[0] + out[2] + 2 * out[4]);
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_trace(mpdo_t h, double* tr) {
-  if (!h || !tr) return fail(MPDO_EINVAL, "null argument");
+  HANDLE_CHECK(h)
+  if (!tr) return fail(MPDO_EINVAL, "null argument");
   const int n = h->cfg.n;
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   std::vector<std::vector<double>> ops(1, std::vector<double>(8 * n));
   for (int i = 0; i < n; ++i) pauli2x2('I', ops[0].data() + 8 * i);
   double out[2];
   expect_ops(h, ops, out, true);
   *tr = out[0];
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_dims(mpdo_t h, int32_t* bonds, int32_t* inner, double* discarded) {
   if (!h) return fail(MPDO_EINVAL, "null handle");
-  GUARD_BEGIN
-  flush_queue(h);
+  const bool was_dead = h->dead;
+  GUARD_BEGIN_H(h)
+  if (!was_dead) flush_queue(h);   // an unusable handle reports its state as it is
   std::vector<int> b, k;
   double d;
   h->eng.dims(0, b, k, d);
   if (bonds) std::memcpy(bonds, b.data(), sizeof(int) * b.size());
   if (inner) std::memcpy(inner, k.data(), sizeof(int) * k.size());
   if (discarded) *discarded = d;
+  if (!was_dead) check_health(h);
+  return MPDO_OK;
+  GUARD_END_H(h)
+}
+
+mpdo_status mpdo_stats(mpdo_t h, mpdo_stats_t* out) {
+  if (!h || !out) return fail(MPDO_EINVAL, "null argument");
+  const bool was_dead = h->dead;
+  GUARD_BEGIN_H(h)
+  std::memset(out, 0, sizeof(*out));
+  double tr = std::nan("");
+  if (!was_dead) {
+    flush_queue(h);
+    const int n = h->cfg.n;
+    std::vector<std::vector<double>> ops(1, std::vector<double>(8 * n));
+    for (int i = 0; i < n; ++i) pauli2x2('I', ops[0].data() + 8 * i);
+    std::vector<int> inst(1, 0);
+    std::vector<const double*> p(1, ops[0].data());
+    DevBuf res;
+    res.alloc(sizeof(double) * 2);
+    h->eng.expect(inst, p, res.as<double>(), true);
+    double v[2];
+    hip_check(hipMemcpyAsync(v, res.p, sizeof(v), hipMemcpyDeviceToHost, h->st), "trace");
+    hip_check(hipStreamSynchronize(h->st), "hipStreamSynchronize");
+    tr = v[0];
+  }
+  const InstStats st = h->eng.stats(0);
+  std::vector<int> b, k;
+  double d;
+  h->eng.dims(0, b, k, d);
+  out->truncations = st.cuts;
+  out->failures = st.failures;
+  out->discarded = st.discarded;
+  out->max_discarded = st.max_discarded;
+  out->min_gap = st.min_gap;
+  out->trace = tr;
+  out->max_bond = b.empty() ? 1 : *std::max_element(b.begin(), b.end());
+  out->max_inner = k.empty() ? 1 : *std::max_element(k.begin(), k.end());
+  if (st.failures > 0 && !h->dead) {
+    h->dead = true;
+    h->why = "numerical failure recorded on the device";
+  }
+  return MPDO_OK;
+  GUARD_END_H(h)
+}
+
+mpdo_status mpdo_release_cached_memory(size_t* cached) {
+  GUARD_BEGIN
+  if (cached) *cached = cached_device_bytes();
+  release_cached_memory();
   return MPDO_OK;
   GUARD_END
 }
 
 mpdo_status mpdo_to_dense(mpdo_t h, double* rho) {
-  if (!h || !rho) return fail(MPDO_EINVAL, "null argument");
-  if (h->dead) return fail(MPDO_EDEVICE, "handle is unusable after a device error");
+  HANDLE_CHECK(h)
+  if (!rho) return fail(MPDO_EINVAL, "null argument");
   if (h->cfg.n > 12) return fail(MPDO_EINVAL, "dense state needs n <= 12");
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   flush_queue(h);
   h->eng.to_dense(0, rho);
+  check_health(h);
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_probabilities(mpdo_t h, const uint8_t* bits, int32_t nz, double* p) {
-  if (!h || !bits || !p) return fail(MPDO_EINVAL, "null argument");
+  HANDLE_CHECK(h)
+  if (!bits || !p) return fail(MPDO_EINVAL, "null argument");
   if (nz < 1) return fail(MPDO_EINVAL, "nz must be >= 1");
   const int n = h->cfg.n;
   for (long long e = 0; e < (long long)nz * n; ++e)
     if (bits[e] > 1) return fail(MPDO_EINVAL, "bits must be 0 or 1");
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   // <z| rho |z> / Tr rho: the product of the projectors |z_i><z_i|
   const double P0[8] = {1, 0, 0, 0, 0, 0, 0, 0}, P1[8] = {0, 0, 0, 0, 0, 0, 1, 0};
   std::vector<std::vector<double>> ops(nz, std::vector<double>(8 * n));
@@ -420,33 +532,36 @@ mpdo_status mpdo_probabilities(mpdo_t h, const uint8_t* bits, int32_t nz, double
   expect_ops(h, ops, out.data(), false);
   for (int z = 0; z < nz; ++z) p[z] = out[2 * (size_t)z];
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_sample(mpdo_t h, const double* u, int32_t nshots, uint8_t* bits, double* pz) {
-  if (!h || !u || !bits) return fail(MPDO_EINVAL, "null argument");
-  if (h->dead) return fail(MPDO_EDEVICE, "handle is unusable after a device error");
+  HANDLE_CHECK(h)
+  if (!u || !bits) return fail(MPDO_EINVAL, "null argument");
   if (nshots < 1) return fail(MPDO_EINVAL, "nshots must be >= 1");
   const int n = h->cfg.n;
   for (long long e = 0; e < (long long)nshots * n; ++e)
     if (!(u[e] >= 0.0 && u[e] < 1.0)) return fail(MPDO_EINVAL, "uniforms must lie in [0, 1)");
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   flush_queue(h);
   h->eng.sample(0, u, nshots, bits, pz);
+  check_health(h);
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 mpdo_status mpdo_bond_weights(mpdo_t h, int32_t b, double* out, int32_t cap, int32_t* len) {
-  if (!h || !out || !len) return fail(MPDO_EINVAL, "null argument");
+  HANDLE_CHECK(h)
+  if (!out || !len) return fail(MPDO_EINVAL, "null argument");
   if (b < 0 || b >= h->cfg.n - 1) return fail(MPDO_EINVAL, "bond out of range");
-  GUARD_BEGIN
+  GUARD_BEGIN_H(h)
   flush_queue(h);
   std::vector<double> v = h->eng.bond_weights(0, b);
+  check_health(h);
   *len = (int)v.size();
   std::memcpy(out, v.data(), sizeof(double) * std::min<size_t>(v.size(), cap));
   return MPDO_OK;
-  GUARD_END
+  GUARD_END_H(h)
 }
 
 }  // extern "C"
@@ -474,6 +589,8 @@ void batch_exec(const Config& c, const std::vector<int>& nq, const std::vector<s
     for (const auto& L : layers) eng.run_sublayer(L);
     if (!oinst.empty()) eng.expect(oinst, oops, out_dev);
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (const long long f = eng.failures())
+      throw Error{MPDO_ENOTCONV, std::to_string(f) + " numerical failure(s) in the batch's truncations"};
     return;
   }
   Upload dry;
@@ -482,12 +599,17 @@ void batch_exec(const Config& c, const std::vector<int>& nq, const std::vector<s
   if (!oinst.empty()) eng.expect(oinst, oops, out_dev, false, dry);
   eng.prepare_capture(dry);
   const size_t bytes = std::max<size_t>(dry.cursor, 256);
-  void* himg = nullptr;
-  hip_check(hipHostMalloc(&himg, bytes, hipHostMallocDefault), "hipHostMalloc");
+  size_t hbytes = 0;
+  void* himg = pinned_get(bytes, &hbytes);
   struct HostFree {
     void* p;
-    ~HostFree() { if (p) (void)hipHostFree(p); }
-  } guard{himg};
+    size_t n;
+    hipStream_t s;
+    ~HostFree() {
+      (void)hipStreamSynchronize(s);
+      pinned_put(p, n);
+    }
+  } guard{himg, hbytes, st};
   DevBuf dimg;
   dimg.alloc(bytes);
   hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -517,6 +639,8 @@ void batch_exec(const Config& c, const std::vector<int>& nq, const std::vector<s
   (void)hipGraphDestroy(graph);
   hip_check(le, "hipGraphLaunch");
   hip_check(se, "hipStreamSynchronize");
+  if (const long long f = eng.failures())
+    throw Error{MPDO_ENOTCONV, std::to_string(f) + " numerical failure(s) in the batch's truncations"};
 }
 }  // namespace
 
@@ -561,6 +685,9 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
     }
   }
   if (total_obs > 0 && !out_dev) return fail(MPDO_EINVAL, "null out_dev");
+  if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return fail(MPDO_EINVAL, "set both allocator hooks or none");
+  const DeviceAllocator hooks = hooks_of(cfg);
+  AllocScope scope(hooks.alloc ? &hooks : nullptr);
   GUARD_BEGIN
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   // fixed gates: a 4x4 slot and its compact top-left 2x2 per entry
@@ -820,4 +947,18 @@ extern "C" mpdo_status mpdo_test_eigh(int32_t n, int32_t kvec, const double* A, 
   if (ran != 1) return fail(MPDO_EDEVICE, "eigensolver kernel did not run");
   return MPDO_OK;
   GUARD_END
+}
+
+extern "C" mpdo_status mpdo_test_eig_residual_bound(double rtol) {
+  if (!std::isfinite(rtol)) return fail(MPDO_EINVAL, "rtol must be finite");
+  GUARD_BEGIN
+  hip_check(set_eig_residual_bound(rtol), "hipMemcpyToSymbol");
+  return MPDO_OK;
+  GUARD_END
+}
+
+extern "C" mpdo_status mpdo_test_fail_next_update(int32_t status) {
+  if (status < 0 || status > MPDO_EUNSUPPORTED) return fail(MPDO_EINVAL, "unknown status");
+  inject_update_failure(status);
+  return MPDO_OK;
 }

@@ -78,6 +78,17 @@ struct EigDesc {
   int upad;
 };
 
+// Per-site record of the truncations applied to a site (device, doubles):
+// summed discarded weight, largest single discarded weight, number of
+// truncations, smallest relative gap eta_{r-1}/eta_r - 1 at a cut that
+// dropped weight, numerical failures (non-finite weights, an eigensolver
+// residual above its bound, a non-positive or non-finite trace).
+enum StatField : int { ST_DISC = 0, ST_MAXD = 1, ST_CUTS = 2, ST_GAP = 3, ST_FAIL = 4, ST_W = 5 };
+
+// Relative floor of the Gram eigenvalues the library keeps (its FP64 Gram
+// matrices resolve eigenvalues to about 1e-15 of the largest; below this
+// floor an eigenvector is noise).  A truncation with cutoff >= N * 1e-13
+// (N the Gram size, <= 1024) cannot be changed by the floor.
 constexpr double EIG_FLOOR = 1e-13;
 constexpr int EIG_NMAX = 1024;
 constexpr int EIG_THREADS = 512;

@@ -34,6 +34,11 @@
 
 namespace mpdo {
 
+// Residual bound of an eigenpair relative to ||T||, and a host-set
+// override (0: the default; tests force a failure with a negative bound).
+constexpr double EIG_RESIDUAL_BOUND = 1e-9;
+__device__ double g_eig_rtol = 0.0;
+
 namespace {
 constexpr int NT = EIG_THREADS;
 constexpr int NW = NT / 64;
@@ -207,6 +212,8 @@ __device__ void fused_pass(cpx<double>* __restrict__ A, int n, int c0, int base,
 template <int NTH, class SH>
 __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   const int tid = threadIdx.x;
+  __shared__ int s_resbad;  // an eigenpair failed its residual bound
+  if (tid == 0) s_resbad = 0;
   // ---- multisection for the leading kb = kvec + 1 eigenvalues ----
   // A group of L lanes (inside one wave) brackets one eigenvalue;
   // each round evaluates L Sturm counts at equally spaced interior points
@@ -279,6 +286,7 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
     double* __restrict__ LL = U2 + (long long)n * ks;
     double* __restrict__ PV = LL + (long long)n * ks;
     const double pivtol = 2.2204460492503131e-16 * fmax(tnorm, 1e-300);
+  const double rtol = g_eig_rtol != 0.0 ? g_eig_rtol : EIG_RESIDUAL_BOUND;
     for (int j = tid; j < kvec; j += NTH) {
       if (j >= kz) {
         for (int i = 0; i < n; ++i) Z[(long long)i * n + j] = mk(0.0, 0.0);
@@ -377,9 +385,25 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
       }
       const double s = scale / sqrt(nn);
       for (int i = 0; i < n; ++i) Z[(long long)i * n + j] = mk(X[(long long)i * ks + j] * s, 0.0);
+      // residual of the tridiagonal eigenpair: ||(T - lambda) z|| <= rtol ||T||
+      // (inverse iteration from a bisected eigenvalue reaches about eps ||T||)
+      double rr = 0, zp = 0, zc = Z[j].re;
+      for (int i = 0; i < n; ++i) {
+        const double zn = i + 1 < n ? Z[(long long)(i + 1) * n + j].re : 0.0;
+        double t = (S.d[i] - lam) * zc;
+        if (i > 0) t += S.e[i - 1] * zp;
+        if (i + 1 < n) t += S.e[i] * zn;
+        rr += t * t;
+        zp = zc;
+        zc = zn;
+      }
+      if (!(sqrt(rr) <= rtol * tnorm)) s_resbad = 1;
     }
   }
   __syncthreads();
+  // a failed bound or a non-finite spectrum marks the result by a NaN trace,
+  // which the consumers of the eigenvalues count as a numerical failure
+  if (tid == 0 && dsc.trace && (s_resbad || !(tnorm < 1e300))) *dsc.trace = __builtin_nan("");
   // ---- 5. Gram-Schmidt (twice) inside clusters of close eigenvalues ----
   // Inverse iteration leaves vectors of eigenvalues closer than about
   // eps ||T|| / gap non-orthogonal, so a cluster joins eigenvalues whose gap
@@ -1353,6 +1377,10 @@ __global__ __launch_bounds__(NT) void k_heev_big(const EigDesc* __restrict__ des
   if (!d.active || d.n <= 512 || d.n > EIG_NMAX) return;
   heev_core<false>(d, reinterpret_cast<cpx<double>*>(d.work), S);
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
+}
+
+hipError_t set_eig_residual_bound(double rtol) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_eig_rtol), &rtol, sizeof(double));
 }
 
 void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hipStream_t s) {

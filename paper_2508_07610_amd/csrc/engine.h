@@ -14,19 +14,51 @@ struct Error {
   std::string msg;
 };
 
+// Makes the next run_sublayer of any engine throw Error{status} before it
+// launches anything (tests of the error paths; 0 cancels).
+void inject_update_failure(int status);
+
 void hip_check(hipError_t e, const char* what);
 // Records the message returned by mpdo_last_error() and passes the status through.
 int set_last_error(int status, const std::string& msg);
 
-// Device allocation owned by the runtime (freed on destruction).
+// Where device memory comes from.  A caller may supply an allocator (the
+// alloc/free hooks of mpdo_config, e.g. a framework's caching allocator);
+// otherwise blocks come from the library's own cache: a freed block is kept
+// per device and handed to the next request it fits (at most twice its
+// size), so repeated runs of the same shapes allocate nothing after the
+// first.  mpdo_release_cached_memory() returns the cache to the driver.
+struct DeviceAllocator {
+  void* (*alloc)(size_t bytes, void* ctx) = nullptr;
+  void (*free)(void* ptr, void* ctx) = nullptr;
+  void* ctx = nullptr;
+};
+// The allocator of the running entry point (set by an AllocScope; none: the cache).
+const DeviceAllocator* current_allocator();
+struct AllocScope {
+  const DeviceAllocator* prev;
+  explicit AllocScope(const DeviceAllocator* a);
+  ~AllocScope();
+};
+void release_cached_memory();
+size_t cached_device_bytes();
+// Pinned host blocks from the same kind of cache.
+void* pinned_get(size_t n, size_t* got);
+void pinned_put(void* p, size_t n);
+
+// Device allocation owned by the runtime (freed on destruction, through the
+// allocator it came from).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  DeviceAllocator from;   // hooks of the allocation (alloc == null: the cache)
+  int device = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf();
   void alloc(size_t n);   // (re)allocates when n > bytes; contents are lost
+  void release();
   template <typename X> X* as() const { return reinterpret_cast<X*>(p); }
 };
 
@@ -37,6 +69,11 @@ struct HostStage {
   hipEvent_t done = nullptr;
   ~HostStage();
   void* get(size_t n);    // waits until the previous upload finished
+};
+
+struct InstStats {
+  double discarded = 0, max_discarded = 0, min_gap = 0;
+  long long cuts = 0, failures = 0;
 };
 
 struct Channel {
@@ -102,6 +139,12 @@ template <typename T> class Engine {
   double truncate_sweep(int b, int chi_max, int kap_max, double cut);
 
   void dims(int b, std::vector<int>& bonds, std::vector<int>& inner, double& disc);
+  // truncation statistics of instance b (reads the per-site records)
+  InstStats stats(int b);
+  // numerical failures recorded on the device, summed over all instances
+  long long failures();
+  // site tensor of instance b, site i (current buffer): for host-side tests
+  void* site_ptr(int b, int i) { return site(b, i, par_[soff_[b] + i]); }
   std::vector<double> bond_weights(int b, int bond);
   // rho of instance b (n <= 12) as 2^n x 2^n complex doubles into `host`
   void to_dense(int b, double* host);
@@ -137,7 +180,7 @@ template <typename T> class Engine {
   double* lam_ptr(int b, int bond) const { return lam_.as<double>() + (size_t)(soff_[b] + bond) * cfg_.chi_max; }
   double* lam2_ptr(int b, int bond) const { return lam2_.as<double>() + (size_t)(soff_[b] + bond) * cfg_.chi_max; }
   const double* laml2(int b, int i) const { return i == 0 ? one_.as<double>() : lam2_ptr(b, i - 1); }
-  double* disc_ptr(int b, int i) const { return disc_.as<double>() + soff_[b] + i; }
+  double* disc_ptr(int b, int i) const { return disc_.as<double>() + (size_t)(soff_[b] + i) * ST_W; }
 
   // force: truncate the inner index even for unitary ops; tpo overrides the
   // truncation parameters of the configuration.

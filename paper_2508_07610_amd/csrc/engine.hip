@@ -9,8 +9,11 @@
 // sites are therefore independent and a whole sublayer runs as one launch
 // sequence over all its gates (and all instances of a batch).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 
 #include "engine.h"
@@ -22,40 +25,145 @@ void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error{4 /*MPDO_EDEVICE*/, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-DevBuf::~DevBuf() {
-  if (p) (void)hipFree(p);
+namespace {
+thread_local const DeviceAllocator* t_alloc = nullptr;
+
+// Free blocks of the library's caches: device blocks per device, pinned
+// host blocks in one list, keyed by size.
+constexpr int MAX_DEV = 64;
+std::mutex g_cache_mu;
+std::multimap<size_t, void*> g_dev_free[MAX_DEV];
+std::multimap<size_t, void*> g_pin_free;
+
+void* take_fitting(std::multimap<size_t, void*>& m, size_t n, size_t* got) {
+  auto it = m.lower_bound(n);
+  if (it == m.end() || it->first > 2 * n + (1 << 20)) return nullptr;
+  void* p = it->second;
+  *got = it->first;
+  m.erase(it);
+  return p;
 }
+}  // namespace
+
+const DeviceAllocator* current_allocator() { return t_alloc; }
+AllocScope::AllocScope(const DeviceAllocator* a) : prev(t_alloc) { t_alloc = (a && a->alloc) ? a : nullptr; }
+AllocScope::~AllocScope() { t_alloc = prev; }
+
+void release_cached_memory() {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (int d = 0; d < MAX_DEV; ++d) {
+    if (g_dev_free[d].empty()) continue;
+    (void)hipSetDevice(d);
+    for (auto& kv : g_dev_free[d]) (void)hipFree(kv.second);
+    g_dev_free[d].clear();
+  }
+  (void)hipSetDevice(cur);
+  for (auto& kv : g_pin_free) (void)hipHostFree(kv.second);
+  g_pin_free.clear();
+}
+
+size_t cached_device_bytes() {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  size_t t = 0;
+  for (int d = 0; d < MAX_DEV; ++d)
+    for (auto& kv : g_dev_free[d]) t += kv.first;
+  return t;
+}
+
+void* pinned_get(size_t n, size_t* got) {
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    if (void* p = take_fitting(g_pin_free, n, got)) return p;
+  }
+  void* p = nullptr;
+  hip_check(hipHostMalloc(&p, n, hipHostMallocDefault), "hipHostMalloc");
+  *got = n;
+  return p;
+}
+
+void pinned_put(void* p, size_t n) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  g_pin_free.emplace(n, p);
+}
+
+void DevBuf::release() {
+  if (!p) return;
+  // the block may still be read by queued work: wait for the device before
+  // it can be handed out again (hipFree would wait the same way)
+  (void)hipDeviceSynchronize();
+  if (from.alloc) {
+    if (from.free) from.free(p, from.ctx);
+  } else if (device >= 0 && device < MAX_DEV) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    g_dev_free[device].emplace(bytes, p);
+  } else {
+    (void)hipFree(p);
+  }
+  p = nullptr;
+  bytes = 0;
+}
+
+DevBuf::~DevBuf() { release(); }
 
 void DevBuf::alloc(size_t n) {
   if (n <= bytes && p) return;
-  if (p) {
-    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    hip_check(hipFree(p), "hipFree");
-    p = nullptr;
-    bytes = 0;
-  }
+  release();
   if (n == 0) n = 256;
+  n = (n + 255) & ~size_t(255);
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  const DeviceAllocator* a = current_allocator();
+  if (a) {
+    p = a->alloc(n, a->ctx);
+    if (!p) throw Error{3 /*MPDO_ENOMEM*/, "caller allocator refused " + std::to_string(n) + " bytes"};
+    from = *a;
+    device = dev;
+    bytes = n;
+    return;
+  }
+  from = DeviceAllocator{};
+  device = dev;
+  if (dev >= 0 && dev < MAX_DEV) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    size_t got = 0;
+    if (void* q = take_fitting(g_dev_free[dev], n, &got)) {
+      p = q;
+      bytes = got;
+      return;
+    }
+  }
   if (hipMalloc(&p, n) != hipSuccess) {
     (void)hipGetLastError();
     p = nullptr;
-    throw Error{3 /*MPDO_ENOMEM*/, "device allocation of " + std::to_string(n) + " bytes failed"};
+    release_cached_memory();   // give the cache back to the driver and try once more
+    if (hipMalloc(&p, n) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw Error{3 /*MPDO_ENOMEM*/, "device allocation of " + std::to_string(n) + " bytes failed"};
+    }
   }
   bytes = n;
 }
 
 HostStage::~HostStage() {
-  if (done) (void)hipEventDestroy(done);
-  if (p) (void)hipHostFree(p);
+  if (done) {
+    (void)hipEventSynchronize(done);
+    (void)hipEventDestroy(done);
+  }
+  pinned_put(p, bytes);
 }
 
 void* HostStage::get(size_t n) {
   if (done) hip_check(hipEventSynchronize(done), "hipEventSynchronize");
   else hip_check(hipEventCreateWithFlags(&done, hipEventDisableTiming), "hipEventCreate");
   if (n > bytes) {
-    if (p) hip_check(hipHostFree(p), "hipHostFree");
-    size_t cap = std::max<size_t>(n, 1 << 20);
-    hip_check(hipHostMalloc(&p, cap, hipHostMallocDefault), "hipHostMalloc");
-    bytes = cap;
+    pinned_put(p, bytes);
+    p = nullptr;
+    bytes = 0;
+    p = pinned_get(std::max<size_t>(n, 1 << 20), &bytes);
   }
   return p;
 }
@@ -116,7 +224,8 @@ Engine<T>::Engine(const Config& cfg, const std::vector<int>& nq, hipStream_t s) 
   std::vector<int> d(nsites_ + nq_.size() + nsites_, 1);
   dims_.alloc(d.size() * sizeof(int));
   hip_check(hipMemcpyAsync(dims_.p, d.data(), d.size() * sizeof(int), hipMemcpyHostToDevice, st_), "copy");
-  std::vector<double> z(nsites_, 0.0);
+  std::vector<double> z((size_t)nsites_ * ST_W, 0.0);
+  for (int i = 0; i < nsites_; ++i) z[(size_t)i * ST_W + ST_GAP] = 1e300;
   disc_.alloc(z.size() * sizeof(double));
   hip_check(hipMemcpyAsync(disc_.p, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice, st_), "copy");
   hip_check(hipStreamSynchronize(st_), "hipStreamSynchronize");
@@ -171,7 +280,15 @@ template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& op
   run_sublayer(ops, up);
 }
 
+namespace {
+std::atomic<int> g_fail_next{0};
+}
+void inject_update_failure(int status) { g_fail_next.store(status); }
+
 template <typename T> void Engine<T>::run_sublayer(const std::vector<GateOp>& ops, Upload& up) {
+  if (!ops.empty()) {
+    if (const int f = g_fail_next.exchange(0)) throw Error{f, "injected failure before a sublayer"};
+  }
   std::vector<const GateOp*> one, two, three;
   for (const GateOp& g : ops) {
     if (g.q == 1) one.push_back(&g);
@@ -564,6 +681,7 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
       c.site = s;
       c.active = s < nb && s >= fst[it] && s <= lst[it];
       c.trace_idx = raw ? -1 : items[it].trace;
+      c.stat = rec ? disc_ptr(b, 0) : nullptr;
       if (rec) {
         c.Ecur = Lp(it, s);
         c.Enext = Lp(it, s + 1);
@@ -640,15 +758,42 @@ template <typename T>
 void Engine<T>::dims(int b, std::vector<int>& bonds, std::vector<int>& inner, double& disc) {
   const int nb = nq_[b];
   std::vector<int> chi(nb + 1), kap(nb);
-  std::vector<double> d(nb);
+  std::vector<double> d((size_t)nb * ST_W);
   hip_check(hipMemcpyAsync(chi.data(), chi_ptr(b, 0), sizeof(int) * (nb + 1), hipMemcpyDeviceToHost, st_), "dims");
   hip_check(hipMemcpyAsync(kap.data(), kap_ptr(b, 0), sizeof(int) * nb, hipMemcpyDeviceToHost, st_), "dims");
-  hip_check(hipMemcpyAsync(d.data(), disc_ptr(b, 0), sizeof(double) * nb, hipMemcpyDeviceToHost, st_), "dims");
+  hip_check(hipMemcpyAsync(d.data(), disc_ptr(b, 0), sizeof(double) * nb * ST_W, hipMemcpyDeviceToHost, st_), "dims");
   hip_check(hipStreamSynchronize(st_), "hipStreamSynchronize");
   bonds.assign(chi.begin() + 1, chi.end() - 1);
   inner = kap;
   disc = 0;
-  for (double x : d) disc += x;
+  for (int i = 0; i < nb; ++i) disc += d[(size_t)i * ST_W + ST_DISC];
+}
+
+template <typename T> InstStats Engine<T>::stats(int b) {
+  const int nb = nq_[b];
+  std::vector<double> d((size_t)nb * ST_W);
+  hip_check(hipMemcpyAsync(d.data(), disc_ptr(b, 0), sizeof(double) * nb * ST_W, hipMemcpyDeviceToHost, st_), "stats");
+  hip_check(hipStreamSynchronize(st_), "hipStreamSynchronize");
+  InstStats r;
+  r.min_gap = 1e300;
+  for (int i = 0; i < nb; ++i) {
+    const double* x = &d[(size_t)i * ST_W];
+    r.discarded += x[ST_DISC];
+    r.max_discarded = std::max(r.max_discarded, x[ST_MAXD]);
+    r.cuts += (long long)x[ST_CUTS];
+    r.min_gap = std::min(r.min_gap, x[ST_GAP]);
+    r.failures += (long long)x[ST_FAIL];
+  }
+  return r;
+}
+
+template <typename T> long long Engine<T>::failures() {
+  std::vector<double> d((size_t)nsites_ * ST_W);
+  hip_check(hipMemcpyAsync(d.data(), disc_.p, sizeof(double) * d.size(), hipMemcpyDeviceToHost, st_), "stats");
+  hip_check(hipStreamSynchronize(st_), "hipStreamSynchronize");
+  long long f = 0;
+  for (int i = 0; i < nsites_; ++i) f += (long long)d[(size_t)i * ST_W + ST_FAIL];
+  return f;
 }
 
 template <typename T> std::vector<double> Engine<T>::bond_weights(int b, int bond) {

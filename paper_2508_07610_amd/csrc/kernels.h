@@ -26,6 +26,10 @@ void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int ni
 // Batched Hermitian eigensolver (FP64, Householder tridiagonalisation,
 // multisection, inverse iteration), one workgroup per problem; maxn bounds
 // every item's n.  d_status[item] is set to 1 when the item's workgroup ran.
+// An eigenpair whose tridiagonal residual ||(T - lambda) z|| exceeds
+// 1e-9 ||T||, or a non-finite spectrum, sets the item's trace to NaN.
 void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hipStream_t s);
+// Overrides the residual bound on the current device (0 restores 1e-9).
+hipError_t set_eig_residual_bound(double rtol);
 
 }  // namespace mpdo

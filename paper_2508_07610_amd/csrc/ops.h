@@ -28,7 +28,7 @@ template <typename T> struct Ctx1 {
   const int* chil;
   const int* chir;
   int* kap;
-  double* disc;
+  double* disc;           // the site's truncation record (StatField)
   double* G;              // m x 2 x 2 complex: G_j = K_j U
   double* H;              // (2k)^2 Gram over (l, r)
   double* Gam;            // (k m)^2
@@ -57,7 +57,7 @@ template <typename T> struct Ctx2 {
   const int* chir;
   int* kap1;
   const int* kap2;
-  double* disc;
+  double* disc;           // the site's truncation record (StatField)
   int* scratch;           // [0] = kappa', [1] = r_F
   double* G;              // m x 4 x 4
   double* H;              // (4 k1)^2
@@ -134,7 +134,7 @@ template <typename T> struct Ctx3 {
   const int* kap1;
   int* kap2;
   const int* kap3;
-  double* disc;
+  double* disc;           // the site's truncation record (StatField)
   int* scratch;           // [0] kappa', [1] r_N, [2] r_3, [3] bond i, [4] bond i+1
   double* kept;           // [0] kept weight at bond i, [1] at bond i+1
   double* G;              // m x 8 x 8
@@ -188,7 +188,7 @@ template <typename T> struct CtxS {
   const int* kapn;        // the neighbour's inner dimension
   double* lam;            // weights of the shared bond (pass 1)
   double* lam2;
-  double* disc;
+  double* disc;           // the site's truncation record (StatField)
   double* ev;
   double* evec;
   cpx<T>* P1;             // pass 0: V D^(-1/2);  pass 1: U_r S_r^(-1)
@@ -215,6 +215,8 @@ template <typename T> struct CtxT {
   const int* chif;        // bond dimension of Efinal and Rfin
   GemmDesc* d1;
   GemmDesc* d2;
+  double* stat;           // trace item: the instance's first site record (a
+                          // non-finite or non-positive trace counts as a failure)
   int site, active, trace_idx, pad;
 };
 

@@ -93,6 +93,27 @@ __device__ int select_rank(const double* eta, int kb, int n, double W, int maxd,
   return r;
 }
 
+// Records one truncation in a site's statistics (see StatField): the
+// discarded fraction, the relative gap at the cut when weight was dropped,
+// and a failure when the weights are not finite (a NaN in the state, or an
+// eigensolver that marked its result by a non-finite trace).
+__device__ void record_cut(double* st, const double* eta, int r, int kb, double tot, double kept) {
+  if (!(tot >= 0 && tot < 1e300) || !(kept > 0 && kept < 1e300)) {
+    st[ST_FAIL] += 1.0;
+    return;
+  }
+  const double d = tot > 0 ? (tot - kept) / tot : 0.0;
+  st[ST_DISC] += d;
+  st[ST_MAXD] = fmax(st[ST_MAXD], d);
+  st[ST_CUTS] += 1.0;
+  if (r < kb && eta[r] > 0) st[ST_GAP] = fmin(st[ST_GAP], eta[r - 1] / eta[r] - 1.0);
+}
+
+// A basis eigendecomposition (no truncation): its trace must be finite.
+__device__ inline void check_basis(double* st, double trace) {
+  if (!(trace >= 0 && trace < 1e300)) st[ST_FAIL] += 1.0;
+}
+
 __device__ inline void clear_desc(GemmDesc& d) {
   d.w = nullptr; d.kstride = 0; d.sA = d.sB = d.sC = 0;
   d.M = d.N = d.K = 0; d.lda = d.ldb = d.ldc = 0; d.kinner = 0; d.wdiv = 1;
@@ -180,7 +201,7 @@ __global__ __launch_bounds__(GT) void k_q1_select(Ctx1<T>* ctxs, TruncParams tp)
       const int kp = select_rank(c.ev, min(ng, tp.kap_max + 1), ng, c.ev[ng], tp.kap_max, tp.kap_cut, &kept, &tot);
       s_kp = kp;
       s_scale = 1.0 / sqrt(kept);
-      if (tot > 0) *c.disc += (tot - kept) / tot;
+      record_cut(c.disc, c.ev, kp, min(ng, tp.kap_max + 1), tot, kept);
     }
   }
   __syncthreads();
@@ -268,6 +289,7 @@ __global__ __launch_bounds__(GT) void k_q2_select_e(Ctx2<T>* ctxs, int splitsH, 
     const double e0 = c.evE[0];
     for (int b = 0; b < nE; ++b) rF += (c.evE[b] > tp.tolE * e0) ? 1 : 0;
     if (rF < 1) rF = 1;
+    check_basis(c.disc, c.evE[nE]);
     s_rF = rF;
     c.scratch[1] = rF;
   }
@@ -381,7 +403,7 @@ __global__ __launch_bounds__(GT) void k_q2_select_g(Ctx2<T>* ctxs, int splitsC, 
       const int kp = select_rank(c.evG, min(ng, tp.kap_max + 1), ng, c.evG[ng], tp.kap_max, tp.kap_cut, &kept, &tot);
       s_kp = kp;
       s_scale = 1.0 / sqrt(kept);
-      if (tot > 0) *c.disc += (tot - kept) / tot;
+      record_cut(c.disc, c.evG, kp, min(ng, tp.kap_max + 1), tot, kept);
     }
     c.scratch[0] = s_kp;
   }
@@ -449,7 +471,7 @@ __global__ __launch_bounds__(GT) void k_q2_select_b(Ctx2<T>* ctxs, TruncParams t
     const int r = select_rank(c.evC, min(n, tp.chi_max + 1), n, c.evC[n], tp.chi_max, tp.svd_cut, &kept, &tot);
     s_r = r;
     s_scale = 1.0 / sqrt(kept);
-    if (tot > 0) *c.disc += (tot - kept) / tot;
+    record_cut(c.disc, c.evC, r, min(n, tp.chi_max + 1), tot, kept);
   }
   __syncthreads();
   const int r = s_r;
@@ -581,6 +603,8 @@ __global__ __launch_bounds__(GT) void k_q3_sel_env(Ctx3<T>* ctxs, int splitsH, d
     for (int b = 0; b < nE; ++b) r3 += (c.evE3[b] > floor * c.evE3[0]) ? 1 : 0;
     s_r[0] = rN < 1 ? 1 : rN;
     s_r[1] = r3 < 1 ? 1 : r3;
+    check_basis(c.disc, c.evN[nN]);
+    check_basis(c.disc, c.evE3[nE]);
     c.scratch[1] = s_r[0];
     c.scratch[2] = s_r[1];
   }
@@ -693,7 +717,7 @@ __global__ __launch_bounds__(GT) void k_q3_sel_h(Ctx3<T>* ctxs, int splitsC, Tru
       const int kp = select_rank(c.evG, min(n, tp.kap_max + 1), n, c.evG[n], tp.kap_max, tp.kap_cut, &kept, &tot);
       s_kp = kp;
       s_scale = 1.0 / sqrt(kept);
-      if (tot > 0) *c.disc += (tot - kept) / tot;
+      record_cut(c.disc, c.evG, kp, min(n, tp.kap_max + 1), tot, kept);
     }
     c.scratch[0] = s_kp;
   }
@@ -760,7 +784,7 @@ __global__ __launch_bounds__(GT) void k_q3_sel_1(Ctx3<T>* ctxs, int splitsC, Tru
     const int r = select_rank(c.ev1, min(n, tp.chi_max + 1), n, c.ev1[n], tp.chi_max, tp.svd_cut, &kept, &tot);
     s_r = r;
     s_kept = kept;
-    if (tot > 0) *c.disc += (tot - kept) / tot;
+    record_cut(c.disc, c.ev1, r, min(n, tp.chi_max + 1), tot, kept);
     c.scratch[3] = r;
     c.kept[0] = kept;
   }
@@ -857,7 +881,7 @@ __global__ __launch_bounds__(GT) void k_q3_sel_2(Ctx3<T>* ctxs, TruncParams tp) 
     const int r = select_rank(c.ev2, min(n, tp.chi_max + 1), n, c.ev2[n], tp.chi_max, tp.svd_cut, &kept, &tot);
     s_r = r;
     s_kept = kept;
-    if (tot > 0) *c.disc += (tot - kept) / tot;
+    record_cut(c.disc, c.ev2, r, min(n, tp.chi_max + 1), tot, kept);
     c.scratch[4] = r;
     c.kept[1] = kept;
   }
@@ -972,13 +996,14 @@ __global__ __launch_bounds__(GT) void k_sw_select(CtxS<T>* ctxs, TruncParams tp)
       int rr = 0;
       while (rr < n && c.ev[rr] > EIG_FLOOR * c.ev[0] && c.ev[0] > 0) ++rr;
       s_r = rr < 1 ? 1 : rr;
+      check_basis(c.disc, c.ev[n]);
       s_kept = 1.0;
     } else {
       double kept, tot;
       const int rr = select_rank(c.ev, min(n, tp.chi_max + 1), n, c.ev[n], tp.chi_max, tp.svd_cut, &kept, &tot);
       s_r = rr;
       s_kept = kept;
-      if (tot > 0) *c.disc += (tot - kept) / tot;
+      record_cut(c.disc, c.ev, rr, min(n, tp.chi_max + 1), tot, kept);
     }
   }
   __syncthreads();
@@ -1169,6 +1194,7 @@ __global__ __launch_bounds__(256) void k_transfer_finish(CtxT<T>* ctxs, double* 
     b = sim[0];
   }
   if (threadIdx.x == 0) {
+    if (c.stat && !(a > 0 && a < 1e300)) c.stat[ST_FAIL] += 1.0;  // trace item (NaN fails too)
     double ta = 1.0;  // trace_idx < 0: raw value
     if (c.trace_idx >= 0) ta = (double)ctxs[c.trace_idx].Efinal[0].re;
     out[2 * it] = a / ta;

@@ -24,6 +24,7 @@ EXPORTED = (
     "mpdo_channel_info", "mpdo_channel_destroy", "mpdo_apply_gate", "mpdo_apply_channel", "mpdo_flush",
     "mpdo_truncate", "mpdo_expect", "mpdo_expect_products", "mpdo_fidelity_ghz", "mpdo_trace", "mpdo_dims",
     "mpdo_bond_weights", "mpdo_to_dense", "mpdo_probabilities", "mpdo_sample", "mpdo_batch_run",
+    "mpdo_stats", "mpdo_release_cached_memory",
 )
 
 
@@ -33,10 +34,60 @@ class MPDOError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class mpdo_config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("chi_max", ctypes.c_int32), ("kappa_max", ctypes.c_int32),
                 ("max_kraus", ctypes.c_int32), ("svd_cutoff", ctypes.c_double),
-                ("kappa_cutoff", ctypes.c_double), ("prec", ctypes.c_int32)]
+                ("kappa_cutoff", ctypes.c_double), ("prec", ctypes.c_int32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+
+
+class mpdo_stats_t(ctypes.Structure):
+    _fields_ = [("truncations", ctypes.c_int64), ("failures", ctypes.c_int64), ("discarded", ctypes.c_double),
+                ("max_discarded", ctypes.c_double), ("min_gap", ctypes.c_double), ("trace", ctypes.c_double),
+                ("max_bond", ctypes.c_int32), ("max_inner", ctypes.c_int32)]
+
+
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator, through
+    the allocator hooks of mpdo_config: handles and batch runs then draw from
+    (and return to) the same pool as the caller's tensors.  Keep the object
+    alive while any handle made with it exists."""
+
+    def __init__(self, stream=None):
+        import torch
+        self._torch = torch
+        self._stream = stream
+        dev = torch.cuda.current_device()
+
+        def _alloc(nbytes, _ctx):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, self._stream))
+            except Exception:
+                return None
+
+        def _free(ptr, _ctx):
+            if ptr:
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+    def apply(self, cfg: "mpdo_config") -> None:
+        cfg.alloc = self.alloc
+        cfg.free = self.free
+        cfg.alloc_ctx = None
+
+
+def release_cached_memory() -> int:
+    """Return the library's cache of released device blocks to the driver;
+    returns the bytes it held."""
+    n = ctypes.c_size_t()
+    check(lib().mpdo_release_cached_memory(ctypes.byref(n)))
+    return n.value
 
 
 class mpdo_op(ctypes.Structure):
@@ -84,6 +135,8 @@ def lib() -> ctypes.CDLL:
         "mpdo_trace": [vp, pd],
         "mpdo_dims": [vp, pi, pi, pd],
         "mpdo_bond_weights": [vp, i32, pd, i32, pi],
+        "mpdo_stats": [vp, ctypes.POINTER(mpdo_stats_t)],
+        "mpdo_release_cached_memory": [ctypes.POINTER(ctypes.c_size_t)],
         "mpdo_to_dense": [vp, pd],
         "mpdo_probabilities": [vp, ctypes.POINTER(ctypes.c_uint8), i32, pd],
         "mpdo_sample": [vp, pd, i32, ctypes.POINTER(ctypes.c_uint8), pd],
@@ -181,9 +234,13 @@ class MPDO:
     """One MPDO state on the GPU (see include/mpdo.h)."""
 
     def __init__(self, n: int, chi_max: int, kappa_max: int, max_kraus: int = 16,
-                 svd_cutoff: float = 1e-14, kappa_cutoff: float = 1e-14, prec: int = C128, stream=None):
+                 svd_cutoff: float = 1e-14, kappa_cutoff: float = 1e-14, prec: int = C128, stream=None,
+                 allocator: Optional[TorchAllocator] = None):
         self.n = n
         self.cfg = mpdo_config(n, chi_max, kappa_max, max_kraus, svd_cutoff, kappa_cutoff, prec)
+        self._allocator = allocator
+        if allocator is not None:
+            allocator.apply(self.cfg)
         h = ctypes.c_void_p()
         check(lib().mpdo_create(ctypes.byref(self.cfg), stream_handle(stream), ctypes.byref(h)))
         self._h = h
@@ -280,6 +337,14 @@ class MPDO:
                                 _dptr(pz)))
         return bits, pz
 
+    def stats(self) -> dict:
+        """Truncation statistics (mpdo_stats): truncations, failures, summed
+        and largest discarded weight, smallest gap at a cut, Tr(rho), largest
+        bond and inner dimension."""
+        st = mpdo_stats_t()
+        check(lib().mpdo_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in mpdo_stats_t._fields_}
+
     def bond_weights(self, bond: int) -> np.ndarray:
         cap = self.cfg.chi_max
         out = np.zeros(cap)
@@ -353,7 +418,7 @@ class BatchPlan:
 
 def batch_run(programs, params, channels: Sequence[Channel], observables, chi_max: int, kappa_max: int,
               max_kraus: int = 16, svd_cutoff: float = 1e-14, kappa_cutoff: float = 1e-14, prec: int = C128,
-              use_graph: bool = True, stream=None, out=None):
+              use_graph: bool = True, stream=None, out=None, allocator: Optional[TorchAllocator] = None):
     """Run many programs through mpdo_batch_run.
 
     programs: workloads.Program list, or a BatchPlan built from them (then
@@ -369,10 +434,17 @@ def batch_run(programs, params, channels: Sequence[Channel], observables, chi_ma
     if out is None:
         out = torch.zeros(max(1, total), dtype=torch.complex128, device="cuda")
     chans = (ctypes.c_void_p * max(1, len(channels)))(*[c.handle.value for c in channels])
+    if out.dtype != torch.complex128 or not out.is_cuda or not out.is_contiguous() or out.numel() < total:
+        raise ValueError("out must be a contiguous complex128 CUDA tensor of at least %d entries" % total)
     cfg = mpdo_config(0, chi_max, kappa_max, max_kraus, svd_cutoff, kappa_cutoff, prec)
+    if allocator is not None:
+        allocator.apply(cfg)
     pptr, pstride = None, 0
     if params is not None:
-        assert params.is_cuda and params.dtype == torch.float64 and params.is_contiguous()
+        if not (params.is_cuda and params.dtype == torch.float64 and params.is_contiguous()):
+            raise ValueError("params must be a contiguous float64 CUDA tensor")
+        if params.ndim != 2 or params.shape[0] < ninst:
+            raise ValueError("params must have shape (>= %d instances, P)" % ninst)
         pptr, pstride = params.data_ptr(), params.shape[1]
     check(lib().mpdo_batch_run(ctypes.byref(cfg), progs, ninst, pptr, pstride, _dptr(plan.fbuf), plan.nfixed, chans,
                                len(channels), out.data_ptr(), 1 if use_graph else 0, stream_handle(stream)))
@@ -423,8 +495,23 @@ def _testing_lib():
         L.mpdo_test_gemm_rate.argtypes = [i32] * 6 + [pd]
         L.mpdo_test_gemm_rate.restype = ctypes.c_int
         L.mpdo_test_eigh.restype = ctypes.c_int
+        L.mpdo_test_eig_residual_bound.argtypes = [ctypes.c_double]
+        L.mpdo_test_eig_residual_bound.restype = ctypes.c_int
+        L.mpdo_test_fail_next_update.argtypes = [i32]
+        L.mpdo_test_fail_next_update.restype = ctypes.c_int
         L._testing_sig = True
     return L
+
+
+def test_eig_residual_bound(rtol: float) -> None:
+    """Residual bound of the eigensolver (0: the default 1e-9; negative:
+    every eigenpair fails its check)."""
+    check(_testing_lib().mpdo_test_eig_residual_bound(float(rtol)))
+
+
+def test_fail_next_update(status: int) -> None:
+    """The next sublayer of gates fails with `status` before launching."""
+    check(_testing_lib().mpdo_test_fail_next_update(int(status)))
 
 
 def test_gemm(prec: int, opA: int, opB: int, M: int, N: int, K: int, A: np.ndarray, B: np.ndarray,

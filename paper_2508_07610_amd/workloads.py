@@ -426,6 +426,12 @@ def pauli_string(n: int, terms: dict) -> str:
     return "".join(s)
 
 
+def pauli_ops(s: str) -> np.ndarray:
+    """The product operator of a Pauli string as per-site 2x2 factors,
+    shape (n, 2, 2) (an observable row of a batch run)."""
+    return np.stack([PAULI[PAULI_CHARS.index(c)] for c in s]).astype(np.complex128)
+
+
 def zz_strings(n: int) -> List[str]:
     return [pauli_string(n, {i: "Z", i + 1: "Z"}) for i in range(n - 1)]
 

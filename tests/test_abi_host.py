@@ -39,13 +39,30 @@ def test_version_string():
 @pytest.mark.parametrize("field,value", [("n", 0), ("n", 65), ("chi_max", 0), ("chi_max", 129), ("kappa_max", 0),
                                          ("max_kraus", 0), ("max_kraus", 257), ("svd_cutoff", -1.0), ("prec", 7)])
 def test_create_rejects_bad_config(field, value):
-    cfg = M.mpdo_config(6, 16, 4, 16, 1e-10, 1e-14, 0)
+    cfg = M.mpdo_config(6, 16, 4, 16, 1e-10, 1e-10, 0)
     setattr(cfg, field, value)
     h = ctypes.c_void_p()
     st = M.lib().mpdo_create(ctypes.byref(cfg), None, ctypes.byref(h))
     assert st == M.EINVAL
     assert not h.value
     assert len(M.lib().mpdo_last_error()) > 0
+
+
+def test_create_rejects_a_single_allocator_hook():
+    cfg = M.mpdo_config(6, 16, 4, 16, 1e-10, 1e-10, 0)
+    cfg.alloc = M.ALLOC_FN(lambda n, ctx: None)
+    h = ctypes.c_void_p()
+    assert M.lib().mpdo_create(ctypes.byref(cfg), None, ctypes.byref(h)) == M.EINVAL
+    assert b"hooks" in M.lib().mpdo_last_error()
+    assert not h.value
+
+
+def test_handle_calls_reject_null_handles():
+    L = M.lib()
+    st = M.mpdo_stats_t()
+    assert L.mpdo_stats(None, ctypes.byref(st)) == M.EINVAL
+    assert L.mpdo_flush(None) == M.EINVAL
+    assert L.mpdo_dims(None, None, None, None) == M.EINVAL
 
 
 def test_channel_rejects_bad_chi():
@@ -104,7 +121,7 @@ def test_profile_read_rejects_unknown_class():
 def test_batch_run_validates_op_arity(q, kind, fixed, chi, status):
     """Three-site ops in batch runs are channels without a gate matrix; the
     call fails before touching the device."""
-    cfg = M.mpdo_config(6, chi, 4, 16, 1e-10, 1e-14, 0)
+    cfg = M.mpdo_config(6, chi, 4, 16, 1e-10, 1e-10, 0)
     ops = (M.mpdo_op * 1)()
     ops[0].q, ops[0].site, ops[0].kind, ops[0].param, ops[0].scale, ops[0].chan, ops[0].fixed = (
         q, 0, kind, -1, 1.0, -1, fixed)
