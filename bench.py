@@ -32,7 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 N_QUBITS, DEPTH, CHI, KAPPA = 16, 10, 64, 8
-SVD_CUT, KAP_CUT = 1e-10, 1e-14
+SVD_CUT, KAP_CUT = 1e-10, 1e-10
 # MI355X published peaks
 PEAK = {"f64_mfma": 78.6, "f32_mfma": 157.3, "f64_valu": 78.6, "hbm": 8000.0}
 
@@ -45,7 +45,6 @@ def parse():
     ap.add_argument("--prec", choices=["c128", "c64"], default="c128")
     ap.add_argument("--depth", type=int, default=DEPTH)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-layers", type=int, default=5)
     ap.add_argument("--mode", choices=["batched", "plain"], default="batched")
     ap.add_argument("--batch", type=int, default=64, help="parameter points per step (batched mode)")
     ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-fidelity leg (C5 variational loop)")
@@ -61,9 +60,17 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB three times (b.copy_(a), 2^28 float32): the reference run that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture each batched step into one HIP graph (the roofline then comes from one "
-                         "extra profiled step outside the timed region)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch each batched step kernel by kernel instead of as one captured HIP graph (with "
+                         "the graph, the roofline comes from one extra profiled step outside the timed region)")
+    ap.add_argument("--cpu-threads1", action="store_true",
+                    help="also time the oracle's two-site gate on one BLAS thread (minutes)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's built-in GEMM choices (no autotuner settings)")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the GEMM autotuner even if its cache holds settings for this workload")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the plain-vs-batched sweep (B, precision, noise strength)")
     return ap.parse_args()
 
 
@@ -88,19 +95,164 @@ def blas_threads():
     return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
 
 
-def cpu_baseline(W, layers):
-    """The oracle MPDO as it stands, on the first `layers` layers of the same circuit."""
+def cpu_baseline(W, threads1=True):
+    """The oracle MPDO as it stands, timed at the workload's steady state: one
+    two-site and one one-site noisy gate (CZ then the 2q channel, RY then the
+    1q channel) on a state whose touched sites are at the full limits
+    (bonds chi = 64, inner kappa = 8; random right-orthonormal tensors, whose
+    values do not change the cost of the dense decompositions).  A layer is
+    15 two-site and 32 one-site gates, so gate-layers/s = 1 / (15 t2 + 32 t1).
+    Timed with every host core and with one BLAS thread."""
+    import numpy as np
     from oracle import channels as OC
     from oracle import mpdo as OM
-    prog = W.ghz_ansatz(N_QUBITS, layers, W.ansatz_params(N_QUBITS, DEPTH, 0))
-    kr = [OC.kraus_from_chi(c)[0] for c in prog.chis]
+
+    rng = np.random.default_rng(7690)
+
+    def site(l, r):
+        a = rng.normal(size=(l, 2 * KAPPA * r)) + 1j * rng.normal(size=(l, 2 * KAPPA * r))
+        q, _ = np.linalg.qr(a.conj().T)
+        return q.conj().T.reshape(l, 2, KAPPA, r)
+
+    edge = 2 * KAPPA
+
+    def fresh():
+        # bonds edge, chi, chi, chi, edge: the gate's sites 2, 3 see chi on both sides
+        m = OM.MPDO(6, CHI, KAPPA, SVD_CUT, KAP_CUT)
+        dims = [1, edge, CHI, CHI, CHI, edge, 1]
+        m.T = [site(dims[i], dims[i + 1]) for i in range(6)]
+        m.lam = []
+        for d in dims[1:-1]:
+            lam = np.sort(rng.uniform(size=d))[::-1] ** 4
+            m.lam.append(lam / np.linalg.norm(lam))
+        return m
+
+    k1 = OC.kraus_from_chi(W.chi_1q_default())[0]
+    k2 = OC.kraus_from_chi(W.chi_2q_default())[0]
+    G1 = [K @ W.ry(0.7) for K in k1]
+    G2 = [K @ W.CZ for K in k2]
+
+    def timed(two=True):
+        t2 = None
+        if two:
+            m = fresh()
+            t0 = time.perf_counter()
+            m.apply_2q(2, G2)
+            t2 = time.perf_counter() - t0
+        m = fresh()
+        t0 = time.perf_counter()
+        m.apply_1q(2, G1)
+        t1 = time.perf_counter() - t0
+        return t2, t1
+
+    cores = blas_threads()
+    t2, t1 = timed()
+    rate = 1.0 / (15 * t2 + 32 * t1)
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            u2, u1 = timed(two=threads1)
+        if threads1:
+            one = {"value": 1.0 / (15 * u2 + 32 * u1), "unit": "gate-layers/s", "cores": 1,
+                   "sample": f"one 2q gate {u2:.2f} s, one 1q gate {u1:.2f} s, one BLAS thread"}
+        else:
+            one = {"one_site_gate_seconds": u1, "cores": 1,
+                   "note": "one BLAS thread, one-site gate only (the two-site gate takes minutes on one thread; "
+                           "bench.py --cpu-threads1 times it)"}
+    except ImportError:
+        pass
+    host = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            host = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": rate, "unit": "gate-layers/s", "cores": cores, "kind": "oracle",
+            "sample": f"steady state of the same workload: one two-site noisy gate ({t2:.2f} s) and one one-site "
+                      f"noisy gate ({t1:.2f} s) on sites at chi={CHI}, kappa={KAPPA} (complex128 NumPy/LAPACK), "
+                      f"scaled to a layer of 15 + 32 gates",
+            "host_cpu": host, "one_thread": one}
+
+
+def oracle_error(zz, f, noise_scale=1.0):
+    """Error of instance 0 (parameter point 0) against the oracle's truncated
+    MPDO of the same circuit, stored by tests/golden/make_c2_reference.py
+    (complex128, oracle/ only)."""
+    path = os.path.join(ROOT, "tests", "golden", "c2_reference.json")
+    try:
+        with open(path) as fh:
+            ref = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    case = next((c for c in ref["cases"] if c["noise_scale"] == noise_scale and c["param_tag"] == 0), None)
+    if case is None:
+        return None
+    ezz = max(abs(a - b) for a, b in zip(zz, case["zz"]))
+    return {"max_abs_err_zz": ezz, "abs_err_ghz_fidelity": abs(f - case["ghz_fidelity"]),
+            "reference": "oracle truncated MPDO, complex128 (tests/golden/c2_reference.json)"}
+
+
+def batched_rate(M, W, ninst, prec, noise_scale=1.0, graph=True, steps=2, warmup=1, depth=DEPTH):
+    """gate-layers/s of ninst parameter points of the C2 circuit in one
+    mpdo_batch_run per step, and instance 0's <Z_i Z_i+1> and GHZ fidelity."""
+    import numpy as np
+    import torch
+    prog0 = W.ghz_ansatz(N_QUBITS, depth, W.ansatz_params(N_QUBITS, DEPTH, 0), noise_scale=noise_scale)
+    chans = [M.Channel(prog0.chis[0], 1), M.Channel(prog0.chis[1], 2)]
+    P = np.stack([W.ansatz_params(N_QUBITS, DEPTH, t) for t in range(ninst)])
+    progs = [W.ghz_ansatz(N_QUBITS, depth, P[b], noise_scale=noise_scale) for b in range(ninst)]
+    pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
+    obs = observables(N_QUBITS)
+    nobs = obs.shape[0]
+    plan = M.BatchPlan(progs, [obs] * ninst, use_params=True)
+
+    def step():
+        return M.batch_run(plan, pdev, chans, None, chi_max=CHI, kappa_max=KAPPA, max_kraus=16,
+                           svd_cutoff=SVD_CUT, kappa_cutoff=KAP_CUT, prec=prec, use_graph=graph).view(ninst, nobs)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    OM.run_program(prog, OM.MPDO(N_QUBITS, CHI, KAPPA, SVD_CUT, KAP_CUT), kr)
+    for _ in range(steps):
+        r = step()
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"value": layers / dt, "unit": "gate-layers/s", "cores": blas_threads(), "kind": "oracle",
-            "sample": f"first {layers} of {DEPTH} layers of the same circuit (parameter point 0), one instance, "
-                      f"complex128 NumPy/LAPACK, {dt:.1f} s; the early layers have smaller bonds, so this "
-                      f"overstates the CPU rate on the full circuit"}
+    f = 0.5 * (r[0, -3] + r[0, -2] + 2 * r[0, -1]).real.item()
+    return ninst * depth * steps / dt, r[0, : N_QUBITS - 1].real.cpu().tolist(), f
+
+
+def plain_rate(M, W, prec, noise_scale=1.0):
+    """gate-layers/s of one instance of the C2 circuit through per-gate calls."""
+    import torch
+    prog = W.ghz_ansatz(N_QUBITS, DEPTH, W.ansatz_params(N_QUBITS, DEPTH, 0), noise_scale=noise_scale)
+    chans = [M.Channel(prog.chis[0], 1), M.Channel(prog.chis[1], 2)]
+    gpu_step(M, W, prog, chans, prec)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f, zz = gpu_step(M, W, prog, chans, prec)
+    dt = time.perf_counter() - t0
+    return DEPTH / dt, zz, f
+
+
+def sweep_leg(M, W):
+    """Plain (per-gate calls, one instance) against batched (B parameter points
+    in one graph-captured mpdo_batch_run) on the C2 circuit, in both precisions,
+    noise strengths x1 and x3, with each configuration's error against the
+    oracle (instance 0)."""
+    out = {"plain": {}, "batched": {}}
+    for pname, prec in (("c128", M.C128), ("c64+f64", M.C64_MIXED)):
+        for ns in (1.0, 3.0):
+            v, zz, f = plain_rate(M, W, prec, ns)
+            out["plain"][f"{pname},noise_x{ns:g}"] = {"gate_layers_per_s": v,
+                                                       "error_vs_oracle": oracle_error(zz, f, ns)}
+        for B in (16, 64, 256):
+            for ns in ((1.0, 3.0) if B == 64 else (1.0,)):
+                v, zz, f = batched_rate(M, W, B, prec, ns, graph=True, steps=1 if B == 256 else 2)
+                out["batched"][f"{pname},B={B},noise_x{ns:g}"] = {"gate_layers_per_s": v,
+                                                                  "error_vs_oracle": oracle_error(zz, f, ns)}
+    return out
 
 
 def observables(n):
@@ -172,37 +324,68 @@ def roofline(M, prec_c128, steps):
     return out, share
 
 
-def ttf_leg(steps):
-    """Time to fidelity of the variational GHZ loop (n=12, depth 6, chi=32,
-    kappa=4, c128 judge): plain parameter-shift Adam versus the surrogate-
-    assisted loop, both from the same start.  The target is 0.9 x the best
-    fidelity of the plain run (the 0.9 target itself is out of reach under
-    this noise), each time measured from the start of its own optimisation."""
+def ttf_leg(steps, nsamples=65536, pretrain_steps=6000, seeds=(0, 1, 2)):
+    """Time to fidelity of the variational GHZ loop (C5: n=12, depth 6,
+    chi=32, kappa=4, c128 judge).  The surrogate is trained first on
+    `nsamples` MPDO-generated samples (theta ~ U[0, 2 pi)^144, noise strengths
+    ~ U[0.5, 2]^24, complex64 contractions), then plain parameter-shift Adam
+    and the surrogate-assisted loop start from the same random angles; the
+    target is 0.9 x F_best, F_best the best fidelity of `steps` plain steps
+    from a reference start (the 0.9 target itself is out of reach under this
+    noise).  Times are from the start of each optimisation; the data
+    generation and pre-training are reported apart, with the number of
+    optimisations after which they are repaid."""
+    import math
     import numpy as np
+    import torch
+    from paper_2508_07610_amd import mpdo as M
     from paper_2508_07610_amd import surrogate as S
     from paper_2508_07610_amd import variational as V
     n, depth = 12, 6
-    theta0 = np.random.default_rng(7610).uniform(-0.3, 0.3, size=2 * n * depth)
+    P = 2 * n * depth
     ev = V.AnsatzEvaluator(n, depth, chi_max=32, kappa_max=4)
-    ev(theta0[None, :])  # warm-up
-    plain = V.plain_optimize(ev, theta0, target=2.0, max_steps=steps, lr=0.05)
-    f_best = plain["best"]
-    target = 0.9 * f_best
-    t_plain = next(h[0] for h in plain["history"] if h[1] >= target)
-    e_plain = next(h[2] for h in plain["history"] if h[1] >= target)
-    ev2 = V.AnsatzEvaluator(n, depth, chi_max=32, kappa_max=4)
-    net = S.MLP(list(S.C5_WIDTHS), max_batch=1024, seed=1)
-    sur = V.surrogate_optimize(ev2, net, theta0, target=target, max_steps=steps, lr=0.05,
-                               time_limit=10 * plain["history"][-1][0])
+    ev64 = V.AnsatzEvaluator(n, depth, chi_max=32, kappa_max=4, prec=M.C64_MIXED)
+    rng = np.random.default_rng(7620)
+    ev64(rng.uniform(0, 2 * math.pi, (4, P)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, Y = V.generate_dataset(ev64, nsamples, rng)
+    t_gen = time.perf_counter() - t0
+    net = S.MLP(list(S.C5_WIDTHS), max_batch=1024, seed=0)
+    pre = V.pretrain(net, X, Y, steps=pretrain_steps)
+    params = net.get_params()
+    net.close()
+    ref = V.plain_optimize(ev, np.random.default_rng(7610).uniform(0, 2 * math.pi, P), target=2.0,
+                           max_steps=steps, lr=0.05)
+    target = 0.9 * ref["best"]
+    runs = []
+    for sd in seeds:
+        th0 = np.random.default_rng(7611 + sd).uniform(0, 2 * math.pi, P)
+        plain = V.plain_optimize(ev, th0, target=target, max_steps=3 * steps, lr=0.05)
+        net = S.MLP(list(S.C5_WIDTHS), max_batch=1024, seed=sd)
+        net.set_params(params)
+        sur = V.surrogate_optimize(ev, net, th0, target=target, max_rows=3 * max(plain["evaluations"], 2000))
+        net.close()
+        runs.append({"seed": sd, "plain_seconds": plain["time"], "plain_mpdo_rows": plain["rows_to_target"],
+                     "surrogate_seconds": sur["time"], "surrogate_mpdo_rows": sur["rows_to_target"],
+                     "surrogate_gradients": sur["gradients"], "proposal_rounds": sur["proposal_rounds"],
+                     "surrogate_steps_accepted": sur["surrogate_accepted"],
+                     "surrogate_abs_err_on_verified": sur["surrogate_abs_err"]})
+    ok = [r for r in runs if r["plain_seconds"] and r["surrogate_seconds"]]
+    tp = float(np.mean([r["plain_seconds"] for r in ok])) if ok else None
+    tsur = float(np.mean([r["surrogate_seconds"] for r in ok])) if ok else None
+    rp = float(np.mean([r["plain_mpdo_rows"] for r in ok])) if ok else None
+    rsur = float(np.mean([r["surrogate_mpdo_rows"] for r in ok])) if ok else None
+    overhead = t_gen + pre["train_seconds"]
     return {"workload": "variational GHZ fidelity, noisy RY/CZ ansatz n=12 depth=6 chi=32 kappa=4, c128 MPDO judge, "
-                        "parameter-shift gradients (289 rows per step in one mpdo_batch_run)",
-            "f_best_plain": f_best, "target": target,
-            "plain_seconds": t_plain, "plain_mpdo_rows": e_plain,
-            "surrogate_seconds": sur["time"], "surrogate_reached": sur["reached"],
-            "surrogate_mpdo_rows": sur["evaluations"] if sur["reached"] else None,
-            "surrogate_longer_steps_chosen": sur["longer_steps_chosen"], "surrogate_proposals": sur["proposals"],
-            "surrogate_abs_err_on_verified": sur["surrogate_abs_err"],
-            "note": "surrogate seconds include its online training; no pre-training data"}
+                        "parameter-shift gradients (289 rows per step in one mpdo_batch_run); surrogate 168-256-256-"
+                        "256-12 GELU, bf16 operands, FP32 accumulation, trained by the library's kernels",
+            "f_best_plain": ref["best"], "target": target, "runs": runs,
+            "mean_plain_seconds": tp, "mean_surrogate_seconds": tsur,
+            "mean_plain_mpdo_rows": rp, "mean_surrogate_mpdo_rows": rsur,
+            "data_generation": {"samples": nsamples, "seconds": t_gen, "precision": "c64 contractions + FP64 truncation"},
+            "pretraining": pre,
+            "break_even_optimisations": (overhead / (tp - tsur)) if tp and tsur and tp > tsur else None}
 
 
 def maxcut_leg():
@@ -247,7 +430,7 @@ def sampling_leg(shots=4096):
     from paper_2508_07610_amd import mpdo as M
     from paper_2508_07610_amd import workloads as W
     prog = W.ghz_ansatz(N_QUBITS, DEPTH, W.ansatz_params(N_QUBITS, DEPTH, 0))
-    st = M.MPDO(N_QUBITS, chi_max=CHI, kappa_max=KAPPA, max_kraus=16, svd_cutoff=SVD_CUT, kappa_cutoff=1e-14)
+    st = M.MPDO(N_QUBITS, chi_max=CHI, kappa_max=KAPPA, max_kraus=16, svd_cutoff=SVD_CUT, kappa_cutoff=KAP_CUT)
     M.run_program(prog, st, [M.Channel(c, 1 if c.shape[0] == 4 else 2) for c in prog.chis])
     u = np.random.default_rng(7616).random((shots, N_QUBITS))
     st.sample(u[:64])
@@ -398,16 +581,27 @@ def main():
         # every parameter point on the device
         plan = M.BatchPlan(progs, [obs] * ninst, use_params=True)
 
-        def step(graph=a.graph):
+        def step(graph=not a.no_graph):
             r = M.batch_run(plan, pdev, chans, None, chi_max=CHI, kappa_max=KAPPA, max_kraus=16,
                             svd_cutoff=SVD_CUT, kappa_cutoff=KAP_CUT, prec=prec, use_graph=graph)
             r = r.view(ninst, nobs)
             f = 0.5 * (r[0, -3] + r[0, -2] + 2 * r[0, -1]).real.item()
             return f, r[0, : N_QUBITS - 1].real.cpu().tolist()
+    tune_info = None
+    if a.mode == "batched" and not a.no_tune:
+        from paper_2508_07610_amd import autotune as AT
+        path = os.path.join(ROOT, "paper_2508_07610_amd", "autotune_cache.json")
+        key = AT.cache_key(prec, CHI, KAPPA, 16, f"ansatz n={N_QUBITS} depth={a.depth} B={ninst}")
+        if a.retune:
+            AT.save(path, key, None)
+        t_tune = time.perf_counter()
+        tune_info = AT.tuned(lambda: step(graph=False), path, key)
+        tune_info["seconds"] = time.perf_counter() - t_tune
+        tune_info["cache_key"] = key
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
-    profiled_timed = not (a.mode == "batched" and a.graph)
+    profiled_timed = not (a.mode == "batched" and not a.no_graph)
     if profiled_timed:
         M.profile_enable(True)
     t0 = time.perf_counter()
@@ -420,6 +614,15 @@ def main():
         step(graph=False)
         torch.cuda.synchronize()
     roof, share = roofline(M, prec == M.C128, a.steps if profiled_timed else 1)
+    gcls = M.PROF_GEMM_F64 if prec == M.C128 else M.PROF_GEMM_F32
+    g = M.profile_read(gcls)
+    gemm_tf = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    gpeak = PEAK["f64_mfma"] if prec == M.C128 else PEAK["f32_mfma"]
+    gemm_roof = {"kernel": M.PROF_NAMES[gcls], "bound": "mfma", "achieved": gemm_tf, "peak": gpeak,
+                 "unit": "TFLOP/s", "frac": gemm_tf / gpeak, "launches": g["launches"],
+                 "avg_launch_ms": g["ms"] / max(1, g["launches"]),
+                 "note": "the contraction class, reported beside the dominant class"}
+    sites = M.profile_sites()
     M.profile_enable(False)
     ms = 1e3 * dt / a.steps
     value = ninst * a.depth * a.steps / dt
@@ -429,7 +632,7 @@ def main():
     else:
         wl = (f"batched MPDO, {ninst} parameter points of the noisy RY/CZ ansatz n={N_QUBITS} depth={a.depth} "
               f"chi={CHI} kappa={KAPPA} svd_cutoff={SVD_CUT}, one mpdo_batch_run per step"
-              + (" captured in one HIP graph" if a.graph else ""))
+              + ("" if a.no_graph else " captured in one HIP graph"))
     out = {
         "metric": "MPDO gate-layers/s (n=16,chi=64,kappa=8) plain vs batched; surrogate time-to-fidelity",
         "value": value, "unit": "gate-layers/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -438,9 +641,14 @@ def main():
         "config": {"workload": wl, "instances": ninst, "mode": a.mode, "ghz_fidelity_instance0": f,
                    "zz01_instance0": zz[0], "roofline_from": "timed steps" if profiled_timed
                    else "one extra profiled step (graph launches are not profiled)"},
+        "error_vs_oracle_instance0": oracle_error(zz, f) if a.depth == DEPTH else None,
         "roofline": roof,
+        "gemm_roofline": gemm_roof,
         "kernel_time_ms": share,
-        "cpu_baseline": None if a.no_cpu else cpu_baseline(W, a.cpu_layers),
+        "gemm_sites": {k: {"ms": v["ms"], "launches": v["launches"], "tflops": v["tflops"]} for k, v in sites.items()},
+        "autotune": tune_info,
+        "sweep": None if a.no_sweep else sweep_leg(M, W),
+        "cpu_baseline": None if a.no_cpu else cpu_baseline(W, threads1=a.cpu_threads1),
         "time_to_fidelity": None if a.no_ttf else ttf_leg(a.ttf_steps),
         "maxcut_batch": None if a.no_maxcut else maxcut_leg(),
         "gemm_full_tiles": None if a.no_gemm_tiles else gemm_tiles_leg(),

@@ -304,6 +304,18 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
                            const mpdo_chan_t* chans, int32_t nchans,
                            double* out_dev, int32_t use_graph, void* hip_stream);
 
+/* As mpdo_batch_run (launch by launch; observables of the programs are
+ * ignored), then the dense density matrix of every instance, as
+ * mpdo_to_dense computes it (unnormalised, FP64), to device memory: instance
+ * b's 2^n x 2^n complex matrix at rho_dev + 2 * off_b doubles, off_b the sum
+ * of 4^n over the earlier instances.  For verification workloads with
+ * n <= 12 (EINVAL above), such as the fidelity study of Sec. IV.C. */
+mpdo_status mpdo_batch_run_dense(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
+                                 const double* params_dev, int32_t param_stride,
+                                 const double* fixed_u, int32_t nfixed,
+                                 const mpdo_chan_t* chans, int32_t nchans,
+                                 double* rho_dev, void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Kernel profiling (process-wide, not thread-safe).  While enabled, every
  * launch of the library's compute kernels on a stream that is not being
@@ -332,6 +344,25 @@ mpdo_status mpdo_profile_enable(int32_t on);
  * milliseconds, algorithmic flops and bytes (any pointer may be NULL).
  * Synchronises the device.  EINVAL for an unknown class. */
 mpdo_status mpdo_profile_read(int32_t cls, int32_t* launches, double* ms, double* flops, double* bytes);
+
+/* ---------------------------------------------------------------------------
+ * GEMM tuning (process-wide; an autotuner times candidates and sets them).
+ * The contractions of the MPDO update are grouped by call site:
+ *   1-2 one-site update: Gram, projection; 3-9 two-site update: E Gram,
+ *   theta, H Gram, theta'', C Gram, X, outputs; 10-11 right and left transfer
+ *   steps; 12-22 three-site update (N/E3 Grams, Xt, Psi, H Gram, Psi2, C1
+ *   Gram, Y1, W1, C2 Gram, Y3, outputs); 23-24 truncation sweep (Gram,
+ *   outputs).
+ * Per site: tile edge (32 or 64), complex-product form (4: four real MFMA
+ * products per complex product; 3: Gauss's three, P1 = Ar Br, P2 = Ai Bi,
+ * P3 = (Ar + Ai)(Br + Bi), Re = P1 - P2, Im = P3 - P1 - P2) and a factor on
+ * the split-K count of the Gram sites; 0 keeps the library's built-in choice.
+ * Settings apply to launches issued after the call (a captured graph keeps
+ * the settings of its capture).  EINVAL for a site outside 1..24 or values
+ * outside those sets (split_scale in [0, 16]).
+ * ------------------------------------------------------------------------- */
+mpdo_status mpdo_tune_set(int32_t site, int32_t tile, int32_t form, double split_scale);
+mpdo_status mpdo_tune_get(int32_t site, int32_t* tile, int32_t* form, double* split_scale);
 
 /* ---------------------------------------------------------------------------
  * Surrogate network: a multilayer perceptron trained on MPDO-generated

@@ -62,6 +62,23 @@ mpdo_status mpdo_test_eigh(int32_t n, int32_t kvec, const double* A, double* eva
  *   mpdo_test_fail_next_update: the next sublayer of gates of any handle
  *     fails with `status` before launching anything (0 cancels). */
 mpdo_status mpdo_test_eig_residual_bound(double rtol);
+
+/* Complex-product form of the GEMM launches of one MFMA precision (prec 0:
+ * FP64, 1: FP32) and tile edge (32 or 64), process-wide: form 4 = four real
+ * MFMA products per complex product, form 3 = Gauss's three (P1 = Ar Br,
+ * P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); Re = P1 - P2, Im = P3 - P1 - P2).
+ * *previous (may be NULL) receives the form in force before the call.  The
+ * defaults: 3 for FP32, 4 for FP64. */
+mpdo_status mpdo_test_gemm_form(int32_t prec, int32_t tile, int32_t form, int32_t* previous);
+
+/* Profile of one GEMM call site of the MPDO update (while profiling is on,
+ * see mpdo_profile_enable): launches, summed HIP-event milliseconds and
+ * algorithmic flops of the contractions labelled `site` (0: other; 1-2 the
+ * one-site update's Gram and projection; 3-9 the two-site update's E Gram,
+ * theta, H Gram, theta'', C Gram, X and output products; 10-11 right and left
+ * transfer steps; 12-22 the three-site update; 23-24 the truncation sweep).
+ * EINVAL outside 0..24. */
+mpdo_status mpdo_test_profile_site(int32_t site, int32_t* launches, double* ms, double* flops);
 mpdo_status mpdo_test_fail_next_update(int32_t status);
 
 #ifdef __cplusplus

@@ -43,7 +43,7 @@ struct AnyEngine {
     d ? d->dims(b, bo, in, disc) : f->dims(b, bo, in, disc);
   }
   std::vector<double> bond_weights(int b, int bond) { return d ? d->bond_weights(b, bond) : f->bond_weights(b, bond); }
-  void to_dense(int b, double* host) { d ? d->to_dense(b, host) : f->to_dense(b, host); }
+  void to_dense(int b, double* host) { d ? d->to_dense(b, host, false) : f->to_dense(b, host, false); }
   void sample(int b, const double* u, int ns, unsigned char* bits, double* pz) {
     d ? d->sample(b, u, ns, bits, pz) : f->sample(b, u, ns, bits, pz);
   }
@@ -572,7 +572,7 @@ namespace {
 template <typename T>
 void batch_exec(const Config& c, const std::vector<int>& nq, const std::vector<std::vector<GateOp>>& layers,
                 const std::vector<int>& oinst, const std::vector<const double*>& oops, double* out_dev,
-                bool use_graph, hipStream_t user_st) {
+                bool use_graph, hipStream_t user_st, double* rho_dev = nullptr) {
   // graph capture needs a real stream: use a private one when given NULL
   struct OwnStream {
     hipStream_t s = nullptr;
@@ -585,6 +585,18 @@ void batch_exec(const Config& c, const std::vector<int>& nq, const std::vector<s
     st = own.s;
   }
   Engine<T> eng(c, nq, st);
+  if (rho_dev) {  // dense state of every instance, offsets by the prefix sum of 4^n
+    for (const auto& L : layers) eng.run_sublayer(L);
+    long long off = 0;
+    for (size_t b = 0; b < nq.size(); ++b) {
+      eng.to_dense((int)b, rho_dev + 2 * off, true);
+      off += 1LL << (2 * nq[b]);
+    }
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (const long long f = eng.failures())
+      throw Error{MPDO_ENOTCONV, std::to_string(f) + " numerical failure(s) in the batch's truncations"};
+    return;
+  }
   if (!use_graph) {
     for (const auto& L : layers) eng.run_sublayer(L);
     if (!oinst.empty()) eng.expect(oinst, oops, out_dev);
@@ -646,10 +658,37 @@ void batch_exec(const Config& c, const std::vector<int>& nq, const std::vector<s
 
 extern "C" {
 
+static mpdo_status batch_common(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
+                                const double* params_dev, int32_t param_stride, const double* fixed_u, int32_t nfixed,
+                                const mpdo_chan_t* chans, int32_t nchans, double* out_dev, int32_t use_graph,
+                                void* hip_stream, double* rho_dev);
+
 mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
                            const double* params_dev, int32_t param_stride, const double* fixed_u, int32_t nfixed,
                            const mpdo_chan_t* chans, int32_t nchans, double* out_dev, int32_t use_graph,
                            void* hip_stream) {
+  return batch_common(cfg, progs, ninst, params_dev, param_stride, fixed_u, nfixed, chans, nchans, out_dev,
+                      use_graph, hip_stream, nullptr);
+}
+
+mpdo_status mpdo_batch_run_dense(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
+                                 const double* params_dev, int32_t param_stride, const double* fixed_u,
+                                 int32_t nfixed, const mpdo_chan_t* chans, int32_t nchans, double* rho_dev,
+                                 void* hip_stream) {
+  if (!rho_dev) return fail(MPDO_EINVAL, "null rho_dev");
+  if (progs && ninst >= 1)
+    for (int b = 0; b < ninst; ++b)
+      if (progs[b].n > 12) return fail(MPDO_EINVAL, "dense states need n <= 12");
+  return batch_common(cfg, progs, ninst, params_dev, param_stride, fixed_u, nfixed, chans, nchans, nullptr, 0,
+                      hip_stream, rho_dev);
+}
+
+}  // extern "C"
+
+static mpdo_status batch_common(const mpdo_config* cfg, const mpdo_program* progs, int32_t ninst,
+                                const double* params_dev, int32_t param_stride, const double* fixed_u, int32_t nfixed,
+                                const mpdo_chan_t* chans, int32_t nchans, double* out_dev, int32_t use_graph,
+                                void* hip_stream, double* rho_dev) {
   if (const char* why = check_config(cfg, false)) return fail(MPDO_EINVAL, why);
   if (!progs || ninst < 1) return fail(MPDO_EINVAL, "no programs");
   if (nfixed < 0 || nchans < 0 || param_stride < 0) return fail(MPDO_EINVAL, "negative count");
@@ -684,7 +723,7 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
       }
     }
   }
-  if (total_obs > 0 && !out_dev) return fail(MPDO_EINVAL, "null out_dev");
+  if (total_obs > 0 && !out_dev && !rho_dev) return fail(MPDO_EINVAL, "null out_dev");
   if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return fail(MPDO_EINVAL, "set both allocator hooks or none");
   const DeviceAllocator hooks = hooks_of(cfg);
   AllocScope scope(hooks.alloc ? &hooks : nullptr);
@@ -739,15 +778,39 @@ mpdo_status mpdo_batch_run(const mpdo_config* cfg, const mpdo_program* progs, in
       oops.push_back(progs[b].obs + (size_t)k * progs[b].n * 8);
     }
   const Config c = make_config(cfg);
-  if (cfg->prec == MPDO_C128) batch_exec<double>(c, nq, layers, oinst, oops, out_dev, use_graph != 0, st);
-  else batch_exec<float>(c, nq, layers, oinst, oops, out_dev, use_graph != 0, st);
+  if (cfg->prec == MPDO_C128) batch_exec<double>(c, nq, layers, oinst, oops, out_dev, use_graph != 0, st, rho_dev);
+  else batch_exec<float>(c, nq, layers, oinst, oops, out_dev, use_graph != 0, st, rho_dev);
   return MPDO_OK;
   GUARD_END
 }
 
+extern "C" {
+
 }  // extern "C"
 
 extern "C" {
+
+mpdo_status mpdo_tune_set(int32_t site, int32_t tile, int32_t form, double split_scale) {
+  if (site < 1 || site >= GS_N) return fail(MPDO_EINVAL, "site must be in 1..24");
+  if (tile != 0 && tile != 32 && tile != 64) return fail(MPDO_EINVAL, "tile must be 0, 32 or 64");
+  if (form != 0 && form != 3 && form != 4) return fail(MPDO_EINVAL, "form must be 0, 3 or 4");
+  if (!(split_scale >= 0 && split_scale <= 16)) return fail(MPDO_EINVAL, "split_scale must be in [0, 16]");
+  SiteTune t;
+  t.tile = tile;
+  t.form = form;
+  t.split_scale = split_scale;
+  set_site_tune(site, t);
+  return MPDO_OK;
+}
+
+mpdo_status mpdo_tune_get(int32_t site, int32_t* tile, int32_t* form, double* split_scale) {
+  if (site < 1 || site >= GS_N) return fail(MPDO_EINVAL, "site must be in 1..24");
+  const SiteTune t = get_site_tune(site);
+  if (tile) *tile = t.tile;
+  if (form) *form = t.form;
+  if (split_scale) *split_scale = t.split_scale;
+  return MPDO_OK;
+}
 
 mpdo_status mpdo_profile_enable(int32_t on) {
   GUARD_BEGIN
@@ -960,5 +1023,21 @@ extern "C" mpdo_status mpdo_test_eig_residual_bound(double rtol) {
 extern "C" mpdo_status mpdo_test_fail_next_update(int32_t status) {
   if (status < 0 || status > MPDO_EUNSUPPORTED) return fail(MPDO_EINVAL, "unknown status");
   inject_update_failure(status);
+  return MPDO_OK;
+}
+
+extern "C" mpdo_status mpdo_test_profile_site(int32_t site, int32_t* launches, double* ms, double* flops) {
+  if (site < 0 || site >= GS_N) return fail(MPDO_EINVAL, "unknown GEMM site");
+  GUARD_BEGIN
+  prof_read_site(site, launches, ms, flops);
+  return MPDO_OK;
+  GUARD_END
+}
+
+extern "C" mpdo_status mpdo_test_gemm_form(int32_t prec, int32_t tile, int32_t form, int32_t* previous) {
+  if (prec < 0 || prec > 1 || (tile != 32 && tile != 64) || (form != 3 && form != 4))
+    return fail(MPDO_EINVAL, "prec 0/1, tile 32/64, form 3/4");
+  if (previous) *previous = gemm_form(prec == 0, tile);
+  set_gemm_form(prec == 0, tile, form);
   return MPDO_OK;
 }

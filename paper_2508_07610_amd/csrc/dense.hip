@@ -81,7 +81,7 @@ void gemm(DevBuf& dd, const cpx<double>* A, const cpx<double>* B, cpx<double>* C
 }
 }  // namespace
 
-template <typename T> void Engine<T>::to_dense(int b, double* host) {
+template <typename T> void Engine<T>::to_dense(int b, double* host, bool device_out) {
   const int n = nq_[b];
   std::vector<int> bonds, inner;
   double disc;
@@ -152,11 +152,12 @@ template <typename T> void Engine<T>::to_dense(int b, double* host) {
        (int)(cm * cm), (int)(SR * SR), st_);
   // rho[(S_L S_R), (S_L' S_R')]
   permute<double>(Y, Mf, {SL, SR, SL, SR}, {SL * SR * SR, SR, SR * SR, 1}, false, st_);
-  hip_check(hipMemcpyAsync(host, Mf, (size_t)(SL * SR) * (SL * SR) * 16, hipMemcpyDeviceToHost, st_), "rho");
+  hip_check(hipMemcpyAsync(host, Mf, (size_t)(SL * SR) * (SL * SR) * 16,
+                           device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st_), "rho");
   hip_check(hipStreamSynchronize(st_), "hipStreamSynchronize");
 }
 
-template void Engine<double>::to_dense(int, double*);
-template void Engine<float>::to_dense(int, double*);
+template void Engine<double>::to_dense(int, double*, bool);
+template void Engine<float>::to_dense(int, double*, bool);
 
 }  // namespace mpdo

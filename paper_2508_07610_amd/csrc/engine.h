@@ -146,8 +146,9 @@ template <typename T> class Engine {
   // site tensor of instance b, site i (current buffer): for host-side tests
   void* site_ptr(int b, int i) { return site(b, i, par_[soff_[b] + i]); }
   std::vector<double> bond_weights(int b, int bond);
-  // rho of instance b (n <= 12) as 2^n x 2^n complex doubles into `host`
-  void to_dense(int b, double* host);
+  // rho of instance b (n <= 12) as 2^n x 2^n complex doubles into `out`
+  // (host memory, or device memory when device_out)
+  void to_dense(int b, double* out, bool device_out = false);
   // nshots bitstrings by sequential conditionals (u: nshots x n uniforms,
   // host; bits: nshots x n, host; pz: probability of each, host or null)
   void sample(int b, const double* u_host, int nshots, unsigned char* bits_host, double* pz_host);

@@ -18,6 +18,7 @@
 
 #include "engine.h"
 #include "kernels.h"
+#include "profile.h"
 
 namespace mpdo {
 
@@ -317,8 +318,8 @@ void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up, bool f
   int m1 = 1;
   for (auto* g : ops) m1 = std::max(m1, g->ch ? g->ch->m : 1);
   // (2k)^2 Gram over chi^2 terms: small output, long K -> 32 x 32 tiles, more splits
-  const int tileH = 2 * kx <= 32 ? 32 : 64;
-  const int splitsH = splits_for((long long)cx * cx * (tileH == 32 ? 4 : 1));
+  const int tileH = tuned_tile(GS_Q1_GRAM, 2 * kx <= 32 ? 32 : 64);
+  const int splitsH = tuned_splits(GS_Q1_GRAM, splits_for((long long)cx * cx * (tileH == 32 ? 4 : 1)));
   const int ng = kx * m1;  // largest Gamma
   // ---- workspace layout per item ----
   Layout w;
@@ -387,14 +388,15 @@ void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up, bool f
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   if (tpo) tp = *tpo;
   launch_q1_prepare<T>(dctx, n, splitsH, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH,
-                                 gemm_tiles(2 * kx, 2 * kx, tileH), st_, tileH);
+  launch_gemm_site<T, double, double>(GS_Q1_GRAM, reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH,
+                          [&](int tl) { return gemm_tiles(2 * kx, 2 * kx, tl); }, st_, tileH);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uH), reinterpret_cast<double**>(dv + uOut), n,
                        4 * kx * kx, st_);
   launch_q1_gamma<T>(dctx, n, st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uE), n, ng, sweeps_.as<int>(), st_);
   launch_q1_select<T>(dctx, n, tp, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uA), n, cx, 1, gemm_tiles(2 * kx, cx), st_);
+  launch_gemm_site<T, T, T>(GS_Q1_PROJ, reinterpret_cast<GemmDesc*>(dv + uA), n, cx, 1,
+                          [&](int tl) { return gemm_tiles(2 * kx, cx, tl); }, st_, 64);
   hip_check(hipGetLastError(), "launch (1q sublayer)");
   for (auto* g : ops) par_[soff_[g->inst] + g->site] ^= 1;
 }
@@ -405,10 +407,11 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
   int m2 = 1;
   for (auto* g : ops) m2 = std::max(m2, g->ch ? g->ch->m : 1);
-  const int tileH = 4 * kx <= 32 ? 32 : 64;
-  const int splitsH = splits_for((long long)cx * 2 * cx * (tileH == 32 ? 4 : 1));
-  const int splitsE = splits_for((long long)kx * cx);
-  const int splitsC = splits_for((long long)2 * kx * cx);
+  const int tileH0 = 4 * kx <= 32 ? 32 : 64;  // default tile of the H Gram and of theta''
+  const int tileH = tuned_tile(GS_Q2_GRAM_H, tileH0);
+  const int splitsH = tuned_splits(GS_Q2_GRAM_H, splits_for((long long)cx * 2 * cx * (tileH == 32 ? 4 : 1)));
+  const int splitsE = tuned_splits(GS_Q2_GRAM_E, splits_for((long long)kx * cx));
+  const int splitsC = tuned_splits(GS_Q2_GRAM_C, splits_for((long long)2 * kx * cx));
   const int ng = kx * m2;
   const long long thetaN = (long long)2 * kx * cx;
   Layout w;
@@ -542,30 +545,34 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   int* status = sweeps_.as<int>();
   launch_q2_prepare<T>(dctx, n, splitsE, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGramE), n, 1, splitsE, gemm_tiles_herm(2 * cx),
-                                 st_);
+  launch_gemm_site<T, double, double>(GS_Q2_GRAM_E, reinterpret_cast<GemmDesc*>(dv + uGramE), n, 1, splitsE,
+                          [&](int tl) { return gemm_tiles_herm(2 * cx, tl); }, st_, 64);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramE), reinterpret_cast<double**>(dv + uOutsE), n,
                        4 * cx * cx, st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigE), n, 2 * cx, status, st_);
   launch_q2_select_e<T>(dctx, n, splitsH, tp, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh), n, 1, 1, gemm_tiles((int)thetaN, 4 * cx), st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uGramH), n, 1, splitsH,
-                                 gemm_tiles(4 * kx, 4 * kx, tileH), st_, tileH);
+  launch_gemm_site<T, T, T>(GS_Q2_THETA, reinterpret_cast<GemmDesc*>(dv + uTh), n, 1, 1,
+                          [&](int tl) { return gemm_tiles((int)thetaN, 4 * cx, tl); }, st_, 64);
+  launch_gemm_site<T, double, double>(GS_Q2_GRAM_H, reinterpret_cast<GemmDesc*>(dv + uGramH), n, 1, splitsH,
+                          [&](int tl) { return gemm_tiles(4 * kx, 4 * kx, tl); }, st_, tileH);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramH), reinterpret_cast<double**>(dv + uOutsH), n,
                        16 * kx * kx, st_);
   launch_q2_gamma<T>(dctx, n, st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigG), n, ng, status + n, st_);
   launch_q2_select_g<T>(dctx, n, splitsC, tp, st_);
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uTh2), n, cx, 1, gemm_tiles(4 * kx, 2 * cx, tileH), st_, tileH);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uC), n, 1, splitsC, gemm_tiles_herm(4 * cx), st_);
+  launch_gemm_site<T, T, T>(GS_Q2_THETA2, reinterpret_cast<GemmDesc*>(dv + uTh2), n, cx, 1,
+                          [&](int tl) { return gemm_tiles(4 * kx, 2 * cx, tl); }, st_, tileH0);
+  launch_gemm_site<T, double, double>(GS_Q2_GRAM_C, reinterpret_cast<GemmDesc*>(dv + uC), n, 1, splitsC,
+                          [&](int tl) { return gemm_tiles_herm(4 * cx, tl); }, st_, 64);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uC), reinterpret_cast<double**>(dv + uOutsC), n,
                        16 * cx * cx, st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigC), n, 4 * cx, status + 2 * n, st_);
   launch_q2_select_b<T>(dctx, n, tp, st_);
-  launch_gemm<double, double, T>(reinterpret_cast<GemmDesc*>(dv + uX), n, 1, 1, gemm_tiles(2 * cx, 2 * cx), st_);
+  launch_gemm_site<double, double, T>(GS_Q2_X, reinterpret_cast<GemmDesc*>(dv + uX), n, 1, 1,
+                          [&](int tl) { return gemm_tiles(2 * cx, 2 * cx, tl); }, st_, 64);
   // B_i' (at most thetaN x cx) and B_{i+1}' (at most 2 cx x kx cx) share a launch
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uOut), 2 * n, 1, 1,
-                       std::max(gemm_tiles((int)thetaN, cx), gemm_tiles(2 * cx, kx * cx)), st_);
+  launch_gemm_site<T, T, T>(GS_Q2_OUT, reinterpret_cast<GemmDesc*>(dv + uOut), 2 * n, 1, 1,
+                          [&](int tl) { return std::max(gemm_tiles((int)thetaN, cx, tl), gemm_tiles(2 * cx, kx * cx, tl)); }, st_, 64);
   hip_check(hipGetLastError(), "launch (2q sublayer)");
   for (auto* g : ops) {
     par_[soff_[g->inst] + g->site] ^= 1;
@@ -732,18 +739,18 @@ void Engine<T>::expect(const std::vector<int>& inst, const std::vector<const dou
   launch_transfer_init<T>(dctx, n, st_);
   for (int t = 0; t < nmax - 1; ++t) {
     launch_rtransfer_prep<T>(rctx + (size_t)t * ninst, ninst, st_);
-    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD3) + (size_t)t * ninst, ninst, 1, 1,
-                         gemm_tiles((int)(2 * cfg_.kap_max * cx), cx), st_);
-    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD4) + (size_t)t * ninst, ninst, 1, 1,
-                         gemm_tiles(cx, cx, 32), st_, 32);
+    launch_gemm_site<T, T, T>(GS_TRANSFER_R, reinterpret_cast<GemmDesc*>(dv + uD3) + (size_t)t * ninst, ninst, 1, 1,
+                            [&](int tl) { return gemm_tiles((int)(2 * cfg_.kap_max * cx), cx, tl); }, st_, 64);
+    launch_gemm_site<T, T, T>(GS_TRANSFER_R, reinterpret_cast<GemmDesc*>(dv + uD4) + (size_t)t * ninst, ninst, 1, 1,
+                            [&](int tl) { return gemm_tiles(cx, cx, tl); }, st_, 32);
   }
   for (int s = 0; s < nmax; ++s) {
     launch_transfer_prep<T>(dctx + (size_t)s * n, n, (int)cap_site_ / 2, st_);
-    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n, n, 1, 1,
-                         gemm_tiles(cx, (int)(2 * cfg_.kap_max * cx)), st_);
+    launch_gemm_site<T, T, T>(GS_TRANSFER_L, reinterpret_cast<GemmDesc*>(dv + uD1) + (size_t)s * n, n, 1, 1,
+                            [&](int tl) { return gemm_tiles(cx, (int)(2 * cfg_.kap_max * cx), tl); }, st_, 64);
     // one cx x cx output over a long K per item: 32 x 32 tiles fill the CUs
-    launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uD2) + (size_t)s * n, n, 1, 1, gemm_tiles(cx, cx, 32), st_,
-                         32);
+    launch_gemm_site<T, T, T>(GS_TRANSFER_L, reinterpret_cast<GemmDesc*>(dv + uD2) + (size_t)s * n, n, 1, 1,
+                            [&](int tl) { return gemm_tiles(cx, cx, tl); }, st_, 32);
   }
   double* res = reinterpret_cast<double*>(dv + uRes);
   launch_transfer_finish<T>(dctx, n, res, st_);
@@ -820,9 +827,11 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
     throw Error{6 /*MPDO_EUNSUPPORTED*/, "3-site channels need kappa_max * (Kraus operators) <= 1024"};
   const int n2 = 2 * cx, n4 = 4 * cx, nh = 8 * kx;
   const size_t sT = sizeof(cpx<T>);
-  const int spN = splits_for((long long)cx * kx), spE = splits_for((long long)kx * cx);
-  const int spH = splits_for((long long)n2 * n2), spC1 = splits_for((long long)nh * n2);
-  const int spC2 = splits_for((long long)cx * 2 * kx);
+  const int spN = tuned_splits(GS_Q3_GRAM_NE, splits_for((long long)cx * kx));
+  const int spE = tuned_splits(GS_Q3_GRAM_NE, splits_for((long long)kx * cx));
+  const int spH = tuned_splits(GS_Q3_GRAM_H, splits_for((long long)n2 * n2));
+  const int spC1 = tuned_splits(GS_Q3_GRAM_C1, splits_for((long long)nh * n2));
+  const int spC2 = tuned_splits(GS_Q3_GRAM_C2, splits_for((long long)cx * 2 * kx));
   Layout w;
   const size_t oG = w.add((size_t)m3 * 64 * 16);
   const size_t oBp = w.add((size_t)cx * kx * n2 * sT);
@@ -967,36 +976,45 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
   // outer bases
   launch_q3_prepare<T>(dctx, n, spN, spE, st_);
   launch_q3_perm_in<T>(dctx, n, st_);
-  launch_gemm<T, double, double>(dG + gN * n, 2 * n, 1, std::max(spN, spE), gemm_tiles_herm(n2), st_);
+  launch_gemm_site<T, double, double>(GS_Q3_GRAM_NE, dG + gN * n, 2 * n, 1, std::max(spN, spE),
+                          [&](int tl) { return gemm_tiles_herm(n2, tl); }, st_, 64);
   launch_reduce_splits(dG + gN * n, douts, 2 * n, n2 * n2, st_);
   launch_eigh(dE + eN * n, 2 * n, n2, status, st_);
   launch_q3_sel_env<T>(dctx, n, spH, Q3_BASIS_FLOOR, st_);
   // reduced block, middle inner truncation
-  launch_gemm<T, T, T>(dG + gXt * n, n, 1, 1, gemm_tiles(cx * 2 * kx, n4), st_);
-  launch_gemm<T, T, T>(dG + gPsi * n, n, 2, 1, gemm_tiles(n2, 4 * kx * n2), st_);
-  launch_gemm<T, double, double>(dG + gHin * n, n, 1, spH, gemm_tiles(nh, nh), st_);
+  launch_gemm_site<T, T, T>(GS_Q3_XT, dG + gXt * n, n, 1, 1,
+                          [&](int tl) { return gemm_tiles(cx * 2 * kx, n4, tl); }, st_, 64);
+  launch_gemm_site<T, T, T>(GS_Q3_PSI, dG + gPsi * n, n, 2, 1,
+                          [&](int tl) { return gemm_tiles(n2, 4 * kx * n2, tl); }, st_, 64);
+  launch_gemm_site<T, double, double>(GS_Q3_GRAM_H, dG + gHin * n, n, 1, spH,
+                          [&](int tl) { return gemm_tiles(nh, nh, tl); }, st_, 64);
   launch_reduce_splits(dG + gHin * n, douts + 2 * n, n, nh * nh, st_);
   launch_q3_gamma<T>(dctx, n, m3, st_);
   launch_eigh(dE + eG * n, n, ng, status + 2 * n, st_);
   launch_q3_sel_h<T>(dctx, n, spC1, tp, st_);
-  launch_gemm<T, T, T>(dG + gPsi2 * n, n, n2, 1, gemm_tiles(nh, n2), st_);
+  launch_gemm_site<T, T, T>(GS_Q3_PSI2, dG + gPsi2 * n, n, n2, 1,
+                          [&](int tl) { return gemm_tiles(nh, n2, tl); }, st_, 64);
   // bond i
-  launch_gemm<T, double, double>(dG + gC1 * n, n, 1, spC1, gemm_tiles_herm(n4), st_);
+  launch_gemm_site<T, double, double>(GS_Q3_GRAM_C1, dG + gC1 * n, n, 1, spC1,
+                          [&](int tl) { return gemm_tiles_herm(n4, tl); }, st_, 64);
   launch_reduce_splits(dG + gC1 * n, douts + 3 * n, n, n4 * n4, st_);
   launch_eigh(dE + e1 * n, n, n4, status + 3 * n, st_);
   launch_q3_sel_1<T>(dctx, n, spC2, tp, st_);
-  launch_gemm<double, double, T>(dG + gY1 * n, n, 1, 1, gemm_tiles(n2, n2), st_);
-  launch_gemm<T, T, T>(dG + gW1 * n, 2 * n, 1, 1,
-                       std::max(gemm_tiles(cx, 4 * kx * n2), gemm_tiles(cx * kx, n2)), st_);
+  launch_gemm_site<double, double, T>(GS_Q3_Y1, dG + gY1 * n, n, 1, 1,
+                          [&](int tl) { return gemm_tiles(n2, n2, tl); }, st_, 64);
+  launch_gemm_site<T, T, T>(GS_Q3_W1, dG + gW1 * n, 2 * n, 1, 1,
+                          [&](int tl) { return std::max(gemm_tiles(cx, 4 * kx * n2, tl), gemm_tiles(cx * kx, n2, tl)); }, st_, 64);
   launch_q3_perm_out<T>(dctx, n, st_);
   // bond i+1
-  launch_gemm<T, double, double>(dG + gC2 * n, n, 1, spC2, gemm_tiles_herm(n4), st_);
+  launch_gemm_site<T, double, double>(GS_Q3_GRAM_C2, dG + gC2 * n, n, 1, spC2,
+                          [&](int tl) { return gemm_tiles_herm(n4, tl); }, st_, 64);
   launch_reduce_splits(dG + gC2 * n, douts + 4 * n, n, n4 * n4, st_);
   launch_eigh(dE + e2 * n, n, n4, status + 4 * n, st_);
   launch_q3_sel_2<T>(dctx, n, tp, st_);
-  launch_gemm<double, double, T>(dG + gY3 * n, n, 1, 1, gemm_tiles(n2, n2), st_);
-  launch_gemm<T, T, T>(dG + gBk * n, 2 * n, 1, 1,
-                       std::max(gemm_tiles(n2, kx * cx), gemm_tiles(2 * kx * cx, cx)), st_);
+  launch_gemm_site<double, double, T>(GS_Q3_Y3, dG + gY3 * n, n, 1, 1,
+                          [&](int tl) { return gemm_tiles(n2, n2, tl); }, st_, 64);
+  launch_gemm_site<T, T, T>(GS_Q3_OUT, dG + gBk * n, 2 * n, 1, 1,
+                          [&](int tl) { return std::max(gemm_tiles(n2, kx * cx, tl), gemm_tiles(2 * kx * cx, cx, tl)); }, st_, 64);
   launch_q3_finish<T>(dctx, n, st_);
   hip_check(hipGetLastError(), "launch (3-site sublayer)");
   for (auto* g : ops)
@@ -1010,7 +1028,7 @@ void Engine<T>::sweep_step(const std::vector<int>& inst, int pass, int si, const
   const int n = (int)inst.size();
   if (n == 0) return;
   const int kx = cfg_.kap_max, cx = cfg_.chi_max;
-  const int splits = splits_for((long long)2 * kx * cx);
+  const int splits = tuned_splits(GS_SWEEP_GRAM, splits_for((long long)2 * kx * cx));
   Layout w;
   const size_t oG = w.add((size_t)cx * cx * 16);
   const size_t oGp = w.add((size_t)splits * cx * cx * 16);
@@ -1070,13 +1088,16 @@ void Engine<T>::sweep_step(const std::vector<int>& inst, int pass, int si, const
   commit(up, h, dv, u.off);
   CtxS<T>* dctx = reinterpret_cast<CtxS<T>*>(dv + uCtx);
   launch_sw_prepare<T>(dctx, n, splits, st_);
-  launch_gemm<T, double, double>(reinterpret_cast<GemmDesc*>(dv + uG), n, 1, splits, gemm_tiles_herm(cx), st_);
+  launch_gemm_site<T, double, double>(GS_SWEEP_GRAM, reinterpret_cast<GemmDesc*>(dv + uG), n, 1, splits,
+                          [&](int tl) { return gemm_tiles_herm(cx, tl); }, st_, 64);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uG), reinterpret_cast<double**>(dv + uOut), n, cx * cx,
                        st_);
   launch_eigh(reinterpret_cast<EigDesc*>(dv + uE), n, cx, sweeps_.as<int>(), st_);
   launch_sw_select<T>(dctx, n, tp, st_);
   const int tiles = std::max(gemm_tiles(2 * kx * cx, cx), gemm_tiles(cx, 2 * kx * cx));
-  launch_gemm<T, T, T>(reinterpret_cast<GemmDesc*>(dv + uA), 2 * n, 1, 1, tiles, st_);
+  const int tiles32 = std::max(gemm_tiles(2 * kx * cx, cx, 32), gemm_tiles(cx, 2 * kx * cx, 32));
+  launch_gemm_site<T, T, T>(GS_SWEEP_OUT, reinterpret_cast<GemmDesc*>(dv + uA), 2 * n, 1, 1,
+                          [&](int tl) { return tl == 64 ? tiles : tiles32; }, st_, 64);
   hip_check(hipGetLastError(), "launch (truncation sweep)");
   for (int b : inst) {
     par_[soff_[b] + si] ^= 1;

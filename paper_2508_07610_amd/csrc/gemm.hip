@@ -11,6 +11,8 @@
 // one is multiplied.  At these sizes the products are latency-bound rather
 // than MFMA-bound, so the design favours occupancy: short K slices and a
 // register budget of four waves per SIMD.
+#include <cmath>
+
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
@@ -103,9 +105,17 @@ template <typename Tin, typename Tc, int T> struct Slice {
 // computes (TM/2) x (TN/2) from 16 x 16 MFMA blocks.  The next K slice is
 // loaded into registers while the current one is multiplied from LDS.  The
 // 32 x 32 tiles (small outputs, long K) fit eight waves per SIMD, the 64 x 64
-// tiles four.
-template <typename Tin, typename Tc, typename Tout, int TM, int TN>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(TM == 32 ? 8 : 4, TM == 32 ? 8 : 4)))
+// tiles four (the FP64 three-product form, with its third accumulator set,
+// fits three and seven).
+//
+// Two forms of the complex product: G3 = false, four real products per
+// complex one (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br); G3 = true, three
+// (Gauss: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); Re = P1 - P2,
+// Im = P3 - P1 - P2), a quarter fewer MFMAs for a third accumulator set.
+template <typename Tin, typename Tc, typename Tout, int TM, int TN, bool G3>
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(
+    (G3 && sizeof(Tc) == 8) ? (TM == 64 ? 3 : 7) : (TM == 32 ? 8 : 4),
+    (G3 && sizeof(Tc) == 8) ? (TM == 64 ? 3 : 7) : (TM == 32 ? 8 : 4))))
 void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int maxTiles, long long nblocks) {
   typedef typename Mfma<Tc>::v4 v4;
   constexpr int FM = TM / 32, FN = TN / 32;  // 16 x 16 blocks per wave and dimension
@@ -174,13 +184,16 @@ void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
 
-  v4 acc_re[FM][FN], acc_im[FM][FN];
+  // four-product form: acc_re, acc_im; three-product form: acc_re = P1,
+  // acc_im = P2, acc_s = P3
+  v4 acc_re[FM][FN], acc_im[FM][FN], acc_s[G3 ? FM : 1][G3 ? FN : 1];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       acc_re[i][j] = v4{0, 0, 0, 0};
       acc_im[i][j] = v4{0, 0, 0, 0};
+      if (G3) acc_s[G3 ? i : 0][G3 ? j : 0] = v4{0, 0, 0, 0};
     }
 
   const bool aKfast = (opA == OP_N || opA == OP_C);
@@ -215,17 +228,43 @@ void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int
         br[j] = Bs_re[kb + lk][wn * (TN / 2) + j * 16 + li];
         bi[j] = Bs_im[kb + lk][wn * (TN / 2) + j * 16 + li];
       }
+      if (G3) {
+        Tc as[FM], bs[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i) as[i] = ar[i] + ai[i];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          acc_re[i][j] = Mfma<Tc>::mma(ar[i], br[j], acc_re[i][j]);
-          acc_re[i][j] = Mfma<Tc>::mma(-ai[i], bi[j], acc_re[i][j]);
-          acc_im[i][j] = Mfma<Tc>::mma(ar[i], bi[j], acc_im[i][j]);
-          acc_im[i][j] = Mfma<Tc>::mma(ai[i], br[j], acc_im[i][j]);
-        }
+        for (int j = 0; j < FN; ++j) bs[j] = br[j] + bi[j];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc_re[i][j] = Mfma<Tc>::mma(ar[i], br[j], acc_re[i][j]);
+            acc_im[i][j] = Mfma<Tc>::mma(ai[i], bi[j], acc_im[i][j]);
+            acc_s[G3 ? i : 0][G3 ? j : 0] = Mfma<Tc>::mma(as[i], bs[j], acc_s[G3 ? i : 0][G3 ? j : 0]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc_re[i][j] = Mfma<Tc>::mma(ar[i], br[j], acc_re[i][j]);
+            acc_re[i][j] = Mfma<Tc>::mma(-ai[i], bi[j], acc_re[i][j]);
+            acc_im[i][j] = Mfma<Tc>::mma(ar[i], bi[j], acc_im[i][j]);
+            acc_im[i][j] = Mfma<Tc>::mma(ai[i], br[j], acc_im[i][j]);
+          }
+      }
     }
     __syncthreads();
+  }
+  if (G3) {  // Re = P1 - P2, Im = P3 - P1 - P2
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const v4 p1 = acc_re[i][j], p2 = acc_im[i][j];
+        acc_re[i][j] = p1 - p2;
+        acc_im[i][j] = acc_s[G3 ? i : 0][G3 ? j : 0] - p1 - p2;
+      }
   }
 
   const Tc alpha = (Tc)d.alpha;
@@ -276,26 +315,67 @@ __global__ void k_reduce_splits(const GemmDesc* __restrict__ descs, double* cons
 
 int gemm_tiles(int maxM, int maxN, int tile) { return ((maxM + tile - 1) / tile) * ((maxN + tile - 1) / tile); }
 
+namespace {
+// complex-product form (3 or 4 real products) per MFMA precision and tile
+// FP32: three products (measured faster: 98 against 87 TFLOP/s on 16 products
+// of 512 x 512 x 1024); FP64: four (the three-product kernel's third
+// accumulator set costs a wave per SIMD: 46 against 51 TFLOP/s)
+int g_form[2][2] = {{3, 3}, {4, 4}};  // [fp64][tile == 64]
+}
+int gemm_form(bool fp64, int tile) { return g_form[fp64 ? 1 : 0][tile == 64 ? 1 : 0]; }
+void set_gemm_form(bool fp64, int tile, int form) { g_form[fp64 ? 1 : 0][tile == 64 ? 1 : 0] = form == 3 ? 3 : 4; }
+
 int gemm_tiles_herm(int maxN, int tile) {
   const int t = (maxN + tile - 1) / tile;
   return t * (t + 1) / 2;
 }
 
+namespace {
+SiteTune g_site[GS_N];
+}
+void set_site_tune(int site, const SiteTune& t) {
+  if (site >= 0 && site < GS_N) g_site[site] = t;
+}
+SiteTune get_site_tune(int site) { return (site >= 0 && site < GS_N) ? g_site[site] : SiteTune{}; }
+int tuned_tile(int site, int dflt) {
+  const int t = get_site_tune(site).tile;
+  return (t == 32 || t == 64) ? t : dflt;
+}
+int tuned_splits(int site, int dflt) {
+  const double f = get_site_tune(site).split_scale;
+  if (!(f > 0)) return dflt;
+  const int s = (int)std::lround(dflt * f);
+  return s < 1 ? 1 : (s > 64 ? 64 : s);
+}
+
 template <typename Tin, typename Tc, typename Tout>
 void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s,
-                 int tile) {
+                 int tile, int site) {
   if (nitems <= 0 || maxTiles <= 0) return;
   const long long blocks = (long long)nitems * maxBatch * maxSplits * maxTiles;
   if (blocks <= 0) return;
   const long long grid = (blocks + NXCD - 1) / NXCD * NXCD;
   const int cls = sizeof(Tc) == 8 ? PC_GEMM_F64 : PC_GEMM_F32;
+  if (site >= 0) prof_set_site(site);
   const int tok = prof_begin(cls, s);
-  if (tile == 32)
-    hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 32, 32>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs, maxBatch,
-                       maxSplits, maxTiles, blocks);
-  else
-    hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 64, 64>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs, maxBatch,
-                       maxSplits, maxTiles, blocks);
+  prof_set_site(GS_OTHER);  // a call site labels only the launch that follows it
+  const int sf = get_site_tune(site).form;
+  const bool g3 = (sf == 3 || sf == 4) ? sf == 3 : gemm_form(sizeof(Tc) == 8, tile) == 3;
+  if (tile == 32) {
+    if (g3)
+      hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 32, 32, true>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs,
+                         maxBatch, maxSplits, maxTiles, blocks);
+    else
+      hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 32, 32, false>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs,
+                         maxBatch, maxSplits, maxTiles, blocks);
+  } else {
+    if (g3)
+      hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 64, 64, true>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs,
+                         maxBatch, maxSplits, maxTiles, blocks);
+    else
+      hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 64, 64, false>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs,
+                         maxBatch, maxSplits, maxTiles, blocks);
+  }
   prof_end_gemm(tok, cls, d_descs, nitems, (int)sizeof(cpx<Tin>), (int)sizeof(cpx<Tout>), s);
 }
 
@@ -308,9 +388,9 @@ void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int ni
                      d_outs, maxCount);
 }
 
-template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int);
-template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, hipStream_t, int);
-template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int);
-template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, hipStream_t, int);
+template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int, int);
+template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, hipStream_t, int, int);
+template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int, int);
+template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, hipStream_t, int, int);
 
 }  // namespace mpdo

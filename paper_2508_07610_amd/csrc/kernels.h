@@ -13,10 +13,36 @@ namespace mpdo {
 // of such items needs only gemm_tiles_herm of the largest N.
 // Tin: input precision, Tc: MFMA precision, Tout: output precision.
 int gemm_tiles(int maxM, int maxN, int tile = 64);
+// Complex-product form of the launches of one MFMA precision and tile size:
+// 4 (four real products) or 3 (Gauss's three); process-wide, default 4.
+int gemm_form(bool fp64, int tile);
+void set_gemm_form(bool fp64, int tile, int form);
 int gemm_tiles_herm(int maxN, int tile = 64);
 template <typename Tin, typename Tc, typename Tout>
 void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s,
-                 int tile = 64);
+                 int tile = 64, int site = -1);
+
+// Per call site of the MPDO update (a GemmSite of profile.h), the settings
+// an autotuner may choose: the tile edge (32 or 64), the complex-product form
+// (3 or 4) and a factor on the split-K count; 0 keeps the built-in choice.
+struct SiteTune {
+  int tile = 0;
+  int form = 0;
+  double split_scale = 0;
+};
+void set_site_tune(int site, const SiteTune& t);
+SiteTune get_site_tune(int site);
+int tuned_tile(int site, int dflt);
+int tuned_splits(int site, int dflt);
+
+// A call site's launch: its tuned tile (else `dflt_tile`), the tile count for
+// that tile from tiles_of(tile), and its tuned form.
+template <typename Tin, typename Tc, typename Tout, typename F>
+void launch_gemm_site(int site, const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, F tiles_of,
+                      hipStream_t s, int dflt_tile = 64) {
+  const int tile = tuned_tile(site, dflt_tile);
+  launch_gemm<Tin, Tc, Tout>(d_descs, nitems, maxBatch, maxSplits, tiles_of(tile), s, tile, site);
+}
 
 // out[item] = sum over splits of the partial products of descs[item]
 // (complex double, dense M x ldc).

@@ -28,6 +28,23 @@ void prof_end_gemm(int token, int cls, const GemmDesc* d_descs, int nitems, int 
 // writing the k vectors.  Items outside [nlo, nhi] are skipped.
 void prof_end_eig(int token, int cls, const EigDesc* d_descs, int nitems, int nlo, int nhi, hipStream_t s);
 
+// Call site of the following GEMM launches on this thread (a label of the
+// contraction, see GemmSite); each site's time and work are also summed.
+enum GemmSite : int {
+  GS_OTHER = 0,
+  GS_Q1_GRAM = 1, GS_Q1_PROJ = 2,
+  GS_Q2_GRAM_E = 3, GS_Q2_THETA = 4, GS_Q2_GRAM_H = 5, GS_Q2_THETA2 = 6, GS_Q2_GRAM_C = 7, GS_Q2_X = 8,
+  GS_Q2_OUT = 9,
+  GS_TRANSFER_R = 10, GS_TRANSFER_L = 11,
+  GS_Q3_GRAM_NE = 12, GS_Q3_XT = 13, GS_Q3_PSI = 14, GS_Q3_GRAM_H = 15, GS_Q3_PSI2 = 16, GS_Q3_GRAM_C1 = 17,
+  GS_Q3_Y1 = 18, GS_Q3_W1 = 19, GS_Q3_GRAM_C2 = 20, GS_Q3_Y3 = 21, GS_Q3_OUT = 22,
+  GS_SWEEP_GRAM = 23, GS_SWEEP_OUT = 24,
+  GS_N = 25
+};
+void prof_set_site(int site);
+// Sums of one GEMM call site (both precisions); synchronises the device.
+void prof_read_site(int site, int* launches, double* ms, double* flops);
+
 bool prof_enabled();
 void prof_reset(bool on);
 // Sums of one class; synchronises the device.

@@ -14,15 +14,22 @@ namespace {
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
   int cls = 0;
+  int site = -1;
 };
+
+// device counters: flops[PC_NCLASS], bytes[PC_NCLASS], then flops and bytes per GEMM site
+constexpr int NCOUNT = 2 * PC_NCLASS + 2 * GS_N;
 
 struct Prof {
   std::mutex mu;
   bool on = false;
   std::vector<EventPair> ev;
   int launches[PC_NCLASS] = {0, 0, 0, 0};
-  double* dcount = nullptr;  // device: flops[PC_NCLASS], bytes[PC_NCLASS]
+  int site_launches[GS_N] = {};
+  double* dcount = nullptr;
 };
+
+thread_local int t_site = GS_OTHER;
 
 Prof& P() {
   static Prof p;
@@ -97,8 +104,9 @@ void prof_reset(bool on) {
   }
   p.ev.clear();
   for (int c = 0; c < PC_NCLASS; ++c) p.launches[c] = 0;
-  if (!p.dcount && hipMalloc(&p.dcount, sizeof(double) * 2 * PC_NCLASS) != hipSuccess) p.dcount = nullptr;
-  if (p.dcount) (void)hipMemset(p.dcount, 0, sizeof(double) * 2 * PC_NCLASS);
+  for (int c = 0; c < GS_N; ++c) p.site_launches[c] = 0;
+  if (!p.dcount && hipMalloc(&p.dcount, sizeof(double) * NCOUNT) != hipSuccess) p.dcount = nullptr;
+  if (p.dcount) (void)hipMemset(p.dcount, 0, sizeof(double) * NCOUNT);
   p.on = on && p.dcount != nullptr;
 }
 
@@ -108,6 +116,7 @@ int prof_begin(int cls, hipStream_t s) {
   std::lock_guard<std::mutex> g(p.mu);
   EventPair e;
   e.cls = cls;
+  if (cls == PC_GEMM_F64 || cls == PC_GEMM_F32) e.site = t_site;
   if (hipEventCreate(&e.a) != hipSuccess) return -1;
   if (hipEventCreate(&e.b) != hipSuccess) {
     (void)hipEventDestroy(e.a);
@@ -123,7 +132,10 @@ static void end_common(int token, int cls, hipStream_t s) {
   std::lock_guard<std::mutex> g(p.mu);
   (void)hipEventRecord(p.ev[token].b, s);
   p.launches[cls] += 1;
+  if (p.ev[token].site >= 0) p.site_launches[p.ev[token].site] += 1;
 }
+
+void prof_set_site(int site) { t_site = (site >= 0 && site < GS_N) ? site : GS_OTHER; }
 
 void prof_end_gemm(int token, int cls, const GemmDesc* d_descs, int nitems, int in_bytes, int out_bytes,
                    hipStream_t s) {
@@ -132,6 +144,10 @@ void prof_end_gemm(int token, int cls, const GemmDesc* d_descs, int nitems, int 
   double* c = P().dcount;
   hipLaunchKernelGGL(k_account_gemm, dim3(1), dim3(AT), 0, s, d_descs, nitems, in_bytes, out_bytes, c + cls,
                      c + PC_NCLASS + cls);
+  const int site = P().ev[token].site;
+  if (site >= 0)
+    hipLaunchKernelGGL(k_account_gemm, dim3(1), dim3(AT), 0, s, d_descs, nitems, in_bytes, out_bytes,
+                       c + 2 * PC_NCLASS + site, c + 2 * PC_NCLASS + GS_N + site);
 }
 
 void prof_end_eig(int token, int cls, const EigDesc* d_descs, int nitems, int nlo, int nhi, hipStream_t s) {
@@ -152,12 +168,29 @@ void prof_read(int cls, int* launches, double* ms, double* flops, double* bytes)
     float x = 0;
     if (hipEventElapsedTime(&x, e.a, e.b) == hipSuccess) t += x;
   }
-  double h[2 * PC_NCLASS] = {0};
+  double h[NCOUNT] = {0};
   if (p.dcount) (void)hipMemcpy(h, p.dcount, sizeof(h), hipMemcpyDeviceToHost);
   if (launches) *launches = p.launches[cls];
   if (ms) *ms = t;
   if (flops) *flops = h[cls];
   if (bytes) *bytes = h[PC_NCLASS + cls];
+}
+
+void prof_read_site(int site, int* launches, double* ms, double* flops) {
+  Prof& p = P();
+  std::lock_guard<std::mutex> g(p.mu);
+  (void)hipDeviceSynchronize();
+  double t = 0;
+  for (auto& e : p.ev) {
+    if (e.site != site) continue;
+    float x = 0;
+    if (hipEventElapsedTime(&x, e.a, e.b) == hipSuccess) t += x;
+  }
+  double h[NCOUNT] = {0};
+  if (p.dcount) (void)hipMemcpy(h, p.dcount, sizeof(h), hipMemcpyDeviceToHost);
+  if (launches) *launches = p.site_launches[site];
+  if (ms) *ms = t;
+  if (flops) *flops = h[2 * PC_NCLASS + site];
 }
 
 }  // namespace mpdo

@@ -24,7 +24,7 @@ EXPORTED = (
     "mpdo_channel_info", "mpdo_channel_destroy", "mpdo_apply_gate", "mpdo_apply_channel", "mpdo_flush",
     "mpdo_truncate", "mpdo_expect", "mpdo_expect_products", "mpdo_fidelity_ghz", "mpdo_trace", "mpdo_dims",
     "mpdo_bond_weights", "mpdo_to_dense", "mpdo_probabilities", "mpdo_sample", "mpdo_batch_run",
-    "mpdo_stats", "mpdo_release_cached_memory",
+    "mpdo_stats", "mpdo_release_cached_memory", "mpdo_batch_run_dense", "mpdo_tune_set", "mpdo_tune_get",
 )
 
 
@@ -142,6 +142,10 @@ def lib() -> ctypes.CDLL:
         "mpdo_sample": [vp, pd, i32, ctypes.POINTER(ctypes.c_uint8), pd],
         "mpdo_batch_run": [ctypes.POINTER(mpdo_config), ctypes.POINTER(mpdo_program), i32, vp, i32, pd, i32,
                            ctypes.POINTER(vp), i32, vp, i32, vp],
+        "mpdo_batch_run_dense": [ctypes.POINTER(mpdo_config), ctypes.POINTER(mpdo_program), i32, vp, i32, pd, i32,
+                                 ctypes.POINTER(vp), i32, vp, vp],
+        "mpdo_tune_set": [i32, i32, i32, dbl],
+        "mpdo_tune_get": [i32, pi, pi, pd],
         "mpdo_profile_enable": [i32],
         "mpdo_profile_read": [i32, pi, pd, pd, pd],
         "mpdo_mlp_create": [pi, i32, i32, vp, ctypes.POINTER(vp)],
@@ -451,6 +455,46 @@ def batch_run(programs, params, channels: Sequence[Channel], observables, chi_ma
     return out[:total]
 
 
+def batch_run_dense(programs, params, channels: Sequence[Channel], chi_max: int, kappa_max: int,
+                    max_kraus: int = 16, svd_cutoff: float = 1e-14, kappa_cutoff: float = 1e-14, prec: int = C128,
+                    stream=None):
+    """Run many programs (n <= 12) through mpdo_batch_run_dense and return the
+    list of their dense density matrices (unnormalised) as torch complex128
+    CUDA tensors (2^n, 2^n) viewing one device buffer."""
+    import torch
+    plan = programs if isinstance(programs, BatchPlan) else BatchPlan(programs, [np.zeros((0,))] * len(programs),
+                                                                     params is not None)
+    ns = [plan.progs[b].n for b in range(plan.ninst)]
+    sizes = [4 ** n for n in ns]
+    buf = torch.zeros(sum(sizes), dtype=torch.complex128, device="cuda")
+    chans = (ctypes.c_void_p * max(1, len(channels)))(*[c.handle.value for c in channels])
+    cfg = mpdo_config(0, chi_max, kappa_max, max_kraus, svd_cutoff, kappa_cutoff, prec)
+    pptr, pstride = None, 0
+    if params is not None:
+        if params.ndim != 2 or params.shape[0] < plan.ninst or params.dtype != torch.float64 or not params.is_cuda:
+            raise ValueError("params must be a float64 CUDA tensor of shape (>= ninst, P)")
+        params = params.contiguous()
+        pptr, pstride = params.data_ptr(), params.shape[1]
+    check(lib().mpdo_batch_run_dense(ctypes.byref(cfg), plan.progs, plan.ninst, pptr, pstride, _dptr(plan.fbuf),
+                                     plan.nfixed, chans, len(channels), buf.data_ptr(), stream_handle(stream)))
+    out, off = [], 0
+    for n, sz in zip(ns, sizes):
+        out.append(buf[off: off + sz].view(2 ** n, 2 ** n))
+        off += sz
+    return out
+
+
+def tune_set(site: int, tile: int = 0, form: int = 0, split_scale: float = 0.0) -> None:
+    """GEMM settings of one call site (see mpdo_tune_set); zeros restore the built-in choice."""
+    check(lib().mpdo_tune_set(site, tile, form, float(split_scale)))
+
+
+def tune_get(site: int):
+    t, f, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    check(lib().mpdo_tune_get(site, ctypes.byref(t), ctypes.byref(f), ctypes.byref(s)))
+    return t.value, f.value, s.value
+
+
 PROF_GEMM_F64, PROF_GEMM_F32, PROF_EIG_REG, PROF_EIG_GLOBAL = range(4)
 PROF_NAMES = {PROF_GEMM_F64: "k_gemm (FP64 MFMA)", PROF_GEMM_F32: "k_gemm (FP32 MFMA)",
               PROF_EIG_REG: "k_heev_reg", PROF_EIG_GLOBAL: "k_heev_global"}
@@ -499,6 +543,10 @@ def _testing_lib():
         L.mpdo_test_eig_residual_bound.restype = ctypes.c_int
         L.mpdo_test_fail_next_update.argtypes = [i32]
         L.mpdo_test_fail_next_update.restype = ctypes.c_int
+        L.mpdo_test_profile_site.argtypes = [i32, ctypes.POINTER(i32), pd, pd]
+        L.mpdo_test_profile_site.restype = ctypes.c_int
+        L.mpdo_test_gemm_form.argtypes = [i32, i32, i32, ctypes.POINTER(i32)]
+        L.mpdo_test_gemm_form.restype = ctypes.c_int
         L._testing_sig = True
     return L
 
@@ -507,6 +555,35 @@ def test_eig_residual_bound(rtol: float) -> None:
     """Residual bound of the eigensolver (0: the default 1e-9; negative:
     every eigenpair fails its check)."""
     check(_testing_lib().mpdo_test_eig_residual_bound(float(rtol)))
+
+
+GEMM_SITES = ("other", "q1_gram", "q1_proj", "q2_gram_E", "q2_theta", "q2_gram_H", "q2_theta2", "q2_gram_C",
+              "q2_X", "q2_out", "transfer_R", "transfer_L", "q3_gram_NE", "q3_Xt", "q3_Psi", "q3_gram_H", "q3_Psi2",
+              "q3_gram_C1", "q3_Y1", "q3_W1", "q3_gram_C2", "q3_Y3", "q3_out", "sweep_gram", "sweep_out")
+
+
+def profile_sites() -> dict:
+    """Per call site of the GEMM: launches, summed event ms, algorithmic
+    flops and TFLOP/s (sites with launches only)."""
+    L = _testing_lib()
+    out = {}
+    for i, name in enumerate(GEMM_SITES):
+        n = ctypes.c_int32()
+        ms, fl = ctypes.c_double(), ctypes.c_double()
+        check(L.mpdo_test_profile_site(i, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+        if n.value:
+            out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value,
+                         "tflops": fl.value / (ms.value * 1e-3) / 1e12 if ms.value > 0 else 0.0}
+    return out
+
+
+def gemm_form(prec: int, tile: int, form: int) -> int:
+    """Set the complex-product form (3 or 4 real products) of the GEMM
+    launches of one MFMA precision (0: FP64, 1: FP32) and tile edge; returns
+    the previous form."""
+    prev = ctypes.c_int32()
+    check(_testing_lib().mpdo_test_gemm_form(prec, tile, form, ctypes.byref(prev)))
+    return prev.value
 
 
 def test_fail_next_update(status: int) -> None:

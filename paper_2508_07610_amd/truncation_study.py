@@ -10,8 +10,13 @@ averaged over many circuits.
 The crosstalk rotation acts on a qubit the CNOT does not touch, so it is
 applied as a unitary on that qubit right after the CNOT (the same map as the
 three-qubit gate of Fig. `randomCirc_fig`(b)).  Every simulation runs on the
-device; the fidelity is a host-side measurement of the dense results
-(n <= 12)."""
+device; the fidelity is a host-side measurement (NumPy eigendecompositions)
+of the dense results (n <= 12).
+
+``run_batched`` is the study at the paper's scale: all circuits of one
+(Q, depth) point and one (chi, kappa) limit in one ``mpdo_batch_run_dense``
+call (the lossless reference at chi = kappa = 64 is one more such call), the
+paper's 1,000 circuits per point."""
 from __future__ import annotations
 
 import math
@@ -76,3 +81,65 @@ def run(q: int, depth: int, limits: Sequence[Tuple[int, int]], ncirc: int, seed:
         ch.close()
     return {f"chi={c},kappa={k}": {"mean": float(np.mean(v)), "std": float(np.std(v)), "min": float(np.min(v))}
             for (c, k), v in fid.items()}
+
+
+def uhlmann_batch(rho: np.ndarray, sigma: np.ndarray) -> np.ndarray:
+    """Eq. (23) for stacks (B, d, d) of density matrices (normalised here):
+    F = (tr sqrt(sqrt(rho) sigma sqrt(rho)))^2, by two batched Hermitian
+    eigendecompositions on the host."""
+    rho = rho / np.trace(rho, axis1=1, axis2=2).real[:, None, None]
+    sigma = sigma / np.trace(sigma, axis1=1, axis2=2).real[:, None, None]
+    rho = 0.5 * (rho + np.conj(np.swapaxes(rho, 1, 2)))
+    w, v = np.linalg.eigh(rho)
+    sq = (v * np.sqrt(np.clip(w, 0.0, None))[:, None, :]) @ np.conj(np.swapaxes(v, 1, 2))
+    m = sq @ sigma @ sq
+    m = 0.5 * (m + np.conj(np.swapaxes(m, 1, 2)))
+    ev = np.clip(np.linalg.eigvalsh(m), 0.0, None)
+    return np.sum(np.sqrt(ev), axis=1) ** 2
+
+
+def run_batched(q: int, depth: int, limits: Sequence[Tuple[int, int]], ncirc: int = 1000, seed: int = 0,
+                full: Tuple[int, int] = (64, 64), prec: int = M.C128) -> Dict:
+    """The Sec. IV.C study at scale: `ncirc` seeded circuits of one (q, depth)
+    point, each (chi, kappa) of `limits` and the lossless `full` limits run
+    as one batch each; returns per limit the mean, standard deviation and
+    minimum of the Uhlmann fidelity against the lossless state, and the
+    device seconds of the batches."""
+    import time
+    import torch
+    rng = W.rng_for(4500 + 100 * q + depth + 10000 * seed)
+    progs = [circuit(q, depth, rng) for _ in range(ncirc)]
+    chans = [M.Channel(progs[0].chis[0], 1), M.Channel(progs[0].chis[1], 2)]
+    plan = M.BatchPlan(progs, [np.zeros((0,))] * ncirc, use_params=False)
+    kw = dict(max_kraus=16, svd_cutoff=1e-14, kappa_cutoff=1e-14, prec=prec)
+    t = {}
+
+    def dense(chi, kap):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mats = M.batch_run_dense(plan, None, chans, chi_max=chi, kappa_max=kap, **kw)
+        torch.cuda.synchronize()
+        t[f"chi={chi},kappa={kap}"] = time.perf_counter() - t0
+        return torch.stack(mats).cpu().numpy()
+
+    rho = dense(*full)
+    out = {}
+    for lim in limits:
+        f = uhlmann_batch(rho, dense(*lim))
+        out[f"chi={lim[0]},kappa={lim[1]}"] = {"mean": float(np.mean(f)), "std": float(np.std(f)),
+                                               "min": float(np.min(f))}
+    for ch in chans:
+        ch.close()
+    return {"fidelity": out, "device_seconds": t, "circuits": ncirc}
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+    lims = [(2, 2), (4, 4), (8, 8), (16, 4), (16, 16)]
+    res = {}
+    for q in (3, 6):
+        for depth in (2, 4, 6, 8, 10):
+            res[f"Q={q},depth={depth}"] = run_batched(q, depth, lims, ncirc=int(sys.argv[1]) if len(sys.argv) > 1
+                                                      else 1000)
+            print(f"Q={q} depth={depth}", json.dumps(res[f"Q={q},depth={depth}"]["fidelity"]), flush=True)

@@ -35,6 +35,31 @@ def test_gemm_fp64(M_, N_, K_, opA, opB, tile):
     assert err <= 1e-12 * max(1.0, float(np.abs(ref).max())) * np.sqrt(K_), (err, bad)
 
 
+@pytest.mark.parametrize("M_,N_,K_", [(1, 1, 1), (65, 70, 33), (130, 37, 257), (5, 300, 9)])
+@pytest.mark.parametrize("opA,opB", [(0, 0), (2, 1), (3, 0)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("tile", [64, 32])
+def test_gemm_three_product_form(M_, N_, K_, opA, opB, prec, tile):
+    """Gauss's three-product form of the complex product against NumPy, in
+    every precision (FP64 MFMA for prec 0 and 2, FP32 for prec 1)."""
+    require_gpu()
+    fp64 = 0 if prec != 1 else 1
+    prev = M.gemm_form(fp64, tile, 3)
+    try:
+        rng = np.random.default_rng(M_ * 100 + N_ + K_ + prec)
+        A = _rand((K_, M_) if opA in (1, 3) else (M_, K_), rng)
+        B = _rand((N_, K_) if opB in (1, 3) else (K_, N_), rng)
+        C = M.test_gemm(prec, opA, opB, M_, N_, K_, A, B, alpha=0.5, tile=tile)
+    finally:
+        M.gemm_form(fp64, tile, prev)
+    if prec:
+        A, B = A.astype(np.complex64).astype(np.complex128), B.astype(np.complex64).astype(np.complex128)
+    ref = 0.5 * _op(A, opA) @ _op(B, opB)
+    tol = (3e-6 if prec == 1 else 3e-12) * max(1.0, float(np.abs(ref).max())) * np.sqrt(K_)
+    err = float(np.abs(C - ref).max())
+    assert err <= tol, (err, tol)
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("tile", [64, 32])
 def test_gemm_fp32_paths(prec, tile):
