@@ -6,11 +6,13 @@ angles, a process-tomography channel after every gate).  The plain optimizer
 ascends it with exact parameter-shift gradients: for an RY angle, followed
 by a channel that does not depend on it, dF/dtheta_k =
 [F(theta + pi/2 e_k) - F(theta - pi/2 e_k)] / 2, so one step is one
-``mpdo_batch_run`` over 2P + 1 parameter rows.  The surrogate-assisted
-optimizer trains the MLP (``surrogate.MLP``) on every MPDO evaluation it has
-made, proposes a step by ascending the network's prediction, and accepts it
-only if one MPDO evaluation confirms an improvement; otherwise it falls back
-to a parameter-shift step.  Every accepted point is an MPDO-verified value.
+``mpdo_batch_run`` over 2P + 1 parameter rows.  The surrogate (``surrogate.MLP``)
+is first trained on MPDO-generated (theta, noise) -> observables data
+(``generate_dataset``, ``pretrain``); in the variational loop it is refit on
+the MPDO rows around the iterate and proposes steps by ascending its own
+prediction, and the MPDO verifies every proposal (``surrogate_optimize``);
+every accepted point is an MPDO-verified value and the plain parameter-shift
+step is the fallback.
 
 Noise inputs (the 2n = 24 strengths of the surrogate's input at n = 12):
 n per-qubit scales of the 1q channel, n - 1 per-bond scales of the 2q
@@ -163,28 +165,34 @@ def plain_optimize(ev: AnsatzEvaluator, theta0: np.ndarray, target: float, max_s
     theta = theta0.copy()
     opt = Adam(theta.size, lr)
     t0 = time.perf_counter()
+    e0 = ev.evaluations
     hist: List[tuple] = []
     best = -1.0
     for step in range(max_steps):
         F, g, _, _ = parameter_shift(ev, theta)
         best = max(best, F)
-        hist.append((time.perf_counter() - t0, F, ev.evaluations))
+        hist.append((time.perf_counter() - t0, F, ev.evaluations - e0))
         if F >= target or time.perf_counter() - t0 > time_limit:
             break
         theta = opt.step(theta, g)
     reached = best >= target
-    return {"reached": reached, "time": hist[-1][0] if reached else None, "best": best, "steps": len(hist),
-            "history": hist, "theta": theta, "evaluations": ev.evaluations}
+    tr = next((h[0] for h in hist if h[1] >= target), None)
+    rr = next((h[2] for h in hist if h[1] >= target), None)
+    return {"reached": reached, "time": tr, "rows_to_target": rr, "best": best, "steps": len(hist),
+            "history": hist, "theta": theta, "evaluations": ev.evaluations - e0}
 
 
-def encode(thetas: np.ndarray, noises: np.ndarray) -> np.ndarray:
-    """Network input: angles reduced to [-pi, pi) and divided by pi, then the noise scales."""
-    th = np.mod(thetas + math.pi, 2 * math.pi) / math.pi - 1.0
+def encode(thetas: np.ndarray, noises: np.ndarray, center: Optional[np.ndarray] = None) -> np.ndarray:
+    """Network input: each angle's offset from `center` (0 if None) reduced to
+    [-pi, pi) and divided by pi, then the noise strengths."""
+    d = thetas if center is None else thetas - center
+    th = np.mod(d + math.pi, 2 * math.pi) / math.pi - 1.0
     return np.concatenate([th, noises], axis=1).astype(np.float32)
 
 
-def generate_dataset(ev: AnsatzEvaluator, count: int, rng: np.random.Generator, batch: int = 256):
-    """(theta ~ U[0, 2 pi), noise scales ~ U[0.5, 2]) -> MPDO outputs."""
+def generate_dataset(ev: AnsatzEvaluator, count: int, rng: np.random.Generator, batch: int = 2048):
+    """The surrogate's data: (theta ~ U[0, 2 pi)^P, noise strengths ~ U[0.5, 2]^2n)
+    -> MPDO outputs (GHZ fidelity, <Z_i Z_i+1>), `batch` rows per mpdo_batch_run."""
     X, Y = [], []
     for a in range(0, count, batch):
         k = min(batch, count - a)
@@ -196,60 +204,155 @@ def generate_dataset(ev: AnsatzEvaluator, count: int, rng: np.random.Generator, 
     return np.concatenate(X), np.concatenate(Y)
 
 
-def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: float, max_steps: int = 200,
-                       lr: float = 0.05, fit_steps: int = 150, fit_lr: float = 2e-3,
-                       scales=(1.0, 2.0, 3.0, 4.0, 6.0, 8.0), window: int = 4096, time_limit: float = 600.0,
-                       rng: Optional[np.random.Generator] = None) -> dict:
-    """Surrogate-assisted ascent.  Each iteration computes the parameter-shift
-    gradient (2P + 1 MPDO rows, which also label the network's training data
-    around the iterate), refits the network on the samples seen so far, and
-    lets it choose the length of the Adam step: the candidates
-    theta + a * delta (delta the plain Adam step, a in `scales`) are ranked by
-    the predicted fidelity, and the MPDO evaluates the network's choice next to
-    the plain step (a = 1); the better verified point is taken.  With a = 1
-    always chosen this is the plain optimizer, so the network can only change
-    which MPDO-verified point is kept.  Returns the plain_optimize record plus
-    the choices and the network's error on the verified points."""
+def pretrain(net, X: np.ndarray, Y: np.ndarray, steps: int, batch: int = 512, lr: float = 1e-3,
+             holdout: float = 0.1, rng: Optional[np.random.Generator] = None) -> dict:
+    """Train on (X, Y) with the library's kernels (cosine learning-rate
+    decay); report the held-out mean absolute error and R^2 per output
+    group (fidelity; correlators)."""
     import torch
     rng = rng or np.random.default_rng(0)
+    nv = int(len(X) * holdout)
+    perm = rng.permutation(len(X))
+    va, tr = perm[:nv], perm[nv:]
+    xd = torch.tensor(X[tr], device="cuda")
+    yd = torch.tensor(Y[tr], device="cuda")
+    b = min(batch, net.max_batch, len(tr))
+    t0 = time.perf_counter()
+    for it in range(steps):
+        idx = torch.randint(0, xd.shape[0], (b,), device="cuda")
+        net.train_step(xd[idx].contiguous(), yd[idx].contiguous(),
+                       lr * 0.5 * (1 + math.cos(math.pi * it / steps)), want_loss=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    xv = torch.tensor(X[va], device="cuda")
+    pv = np.concatenate([net.forward(xv[a: a + net.max_batch].contiguous()).cpu().numpy()
+                         for a in range(0, nv, net.max_batch)])
+    yv = Y[va]
+    mae = np.abs(pv - yv).mean(0)
+    r2 = 1 - ((pv - yv) ** 2).mean(0) / np.maximum(yv.var(0), 1e-30)
+    return {"train_seconds": dt, "steps": steps, "holdout": nv, "mae_fidelity": float(mae[0]),
+            "mae_correlators": float(mae[1:].mean()), "r2_fidelity": float(r2[0]),
+            "r2_correlators": float(r2[1:].mean()), "fidelity_mean": float(yv[:, 0].mean()),
+            "fidelity_max": float(yv[:, 0].max())}
+
+
+def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: float, max_rows: int = 20000,
+                       lr: float = 0.05, fit_steps: int = 150, fit_lr: float = 1e-3, window: int = 4,
+                       inner: int = 60, inner_lr: float = 0.02, cand_at=(5, 10, 20, 30, 45, 60),
+                       out_scale: float = 10.0, time_limit: float = 600.0) -> dict:
+    """Surrogate-assisted ascent: the network proposes steps, the MPDO judges.
+
+    Every parameter-shift evaluation (2P + 1 rows: the exact gradient, which
+    also labels data around the iterate) is added to a buffer.  The network is
+    refit on the buffer's last `window` gradient evaluations in coordinates
+    centred on the iterate (inputs: angle offsets, outputs: the change of
+    fidelity, scaled), then its input gradient is ascended from the iterate
+    on the device (Adam, `inner` steps); the points reached after the steps
+    in `cand_at`, and the plain Adam step, are evaluated together by one
+    MPDO batch.  The best verified point is taken if it beats the iterate;
+    when it is one of the network's points, the network proposes again from
+    there without a new gradient, otherwise the next iteration starts with a
+    parameter-shift evaluation.  The network is refit only after a gradient
+    evaluation; a proposal round that continues from an accepted point of the
+    network keeps ascending in the same coordinates.  Every accepted point is
+    an MPDO value; the plain step is the fallback.  Returns the record of plain_optimize plus
+    the surrogate's proposal statistics and its error on verified points."""
+    import torch
+    P = ev.P
+    nn_ = n_noise(ev.n)
+    noise = np.ones((1, nn_))
+    opt = Adam(P, lr)
     theta = theta0.copy()
-    opt = Adam(theta.size, lr)
-    noise = np.ones((1, n_noise(ev.n)))
-    X = np.zeros((0, ev.P + n_noise(ev.n)), np.float32)
-    Y = np.zeros((0, ev.n), np.float32)
+    Xr = np.zeros((0, P))
+    Yr = np.zeros((0,))
     t0 = time.perf_counter()
     hist: List[tuple] = []
-    picks, errs = [], []
+    counts = {"gradients": 0, "proposal_rounds": 0, "surrogate_accepted": 0, "plain_accepted": 0}
+    errs = []
     best = -1.0
-    for step in range(max_steps):
-        F, g, rows, out = parameter_shift(ev, theta)
-        X = np.concatenate([X, encode(rows, np.repeat(noise, rows.shape[0], 0))])[-window:]
-        Y = np.concatenate([Y, out.astype(np.float32)])[-window:]
-        best = max(best, F)
-        hist.append((time.perf_counter() - t0, F, ev.evaluations))
-        if F >= target or time.perf_counter() - t0 > time_limit:
+    need_grad = True
+    Fc = -1.0
+    plain_next = theta
+    gy = torch.zeros((1, net.widths[-1]), dtype=torch.float32, device="cuda")
+    gy[0, 0] = 1.0
+    nz_t = torch.tensor(noise.astype(np.float32), device="cuda")
+    rows_per_grad = 2 * P + 1
+    e0 = ev.evaluations
+    while ev.evaluations - e0 < max_rows:
+        if need_grad:
+            F, g, rows, out = parameter_shift(ev, theta)
+            counts["gradients"] += 1
+            Xr = np.concatenate([Xr, rows])[-window * rows_per_grad * 2:]
+            Yr = np.concatenate([Yr, out[:, 0]])[-window * rows_per_grad * 2:]
+            Fc = F
+            best = max(best, F)
+            hist.append((time.perf_counter() - t0, F, ev.evaluations - e0))
+            if F >= target or time.perf_counter() - t0 > time_limit:
+                break
+            plain_next = opt.step(theta, g)
+        if need_grad:
+            # refit around the iterate (inputs: offsets from it; output: the
+            # change of fidelity); the ascent starts there
+            center, Fref = theta.copy(), Fc
+            xd = torch.tensor(encode(Xr, np.repeat(noise, len(Xr), 0), center), device="cuda")
+            yt = np.zeros((len(Xr), net.widths[-1]), np.float32)
+            yt[:, 0] = (Yr - Fref) * out_scale
+            yd = torch.tensor(yt, device="cuda")
+            nb = min(net.max_batch, len(Xr), 512)
+            for _ in range(fit_steps):
+                idx = torch.randint(0, xd.shape[0], (nb,), device="cuda")
+                net.train_step(xd[idx].contiguous(), yd[idx].contiguous(), fit_lr, want_loss=False)
+            x = torch.zeros((1, P), dtype=torch.float32, device="cuda")
+            m = torch.zeros_like(x)
+            v = torch.zeros_like(x)
+            t_in = 0
+        # ascend the network on the device from the last accepted point
+        cands = []
+        for t in range(t_in + 1, t_in + inner + 1):
+            xin = torch.cat([x / math.pi, nz_t], dim=1).contiguous()
+            _, _, dx, _ = net.backward(xin, gy=gy, want_dx=True, want_loss=False)
+            gr = dx[:, :P] / math.pi
+            m.mul_(0.9).add_(0.1 * gr)
+            v.mul_(0.999).add_(0.001 * gr * gr)
+            x = x + inner_lr * (m / (1 - 0.9 ** t)) / (torch.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
+            if t - t_in in cand_at:
+                cands.append(x.clone())
+        t_in += inner
+        xs = torch.cat(cands).double().cpu().numpy()
+        pred = net.forward(torch.cat([torch.cat(cands) / math.pi, nz_t.repeat(len(cands), 1)],
+                                     dim=1).contiguous()).cpu().numpy()[:, 0] / out_scale + Fref
+        C = center[None, :] + xs
+        if need_grad:
+            C = np.concatenate([C, plain_next[None, :]])
+        out = ev(C)
+        counts["proposal_rounds"] += 1
+        errs.extend(np.abs(pred - out[: len(cands), 0]).tolist())
+        Xr = np.concatenate([Xr, C])[-window * rows_per_grad * 2:]
+        Yr = np.concatenate([Yr, out[:, 0]])[-window * rows_per_grad * 2:]
+        b = int(np.argmax(out[:, 0]))
+        if out[b, 0] > Fc:
+            theta, Fc = C[b], float(out[b, 0])
+            best = max(best, Fc)
+            hist.append((time.perf_counter() - t0, Fc, ev.evaluations - e0))
+            if b < len(cands):
+                counts["surrogate_accepted"] += 1
+                need_grad = False
+                x = cands[b].clone()   # continue from the accepted point
+            else:
+                counts["plain_accepted"] += 1
+                need_grad = True
+            if Fc >= target:
+                break
+        else:
+            if need_grad:
+                theta = plain_next   # the plain step is taken as the fallback
+                counts["plain_accepted"] += 1
+            need_grad = True
+        if time.perf_counter() - t0 > time_limit:
             break
-        delta = opt.step(theta, g) - theta
-        # refit on the samples seen so far
-        xd = torch.tensor(X, device="cuda")
-        yd = torch.tensor(Y, device="cuda")
-        nb = min(net.max_batch, X.shape[0])
-        for _ in range(fit_steps):
-            idx = torch.randint(0, X.shape[0], (nb,), device="cuda")
-            net.train_step(xd[idx].contiguous(), yd[idx].contiguous(), fit_lr, want_loss=False)
-        cands = np.stack([theta + a * delta for a in scales])
-        pred = net.forward(torch.tensor(encode(cands, np.repeat(noise, len(scales), 0)), device="cuda"))
-        pred = pred.cpu().numpy()[:, 0]
-        pick = int(np.argmax(pred))
-        picks.append(scales[pick])
-        if pick == 0:
-            theta = cands[0]
-            continue
-        ver = ev(np.stack([cands[0], cands[pick]]))[:, 0]
-        errs.append(abs(float(pred[pick]) - float(ver[1])))
-        theta = cands[pick] if ver[1] > ver[0] else cands[0]
     reached = best >= target
-    return {"reached": reached, "time": hist[-1][0] if reached else None, "best": best, "steps": len(hist),
-            "history": hist, "theta": theta, "evaluations": ev.evaluations, "proposals": len(picks),
-            "longer_steps_chosen": int(sum(1 for p in picks if p != 1.0)),
+    tr = next((h[0] for h in hist if h[1] >= target), None)
+    rr = next((h[2] for h in hist if h[1] >= target), None)
+    return {"reached": reached, "time": tr, "rows_to_target": rr, "best": best, "history": hist,
+            "theta": theta, "evaluations": ev.evaluations - e0, **counts,
             "surrogate_abs_err": float(np.mean(errs)) if errs else None}
