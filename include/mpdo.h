@@ -365,6 +365,55 @@ mpdo_status mpdo_tune_set(int32_t site, int32_t tile, int32_t form, double split
 mpdo_status mpdo_tune_get(int32_t site, int32_t* tile, int32_t* form, double* split_scale);
 
 /* ---------------------------------------------------------------------------
+ * Error mitigation by the inverse of the noisy process (Sec. V: the noisy
+ * process can be undone with a matrix product operator of its inverse).
+ *
+ * An mpdo_mpo_t holds rho of a state as the chain of the paper's local
+ * density tensors (Eq. (6)),
+ *   R_i[(l l'), (p p'), (r r')] = sum_n T_i[l, p, n, r] conj(T_i[l', p', n, r']),
+ * whose contraction is rho (Eq. (7)), in complex double on the device.  A
+ * channel rho -> sum_j K_j rho K_j^dagger acts on the row-major vector of
+ * rho as the superoperator S = sum_j K_j (x) conj(K_j); on q sites it acts
+ * on the pair indices (p_1 p_1' .. p_q p_q').  The inverse of a channel is
+ * the matrix inverse of its S (a linear map, not completely positive), the
+ * inverse of a gate U is U^dagger.  Mitigating the output of a noisy circuit
+ * N_L U_L .. N_1 U_1 with a noise model N^ applies N^_L^-1, U_L^-1, ..,
+ * N^_2^-1, U_2^-1, N^_1^-1 and then U_2 .. U_L (unwinding the circuit, then
+ * replaying it without noise).  After the map rho is linear in the tensors
+ * and may be non-positive; the two-site maps split the contracted pair again
+ * by an SVD (the Gram matrix of its smaller side and the library's
+ * eigensolver) with the rule: smallest rank whose dropped squared singular
+ * values are <= cutoff times their total, at most d_max.
+ *
+ * Limits: one MPO per call sequence on the stream of the state it was made
+ * from (the caller's; destroy the MPO before that stream); bonds of the
+ * source state <= 32 (MPO bonds <= 1024); a two-site map needs one of its
+ * two outer bonds <= 256; gates and channels on q <= 2 adjacent sites.
+ * ------------------------------------------------------------------------- */
+typedef struct mpdo_mpo_s* mpdo_mpo_t;
+
+/* rho of state h (its queued gates applied first) as an MPO; d_max in
+ * [1, 256], cutoff in [0, 1).  Allocates through h's allocator. */
+mpdo_status mpdo_mpo_from_state(mpdo_t h, int32_t d_max, double cutoff, mpdo_mpo_t* out);
+mpdo_status mpdo_mpo_destroy(mpdo_mpo_t m);
+/* The gate U (host, 2^q x 2^q complex, row-major, interleaved re/im) on
+ * sites site .. site + q - 1, or its inverse U^dagger when inverse != 0.
+ * U is not checked for unitarity. */
+mpdo_status mpdo_mpo_apply_gate(mpdo_mpo_t m, int32_t site, int32_t q, const double* U, int32_t inverse);
+/* The channel ch (q <= 2, on sites site .. site + q - 1), or the inverse of
+ * its superoperator when inverse != 0 (MPDO_ENOTCONV if it is singular:
+ * a pivot below 1e-13 of its largest entry). */
+mpdo_status mpdo_mpo_apply_channel(mpdo_mpo_t m, int32_t site, mpdo_chan_t ch, int32_t inverse);
+/* out[2k], out[2k+1] = Tr(O_k rho) for nops product operators
+ * O_k = (x)_i ops[k][i] (ops: host, nops x n x 2 x 2 complex), unnormalised
+ * (divide by the value for identities for a normalised expectation). */
+mpdo_status mpdo_mpo_expect(mpdo_mpo_t m, const double* ops, int32_t nops, double* out);
+/* bonds: n - 1 ints; discarded: summed dropped fraction of the splits. */
+mpdo_status mpdo_mpo_dims(mpdo_mpo_t m, int32_t* bonds, double* discarded);
+/* rho (host, 2^n x 2^n complex, row-major), n <= 12. */
+mpdo_status mpdo_mpo_to_dense(mpdo_mpo_t m, double* rho);
+
+/* ---------------------------------------------------------------------------
  * Surrogate network: a multilayer perceptron trained on MPDO-generated
  * (parameters, noise) -> observables data.  Widths d_0 .. d_L; hidden
  * layers z_l = W_l h_{l-1} + b_l, h_l = GELU(z_l) = z Phi(z) (exact erf

@@ -11,6 +11,7 @@
 #include "../../include/mpdo.h"
 #include "engine.h"
 #include "kernels.h"
+#include "mpo.h"
 #include "ops.h"
 #include "profile.h"
 
@@ -51,6 +52,17 @@ struct AnyEngine {
     return d ? d->truncate_sweep(b, c, k, cut) : f->truncate_sweep(b, c, k, cut);
   }
   InstStats stats(int b) { return d ? d->stats(b) : f->stats(b); }
+  // rho of instance b as local density tensors
+  void load_mpo(int b, MpoState& m) {
+    std::vector<int> bo, in;
+    double disc;
+    dims(b, bo, in, disc);
+    for (int i = 0; i < m.n; ++i) {
+      const int l = i ? bo[i - 1] : 1, r = i + 1 < m.n ? bo[i] : 1;
+      if (d) m.load_site<double>(i, reinterpret_cast<const cpx<double>*>(d->site_ptr(b, i)), l, in[i], r);
+      else m.load_site<float>(i, reinterpret_cast<const cpx<float>*>(f->site_ptr(b, i)), l, in[i], r);
+    }
+  }
   long long failures() { return d ? d->failures() : f->failures(); }
 };
 
@@ -1041,3 +1053,133 @@ extern "C" mpdo_status mpdo_test_gemm_form(int32_t prec, int32_t tile, int32_t f
   set_gemm_form(prec == 0, tile, form);
   return MPDO_OK;
 }
+
+// ---- error mitigation on an MPO of rho ----
+
+struct mpdo_mpo_s {
+  DeviceAllocator alloc;
+  std::unique_ptr<MpoState> m;
+  bool dead = false;
+  std::string why;
+};
+
+static mpdo_status mark_dead_mpo(mpdo_mpo_t h, int st, const std::string& msg) {
+  h->dead = true;
+  h->why = msg;
+  return fail(st, msg);
+}
+
+#define MPO_CHECK(h)                                                         \
+  if (!(h)) return fail(MPDO_EINVAL, "null MPO handle");                     \
+  if ((h)->dead) return fail(MPDO_EDEVICE, "MPO handle is unusable after an earlier error: " + (h)->why);
+#define MPO_GUARD_END(h)                                                     \
+  }                                                                          \
+  catch (const Error& e) {                                                   \
+    return mark_dead_mpo((h), e.status, e.msg);                              \
+  }                                                                          \
+  catch (const std::exception& e) {                                          \
+    return mark_dead_mpo((h), MPDO_EDEVICE, std::string("internal error: ") + e.what()); \
+  }                                                                          \
+  catch (...) {                                                              \
+    return mark_dead_mpo((h), MPDO_EDEVICE, "internal error");               \
+  }
+
+extern "C" {
+
+mpdo_status mpdo_mpo_from_state(mpdo_t h, int32_t d_max, double cutoff, mpdo_mpo_t* out) {
+  if (!out) return fail(MPDO_EINVAL, "null output pointer");
+  *out = nullptr;
+  HANDLE_CHECK(h)
+  if (d_max < 1 || d_max > 256) return fail(MPDO_EINVAL, "d_max must be in [1, 256]");
+  if (!(cutoff >= 0 && cutoff < 1)) return fail(MPDO_EINVAL, "cutoff must be in [0, 1)");
+  std::unique_ptr<mpdo_mpo_s> m(new mpdo_mpo_s);
+  m->alloc = h->alloc;
+  GUARD_BEGIN_H(h)
+  flush_queue(h);
+  check_health(h);
+  std::vector<int> bo, in;
+  double disc;
+  h->eng.dims(0, bo, in, disc);
+  for (int x : bo)
+    if (x > 32) return fail(MPDO_EUNSUPPORTED, "MPO of a state with a bond above 32 (MPO bond above 1024)");
+  m->m.reset(new MpoState(h->cfg.n, d_max, cutoff, h->st));
+  h->eng.load_mpo(0, *m->m);
+  hip_check(hipStreamSynchronize(h->st), "hipStreamSynchronize");
+  *out = m.release();
+  return MPDO_OK;
+  GUARD_END_H(h)
+}
+
+mpdo_status mpdo_mpo_destroy(mpdo_mpo_t m) {
+  if (!m) return MPDO_OK;
+  GUARD_BEGIN
+  AllocScope scope(m->alloc.alloc ? &m->alloc : nullptr);
+  (void)hipDeviceSynchronize();
+  delete m;
+  return MPDO_OK;
+  GUARD_END
+}
+
+mpdo_status mpdo_mpo_apply_gate(mpdo_mpo_t m, int32_t site, int32_t q, const double* U, int32_t inverse) {
+  MPO_CHECK(m)
+  if (!U) return fail(MPDO_EINVAL, "null gate");
+  if (q < 1 || q > 2) return fail(MPDO_EINVAL, "q must be 1 or 2");
+  if (site < 0 || site + q > m->m->n) return fail(MPDO_EINVAL, "sites out of range");
+  for (int e = 0; e < 2 << (2 * q); ++e)
+    if (!std::isfinite(U[e])) return fail(MPDO_EINVAL, "non-finite gate entry");
+  AllocScope alloc_scope_(m->alloc.alloc ? &m->alloc : nullptr);
+  try {
+    m->m->gate_superop(U, q, inverse != 0);
+    m->m->apply(site, q);
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    return MPDO_OK;
+  MPO_GUARD_END(m)
+}
+
+mpdo_status mpdo_mpo_apply_channel(mpdo_mpo_t m, int32_t site, mpdo_chan_t ch, int32_t inverse) {
+  MPO_CHECK(m)
+  if (!ch) return fail(MPDO_EINVAL, "null channel");
+  const int q = ch->ch.q;
+  if (q > 2) return fail(MPDO_EUNSUPPORTED, "MPO maps act on at most two sites");
+  if (site < 0 || site + q > m->m->n) return fail(MPDO_EINVAL, "sites out of range");
+  AllocScope alloc_scope_(m->alloc.alloc ? &m->alloc : nullptr);
+  try {
+    m->m->superop(ch->ch.kraus.as<double>(), ch->ch.m, q, false, inverse != 0);
+    m->m->apply(site, q);
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    return MPDO_OK;
+  MPO_GUARD_END(m)
+}
+
+mpdo_status mpdo_mpo_expect(mpdo_mpo_t m, const double* ops, int32_t nops, double* out) {
+  MPO_CHECK(m)
+  if (!ops || !out) return fail(MPDO_EINVAL, "null argument");
+  if (nops < 1) return fail(MPDO_EINVAL, "nops must be >= 1");
+  AllocScope alloc_scope_(m->alloc.alloc ? &m->alloc : nullptr);
+  try {
+    m->m->expect(ops, nops, out);
+    return MPDO_OK;
+  MPO_GUARD_END(m)
+}
+
+mpdo_status mpdo_mpo_dims(mpdo_mpo_t m, int32_t* bonds, double* discarded) {
+  MPO_CHECK(m)
+  const auto& D = m->m->bonds();
+  if (bonds)
+    for (int i = 1; i < m->m->n; ++i) bonds[i - 1] = D[i];
+  if (discarded) *discarded = m->m->discarded;
+  return MPDO_OK;
+}
+
+mpdo_status mpdo_mpo_to_dense(mpdo_mpo_t m, double* rho) {
+  MPO_CHECK(m)
+  if (!rho) return fail(MPDO_EINVAL, "null argument");
+  if (m->m->n > 12) return fail(MPDO_EINVAL, "dense rho needs n <= 12");
+  AllocScope alloc_scope_(m->alloc.alloc ? &m->alloc : nullptr);
+  try {
+    m->m->to_dense(rho);
+    return MPDO_OK;
+  MPO_GUARD_END(m)
+}
+
+}  // extern "C"

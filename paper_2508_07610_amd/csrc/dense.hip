@@ -65,9 +65,12 @@ void permute(const cpx<Tin>* src, cpx<double>* dst, std::vector<long long> dims,
   hipLaunchKernelGGL(k_permute<Tin>, dim3((unsigned)std::max<long long>(1, blocks)), dim3(256), 0, s, src, dst, p);
 }
 
-// C = alpha op(A) op(B) in FP64 with a one-item descriptor in `dd`.
-void gemm(DevBuf& dd, const cpx<double>* A, const cpx<double>* B, cpx<double>* C, int M, int N, int K, int opA,
-          int opB, int lda, int ldb, int ldc, hipStream_t s) {
+}  // namespace
+
+// C = op(A) op(B) in FP64 with a one-item descriptor in `dd` (herm: C is
+// Hermitian and only its upper triangle of tiles is computed); synchronises s.
+void gemm_once(DevBuf& dd, const cpx<double>* A, const cpx<double>* B, cpx<double>* C, int M, int N, int K, int opA,
+               int opB, int lda, int ldb, int ldc, hipStream_t s, bool herm) {
   GemmDesc d;
   std::memset(&d, 0, sizeof(d));
   d.A = A; d.B = B; d.C = C;
@@ -75,9 +78,17 @@ void gemm(DevBuf& dd, const cpx<double>* A, const cpx<double>* B, cpx<double>* C
   d.lda = lda; d.ldb = ldb; d.ldc = ldc;
   d.opA = opA; d.opB = opB;
   d.nbatch = 1; d.splits = 1; d.wdiv = 1; d.active = 1; d.alpha = 1.0;
+  d.herm = herm ? 1 : 0;
+  dd.alloc(sizeof(GemmDesc));
   hip_check(hipMemcpyAsync(dd.p, &d, sizeof(d), hipMemcpyHostToDevice, s), "descriptor");
-  launch_gemm<double, double, double>(dd.as<GemmDesc>(), 1, 1, 1, gemm_tiles(M, N), s);
+  launch_gemm<double, double, double>(dd.as<GemmDesc>(), 1, 1, 1, herm ? gemm_tiles_herm(N) : gemm_tiles(M, N), s);
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");  // dd is reused by the next call
+}
+
+namespace {
+void gemm(DevBuf& dd, const cpx<double>* A, const cpx<double>* B, cpx<double>* C, int M, int N, int K, int opA,
+          int opB, int lda, int ldb, int ldc, hipStream_t s) {
+  gemm_once(dd, A, B, C, M, N, K, opA, opB, lda, ldb, ldc, s, false);
 }
 }  // namespace
 

@@ -71,6 +71,11 @@ struct HostStage {
   void* get(size_t n);    // waits until the previous upload finished
 };
 
+// C = op(A) op(B) in FP64, one item (descriptor staged in `dd`); herm: C is
+// Hermitian and only its upper triangle of tiles is written.  Synchronises s.
+void gemm_once(DevBuf& dd, const cpx<double>* A, const cpx<double>* B, cpx<double>* C, int M, int N, int K, int opA,
+               int opB, int lda, int ldb, int ldc, hipStream_t s, bool herm);
+
 struct InstStats {
   double discarded = 0, max_discarded = 0, min_gap = 0;
   long long cuts = 0, failures = 0;

@@ -25,6 +25,8 @@ EXPORTED = (
     "mpdo_truncate", "mpdo_expect", "mpdo_expect_products", "mpdo_fidelity_ghz", "mpdo_trace", "mpdo_dims",
     "mpdo_bond_weights", "mpdo_to_dense", "mpdo_probabilities", "mpdo_sample", "mpdo_batch_run",
     "mpdo_stats", "mpdo_release_cached_memory", "mpdo_batch_run_dense", "mpdo_tune_set", "mpdo_tune_get",
+    "mpdo_mpo_from_state", "mpdo_mpo_destroy", "mpdo_mpo_apply_gate", "mpdo_mpo_apply_channel", "mpdo_mpo_expect",
+    "mpdo_mpo_dims", "mpdo_mpo_to_dense",
 )
 
 
@@ -145,6 +147,13 @@ def lib() -> ctypes.CDLL:
         "mpdo_batch_run_dense": [ctypes.POINTER(mpdo_config), ctypes.POINTER(mpdo_program), i32, vp, i32, pd, i32,
                                  ctypes.POINTER(vp), i32, vp, vp],
         "mpdo_tune_set": [i32, i32, i32, dbl],
+        "mpdo_mpo_from_state": [vp, i32, dbl, ctypes.POINTER(vp)],
+        "mpdo_mpo_destroy": [vp],
+        "mpdo_mpo_apply_gate": [vp, i32, i32, pd, i32],
+        "mpdo_mpo_apply_channel": [vp, i32, vp, i32],
+        "mpdo_mpo_expect": [vp, pd, i32, pd],
+        "mpdo_mpo_dims": [vp, pi, pd],
+        "mpdo_mpo_to_dense": [vp, pd],
         "mpdo_tune_get": [i32, pi, pi, pd],
         "mpdo_profile_enable": [i32],
         "mpdo_profile_read": [i32, pi, pd, pd, pd],
@@ -323,6 +332,10 @@ class MPDO:
         out = np.zeros(2 * d * d)
         check(lib().mpdo_to_dense(self._h, _dptr(out)))
         return out.view(np.complex128).reshape(d, d)
+
+    def to_mpo(self, d_max: int = 256, cutoff: float = 0.0) -> "MPO":
+        """rho as an MPO of local density tensors (see MPO)."""
+        return MPO(self, d_max, cutoff)
 
     def probabilities(self, bits: np.ndarray) -> np.ndarray:
         """bits: (nz, n) of 0/1 -> <z|rho|z> / Tr(rho) for each row."""
@@ -627,3 +640,61 @@ def test_gemm_rate(prec: int, M: int, N: int, K: int, items: int = 1, reps: int 
     ms = ctypes.c_double()
     check(_testing_lib().mpdo_test_gemm_rate(prec, M, N, K, items, reps, ctypes.byref(ms)))
     return ms.value
+
+
+class MPO:
+    """rho of a state as the chain of local density tensors (Eq. (6)), on the
+    GPU, for error mitigation by inverse maps (Sec. V; include/mpdo.h,
+    mpdo_mpo_*).  Runs on the stream of the state it was made from."""
+
+    def __init__(self, state: "MPDO", d_max: int = 256, cutoff: float = 0.0):
+        self.n = state.n
+        h = ctypes.c_void_p()
+        check(lib().mpdo_mpo_from_state(state._h, d_max, cutoff, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mpdo_mpo_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def apply_gate(self, site: int, U: np.ndarray, inverse: bool = False) -> None:
+        U = np.asarray(U, dtype=np.complex128)
+        q = int(round(np.log2(U.shape[0])))
+        u = _cplx(U)
+        check(lib().mpdo_mpo_apply_gate(self._h, site, q, _dptr(u), 1 if inverse else 0))
+
+    def apply_channel(self, site: int, ch: Channel, inverse: bool = False) -> None:
+        check(lib().mpdo_mpo_apply_channel(self._h, site, ch.handle, 1 if inverse else 0))
+
+    def expect_products(self, ops: np.ndarray) -> np.ndarray:
+        """ops: (nops, n, 2, 2) complex -> Tr(O rho) (unnormalised) for each."""
+        ops = np.asarray(ops, dtype=np.complex128)
+        buf = _cplx(ops)
+        out = np.zeros(2 * ops.shape[0])
+        check(lib().mpdo_mpo_expect(self._h, _dptr(buf), ops.shape[0], _dptr(out)))
+        return out.view(np.complex128)
+
+    def dims(self):
+        b = (ctypes.c_int32 * max(1, self.n - 1))()
+        d = ctypes.c_double()
+        check(lib().mpdo_mpo_dims(self._h, b, ctypes.byref(d)))
+        return list(b)[: self.n - 1], d.value
+
+    def to_dense(self) -> np.ndarray:
+        d = 1 << self.n
+        out = np.zeros(2 * d * d)
+        check(lib().mpdo_mpo_to_dense(self._h, _dptr(out)))
+        return out.view(np.complex128).reshape(d, d)

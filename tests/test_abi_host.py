@@ -86,6 +86,24 @@ def test_null_handles_are_rejected():
     assert L.mpdo_channel_info(None, None, None, None) == M.EINVAL
 
 
+def test_mpo_calls_reject_null_handles():
+    """The error-mitigation entry points check their handles and output
+    pointers before any device work."""
+    L = M.lib()
+    h = ctypes.c_void_p(1234)
+    assert L.mpdo_mpo_from_state(None, 8, 0.0, ctypes.byref(h)) == M.EINVAL
+    assert not h.value                                  # cleared on failure
+    assert L.mpdo_mpo_from_state(None, 8, 0.0, None) == M.EINVAL
+    u = np.eye(2, dtype=np.complex128).view(np.float64).copy()
+    assert L.mpdo_mpo_apply_gate(None, 0, 1, M._dptr(u), 0) == M.EINVAL
+    assert L.mpdo_mpo_apply_channel(None, 0, None, 1) == M.EINVAL
+    out = np.zeros(2)
+    assert L.mpdo_mpo_expect(None, M._dptr(u), 1, M._dptr(out)) == M.EINVAL
+    assert L.mpdo_mpo_dims(None, None, None) == M.EINVAL
+    assert L.mpdo_mpo_to_dense(None, M._dptr(out)) == M.EINVAL
+    assert L.mpdo_mpo_destroy(None) == M.OK
+
+
 def test_test_entry_points_validate_sizes():
     L = M.lib()
     a = np.zeros(8)
