@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-gemm-tiles", action="store_true", help="skip the full-tile GEMM throughput leg")
     ap.add_argument("--no-noise-models", action="store_true", help="skip the standard noise model comparison")
     ap.add_argument("--no-truncation-study", action="store_true", help="skip the truncation study leg")
+    ap.add_argument("--no-mitigation", action="store_true", help="skip the error-mitigation leg")
     ap.add_argument("--no-crosstalk", action="store_true",
                     help="skip the crosstalk leg (three-site channels, Kraus pruning thresholds)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -483,19 +484,68 @@ def noise_models_leg(shots=4096):
             "jsd_sampled_vs_exact": {"shots": shots, "jsd": D.jsd(q, hist)}}
 
 
-def truncation_study_leg(ncirc=16):
-    """Sec. IV.C: mean Uhlmann fidelity between lossless and truncated states
-    of random circuits with RZ crosstalk (Q = 3 and 6, depth 4) over a grid
-    of (chi, kappa), ncirc circuits each, per-gate calls, FP64."""
+def truncation_study_leg(ncirc=1000):
+    """Sec. IV.C at the paper's scale: mean Uhlmann fidelity between lossless
+    and truncated states of random circuits with RZ crosstalk (Q = 3 and 6,
+    depth 4), 1,000 circuits per point, over a grid of (chi, kappa); every
+    circuit of a point and limit in one mpdo_batch_run_dense, FP64."""
     from paper_2508_07610_amd import truncation_study as TS
     limits = [(2, 2), (4, 4), (8, 8), (16, 4), (16, 16)]
     out = {}
     for q in (3, 6):
         t0 = time.perf_counter()
-        r = TS.run(q, 4, limits, ncirc=ncirc)
-        out[f"Q={q},depth=4"] = {"fidelity": r, "seconds": time.perf_counter() - t0}
+        r = TS.run_batched(q, 4, limits, ncirc=ncirc)
+        out[f"Q={q},depth=4"] = {"fidelity": r["fidelity"], "device_seconds": r["device_seconds"],
+                                 "seconds": time.perf_counter() - t0}
     return {"workload": f"{ncirc} random RX/RY/RZ + CNOT circuits per Q, RZ(alpha) crosstalk on the neighbour of "
-                        "every CNOT, QPT-style channels, lossless reference at chi=64 kappa=64", "results": out}
+                        "every CNOT, QPT-style channels, lossless reference at chi=64 kappa=64, one batched dense "
+                        "run per limit", "results": out}
+
+
+def mitigation_leg(n=16, scale=3.0):
+    """Sec. V: the output of a noisy GHZ preparation (H and compiled CNOTs on
+    a chain of n qubits, QPT-style channels x`scale` after every gate) mapped
+    by the inverse of the noisy process on an MPO of rho, with the circuit's
+    own channels as the model (exact: fidelity 1 in closed form) and with a
+    standard noise model (thermal relaxation + depolarizing, unified 2q form)
+    in their place; GHZ fidelity before and after, and the device time."""
+    import torch
+    from paper_2508_07610_amd import mitigation as GM
+    from paper_2508_07610_amd import mpdo as M
+    from paper_2508_07610_amd import workloads as W
+    chis = [W.chi_1q_default(scale), W.chi_2q_default(scale)]
+    ops = [W.Op((0,), W.H, 0, "h")]
+    for q in range(n - 1):
+        for name, loc, U in W.cnot_compiled():
+            ops.append(W.Op(tuple(q + s for s in loc), U, 0 if len(loc) == 1 else 1, name))
+    prog = W.Program(n, ops, chis, 0)
+    chans = [M.Channel(chis[0], 1), M.Channel(chis[1], 2)]
+    std = [M.Channel(W.chi_standard_1q(3e-3, 0.03, 30.0, 20.0), 1),
+           M.Channel(W.chi_unified_2q(3e-2, 0.3, 30.0, 20.0), 2)]
+    st = M.MPDO(n, chi_max=64, kappa_max=64, max_kraus=16, svd_cutoff=1e-14, kappa_cutoff=1e-14)
+    M.run_program(prog, st, chans)
+    f_noisy = st.fidelity_ghz()
+    res = {}
+    for name, model in (("exact_model", chans), ("standard_model", std)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m = GM.mitigate(prog, st, model, d_max=256, cutoff=1e-12)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bonds, disc = m.dims()
+        res[name] = {"ghz_fidelity": GM.ghz_fidelity(m), "seconds": dt, "max_bond": max(bonds),
+                     "discarded": disc}
+        m.close()
+    nmaps = sum(1 for o in ops if o.chan >= 0) + 2 * (len(ops) - 1)   # inverse channels, U^-1 and U replays
+    for r in res.values():
+        r["maps"] = nmaps
+        r["ms_per_map"] = 1e3 * r["seconds"] / nmaps
+    st.close()
+    for c in chans + std:
+        c.close()
+    return {"workload": f"noisy GHZ preparation n={n} (H + {n - 1} compiled CNOTs), QPT-style channels x{scale:g}, "
+                        "MPO of rho from the lossless MPDO, d_max=256 cutoff=1e-12, FP64",
+            "ghz_fidelity_noisy": f_noisy, "mitigated": res}
 
 
 def crosstalk_leg():
@@ -656,6 +706,7 @@ def main():
         "noise_models": None if a.no_noise_models else noise_models_leg(),
         "truncation_study": None if a.no_truncation_study else truncation_study_leg(),
         "crosstalk": None if a.no_crosstalk else crosstalk_leg(),
+        "mitigation": None if a.no_mitigation else mitigation_leg(),
     }
     print(json.dumps(out, default=lambda o: o.item() if hasattr(o, "item") else str(o)))
 

@@ -86,29 +86,41 @@ def run(q: int, depth: int, limits: Sequence[Tuple[int, int]], ncirc: int, seed:
 def uhlmann_batch(rho: np.ndarray, sigma: np.ndarray) -> np.ndarray:
     """Eq. (23) for stacks (B, d, d) of density matrices (normalised here):
     F = (tr sqrt(sqrt(rho) sigma sqrt(rho)))^2, by two batched Hermitian
-    eigendecompositions on the host."""
+    eigendecompositions on the host.  Eigenvalues below 1e-12 of each
+    matrix's largest are rounding and are set to zero (their square roots,
+    ~1e-8 each, would otherwise add up in the trace of a rank-deficient
+    product)."""
     rho = rho / np.trace(rho, axis1=1, axis2=2).real[:, None, None]
     sigma = sigma / np.trace(sigma, axis1=1, axis2=2).real[:, None, None]
     rho = 0.5 * (rho + np.conj(np.swapaxes(rho, 1, 2)))
+    sigma = 0.5 * (sigma + np.conj(np.swapaxes(sigma, 1, 2)))
     w, v = np.linalg.eigh(rho)
-    sq = (v * np.sqrt(np.clip(w, 0.0, None))[:, None, :]) @ np.conj(np.swapaxes(v, 1, 2))
+    w = np.where(w > 1e-12 * w.max(axis=1, keepdims=True), w, 0.0)
+    sq = (v * np.sqrt(w)[:, None, :]) @ np.conj(np.swapaxes(v, 1, 2))
     m = sq @ sigma @ sq
     m = 0.5 * (m + np.conj(np.swapaxes(m, 1, 2)))
-    ev = np.clip(np.linalg.eigvalsh(m), 0.0, None)
+    ev = np.linalg.eigvalsh(m)
+    ev = np.where(ev > 1e-12 * ev.max(axis=1, keepdims=True), ev, 0.0)
     return np.sum(np.sqrt(ev), axis=1) ** 2
 
 
+def circuits(q: int, depth: int, ncirc: int, seed: int = 0) -> List["W.Program"]:
+    """The seeded circuits of one (q, depth) point of run_batched."""
+    rng = W.rng_for(4500 + 100 * q + depth + 10000 * seed)
+    return [circuit(q, depth, rng) for _ in range(ncirc)]
+
+
 def run_batched(q: int, depth: int, limits: Sequence[Tuple[int, int]], ncirc: int = 1000, seed: int = 0,
-                full: Tuple[int, int] = (64, 64), prec: int = M.C128) -> Dict:
+                full: Tuple[int, int] = (64, 64), prec: int = M.C128, per_circuit: bool = False) -> Dict:
     """The Sec. IV.C study at scale: `ncirc` seeded circuits of one (q, depth)
     point, each (chi, kappa) of `limits` and the lossless `full` limits run
     as one batch each; returns per limit the mean, standard deviation and
-    minimum of the Uhlmann fidelity against the lossless state, and the
-    device seconds of the batches."""
+    minimum of the Uhlmann fidelity against the lossless state (and every
+    circuit's value with per_circuit), and the device seconds of the
+    batches."""
     import time
     import torch
-    rng = W.rng_for(4500 + 100 * q + depth + 10000 * seed)
-    progs = [circuit(q, depth, rng) for _ in range(ncirc)]
+    progs = circuits(q, depth, ncirc, seed)
     chans = [M.Channel(progs[0].chis[0], 1), M.Channel(progs[0].chis[1], 2)]
     plan = M.BatchPlan(progs, [np.zeros((0,))] * ncirc, use_params=False)
     kw = dict(max_kraus=16, svd_cutoff=1e-14, kappa_cutoff=1e-14, prec=prec)
@@ -128,6 +140,8 @@ def run_batched(q: int, depth: int, limits: Sequence[Tuple[int, int]], ncirc: in
         f = uhlmann_batch(rho, dense(*lim))
         out[f"chi={lim[0]},kappa={lim[1]}"] = {"mean": float(np.mean(f)), "std": float(np.std(f)),
                                                "min": float(np.min(f))}
+        if per_circuit:
+            out[f"chi={lim[0]},kappa={lim[1]}"]["all"] = f.tolist()
     for ch in chans:
         ch.close()
     return {"fidelity": out, "device_seconds": t, "circuits": ncirc}

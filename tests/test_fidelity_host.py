@@ -58,3 +58,18 @@ def test_host_jsd_and_bitstrings_match_the_oracle():
     assert b.dtype == np.uint8 and b.shape == (32, 5)
     for z in range(32):
         assert list(b[z]) == OS.bits_of(z, 5)
+
+
+def test_batched_fidelity_equals_the_single_one():
+    """uhlmann_batch (the Sec. IV.C study's host measurement over a stack of
+    states) equals the pinned single-pair form on every pair, including
+    rank-deficient and identical pairs."""
+    from paper_2508_07610_amd.truncation_study import uhlmann_batch
+    rng = np.random.default_rng(5)
+    R = np.stack([_rand_rho(8, k, rng) for k in (1, 3, 8, 8)])
+    S = np.stack([_rand_rho(8, k, rng) for k in (8, 2, 8, 1)])
+    S[2] = R[2]
+    f = uhlmann_batch(R, S)
+    for i in range(4):
+        assert abs(f[i] - uhlmann_fidelity(R[i], S[i])) < 1e-9
+    assert abs(f[2] - 1) < 1e-9

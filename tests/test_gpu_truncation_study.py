@@ -55,3 +55,27 @@ def test_study_limits():
     for v in r.values():
         assert 0 < v["min"] <= v["mean"] <= 1 + 1e-9
     assert r["chi=4,kappa=4"]["mean"] >= r["chi=1,kappa=1"]["mean"] - 1e-12
+
+
+def test_batched_study_equals_per_circuit_runs():
+    """run_batched (every circuit of a point in one mpdo_batch_run_dense per
+    limit) gives each circuit the fidelity of its own per-gate runs."""
+    require_gpu()
+    q, depth, lims = 3, 4, [(4, 4), (8, 4)]
+    r = TS.run_batched(q, depth, lims, ncirc=6, seed=2, per_circuit=True)
+    progs = TS.circuits(q, depth, 6, seed=2)
+    chans = [M.Channel(progs[0].chis[0], 1), M.Channel(progs[0].chis[1], 2)]
+
+    def dev(prog, chi, kap):
+        st = M.MPDO(q, chi_max=chi, kappa_max=kap, max_kraus=16, svd_cutoff=1e-14, kappa_cutoff=1e-14)
+        M.run_program(prog, st, chans)
+        x = st.to_dense()
+        st.close()
+        return x / np.trace(x).real
+
+    for i, prog in enumerate(progs):
+        full = dev(prog, 64, 64)
+        for lim in lims:
+            f = TS.uhlmann_fidelity(full, dev(prog, *lim))
+            assert abs(f - r["fidelity"][f"chi={lim[0]},kappa={lim[1]}"]["all"][i]) < 1e-9, (i, lim)
+    assert r["circuits"] == 6
