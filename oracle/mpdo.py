@@ -85,8 +85,15 @@ def select_rank(eta: np.ndarray, max_dim: int, cutoff: float) -> int:
 
 
 def _svd(M: np.ndarray):
-    """Thin SVD M = U diag(S) Vh, singular values descending."""
-    return np.linalg.svd(M, full_matrices=False)
+    """Thin SVD M = U diag(S) Vh, singular values descending.  NumPy's
+    divide-and-conquer driver (gesdd) occasionally reports non-convergence on
+    matrices with many tiny singular values; the same decomposition is then
+    taken with the one-sided QR-iteration driver (gesvd)."""
+    try:
+        return np.linalg.svd(M, full_matrices=False)
+    except np.linalg.LinAlgError:
+        import scipy.linalg
+        return scipy.linalg.svd(M, full_matrices=False, lapack_driver="gesvd")
 
 
 class MPDO:

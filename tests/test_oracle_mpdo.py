@@ -418,3 +418,25 @@ def test_inner_truncation_eckart_young():
     m2.T[site] = m2._compress_inner(T, 2, lam)
     assert abs(m2.discarded - tail) < 1e-12
     assert np.abs(m2.to_dense() - proj.to_dense() / (1 - tail)).max() < 1e-12
+
+
+def test_svd_fallback_driver_gives_the_same_decomposition(monkeypatch):
+    """When NumPy's gesdd driver reports non-convergence the oracle takes the
+    same thin SVD with gesvd: U diag(S) Vh reconstructs M, S descending,
+    U and Vh orthonormal, S equal to the singular values of M."""
+    rng = np.random.default_rng(9)
+    M_ = rng.normal(size=(12, 7)) + 1j * rng.normal(size=(12, 7))
+    want = np.linalg.svd(M_, compute_uv=False)
+    orig = np.linalg.svd
+
+    def failing(a, full_matrices=True, compute_uv=True, **kw):
+        raise np.linalg.LinAlgError("SVD did not converge")
+
+    monkeypatch.setattr(np.linalg, "svd", failing)
+    U, S, Vh = mpdo._svd(M_)
+    monkeypatch.setattr(np.linalg, "svd", orig)
+    assert np.abs(U @ np.diag(S) @ Vh - M_).max() < 1e-13
+    assert np.all(np.diff(S) <= 0)
+    assert np.abs(U.conj().T @ U - np.eye(7)).max() < 1e-13
+    assert np.abs(Vh @ Vh.conj().T - np.eye(7)).max() < 1e-13
+    assert np.abs(S - want).max() < 1e-13
