@@ -332,8 +332,9 @@ typedef enum {
   MPDO_PROF_GEMM_F64 = 0,   /* complex GEMMs on FP64 MFMA                     */
   MPDO_PROF_GEMM_F32 = 1,   /* complex GEMMs on FP32 MFMA (mixed precision)   */
   MPDO_PROF_EIG_REG = 2,    /* eigensolver, n <= 128 (register-resident)      */
-  MPDO_PROF_EIG_GLOBAL = 3, /* eigensolver, 128 < n <= 512                    */
-  MPDO_PROF_NCLASS = 4
+  MPDO_PROF_EIG_GLOBAL = 3, /* eigensolver, one-stage, matrix in global memory */
+  MPDO_PROF_EIG_BAND = 4,   /* eigensolver, 128 < n <= 256, through a band    */
+  MPDO_PROF_NCLASS = 5
 } mpdo_prof_class;
 
 /* Reset the counters (synchronises the device) and switch profiling on

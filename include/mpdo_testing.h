@@ -81,6 +81,12 @@ mpdo_status mpdo_test_gemm_form(int32_t prec, int32_t tile, int32_t form, int32_
 mpdo_status mpdo_test_profile_site(int32_t site, int32_t* launches, double* ms, double* flops);
 mpdo_status mpdo_test_fail_next_update(int32_t status);
 
+/* Eigenproblems with 128 < n <= 256 through the two-stage reduction via a
+ * band of half-width 16 (on = 1) or the one-stage panel reduction (on = 0,
+ * the default); process-wide.  *previous (may be NULL) receives the
+ * setting before the call.  EINVAL unless on is 0 or 1. */
+mpdo_status mpdo_test_eig_band(int32_t on, int32_t* previous);
+
 #ifdef __cplusplus
 }
 #endif

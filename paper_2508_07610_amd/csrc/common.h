@@ -94,9 +94,12 @@ constexpr int EIG_NMAX = 1024;
 constexpr int EIG_THREADS = 512;
 
 // matrix (2 n^2) + two n x np solve vectors + five n x np factor arrays
+// and, for 128 < n <= 256 (the band path), the panels' T (16 of 16 x 16)
+// and the bulge-chasing reflectors (at most n^2 / 32 + n records of 18)
 __host__ __device__ inline long long eig_work_doubles(int n) {
   const long long np = (n + 63) / 64 * 64;
-  return 2LL * n * n + 7LL * n * np + 64;
+  const long long band = (n > 128 && n <= 256) ? 2LL * 16 * 256 + 36LL * ((long long)n * n / 32 + n) : 0;
+  return 2LL * n * n + 7LL * n * np + 64 + band;
 }
 
 }  // namespace mpdo

@@ -962,6 +962,554 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
     back_transform(dsc, A, n, kz, S);
   }
 }
+
+// ---------------------------------------------------------------------------
+// Two-stage reduction for 128 < n <= 256 (the new-bond Grams of the two-site
+// update, n = 2 r_F):
+//
+//  1. dense -> band of half-width BW: Householder QR of each BW-column panel
+//     below the band (in LDS), Q = I - V T V^H (T upper triangular), and the
+//     two-sided update A22 <- Q^H A22 Q = A22 - W V^H - V W^H with
+//     X = A22 V T, W = X - V (T^H V^H X) / 2: the trailing block is read twice
+//     and written once per BW columns (the one-stage form reads it once per
+//     column);
+//  2. band -> real symmetric tridiagonal by bulge chasing in LDS (lower band
+//     with room for the bulge, 2 BW + 1 entries per column): sweep j reduces
+//     column j with a reflector on rows j+1..j+BW, then chases the bulge it
+//     creates down the band block by block (right application to the block
+//     below, a reflector on that block's first column, its left application
+//     to the rest, two-sided application to the next diagonal block).  The
+//     eight waves run consecutive sweeps concurrently: step t of sweep j
+//     waits until sweep j - 1 has finished step t + 2 (the steps touch rows
+//     [j + 1 + (t - 1) BW, j + 1 + (t + 1) BW)), through progress stamps in
+//     LDS;
+//  3. eigenvalues and eigenvectors of the tridiagonal matrix (eig_tail);
+//  4. back-transformation z <- Q1 Q2 z: the chase reflectors in reverse
+//     order, one 16-lane group per eigenvector column (no barriers: a column
+//     is one group's sequential work), then the panels' Q in reverse.
+// ---------------------------------------------------------------------------
+constexpr int BW = 16;
+constexpr int BS_NMAX = 256;
+constexpr int BS_LD = 2 * BW + 1;
+constexpr int BS_ROWS = BS_NMAX - BW;
+constexpr int BS_ZC = 32;  // eigenvector columns per back-transformation pass
+constexpr int BS_RC = 16;  // chase reflectors staged in LDS per chunk
+constexpr int BS_REC = 18; // complex entries per chase reflector record: v[BW], tau, (row0, len)
+constexpr int BS_PANELS = BS_NMAX / BW; // panel T matrices kept for the back-transformation
+constexpr int BS_BIG_S1 = 2 * BS_ROWS * BW + 3 * BW * BW;
+constexpr int BS_BIG_S2 = BS_NMAX * BS_LD;
+constexpr int BS_BIG_S4 = BS_NMAX * BS_ZC + (BS_RC * BS_REC > BW * BS_ZC ? BS_RC * BS_REC : BW * BS_ZC);
+constexpr int BS_BIG = BS_BIG_S1 > BS_BIG_S2 ? (BS_BIG_S1 > BS_BIG_S4 ? BS_BIG_S1 : BS_BIG_S4)
+                                             : (BS_BIG_S2 > BS_BIG_S4 ? BS_BIG_S2 : BS_BIG_S4);
+
+// number of chase reflectors of an n x n band reduction (sweep j has
+// ceil((n - 1 - j) / BW) steps)
+__host__ __device__ inline int band_reflectors(int n) {
+  int c = 0;
+  for (int k = 1; k < n; ++k) c += (k + BW - 1) / BW;
+  return c;
+}
+
+struct alignas(16) SharedBand {
+  alignas(16) cpx<double> big[BS_BIG];
+  alignas(16) cpx<double> pp[BS_NMAX];  // eig_tail's dot products
+  cpx<double> tau[BW];
+  double d[BS_NMAX], e[BS_NMAX], e2[BS_NMAX];
+  double ev[BS_NMAX + 1];
+  double red[2 * NW];
+  double scal[4];
+  int flag[4];
+  int clus[BS_NMAX + 1];
+  int stamp[NW];  // per wave: sweep * 65536 + steps done (65535: sweep finished)
+  int fail;
+  static constexpr int SOLVE_CAP = 0;
+  __device__ double* solve() { return nullptr; }
+};
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Householder reflector of x (length len <= BW, lanes 4 i + q hold x_i when
+// q == 0; other lanes pass zero): (I - tau v v^H)^H x = beta e_1, beta real,
+// v_0 = 1.  Every lane returns tau, beta and its v_i (lanes 4 i + q, any q).
+__device__ inline void wave_house(cpx<double> x, int len, cpx<double>& v, cpx<double>& tau, double& beta) {
+  const int lane = threadIdx.x & 63, i = lane >> 2;
+  const cpx<double> alpha = mk(__shfl(x.re, 0, 64), __shfl(x.im, 0, 64));
+  double xn = ((lane & 3) == 0 && i >= 1 && i < len) ? cabs2(x) : 0.0;
+  for (int off = 32; off > 0; off >>= 1) xn += __shfl_xor(xn, off, 64);
+  const cpx<double> xi = mk(__shfl(x.re, 4 * i, 64), __shfl(x.im, 4 * i, 64));
+  if (xn == 0.0 && alpha.im == 0.0) {
+    tau = mk(0.0, 0.0);
+    beta = alpha.re;
+    v = i == 0 ? mk(1.0, 0.0) : mk(0.0, 0.0);
+    return;
+  }
+  const double nrm = sqrt(cabs2(alpha) + xn);
+  beta = alpha.re >= 0 ? -nrm : nrm;
+  tau = mk((beta - alpha.re) / beta, -alpha.im / beta);
+  const cpx<double> den = mk(alpha.re - beta, alpha.im);
+  const double dd = cabs2(den);
+  const cpx<double> sc = mk(den.re / dd, -den.im / dd);
+  v = i == 0 ? mk(1.0, 0.0) : (i < len ? xi * sc : mk(0.0, 0.0));
+}
+
+// Stage 1: A (n x n, both triangles) -> lower band of half-width BW in place;
+// the panels' V stay below the band, their T go to Tg (BW x BW each).
+template <class SH>
+__device__ void band_stage1(cpx<double>* __restrict__ A, int n, cpx<double>* __restrict__ Tg, SH& S, int& par) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  cpx<double>* Pl = S.big;                  // panel, m x BW: R on top, V below the diagonal
+  cpx<double>* Xl = S.big + BS_ROWS * BW;   // Y = V T, then X = A22 Y, then W
+  cpx<double>* Gs = Xl + BS_ROWS * BW;      // BW x BW scratch
+  cpx<double>* Ts = Gs + BW * BW;
+  cpx<double>* Ms = Ts + BW * BW;
+  for (int kb = 0, p = 0; kb + BW < n; kb += BW, ++p) {
+    const int r0 = kb + BW, m = n - r0, nc = m < BW ? m : BW;
+    for (int e = tid; e < m * BW; e += NT) Pl[e] = A[(long long)(r0 + e / BW) * n + kb + e % BW];
+    __syncthreads();
+    // Householder QR of the panel
+    for (int c = 0; c < nc; ++c) {
+      double xn = 0;
+      for (int i = c + 1 + tid; i < m; i += NT) xn += cabs2(Pl[i * BW + c]);
+      xn = block_sum(xn, S.red, par);
+      if (tid == 0) {
+        const cpx<double> alpha = Pl[c * BW + c];
+        if (xn == 0.0 && alpha.im == 0.0) {
+          S.tau[c] = mk(0.0, 0.0);
+          S.flag[0] = 0;
+        } else {
+          const double nrm = sqrt(cabs2(alpha) + xn);
+          const double beta = alpha.re >= 0 ? -nrm : nrm;
+          S.tau[c] = mk((beta - alpha.re) / beta, -alpha.im / beta);
+          const cpx<double> den = mk(alpha.re - beta, alpha.im);
+          const double dd = cabs2(den);
+          S.scal[0] = den.re / dd;
+          S.scal[1] = -den.im / dd;
+          S.scal[2] = beta;
+          S.flag[0] = 1;
+        }
+      }
+      __syncthreads();
+      if (S.flag[0] == 0) continue;  // uniform: the reflector is the identity
+      const cpx<double> sc = mk(S.scal[0], S.scal[1]);
+      for (int i = c + 1 + tid; i < m; i += NT) Pl[i * BW + c] = Pl[i * BW + c] * sc;
+      __syncthreads();
+      if (tid == 0) Pl[c * BW + c] = mk(S.scal[2], 0.0);
+      // H^H on the panel's later columns: s = v^H P[c:, cc], P[c:, cc] -= conj(tau) v s
+      for (int cc = c + 1 + wave; cc < BW; cc += NW) {
+        double sr = 0, si = 0;
+        for (int i = c + lane; i < m; i += 64) {
+          const cpx<double> v = i == c ? mk(1.0, 0.0) : Pl[i * BW + c];
+          dotacc(sr, si, v, Pl[i * BW + cc]);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off, 64);
+          si += __shfl_xor(si, off, 64);
+        }
+        if (lane == 0) Gs[cc] = mk(sr, si);
+      }
+      __syncthreads();
+      const cpx<double> ct = cconj(S.tau[c]);
+      const int w = BW - c - 1;
+      for (int e = tid; e < (m - c) * w; e += NT) {
+        const int i = c + e / w, cc = c + 1 + e % w;
+        const cpx<double> v = i == c ? mk(1.0, 0.0) : Pl[i * BW + c];
+        Pl[i * BW + cc] = subprod(Pl[i * BW + cc], ct * v, Gs[cc]);
+      }
+      __syncthreads();
+    }
+    auto V = [&](int i, int c) -> cpx<double> {
+      return (c >= nc || i < c) ? mk(0.0, 0.0) : (i == c ? mk(1.0, 0.0) : Pl[i * BW + c]);
+    };
+    // T: T_cc = tau_c, T(0:c, c) = -tau_c T(0:c, 0:c) (V(:, 0:c)^H v_c)
+    for (int e = tid; e < BW * BW; e += NT) {
+      const int c1 = e / BW, c2 = e % BW;
+      double sr = 0, si = 0;
+      if (c1 < c2 && c2 < nc)
+        for (int i = c2; i < m; ++i) dotacc(sr, si, V(i, c1), V(i, c2));
+      Gs[e] = mk(sr, si);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int e = 0; e < BW * BW; ++e) Ts[e] = mk(0.0, 0.0);
+      for (int c = 0; c < nc; ++c) {
+        const cpx<double> t = S.tau[c];
+        Ts[c * BW + c] = t;
+        for (int r = 0; r < c; ++r) {
+          cpx<double> s = mk(0.0, 0.0);
+          for (int k = r; k < c; ++k) s = s + Ts[r * BW + k] * Gs[k * BW + c];
+          Ts[r * BW + c] = mk(-(t.re * s.re - t.im * s.im), -(t.re * s.im + t.im * s.re));
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < BW * BW; e += NT) Tg[(long long)p * BW * BW + e] = Ts[e];
+    // Y = V T
+    for (int e = tid; e < m * BW; e += NT) {
+      const int i = e / BW, c = e % BW;
+      cpx<double> s = mk(0.0, 0.0);
+      const int kmax = min(c, min(i, nc - 1));
+      for (int k = 0; k <= kmax; ++k) s = s + V(i, k) * Ts[k * BW + c];
+      Xl[e] = s;
+    }
+    __syncthreads();
+    // X = A22 Y: thread (i, h) sums its row's eight columns 8 h .. 8 h + 7
+    {
+      cpx<double> acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = mk(0.0, 0.0);
+      const bool own = tid < 2 * m;
+      const int i = tid % (m > 0 ? m : 1), h = tid / (m > 0 ? m : 1);
+      if (own) {
+        for (int j = 0; j < m; ++j) {
+          const cpx<double> a = cconj(A[(long long)(r0 + j) * n + r0 + i]);  // A22[i][j]
+          const cpx<double>* y = Xl + j * BW + 8 * h;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] = acc[u] + a * y[u];
+        }
+      }
+      __syncthreads();
+      if (own)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Xl[i * BW + 8 * h + u] = acc[u];
+      __syncthreads();
+    }
+    // G = V^H X, M = T^H G, W = X - V M / 2
+    for (int e = tid; e < BW * BW; e += NT) {
+      const int c1 = e / BW, c2 = e % BW;
+      double sr = 0, si = 0;
+      if (c1 < nc)
+        for (int i = c1; i < m; ++i) dotacc(sr, si, V(i, c1), Xl[i * BW + c2]);
+      Gs[e] = mk(sr, si);
+    }
+    __syncthreads();
+    for (int e = tid; e < BW * BW; e += NT) {
+      const int c1 = e / BW, c2 = e % BW;
+      double sr = 0, si = 0;
+      for (int k = 0; k <= c1; ++k) dotacc(sr, si, Ts[k * BW + c1], Gs[k * BW + c2]);
+      Ms[e] = mk(sr, si);
+    }
+    __syncthreads();
+    for (int e = tid; e < m * BW; e += NT) {
+      const int i = e / BW, c = e % BW;
+      cpx<double> s = mk(0.0, 0.0);
+      const int kmax = min(i, nc - 1);
+      for (int k = 0; k <= kmax; ++k) s = s + V(i, k) * Ms[k * BW + c];
+      Xl[e] = Xl[e] - 0.5 * s;
+    }
+    // the panel back: R on and above the diagonal, V below
+    for (int e = tid; e < m * BW; e += NT) A[(long long)(r0 + e / BW) * n + kb + e % BW] = Pl[e];
+    __syncthreads();
+    // A22 -= W V^H + V W^H, 4 x 4 blocks per thread
+    const int nb = (m + 3) >> 2;
+    for (int u = tid; u < nb * nb; u += NT) {
+      const int i0 = 4 * (u / nb), j0 = 4 * (u % nb);
+      cpx<double> x[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          x[a][b] = (i0 + a < m && j0 + b < m) ? A[(long long)(r0 + i0 + a) * n + r0 + j0 + b] : mk(0.0, 0.0);
+      for (int c = 0; c < nc; ++c) {
+        cpx<double> vr[4], wr[4], vc[4], wc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int ir = min(i0 + a, m - 1), jc = min(j0 + a, m - 1);
+          vr[a] = V(ir, c);
+          wr[a] = Xl[ir * BW + c];
+          vc[a] = cconj(V(jc, c));
+          wc[a] = cconj(Xl[jc * BW + c]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) x[a][b] = sub2prod(x[a][b], wr[a], vc[b], vr[a], wc[b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (i0 + a < m && j0 + b < m) A[(long long)(r0 + i0 + a) * n + r0 + j0 + b] = x[a][b];
+    }
+    __syncthreads();
+  }
+}
+
+
+// Stage 2: the lower band (half-width BW) of A -> real symmetric tridiagonal
+// (S.d, S.e); the chase reflectors go to R2 in application order, BS_REC
+// complex each: v[0..BW) (v_0 = 1, zero past len), tau, (row0, len).
+// Returns false if a wave waited past its spin limit (the result is then
+// marked failed by the caller).
+template <class SH>
+__device__ bool band_stage2(const cpx<double>* __restrict__ A, int n, cpx<double>* __restrict__ R2, SH& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  cpx<double>* L = S.big;  // L[c * BS_LD + d] = A[c + d][c], d <= 2 BW
+  for (int e = tid; e < n * BS_LD; e += NT) {
+    const int c = e / BS_LD, d = e % BS_LD;
+    cpx<double> x = (d <= BW && c + d < n) ? A[(long long)(c + d) * n + c] : mk(0.0, 0.0);
+    if (d == 0) x.im = 0.0;
+    L[e] = x;
+  }
+  if (tid < NW) S.stamp[tid] = -1;
+  if (tid == 0) S.fail = 0;
+  __syncthreads();
+  // lane = 4 bi + bq owns row bi of a BW x BW block and its columns 4 bq .. 4 bq + 3
+  const int bi = lane >> 2, bq = lane & 3;
+  auto at = [&](int i, int j) -> cpx<double>& { return L[j * BS_LD + (i - j)]; };  // i >= j
+  auto bcast = [&](cpx<double> x, int k) -> cpx<double> {  // row k's value from lane 4 k
+    return mk(__shfl(x.re, 4 * k, 64), __shfl(x.im, 4 * k, 64));
+  };
+  // D <- H^H D H on the diagonal block [r, r + len): p = D v, w = tau p -
+  // (|tau|^2 / 2)(v^H p) v, D -= w v^H + v w^H (lower triangle written)
+  auto two_sided = [&](int r, int len, cpx<double> v, cpx<double> tau) {
+    cpx<double> dl[4];
+    double pr = 0, pim = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * bq + u;
+      const cpx<double> vk = bcast(v, k);
+      dl[u] = mk(0.0, 0.0);
+      if (bi < len && k < len) dl[u] = bi >= k ? at(r + bi, r + k) : cconj(at(r + k, r + bi));
+      const cpx<double> t = dl[u] * vk;
+      pr += t.re;
+      pim += t.im;
+    }
+    pr += __shfl_xor(pr, 1, 64);
+    pim += __shfl_xor(pim, 1, 64);
+    pr += __shfl_xor(pr, 2, 64);
+    pim += __shfl_xor(pim, 2, 64);
+    const cpx<double> p = mk(pr, pim);
+    double g = bq == 0 ? v.re * p.re + v.im * p.im : 0.0;
+    for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off, 64);
+    const double cc = 0.5 * cabs2(tau) * g;
+    const cpx<double> w = tau * p - cc * v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * bq + u;
+      const cpx<double> vk = bcast(v, k), wk = bcast(w, k);
+      if (bi < len && k <= bi) {
+        cpx<double> x = sub2prod(dl[u], w, cconj(vk), v, cconj(wk));
+        if (k == bi) x.im = 0.0;
+        at(r + bi, r + k) = x;
+      }
+    }
+  };
+  auto record = [&](int idx, int r, int len, cpx<double> v, cpx<double> tau) {
+    cpx<double>* rec = R2 + (long long)idx * BS_REC;
+    if (bq == 0) rec[bi] = v;
+    if (lane == 0) {
+      rec[BW] = tau;
+      rec[BW + 1] = mk((double)r, (double)len);
+    }
+  };
+  bool ok = true;
+  for (int j = wave; j + 1 < n; j += NW) {
+    int idx = 0;  // first reflector of sweep j
+    for (int jj = 0; jj < j; ++jj) idx += (n - 1 - jj + BW - 1) / BW;
+    cpx<double> pv = mk(0.0, 0.0), ptau = mk(0.0, 0.0);  // the previous step's reflector
+    for (int t = 0;; ++t) {
+      const int r = j + 1 + t * BW;  // this step's diagonal block [r, r + len)
+      if (r > n - 1) break;
+      const int len = min(BW, n - r);
+      if (j > 0 && ok) {  // sweep j - 1 must have finished its step t + 2
+        // (a step takes microseconds: a wait past the spin limit means a
+        // fault of this code; the wave then stops waiting and the result is
+        // reported as failed, so the kernel always ends)
+        const int target = (j - 1) * 65536 + t + 3;
+        int spins = 0;
+        while (__hip_atomic_load(&S.stamp[(j - 1) % NW], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+          if (++spins > (1 << 20)) {
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      cpx<double> v, tau;
+      double beta;
+      if (t == 0) {
+        // column j, rows [r, r + len)
+        const cpx<double> x = (bq == 0 && bi < len) ? at(r + bi, j) : mk(0.0, 0.0);
+        wave_house(x, len, v, tau, beta);
+        if (bq == 0 && bi < len) at(r + bi, j) = bi == 0 ? mk(beta, 0.0) : mk(0.0, 0.0);
+        if (lane == 0) S.e[j] = beta;
+      } else {
+        // the block B below the previous diagonal block: rows [r, r + len),
+        // columns [pr, pr + BW): B <- B H_prev, then the reflector of B's
+        // first column and its left application to the other columns
+        const int pr = r - BW;
+        cpx<double> b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) b[u] = bi < len ? at(r + bi, pr + 4 * bq + u) : mk(0.0, 0.0);
+        double sr = 0, si = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const cpx<double> t2 = b[u] * bcast(pv, 4 * bq + u);
+          sr += t2.re;
+          si += t2.im;
+        }
+        sr += __shfl_xor(sr, 1, 64);
+        si += __shfl_xor(si, 1, 64);
+        sr += __shfl_xor(sr, 2, 64);
+        si += __shfl_xor(si, 2, 64);
+        const cpx<double> ts = ptau * mk(sr, si);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) b[u] = subprod(b[u], ts, cconj(bcast(pv, 4 * bq + u)));
+        const cpx<double> x = (bq == 0 && bi < len) ? b[0] : mk(0.0, 0.0);
+        wave_house(x, len, v, tau, beta);
+        const cpx<double> ctv = cconj(tau) * v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          double qr = 0, qi = 0;
+          dotacc(qr, qi, v, b[u]);  // conj(v_bi) B[bi][k]
+          for (int off = 4; off < 64; off <<= 1) {
+            qr += __shfl_xor(qr, off, 64);
+            qi += __shfl_xor(qi, off, 64);
+          }
+          if (4 * bq + u >= 1) b[u] = subprod(b[u], ctv, mk(qr, qi));
+        }
+        if (bq == 0) b[0] = bi == 0 ? mk(beta, 0.0) : mk(0.0, 0.0);
+        if (bi < len)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) at(r + bi, pr + 4 * bq + u) = b[u];
+      }
+      record(idx + t, r, len, v, tau);
+      two_sided(r, len, v, tau);
+      pv = v;
+      ptau = tau;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __hip_atomic_store(&S.stamp[wave], j * 65536 + t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __hip_atomic_store(&S.stamp[wave], j * 65536 + 65535, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  if (!ok) S.fail = 1;
+  __syncthreads();
+  for (int c = tid; c < n; c += NT) S.d[c] = L[c * BS_LD].re;
+  __syncthreads();
+  return S.fail == 0;
+}
+
+// Stage 4: Z <- Q1 Q2 Z for the kz leading columns of dsc.evecs (ld n).
+template <class SH>
+__device__ void band_back(const EigDesc& dsc, const cpx<double>* __restrict__ A, int n, int kz,
+                          const cpx<double>* __restrict__ Tg, const cpx<double>* __restrict__ R2, SH& S) {
+  cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
+  cpx<double>* Zl = S.big;                       // n x BS_ZC
+  cpx<double>* Xl = S.big + BS_NMAX * BS_ZC;     // staged reflectors, then BW x BS_ZC products
+  const int tid = threadIdx.x, g = tid >> 4, li = tid & 15;
+  const int nrefl = band_reflectors(n);
+  int npan = 0;
+  while (npan * BW + BW < n) ++npan;
+  for (int z0 = 0; z0 < kz; z0 += BS_ZC) {
+    const int zc = min(BS_ZC, kz - z0);
+    for (int e = tid; e < n * BS_ZC; e += NT) {
+      const int r = e / BS_ZC, c = e % BS_ZC;
+      Zl[e] = c < zc ? Z[(long long)r * n + z0 + c] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    // chase reflectors, the last first; group g (16 lanes) owns column g
+    for (int top = nrefl; top > 0; top -= BS_RC) {
+      const int lo = top > BS_RC ? top - BS_RC : 0, cnt = top - lo;
+      for (int e = tid; e < cnt * BS_REC; e += NT) Xl[e] = R2[(long long)lo * BS_REC + e];
+      __syncthreads();
+      if (g < zc) {
+        for (int k = cnt - 1; k >= 0; --k) {
+          const cpx<double>* rec = Xl + k * BS_REC;
+          const cpx<double> meta = rec[BW + 1];
+          const int r = (int)meta.re, len = (int)meta.im;
+          const cpx<double> tau = rec[BW];
+          const cpx<double> v = rec[li];
+          cpx<double> z = li < len ? Zl[(r + li) * BS_ZC + g] : mk(0.0, 0.0);
+          double sr = 0, si = 0;
+          dotacc(sr, si, v, z);
+          for (int off = 1; off < 16; off <<= 1) {
+            sr += __shfl_xor(sr, off, 16);
+            si += __shfl_xor(si, off, 16);
+          }
+          z = subprod(z, tau * v, mk(sr, si));
+          if (li < len) Zl[(r + li) * BS_ZC + g] = z;
+        }
+      }
+      __syncthreads();
+    }
+    // panels, the last first: Z[r0:] -= V (T (V^H Z[r0:]))
+    for (int p = npan - 1; p >= 0; --p) {
+      const int kb = p * BW, r0 = kb + BW, m = n - r0, nc = m < BW ? m : BW;
+      auto V = [&](int i, int c) -> cpx<double> {
+        return (c >= nc || i < c) ? mk(0.0, 0.0) : (i == c ? mk(1.0, 0.0) : A[(long long)(r0 + i) * n + kb + c]);
+      };
+      for (int e = tid; e < BW * BS_ZC; e += NT) {
+        const int c1 = e / BS_ZC, c = e % BS_ZC;
+        double sr = 0, si = 0;
+        if (c1 < nc && c < zc)
+          for (int i = c1; i < m; ++i) dotacc(sr, si, V(i, c1), Zl[(r0 + i) * BS_ZC + c]);
+        Xl[e] = mk(sr, si);
+      }
+      __syncthreads();
+      // Xl <- T Xl in place (T upper triangular: row c1 needs rows >= c1)
+      if (tid < zc) {
+        const cpx<double>* T = Tg + (long long)p * BW * BW;
+        for (int c1 = 0; c1 < nc; ++c1) {
+          cpx<double> s = mk(0.0, 0.0);
+          for (int k = c1; k < nc; ++k) s = s + T[c1 * BW + k] * Xl[k * BS_ZC + tid];
+          Xl[c1 * BS_ZC + tid] = s;
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < m * BS_ZC; e += NT) {
+        const int i = e / BS_ZC, c = e % BS_ZC;
+        if (c >= zc) continue;
+        cpx<double> s = mk(0.0, 0.0);
+        const int kmax = min(i, nc - 1);
+        for (int k = 0; k <= kmax; ++k) s = s + V(i, k) * Xl[k * BS_ZC + c];
+        Zl[(r0 + i) * BS_ZC + c] = Zl[(r0 + i) * BS_ZC + c] - s;
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < n * BS_ZC; e += NT) {
+      const int r = e / BS_ZC, c = e % BS_ZC;
+      if (c < zc) Z[(long long)r * n + z0 + c] = Zl[e];
+    }
+    __syncthreads();
+  }
+}
+
+// The whole solver for 128 < n <= BS_NMAX (see the section comment).
+template <class SH>
+__device__ void heev_band(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S) {
+  const int n = dsc.n, tid = threadIdx.x;
+  int par = 0;
+  const cpx<double>* a = reinterpret_cast<const cpx<double>*>(dsc.a);
+  for (int e = tid; e < n * n; e += NT) {
+    const int i = e / n, j = e % n;
+    if (dsc.upper) {
+      const cpx<double> x = i <= j ? a[(long long)i * dsc.lda + j] : a[(long long)j * dsc.lda + i];
+      A[e] = i < j ? x : i > j ? cconj(x) : mk(x.re, 0.0);
+    } else {
+      const cpx<double> x = a[(long long)i * dsc.lda + j], y = a[(long long)j * dsc.lda + i];
+      A[e] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+    }
+  }
+  __syncthreads();
+  double tr = 0;
+  for (int i = tid; i < n; i += NT) tr += A[i * n + i].re;
+  tr = block_sum(tr, S.red, par);
+  const long long np = (n + 63) / 64 * 64;
+  cpx<double>* Tg = reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n + 7LL * n * np + 64);
+  cpx<double>* R2 = Tg + BS_PANELS * BW * BW;
+  band_stage1(A, n, Tg, S, par);
+  const bool ok = band_stage2(A, n, R2, S);
+  for (int i = tid; i + 1 < n; i += NT) S.e2[i] = S.e[i] * S.e[i];
+  __syncthreads();
+  const int kz = eig_tail<NT>(dsc, n, tr, S, par);
+  if (!ok && tid == 0 && dsc.trace) *dsc.trace = __builtin_nan("");
+  if (kz > 0) band_back(dsc, A, n, kz, Tg, R2, S);
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1361,12 +1909,22 @@ __global__ __launch_bounds__(NTR) void k_heev_reg(const EigDesc* __restrict__ de
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
 
-// n in (128, 512]: the matrix in global memory (L2-resident).
-__global__ __launch_bounds__(NT) void k_heev_global(const EigDesc* __restrict__ descs, int* __restrict__ status) {
+// n in (nlo, 512], nlo >= 128: the matrix in global memory (L2-resident).
+__global__ __launch_bounds__(NT) void k_heev_global(const EigDesc* __restrict__ descs, int* __restrict__ status,
+                                                    int nlo) {
   __shared__ SharedG<512> S;
   const EigDesc& d = descs[blockIdx.x];
-  if (!d.active || d.n <= REG_NMAX || d.n > 512) return;
+  if (!d.active || d.n <= nlo || d.n > 512) return;
   heev_core<true>(d, reinterpret_cast<cpx<double>*>(d.work), S);
+  if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
+}
+
+// n in (128, 256]: the two-stage reduction through a band (heev_band).
+__global__ __launch_bounds__(NT) void k_heev_band(const EigDesc* __restrict__ descs, int* __restrict__ status) {
+  __shared__ SharedBand S;
+  const EigDesc& d = descs[blockIdx.x];
+  if (!d.active || d.n <= REG_NMAX || d.n > BS_NMAX) return;
+  heev_band(d, reinterpret_cast<cpx<double>*>(d.work), S);
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
 
@@ -1378,6 +1936,16 @@ __global__ __launch_bounds__(NT) void k_heev_big(const EigDesc* __restrict__ des
   heev_core<false>(d, reinterpret_cast<cpx<double>*>(d.work), S);
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
+
+namespace {
+// n in (128, 256] through the band path.  Off by default: every stage of it
+// is a long chain of small dependent steps (about 2,200 chase steps and as
+// many reflector applications per n = 256 matrix, each ~1 us), which costs
+// more than the one-stage kernel's extra memory traffic on this hardware.
+bool g_band = false;
+}  // namespace
+void set_eig_band(bool on) { g_band = on; }
+bool eig_band() { return g_band; }
 
 hipError_t set_eig_residual_bound(double rtol) {
   return hipMemcpyToSymbol(HIP_SYMBOL(g_eig_rtol), &rtol, sizeof(double));
@@ -1391,10 +1959,16 @@ void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hi
   if (maxn > SMALL_NMAX)
     hipLaunchKernelGGL((k_heev_reg<REG_NMAX, 512, SMALL_NMAX, 4>), dim3(nitems), dim3(512), 0, s, d_descs, d_status);
   prof_end_eig(tok, PC_EIG_REG, d_descs, nitems, 1, REG_NMAX, s);
-  if (maxn > REG_NMAX) {
+  const int nlo = g_band ? BS_NMAX : REG_NMAX;  // largest n left to the band path
+  if (maxn > REG_NMAX && g_band) {
+    tok = prof_begin(PC_EIG_BAND, s);
+    hipLaunchKernelGGL(k_heev_band, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
+    prof_end_eig(tok, PC_EIG_BAND, d_descs, nitems, REG_NMAX + 1, BS_NMAX, s);
+  }
+  if (maxn > nlo) {
     tok = prof_begin(PC_EIG_GLOBAL, s);
-    hipLaunchKernelGGL(k_heev_global, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
-    prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, REG_NMAX + 1, 512, s);
+    hipLaunchKernelGGL(k_heev_global, dim3(nitems), dim3(NT), 0, s, d_descs, d_status, nlo);
+    prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, nlo + 1, 512, s);
   }
   if (maxn > 512) {
     tok = prof_begin(PC_EIG_GLOBAL, s);

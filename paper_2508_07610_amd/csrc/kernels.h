@@ -55,6 +55,10 @@ void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int ni
 // An eigenpair whose tridiagonal residual ||(T - lambda) z|| exceeds
 // 1e-9 ||T||, or a non-finite spectrum, sets the item's trace to NaN.
 void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hipStream_t s);
+// 128 < n <= 256 through the two-stage (band) reduction or the one-stage
+// panel reduction (the default); process-wide.
+void set_eig_band(bool on);
+bool eig_band();
 // Overrides the residual bound on the current device (0 restores 1e-9).
 hipError_t set_eig_residual_bound(double rtol);
 

@@ -14,7 +14,8 @@ enum ProfClass : int {
   PC_GEMM_F32 = 1,   // contractions on FP32 MFMA (mixed precision)
   PC_EIG_REG = 2,    // Hermitian eigensolver, matrix in registers (n <= 128)
   PC_EIG_GLOBAL = 3, // Hermitian eigensolver, matrix in global memory
-  PC_NCLASS = 4
+  PC_EIG_BAND = 4,   // Hermitian eigensolver, two-stage through a band (128 < n <= 256)
+  PC_NCLASS = 5
 };
 
 // Returns an opaque token (>= 0) if the launch is profiled, else -1.

@@ -24,7 +24,7 @@ struct Prof {
   std::mutex mu;
   bool on = false;
   std::vector<EventPair> ev;
-  int launches[PC_NCLASS] = {0, 0, 0, 0};
+  int launches[PC_NCLASS] = {};
   int site_launches[GS_N] = {};
   double* dcount = nullptr;
 };

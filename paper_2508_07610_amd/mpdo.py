@@ -508,9 +508,9 @@ def tune_get(site: int):
     return t.value, f.value, s.value
 
 
-PROF_GEMM_F64, PROF_GEMM_F32, PROF_EIG_REG, PROF_EIG_GLOBAL = range(4)
+PROF_GEMM_F64, PROF_GEMM_F32, PROF_EIG_REG, PROF_EIG_GLOBAL, PROF_EIG_BAND = range(5)
 PROF_NAMES = {PROF_GEMM_F64: "k_gemm (FP64 MFMA)", PROF_GEMM_F32: "k_gemm (FP32 MFMA)",
-              PROF_EIG_REG: "k_heev_reg", PROF_EIG_GLOBAL: "k_heev_global"}
+              PROF_EIG_REG: "k_heev_reg", PROF_EIG_GLOBAL: "k_heev_global", PROF_EIG_BAND: "k_heev_band"}
 
 
 def profile_enable(on: bool = True) -> None:
@@ -560,6 +560,8 @@ def _testing_lib():
         L.mpdo_test_profile_site.restype = ctypes.c_int
         L.mpdo_test_gemm_form.argtypes = [i32, i32, i32, ctypes.POINTER(i32)]
         L.mpdo_test_gemm_form.restype = ctypes.c_int
+        L.mpdo_test_eig_band.argtypes = [i32, ctypes.POINTER(i32)]
+        L.mpdo_test_eig_band.restype = ctypes.c_int
         L._testing_sig = True
     return L
 
@@ -597,6 +599,15 @@ def gemm_form(prec: int, tile: int, form: int) -> int:
     prev = ctypes.c_int32()
     check(_testing_lib().mpdo_test_gemm_form(prec, tile, form, ctypes.byref(prev)))
     return prev.value
+
+
+def eig_band(on: bool) -> bool:
+    """Route 128 < n <= 256 eigenproblems through the two-stage band
+    reduction (True) or the one-stage panel reduction (False, the default);
+    returns the previous setting."""
+    prev = ctypes.c_int32()
+    check(_testing_lib().mpdo_test_eig_band(1 if on else 0, ctypes.byref(prev)))
+    return bool(prev.value)
 
 
 def test_fail_next_update(status: int) -> None:

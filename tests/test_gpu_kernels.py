@@ -203,14 +203,53 @@ def test_profiler_counts_gemm_and_eig_work():
     M.test_eigh(X @ X.conj().T, 10)
     e = M.profile_read(M.PROF_EIG_REG)
     Y = _rand((200, 200), rng)
-    M.test_eigh(Y @ Y.conj().T, 20)
-    e2 = M.profile_read(M.PROF_EIG_GLOBAL)
+    prev = M.eig_band(True)
+    try:
+        M.test_eigh(Y @ Y.conj().T, 20)
+    finally:
+        M.eig_band(prev)
+    e2 = M.profile_read(M.PROF_EIG_BAND)
+    Z = _rand((300, 300), rng)
+    M.test_eigh(Z @ Z.conj().T, 30)
+    e3 = M.profile_read(M.PROF_EIG_GLOBAL)
     M.profile_enable(False)
     assert g["launches"] == 1 and g["ms"] > 0
     assert g["flops"] == 8.0 * 70 * 90 * 33
     assert g["bytes"] == 16.0 * (70 * 33 + 33 * 90 + 70 * 90)
     assert e["launches"] == 1 and abs(e["flops"] - (16.0 / 3.0 * 100 ** 3 + 8.0 * 100 ** 2 * 10)) < 1.0
     assert e2["launches"] == 1 and abs(e2["flops"] - (16.0 / 3.0 * 200 ** 3 + 8.0 * 200 ** 2 * 20)) < 1.0
+    assert e3["launches"] == 1 and abs(e3["flops"] - (16.0 / 3.0 * 300 ** 3 + 8.0 * 300 ** 2 * 30)) < 1.0
+
+
+@pytest.mark.parametrize("band", [True, False])
+@pytest.mark.parametrize("n,kvec", [(129, 129), (144, 20), (200, 64), (256, 65), (256, 256)])
+def test_eigh_band_and_panel_paths(band, n, kvec):
+    """128 < n <= 256 through the two-stage reduction (dense -> band of
+    half-width 16 by blocked Householder, bulge chasing to tridiagonal,
+    back-transformation through both) and through the one-stage panel
+    reduction: eigenvalues to 1e-13, orthonormal vectors and residuals to
+    1e-12 of the largest eigenvalue, on a spectrum with a degenerate pair, a
+    tight cluster and a null space (as in a bond Gram)."""
+    require_gpu()
+    rng = np.random.default_rng(n + kvec)
+    Q, _ = np.linalg.qr(_rand((n, n), rng))
+    d = np.concatenate([[3.0, 3.0], np.sort(rng.uniform(0.0, 1.0, n // 2))[::-1],
+                        1e-3 * (1 + 1e-9 * np.arange(6)), np.zeros(n - n // 2 - 8)])
+    A = (Q * d) @ Q.conj().T
+    prev = M.eig_band(band)
+    try:
+        ev, V, tr = M.test_eigh(A, kvec)
+    finally:
+        M.eig_band(prev)
+    ref = np.sort(np.linalg.eigvalsh(A))[::-1]
+    kb = min(n, kvec + 1)
+    assert float(np.abs(ev[:kb] - ref[:kb]).max()) <= 1e-13 * 3
+    assert abs(tr - np.trace(A).real) < 1e-12 * n
+    kz = int(np.sum(ref[:kvec] > 1e-13 * ref[0]))
+    Vk = V[:, :kz]
+    assert float(np.abs(Vk.conj().T @ Vk - np.eye(kz)).max()) < 1e-12
+    assert float(np.abs(A @ Vk - Vk * ev[:kz]).max()) < 1e-12 * 3
+    assert float(np.abs(V[:, kz:kvec]).max(initial=0.0)) == 0.0
 
 
 def test_gemm_rate_entry_point():
