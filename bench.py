@@ -485,7 +485,7 @@ def noise_models_leg(shots=4096):
 
 
 def truncation_study_leg(ncirc=1000):
-    """Sec. IV.C at the paper's scale: mean Uhlmann fidelity between lossless
+    """Sec. IV.C at the paper's scale: mean Uhlmann fidelity between reference
     and truncated states of random circuits with RZ crosstalk (Q = 3 and 6,
     depth 4), 1,000 circuits per point, over a grid of (chi, kappa); every
     circuit of a point and limit in one mpdo_batch_run_dense, FP64."""
@@ -498,7 +498,7 @@ def truncation_study_leg(ncirc=1000):
         out[f"Q={q},depth=4"] = {"fidelity": r["fidelity"], "device_seconds": r["device_seconds"],
                                  "seconds": time.perf_counter() - t0}
     return {"workload": f"{ncirc} random RX/RY/RZ + CNOT circuits per Q, RZ(alpha) crosstalk on the neighbour of "
-                        "every CNOT, QPT-style channels, lossless reference at chi=64 kappa=64, one batched dense "
+                        "every CNOT, QPT-style channels, reference at chi=64 kappa=64 (lossless to its own discarded weight), one batched dense "
                         "run per limit", "results": out}
 
 

@@ -23,46 +23,10 @@ from . import mpdo as M
 from . import workloads as W
 
 
-def _z_pair_products(n: int, pairs) -> np.ndarray:
-    I, Z = np.eye(2, dtype=np.complex128), np.diag([1.0, -1.0]).astype(np.complex128)
-    ops = np.zeros((len(pairs), n, 2, 2), dtype=np.complex128)
-    for k, (a, b) in enumerate(pairs):
-        for s in range(n):
-            ops[k, s] = Z if s in (a, b) else I
-    return ops
-
-
-def _ghz_terms(n: int) -> np.ndarray:
-    p0, p1 = np.diag([1.0, 0.0]), np.diag([0.0, 1.0])
-    up = np.array([[0, 1], [0, 0]], dtype=np.complex128)
-    return np.stack([np.stack([m.astype(np.complex128)] * n) for m in (p0, p1, up)])
-
-
 def instances(n_ghz: int = 256, n_qaoa: int = 128, depth: int = 6, seed_tag: int = 0):
-    """Programs, the parameter matrix, the observables and per-instance info."""
-    progs, params, obs, info = [], [], [], []
-    for t in range(n_ghz):
-        th = W.ansatz_params(12, depth, 100000 * (seed_tag + 1) + t)
-        progs.append(W.ghz_ansatz(12, depth, th))
-        params.append(th)
-        obs.append(np.concatenate([_z_pair_products(12, [(i, i + 1) for i in range(11)]), _ghz_terms(12)]))
-        info.append({"kind": "ghz", "n": 12})
-    rng = W.rng_for(9000 + seed_tag)
-    for t in range(n_qaoa):
-        n = int(rng.choice(np.arange(8, 21, 2)))
-        edges = W.random_3_regular(n, rng)
-        gb = rng.uniform(0, math.pi, size=4)
-        prog, pos = W.qaoa_swap_network(n, edges, gb[0::2], gb[1::2])
-        where = {lq: s for s, lq in enumerate(pos)}
-        progs.append(prog)
-        params.append(gb)
-        obs.append(_z_pair_products(n, [(where[u], where[v]) for u, v in edges]))
-        info.append({"kind": "qaoa", "n": n, "edges": len(edges)})
-    width = max(len(p) for p in params)
-    P = np.zeros((len(params), width))
-    for b, p in enumerate(params):
-        P[b, : len(p)] = p
-    return progs, P, obs, info
+    """Programs, the parameter matrix, the observables and per-instance info
+    (the seeded recipe of workloads.maxcut_batch_instances)."""
+    return W.maxcut_batch_instances(n_ghz, n_qaoa, depth, seed_tag)
 
 
 def run(n_ghz: int = 256, n_qaoa: int = 128, depth: int = 6, chi_max: int = 32, kappa_max: int = 4,
@@ -86,8 +50,10 @@ def run(n_ghz: int = 256, n_qaoa: int = 128, depth: int = 6, chi_max: int = 32, 
     res = out.cpu().numpy()
     off = 0
     per: List[Dict] = []
+    raw: List[np.ndarray] = []
     for b, (pr, ob, inf) in enumerate(zip(progs, obs, info)):
         k = ob.shape[0]
+        raw.append(res[off: off + k])
         v = res[off: off + k].real
         off += k
         if inf["kind"] == "ghz":
@@ -95,5 +61,5 @@ def run(n_ghz: int = 256, n_qaoa: int = 128, depth: int = 6, chi_max: int = 32, 
             per.append({**inf, "ghz_fidelity": float(f), "zz": v[:11].tolist()})
         else:
             per.append({**inf, "h_cut": float(np.sum((1 - v) / 2)), "zz_edges": v.tolist()})
-    return {"instances": per, "seconds": times, "programs": progs, "params": P, "observables": obs,
+    return {"instances": per, "raw": raw, "seconds": times, "programs": progs, "params": P, "observables": obs,
             "channels": chans, "config": kw, "gates": sum(len(p.ops) for p in progs)}

@@ -15,7 +15,8 @@ of the dense results (n <= 12).
 
 ``run_batched`` is the study at the paper's scale: all circuits of one
 (Q, depth) point and one (chi, kappa) limit in one ``mpdo_batch_run_dense``
-call (the lossless reference at chi = kappa = 64 is one more such call), the
+call (the reference at chi = kappa = 64, the largest limits, is one more such
+call; it is lossless only to within its own discarded weight), the
 paper's 1,000 circuits per point."""
 from __future__ import annotations
 
@@ -57,8 +58,10 @@ def circuit(q: int, depth: int, rng: np.random.Generator) -> "W.Program":
 def run(q: int, depth: int, limits: Sequence[Tuple[int, int]], ncirc: int, seed: int = 0,
         full: Tuple[int, int] = (64, 64)) -> Dict:
     """Fidelity of each (chi, kappa) in `limits` against the run with the
-    `full` limits (large enough to be lossless at these sizes), averaged over
-    `ncirc` circuits; FP64 path, svd and inner cutoffs at 1e-14."""
+    `full` limits (the largest the library takes; not exactly lossless: its
+    own discarded weight, ~1e-7 at Q = 3 depth 4, bounds how close to 1 a
+    fidelity is resolved), averaged over `ncirc` circuits; FP64 path, svd and
+    inner cutoffs at 1e-14."""
     rng = W.rng_for(4500 + seed)
     chans = None
     fid = {lim: [] for lim in limits}
@@ -113,9 +116,9 @@ def circuits(q: int, depth: int, ncirc: int, seed: int = 0) -> List["W.Program"]
 def run_batched(q: int, depth: int, limits: Sequence[Tuple[int, int]], ncirc: int = 1000, seed: int = 0,
                 full: Tuple[int, int] = (64, 64), prec: int = M.C128, per_circuit: bool = False) -> Dict:
     """The Sec. IV.C study at scale: `ncirc` seeded circuits of one (q, depth)
-    point, each (chi, kappa) of `limits` and the lossless `full` limits run
+    point, each (chi, kappa) of `limits` and the reference `full` limits run
     as one batch each; returns per limit the mean, standard deviation and
-    minimum of the Uhlmann fidelity against the lossless state (and every
+    minimum of the Uhlmann fidelity against the reference state (and every
     circuit's value with per_circuit), and the device seconds of the
     batches."""
     import time

@@ -480,3 +480,54 @@ def ghz_ansatz_noise(n: int, depth: int, theta: np.ndarray, noise: Optional[np.n
             for q in range(parity, n - 1, 2):
                 ops.append(Op((q, q + 1), CZ.copy(), NOISE_LEVELS + int(l2[q]), "cz"))
     return Program(n, ops, chis, depth)
+
+
+def z_pair_products(n: int, pairs) -> np.ndarray:
+    """(len(pairs), n, 2, 2): the product operators Z_a Z_b of `pairs`."""
+    I2_, Z_ = np.eye(2, dtype=np.complex128), np.diag([1.0, -1.0]).astype(np.complex128)
+    ops = np.zeros((len(pairs), n, 2, 2), dtype=np.complex128)
+    for k, (a, b) in enumerate(pairs):
+        for s in range(n):
+            ops[k, s] = Z_ if s in (a, b) else I2_
+    return ops
+
+
+def ghz_terms(n: int) -> np.ndarray:
+    """The three product operators of the GHZ fidelity: |0><0|^n, |1><1|^n
+    and |0><1|^n (F = (t0 + t1) / 2 + Re t2)."""
+    p0, p1 = np.diag([1.0, 0.0]), np.diag([0.0, 1.0])
+    up = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+    return np.stack([np.stack([m.astype(np.complex128)] * n) for m in (p0, p1, up)])
+
+
+def maxcut_batch_instances(n_ghz: int = 256, n_qaoa: int = 128, depth: int = 6, seed_tag: int = 0):
+    """The mixed batch of variational GHZ points and QAOA MaxCut instances:
+    `n_ghz` parameter points of the noisy RY/CZ ansatz (n = 12, `depth`
+    layers) and `n_qaoa` QAOA p = 2 instances on random 3-regular graphs with
+    n drawn from {8, 10, ..., 20}, edges routed through the odd-even SWAP
+    network.  Returns the programs, the parameter matrix (rows padded with
+    zeros), the observables (<Z_i Z_i+1> and the GHZ fidelity terms of the
+    ansatz points, <Z_a Z_b> of every graph edge) and per-instance info."""
+    progs, params, obs, info = [], [], [], []
+    for t in range(n_ghz):
+        th = ansatz_params(12, depth, 100000 * (seed_tag + 1) + t)
+        progs.append(ghz_ansatz(12, depth, th))
+        params.append(th)
+        obs.append(np.concatenate([z_pair_products(12, [(i, i + 1) for i in range(11)]), ghz_terms(12)]))
+        info.append({"kind": "ghz", "n": 12})
+    rng = rng_for(9000 + seed_tag)
+    for t in range(n_qaoa):
+        n = int(rng.choice(np.arange(8, 21, 2)))
+        edges = random_3_regular(n, rng)
+        gb = rng.uniform(0, math.pi, size=4)
+        prog, pos = qaoa_swap_network(n, edges, gb[0::2], gb[1::2])
+        where = {lq: s for s, lq in enumerate(pos)}
+        progs.append(prog)
+        params.append(gb)
+        obs.append(z_pair_products(n, [(where[u], where[v]) for u, v in edges]))
+        info.append({"kind": "qaoa", "n": n, "edges": len(edges)})
+    width = max(len(p) for p in params)
+    P = np.zeros((len(params), width))
+    for b, p in enumerate(params):
+        P[b, : len(p)] = p
+    return progs, P, obs, info

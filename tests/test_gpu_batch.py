@@ -126,17 +126,32 @@ def test_batch_rejects_bad_programs():
     assert e.value.status == M.EINVAL
 
 
-def test_mixed_ghz_and_maxcut_batch_at_full_size():
+@pytest.mark.parametrize("prec", [M.C64_MIXED, M.C128])
+def test_mixed_ghz_and_maxcut_batch_at_full_size(prec):
     """256 ansatz points (n=12, depth 6) and 128 QAOA p=2 MaxCut instances
-    (n in 8..20) in one graph-captured batch (chi=32, kappa=4, mixed
-    precision): a sample of instances equals the plain per-gate path of the
-    same precision to the mixed path's accuracy target (both are FP32
-    contractions, summed in different orders by different launch shapes), and
-    every <H_cut> lies in [0, |E|]."""
+    (n in 8..20) in one graph-captured batch (chi=32, kappa=4): a sample of
+    instances equals the plain per-gate path of the same precision (1e-5 in
+    the mixed path, whose FP32 contractions are summed in different orders by
+    different launch shapes; 1e-10 in complex128), every <H_cut> lies in
+    [0, |E|], and the first ansatz point and the first n = 20 QAOA instance
+    equal the oracle's truncated MPDO stored in tests/golden/c3_reference.json
+    (written by make_c3_reference.py, oracle/ only).
+
+    Tolerance against the oracle: 1e-10 (complex128) and 1e-5 (mixed), or
+    10 eps / g when larger, with g the smallest relative gap at the oracle's
+    cuts (a cut that close to a multiplet moves the kept subspace by about
+    eps / g; eps = 2.2e-16, and 6e-8 for the FP32 contractions).  The ansatz
+    point has g = 0.05; the n = 20 QAOA instance has g = 4e-7 (every n = 20
+    instance has cuts below 1e-5 at chi = 32), which gives 5e-9 in complex128
+    and no resolution at all in the mixed path: there only a sanity bound of
+    1e-3 is asserted and the error is printed."""
     require_gpu()
+    import json
+    import os
     from paper_2508_07610_amd import maxcut as MC
-    r = MC.run(n_ghz=256, n_qaoa=128, repeats=1)
+    r = MC.run(n_ghz=256, n_qaoa=128, repeats=1, prec=prec)
     per, progs, obs = r["instances"], r["programs"], r["observables"]
+    tol = 1e-5 if prec == M.C64_MIXED else 1e-10
     assert len(per) == 384
     for p in per:
         if p["kind"] == "qaoa":
@@ -149,4 +164,18 @@ def test_mixed_ghz_and_maxcut_batch_at_full_size():
         M.run_program(progs[b], st, r["channels"])
         plain = st.expect_products(obs[b]).real
         got = np.array(per[b]["zz"] if per[b]["kind"] == "ghz" else per[b]["zz_edges"])
-        assert float(np.abs(got - plain[: len(got)]).max()) < 1e-5, b
+        assert float(np.abs(got - plain[: len(got)]).max()) < tol, b
+    ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_reference.json")))
+    raw = r["raw"]
+    eps = 2.2e-16 if prec == M.C128 else 6e-8
+    for case in ref["cases"]:
+        b = case["index"]
+        want = np.array(case["re"]) + 1j * np.array(case["im"])
+        got = raw[b]
+        err = float(np.abs(got - want).max())
+        bound = max(tol, 10 * eps / case["min_gap"])
+        if bound > 1e-3:
+            bound = 1e-3
+        print(f"prec {prec} instance {b} ({case['kind']}, n={case['n']}, min gap {case['min_gap']:.1e}): "
+              f"max |GPU - oracle| = {err:.2e}, bound {bound:.1e}")
+        assert err < bound, (b, err)

@@ -79,3 +79,30 @@ def test_batched_study_equals_per_circuit_runs():
             f = TS.uhlmann_fidelity(full, dev(prog, *lim))
             assert abs(f - r["fidelity"][f"chi={lim[0]},kappa={lim[1]}"]["all"][i]) < 1e-9, (i, lim)
     assert r["circuits"] == 6
+
+
+@pytest.mark.parametrize("q", [3, 6])
+def test_reference_state_against_the_dense_simulator(q):
+    """The study's reference (chi = kappa = 64, cutoffs 1e-14) against the
+    oracle's dense simulation of the same circuits (Eq. (1) gate by gate):
+    the difference in normalised rho is bounded by the reference's own
+    discarded weight (mpdo_stats), which is what limits how close to 1 a
+    study fidelity can be resolved (the cap kappa * max_kraus <= 1024 keeps
+    kappa at 64)."""
+    require_gpu()
+    for prog in TS.circuits(q, 4, 2, seed=3):
+        kr = [OC.kraus_from_chi(c)[0] for c in prog.chis]
+        d = OM.run_program_dense(prog, OD.DenseSim(q), kr).rho
+        d = d / np.trace(d).real
+        chans = [M.Channel(prog.chis[0], 1), M.Channel(prog.chis[1], 2)]
+        st = M.MPDO(q, chi_max=64, kappa_max=64, max_kraus=16, svd_cutoff=1e-14, kappa_cutoff=1e-14)
+        M.run_program(prog, st, chans)
+        r = st.to_dense()
+        r = r / np.trace(r).real
+        disc = st.stats()["discarded"]
+        err = float(np.abs(r - d).max())
+        print(f"Q={q}: max |reference - dense| = {err:.2e}, discarded weight {disc:.2e}")
+        assert err <= 2 * disc + 1e-12
+        st.close()
+        for c in chans:
+            c.close()
