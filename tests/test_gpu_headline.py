@@ -1,0 +1,97 @@
+"""Parity at the headline workload (n = 16, depth 10 noisy RY/CZ ansatz,
+chi = 64, kappa = 8, cutoffs 1e-10, noise strengths x1 and x3): the GPU, through
+per-gate calls and through one mpdo_batch_run holding both noise strengths
+(graph-captured, as the benchmark runs it), against the oracle's truncated
+MPDO stored in tests/golden/c2_reference.json (written by
+tests/golden/make_c2_reference.py, which calls only oracle/).
+
+Tolerances: observables 1e-10 (complex128) and 1e-5 (complex64 contractions
+with FP64 truncation); bond and inner dimensions exactly and bond weights to
+1e-9 in complex128."""
+import copy
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2508_07610_amd import mpdo as M
+from paper_2508_07610_amd import workloads as W
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {M.C128: 1e-10, M.C64_MIXED: 1e-5}
+REF = json.load(open(os.path.join(HERE, "golden", "c2_reference.json")))
+WL = REF["workload"]
+N, DEPTH = WL["n"], WL["depth"]
+KW = dict(chi_max=WL["chi_max"], kappa_max=WL["kappa_max"], max_kraus=16, svd_cutoff=WL["svd_cutoff"],
+          kappa_cutoff=WL["kappa_cutoff"])
+
+
+def _prog(case):
+    return W.ghz_ansatz(N, DEPTH, W.ansatz_params(N, DEPTH, case["param_tag"]), noise_scale=case["noise_scale"])
+
+
+def _ghz_terms(n):
+    return [np.stack([m.astype(np.complex128)] * n)
+            for m in (np.diag([1.0, 0.0]), np.diag([0.0, 1.0]), np.array([[0.0, 1.0], [0.0, 0.0]]))]
+
+
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+@pytest.mark.parametrize("ci", range(len(REF["cases"])))
+def test_headline_per_gate_matches_oracle(prec, ci):
+    require_gpu()
+    case = REF["cases"][ci]
+    prog = _prog(case)
+    chans = [M.Channel(c, int(round(math.log(c.shape[0], 4)))) for c in prog.chis]
+    st = M.MPDO(N, prec=prec, **KW)
+    M.run_program(prog, st, chans)
+    tol = TOL[prec]
+    zz = [st.expect(s).real for s in W.zz_strings(N)]
+    err = max(abs(a - b) for a, b in zip(zz, case["zz"]))
+    err = max(err, abs(st.fidelity_ghz() - case["ghz_fidelity"]))
+    print(f"noise x{case['noise_scale']} prec {prec}: max |GPU - oracle| = {err:.3e}")
+    assert err < tol
+    bonds, inner, disc = st.dims()
+    assert abs(disc - case["discarded"]) < 1e3 * tol
+    if prec == M.C128:
+        assert bonds == case["bond_dims"]
+        assert inner == case["inner_dims"]
+        for b in range(N - 1):
+            assert np.abs(st.bond_weights(b) - np.array(case["lam"][b])).max() < 1e-9, b
+    s = st.stats()
+    print(f"  discarded {disc:.3e} (oracle {case['discarded']:.3e}), smallest gap at a cut {s['min_gap']:.2e}")
+    assert s["failures"] == 0 and abs(s["discarded"] - disc) < 1e-15
+
+
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+def test_headline_batched_matches_oracle(prec):
+    """Both noise strengths in one graph-captured batch run (the channels of
+    the second program renumbered after the first's)."""
+    require_gpu()
+    import torch
+    progs, chans = [], []
+    for case in REF["cases"]:
+        p = copy.deepcopy(_prog(case))
+        off = len(chans)
+        chans += [M.Channel(c, int(round(math.log(c.shape[0], 4)))) for c in p.chis]
+        for op in p.ops:
+            if op.chan >= 0:
+                op.chan += off
+        progs.append(p)
+    ops = [np.stack([W.pauli_ops(s) for s in W.zz_strings(N)] + _ghz_terms(N)) for _ in progs]
+    params = torch.tensor(np.stack([W.ansatz_params(N, DEPTH, c["param_tag"]) for c in REF["cases"]]),
+                          dtype=torch.float64, device="cuda")
+    out = M.batch_run(progs, params, chans, ops, prec=prec, use_graph=True, **KW).cpu().numpy()
+    tol = TOL[prec]
+    k = len(ops[0])
+    for b, case in enumerate(REF["cases"]):
+        got = out[b * k:(b + 1) * k]
+        zz = got[: N - 1].real
+        f = 0.5 * (got[N - 1].real + got[N].real + 2 * got[N + 1].real)
+        err = max(float(np.abs(zz - np.array(case["zz"])).max()), abs(f - case["ghz_fidelity"]))
+        print(f"batched noise x{case['noise_scale']} prec {prec}: max |GPU - oracle| = {err:.3e}")
+        assert err < tol
