@@ -16,7 +16,7 @@
 //       matrix-vector pass of step k+1 (k_heev_big; lowest latency for a
 //       lone matrix).
 //  2. The leading kvec + 1 eigenvalues of T by multisection on Sturm counts
-//     (a group of lanes per eigenvalue, one count per lane and round).
+//     (a group of lanes per eigenvalue, SP counts per lane and round).
 //  3. Their eigenvectors by inverse iteration on T (tridiagonal LU with
 //     partial pivoting, three solves from a fixed pseudo-random start), one
 //     thread per vector; then Gram-Schmidt (twice) inside clusters of
@@ -94,25 +94,36 @@ __device__ inline double block_sum(double v, double* red, int& parity) {
   return s;
 }
 
-// number of eigenvalues of T (diag d, squared off-diagonal e2) below x.
+// cnt[p]: number of eigenvalues of T (diag d, squared off-diagonal e2)
+// below x[p], for SP points at once (independent chains interleaved).  SP = 1:
+// with eight waves per CU the other waves' chains already hide the latency of
+// the reciprocal, and four points per lane made the C2 step's eigensolvers 8 %
+// slower for 1.6 times fewer rounds.
 // e2 / q is formed as e2 times the hardware reciprocal estimate of q refined
 // by two Newton steps (relative error at the rounding level; the IEEE divide
 // sequence is several times longer on this dependent chain).  |q| >= pivmin
 // keeps the reciprocal finite, and the count stays backward stable.
-__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += q < 0;
-  for (int i = 1; i < n; ++i) {
-    double r = __builtin_amdgcn_rcp(q);
-    r = r * (2.0 - q * r);
-    r = r * (2.0 - q * r);
-    q = (d[i] - x) - e2[i - 1] * r;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0;
+constexpr int SP = 1;
+__device__ void sturm_counts(const double* d, const double* e2, int n, const double* x, double pivmin, int* cnt) {
+  double q[SP];
+#pragma unroll
+  for (int p = 0; p < SP; ++p) {
+    q[p] = d[0] - x[p];
+    if (fabs(q[p]) < pivmin) q[p] = -pivmin;
+    cnt[p] = q[p] < 0;
   }
-  return cnt;
+  for (int i = 1; i < n; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+#pragma unroll
+    for (int p = 0; p < SP; ++p) {
+      double r = __builtin_amdgcn_rcp(q[p]);
+      r = r * (2.0 - q[p] * r);
+      r = r * (2.0 - q[p] * r);
+      q[p] = (di - x[p]) - ei * r;
+      if (fabs(q[p]) < pivmin) q[p] = -pivmin;
+      cnt[p] += q[p] < 0;
+    }
+  }
 }
 
 // deterministic start vector entries in [-1, 1]
@@ -232,7 +243,9 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   {
     // groups stay inside a wave: the widest L that still gives every
-    // eigenvalue a group (the last 64 mod L lanes of each wave sit out)
+    // eigenvalue a group (the last 64 mod L lanes of each wave sit out); each
+    // lane evaluates SP points, so a round cuts the bracket into L SP + 1
+    // pieces
     int L = 64;
     while (L > 1 && (64 / L) * (NTH / 64) < kb) --L;
     const int gpw = 64 / L, groups = gpw * (NTH / 64);
@@ -240,20 +253,32 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
     const int gl = (tid & 63) - gi * L;
     const int first = gi * L;  // first lane of the group in its wave
     const unsigned long long gmask = (L == 64) ? ~0ULL : ((1ULL << L) - 1ULL);
-    const double inv = 1.0 / (double)(L + 1);
+    const int K = L * SP;
+    const double inv = 1.0 / (double)(K + 1);
     for (int j = gi < gpw ? (tid >> 6) * gpw + gi : kb; j < kb; j += groups) {
       const int target = n - 1 - j;  // eigenvalues strictly below lambda_j (no ties)
       double l = lo, h = hi;
       for (int it = 0; it < 120; ++it) {
         if (h - l <= fmax(2.5e-16 * fmax(fabs(l), fabs(h)), 4e-17 * tnorm)) break;
         const double w = h - l;
-        const double x = l + w * ((double)(gl + 1) * inv);
-        const bool above = sturm_count(S.d, S.e2, n, x, pivmin) > target;
-        const unsigned long long m = (__ballot(above) >> first) & gmask;
-        // first lane at or above the eigenvalue (L if none)
+        double x[SP];
+        int cnt[SP];
+#pragma unroll
+        for (int p = 0; p < SP; ++p) x[p] = l + w * ((double)(gl * SP + p + 1) * inv);
+        sturm_counts(S.d, S.e2, n, x, pivmin, cnt);
+        // this lane's first point at or above the eigenvalue (SP if none);
+        // the counts grow with x, so the points above form a suffix
+        int fp = SP;
+#pragma unroll
+        for (int p = SP - 1; p >= 0; --p)
+          if (cnt[p] > target) fp = p;
+        const unsigned long long m = (__ballot(fp < SP) >> first) & gmask;
+        // first point of the group at or above the eigenvalue (K if none)
         const int j0 = m ? __builtin_ctzll(m) : L;
-        const double nl = (j0 == 0) ? l : l + w * ((double)j0 * inv);
-        const double nh = (j0 == L) ? h : l + w * ((double)(j0 + 1) * inv);
+        const int fpj = __shfl(fp, first + (j0 < L ? j0 : 0), 64);
+        const int k0 = j0 < L ? j0 * SP + fpj : K;
+        const double nl = (k0 == 0) ? l : l + w * ((double)k0 * inv);
+        const double nh = (k0 == K) ? h : l + w * ((double)(k0 + 1) * inv);
         if (nl == l && nh == h) break;
         l = nl;
         h = nh;
@@ -714,28 +739,23 @@ __device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, i
       double xn = 0;
       for (int i = 2 + tid; i <= m; i += NT) xn += cabs2(xk[i]);
       xn = block_sum(xn, S.red, par);
-      if (tid == 0) {
-        const cpx<double> alpha = xk[1];
-        if (xn == 0.0 && alpha.im == 0.0) {
-          S.tau[k] = mk(0.0, 0.0);
-          S.e[k] = alpha.re;
-          S.flag[0] = 0;
-        } else {
-          const double nrm = sqrt(cabs2(alpha) + xn);
-          const double beta = alpha.re >= 0 ? -nrm : nrm;
-          S.tau[k] = mk((beta - alpha.re) / beta, -alpha.im / beta);
-          const cpx<double> den = mk(alpha.re - beta, alpha.im);  // scal = 1 / (alpha - beta)
-          const double dd = cabs2(den);
-          S.scal[0] = den.re / dd;
-          S.scal[1] = -den.im / dd;
-          S.e[k] = beta;
-          S.flag[0] = 1;
-        }
+      // every thread forms the reflector from the same values (no extra
+      // phase for one thread to publish it)
+      const cpx<double> alpha = xk[1];
+      const bool act = !(xn == 0.0 && alpha.im == 0.0);
+      cpx<double> tau = mk(0.0, 0.0), sc = mk(0.0, 0.0);
+      if (act) {
+        const double nrm = sqrt(cabs2(alpha) + xn);
+        const double beta = alpha.re >= 0 ? -nrm : nrm;
+        tau = mk((beta - alpha.re) / beta, -alpha.im / beta);
+        const cpx<double> den = mk(alpha.re - beta, alpha.im);  // sc = 1 / (alpha - beta)
+        const double dd = cabs2(den);
+        sc = mk(den.re / dd, -den.im / dd);
+        if (tid == 0) S.e[k] = beta;
+      } else if (tid == 0) {
+        S.e[k] = alpha.re;
       }
-      __syncthreads();
-      const bool act = S.flag[0] != 0;
-      const cpx<double> tau = S.tau[k];
-      const cpx<double> sc = mk(S.scal[0], S.scal[1]);
+      if (tid == 0) S.tau[k] = tau;
       for (int i = tid; i < m; i += NT) {
         const cpx<double> v = !act ? mk(0.0, 0.0) : (i == 0) ? mk(1.0, 0.0) : xk[1 + i] * sc;
         S.v[i] = v;
@@ -748,8 +768,10 @@ __device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, i
         __syncthreads();
         continue;
       }
-      fused_pass(A, n, c0, k, false, true, S);  // S.pp = A22 v (stored block)
       // y1 = W^H v, y2 = V^H v over rows c0..n-1, one wave per dot product
+      // (in the phase of the matrix-vector pass, which ends with a barrier;
+      // y12 lives in S.vp, which the pass does not touch without a pending
+      // update)
       for (int d = wave; d < 2 * j; d += NT / 64) {
         const bool isw = d < j;
         const int q = isw ? d : d - j;
@@ -763,7 +785,7 @@ __device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, i
         }
         if (lane == 0) y12[(d < j ? 0 : TRB) + q] = mk(yr, yi);
       }
-      __syncthreads();
+      fused_pass(A, n, c0, k, false, true, S);  // S.pp = A22 v (stored block)
       double g = 0;  // gamma = v^H p with p corrected for the panel
       for (int i = tid; i < m; i += NT) {
         cpx<double> pv = S.pp[i];
