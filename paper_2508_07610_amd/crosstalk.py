@@ -86,7 +86,8 @@ def run(n: int = 24, depth: int = 12, chi_max: int = 128, kappa_max: int = 16,
         vals = st.expect_products(obs).real
         bonds, inner, disc = st.dims()
         rec = {"eps": eps, "kraus": [ch.nkraus for ch in chans], "seconds": dt, "discarded": disc,
-               "max_bond": max(bonds), "max_inner": max(inner), "trace": st.trace(), "obs": vals}
+               "max_bond": max(bonds), "max_inner": max(inner), "trace": st.trace(), "obs": vals,
+               "min_gap": st.stats()["min_gap"]}
         if dense:
             rho = st.to_dense()
             rec["rho"] = rho / np.trace(rho).real

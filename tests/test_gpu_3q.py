@@ -115,11 +115,11 @@ def test_batch_run_with_crosstalk(prec):
 def test_crosstalk_workload_at_full_bond_and_inner_limits(eps):
     """The crosstalk workload at chi=128, kappa=16 (n=24): both precisions give
     a normalised state (trace 1) and agree on every <Z_i>, <Z_i Z_i+1> to the
-    tolerance of the mixed path; bonds and inner indices respect their limits
-    (no oracle at this size: the properties hold at any size).  The mixed
-    path accumulates its FP32 contraction rounding (about 6e-8 sqrt(K) per
-    product, K up to a few thousand) over the ~150 updates of this circuit:
-    its deviation from FP64 measures about 1e-5 here, so the bound is 2e-5."""
+    tolerance of the mixed path, 1e-5, or 10 eps / g when that is larger (g
+    the smallest relative gap at a cut of the complex128 run, eps = 6e-8 the
+    FP32 contraction rounding: a cut that close to a multiplet moves the kept
+    subspace by about eps / g); bonds and inner indices respect their limits
+    (no oracle at this size: the properties hold at any size)."""
     require_gpu()
     from paper_2508_07610_amd import crosstalk as X
     n, depth = 24, 4
@@ -128,7 +128,10 @@ def test_crosstalk_workload_at_full_bond_and_inner_limits(eps):
     assert abs(r128["trace"] - 1) < 1e-10
     assert abs(r64["trace"] - 1) < 1e-4
     assert r128["max_bond"] <= 128 and r128["max_inner"] <= 16
-    assert float(np.abs(r64["obs"] - r128["obs"]).max()) < 2e-5
+    dev = float(np.abs(r64["obs"] - r128["obs"]).max())
+    bound = max(1e-5, 10 * 6e-8 / r128["min_gap"])
+    print(f"eps {eps}: max |c64 - c128| = {dev:.2e}, smallest gap {r128['min_gap']:.2e}, bound {bound:.2e}")
+    assert dev < bound
     assert float(np.abs(r128["obs"]).max()) <= 1 + 1e-12
     assert r128["max_bond"] > 32
 
