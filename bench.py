@@ -327,7 +327,7 @@ def roofline(M, prec_c128, steps):
 
 def ttf_leg(steps, nsamples=65536, pretrain_steps=6000, seeds=(0, 1, 2)):
     """Time to fidelity of the variational GHZ loop (C5: n=12, depth 6,
-    chi=32, kappa=4, c128 judge).  The surrogate is trained first on
+    chi=32, kappa=4, complex128 MPDO as the verifier).  The surrogate is trained first on
     `nsamples` MPDO-generated samples (theta ~ U[0, 2 pi)^144, noise strengths
     ~ U[0.5, 2]^24, complex64 contractions), then plain parameter-shift Adam
     and the surrogate-assisted loop start from the same random angles; the
@@ -378,7 +378,7 @@ def ttf_leg(steps, nsamples=65536, pretrain_steps=6000, seeds=(0, 1, 2)):
     rp = float(np.mean([r["plain_mpdo_rows"] for r in ok])) if ok else None
     rsur = float(np.mean([r["surrogate_mpdo_rows"] for r in ok])) if ok else None
     overhead = t_gen + pre["train_seconds"]
-    return {"workload": "variational GHZ fidelity, noisy RY/CZ ansatz n=12 depth=6 chi=32 kappa=4, c128 MPDO judge, "
+    return {"workload": "variational GHZ fidelity, noisy RY/CZ ansatz n=12 depth=6 chi=32 kappa=4, c128 MPDO verifier, "
                         "parameter-shift gradients (289 rows per step in one mpdo_batch_run); surrogate 168-256-256-"
                         "256-12 GELU, bf16 operands, FP32 accumulation, trained by the library's kernels",
             "f_best_plain": ref["best"], "target": target, "runs": runs,

@@ -1,4 +1,4 @@
-"""Variational GHZ preparation with the MPDO as the judge, and its
+"""Variational GHZ preparation with the MPDO as the verifier, and its
 surrogate-assisted form.
 
 The objective is the GHZ fidelity of the noisy RY/CZ ansatz (2 n depth RY
@@ -240,7 +240,7 @@ def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: flo
                        lr: float = 0.05, fit_steps: int = 150, fit_lr: float = 1e-3, window: int = 4,
                        inner: int = 60, inner_lr: float = 0.02, cand_at=(5, 10, 20, 30, 45, 60),
                        out_scale: float = 10.0, time_limit: float = 600.0) -> dict:
-    """Surrogate-assisted ascent: the network proposes steps, the MPDO judges.
+    """Surrogate-assisted ascent: the network proposes steps, the MPDO verifies them.
 
     Every parameter-shift evaluation (2P + 1 rows: the exact gradient, which
     also labels data around the iterate) is added to a buffer.  The network is
