@@ -112,7 +112,30 @@ __device__ void sturm_counts(const double* d, const double* e2, int n, const dou
     if (fabs(q[p]) < pivmin) q[p] = -pivmin;
     cnt[p] = q[p] < 0;
   }
-  for (int i = 1; i < n; ++i) {
+  // the entries of T are read eight steps at a time, ahead of the dependent
+  // chain (the chain itself is unchanged)
+  constexpr int SB = 8;
+  int i = 1;
+  for (; i + SB <= n; i += SB) {
+    double dd[SB], ee[SB];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      dd[u] = d[i + u];
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < SB; ++u)
+#pragma unroll
+      for (int p = 0; p < SP; ++p) {
+        double r = __builtin_amdgcn_rcp(q[p]);
+        r = r * (2.0 - q[p] * r);
+        r = r * (2.0 - q[p] * r);
+        q[p] = (dd[u] - x[p]) - ee[u] * r;
+        if (fabs(q[p]) < pivmin) q[p] = -pivmin;
+        cnt[p] += q[p] < 0;
+      }
+  }
+  for (; i < n; ++i) {
     const double di = d[i], ei = e2[i - 1];
 #pragma unroll
     for (int p = 0; p < SP; ++p) {
@@ -403,24 +426,60 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
         }
         scale = mx > 0 ? 1.0 / mx : 1.0;
       }
+      // norm, store and residual read X in blocks of UB loads issued ahead
+      // (the arithmetic and its order are those of one element at a time)
       double nn = 0;
-      for (int i = 0; i < n; ++i) {
-        const double x = X[(long long)i * ks + j] * scale;
-        nn += x * x;
+      {
+        int i = 0;
+        for (; i + UB <= n; i += UB) {
+          double xv[UB];
+#pragma unroll
+          for (int u = 0; u < UB; ++u) xv[u] = X[(long long)(i + u) * ks + j];
+#pragma unroll
+          for (int u = 0; u < UB; ++u) {
+            const double x = xv[u] * scale;
+            nn += x * x;
+          }
+        }
+        for (; i < n; ++i) {
+          const double x = X[(long long)i * ks + j] * scale;
+          nn += x * x;
+        }
       }
       const double s = scale / sqrt(nn);
-      for (int i = 0; i < n; ++i) Z[(long long)i * n + j] = mk(X[(long long)i * ks + j] * s, 0.0);
-      // residual of the tridiagonal eigenpair: ||(T - lambda) z|| <= rtol ||T||
-      // (inverse iteration from a bisected eigenvalue reaches about eps ||T||)
-      double rr = 0, zp = 0, zc = Z[j].re;
-      for (int i = 0; i < n; ++i) {
-        const double zn = i + 1 < n ? Z[(long long)(i + 1) * n + j].re : 0.0;
-        double t = (S.d[i] - lam) * zc;
-        if (i > 0) t += S.e[i - 1] * zp;
-        if (i + 1 < n) t += S.e[i] * zn;
-        rr += t * t;
-        zp = zc;
-        zc = zn;
+      // z = X s to Z, and the residual of the tridiagonal eigenpair
+      // ||(T - lambda) z|| <= rtol ||T|| (inverse iteration from a bisected
+      // eigenvalue reaches about eps ||T||) from the same values
+      double rr = 0, zp = 0, zc = X[j] * s;
+      {
+        int i = 0;
+        for (; i + UB < n; i += UB) {
+          double zb[UB + 1];
+#pragma unroll
+          for (int u = 1; u <= UB; ++u) zb[u] = X[(long long)(i + u) * ks + j] * s;
+          zb[0] = zc;
+#pragma unroll
+          for (int u = 0; u < UB; ++u) {
+            Z[(long long)(i + u) * n + j] = mk(zb[u], 0.0);
+            const double zn = zb[u + 1];
+            double t = (S.d[i + u] - lam) * zb[u];
+            if (i + u > 0) t += S.e[i + u - 1] * zp;
+            t += S.e[i + u] * zn;
+            rr += t * t;
+            zp = zb[u];
+          }
+          zc = zb[UB];
+        }
+        for (; i < n; ++i) {
+          Z[(long long)i * n + j] = mk(zc, 0.0);
+          const double zn = i + 1 < n ? X[(long long)(i + 1) * ks + j] * s : 0.0;
+          double t = (S.d[i] - lam) * zc;
+          if (i > 0) t += S.e[i - 1] * zp;
+          if (i + 1 < n) t += S.e[i] * zn;
+          rr += t * t;
+          zp = zc;
+          zc = zn;
+        }
       }
       if (!(sqrt(rr) <= rtol * tnorm)) s_resbad = 1;
     }
