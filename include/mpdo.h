@@ -450,6 +450,28 @@ mpdo_status mpdo_mlp_backward(mpdo_mlp_t h, const float* x_dev, const float* t_d
                               int32_t batch, float* y_dev, float* grad_dev, float* dx_dev, float* loss);
 /* One Adam step (bias-corrected) with the gradients of the last backward. */
 mpdo_status mpdo_mlp_adam(mpdo_mlp_t h, float lr, float beta1, float beta2, float eps);
+/* `steps` training steps in one call (no host synchronisation unless loss
+ * is non-NULL): each draws `batch` rows (in [1, max_batch]) uniformly with
+ * replacement from the nrows-row dataset x_dev (nrows x d_0) / t_dev
+ * (nrows x d_L), takes the MSE gradient as mpdo_mlp_backward and one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8; the step count continues that of
+ * mpdo_mlp_adam).  Row b of step s (from 0) is dataset row
+ * SplitMix64(seed)_k mod nrows with k = s batch + b + 1, where the k-th
+ * output of SplitMix64 seeded with `seed` is its finalizer applied to
+ * seed + k 0x9E3779B97F4A7C15.  Learning rate lr, or with cosine != 0
+ * lr (1 + cos(pi s / steps)) / 2.  *loss (if non-NULL) receives the last
+ * step's MSE and makes the call synchronous. */
+mpdo_status mpdo_mlp_fit(mpdo_mlp_t h, const float* x_dev, const float* t_dev, int64_t nrows, int32_t batch,
+                         int32_t steps, float lr, int32_t cosine, uint64_t seed, float* loss);
+/* Gradient ascent on the network's input: from the input row x0_dev (d_0
+ * floats, device), `steps` Adam steps (bias-corrected) on the first nfree
+ * entries (the rest are held) along the gradient of output out_index,
+ * x += lr mhat / (sqrt(vhat) + eps); the row after step s goes to
+ * xs_dev + s d_0 (steps x d_0 floats, device).  The Adam moments and step
+ * count are kept in the handle between calls; reset != 0 zeroes them first.
+ * Parameter gradients are not touched. */
+mpdo_status mpdo_mlp_ascend(mpdo_mlp_t h, const float* x0_dev, int32_t nfree, int32_t out_index, int32_t steps,
+                            float lr, float beta1, float beta2, float eps, int32_t reset, float* xs_dev);
 
 #ifdef __cplusplus
 }

@@ -1,5 +1,6 @@
 // Surrogate multilayer perceptron: forward, backward and Adam on the gfx950
-// matrix cores in bfloat16 with FP32 accumulation.
+// matrix cores in bfloat16 with FP32 accumulation, and two loops that run
+// entirely in the library (minibatch training, input-gradient ascent).
 //
 // Network (widths d_0 .. d_L): z_l = W_l h_{l-1} + b_l, h_l = GELU(z_l) for
 // hidden layers (exact erf form), y = z_L; loss = mean (y - t)^2.  Operands
@@ -9,7 +10,9 @@
 // weights.  Matrix products use v_mfma_f32_16x16x16_bf16: 64 x 64 tiles per
 // workgroup of four waves, each wave a 32 x 32 quadrant of 2 x 2 MFMA blocks,
 // operand tiles staged in LDS with the K index contiguous, and the bias /
-// activation / rounding epilogues fused into the product kernel.
+// activation / rounding epilogues fused into the product kernel.  The
+// weight gradients (K = batch rows, few output tiles) are split over K into
+// partial sums, which also carry the bias gradients; one pass adds them up.
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -53,6 +56,14 @@ struct MlpGemm {
   uint16_t* Hb;
   const float* bias;
   const float* aux;
+  // split over K (grid dimension y): split s covers k in [s kper, (s + 1) kper)
+  // and writes C + s sC; kper = K without a split
+  int kper;
+  long long sC;
+  // optional (transA only): colout[s sC + i] = sum over the split's k of
+  // colsrc[k ldcol + i] (FP32), from the workgroups of the first column tile
+  const float* colsrc;
+  float* colout;
 };
 
 // C[M x N] = op(A)[M x K] op(B)[K x N]: op(A)[i][k] = transA ? A[k lda + i] : A[i lda + k],
@@ -61,16 +72,21 @@ template <int EPI>
 __global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[MT][KP];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[MT][KP];  // [n][k]
+  __shared__ float red[MTH / MT][MT];
   const int tilesN = (g.N + MT - 1) / MT;
   const int m0 = (blockIdx.x / tilesN) * MT, n0 = (blockIdx.x % tilesN) * MT;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1, li = lane & 15, lg = lane >> 4;
+  const int kb = blockIdx.y * g.kper, ke = min(g.K, kb + g.kper);
+  // with transA each thread stages one row m0 + tid % MT of op(A) (MT divides MTH)
+  const bool colsum = g.colsrc != nullptr && (blockIdx.x % tilesN) == 0;
+  float csum = 0.0f;
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < g.K; k0 += KT) {
+  for (int k0 = kb; k0 < ke; k0 += KT) {
 #pragma unroll
     for (int it = 0; it < (MT * KT) / MTH; ++it) {
       const int idx = tid + it * MTH;
@@ -79,7 +95,10 @@ __global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
       else { kk = idx % KT; mm = idx / KT; }
       const int m = m0 + mm, k = k0 + kk;
       uint16_t v = 0;
-      if (m < g.M && k < g.K) v = g.transA ? g.A[(long long)k * g.lda + m] : g.A[(long long)m * g.lda + k];
+      if (m < g.M && k < ke) {
+        v = g.transA ? g.A[(long long)k * g.lda + m] : g.A[(long long)m * g.lda + k];
+        if (colsum) csum += g.colsrc[(long long)k * g.lda + m];
+      }
       As[mm][kk] = v;
     }
 #pragma unroll
@@ -90,7 +109,7 @@ __global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
       else { nn = idx % MT; kk = idx / MT; }
       const int n = n0 + nn, k = k0 + kk;
       uint16_t v = 0;
-      if (n < g.N && k < g.K) v = g.transB ? g.B[(long long)n * g.ldb + k] : g.B[(long long)k * g.ldb + n];
+      if (n < g.N && k < ke) v = g.transB ? g.B[(long long)n * g.ldb + k] : g.B[(long long)k * g.ldb + n];
       Bs[nn][kk] = v;
     }
     __syncthreads();
@@ -105,6 +124,17 @@ __global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
       for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
+  if (colsum) {  // uniform per workgroup
+    red[tid / MT][tid % MT] = csum;
+    __syncthreads();
+    if (tid < MT && m0 + tid < g.M) {
+      float t = 0;
+#pragma unroll
+      for (int r = 0; r < MTH / MT; ++r) t += red[r][tid];
+      g.colout[blockIdx.y * g.sC + m0 + tid] = t;
+    }
+  }
+  float* C = g.C + blockIdx.y * g.sC;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -117,16 +147,16 @@ __global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
         const float x = acc[i][j][v];
         const long long o = (long long)row * g.ldc + col;
         if (EPI == EPI_STORE) {
-          g.C[o] = x;
+          C[o] = x;
         } else if (EPI == EPI_HIDDEN) {
           const float z = x + g.bias[col];
-          g.C[o] = z;
+          C[o] = z;
           g.Hb[o] = f2bf(gelu(z));
         } else if (EPI == EPI_OUT) {
-          g.C[o] = x + g.bias[col];
+          C[o] = x + g.bias[col];
         } else {
           const float gz = x * gelu_grad(g.aux[o]);
-          g.C[o] = gz;
+          C[o] = gz;
           g.Hb[o] = f2bf(gz);
         }
       }
@@ -167,32 +197,104 @@ __global__ void k_set_grad(const float* __restrict__ gy, long long n, float* __r
   }
 }
 
-// db[j] = sum_b g[b][j]
-__global__ void k_colsum(const float* __restrict__ g, int rows, int cols, float* __restrict__ db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
-  float s = 0;
-  for (int r = 0; r < rows; ++r) s += g[(long long)r * cols + j];
-  db[j] = s;
+// grad[i] = sum over the splits of part[s np + i]
+__global__ void k_grad_reduce(const float* __restrict__ part, long long np, int splits, float* __restrict__ grad) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np; i += (long long)gridDim.x * blockDim.x) {
+    float t = 0;
+    for (int s = 0; s < splits; ++s) t += part[s * np + i];
+    grad[i] = t;
+  }
 }
 
 // Adam on the FP32 master parameters; refreshes the bf16 weight copies.
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ grad, float* __restrict__ m,
-                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps, float c1,
-                       float c2) {
+                       float* __restrict__ v, uint16_t* __restrict__ pb, long long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const float gr = grad[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gr;
     const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
   }
 }
 
-template <int EPI> void gemm(const MlpGemm& g, hipStream_t s) {
+// SplitMix64 (Steele, Lea and Flood, 2014): the k-th output (k >= 1) of the
+// generator seeded with `seed` is the finalizer applied to seed + k * gamma.
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Minibatch of a training loop: row b of step `step` is dataset row
+// splitmix64(seed, step * batch + b + 1) mod nrows; inputs to bf16, targets
+// copied (FP32).
+__global__ void k_gather(const float* __restrict__ x, const float* __restrict__ t, long long nrows, int d0, int dL,
+                         int batch, uint64_t seed, long long step, uint16_t* __restrict__ xb,
+                         float* __restrict__ tg) {
+  const int b = blockIdx.x;
+  const long long r = (long long)(splitmix64(seed, (uint64_t)(step * batch + b + 1)) % (uint64_t)nrows);
+  for (int j = threadIdx.x; j < d0; j += blockDim.x) xb[(long long)b * d0 + j] = f2bf(x[r * d0 + j]);
+  for (int j = threadIdx.x; j < dL; j += blockDim.x) tg[(long long)b * dL + j] = t[r * dL + j];
+}
+
+// One Adam ascent step on the first nfree entries of the input row xa (the
+// rest are held): xa += lr mhat / (sqrt(vhat) + eps) with the gradient dx;
+// the row is recorded in rec and its bf16 copy refreshed for the next pass.
+__global__ void k_ascend(float* __restrict__ xa, const float* __restrict__ dx, float* __restrict__ m,
+                         float* __restrict__ v, int d0, int nfree, float lr, float b1, float b2, float eps, float c1,
+                         float c2, float* __restrict__ rec, uint16_t* __restrict__ xb) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d0; i += gridDim.x * blockDim.x) {
+    float xi = xa[i];
+    if (i < nfree) {
+      const float gr = dx[i];
+      const float mi = b1 * m[i] + (1.0f - b1) * gr;
+      const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
+      m[i] = mi;
+      v[i] = vi;
+      xi += lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+      xa[i] = xi;
+    }
+    rec[i] = xi;
+    xb[i] = f2bf(xi);
+  }
+}
+
+__global__ void k_fill(float* __restrict__ p, int n, float val) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = val;
+}
+
+// output cotangent: one-hot at column `col` for a single row
+__global__ void k_onehot(int n, int col, float* __restrict__ g, uint16_t* __restrict__ gb) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    g[i] = i == col ? 1.0f : 0.0f;
+    gb[i] = f2bf(i == col ? 1.0f : 0.0f);
+  }
+}
+
+// splits: number of K ranges (grid dimension y); g.kper and g.sC must match
+template <int EPI> void gemm(MlpGemm g, hipStream_t s, int splits = 1) {
   const int tiles = ((g.M + MT - 1) / MT) * ((g.N + MT - 1) / MT);
-  if (tiles > 0 && g.K > 0) hipLaunchKernelGGL(k_mlp_gemm<EPI>, dim3(tiles), dim3(MTH), 0, s, g);
+  if (splits <= 1) g.kper = g.K;
+  if (tiles > 0 && g.K > 0)
+    hipLaunchKernelGGL(k_mlp_gemm<EPI>, dim3(tiles, splits > 1 ? splits : 1), dim3(MTH), 0, s, g);
+}
+
+// K split of the weight-gradient products: ranges of a multiple of KT rows,
+// at most SPLIT_MAX of them, about 32 rows each
+constexpr int SPLIT_MAX = 16;
+void split_of(int batch, int* splits, int* kper) {
+  int s = batch / 32;
+  s = s < 1 ? 1 : (s > SPLIT_MAX ? SPLIT_MAX : s);
+  int k = (batch + s - 1) / s;
+  k = (k + KT - 1) / KT * KT;
+  *kper = k;
+  *splits = (batch + k - 1) / k;
 }
 
 int grid_for(long long n) {
@@ -214,18 +316,20 @@ struct mpdo_mlp_s {
   DevBuf p, g, m, v, pb;         // FP32 params / grads / Adam moments; bf16 params
   DevBuf xb;                     // input, bf16
   DevBuf z, hb, gz, gzb, dx, part;
+  DevBuf gpart;                  // split partial gradients, SPLIT_MAX x np
+  DevBuf yb, tb;                 // outputs and gathered targets of the training loop (max_batch x d_L)
+  DevBuf xa, am, av, dxa;        // ascent: input row, its Adam moments, its gradient (d_0 each)
   std::vector<long long> zoff;   // per layer offsets into z / hb / gz / gzb (max_batch x d_l)
   long long step = 0;
+  long long ascent_step = 0;     // Adam steps of the ascent since its last reset
 };
 
 namespace {
 mpdo_status mfail(int st, const std::string& msg) { return (mpdo_status)set_last_error(st, msg); }
 
-// Forward pass for `batch` rows of x (FP32, device) into y (FP32, device).
-void mlp_forward(mpdo_mlp_s* h, const float* x, int batch, float* y) {
+// Forward pass for `batch` rows of the bf16 input already in xb into y (FP32, device).
+void mlp_forward_xb(mpdo_mlp_s* h, int batch, float* y) {
   const int L = h->L;
-  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for((long long)batch * h->w[0])), dim3(256), 0, h->st, x,
-                     h->xb.as<uint16_t>(), (long long)batch * h->w[0]);
   const uint16_t* in = h->xb.as<uint16_t>();
   for (int l = 0; l < L; ++l) {
     MlpGemm g{};
@@ -246,24 +350,38 @@ void mlp_forward(mpdo_mlp_s* h, const float* x, int batch, float* y) {
   }
 }
 
+// Forward pass for `batch` rows of x (FP32, device) into y (FP32, device).
+void mlp_forward(mpdo_mlp_s* h, const float* x, int batch, float* y) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for((long long)batch * h->w[0])), dim3(256), 0, h->st, x,
+                     h->xb.as<uint16_t>(), (long long)batch * h->w[0]);
+  mlp_forward_xb(h, batch, y);
+}
+
 // Backward pass from the output cotangent already in gz/gzb of the last
-// layer: weight and bias gradients into h->g, input gradient into dx (if set).
-void mlp_backward(mpdo_mlp_s* h, int batch, float* dx) {
+// layer: with params, weight and bias gradients into h->g (split over the
+// batch into partial sums, then added up); input gradient into dx (if set).
+void mlp_backward(mpdo_mlp_s* h, int batch, float* dx, bool params = true) {
   const int L = h->L;
+  int splits = 1, kper = batch;
+  split_of(batch, &splits, &kper);
+  float* part = h->gpart.as<float>();
   for (int l = L - 1; l >= 0; --l) {
     const uint16_t* gb = h->gzb.as<uint16_t>() + h->zoff[l];
     const float* gf = h->gz.as<float>() + h->zoff[l];
     const uint16_t* hin = l == 0 ? h->xb.as<uint16_t>() : h->hb.as<uint16_t>() + h->zoff[l - 1];
-    {  // dW_l = G^T H_{l-1}: (d_l x B)(B x d_{l-1})
+    if (params) {  // dW_l = G^T H_{l-1}: (d_l x B)(B x d_{l-1}); db_l = G^T 1 alongside
       MlpGemm g{};
       g.A = gb; g.lda = h->w[l + 1]; g.transA = 1;
       g.B = hin; g.ldb = h->w[l];
       g.M = h->w[l + 1]; g.N = h->w[l]; g.K = batch;
-      g.C = h->g.as<float>() + h->woff[l]; g.ldc = h->w[l];
-      gemm<EPI_STORE>(g, h->st);
+      g.C = part + h->woff[l]; g.ldc = h->w[l];
+      g.kper = kper;
+      g.sC = h->np;
+      g.colsrc = gf;
+      g.colout = part + h->boff[l];
+      gemm<EPI_STORE>(g, h->st, splits);
     }
-    hipLaunchKernelGGL(k_colsum, dim3((h->w[l + 1] + 255) / 256), dim3(256), 0, h->st, gf, batch, h->w[l + 1],
-                       h->g.as<float>() + h->boff[l]);
+    if (l == 0 && !dx) break;
     // dA = G W_l: (B x d_l)(d_l x d_{l-1}); times GELU'(z_{l-1}) for hidden inputs
     MlpGemm g{};
     g.A = gb; g.lda = h->w[l + 1];
@@ -275,11 +393,23 @@ void mlp_backward(mpdo_mlp_s* h, int batch, float* dx) {
       g.Hb = h->gzb.as<uint16_t>() + h->zoff[l - 1];
       g.aux = h->z.as<float>() + h->zoff[l - 1];
       gemm<EPI_ACTGRAD>(g, h->st);
-    } else if (dx) {
+    } else {
       g.C = dx;
       gemm<EPI_STORE>(g, h->st);
     }
   }
+  if (params)
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid_for(h->np)), dim3(256), 0, h->st, part, h->np, splits,
+                       h->g.as<float>());
+}
+
+void adam_step(mpdo_mlp_s* h, float lr, float beta1, float beta2, float eps) {
+  h->step += 1;
+  const float c1 = 1.0f / (1.0f - std::pow(beta1, (float)h->step));
+  const float c2 = 1.0f / (1.0f - std::pow(beta2, (float)h->step));
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(h->np)), dim3(256), 0, h->st, h->p.as<float>(), h->g.as<float>(),
+                     h->m.as<float>(), h->v.as<float>(), h->pb.as<uint16_t>(), h->np, lr, beta1, beta2, eps, c1,
+                     c2);
 }
 
 void refresh_bf16(mpdo_mlp_s* h) {
@@ -342,6 +472,13 @@ mpdo_status mpdo_mlp_create(const int32_t* widths, int32_t nlayers, int32_t max_
     h->gz.alloc(zo * 4);
     h->gzb.alloc(zo * 2);
     h->part.alloc(1024 * 4);
+    h->gpart.alloc((size_t)SPLIT_MAX * off * 4);
+    h->yb.alloc((size_t)max_batch * h->w[nlayers] * 4);
+    h->tb.alloc((size_t)max_batch * h->w[nlayers] * 4);
+    h->xa.alloc((size_t)h->w[0] * 4);
+    h->am.alloc((size_t)h->w[0] * 4);
+    h->av.alloc((size_t)h->w[0] * 4);
+    h->dxa.alloc((size_t)h->w[0] * 4);
     hip_check(hipMemsetAsync(h->p.p, 0, off * 4, h->st), "memset");
     hip_check(hipMemsetAsync(h->m.p, 0, off * 4, h->st), "memset");
     hip_check(hipMemsetAsync(h->v.p, 0, off * 4, h->st), "memset");
@@ -443,13 +580,84 @@ mpdo_status mpdo_mlp_adam(mpdo_mlp_t h, float lr, float beta1, float beta2, floa
   if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
     return mfail(MPDO_EINVAL, "bad Adam hyper-parameters");
   MGUARD_BEGIN
-  h->step += 1;
-  const float c1 = 1.0f / (1.0f - std::pow(beta1, (float)h->step));
-  const float c2 = 1.0f / (1.0f - std::pow(beta2, (float)h->step));
-  hipLaunchKernelGGL(k_adam, dim3(grid_for(h->np)), dim3(256), 0, h->st, h->p.as<float>(), h->g.as<float>(),
-                     h->m.as<float>(), h->v.as<float>(), h->np, lr, beta1, beta2, eps, c1, c2);
-  refresh_bf16(h);
+  adam_step(h, lr, beta1, beta2, eps);
   hip_check(hipGetLastError(), "launch (adam)");
+  return MPDO_OK;
+  MGUARD_END
+}
+
+mpdo_status mpdo_mlp_fit(mpdo_mlp_t h, const float* x_dev, const float* t_dev, int64_t nrows, int32_t batch,
+                         int32_t steps, float lr, int32_t cosine, uint64_t seed, float* loss) {
+  if (const char* why = check_batch(h, batch)) return mfail(MPDO_EINVAL, why);
+  if (!x_dev || !t_dev) return mfail(MPDO_EINVAL, "null buffer");
+  if (nrows < 1) return mfail(MPDO_EINVAL, "nrows must be >= 1");
+  if (steps < 0) return mfail(MPDO_EINVAL, "steps must be >= 0");
+  if (!(lr >= 0)) return mfail(MPDO_EINVAL, "lr must be >= 0");
+  MGUARD_BEGIN
+  const int L = h->L, d0 = h->w[0], dL = h->w[L];
+  const long long n = (long long)batch * dL;
+  float* gl = h->gz.as<float>() + h->zoff[L - 1];
+  uint16_t* glb = h->gzb.as<uint16_t>() + h->zoff[L - 1];
+  const int blocks = grid_for(n);
+  for (int s = 0; s < steps; ++s) {
+    hipLaunchKernelGGL(k_gather, dim3(batch), dim3(64), 0, h->st, x_dev, t_dev, (long long)nrows, d0, dL, batch,
+                       seed, (long long)s, h->xb.as<uint16_t>(), h->tb.as<float>());
+    mlp_forward_xb(h, batch, h->yb.as<float>());
+    hipLaunchKernelGGL(k_out_grad, dim3(blocks), dim3(256), 0, h->st, h->yb.as<float>(), h->tb.as<float>(), n,
+                       1.0f / (float)n, gl, glb, h->part.as<float>());
+    mlp_backward(h, batch, nullptr);
+    const float lr_s = cosine ? lr * 0.5f * (1.0f + std::cos(3.14159265358979f * (float)s / (float)steps)) : lr;
+    adam_step(h, lr_s, 0.9f, 0.999f, 1e-8f);
+  }
+  hip_check(hipGetLastError(), "launch (mlp fit)");
+  if (loss) {
+    *loss = 0;
+    if (steps > 0) {
+      std::vector<float> part(blocks);
+      hip_check(hipMemcpyAsync(part.data(), h->part.p, blocks * 4, hipMemcpyDeviceToHost, h->st), "loss");
+      hip_check(hipStreamSynchronize(h->st), "sync");
+      double t = 0;
+      for (float x : part) t += x;
+      *loss = (float)(t / (double)n);
+    }
+  }
+  return MPDO_OK;
+  MGUARD_END
+}
+
+mpdo_status mpdo_mlp_ascend(mpdo_mlp_t h, const float* x0_dev, int32_t nfree, int32_t out_index, int32_t steps,
+                            float lr, float beta1, float beta2, float eps, int32_t reset, float* xs_dev) {
+  if (!h) return mfail(MPDO_EINVAL, "null network");
+  if (!x0_dev || (steps > 0 && !xs_dev)) return mfail(MPDO_EINVAL, "null buffer");
+  const int L = h->L, d0 = h->w[0];
+  if (nfree < 0 || nfree > d0) return mfail(MPDO_EINVAL, "nfree must be in [0, d_0]");
+  if (out_index < 0 || out_index >= h->w[L]) return mfail(MPDO_EINVAL, "out_index must be in [0, d_L)");
+  if (steps < 0) return mfail(MPDO_EINVAL, "steps must be >= 0");
+  if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return mfail(MPDO_EINVAL, "bad Adam hyper-parameters");
+  MGUARD_BEGIN
+  if (reset) {
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, h->st, h->am.as<float>(), d0, 0.0f);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, h->st, h->av.as<float>(), d0, 0.0f);
+    h->ascent_step = 0;
+  }
+  hip_check(hipMemcpyAsync(h->xa.p, x0_dev, (size_t)d0 * 4, hipMemcpyDeviceToDevice, h->st), "ascent input");
+  hipLaunchKernelGGL(k_to_bf16, dim3(1), dim3(256), 0, h->st, h->xa.as<float>(), h->xb.as<uint16_t>(),
+                     (long long)d0);
+  // the forward pass does not touch the output cotangent, so it is set once
+  hipLaunchKernelGGL(k_onehot, dim3(1), dim3(256), 0, h->st, h->w[L], out_index,
+                     h->gz.as<float>() + h->zoff[L - 1], h->gzb.as<uint16_t>() + h->zoff[L - 1]);
+  for (int s = 0; s < steps; ++s) {
+    mlp_forward_xb(h, 1, h->yb.as<float>());
+    mlp_backward(h, 1, h->dxa.as<float>(), false);
+    h->ascent_step += 1;
+    const float c1 = 1.0f / (1.0f - std::pow(beta1, (float)h->ascent_step));
+    const float c2 = 1.0f / (1.0f - std::pow(beta2, (float)h->ascent_step));
+    hipLaunchKernelGGL(k_ascend, dim3(1), dim3(256), 0, h->st, h->xa.as<float>(), h->dxa.as<float>(),
+                       h->am.as<float>(), h->av.as<float>(), d0, nfree, lr, beta1, beta2, eps, c1, c2,
+                       xs_dev + (long long)s * d0, h->xb.as<uint16_t>());
+  }
+  hip_check(hipGetLastError(), "launch (mlp ascend)");
   return MPDO_OK;
   MGUARD_END
 }

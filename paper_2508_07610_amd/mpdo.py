@@ -165,6 +165,10 @@ def lib() -> ctypes.CDLL:
         "mpdo_mlp_forward": [vp, vp, i32, vp],
         "mpdo_mlp_backward": [vp, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_float)],
         "mpdo_mlp_adam": [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
+        "mpdo_mlp_fit": [vp, vp, vp, ctypes.c_int64, i32, i32, ctypes.c_float, i32, ctypes.c_uint64,
+                         ctypes.POINTER(ctypes.c_float)],
+        "mpdo_mlp_ascend": [vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            i32, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -99,3 +99,29 @@ class MLP:
         _, _, _, loss = self.backward(x, t=t, want_loss=want_loss)
         self.adam(lr)
         return loss
+
+    def fit(self, x, t, steps: int, batch: int, lr: float, cosine: bool = False, seed: int = 0,
+            want_loss: bool = False):
+        """`steps` Adam steps on minibatches of `batch` rows drawn on the
+        device (SplitMix64 from `seed`) from the dataset (x, t), in one call;
+        returns the last step's loss if want_loss."""
+        torch = self._torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape[1] == self.widths[0]
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape == (x.shape[0], self.widths[-1])
+        loss = ctypes.c_float()
+        M.check(M.lib().mpdo_mlp_fit(self._h, x.data_ptr(), t.data_ptr(), x.shape[0], int(batch), int(steps),
+                                     float(lr), 1 if cosine else 0, int(seed) & ((1 << 64) - 1),
+                                     ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def ascend(self, x0, nfree: int, steps: int, lr: float, out_index: int = 0, beta1: float = 0.9,
+               beta2: float = 0.999, eps: float = 1e-8, reset: bool = True):
+        """Adam ascent of output `out_index` over the first `nfree` inputs
+        from the row x0 (d_0 floats on the device); returns the (steps, d_0)
+        rows after each step.  The moments persist between calls unless reset."""
+        torch = self._torch
+        assert x0.is_cuda and x0.dtype == torch.float32 and x0.is_contiguous() and x0.numel() == self.widths[0]
+        xs = torch.empty((max(int(steps), 1), self.widths[0]), dtype=torch.float32, device=x0.device)
+        M.check(M.lib().mpdo_mlp_ascend(self._h, x0.data_ptr(), int(nfree), int(out_index), int(steps), float(lr),
+                                        float(beta1), float(beta2), float(eps), 1 if reset else 0, xs.data_ptr()))
+        return xs[: int(steps)]

@@ -255,8 +255,11 @@ def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: flo
     parameter-shift evaluation.  The network is refit only after a gradient
     evaluation; a proposal round that continues from an accepted point of the
     network keeps ascending in the same coordinates.  Every accepted point is
-    an MPDO value; the plain step is the fallback.  Returns the record of plain_optimize plus
-    the surrogate's proposal statistics and its error on verified points."""
+    an MPDO value; the plain step is the fallback.  The refit (``MLP.fit``)
+    and the ascent (``MLP.ascend``, on the network input u = offset / pi with
+    lr / pi and eps pi: the same Adam path as in the offsets) each run as one
+    library call.  Returns the record of plain_optimize plus the surrogate's
+    proposal statistics and its error on verified points."""
     import torch
     P = ev.P
     nn_ = n_noise(ev.n)
@@ -273,8 +276,6 @@ def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: flo
     need_grad = True
     Fc = -1.0
     plain_next = theta
-    gy = torch.zeros((1, net.widths[-1]), dtype=torch.float32, device="cuda")
-    gy[0, 0] = 1.0
     nz_t = torch.tensor(noise.astype(np.float32), device="cuda")
     rows_per_grad = 2 * P + 1
     e0 = ev.evaluations
@@ -299,28 +300,14 @@ def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: flo
             yt[:, 0] = (Yr - Fref) * out_scale
             yd = torch.tensor(yt, device="cuda")
             nb = min(net.max_batch, len(Xr), 512)
-            for _ in range(fit_steps):
-                idx = torch.randint(0, xd.shape[0], (nb,), device="cuda")
-                net.train_step(xd[idx].contiguous(), yd[idx].contiguous(), fit_lr, want_loss=False)
-            x = torch.zeros((1, P), dtype=torch.float32, device="cuda")
-            m = torch.zeros_like(x)
-            v = torch.zeros_like(x)
-            t_in = 0
+            net.fit(xd, yd, fit_steps, nb, fit_lr, seed=7919 * counts["gradients"] + 17)
+            x0 = torch.cat([torch.zeros((1, P), dtype=torch.float32, device="cuda"), nz_t], dim=1).view(-1)
+            reset = True
         # ascend the network on the device from the last accepted point
-        cands = []
-        for t in range(t_in + 1, t_in + inner + 1):
-            xin = torch.cat([x / math.pi, nz_t], dim=1).contiguous()
-            _, _, dx, _ = net.backward(xin, gy=gy, want_dx=True, want_loss=False)
-            gr = dx[:, :P] / math.pi
-            m.mul_(0.9).add_(0.1 * gr)
-            v.mul_(0.999).add_(0.001 * gr * gr)
-            x = x + inner_lr * (m / (1 - 0.9 ** t)) / (torch.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
-            if t - t_in in cand_at:
-                cands.append(x.clone())
-        t_in += inner
-        xs = torch.cat(cands).double().cpu().numpy()
-        pred = net.forward(torch.cat([torch.cat(cands) / math.pi, nz_t.repeat(len(cands), 1)],
-                                     dim=1).contiguous()).cpu().numpy()[:, 0] / out_scale + Fref
+        rows_all = net.ascend(x0.contiguous(), P, inner, inner_lr / math.pi, eps=1e-8 * math.pi, reset=reset)
+        cands = rows_all[[t - 1 for t in cand_at if t <= inner]].contiguous()
+        xs = cands[:, :P].double().cpu().numpy() * math.pi
+        pred = net.forward(cands).cpu().numpy()[:, 0] / out_scale + Fref
         C = center[None, :] + xs
         if need_grad:
             C = np.concatenate([C, plain_next[None, :]])
@@ -337,7 +324,8 @@ def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: flo
             if b < len(cands):
                 counts["surrogate_accepted"] += 1
                 need_grad = False
-                x = cands[b].clone()   # continue from the accepted point
+                x0 = cands[b].clone()   # continue from the accepted point (same moments)
+                reset = False
             else:
                 counts["plain_accepted"] += 1
                 need_grad = True

@@ -104,6 +104,15 @@ def test_mpo_calls_reject_null_handles():
     assert L.mpdo_mpo_destroy(None) == M.OK
 
 
+def test_mlp_loops_reject_null_handles():
+    """The training and ascent loops check the handle before any device work."""
+    L = M.lib()
+    loss = ctypes.c_float()
+    assert L.mpdo_mlp_fit(None, None, None, 10, 4, 1, 1e-3, 0, 1, ctypes.byref(loss)) == M.EINVAL
+    assert L.mpdo_mlp_ascend(None, None, 1, 0, 1, 1e-2, 0.9, 0.999, 1e-8, 1, None) == M.EINVAL
+    assert L.mpdo_mlp_adam(None, 1e-3, 0.9, 0.999, 1e-8) == M.EINVAL
+
+
 def test_test_entry_points_validate_sizes():
     L = M.lib()
     a = np.zeros(8)
