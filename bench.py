@@ -325,7 +325,7 @@ def roofline(M, prec_c128, steps):
     return out, share
 
 
-def ttf_leg(steps, nsamples=65536, pretrain_steps=6000, seeds=(0, 1, 2)):
+def ttf_leg(steps, nsamples=65536, pretrain_steps=6000, seeds=tuple(range(8))):
     """Time to fidelity of the variational GHZ loop (C5: n=12, depth 6,
     chi=32, kappa=4, complex128 MPDO as the verifier).  The surrogate is trained first on
     `nsamples` MPDO-generated samples (theta ~ U[0, 2 pi)^144, noise strengths

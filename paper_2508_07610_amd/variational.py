@@ -238,7 +238,7 @@ def pretrain(net, X: np.ndarray, Y: np.ndarray, steps: int, batch: int = 512, lr
 
 def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: float, max_rows: int = 20000,
                        lr: float = 0.05, fit_steps: int = 150, fit_lr: float = 1e-3, window: int = 4,
-                       inner: int = 60, inner_lr: float = 0.02, cand_at=(5, 10, 20, 30, 45, 60),
+                       inner: int = 30, inner_lr: float = 0.04, cand_at=(3, 6, 10, 15, 22, 30),
                        out_scale: float = 10.0, time_limit: float = 600.0) -> dict:
     """Surrogate-assisted ascent: the network proposes steps, the MPDO verifies them.
 
