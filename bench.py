@@ -560,7 +560,13 @@ def crosstalk_leg():
     M.profile_enable(False)
     small = X.run(n=8, depth=12, chi_max=64, kappa_max=16, eps_list=(0.0, 1e-4, 1e-3), dense=True)
     nb = 8
-    bat = X.run_batch(nb=nb, n=24, depth=12, chi_max=128, kappa_max=16, eps=1e-4)
+    # the GEMM sites' settings tuned on this batch (autotune.tune, cached), if
+    # the cache holds them; the previous settings are restored afterwards
+    from paper_2508_07610_amd import autotune as AT
+    key = AT.cache_key(M.C64_MIXED, 128, 16, 16, f"crosstalk n=24 depth=12 nb={nb} eps=1e-4")
+    tuned = AT.load(os.path.join(ROOT, "paper_2508_07610_amd", "autotune_cache.json"), key)
+    with AT.applied(tuned):
+        bat = X.run_batch(nb=nb, n=24, depth=12, chi_max=128, kappa_max=16, eps=1e-4)
     b32 = bat["profile"][M.PROF_NAMES[M.PROF_GEMM_F32]]
     tb32 = b32["flops"] / (b32["ms"] * 1e-3) / 1e12 if b32["ms"] > 0 else 0.0
     g32 = prof[M.PROF_NAMES[M.PROF_GEMM_F32]]
@@ -580,6 +586,7 @@ def crosstalk_leg():
                                           "over HIP-event time per launch (per-gate calls: one item per launch)"},
             "batched": {"workload": f"{nb} seeded instances of the same construction (own 3-site channels each), "
                                     "eps=1e-4, one mpdo_batch_run (launch by launch, after one sizing run)",
+                        "autotune": {"cache_key": key, "settings": tuned},
                         "seconds": bat["seconds"], "seconds_per_instance": bat["seconds"] / nb,
                         "kernel_time_ms": {k: {"ms": v["ms"], "launches": v["launches"],
                                                "tflops": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0}

@@ -75,6 +75,35 @@ def reset() -> None:
         M.tune_set(i, 0, 0, 0.0)
 
 
+def snapshot() -> list:
+    """The current settings of every call site (sites 1.., for restore)."""
+    return [M.tune_get(i) for i in range(1, len(M.GEMM_SITES))]
+
+
+def restore(snap: list) -> None:
+    for i, (tile, form, split) in enumerate(snap, start=1):
+        M.tune_set(i, tile, form, split)
+
+
+class applied:
+    """Context manager: the given settings (or the built-in choices for
+    None) while the block runs, the previous ones afterwards."""
+
+    def __init__(self, settings: Optional[dict]):
+        self.settings = settings
+
+    def __enter__(self):
+        self.snap = snapshot()
+        reset()
+        if self.settings:
+            apply(self.settings)
+        return self
+
+    def __exit__(self, *exc):
+        restore(self.snap)
+        return False
+
+
 def device_name() -> str:
     import torch
     return torch.cuda.get_device_name(0)
