@@ -977,7 +977,7 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
   launch_q3_prepare<T>(dctx, n, spN, spE, st_);
   launch_q3_perm_in<T>(dctx, n, st_);
   launch_gemm_site<T, double, double>(GS_Q3_GRAM_NE, dG + gN * n, 2 * n, 1, std::max(spN, spE),
-                          [&](int tl) { return gemm_tiles_herm(n2, tl); }, st_, 64);
+                          [&](int tl) { return gemm_tiles_herm(n2, tl); }, st_, 64, 2);
   launch_reduce_splits(dG + gN * n, douts, 2 * n, n2 * n2, st_);
   launch_eigh(dE + eN * n, 2 * n, n2, status, st_);
   launch_q3_sel_env<T>(dctx, n, spH, Q3_BASIS_FLOOR, st_);
@@ -1003,7 +1003,7 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
   launch_gemm_site<double, double, T>(GS_Q3_Y1, dG + gY1 * n, n, 1, 1,
                           [&](int tl) { return gemm_tiles(n2, n2, tl); }, st_, 64);
   launch_gemm_site<T, T, T>(GS_Q3_W1, dG + gW1 * n, 2 * n, 1, 1,
-                          [&](int tl) { return std::max(gemm_tiles(cx, 4 * kx * n2, tl), gemm_tiles(cx * kx, n2, tl)); }, st_, 64);
+                          [&](int tl) { return std::max(gemm_tiles(cx, 4 * kx * n2, tl), gemm_tiles(cx * kx, n2, tl)); }, st_, 64, 2);
   launch_q3_perm_out<T>(dctx, n, st_);
   // bond i+1
   launch_gemm_site<T, double, double>(GS_Q3_GRAM_C2, dG + gC2 * n, n, 1, spC2,
@@ -1014,7 +1014,7 @@ template <typename T> void Engine<T>::run_3q(const std::vector<const GateOp*>& o
   launch_gemm_site<double, double, T>(GS_Q3_Y3, dG + gY3 * n, n, 1, 1,
                           [&](int tl) { return gemm_tiles(n2, n2, tl); }, st_, 64);
   launch_gemm_site<T, T, T>(GS_Q3_OUT, dG + gBk * n, 2 * n, 1, 1,
-                          [&](int tl) { return std::max(gemm_tiles(n2, kx * cx, tl), gemm_tiles(2 * kx * cx, cx, tl)); }, st_, 64);
+                          [&](int tl) { return std::max(gemm_tiles(n2, kx * cx, tl), gemm_tiles(2 * kx * cx, cx, tl)); }, st_, 64, 2);
   launch_q3_finish<T>(dctx, n, st_);
   hip_check(hipGetLastError(), "launch (3-site sublayer)");
   for (auto* g : ops)

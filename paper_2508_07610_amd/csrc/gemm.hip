@@ -116,7 +116,8 @@ template <typename Tin, typename Tc, typename Tout, int TM, int TN, bool G3>
 __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(
     (G3 && sizeof(Tc) == 8) ? (TM == 64 ? 3 : 7) : (TM == 32 ? 8 : 4),
     (G3 && sizeof(Tc) == 8) ? (TM == 64 ? 3 : 7) : (TM == 32 ? 8 : 4))))
-void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int maxTiles, long long nblocks) {
+void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int maxTiles, long long nblocks,
+            int nitems, int groups) {
   typedef typename Mfma<Tc>::v4 v4;
   constexpr int FM = TM / 32, FN = TN / 32;  // 16 x 16 blocks per wave and dimension
   __shared__ Tc As_re[BK][TM + PAD], As_im[BK][TM + PAD];
@@ -139,7 +140,12 @@ void k_gemm(const GemmDesc* __restrict__ descs, int maxBatch, int maxSplits, int
   const int split = (int)(bid % maxSplits);
   bid /= maxSplits;
   const int batch = (int)(bid % maxBatch);
-  const int item = (int)(bid / maxBatch);
+  int item = (int)(bid / maxBatch);
+  // A launch of `groups` descriptor groups of nitems / groups items each
+  // (different products, e.g. the two outputs of a split) visits them
+  // interleaved, so that every XCD's contiguous range holds items of each
+  // group rather than one group's items only.
+  if (groups > 1) item = (item % groups) * (nitems / groups) + item / groups;
   const GemmDesc& d = descs[item];
   if (!d.active || batch >= d.nbatch || split >= d.splits) return;
   const int M = d.M, N = d.N, K = d.K;
@@ -350,8 +356,9 @@ int tuned_splits(int site, int dflt) {
 
 template <typename Tin, typename Tc, typename Tout>
 void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s,
-                 int tile, int site) {
+                 int tile, int site, int groups) {
   if (nitems <= 0 || maxTiles <= 0) return;
+  if (groups < 1 || nitems % groups != 0) groups = 1;
   const long long blocks = (long long)nitems * maxBatch * maxSplits * maxTiles;
   if (blocks <= 0) return;
   const long long grid = (blocks + NXCD - 1) / NXCD * NXCD;
@@ -364,17 +371,17 @@ void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplit
   if (tile == 32) {
     if (g3)
       hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 32, 32, true>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs,
-                         maxBatch, maxSplits, maxTiles, blocks);
+                         maxBatch, maxSplits, maxTiles, blocks, nitems, groups);
     else
       hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 32, 32, false>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs,
-                         maxBatch, maxSplits, maxTiles, blocks);
+                         maxBatch, maxSplits, maxTiles, blocks, nitems, groups);
   } else {
     if (g3)
       hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 64, 64, true>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs,
-                         maxBatch, maxSplits, maxTiles, blocks);
+                         maxBatch, maxSplits, maxTiles, blocks, nitems, groups);
     else
       hipLaunchKernelGGL((k_gemm<Tin, Tc, Tout, 64, 64, false>), dim3((unsigned)grid), dim3(NTHR), 0, s, d_descs,
-                         maxBatch, maxSplits, maxTiles, blocks);
+                         maxBatch, maxSplits, maxTiles, blocks, nitems, groups);
   }
   prof_end_gemm(tok, cls, d_descs, nitems, (int)sizeof(cpx<Tin>), (int)sizeof(cpx<Tout>), s);
 }
@@ -388,9 +395,9 @@ void launch_reduce_splits(const GemmDesc* d_descs, double* const* d_outs, int ni
                      d_outs, maxCount);
 }
 
-template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int, int);
-template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, hipStream_t, int, int);
-template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int, int);
-template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, hipStream_t, int, int);
+template void launch_gemm<double, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int, int, int);
+template void launch_gemm<float, float, float>(const GemmDesc*, int, int, int, int, hipStream_t, int, int, int);
+template void launch_gemm<float, double, double>(const GemmDesc*, int, int, int, int, hipStream_t, int, int, int);
+template void launch_gemm<double, double, float>(const GemmDesc*, int, int, int, int, hipStream_t, int, int, int);
 
 }  // namespace mpdo

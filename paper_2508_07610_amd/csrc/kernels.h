@@ -12,6 +12,9 @@ namespace mpdo {
 // above the diagonal, ceil(N/tile) (ceil(N/tile) + 1) / 2 of them: a launch
 // of such items needs only gemm_tiles_herm of the largest N.
 // Tin: input precision, Tc: MFMA precision, Tout: output precision.
+// groups > 1: the descriptors form `groups` consecutive groups of
+// nitems / groups (different products of each item); the launch visits them
+// interleaved so that every XCD takes a share of each group.
 int gemm_tiles(int maxM, int maxN, int tile = 64);
 // Complex-product form of the launches of one MFMA precision and tile size:
 // 4 (four real products) or 3 (Gauss's three); process-wide, default 4.
@@ -20,7 +23,7 @@ void set_gemm_form(bool fp64, int tile, int form);
 int gemm_tiles_herm(int maxN, int tile = 64);
 template <typename Tin, typename Tc, typename Tout>
 void launch_gemm(const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, int maxTiles, hipStream_t s,
-                 int tile = 64, int site = -1);
+                 int tile = 64, int site = -1, int groups = 1);
 
 // Per call site of the MPDO update (a GemmSite of profile.h), the settings
 // an autotuner may choose: the tile edge (32 or 64), the complex-product form
@@ -39,9 +42,9 @@ int tuned_splits(int site, int dflt);
 // that tile from tiles_of(tile), and its tuned form.
 template <typename Tin, typename Tc, typename Tout, typename F>
 void launch_gemm_site(int site, const GemmDesc* d_descs, int nitems, int maxBatch, int maxSplits, F tiles_of,
-                      hipStream_t s, int dflt_tile = 64) {
+                      hipStream_t s, int dflt_tile = 64, int groups = 1) {
   const int tile = tuned_tile(site, dflt_tile);
-  launch_gemm<Tin, Tc, Tout>(d_descs, nitems, maxBatch, maxSplits, tiles_of(tile), s, tile, site);
+  launch_gemm<Tin, Tc, Tout>(d_descs, nitems, maxBatch, maxSplits, tiles_of(tile), s, tile, site, groups);
 }
 
 // out[item] = sum over splits of the partial products of descs[item]
