@@ -21,7 +21,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,6 +29,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+from paper_2508_07610_amd.pmc_summary import kernel_sources_hash  # noqa: E402
 
 N_QUBITS, DEPTH, CHI, KAPPA = 16, 10, 64, 8
 SVD_CUT, KAP_CUT = 1e-10, 1e-10
@@ -267,23 +268,6 @@ def observables(n):
     for m in (np.diag([1.0, 0.0]), np.diag([0.0, 1.0]), np.array([[0.0, 1.0], [0.0, 0.0]])):
         ops.append(np.stack([m.astype(np.complex128)] * n))
     return np.stack(ops)
-
-
-# sources that decide a kernel class's code and the shapes it is launched with
-KERNEL_SOURCES = {
-    "k_gemm": ("gemm.hip", "common.h", "ops.hip", "ops.h", "engine.hip", "engine.h", "kernels.h"),
-    "k_heev": ("eigh.hip", "common.h", "ops.hip", "engine.hip", "kernels.h"),
-}
-
-
-def kernel_sources_hash(kernel):
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2508_07610_amd", "csrc")
-    key = "k_gemm" if kernel.startswith("k_gemm") else "k_heev"
-    for f in KERNEL_SOURCES[key]:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
-    return h.hexdigest()[:16]
 
 
 def traffic_for(kernel, launches_per_step):
