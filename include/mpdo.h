@@ -334,7 +334,8 @@ typedef enum {
   MPDO_PROF_EIG_REG = 2,    /* eigensolver, n <= 128 (register-resident)      */
   MPDO_PROF_EIG_GLOBAL = 3, /* eigensolver, one-stage, matrix in global memory */
   MPDO_PROF_EIG_BAND = 4,   /* eigensolver, 128 < n <= 256, through a band    */
-  MPDO_PROF_NCLASS = 5
+  MPDO_PROF_CHOL = 5,       /* pivoted Cholesky of the right-factor Gram      */
+  MPDO_PROF_NCLASS = 6
 } mpdo_prof_class;
 
 /* Reset the counters (synchronises the device) and switch profiling on

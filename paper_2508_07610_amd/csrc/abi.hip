@@ -1054,6 +1054,13 @@ extern "C" mpdo_status mpdo_test_gemm_form(int32_t prec, int32_t tile, int32_t f
   return MPDO_OK;
 }
 
+extern "C" mpdo_status mpdo_test_e_cholesky(int32_t on, int32_t* previous) {
+  if (on != 0 && on != 1) return fail(MPDO_EINVAL, "on must be 0 or 1");
+  if (previous) *previous = e_cholesky() ? 1 : 0;
+  set_e_cholesky(on != 0);
+  return MPDO_OK;
+}
+
 extern "C" mpdo_status mpdo_test_eig_band(int32_t on, int32_t* previous) {
   if (on != 0 && on != 1) return fail(MPDO_EINVAL, "on must be 0 or 1");
   if (previous) *previous = eig_band() ? 1 : 0;

@@ -549,8 +549,12 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
                           [&](int tl) { return gemm_tiles_herm(2 * cx, tl); }, st_, 64);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramE), reinterpret_cast<double**>(dv + uOutsE), n,
                        4 * cx * cx, st_);
-  launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigE), n, 2 * cx, status, st_);
-  launch_q2_select_e<T>(dctx, n, splitsH, tp, st_);
+  if (e_cholesky() && 2 * cx <= 128) {
+    launch_q2_chol_e<T>(dctx, n, splitsH, tp, reinterpret_cast<EigDesc*>(dv + uEigE), st_);
+  } else {
+    launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigE), n, 2 * cx, status, st_);
+    launch_q2_select_e<T>(dctx, n, splitsH, tp, st_);
+  }
   launch_gemm_site<T, T, T>(GS_Q2_THETA, reinterpret_cast<GemmDesc*>(dv + uTh), n, 1, 1,
                           [&](int tl) { return gemm_tiles((int)thetaN, 4 * cx, tl); }, st_, 64);
   launch_gemm_site<T, double, double>(GS_Q2_GRAM_H, reinterpret_cast<GemmDesc*>(dv + uGramH), n, 1, splitsH,

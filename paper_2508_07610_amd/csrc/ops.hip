@@ -4,6 +4,7 @@
 // the following contractions on the device.  One workgroup per item.
 #include "common.h"
 #include "ops.h"
+#include "profile.h"
 
 namespace mpdo {
 
@@ -278,11 +279,13 @@ __global__ __launch_bounds__(GT) void k_q2_prepare(Ctx2<T>* ctxs, int splitsE) {
 
 // r_F, L_F = P D^(1/2), PD = P D^(-1/2); descriptors of th = B_i L_F and of
 // the Gram H of th.
+template <typename T> __device__ void q2_theta_descs(Ctx2<T>& c, int rF, int splitsH);
+
 template <typename T>
 __global__ __launch_bounds__(GT) void k_q2_select_e(Ctx2<T>* ctxs, int splitsH, TruncParams tp) {
   __shared__ int s_rF;
   Ctx2<T>& c = ctxs[blockIdx.x];
-  const int k1 = *c.kap1, cl = *c.chil, cm = *c.chim;
+  const int cm = *c.chim;
   const int nE = 2 * cm;
   if (threadIdx.x == 0) {
     int rF = 0;
@@ -302,7 +305,14 @@ __global__ __launch_bounds__(GT) void k_q2_select_e(Ctx2<T>* ctxs, int splitsH, 
     c.LF[e] = mk<T>((T)(p.re * sq), (T)(p.im * sq));
     st(c.PD, e, mk(p.re / sq, p.im / sq));
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) q2_theta_descs(c, rF, splitsH);
+}
+
+// Descriptors of theta = B_i L_F and of the inner Gram H of theta, once r_F
+// and L_F are known (one thread).
+template <typename T> __device__ void q2_theta_descs(Ctx2<T>& c, int rF, int splitsH) {
+  const int k1 = *c.kap1, cl = *c.chil, cm = *c.chim;
+  {
     {  // th[(l t1 k1),(t2 b)] = sum_m B_i[(l t1 k1), m] L_F[(m t2), b]
       GemmDesc& d = *c.dTh;
       clear_desc(d);
@@ -331,6 +341,212 @@ __global__ __launch_bounds__(GT) void k_q2_select_e(Ctx2<T>* ctxs, int splitsH, 
         d.splits = splitsH;
       }
     }
+  }
+}
+
+// The right-factor basis from a pivoted Cholesky factorisation of
+// E = F F^H (n = 2 chi_m <= 128) in place of its eigendecomposition: with
+// the pivots taken largest first, Pi^T E Pi = L L^H, r = the number of pivots
+// above tolE times the first; L_F = Pi L (rows in E's own order) and
+// PD = Pi [L1^-H; 0], L1 the leading r x r block, so that PD^H F = L1^-1 F1
+// has orthonormal rows and F = L_F (PD^H F) up to the dropped Schur
+// complement (weight below n tolE of the first pivot).  One workgroup of
+// CH_NT threads per item keeps the upper triangle of E packed in LDS (each
+// thread owns up to CH_NE packed entries); a pivot step forms the column
+// l = S[:, p] / sqrt(S[p][p]) (zero on earlier pivots) and updates the Schur
+// complement S -= l l^H in place, and the columns of L go to the
+// eigenvector buffer.  The same LDS then holds X = L1^-1 (packed lower
+// triangle, pivot order), built by right-looking elimination with the
+// columns of L1 read back from that buffer one step ahead.
+constexpr int CH_NT = 1024, CH_NC = 128, CH_NPK = CH_NC * (CH_NC + 1) / 2;
+constexpr int CH_NE = (CH_NPK + CH_NT - 1) / CH_NT;
+
+// Candidate (av, ai) ranks above (bv, bi) as a pivot: any candidate above
+// none (index n), a NaN above a number (so that it is found and reported),
+// else the larger value, ties to the smaller index.
+__device__ inline bool chol_better(double av, int ai, double bv, int bi, int n) {
+  if (ai >= n) return false;
+  if (bi >= n) return true;
+  const bool an = av != av, bn = bv != bv;
+  if (an != bn) return an;
+  if (an) return ai < bi;
+  return av > bv || (av == bv && ai < bi);
+}
+
+// Wave 0: the largest remaining diagonal entry into *piv, *dp (*dp = -1 when
+// every row is a pivot already); row `skip` counts as a pivot.
+__device__ void chol_pivot(const double* dg, const int* done, int n, int skip, int* piv, double* dp) {
+  const int lane = threadIdx.x;
+  double best = 0.0;
+  int bi = n;
+  for (int e = lane; e < CH_NC; e += 64) {
+    if (e >= n || done[e] || e == skip) continue;
+    if (chol_better(dg[e], e, best, bi, n)) {
+      best = dg[e];
+      bi = e;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bi, off);
+    if (chol_better(ob, oi, best, bi, n)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    *piv = bi;
+    *dp = bi < n ? best : -1.0;
+  }
+}
+
+// Row of packed entry e of an m x m triangle stored row by row, rows of
+// length rowlen(i) starting at start[i] (start[m] = the count): the last i
+// with start[i] <= e.
+__device__ inline int packed_row(const int* start, int m, int e) {
+  int lo = 0, hi = m - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(CH_NT) void k_q2_chol_e(Ctx2<T>* ctxs, int splitsH, TruncParams tp) {
+  __shared__ cpx<double> P[CH_NPK];  // S (upper, row i: columns i..n-1), then X (lower, row j: 0..j)
+  __shared__ cpx<double> colbuf[CH_NC];
+  __shared__ cpx<double> lbuf[2][CH_NC];
+  __shared__ double dg[CH_NC];
+  __shared__ int done[CH_NC], pivrow[CH_NC], posr[CH_NC], start[CH_NC + 1];
+  __shared__ int s_piv;
+  __shared__ double s_dp;
+  Ctx2<T>& c = ctxs[blockIdx.x];
+  const int nE = 2 * *c.chim;
+  const int n = nE <= CH_NC ? nE : 0;  // a larger E is reported as a failure below (the host never sends one)
+  const int t = threadIdx.x;
+  const cpx<double> zero = mk(0.0, 0.0);
+  double* Lsc = c.vecE;  // column k of L at Lsc[k n + row]
+  const int npk = n * (n + 1) / 2;
+  // upper triangle: row i holds columns i..n-1
+  if (t <= n) start[t] = t * n - t * (t - 1) / 2;
+  if (t < CH_NC) {
+    dg[t] = t < n ? c.E[2 * ((long long)t * n + t)] : 0.0;
+    done[t] = t < n ? 0 : 1;
+    posr[t] = -1;
+  }
+  __syncthreads();
+  int ei[CH_NE], ej[CH_NE];  // (row, column) of this thread's packed entries
+#pragma unroll
+  for (int q = 0; q < CH_NE; ++q) {
+    const int e = t + CH_NT * q;
+    ei[q] = ej[q] = 0;
+    if (e < npk) {
+      const int i = packed_row(start, n, e);
+      ei[q] = i;
+      ej[q] = i + (e - start[i]);
+      P[e] = ld(c.E, (long long)i * n + ej[q]);
+    }
+  }
+  if (t < 64) chol_pivot(dg, done, n, -1, &s_piv, &s_dp);
+  __syncthreads();
+  const double d0 = s_dp;
+  const double thr = tp.tolE * d0;
+  bool fail = !(d0 > 0.0 && d0 < 1e300) || n != nE;
+  int r = 0;
+  for (int k = 0; k < n && !fail; ++k) {
+    const int p = s_piv;
+    const double dp = s_dp;
+    if (!(dp < 1e300)) {  // NaN or overflow in the Schur complement
+      fail = true;
+      break;
+    }
+    if (!(dp > thr)) break;
+    if (t < n) {  // l = S[:, p] / sqrt(S[p][p]), zero on earlier pivots
+      cpx<double> v = zero;
+      if (!done[t]) {
+        const double inv = 1.0 / sqrt(dp);
+        v = t <= p ? inv * P[start[t] + (p - t)] : inv * cconj(P[start[p] + (t - p)]);
+      }
+      colbuf[t] = v;
+      st(Lsc, (long long)k * n + t, v);
+      dg[t] -= v.re * v.re + v.im * v.im;
+    }
+    if (t == 0) {
+      pivrow[k] = p;
+      posr[p] = k;
+    }
+    __syncthreads();
+    // every read of s_piv, s_dp and done for this step is behind the barrier:
+    // wave 0 picks the next pivot while the Schur complement is updated
+    if (t < 64) {
+      if (t == 0) done[p] = 1;
+      chol_pivot(dg, done, n, p, &s_piv, &s_dp);
+    }
+#pragma unroll
+    for (int q = 0; q < CH_NE; ++q) {
+      const int e = t + CH_NT * q;
+      if (e < npk) {
+        const cpx<double> li = colbuf[ei[q]];
+        if (li.re != 0.0 || li.im != 0.0) P[e] = P[e] - li * cconj(colbuf[ej[q]]);  // rows of pivots: l = 0
+      }
+    }
+    __syncthreads();
+    r = k + 1;
+  }
+  if (r == 0) fail = true;
+  const int rF = fail ? 1 : r;
+  if (!fail) {
+    // X = L1^-1 (lower triangle, pivot order: row j holds columns 0..j)
+    const int nx = r * (r + 1) / 2;
+    if (t <= r) start[t] = t * (t + 1) / 2;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CH_NE; ++q) {
+      const int e = t + CH_NT * q;
+      ei[q] = ej[q] = 0;
+      if (e < nx) {
+        const int j = packed_row(start, r, e);
+        ei[q] = j;
+        ej[q] = e - start[j];
+        P[e] = ej[q] == j ? mk(1.0, 0.0) : zero;
+      }
+    }
+    if (t < r) lbuf[0][t] = ld(Lsc, pivrow[t]);
+    __syncthreads();
+    for (int m = 0; m < r; ++m) {
+      const int cur = m & 1;
+      if (m + 1 < r && t < r) lbuf[cur ^ 1][t] = ld(Lsc, (long long)(m + 1) * n + pivrow[t]);
+      if (t <= m) {  // row m of X, scaled by 1 / L1[m][m]
+        const cpx<double> x = (1.0 / lbuf[cur][m].re) * P[start[m] + t];
+        P[start[m] + t] = x;
+        colbuf[t] = x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < CH_NE; ++q) {
+        const int e = t + CH_NT * q;
+        if (e < nx && ei[q] > m && ej[q] <= m) P[e] = P[e] - lbuf[cur][ei[q]] * colbuf[ej[q]];
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = t; e < nE * rF; e += CH_NT) {
+    const int row = e / rF, b = e % rF;
+    cpx<double> l = zero, pd = zero;
+    if (!fail) {
+      l = ld(Lsc, (long long)b * n + row);
+      const int j = posr[row];
+      if (j >= 0 && j <= b) pd = cconj(P[start[b] + j]);  // conj(X[b][j])
+    }
+    c.LF[e] = mk<T>((T)l.re, (T)l.im);
+    st(c.PD, e, pd);
+  }
+  if (t == 0) {
+    c.scratch[1] = rF;
+    if (fail) c.disc[ST_FAIL] += 1.0;
+    q2_theta_descs(c, rF, splitsH);
   }
 }
 
@@ -1324,6 +1540,19 @@ template <typename T> void launch_q2_prepare(Ctx2<T>* d, int n, int splitsE, hip
 template <typename T> void launch_q2_select_e(Ctx2<T>* d, int n, int splitsH, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_select_e<T>, dim3(n), dim3(GT), 0, s, d, splitsH, tp);
 }
+template <typename T>
+void launch_q2_chol_e(Ctx2<T>* d, int n, int splitsH, TruncParams tp, const EigDesc* d_eig, hipStream_t s) {
+  if (n <= 0) return;
+  const int tok = prof_begin(PC_CHOL_E, s);
+  hipLaunchKernelGGL(k_q2_chol_e<T>, dim3(n), dim3(CH_NT), 0, s, d, splitsH, tp);
+  prof_end_chol(tok, PC_CHOL_E, d_eig, n, s);
+}
+
+namespace {
+bool g_e_chol = true;
+}
+void set_e_cholesky(bool on) { g_e_chol = on; }
+bool e_cholesky() { return g_e_chol; }
 template <typename T> void launch_q2_gamma(Ctx2<T>* d, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_gamma<T>, dim3(n, 4), dim3(GT), 0, s, d);
 }
@@ -1403,6 +1632,7 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_q1_select<T>(Ctx1<T>*, int, TruncParams, hipStream_t);                 \
   template void launch_q2_prepare<T>(Ctx2<T>*, int, int, hipStream_t);                        \
   template void launch_q2_select_e<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
+  template void launch_q2_chol_e<T>(Ctx2<T>*, int, int, TruncParams, const EigDesc*, hipStream_t); \
   template void launch_q2_gamma<T>(Ctx2<T>*, int, hipStream_t);                               \
   template void launch_q2_select_g<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_select_b<T>(Ctx2<T>*, int, TruncParams, hipStream_t);              \

@@ -15,7 +15,8 @@ enum ProfClass : int {
   PC_EIG_REG = 2,    // Hermitian eigensolver, matrix in registers (n <= 128)
   PC_EIG_GLOBAL = 3, // Hermitian eigensolver, matrix in global memory
   PC_EIG_BAND = 4,   // Hermitian eigensolver, two-stage through a band (128 < n <= 256)
-  PC_NCLASS = 5
+  PC_CHOL_E = 5,     // pivoted Cholesky of the two-site right-factor Gram and its triangular inverse
+  PC_NCLASS = 6
 };
 
 // Returns an opaque token (>= 0) if the launch is profiled, else -1.
@@ -28,6 +29,10 @@ void prof_end_gemm(int token, int cls, const GemmDesc* d_descs, int nitems, int 
 // transformation of k = min(kvec, n) vectors) flops; bytes = reading A and
 // writing the k vectors.  Items outside [nlo, nhi] are skipped.
 void prof_end_eig(int token, int cls, const EigDesc* d_descs, int nitems, int nlo, int nhi, hipStream_t s);
+// Pivoted Cholesky of an n x n Hermitian matrix and the inverse of its
+// triangular factor (n from the item's EigDesc): 8/3 n^3 flops (4/3 n^3
+// each); bytes = reading the matrix and writing two n x n factors.
+void prof_end_chol(int token, int cls, const EigDesc* d_descs, int nitems, hipStream_t s);
 
 // Call site of the following GEMM launches on this thread (a label of the
 // contraction, see GemmSite); each site's time and work are also summed.

@@ -90,6 +90,18 @@ __global__ __launch_bounds__(AT) void k_account_eig(const EigDesc* __restrict__ 
   block_add(f, b, flops, bytes);
 }
 
+__global__ __launch_bounds__(AT) void k_account_chol(const EigDesc* __restrict__ d, int n,
+                                                     double* __restrict__ flops, double* __restrict__ bytes) {
+  double f = 0, b = 0;
+  for (int i = threadIdx.x; i < n; i += AT) {
+    if (!d[i].active) continue;
+    const double m = d[i].n;
+    f += 8.0 / 3.0 * m * m * m;
+    b += 48.0 * m * m;
+  }
+  block_add(f, b, flops, bytes);
+}
+
 }  // namespace
 
 bool prof_enabled() { return P().on; }
@@ -156,6 +168,13 @@ void prof_end_eig(int token, int cls, const EigDesc* d_descs, int nitems, int nl
   double* c = P().dcount;
   hipLaunchKernelGGL(k_account_eig, dim3(1), dim3(AT), 0, s, d_descs, nitems, nlo, nhi, c + cls,
                      c + PC_NCLASS + cls);
+}
+
+void prof_end_chol(int token, int cls, const EigDesc* d_descs, int nitems, hipStream_t s) {
+  if (token < 0) return;
+  end_common(token, cls, s);
+  double* c = P().dcount;
+  hipLaunchKernelGGL(k_account_chol, dim3(1), dim3(AT), 0, s, d_descs, nitems, c + cls, c + PC_NCLASS + cls);
 }
 
 void prof_read(int cls, int* launches, double* ms, double* flops, double* bytes) {

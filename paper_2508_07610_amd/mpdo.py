@@ -512,9 +512,10 @@ def tune_get(site: int):
     return t.value, f.value, s.value
 
 
-PROF_GEMM_F64, PROF_GEMM_F32, PROF_EIG_REG, PROF_EIG_GLOBAL, PROF_EIG_BAND = range(5)
+PROF_GEMM_F64, PROF_GEMM_F32, PROF_EIG_REG, PROF_EIG_GLOBAL, PROF_EIG_BAND, PROF_CHOL = range(6)
 PROF_NAMES = {PROF_GEMM_F64: "k_gemm (FP64 MFMA)", PROF_GEMM_F32: "k_gemm (FP32 MFMA)",
-              PROF_EIG_REG: "k_heev_reg", PROF_EIG_GLOBAL: "k_heev_global", PROF_EIG_BAND: "k_heev_band"}
+              PROF_EIG_REG: "k_heev_reg", PROF_EIG_GLOBAL: "k_heev_global", PROF_EIG_BAND: "k_heev_band",
+              PROF_CHOL: "k_q2_chol_e"}
 
 
 def profile_enable(on: bool = True) -> None:
@@ -611,6 +612,15 @@ def eig_band(on: bool) -> bool:
     returns the previous setting."""
     prev = ctypes.c_int32()
     check(_testing_lib().mpdo_test_eig_band(1 if on else 0, ctypes.byref(prev)))
+    return bool(prev.value)
+
+
+def e_cholesky(on: bool) -> bool:
+    """Build the two-site update's right-factor basis from a pivoted Cholesky
+    factorisation of E (True, the default) or from its eigendecomposition
+    (False); returns the previous setting."""
+    prev = ctypes.c_int32()
+    check(_testing_lib().mpdo_test_e_cholesky(1 if on else 0, ctypes.byref(prev)))
     return bool(prev.value)
 
 

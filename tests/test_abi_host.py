@@ -140,7 +140,7 @@ def test_test_entry_points_validate_sizes():
 def test_profile_read_rejects_unknown_class():
     L = M.lib()
     assert L.mpdo_profile_read(-1, None, None, None, None) == M.EINVAL
-    assert L.mpdo_profile_read(5, None, None, None, None) == M.EINVAL
+    assert L.mpdo_profile_read(6, None, None, None, None) == M.EINVAL
 
 
 @pytest.mark.parametrize("q,kind,fixed,chi,status", [(3, 0, 0, 16, M.EINVAL), (3, 1, -1, 16, M.EINVAL),

@@ -139,6 +139,36 @@ def test_truncated_ansatz_matches_oracle(prec, n, depth, chi, kap, tag):
             assert np.abs(lam - o.lam[b]).max() < 1e-9
 
 
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+def test_right_factor_basis_routes_agree_with_oracle(prec):
+    """The two-site update's basis of the right factor from the
+    eigendecomposition of E = F F^H and from its pivoted Cholesky
+    factorisation (the default for 2 chi <= 128): both write F = L_F Q with
+    orthonormal rows Q, an exact change of basis, so either route matches the
+    oracle's truncations and observables."""
+    require_gpu()
+    n, depth, chi, kap = 10, 3, 32, 8
+    prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, 2))
+    o = _oracle_run(prog, chi, kap, 1e-10, 1e-10)
+    tol = TOL[prec]
+    obs = {}
+    for chol in (False, True):
+        prev = M.e_cholesky(chol)
+        try:
+            st = _gpu_run(prog, chi_max=chi, kappa_max=kap, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10,
+                          prec=prec)
+            bonds, inner, disc = st.dims()
+            if prec == M.C128:
+                assert bonds == o.bond_dims() and inner == o.inner_dims(), chol
+            vals = [st.expect(s) for s in W.zz_strings(n)] + [st.fidelity_ghz()]
+            ref = [o.expect_pauli(s) for s in W.zz_strings(n)] + [o.fidelity_ghz()]
+            assert np.abs(np.array(vals) - np.array(ref)).max() < tol, chol
+            obs[chol] = np.array(vals)
+        finally:
+            M.e_cholesky(prev)
+    assert np.abs(obs[True] - obs[False]).max() < tol
+
+
 def test_invalid_sites_rejected():
     require_gpu()
     st = M.MPDO(4, chi_max=8, kappa_max=2, max_kraus=4)
