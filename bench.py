@@ -636,7 +636,7 @@ def main():
         if a.retune:
             AT.save(path, key, None)
         t_tune = time.perf_counter()
-        tune_info = AT.tuned(lambda: step(graph=False), path, key)
+        tune_info = AT.tuned(lambda: step(graph=False), path, key, top=12)
         tune_info["seconds"] = time.perf_counter() - t_tune
         tune_info["cache_key"] = key
     for _ in range(a.warmup):
