@@ -48,6 +48,8 @@ def kernel_sources_hash(kernel: str) -> str:
 
 
 def kernel_class(name: str):
+    if "k_q2_chol_e" in name:
+        return "k_q2_chol_e"
     if "k_heev_global" in name:
         return "k_heev_global"
     if "k_heev_reg" in name:
