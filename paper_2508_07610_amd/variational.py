@@ -237,7 +237,8 @@ def pretrain(net, X: np.ndarray, Y: np.ndarray, steps: int, batch: int = 512, lr
 
 
 def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: float, max_rows: int = 20000,
-                       lr: float = 0.05, fit_steps: int = 150, fit_lr: float = 1e-3, window: int = 4,
+                       lr: float = 0.05, fit_steps: int = 150, fit_lr: float = 1e-3, fit_batch: int = 512,
+                       window: int = 4,
                        inner: int = 30, inner_lr: float = 0.04, cand_at=(3, 6, 10, 15, 22, 30),
                        out_scale: float = 10.0, time_limit: float = 600.0) -> dict:
     """Surrogate-assisted ascent: the network proposes steps, the MPDO verifies them.
@@ -299,7 +300,7 @@ def surrogate_optimize(ev: AnsatzEvaluator, net, theta0: np.ndarray, target: flo
             yt = np.zeros((len(Xr), net.widths[-1]), np.float32)
             yt[:, 0] = (Yr - Fref) * out_scale
             yd = torch.tensor(yt, device="cuda")
-            nb = min(net.max_batch, len(Xr), 512)
+            nb = min(net.max_batch, len(Xr), fit_batch)
             net.fit(xd, yd, fit_steps, nb, fit_lr, seed=7919 * counts["gradients"] + 17)
             x0 = torch.cat([torch.zeros((1, P), dtype=torch.float32, device="cuda"), nz_t], dim=1).view(-1)
             reset = True
