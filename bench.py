@@ -174,7 +174,29 @@ def cpu_baseline(W, threads1=True):
             "sample": f"steady state of the same workload: one two-site noisy gate ({t2:.2f} s) and one one-site "
                       f"noisy gate ({t1:.2f} s) on sites at chi={CHI}, kappa={KAPPA} (complex128 NumPy/LAPACK), "
                       f"scaled to a layer of 15 + 32 gates",
-            "host_cpu": host, "one_thread": one}
+            "host_cpu": host, "one_thread": one, "c5_row": c5_row_seconds(W)}
+
+
+def c5_row_seconds(W):
+    """The oracle's truncated MPDO on one parameter row of the variational
+    workload (noisy RY/CZ ansatz n=12, depth 6, chi=32, kappa=4, cutoffs
+    1e-10, complex128, every host core): the CPU cost of one MPDO evaluation,
+    from which the time-to-fidelity leg estimates the oracle's time to the
+    same target (its rows to target times this)."""
+    import math
+    import numpy as np
+    from oracle import channels as OC
+    from oracle import mpdo as OM
+    n, depth = 12, 6
+    th = np.random.default_rng(7611).uniform(0, 2 * math.pi, 2 * n * depth)
+    prog = W.ghz_ansatz_noise(n, depth, th, None)
+    kr = [OC.kraus_from_chi(c)[0] for c in prog.chis]
+    t0 = time.perf_counter()
+    o = OM.run_program(prog, OM.MPDO(n, 32, 4, 1e-10, 1e-10), kr)
+    o.fidelity_ghz()
+    return {"seconds": time.perf_counter() - t0, "cores": blas_threads(),
+            "sample": "one parameter row of the n=12 depth-6 ansatz (chi=32, kappa=4, complex128), "
+                      "circuit and GHZ fidelity"}
 
 
 def oracle_error(zz, f, noise_scale=1.0):
@@ -368,6 +390,7 @@ def ttf_leg(steps, nsamples=65536, pretrain_steps=6000, seeds=tuple(range(8))):
             "f_best_plain": ref["best"], "target": target, "runs": runs,
             "mean_plain_seconds": tp, "mean_surrogate_seconds": tsur,
             "mean_plain_mpdo_rows": rp, "mean_surrogate_mpdo_rows": rsur,
+            "mean_surrogate_seconds_with_data": (tsur + t_gen + pre["train_seconds"]) if tsur else None,
             "data_generation": {"samples": nsamples, "seconds": t_gen, "precision": "c64 contractions + FP64 truncation"},
             "pretraining": pre,
             "break_even_optimisations": (overhead / (tp - tsur)) if tp and tsur and tp > tsur else None}
@@ -674,6 +697,14 @@ def main():
         wl = (f"batched MPDO, {ninst} parameter points of the noisy RY/CZ ansatz n={N_QUBITS} depth={a.depth} "
               f"chi={CHI} kappa={KAPPA} svd_cutoff={SVD_CUT}, one mpdo_batch_run per step"
               + ("" if a.no_graph else " captured in one HIP graph"))
+    cpu = None if a.no_cpu else cpu_baseline(W, threads1=a.cpu_threads1)
+    ttf = None if a.no_ttf else ttf_leg(a.ttf_steps)
+    if cpu and ttf and ttf.get("mean_plain_mpdo_rows"):
+        row = cpu["c5_row"]
+        ttf["cpu_oracle_estimate"] = {
+            "seconds": row["seconds"] * ttf["mean_plain_mpdo_rows"], "cores": row["cores"],
+            "note": "the plain optimizer's mean MPDO rows to the target times the oracle's seconds per row "
+                    "(cpu_baseline.c5_row): an estimate from one timed row, not a run"}
     out = {
         "metric": "MPDO gate-layers/s (n=16,chi=64,kappa=8) plain vs batched; surrogate time-to-fidelity",
         "value": value, "unit": "gate-layers/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -689,8 +720,8 @@ def main():
         "gemm_sites": {k: {"ms": v["ms"], "launches": v["launches"], "tflops": v["tflops"]} for k, v in sites.items()},
         "autotune": tune_info,
         "sweep": None if a.no_sweep else sweep_leg(M, W),
-        "cpu_baseline": None if a.no_cpu else cpu_baseline(W, threads1=a.cpu_threads1),
-        "time_to_fidelity": None if a.no_ttf else ttf_leg(a.ttf_steps),
+        "cpu_baseline": cpu,
+        "time_to_fidelity": ttf,
         "maxcut_batch": None if a.no_maxcut else maxcut_leg(),
         "gemm_full_tiles": None if a.no_gemm_tiles else gemm_tiles_leg(),
         "sampling": None if a.no_sampling else sampling_leg(),
