@@ -41,8 +41,8 @@ PEAK = {"f64_mfma": 78.6, "f32_mfma": 157.3, "f64_valu": 78.6, "hbm": 8000.0}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", choices=["c128", "c64"], default="c128")
     ap.add_argument("--depth", type=int, default=DEPTH)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -669,8 +669,11 @@ def main():
     if profiled_timed:
         M.profile_enable(True)
     t0 = time.perf_counter()
+    step_s = []
     for _ in range(a.steps):
-        f, zz = step()
+        ts = time.perf_counter()
+        f, zz = step()  # returns host values: each step ends synchronised
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     if not profiled_timed:
@@ -708,7 +711,7 @@ def main():
     out = {
         "metric": "MPDO gate-layers/s (n=16,chi=64,kappa=8) plain vs batched; surrogate time-to-fidelity",
         "value": value, "unit": "gate-layers/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": ms, "ms_per_step_median": 1e3 * float(np.median(step_s)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c128" if prec == M.C128 else "c64+f64", "data": "synthetic",
         "config": {"workload": wl, "instances": ninst, "mode": a.mode, "ghz_fidelity_instance0": f,
                    "zz01_instance0": zz[0], "roofline_from": "timed steps" if profiled_timed
