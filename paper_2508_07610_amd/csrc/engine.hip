@@ -549,8 +549,8 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
                           [&](int tl) { return gemm_tiles_herm(2 * cx, tl); }, st_, 64);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramE), reinterpret_cast<double**>(dv + uOutsE), n,
                        4 * cx * cx, st_);
-  if (e_cholesky() && 2 * cx <= 128) {
-    launch_q2_chol_e<T>(dctx, n, splitsH, tp, reinterpret_cast<EigDesc*>(dv + uEigE), st_);
+  if (e_cholesky() && 2 * cx <= 256) {
+    launch_q2_chol_e<T>(dctx, n, 2 * cx, splitsH, tp, reinterpret_cast<EigDesc*>(dv + uEigE), st_);
   } else {
     launch_eigh(reinterpret_cast<EigDesc*>(dv + uEigE), n, 2 * cx, status, st_);
     launch_q2_select_e<T>(dctx, n, splitsH, tp, st_);

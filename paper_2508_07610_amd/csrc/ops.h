@@ -248,10 +248,13 @@ template <typename T> void launch_q1_select(Ctx1<T>* d_ctx, int n, TruncParams t
 template <typename T> void launch_q2_prepare(Ctx2<T>* d_ctx, int n, int splitsE, hipStream_t s);
 template <typename T> void launch_q2_select_e(Ctx2<T>* d_ctx, int n, int splitsH, TruncParams tp, hipStream_t s);
 // The right-factor basis of the two-site update from a pivoted Cholesky
-// factorisation of E (2 chi_max <= 128) instead of launch_eigh +
-// launch_q2_select_e; d_eig: the items' EigDesc of E (for the profiler).
+// factorisation of E instead of launch_eigh + launch_q2_select_e; maxn
+// (= 2 chi_max) bounds E's size: up to 128 the matrix is held in LDS, up to
+// 256 it is updated in place in global memory.  d_eig: the items' EigDesc of
+// E (for the profiler).
 template <typename T>
-void launch_q2_chol_e(Ctx2<T>* d_ctx, int n, int splitsH, TruncParams tp, const EigDesc* d_eig, hipStream_t s);
+void launch_q2_chol_e(Ctx2<T>* d_ctx, int n, int maxn, int splitsH, TruncParams tp, const EigDesc* d_eig,
+                      hipStream_t s);
 // Process-wide choice of that route (default on).
 void set_e_cholesky(bool on);
 bool e_cholesky();

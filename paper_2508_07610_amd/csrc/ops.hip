@@ -373,13 +373,14 @@ __device__ inline bool chol_better(double av, int ai, double bv, int bi, int n) 
   return av > bv || (av == bv && ai < bi);
 }
 
-// Wave 0: the largest remaining diagonal entry into *piv, *dp (*dp = -1 when
-// every row is a pivot already); row `skip` counts as a pivot.
-__device__ void chol_pivot(const double* dg, const int* done, int n, int skip, int* piv, double* dp) {
+// Wave 0: the largest remaining diagonal entry of rows [0, n) (n <= nmax,
+// the length of dg and done) into *piv, *dp (*dp = -1 when every row is a
+// pivot already); row `skip` counts as a pivot.
+__device__ void chol_pivot(const double* dg, const int* done, int n, int nmax, int skip, int* piv, double* dp) {
   const int lane = threadIdx.x;
   double best = 0.0;
   int bi = n;
-  for (int e = lane; e < CH_NC; e += 64) {
+  for (int e = lane; e < nmax; e += 64) {
     if (e >= n || done[e] || e == skip) continue;
     if (chol_better(dg[e], e, best, bi, n)) {
       best = dg[e];
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(CH_NT) void k_q2_chol_e(Ctx2<T>* ctxs, int splitsH,
       P[e] = ld(c.E, (long long)i * n + ej[q]);
     }
   }
-  if (t < 64) chol_pivot(dg, done, n, -1, &s_piv, &s_dp);
+  if (t < 64) chol_pivot(dg, done, n, CH_NC, -1, &s_piv, &s_dp);
   __syncthreads();
   const double d0 = s_dp;
   const double thr = tp.tolE * d0;
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(CH_NT) void k_q2_chol_e(Ctx2<T>* ctxs, int splitsH,
     // wave 0 picks the next pivot while the Schur complement is updated
     if (t < 64) {
       if (t == 0) done[p] = 1;
-      chol_pivot(dg, done, n, p, &s_piv, &s_dp);
+      chol_pivot(dg, done, n, CH_NC, p, &s_piv, &s_dp);
     }
 #pragma unroll
     for (int q = 0; q < CH_NE; ++q) {
@@ -539,6 +540,136 @@ __global__ __launch_bounds__(CH_NT) void k_q2_chol_e(Ctx2<T>* ctxs, int splitsH,
       l = ld(Lsc, (long long)b * n + row);
       const int j = posr[row];
       if (j >= 0 && j <= b) pd = cconj(P[start[b] + j]);  // conj(X[b][j])
+    }
+    c.LF[e] = mk<T>((T)l.re, (T)l.im);
+    st(c.PD, e, pd);
+  }
+  if (t == 0) {
+    c.scratch[1] = rF;
+    if (fail) c.disc[ST_FAIL] += 1.0;
+    q2_theta_descs(c, rF, splitsH);
+  }
+}
+
+// The same factorisation for 128 < n <= 256 (chi_max <= 128), with the
+// Schur complement updated in place in E's own buffer (row-major, upper
+// triangle) and X = L1^-1 in the bond-Gram eigenvector buffer (row-major,
+// lower triangle).  Thread t owns the columns cp = t % 128 and 255 - cp (so
+// that every thread holds about the same number of upper-triangle entries)
+// in the rows t / 128 + 8 q; each entry is read and written by its owner
+// only, apart from the pivot column, which every thread reads after the
+// step's barrier.
+constexpr int CG_NT = 1024, CG_NC = 256, CG_CP = CG_NC / 2, CG_RP = CG_NT / CG_CP;
+
+template <typename T>
+__global__ __launch_bounds__(CG_NT) void k_q2_chol_e_g(Ctx2<T>* ctxs, int splitsH, TruncParams tp) {
+  __shared__ cpx<double> colbuf[CG_NC];
+  __shared__ cpx<double> lbuf[2][CG_NC];
+  __shared__ double dg[CG_NC];
+  __shared__ int done[CG_NC], pivrow[CG_NC], posr[CG_NC];
+  __shared__ int s_piv;
+  __shared__ double s_dp;
+  Ctx2<T>& c = ctxs[blockIdx.x];
+  const int nE = 2 * *c.chim;
+  const int n = nE <= CG_NC ? nE : 0;  // a larger E is reported as a failure below (the host never sends one)
+  const int t = threadIdx.x, cp = t % CG_CP, g = t / CG_CP;
+  const int cols[2] = {cp, CG_NC - 1 - cp};
+  const cpx<double> zero = mk(0.0, 0.0);
+  double* S = c.E;       // S[i][j] at S[i n + j], i <= j
+  double* Lsc = c.vecE;  // column k of L at Lsc[k n + row]
+  double* X = c.vecC;    // X[j][b] at X[j n + b], b <= j
+  if (t < CG_NC) {
+    dg[t] = t < n ? S[2 * ((long long)t * n + t)] : 0.0;
+    done[t] = t < n ? 0 : 1;
+    posr[t] = -1;
+  }
+  __syncthreads();
+  if (t < 64) chol_pivot(dg, done, n, CG_NC, -1, &s_piv, &s_dp);
+  __syncthreads();
+  const double d0 = s_dp;
+  const double thr = tp.tolE * d0;
+  bool fail = !(d0 > 0.0 && d0 < 1e300) || n != nE;
+  int r = 0;
+  for (int k = 0; k < n && !fail; ++k) {
+    const int p = s_piv;
+    const double dp = s_dp;
+    if (!(dp < 1e300)) {
+      fail = true;
+      break;
+    }
+    if (!(dp > thr)) break;
+    if (t < n) {  // l = S[:, p] / sqrt(S[p][p]), zero on earlier pivots
+      cpx<double> v = zero;
+      if (!done[t]) {
+        const double inv = 1.0 / sqrt(dp);
+        v = t <= p ? inv * ld(S, (long long)t * n + p) : inv * cconj(ld(S, (long long)p * n + t));
+      }
+      colbuf[t] = v;
+      st(Lsc, (long long)k * n + t, v);
+      dg[t] -= v.re * v.re + v.im * v.im;
+    }
+    if (t == 0) {
+      pivrow[k] = p;
+      posr[p] = k;
+    }
+    __syncthreads();
+    if (t < 64) {
+      if (t == 0) done[p] = 1;
+      chol_pivot(dg, done, n, CG_NC, p, &s_piv, &s_dp);
+    }
+    for (int h = 0; h < 2; ++h) {
+      const int j = cols[h];
+      if (j >= n) continue;
+      const cpx<double> lj = cconj(colbuf[j]);
+      if (lj.re == 0.0 && lj.im == 0.0) continue;  // a pivot's column: nothing to subtract
+      for (int i = g; i <= j; i += CG_RP) {
+        const cpx<double> li = colbuf[i];
+        if (li.re != 0.0 || li.im != 0.0) st(S, (long long)i * n + j, ld(S, (long long)i * n + j) - li * lj);
+      }
+    }
+    __syncthreads();
+    r = k + 1;
+  }
+  if (r == 0) fail = true;
+  const int rF = fail ? 1 : r;
+  if (!fail) {
+    // X = L1^-1 (lower triangle, pivot order), right-looking elimination
+    for (int h = 0; h < 2; ++h) {
+      const int b = cols[h];
+      if (b >= r) continue;
+      for (int j = b + ((g - b) % CG_RP + CG_RP) % CG_RP; j < r; j += CG_RP)
+        st(X, (long long)j * n + b, j == b ? mk(1.0, 0.0) : zero);
+    }
+    if (t < r) lbuf[0][t] = ld(Lsc, pivrow[t]);
+    __syncthreads();
+    for (int m = 0; m < r; ++m) {
+      const int cur = m & 1;
+      if (m + 1 < r && t < r) lbuf[cur ^ 1][t] = ld(Lsc, (long long)(m + 1) * n + pivrow[t]);
+      if (t <= m) {  // row m of X, scaled by 1 / L1[m][m]
+        const cpx<double> x = (1.0 / lbuf[cur][m].re) * ld(X, (long long)m * n + t);
+        st(X, (long long)m * n + t, x);
+        colbuf[t] = x;
+      }
+      __syncthreads();
+      for (int h = 0; h < 2; ++h) {
+        const int b = cols[h];
+        if (b > m || b >= r) continue;
+        const cpx<double> xb = colbuf[b];
+        // rows j > m owned by this thread: j = g (mod CG_RP)
+        for (int j = m + 1 + ((g - m - 1) % CG_RP + CG_RP) % CG_RP; j < r; j += CG_RP)
+          st(X, (long long)j * n + b, ld(X, (long long)j * n + b) - lbuf[cur][j] * xb);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < nE * rF; e += CG_NT) {
+    const int row = e / rF, b = e % rF;
+    cpx<double> l = zero, pd = zero;
+    if (!fail) {
+      l = ld(Lsc, (long long)b * n + row);
+      const int j = posr[row];
+      if (j >= 0 && j <= b) pd = cconj(ld(X, (long long)b * n + j));  // conj(X[b][j])
     }
     c.LF[e] = mk<T>((T)l.re, (T)l.im);
     st(c.PD, e, pd);
@@ -1541,10 +1672,14 @@ template <typename T> void launch_q2_select_e(Ctx2<T>* d, int n, int splitsH, Tr
   if (n > 0) hipLaunchKernelGGL(k_q2_select_e<T>, dim3(n), dim3(GT), 0, s, d, splitsH, tp);
 }
 template <typename T>
-void launch_q2_chol_e(Ctx2<T>* d, int n, int splitsH, TruncParams tp, const EigDesc* d_eig, hipStream_t s) {
+void launch_q2_chol_e(Ctx2<T>* d, int n, int maxn, int splitsH, TruncParams tp, const EigDesc* d_eig,
+                      hipStream_t s) {
   if (n <= 0) return;
   const int tok = prof_begin(PC_CHOL_E, s);
-  hipLaunchKernelGGL(k_q2_chol_e<T>, dim3(n), dim3(CH_NT), 0, s, d, splitsH, tp);
+  if (maxn <= CH_NC)
+    hipLaunchKernelGGL(k_q2_chol_e<T>, dim3(n), dim3(CH_NT), 0, s, d, splitsH, tp);
+  else
+    hipLaunchKernelGGL(k_q2_chol_e_g<T>, dim3(n), dim3(CG_NT), 0, s, d, splitsH, tp);
   prof_end_chol(tok, PC_CHOL_E, d_eig, n, s);
 }
 
@@ -1632,7 +1767,7 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_q1_select<T>(Ctx1<T>*, int, TruncParams, hipStream_t);                 \
   template void launch_q2_prepare<T>(Ctx2<T>*, int, int, hipStream_t);                        \
   template void launch_q2_select_e<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
-  template void launch_q2_chol_e<T>(Ctx2<T>*, int, int, TruncParams, const EigDesc*, hipStream_t); \
+  template void launch_q2_chol_e<T>(Ctx2<T>*, int, int, int, TruncParams, const EigDesc*, hipStream_t); \
   template void launch_q2_gamma<T>(Ctx2<T>*, int, hipStream_t);                               \
   template void launch_q2_select_g<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_select_b<T>(Ctx2<T>*, int, TruncParams, hipStream_t);              \

@@ -140,14 +140,15 @@ def test_truncated_ansatz_matches_oracle(prec, n, depth, chi, kap, tag):
 
 
 @pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
-def test_right_factor_basis_routes_agree_with_oracle(prec):
+@pytest.mark.parametrize("n,depth,chi,kap", [(10, 3, 32, 8), (8, 3, 80, 4)])
+def test_right_factor_basis_routes_agree_with_oracle(prec, n, depth, chi, kap):
     """The two-site update's basis of the right factor from the
     eigendecomposition of E = F F^H and from its pivoted Cholesky
-    factorisation (the default for 2 chi <= 128): both write F = L_F Q with
-    orthonormal rows Q, an exact change of basis, so either route matches the
-    oracle's truncations and observables."""
+    factorisation (the default; E in LDS for 2 chi <= 128, in global memory
+    up to 256): both write F = L_F Q with orthonormal rows Q, an exact change
+    of basis, so either route matches the oracle's truncations and
+    observables."""
     require_gpu()
-    n, depth, chi, kap = 10, 3, 32, 8
     prog = W.ghz_ansatz(n, depth, W.ansatz_params(n, depth, 2))
     o = _oracle_run(prog, chi, kap, 1e-10, 1e-10)
     tol = TOL[prec]
