@@ -47,7 +47,8 @@ enum Epi : int {
   EPI_STORE = 0,   // C = acc
   EPI_HIDDEN = 1,  // z = acc + bias[col] -> Z (FP32), h = GELU(z) -> Hb (bf16)
   EPI_OUT = 2,     // y = acc + bias[col] -> C
-  EPI_ACTGRAD = 3  // g = acc * GELU'(aux[row][col]) -> C (FP32) and Hb (bf16)
+  EPI_ACTGRAD = 3, // g = acc * GELU'(aux[row][col]) -> C (FP32) and Hb (bf16)
+  EPI_OUTGRAD = 4  // y = acc + bias[col] -> C; the MSE cotangent 2 (y - aux) scale -> C2 (FP32), Hb (bf16)
 };
 
 struct MlpGemm {
@@ -67,22 +68,25 @@ struct MlpGemm {
   // colsrc[k ldcol + i] (FP32), from the workgroups of the first column tile
   const float* colsrc;
   float* colout;
+  float* C2;    // EPI_OUTGRAD: the cotangent
+  float scale;  // EPI_OUTGRAD: 1 / (rows x outputs)
 };
 
 // C[M x N] = op(A)[M x K] op(B)[K x N]: op(A)[i][k] = transA ? A[k lda + i] : A[i lda + k],
 // op(B)[k][j] = transB ? B[j ldb + k] : B[k ldb + j].
-template <int EPI>
-__global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
+// One output tile (bx) of one K range (by) of the product g, epilogue epi
+// (uniform per workgroup).
+__device__ void mlp_gemm_tile(const MlpGemm& g, int epi, int bx, int by) {
   __shared__ __attribute__((aligned(16))) uint16_t As[MT][KP];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[MT][KP];  // [n][k]
   __shared__ float red[MTH / MT][MT];
   const int tilesN = (g.N + MT - 1) / MT;
-  const int m0 = (blockIdx.x / tilesN) * MT, n0 = (blockIdx.x % tilesN) * MT;
+  const int m0 = (bx / tilesN) * MT, n0 = (bx % tilesN) * MT;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1, li = lane & 15, lg = lane >> 4;
-  const int kb = blockIdx.y * g.kper, ke = min(g.K, kb + g.kper);
+  const int kb = by * g.kper, ke = min(g.K, kb + g.kper);
   // with transA each thread stages one row m0 + tid % MT of op(A) (MT divides MTH)
-  const bool colsum = g.colsrc != nullptr && (blockIdx.x % tilesN) == 0;
+  const bool colsum = g.colsrc != nullptr && (bx % tilesN) == 0;
   float csum = 0.0f;
   f4 acc[2][2];
 #pragma unroll
@@ -138,10 +142,10 @@ __global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
       float t = 0;
 #pragma unroll
       for (int r = 0; r < MTH / MT; ++r) t += red[r][tid];
-      g.colout[blockIdx.y * g.sC + m0 + tid] = t;
+      g.colout[by * g.sC + m0 + tid] = t;
     }
   }
-  float* C = g.C + blockIdx.y * g.sC;
+  float* C = g.C + by * g.sC;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -153,20 +157,43 @@ __global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
         if (row >= g.M || col >= g.N) continue;
         const float x = acc[i][j][v];
         const long long o = (long long)row * g.ldc + col;
-        if (EPI == EPI_STORE) {
+        if (epi == EPI_STORE) {
           C[o] = x;
-        } else if (EPI == EPI_HIDDEN) {
+        } else if (epi == EPI_HIDDEN) {
           const float z = x + g.bias[col];
           C[o] = z;
           g.Hb[o] = f2bf(gelu(z));
-        } else if (EPI == EPI_OUT) {
+        } else if (epi == EPI_OUT) {
           C[o] = x + g.bias[col];
+        } else if (epi == EPI_OUTGRAD) {
+          const float y = x + g.bias[col];
+          C[o] = y;
+          const float d = y - g.aux[o];
+          const float v = 2.0f * d * g.scale;
+          g.C2[o] = v;
+          g.Hb[o] = f2bf(v);
         } else {
           const float gz = x * gelu_grad(g.aux[o]);
           C[o] = gz;
           g.Hb[o] = f2bf(gz);
         }
       }
+}
+
+template <int EPI>
+__global__ __launch_bounds__(MTH) void k_mlp_gemm(MlpGemm g) {
+  mlp_gemm_tile(g, EPI, blockIdx.x, blockIdx.y);
+}
+
+// Two independent products in one launch (grid z = 0, 1): blocks beyond a
+// product's tiles or K ranges return.
+__global__ __launch_bounds__(MTH) void k_mlp_gemm_pair(MlpGemm g0, int epi0, int tiles0, int splits0, MlpGemm g1,
+                                                       int epi1, int tiles1, int splits1) {
+  if (blockIdx.z == 0) {
+    if ((int)blockIdx.x < tiles0 && (int)blockIdx.y < splits0) mlp_gemm_tile(g0, epi0, blockIdx.x, blockIdx.y);
+  } else {
+    if ((int)blockIdx.x < tiles1 && (int)blockIdx.y < splits1) mlp_gemm_tile(g1, epi1, blockIdx.x, blockIdx.y);
+  }
 }
 
 __global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, long long n) {
@@ -219,6 +246,26 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ grad, fl
                        float eps, float c1, float c2) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const float gr = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gr;
+    const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+  }
+}
+
+// The split reduction of k_grad_reduce followed by the update of k_adam, in
+// one pass (same arithmetic; the summed gradient is still written to grad).
+__global__ void k_reduce_adam(const float* __restrict__ part, int splits, float* __restrict__ p,
+                              float* __restrict__ grad, float* __restrict__ m, float* __restrict__ v,
+                              uint16_t* __restrict__ pb, long long n, float lr, float b1, float b2, float eps,
+                              float c1, float c2) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    float gr = 0;
+    for (int s = 0; s < splits; ++s) gr += part[s * n + i];
+    grad[i] = gr;
     const float mi = b1 * m[i] + (1.0f - b1) * gr;
     const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
     m[i] = mi;
@@ -284,12 +331,24 @@ __global__ void k_onehot(int n, int col, float* __restrict__ g, uint16_t* __rest
   }
 }
 
+int tiles_of(const MlpGemm& g) { return ((g.M + MT - 1) / MT) * ((g.N + MT - 1) / MT); }
+
 // splits: number of K ranges (grid dimension y); g.kper and g.sC must match
 template <int EPI> void gemm(MlpGemm g, hipStream_t s, int splits = 1) {
-  const int tiles = ((g.M + MT - 1) / MT) * ((g.N + MT - 1) / MT);
+  const int tiles = tiles_of(g);
   if (splits <= 1) g.kper = g.K;
   if (tiles > 0 && g.K > 0)
     hipLaunchKernelGGL(k_mlp_gemm<EPI>, dim3(tiles, splits > 1 ? splits : 1), dim3(MTH), 0, s, g);
+}
+
+// Two independent products (epilogues e0, e1; K splits s0, s1) in one launch.
+void gemm_pair(MlpGemm g0, int e0, int s0, MlpGemm g1, int e1, int s1, hipStream_t s) {
+  if (s0 <= 1) { g0.kper = g0.K; s0 = 1; }
+  if (s1 <= 1) { g1.kper = g1.K; s1 = 1; }
+  const int t0 = g0.K > 0 ? tiles_of(g0) : 0, t1 = g1.K > 0 ? tiles_of(g1) : 0;
+  const int tx = t0 > t1 ? t0 : t1, sy = s0 > s1 ? s0 : s1;
+  if (tx > 0)
+    hipLaunchKernelGGL(k_mlp_gemm_pair, dim3(tx, sy, 2), dim3(MTH), 0, s, g0, e0, t0, s0, g1, e1, t1, s1);
 }
 
 // K split of the weight-gradient products: ranges of a multiple of KT rows,
@@ -334,8 +393,10 @@ struct mpdo_mlp_s {
 namespace {
 mpdo_status mfail(int st, const std::string& msg) { return (mpdo_status)set_last_error(st, msg); }
 
-// Forward pass for `batch` rows of the bf16 input already in xb into y (FP32, device).
-void mlp_forward_xb(mpdo_mlp_s* h, int batch, float* y) {
+// Forward pass for `batch` rows of the bf16 input already in xb into y (FP32,
+// device). With targets tgt (batch x d_L) the last product also writes the
+// MSE output cotangent 2 (y - tgt) / (batch d_L) into gz/gzb of the last layer.
+void mlp_forward_xb(mpdo_mlp_s* h, int batch, float* y, const float* tgt = nullptr) {
   const int L = h->L;
   const uint16_t* in = h->xb.as<uint16_t>();
   for (int l = 0; l < L; ++l) {
@@ -350,6 +411,13 @@ void mlp_forward_xb(mpdo_mlp_s* h, int batch, float* y) {
       g.Hb = h->hb.as<uint16_t>() + h->zoff[l];
       gemm<EPI_HIDDEN>(g, h->st);
       in = g.Hb;
+    } else if (tgt) {
+      g.C = y;
+      g.aux = tgt;
+      g.C2 = h->gz.as<float>() + h->zoff[l];
+      g.Hb = h->gzb.as<uint16_t>() + h->zoff[l];
+      g.scale = 1.0f / (float)((long long)batch * h->w[L]);
+      gemm<EPI_OUTGRAD>(g, h->st);
     } else {
       g.C = y;
       gemm<EPI_OUT>(g, h->st);
@@ -365,9 +433,12 @@ void mlp_forward(mpdo_mlp_s* h, const float* x, int batch, float* y) {
 }
 
 // Backward pass from the output cotangent already in gz/gzb of the last
-// layer: with params, weight and bias gradients into h->g (split over the
-// batch into partial sums, then added up); input gradient into dx (if set).
-void mlp_backward(mpdo_mlp_s* h, int batch, float* dx, bool params = true) {
+// layer: with params, weight and bias gradients of each layer as split
+// partial sums in gpart (split over the batch); input gradient into dx (if
+// set). The weight-gradient product of a layer and the product for the
+// cotangent of the layer below read the same inputs and write disjoint
+// buffers, so they share one launch. Returns the number of splits.
+int mlp_backward_parts(mpdo_mlp_s* h, int batch, float* dx, bool params) {
   const int L = h->L;
   int splits = 1, kper = batch;
   split_of(batch, &splits, &kper);
@@ -376,38 +447,53 @@ void mlp_backward(mpdo_mlp_s* h, int batch, float* dx, bool params = true) {
     const uint16_t* gb = h->gzb.as<uint16_t>() + h->zoff[l];
     const float* gf = h->gz.as<float>() + h->zoff[l];
     const uint16_t* hin = l == 0 ? h->xb.as<uint16_t>() : h->hb.as<uint16_t>() + h->zoff[l - 1];
-    if (params) {  // dW_l = G^T H_{l-1}: (d_l x B)(B x d_{l-1}); db_l = G^T 1 alongside
-      MlpGemm g{};
-      g.A = gb; g.lda = h->w[l + 1]; g.transA = 1;
-      g.B = hin; g.ldb = h->w[l];
-      g.M = h->w[l + 1]; g.N = h->w[l]; g.K = batch;
-      g.C = part + h->woff[l]; g.ldc = h->w[l];
-      g.kper = kper;
-      g.sC = h->np;
-      g.colsrc = gf;
-      g.colout = part + h->boff[l];
-      gemm<EPI_STORE>(g, h->st, splits);
+    // dW_l = G^T H_{l-1}: (d_l x B)(B x d_{l-1}); db_l = G^T 1 alongside
+    MlpGemm gw{};
+    gw.A = gb; gw.lda = h->w[l + 1]; gw.transA = 1;
+    gw.B = hin; gw.ldb = h->w[l];
+    gw.M = h->w[l + 1]; gw.N = h->w[l]; gw.K = batch;
+    gw.C = part + h->woff[l]; gw.ldc = h->w[l];
+    gw.kper = kper;
+    gw.sC = h->np;
+    gw.colsrc = gf;
+    gw.colout = part + h->boff[l];
+    const bool need_da = l > 0 || dx;
+    if (!need_da) {
+      if (params) gemm<EPI_STORE>(gw, h->st, splits);
+      break;
     }
-    if (l == 0 && !dx) break;
     // dA = G W_l: (B x d_l)(d_l x d_{l-1}); times GELU'(z_{l-1}) for hidden inputs
-    MlpGemm g{};
-    g.A = gb; g.lda = h->w[l + 1];
-    g.B = h->pb.as<uint16_t>() + h->woff[l]; g.ldb = h->w[l];
-    g.M = batch; g.N = h->w[l]; g.K = h->w[l + 1];
-    g.ldc = h->w[l];
+    MlpGemm ga{};
+    ga.A = gb; ga.lda = h->w[l + 1];
+    ga.B = h->pb.as<uint16_t>() + h->woff[l]; ga.ldb = h->w[l];
+    ga.M = batch; ga.N = h->w[l]; ga.K = h->w[l + 1];
+    ga.ldc = h->w[l];
+    int ea = EPI_STORE;
     if (l > 0) {
-      g.C = h->gz.as<float>() + h->zoff[l - 1];
-      g.Hb = h->gzb.as<uint16_t>() + h->zoff[l - 1];
-      g.aux = h->z.as<float>() + h->zoff[l - 1];
-      gemm<EPI_ACTGRAD>(g, h->st);
+      ga.C = h->gz.as<float>() + h->zoff[l - 1];
+      ga.Hb = h->gzb.as<uint16_t>() + h->zoff[l - 1];
+      ga.aux = h->z.as<float>() + h->zoff[l - 1];
+      ea = EPI_ACTGRAD;
     } else {
-      g.C = dx;
-      gemm<EPI_STORE>(g, h->st);
+      ga.C = dx;
+    }
+    if (params) {
+      gemm_pair(gw, EPI_STORE, splits, ga, ea, 1, h->st);
+    } else if (ea == EPI_ACTGRAD) {
+      gemm<EPI_ACTGRAD>(ga, h->st);
+    } else {
+      gemm<EPI_STORE>(ga, h->st);
     }
   }
+  return splits;
+}
+
+// mlp_backward_parts, then the split partial sums added up into h->g.
+void mlp_backward(mpdo_mlp_s* h, int batch, float* dx, bool params = true) {
+  const int splits = mlp_backward_parts(h, batch, dx, params);
   if (params)
-    hipLaunchKernelGGL(k_grad_reduce, dim3(grid_for(h->np)), dim3(256), 0, h->st, part, h->np, splits,
-                       h->g.as<float>());
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid_for(h->np)), dim3(256), 0, h->st, h->gpart.as<float>(), h->np,
+                       splits, h->g.as<float>());
 }
 
 void adam_step(mpdo_mlp_s* h, float lr, float beta1, float beta2, float eps) {
@@ -606,15 +692,25 @@ mpdo_status mpdo_mlp_fit(mpdo_mlp_t h, const float* x_dev, const float* t_dev, i
   float* gl = h->gz.as<float>() + h->zoff[L - 1];
   uint16_t* glb = h->gzb.as<uint16_t>() + h->zoff[L - 1];
   const int blocks = grid_for(n);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   for (int s = 0; s < steps; ++s) {
     hipLaunchKernelGGL(k_gather, dim3(batch), dim3(64), 0, h->st, x_dev, t_dev, (long long)nrows, d0, dL, batch,
                        seed, (long long)s, h->xb.as<uint16_t>(), h->tb.as<float>());
-    mlp_forward_xb(h, batch, h->yb.as<float>());
-    hipLaunchKernelGGL(k_out_grad, dim3(blocks), dim3(256), 0, h->st, h->yb.as<float>(), h->tb.as<float>(), n,
-                       1.0f / (float)n, gl, glb, h->part.as<float>());
-    mlp_backward(h, batch, nullptr);
+    if (loss && s + 1 == steps) {  // the last step also leaves the loss partials
+      mlp_forward_xb(h, batch, h->yb.as<float>());
+      hipLaunchKernelGGL(k_out_grad, dim3(blocks), dim3(256), 0, h->st, h->yb.as<float>(), h->tb.as<float>(), n,
+                         1.0f / (float)n, gl, glb, h->part.as<float>());
+    } else {
+      mlp_forward_xb(h, batch, h->yb.as<float>(), h->tb.as<float>());
+    }
+    const int splits = mlp_backward_parts(h, batch, nullptr, true);
     const float lr_s = cosine ? lr * 0.5f * (1.0f + std::cos(3.14159265358979f * (float)s / (float)steps)) : lr;
-    adam_step(h, lr_s, 0.9f, 0.999f, 1e-8f);
+    h->step += 1;
+    const float c1 = 1.0f / (1.0f - std::pow(b1, (float)h->step));
+    const float c2 = 1.0f / (1.0f - std::pow(b2, (float)h->step));
+    hipLaunchKernelGGL(k_reduce_adam, dim3(grid_for(h->np)), dim3(256), 0, h->st, h->gpart.as<float>(), splits,
+                       h->p.as<float>(), h->g.as<float>(), h->m.as<float>(), h->v.as<float>(),
+                       h->pb.as<uint16_t>(), h->np, lr_s, b1, b2, eps, c1, c2);
   }
   hip_check(hipGetLastError(), "launch (mlp fit)");
   if (loss) {
