@@ -87,6 +87,15 @@ mpdo_status mpdo_test_fail_next_update(int32_t status);
  * setting before the call.  EINVAL unless on is 0 or 1. */
 mpdo_status mpdo_test_eig_band(int32_t on, int32_t* previous);
 
+/* Eigenproblems with n > 128 in launches of at most 32 matrices: several
+ * workgroups share each matrix during the Householder reduction to
+ * tridiagonal form, one launch per step while the trailing block is wider
+ * than 128, then one workgroup per matrix finishes (on = 1, the default); or
+ * one workgroup per matrix throughout (on = 0).  Same results up to rounding
+ * order.  Process-wide; *previous (may be NULL) receives the setting before
+ * the call.  EINVAL unless on is 0 or 1. */
+mpdo_status mpdo_test_eig_coop(int32_t on, int32_t* previous);
+
 /* The basis of the two-site update's right factor (E = F F^H, n = 2 chi <=
  * 128): a pivoted Cholesky factorisation of E (on = 1, the default) or its
  * eigendecomposition (on = 0); both give F = L_F Q with orthonormal rows Q

@@ -28,6 +28,8 @@
 //
 // Only the eigenpairs a truncation can keep are computed; the discarded
 // weight comes from Tr(A) minus the kept eigenvalues.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
@@ -932,6 +934,84 @@ __device__ void panel_tridiag(const EigDesc& dsc, cpx<double>* __restrict__ A, i
   }
 }
 
+// Steps k0 .. n-2 of the reduction with one column per step (the previous
+// step's rank-2 update fused with this step's matrix-vector pass) on A in
+// global memory; `pend`: the update of step k0 - 1 (S.vp, S.wp; index 0 = row
+// k0) is still to be applied to the block [k0, n)^2.  Writes S.d, S.e, S.tau
+// from k0 on (S.d[n - 1] excepted: A[n-1][n-1] holds it at the end).
+template <class SH>
+__device__ void onecol_steps(cpx<double>* __restrict__ A, int n, int k0, bool pend, SH& S, int& par) {
+  const int tid = threadIdx.x;
+  for (int k = k0; k + 1 < n; ++k) {
+    const int m = n - k - 1;
+    const int c0 = k + 1;
+    if (pend) {  // bring column k (rows k..n-1) up to date first
+      const cpx<double> wk = cconj(S.wp[0]), vk = cconj(S.vp[0]);
+      for (int i = k + tid; i < n; i += NT) {
+        cpx<double> x = A[(long long)i * n + k];
+        x = sub2prod(x, S.vp[i - k], wk, S.wp[i - k], vk);
+        A[(long long)i * n + k] = x;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) S.d[k] = A[(long long)k * n + k].re;
+    double xn = 0;
+    for (int i = 1 + tid; i < m; i += NT) xn += cabs2(A[(long long)(c0 + i) * n + k]);
+    xn = block_sum(xn, S.red, par);
+    if (tid == 0) {
+      const cpx<double> alpha = A[(long long)c0 * n + k];
+      if (xn == 0.0 && alpha.im == 0.0) {
+        S.tau[k] = mk(0.0, 0.0);
+        S.e[k] = alpha.re;
+        S.flag[0] = 0;
+      } else {
+        const double nrm = sqrt(cabs2(alpha) + xn);
+        const double beta = alpha.re >= 0 ? -nrm : nrm;
+        S.tau[k] = mk((beta - alpha.re) / beta, -alpha.im / beta);
+        const cpx<double> den = mk(alpha.re - beta, alpha.im);  // scal = 1 / (alpha - beta)
+        const double dd = cabs2(den);
+        S.scal[0] = den.re / dd;
+        S.scal[1] = -den.im / dd;
+        S.e[k] = beta;
+        S.flag[0] = 1;
+      }
+    }
+    __syncthreads();
+    const bool act = S.flag[0] != 0;
+    const cpx<double> tau = S.tau[k];
+    if (act) {
+      const cpx<double> sc = mk(S.scal[0], S.scal[1]);
+      for (int i = tid; i < m; i += NT) {
+        const cpx<double> v = (i == 0) ? mk(1.0, 0.0) : A[(long long)(c0 + i) * n + k] * sc;
+        S.v[i] = v;
+        A[(long long)(c0 + i) * n + k] = v;  // kept for the back-transformation
+      }
+    }
+    __syncthreads();
+    fused_pass(A, n, c0, k, pend, act, S);
+    if (act) {
+      double g = 0;  // gamma = v^H p
+      for (int i = tid; i < m; i += NT) g += S.v[i].re * S.pp[i].re + S.v[i].im * S.pp[i].im;
+      g = block_sum(g, S.red, par);
+      const double cc = 0.5 * cabs2(tau) * g;
+      for (int i = tid; i < m; i += NT) {
+        S.wp[i] = tau * S.pp[i] - cc * S.v[i];
+        S.vp[i] = S.v[i];
+      }
+      __syncthreads();
+    }
+    pend = act;
+  }
+  if (pend) {  // the last pending update touches only A[n-1][n-1]
+    if (tid == 0) {
+      cpx<double> x = A[(long long)(n - 1) * n + n - 1];
+      x = x - S.vp[0] * cconj(S.wp[0]) - S.wp[0] * cconj(S.vp[0]);
+      A[(long long)(n - 1) * n + n - 1] = x;
+    }
+    __syncthreads();
+  }
+}
+
 // PANEL: the panel-blocked reduction (less memory traffic per step, more
 // work per step: faster when many matrices share the memory system);
 // otherwise one fused pass per step (lower latency for a lone matrix).
@@ -959,77 +1039,8 @@ __device__ void heev_core(const EigDesc& dsc, cpx<double>* __restrict__ A, SH& S
     if (n <= 256) panel_tridiag<true>(dsc, A, n, S, par);
     else panel_tridiag<false>(dsc, A, n, S, par);
   } else {
-    // ---- 2. tridiagonalisation, one column per step: the previous step's
-    // rank-2 update is fused with this step's matrix-vector pass ----
-    bool pend = false;  // a rank-2 update (vp, wp; index 0 = row k) is pending
-    for (int k = 0; k + 1 < n; ++k) {
-      const int m = n - k - 1;
-      const int c0 = k + 1;
-      if (pend) {  // bring column k (rows k..n-1) up to date first
-        const cpx<double> wk = cconj(S.wp[0]), vk = cconj(S.vp[0]);
-        for (int i = k + tid; i < n; i += NT) {
-          cpx<double> x = A[(long long)i * n + k];
-          x = sub2prod(x, S.vp[i - k], wk, S.wp[i - k], vk);
-          A[(long long)i * n + k] = x;
-        }
-        __syncthreads();
-      }
-      if (tid == 0) S.d[k] = A[(long long)k * n + k].re;
-      double xn = 0;
-      for (int i = 1 + tid; i < m; i += NT) xn += cabs2(A[(long long)(c0 + i) * n + k]);
-      xn = block_sum(xn, S.red, par);
-      if (tid == 0) {
-        const cpx<double> alpha = A[(long long)c0 * n + k];
-        if (xn == 0.0 && alpha.im == 0.0) {
-          S.tau[k] = mk(0.0, 0.0);
-          S.e[k] = alpha.re;
-          S.flag[0] = 0;
-        } else {
-          const double nrm = sqrt(cabs2(alpha) + xn);
-          const double beta = alpha.re >= 0 ? -nrm : nrm;
-          S.tau[k] = mk((beta - alpha.re) / beta, -alpha.im / beta);
-          const cpx<double> den = mk(alpha.re - beta, alpha.im);  // scal = 1 / (alpha - beta)
-          const double dd = cabs2(den);
-          S.scal[0] = den.re / dd;
-          S.scal[1] = -den.im / dd;
-          S.e[k] = beta;
-          S.flag[0] = 1;
-        }
-      }
-      __syncthreads();
-      const bool act = S.flag[0] != 0;
-      const cpx<double> tau = S.tau[k];
-      if (act) {
-        const cpx<double> sc = mk(S.scal[0], S.scal[1]);
-        for (int i = tid; i < m; i += NT) {
-          const cpx<double> v = (i == 0) ? mk(1.0, 0.0) : A[(long long)(c0 + i) * n + k] * sc;
-          S.v[i] = v;
-          A[(long long)(c0 + i) * n + k] = v;  // kept for the back-transformation
-        }
-      }
-      __syncthreads();
-      fused_pass(A, n, c0, k, pend, act, S);
-      if (act) {
-        double g = 0;  // gamma = v^H p
-        for (int i = tid; i < m; i += NT) g += S.v[i].re * S.pp[i].re + S.v[i].im * S.pp[i].im;
-        g = block_sum(g, S.red, par);
-        const double cc = 0.5 * cabs2(tau) * g;
-        for (int i = tid; i < m; i += NT) {
-          S.wp[i] = tau * S.pp[i] - cc * S.v[i];
-          S.vp[i] = S.v[i];
-        }
-        __syncthreads();
-      }
-      pend = act;
-    }
-    if (pend) {  // the last pending update touches only A[n-1][n-1]
-      if (tid == 0) {
-        cpx<double> x = A[(long long)(n - 1) * n + n - 1];
-        x = x - S.vp[0] * cconj(S.wp[0]) - S.wp[0] * cconj(S.vp[0]);
-        A[(long long)(n - 1) * n + n - 1] = x;
-      }
-      __syncthreads();
-    }
+    // ---- 2. tridiagonalisation, one column per step ----
+    onecol_steps(A, n, 0, false, S, par);
   }
   if (tid == 0) S.d[n - 1] = A[(long long)(n - 1) * n + n - 1].re;
   for (int i = tid; i + 1 < n; i += NT) S.e2[i] = S.e[i] * S.e[i];
@@ -2018,15 +2029,313 @@ __global__ __launch_bounds__(NT) void k_heev_big(const EigDesc* __restrict__ des
   if (threadIdx.x == 0 && status) status[blockIdx.x] = 1;
 }
 
+// ---------------------------------------------------------------------------
+// Shared reduction for launches of few large matrices.  With one workgroup
+// per matrix such a launch leaves most compute units idle, and every
+// Householder step waits on one CU's memory latency.  Here G workgroups share
+// a matrix during the reduction: workgroup g owns the columns of every G-th
+// chunk of CO_CW columns (chunks j = g, g + G, ...), applies the pending
+// rank-2 update to its columns of the trailing block and forms their entries
+// of p = A v; every workgroup forms the same reflector and the same w from
+// the column and the p of the previous step, read back from global memory.
+// One kernel launch per step (the launch boundary is the only barrier
+// between workgroups), as long as the trailing block is wider than
+// CO_TAIL; one workgroup per matrix then finishes the last CO_TAIL steps
+// (onecol_steps), the eigenvalues, the vectors and the back-transformation.
+// Per matrix, after the n x n copy in the work array: v of the last two steps
+// (2 n), their p (2 n), tau (n) complex; d and e (n each).
+// ---------------------------------------------------------------------------
+constexpr int CO_CW = 16;     // columns per ownership chunk
+constexpr int CO_TAIL = 128;  // steps left to one workgroup (trailing block <= CO_TAIL)
+constexpr int CO_NQ = 32;     // most row groups per column
+
+struct CoopBufs {
+  cpx<double>* A;
+  cpx<double>* x;  // after the matrix: V of even and odd steps, P of even and odd steps, tau
+  double* d;
+  double* e;
+  int n;
+  __device__ cpx<double>* V(int k) const { return x + (k & 1) * n; }
+  __device__ cpx<double>* P(int k) const { return x + (2 + (k & 1)) * n; }
+  __device__ cpx<double>* tau() const { return x + 4 * n; }
+};
+
+__device__ inline CoopBufs coop_bufs(const EigDesc& dsc) {
+  const int n = dsc.n;
+  CoopBufs b;
+  b.n = n;
+  b.A = reinterpret_cast<cpx<double>*>(dsc.work);
+  b.x = b.A + (long long)n * n;
+  b.d = reinterpret_cast<double*>(b.x + 5 * n);
+  b.e = b.d + n;
+  return b;
+}
+
+// the matrix takes part in a cooperative step k: a reduction step with a
+// trailing block wider than CO_TAIL
+__device__ inline bool coop_step_active(const EigDesc& dsc, int nlo, int k) {
+  return dsc.active && dsc.n > nlo && dsc.n <= EIG_NMAX && dsc.n - k - 1 > CO_TAIL;
+}
+
+struct alignas(16) CoopS {
+  alignas(16) cpx<double> v[EIG_NMAX];   // reflector of this step (index 0 = row k + 1)
+  alignas(16) cpx<double> vp[EIG_NMAX];  // the previous step's v and w (index 0 = row k)
+  alignas(16) cpx<double> wp[EIG_NMAX];
+  alignas(16) cpx<double> xk[EIG_NMAX];  // column k, rows k .. n-1, with the previous update
+  alignas(16) cpx<double> pp[NT];        // partial products (row group, column)
+  double red[2 * NW];
+};
+
+// Symmetrised copy of the input into the work array, spread over the G
+// workgroups of each matrix.
+__global__ __launch_bounds__(NT) void k_coop_load(const EigDesc* __restrict__ descs, int G, int nlo) {
+  const EigDesc& dsc = descs[blockIdx.x / G];
+  const int g = blockIdx.x % G;
+  if (!dsc.active || dsc.n <= nlo || dsc.n > EIG_NMAX) return;
+  const int n = dsc.n;
+  cpx<double>* __restrict__ A = reinterpret_cast<cpx<double>*>(dsc.work);
+  const cpx<double>* a = reinterpret_cast<const cpx<double>*>(dsc.a);
+  for (long long e = (long long)g * NT + threadIdx.x; e < (long long)n * n; e += (long long)G * NT) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (dsc.upper) {
+      const cpx<double> x = i <= j ? a[(long long)i * dsc.lda + j] : a[(long long)j * dsc.lda + i];
+      A[e] = i < j ? x : i > j ? cconj(x) : mk(x.re, 0.0);
+    } else {
+      const cpx<double> x = a[(long long)i * dsc.lda + j], y = a[(long long)j * dsc.lda + i];
+      A[e] = mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+    }
+  }
+}
+
+// The previous step's w = tau p - (|tau|^2 / 2)(v^H p) v into S.wp, its v
+// into S.vp (m1 entries from row k); returns false if that step had no
+// reflector (tau = 0).
+__device__ bool coop_prev_update(const CoopBufs& b, int k, int m1, CoopS& S, int& par) {
+  const int tid = threadIdx.x;
+  const cpx<double> tp = b.tau()[k - 1];
+  if (tp.re == 0.0 && tp.im == 0.0) return false;
+  const cpx<double>* vprev = b.V(k - 1);
+  const cpx<double>* pprev = b.P(k - 1);
+  double gsum = 0;
+  for (int i = tid; i < m1; i += NT) {
+    const cpx<double> v = vprev[i], p = pprev[i];
+    S.vp[i] = v;
+    S.wp[i] = p;
+    gsum += v.re * p.re + v.im * p.im;
+  }
+  gsum = block_sum(gsum, S.red, par);
+  const double cc = 0.5 * cabs2(tp) * gsum;
+  for (int i = tid; i < m1; i += NT) S.wp[i] = tp * S.wp[i] - cc * S.vp[i];
+  __syncthreads();
+  return true;
+}
+
+// This workgroup's columns of the trailing block [c0, n)^2: the pending
+// update (S.vp, S.wp; index 0 = row `base`) applied in place and, if `act`,
+// p_c = sum_i conj(A[i][c]) v[i - c0] (= (A v)_c) written to P[c - c0].
+__device__ void coop_pass(cpx<double>* __restrict__ A, int n, int c0, int base, bool pend, bool act, CoopS& S,
+                          int g, int G, cpx<double>* __restrict__ P) {
+  if (!pend && !act) return;
+  const int m = n - c0;
+  const int jc = c0 / CO_CW;                        // chunk holding column c0
+  const int j0 = jc + ((g - jc % G) % G + G) % G;   // this workgroup's first chunk from there
+  if (CO_CW * j0 >= n) return;                      // uniform over the workgroup
+  const int nch = ((n - 1) / CO_CW - j0) / G + 1;   // its chunks j0, j0 + G, ... below n
+  const int off = c0 > CO_CW * j0 ? c0 - CO_CW * j0 : 0;
+  const int W = CO_CW * nch - off;                  // its columns from c0 on (some past n)
+  int nq = NT / W;
+  nq = nq < 1 ? 1 : (nq > CO_NQ ? CO_NQ : nq);
+  const int rows_per = (m + nq - 1) / nq;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < W * nq; t += NT) {
+    const int cl = t % W, q = t / W;
+    const int u = cl + off;
+    const int c = CO_CW * (j0 + (u / CO_CW) * G) + u % CO_CW;
+    double ar = 0, ai = 0;
+    if (c < n) {
+      const cpx<double> wpc = pend ? cconj(S.wp[c - base]) : mk(0.0, 0.0);
+      const cpx<double> vpc = pend ? cconj(S.vp[c - base]) : mk(0.0, 0.0);
+      const int i0 = c0 + q * rows_per, i1 = min(n, i0 + rows_per);
+      int i = i0;
+      for (; i + UB <= i1; i += UB) {
+        cpx<double> a[UB];
+#pragma unroll
+        for (int x = 0; x < UB; ++x) a[x] = A[(long long)(i + x) * n + c];
+        if (pend) {
+#pragma unroll
+          for (int x = 0; x < UB; ++x) {
+            a[x] = sub2prod(a[x], S.vp[i + x - base], wpc, S.wp[i + x - base], vpc);
+            A[(long long)(i + x) * n + c] = a[x];
+          }
+        }
+        if (act) {
+#pragma unroll
+          for (int x = 0; x < UB; ++x) dotacc(ar, ai, a[x], S.v[i + x - c0]);
+        }
+      }
+      for (; i < i1; ++i) {
+        cpx<double> a = A[(long long)i * n + c];
+        if (pend) {
+          a = sub2prod(a, S.vp[i - base], wpc, S.wp[i - base], vpc);
+          A[(long long)i * n + c] = a;
+        }
+        if (act) dotacc(ar, ai, a, S.v[i - c0]);
+      }
+      if (act && nq == 1) P[c - c0] = mk(ar, ai);
+    }
+    if (nq > 1) S.pp[q * W + cl] = mk(ar, ai);  // nq > 1: W nq <= NT
+  }
+  if (act && nq > 1) {
+    __syncthreads();
+    for (int cl = tid; cl < W; cl += NT) {
+      const int u = cl + off;
+      const int c = CO_CW * (j0 + (u / CO_CW) * G) + u % CO_CW;
+      if (c >= n) continue;
+      cpx<double> x = S.pp[cl];
+      for (int q = 1; q < nq; ++q) x = x + S.pp[q * W + cl];
+      P[c - c0] = x;
+    }
+  }
+}
+
+// Step k of the shared reduction for every matrix whose trailing block after
+// this step is still wider than CO_TAIL.
+__global__ __launch_bounds__(NT) void k_coop_step(const EigDesc* __restrict__ descs, int G, int nlo, int k) {
+  __shared__ CoopS S;
+  const EigDesc& dsc = descs[blockIdx.x / G];
+  const int g = blockIdx.x % G;
+  if (!coop_step_active(dsc, nlo, k)) return;
+  const int n = dsc.n, tid = threadIdx.x;
+  int par = 0;
+  const CoopBufs b = coop_bufs(dsc);
+  cpx<double>* __restrict__ A = b.A;
+  const int m = n - k - 1, c0 = k + 1;
+  // 1. the update of step k - 1 (v from row k, w); its reflector goes to
+  // column k - 1 for the back-transformation (no workgroup reads that column
+  // in this step)
+  const bool pend = k > 0 && coop_prev_update(b, k, m + 1, S, par);
+  if (pend && g == 0)
+    for (int i = tid; i <= m; i += NT) A[(long long)(k + i) * n + (k - 1)] = S.vp[i];
+  // 2. column k with that update, and this step's reflector (every workgroup
+  // alike; workgroup 0 records d, e, tau and v)
+  for (int i = tid; i <= m; i += NT) {
+    cpx<double> x = A[(long long)(k + i) * n + k];
+    if (pend) x = sub2prod(x, S.vp[i], cconj(S.wp[0]), S.wp[i], cconj(S.vp[0]));
+    S.xk[i] = x;
+  }
+  __syncthreads();
+  double xn = 0;
+  for (int i = 2 + tid; i <= m; i += NT) xn += cabs2(S.xk[i]);
+  xn = block_sum(xn, S.red, par);
+  const cpx<double> alpha = S.xk[1];
+  const bool act = !(xn == 0.0 && alpha.im == 0.0);
+  cpx<double> tau = mk(0.0, 0.0), sc = mk(0.0, 0.0);
+  double ek = alpha.re;
+  if (act) {
+    const double nrm = sqrt(cabs2(alpha) + xn);
+    const double beta = alpha.re >= 0 ? -nrm : nrm;
+    tau = mk((beta - alpha.re) / beta, -alpha.im / beta);
+    const cpx<double> den = mk(alpha.re - beta, alpha.im);  // sc = 1 / (alpha - beta)
+    const double dd = cabs2(den);
+    sc = mk(den.re / dd, -den.im / dd);
+    ek = beta;
+  }
+  if (g == 0 && tid == 0) {
+    b.d[k] = S.xk[0].re;
+    b.e[k] = ek;
+    b.tau()[k] = tau;
+  }
+  if (act) {
+    cpx<double>* __restrict__ vout = b.V(k);
+    for (int i = tid; i < m; i += NT) {
+      const cpx<double> v = (i == 0) ? mk(1.0, 0.0) : S.xk[1 + i] * sc;
+      S.v[i] = v;
+      if (g == 0) vout[i] = v;
+    }
+  }
+  __syncthreads();
+  // 3. this workgroup's columns of the trailing block
+  coop_pass(A, n, c0, k, pend, act, S, g, G, b.P(k));
+}
+
+// One workgroup per matrix: the steps from the first one with a trailing
+// block of at most CO_TAIL (onecol_steps), then the tridiagonal eigenpairs
+// and the back-transformation, as in heev_core.  Matrices with n in
+// (nmin, NMAX].
+template <int NMAX>
+__global__ __launch_bounds__(NT) void k_coop_tail(const EigDesc* __restrict__ descs, int* __restrict__ status,
+                                                  int nlo, int nmin) {
+  __shared__ SharedG<NMAX> S;
+  const EigDesc& dsc = descs[blockIdx.x];
+  const int n = dsc.n;
+  if (!dsc.active || n <= nlo || n <= nmin || n > NMAX) return;
+  const int tid = threadIdx.x;
+  int par = 0;
+  const CoopBufs b = coop_bufs(dsc);
+  cpx<double>* __restrict__ A = b.A;
+  const int ks = n - 1 > CO_TAIL ? n - 1 - CO_TAIL : 0;  // first step left to this workgroup
+  for (int i = tid; i < ks; i += NT) {
+    S.d[i] = b.d[i];
+    S.e[i] = b.e[i];
+    S.tau[i] = b.tau()[i];
+  }
+  // the pending update of step ks - 1 (as coop_prev_update, into S.vp, S.wp)
+  bool pend = false;
+  if (ks > 0) {
+    const cpx<double> tp = b.tau()[ks - 1];
+    pend = !(tp.re == 0.0 && tp.im == 0.0);
+    if (pend) {
+      const int m1 = n - ks;
+      const cpx<double>* vprev = b.V(ks - 1);
+      const cpx<double>* pprev = b.P(ks - 1);
+      double gsum = 0;
+      for (int i = tid; i < m1; i += NT) {
+        const cpx<double> v = vprev[i], p = pprev[i];
+        S.vp[i] = v;
+        S.wp[i] = p;
+        gsum += v.re * p.re + v.im * p.im;
+      }
+      gsum = block_sum(gsum, S.red, par);
+      const double cc = 0.5 * cabs2(tp) * gsum;
+      for (int i = tid; i < m1; i += NT) {
+        S.wp[i] = tp * S.wp[i] - cc * S.vp[i];
+        A[(long long)(ks + i) * n + (ks - 1)] = S.vp[i];  // reflector ks - 1, for the back-transformation
+      }
+    }
+  }
+  double tr = 0;  // trace of the input (its diagonal is real after symmetrisation)
+  const cpx<double>* a = reinterpret_cast<const cpx<double>*>(dsc.a);
+  for (int i = tid; i < n; i += NT) tr += a[(long long)i * dsc.lda + i].re;
+  tr = block_sum(tr, S.red, par);
+  __syncthreads();
+  onecol_steps(A, n, ks, pend, S, par);
+  if (tid == 0) S.d[n - 1] = A[(long long)(n - 1) * n + n - 1].re;
+  for (int i = tid; i + 1 < n; i += NT) S.e2[i] = S.e[i] * S.e[i];
+  __syncthreads();
+  const int kz = eig_tail<NT>(dsc, n, tr, S, par);
+  if (kz > 0) {
+    if (NMAX <= 512 && n <= 256 && kz <= 64) back_transform_reg(dsc, A, n, kz, S);
+    else back_transform(dsc, A, n, kz, S);
+  }
+  if (tid == 0 && status) status[blockIdx.x] = 1;
+}
+
 namespace {
 // n in (128, 256] through the band path.  Off by default: every stage of it
 // is a long chain of small dependent steps (about 2,200 chase steps and as
 // many reflector applications per n = 256 matrix, each ~1 us), which costs
 // more than the one-stage kernel's extra memory traffic on this hardware.
 bool g_band = false;
+// the shared reduction for launches of at most CO_MAX_ITEMS matrices
+bool g_coop = true;
+constexpr int CO_MAX_ITEMS = 32;
+constexpr int CO_GRID = 512;  // workgroups per step launch (two per CU fit: 72 KB of LDS each)
+constexpr int CO_GMAX = 64;   // workgroups per matrix
 }  // namespace
 void set_eig_band(bool on) { g_band = on; }
 bool eig_band() { return g_band; }
+void set_eig_coop(bool on) { g_coop = on; }
+bool eig_coop() { return g_coop; }
 
 hipError_t set_eig_residual_bound(double rtol) {
   return hipMemcpyToSymbol(HIP_SYMBOL(g_eig_rtol), &rtol, sizeof(double));
@@ -2045,6 +2354,22 @@ void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hi
     tok = prof_begin(PC_EIG_BAND, s);
     hipLaunchKernelGGL(k_heev_band, dim3(nitems), dim3(NT), 0, s, d_descs, d_status);
     prof_end_eig(tok, PC_EIG_BAND, d_descs, nitems, REG_NMAX + 1, BS_NMAX, s);
+  }
+  if (maxn > nlo && g_coop && nitems <= CO_MAX_ITEMS) {
+    // few matrices: G workgroups share each one during the reduction
+    const int chunks = (maxn + CO_CW - 1) / CO_CW;
+    int G = CO_GRID / nitems;
+    G = std::min(G, std::min(chunks, CO_GMAX));
+    G = std::max(G, 1);
+    tok = prof_begin(PC_EIG_GLOBAL, s);
+    hipLaunchKernelGGL(k_coop_load, dim3(nitems * G), dim3(NT), 0, s, d_descs, G, nlo);
+    for (int k = 0; maxn - k - 1 > CO_TAIL; ++k)
+      hipLaunchKernelGGL(k_coop_step, dim3(nitems * G), dim3(NT), 0, s, d_descs, G, nlo, k);
+    hipLaunchKernelGGL(k_coop_tail<512>, dim3(nitems), dim3(NT), 0, s, d_descs, d_status, nlo, 0);
+    if (maxn > 512)
+      hipLaunchKernelGGL(k_coop_tail<EIG_NMAX>, dim3(nitems), dim3(NT), 0, s, d_descs, d_status, nlo, 512);
+    prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, nlo + 1, EIG_NMAX, s);
+    return;
   }
   if (maxn > nlo) {
     tok = prof_begin(PC_EIG_GLOBAL, s);

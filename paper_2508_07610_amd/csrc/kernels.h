@@ -62,6 +62,10 @@ void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hi
 // panel reduction (the default); process-wide.
 void set_eig_band(bool on);
 bool eig_band();
+// launches of at most 32 matrices with n > 128: several workgroups share each
+// matrix during the Householder reduction (default on)
+void set_eig_coop(bool on);
+bool eig_coop();
 // Overrides the residual bound on the current device (0 restores 1e-9).
 hipError_t set_eig_residual_bound(double rtol);
 

@@ -567,6 +567,8 @@ def _testing_lib():
         L.mpdo_test_gemm_form.restype = ctypes.c_int
         L.mpdo_test_eig_band.argtypes = [i32, ctypes.POINTER(i32)]
         L.mpdo_test_eig_band.restype = ctypes.c_int
+        L.mpdo_test_eig_coop.argtypes = [i32, ctypes.POINTER(i32)]
+        L.mpdo_test_eig_coop.restype = ctypes.c_int
         L._testing_sig = True
     return L
 
@@ -612,6 +614,16 @@ def eig_band(on: bool) -> bool:
     returns the previous setting."""
     prev = ctypes.c_int32()
     check(_testing_lib().mpdo_test_eig_band(1 if on else 0, ctypes.byref(prev)))
+    return bool(prev.value)
+
+
+def eig_coop(on: bool) -> bool:
+    """Share each matrix of launches with at most 32 eigenproblems of n > 128
+    among several workgroups during the reduction to tridiagonal form (True,
+    the default) or keep one workgroup per matrix (False); returns the
+    previous setting."""
+    prev = ctypes.c_int32()
+    check(_testing_lib().mpdo_test_eig_coop(1 if on else 0, ctypes.byref(prev)))
     return bool(prev.value)
 
 

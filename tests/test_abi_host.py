@@ -137,6 +137,18 @@ def test_test_entry_points_validate_sizes():
                             M._dptr(a), 64, 2) == M.EINVAL
 
 
+def test_eigensolver_switches_validate_and_restore():
+    """The eigensolver routing switches take 0 or 1, report the previous
+    setting and touch no device."""
+    L = M._testing_lib()
+    prev = ctypes.c_int32(-1)
+    assert L.mpdo_test_eig_coop(2, ctypes.byref(prev)) == M.EINVAL
+    assert L.mpdo_test_eig_coop(0, ctypes.byref(prev)) == M.OK and prev.value == 1  # on by default
+    assert L.mpdo_test_eig_coop(1, ctypes.byref(prev)) == M.OK and prev.value == 0
+    assert M.eig_coop(True) is True
+    assert L.mpdo_test_eig_band(-1, None) == M.EINVAL
+
+
 def test_profile_read_rejects_unknown_class():
     L = M.lib()
     assert L.mpdo_profile_read(-1, None, None, None, None) == M.EINVAL

@@ -237,10 +237,12 @@ def test_eigh_band_and_panel_paths(band, n, kvec):
                         1e-3 * (1 + 1e-9 * np.arange(6)), np.zeros(n - n // 2 - 8)])
     A = (Q * d) @ Q.conj().T
     prev = M.eig_band(band)
+    prev_coop = M.eig_coop(False)  # one workgroup per matrix: the panel kernel itself
     try:
         ev, V, tr = M.test_eigh(A, kvec)
     finally:
         M.eig_band(prev)
+        M.eig_coop(prev_coop)
     ref = np.sort(np.linalg.eigvalsh(A))[::-1]
     kb = min(n, kvec + 1)
     assert float(np.abs(ev[:kb] - ref[:kb]).max()) <= 1e-13 * 3
@@ -263,3 +265,40 @@ def test_gemm_rate_entry_point():
         with pytest.raises(M.MPDOError) as e:
             M.test_gemm_rate(*bad)
         assert e.value.status == M.EINVAL
+
+
+@pytest.mark.parametrize("n,kvec", [(129, 129), (130, 8), (200, 64), (257, 257), (258, 65), (300, 100), (513, 64),
+                                    (700, 17), (1024, 16), (1024, 1024)])
+def test_eigh_shared_reduction(n, kvec):
+    """Lone eigenproblems with n > 128 go through the reduction shared by
+    several workgroups (one launch per Householder step while the trailing
+    block is wider than 128, one workgroup for the rest): eigenvalues to
+    1e-13, residuals to 1e-12 of the largest eigenvalue, orthonormal vectors
+    to 2e-14 max(n, 500) (inverse iteration: eps ||A|| / gap, and n / 2
+    eigenvalues in [0, 1] leave gaps of about 2 / n), with the degenerate
+    pair, the cluster and the null space of a bond Gram; the one-workgroup
+    kernels give the same to rounding."""
+    require_gpu()
+    rng = np.random.default_rng(3 * n + kvec)
+    Q, _ = np.linalg.qr(_rand((n, n), rng))
+    d = np.concatenate([[3.0, 3.0], np.sort(rng.uniform(0.0, 1.0, n // 2))[::-1],
+                        1e-3 * (1 + 1e-9 * np.arange(6)), np.zeros(n - n // 2 - 8)])
+    A = (Q * d) @ Q.conj().T
+    ref = np.sort(np.linalg.eigvalsh(A))[::-1]
+    kb = min(n, kvec + 1)
+    kz = int(np.sum(ref[:kvec] > 1e-13 * ref[0]))
+    out = {}
+    for coop in (True, False):
+        prev = M.eig_coop(coop)
+        try:
+            out[coop] = M.test_eigh(A, kvec)
+        finally:
+            M.eig_coop(prev)
+        ev, V, tr = out[coop]
+        assert float(np.abs(ev[:kb] - ref[:kb]).max()) <= 1e-13 * 3, coop
+        assert abs(tr - np.trace(A).real) < 1e-12 * n
+        Vk = V[:, :kz]
+        assert float(np.abs(Vk.conj().T @ Vk - np.eye(kz)).max()) < 2e-14 * max(n, 500), coop
+        assert float(np.abs(A @ Vk - Vk * ev[:kz]).max()) < 1e-12 * 3, coop
+        assert float(np.abs(V[:, kz:kvec]).max(initial=0.0)) == 0.0
+    assert float(np.abs(out[True][0] - out[False][0]).max()) <= 1e-13 * 3
