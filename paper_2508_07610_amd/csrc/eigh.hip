@@ -548,6 +548,7 @@ __device__ int eig_tail(const EigDesc& dsc, int n, double tr, SH& S, int& par) {
 // W = V^H Z, W <- T W, Z <- Z - V W, so Z is read twice and written once per
 // block instead of once per reflector.
 constexpr int BTB = 8;
+constexpr int BT_NQ = 64;  // most row chunks per column in the back-transformation
 constexpr int TRB = 8;  // tridiagonalisation panel width
 template <class SH>
 __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict__ A, int n, int kz, SH& S) {
@@ -559,7 +560,9 @@ __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict
   constexpr int LV = sizeof(S.pf) / sizeof(S.pf[0]);
   cpx<double>* __restrict__ Vb = n * BTB <= LV ? S.pf : Vg;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nq = kz < NT ? NT / kz : 1;          // row chunks per column
+  // row chunks per column (at most BT_NQ: their partial sums are added up
+  // by one thread per reflector and column)
+  const int nq = kz < NT ? (NT / kz < BT_NQ ? NT / kz : BT_NQ) : 1;
   cpx<double>* __restrict__ Wt = part + (long long)nq * BTB * kz;                       // BTB x kz
   cpx<double>* G = S.v;                          // BTB x BTB (LDS, free here)
   cpx<double>* T = S.vp;
@@ -632,15 +635,28 @@ __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict
       for (int j = 0; j < BTB; ++j) part[((long long)q * BTB + j) * kz + c] = acc[j];
     }
     __syncthreads();
-    // Wt = T (sum of the partials), one thread per column
+    // W = V^H Z: the partials added up (in chunk order), one thread per
+    // reflector and column, loads issued eight chunks ahead; into Wt
+    for (int u = tid; u < BTB * kz; u += NT) {
+      const int j = u / kz, c = u % kz;
+      cpx<double> x = mk(0.0, 0.0);
+      int q = 0;
+      for (; q + 8 <= nq; q += 8) {
+        cpx<double> p8[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) p8[r] = part[((long long)(q + r) * BTB + j) * kz + c];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x = x + p8[r];
+      }
+      for (; q < nq; ++q) x = x + part[((long long)q * BTB + j) * kz + c];
+      Wt[(long long)j * kz + c] = x;
+    }
+    __syncthreads();
+    // Wt = T W, one thread per column (in place: the column is read first)
     for (int c = tid; c < kz; c += NT) {
       cpx<double> w[BTB];
 #pragma unroll
-      for (int j = 0; j < BTB; ++j) {
-        cpx<double> x = mk(0.0, 0.0);
-        for (int q = 0; q < nq; ++q) x = x + part[((long long)q * BTB + j) * kz + c];
-        w[j] = x;
-      }
+      for (int j = 0; j < BTB; ++j) w[j] = Wt[(long long)j * kz + c];
 #pragma unroll
       for (int i = 0; i < BTB; ++i) {
         cpx<double> x = mk(0.0, 0.0);
