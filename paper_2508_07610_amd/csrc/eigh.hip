@@ -551,10 +551,12 @@ constexpr int BTB = 8;
 constexpr int BT_NQ = 64;  // most row chunks per column in the back-transformation
 constexpr int TRB = 8;  // tridiagonalisation panel width
 template <class SH>
-__device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict__ A, int n, int kz, SH& S) {
-  cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs);
-  // scratch after the matrix: free once the inverse iteration is done
-  cpx<double>* const Vg = reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n);  // n x BTB
+__device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict__ A, int n, int kz, SH& S,
+                               int cz0 = 0, cpx<double>* scratch = nullptr) {
+  // columns cz0 .. cz0 + kz - 1 of the eigenvector block
+  cpx<double>* __restrict__ Z = reinterpret_cast<cpx<double>*>(dsc.evecs) + cz0;
+  // scratch (default: after the matrix, free once the inverse iteration is done)
+  cpx<double>* const Vg = scratch ? scratch : reinterpret_cast<cpx<double>*>(dsc.work + 2LL * n * n);  // n x BTB
   cpx<double>* __restrict__ part = Vg + (long long)n * BTB;                        // nq x BTB x kz
   // the block of reflectors in LDS when the panel factors' array holds it
   constexpr int LV = sizeof(S.pf) / sizeof(S.pf[0]);
@@ -623,7 +625,21 @@ __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict
 #pragma unroll
       for (int j = 0; j < BTB; ++j) acc[j] = mk(0.0, 0.0);
       const int i1 = min(m, (q + 1) * rows_per);
-      for (int i = q * rows_per; i < i1; ++i) {
+      int i = q * rows_per;
+      for (; i + UB <= i1; i += UB) {  // the rows' loads issued together
+        cpx<double> zb[UB];
+#pragma unroll
+        for (int x = 0; x < UB; ++x) zb[x] = Z[(long long)(r0 + i + x) * n + c];
+#pragma unroll
+        for (int x = 0; x < UB; ++x) {
+#pragma unroll
+          for (int j = 0; j < BTB; ++j) {
+            const cpx<double> v = Vb[(long long)(i + x) * BTB + j], z = zb[x];
+            acc[j] = acc[j] + mk(v.re * z.re + v.im * z.im, v.re * z.im - v.im * z.re);  // conj(v) z
+          }
+        }
+      }
+      for (; i < i1; ++i) {
         const cpx<double> z = Z[(long long)(r0 + i) * n + c];
 #pragma unroll
         for (int j = 0; j < BTB; ++j) {
@@ -674,7 +690,20 @@ __device__ void back_transform(const EigDesc& dsc, const cpx<double>* __restrict
 #pragma unroll
       for (int j = 0; j < BTB; ++j) w[j] = Wt[(long long)j * kz + c];
       const int i1 = min(m, (q + 1) * rows_per);
-      for (int i = q * rows_per; i < i1; ++i) {
+      int i = q * rows_per;
+      for (; i + UB <= i1; i += UB) {
+        cpx<double> zb[UB];
+#pragma unroll
+        for (int x = 0; x < UB; ++x) zb[x] = Z[(long long)(r0 + i + x) * n + c];
+#pragma unroll
+        for (int x = 0; x < UB; ++x) {
+          cpx<double> z = zb[x];
+#pragma unroll
+          for (int j = 0; j < BTB; ++j) z = z - Vb[(long long)(i + x) * BTB + j] * w[j];
+          Z[(long long)(r0 + i + x) * n + c] = z;
+        }
+      }
+      for (; i < i1; ++i) {
         cpx<double> z = Z[(long long)(r0 + i) * n + c];
 #pragma unroll
         for (int j = 0; j < BTB; ++j) z = z - Vb[(long long)i * BTB + j] * w[j];
@@ -2329,11 +2358,54 @@ __global__ __launch_bounds__(NT) void k_coop_tail(const EigDesc* __restrict__ de
   for (int i = tid; i + 1 < n; i += NT) S.e2[i] = S.e[i] * S.e[i];
   __syncthreads();
   const int kz = eig_tail<NT>(dsc, n, tr, S, par);
-  if (kz > 0) {
-    if (NMAX <= 512 && n <= 256 && kz <= 64) back_transform_reg(dsc, A, n, kz, S);
-    else back_transform(dsc, A, n, kz, S);
+  int kleft = kz;  // vectors left to k_coop_back
+  if (kz > 0 && NMAX <= 512 && n <= 256 && kz <= 64) {
+    back_transform_reg(dsc, A, n, kz, S);
+    kleft = 0;
   }
+  // hand-over to k_coop_back: tau on the diagonal of A (no longer read), the
+  // vector count in its last entry
+  for (int i = tid; i + 1 < n; i += NT) A[(long long)i * n + i] = S.tau[i];
+  if (tid == 0) A[(long long)(n - 1) * n + n - 1] = mk((double)kleft, 0.0);
   if (tid == 0 && status) status[blockIdx.x] = 1;
+}
+
+struct alignas(16) CoopBackS {
+  alignas(16) cpx<double> tau[EIG_NMAX];
+  alignas(16) cpx<double> v[BTB * BTB];   // G of a reflector block
+  alignas(16) cpx<double> vp[BTB * BTB];  // its T
+  alignas(16) cpx<double> pf[8 * 512];    // the reflector block when n <= 512
+};
+
+// One of Gb workgroups per matrix: the back-transformation z <- H_0 ... H_{n-2} z
+// of its share of the eigenvector columns (each column is independent), for
+// the matrices whose vectors k_coop_tail left (n in (nmin, NMAX]).  Each
+// workgroup's scratch (reflector block, partial sums) lies after the matrix.
+template <int NMAX>
+__global__ __launch_bounds__(NT) void k_coop_back(const EigDesc* __restrict__ descs, int Gb, int nlo, int nmin) {
+  __shared__ CoopBackS S;
+  const EigDesc& dsc = descs[blockIdx.x / Gb];
+  const int g = blockIdx.x % Gb, n = dsc.n, tid = threadIdx.x;
+  if (!dsc.active || n <= nlo || n <= nmin || n > NMAX) return;
+  cpx<double>* __restrict__ A = reinterpret_cast<cpx<double>*>(dsc.work);
+  const int kz = (int)A[(long long)(n - 1) * n + n - 1].re;
+  if (kz <= 0) return;
+  // scratch per workgroup (complex): reflector block n BTB, partial sums
+  // BTB max(NT, columns), the block product BTB columns; as many workgroups
+  // as the work array holds
+  const long long np = (n + 63) / 64 * 64;
+  const long long per = (long long)BTB * n + (long long)BTB * (NT > kz ? NT : kz) + (long long)BTB * kz;
+  const long long room = (7LL * n * np) / 2;  // complex entries after the matrix
+  int gb = (int)(room / per);
+  gb = gb < Gb ? gb : Gb;
+  gb = gb < kz ? gb : kz;
+  if (g >= gb) return;
+  const int cw = (kz + gb - 1) / gb, c0 = g * cw, c1 = min(kz, c0 + cw);
+  if (c0 >= c1) return;
+  for (int i = tid; i + 1 < n; i += NT) S.tau[i] = A[(long long)i * n + i];
+  __syncthreads();
+  cpx<double>* scratch = A + (long long)n * n + (long long)g * per;
+  back_transform(dsc, A, n, c1 - c0, S, c0, scratch);
 }
 
 namespace {
@@ -2346,7 +2418,8 @@ bool g_band = false;
 bool g_coop = true;
 constexpr int CO_MAX_ITEMS = 32;
 constexpr int CO_GRID = 512;  // workgroups per step launch (two per CU fit: 72 KB of LDS each)
-constexpr int CO_GMAX = 64;   // workgroups per matrix
+constexpr int CO_GMAX = 64;   // workgroups per matrix in the reduction
+constexpr int CO_BMAX = 16;   // workgroups per matrix in the back-transformation
 }  // namespace
 void set_eig_band(bool on) { g_band = on; }
 bool eig_band() { return g_band; }
@@ -2384,6 +2457,10 @@ void launch_eigh(const EigDesc* d_descs, int nitems, int maxn, int* d_status, hi
     hipLaunchKernelGGL(k_coop_tail<512>, dim3(nitems), dim3(NT), 0, s, d_descs, d_status, nlo, 0);
     if (maxn > 512)
       hipLaunchKernelGGL(k_coop_tail<EIG_NMAX>, dim3(nitems), dim3(NT), 0, s, d_descs, d_status, nlo, 512);
+    const int Gb = std::max(1, std::min(CO_BMAX, CO_GRID / nitems));
+    hipLaunchKernelGGL(k_coop_back<512>, dim3(nitems * Gb), dim3(NT), 0, s, d_descs, Gb, nlo, 0);
+    if (maxn > 512)
+      hipLaunchKernelGGL(k_coop_back<EIG_NMAX>, dim3(nitems * Gb), dim3(NT), 0, s, d_descs, Gb, nlo, 512);
     prof_end_eig(tok, PC_EIG_GLOBAL, d_descs, nitems, nlo + 1, EIG_NMAX, s);
     return;
   }
