@@ -2093,6 +2093,7 @@ __global__ __launch_bounds__(NT) void k_heev_big(const EigDesc* __restrict__ des
 constexpr int CO_CW = 16;     // columns per ownership chunk
 constexpr int CO_TAIL = 128;  // steps left to one workgroup (trailing block <= CO_TAIL)
 constexpr int CO_NQ = 32;     // most row groups per column
+constexpr int CO_UB = 16;     // rows loaded together per thread in a step
 
 struct CoopBufs {
   cpx<double>* A;
@@ -2202,6 +2203,22 @@ __device__ void coop_pass(cpx<double>* __restrict__ A, int n, int c0, int base, 
       const cpx<double> vpc = pend ? cconj(S.vp[c - base]) : mk(0.0, 0.0);
       const int i0 = c0 + q * rows_per, i1 = min(n, i0 + rows_per);
       int i = i0;
+      for (; i + CO_UB <= i1; i += CO_UB) {  // a thread's rows in as few load batches as fit
+        cpx<double> a[CO_UB];
+#pragma unroll
+        for (int x = 0; x < CO_UB; ++x) a[x] = A[(long long)(i + x) * n + c];
+        if (pend) {
+#pragma unroll
+          for (int x = 0; x < CO_UB; ++x) {
+            a[x] = sub2prod(a[x], S.vp[i + x - base], wpc, S.wp[i + x - base], vpc);
+            A[(long long)(i + x) * n + c] = a[x];
+          }
+        }
+        if (act) {
+#pragma unroll
+          for (int x = 0; x < CO_UB; ++x) dotacc(ar, ai, a[x], S.v[i + x - c0]);
+        }
+      }
       for (; i + UB <= i1; i += UB) {
         cpx<double> a[UB];
 #pragma unroll
@@ -2370,11 +2387,11 @@ __global__ __launch_bounds__(NT) void k_coop_tail(const EigDesc* __restrict__ de
   if (tid == 0 && status) status[blockIdx.x] = 1;
 }
 
-struct alignas(16) CoopBackS {
-  alignas(16) cpx<double> tau[EIG_NMAX];
-  alignas(16) cpx<double> v[BTB * BTB];   // G of a reflector block
-  alignas(16) cpx<double> vp[BTB * BTB];  // its T
-  alignas(16) cpx<double> pf[8 * 512];    // the reflector block when n <= 512
+template <int NMAX> struct alignas(16) CoopBackS {
+  alignas(16) cpx<double> tau[NMAX];
+  alignas(16) cpx<double> v[BTB * BTB];    // G of a reflector block
+  alignas(16) cpx<double> vp[BTB * BTB];   // its T
+  alignas(16) cpx<double> pf[BTB * NMAX];  // the reflector block (145 KB of LDS in all at NMAX = 1024)
 };
 
 // One of Gb workgroups per matrix: the back-transformation z <- H_0 ... H_{n-2} z
@@ -2383,7 +2400,7 @@ struct alignas(16) CoopBackS {
 // workgroup's scratch (reflector block, partial sums) lies after the matrix.
 template <int NMAX>
 __global__ __launch_bounds__(NT) void k_coop_back(const EigDesc* __restrict__ descs, int Gb, int nlo, int nmin) {
-  __shared__ CoopBackS S;
+  __shared__ CoopBackS<NMAX> S;
   const EigDesc& dsc = descs[blockIdx.x / Gb];
   const int g = blockIdx.x % Gb, n = dsc.n, tid = threadIdx.x;
   if (!dsc.active || n <= nlo || n <= nmin || n > NMAX) return;
@@ -2417,7 +2434,7 @@ bool g_band = false;
 // the shared reduction for launches of at most CO_MAX_ITEMS matrices
 bool g_coop = true;
 constexpr int CO_MAX_ITEMS = 32;
-constexpr int CO_GRID = 512;  // workgroups per step launch (two per CU fit: 72 KB of LDS each)
+constexpr int CO_GRID = 256;  // workgroups per step launch (one per CU: 134 VGPRs, 72 KB of LDS)
 constexpr int CO_GMAX = 64;   // workgroups per matrix in the reduction
 constexpr int CO_BMAX = 16;   // workgroups per matrix in the back-transformation
 }  // namespace
