@@ -67,10 +67,14 @@ def test_headline_per_gate_matches_oracle(prec, ci):
     assert s["failures"] == 0 and abs(s["discarded"] - disc) < 1e-15
 
 
+@pytest.mark.parametrize("coop", [True, False])
 @pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
-def test_headline_batched_matches_oracle(prec):
+def test_headline_batched_matches_oracle(prec, coop):
     """Both noise strengths in one graph-captured batch run (the channels of
-    the second program renumbered after the first's)."""
+    the second program renumbered after the first's).  With two instances
+    the n = 256 bond Grams go through the eigensolver that shares each
+    matrix among several workgroups (coop); with it switched off, through
+    the one-workgroup kernel that the 64-instance benchmark step uses."""
     require_gpu()
     import torch
     progs, chans = [], []
@@ -85,7 +89,11 @@ def test_headline_batched_matches_oracle(prec):
     ops = [np.stack([W.pauli_ops(s) for s in W.zz_strings(N)] + _ghz_terms(N)) for _ in progs]
     params = torch.tensor(np.stack([W.ansatz_params(N, DEPTH, c["param_tag"]) for c in REF["cases"]]),
                           dtype=torch.float64, device="cuda")
-    out = M.batch_run(progs, params, chans, ops, prec=prec, use_graph=True, **KW).cpu().numpy()
+    prev = M.eig_coop(coop)
+    try:
+        out = M.batch_run(progs, params, chans, ops, prec=prec, use_graph=True, **KW).cpu().numpy()
+    finally:
+        M.eig_coop(prev)
     tol = TOL[prec]
     k = len(ops[0])
     for b, case in enumerate(REF["cases"]):
@@ -93,5 +101,5 @@ def test_headline_batched_matches_oracle(prec):
         zz = got[: N - 1].real
         f = 0.5 * (got[N - 1].real + got[N].real + 2 * got[N + 1].real)
         err = max(float(np.abs(zz - np.array(case["zz"])).max()), abs(f - case["ghz_fidelity"]))
-        print(f"batched noise x{case['noise_scale']} prec {prec}: max |GPU - oracle| = {err:.3e}")
+        print(f"batched noise x{case['noise_scale']} prec {prec} coop {coop}: max |GPU - oracle| = {err:.3e}")
         assert err < tol
