@@ -54,6 +54,8 @@ def parse():
                     help="skip the mixed GHZ-ansatz / QAOA MaxCut batch leg")
     ap.add_argument("--no-sampling", action="store_true", help="skip the bitstring sampling leg")
     ap.add_argument("--no-gemm-tiles", action="store_true", help="skip the full-tile GEMM throughput leg")
+    ap.add_argument("--no-eig-lone", action="store_true",
+                    help="skip the lone-eigenproblem leg (shared reduction against one workgroup per matrix)")
     ap.add_argument("--no-noise-models", action="store_true", help="skip the standard noise model comparison")
     ap.add_argument("--no-truncation-study", action="store_true", help="skip the truncation study leg")
     ap.add_argument("--no-mitigation", action="store_true", help="skip the error-mitigation leg")
@@ -429,6 +431,38 @@ def gemm_tiles_leg():
     return out
 
 
+def eig_lone_leg():
+    """Lone Hermitian eigenproblems of the crosstalk workload's sizes (the
+    three-site update's N / E3 Grams n = 256 with all vectors, its bond Grams
+    n = 512 with chi = 128 vectors, its Gamma n = 1024 with kappa = 16), one
+    per launch as the per-gate path issues them: the library's eigensolver
+    window (HIP events of the in-library profiler) with the reduction shared
+    by several workgroups per matrix (the default for launches of at most 32
+    matrices) and with one workgroup per matrix."""
+    import numpy as np
+    from paper_2508_07610_amd import mpdo as M
+    rng = np.random.default_rng(7617)
+    out = {}
+    for n, kvec in ((256, 256), (512, 128), (1024, 16)):
+        X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        A = X @ X.conj().T
+        rec = {}
+        for coop in (True, False):
+            prev = M.eig_coop(coop)
+            try:
+                for _ in range(2):  # the second call is timed
+                    M.profile_enable(True)
+                    M.test_eigh(A, kvec)
+                    r = M.profile_read(M.PROF_EIG_GLOBAL)
+                    M.profile_enable(False)
+            finally:
+                M.eig_coop(prev)
+            rec["shared_ms" if coop else "one_workgroup_ms"] = r["ms"]
+        rec["speedup"] = rec["one_workgroup_ms"] / rec["shared_ms"]
+        out[f"n={n},vectors={kvec}"] = rec
+    return out
+
+
 def sampling_leg(shots=4096):
     """Computational-basis sampling of the benchmark state (parameter point 0
     of the noisy RY/CZ ansatz, n=16, depth 10, chi=64, kappa=8, c128): shots
@@ -727,6 +761,7 @@ def main():
         "time_to_fidelity": ttf,
         "maxcut_batch": None if a.no_maxcut else maxcut_leg(),
         "gemm_full_tiles": None if a.no_gemm_tiles else gemm_tiles_leg(),
+        "eig_lone": None if a.no_eig_lone else eig_lone_leg(),
         "sampling": None if a.no_sampling else sampling_leg(),
         "noise_models": None if a.no_noise_models else noise_models_leg(),
         "truncation_study": None if a.no_truncation_study else truncation_study_leg(),
