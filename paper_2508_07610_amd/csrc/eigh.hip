@@ -1,5 +1,7 @@
 // Hermitian eigensolver for the truncations (FP64), one workgroup per matrix
-// (512 threads; 64 for n <= 32):
+// (512 threads; 64 for n <= 32), except in launches of at most 32 matrices
+// with n > 128, which share each matrix among several workgroups (the k_coop_*
+// kernels further down):
 //
 //  1. Householder reduction to real symmetric tridiagonal form
 //     T = Q^H A Q,  Q = H_0 H_1 ... H_{n-2},  H_k = I - tau_k v_k v_k^H,
@@ -2086,7 +2088,8 @@ __global__ __launch_bounds__(NT) void k_heev_big(const EigDesc* __restrict__ des
 // One kernel launch per step (the launch boundary is the only barrier
 // between workgroups), as long as the trailing block is wider than
 // CO_TAIL; one workgroup per matrix then finishes the last CO_TAIL steps
-// (onecol_steps), the eigenvalues, the vectors and the back-transformation.
+// (onecol_steps), the eigenvalues and the eigenvectors of T, and up to
+// CO_BMAX workgroups per matrix back-transform the vectors, split by columns.
 // Per matrix, after the n x n copy in the work array: v of the last two steps
 // (2 n), their p (2 n), tau (n) complex; d and e (n each).
 // ---------------------------------------------------------------------------
