@@ -218,10 +218,8 @@ def pretrain(net, X: np.ndarray, Y: np.ndarray, steps: int, batch: int = 512, lr
     yd = torch.tensor(Y[tr], device="cuda")
     b = min(batch, net.max_batch, len(tr))
     t0 = time.perf_counter()
-    for it in range(steps):
-        idx = torch.randint(0, xd.shape[0], (b,), device="cuda")
-        net.train_step(xd[idx].contiguous(), yd[idx].contiguous(),
-                       lr * 0.5 * (1 + math.cos(math.pi * it / steps)), want_loss=False)
+    # one library call: minibatches drawn on the device, cosine decay of lr
+    net.fit(xd, yd, steps, b, lr, cosine=True, seed=int(rng.integers(1 << 62)))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     xv = torch.tensor(X[va], device="cuda")
