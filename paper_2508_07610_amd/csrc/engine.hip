@@ -387,9 +387,14 @@ void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up, bool f
   Ctx1<T>* dctx = reinterpret_cast<Ctx1<T>*>(dv + uCtx);
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   if (tpo) tp = *tpo;
+  // 2 kappa <= 32: the Gram on the vector units
+  const bool vec = q1_vector() && 2 * kx <= 32;
   launch_q1_prepare<T>(dctx, n, splitsH, st_);
-  launch_gemm_site<T, double, double>(GS_Q1_GRAM, reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH,
-                          [&](int tl) { return gemm_tiles(2 * kx, 2 * kx, tl); }, st_, tileH);
+  if (vec)
+    launch_q1_gram_v<T>(dctx, n, splitsH, st_);
+  else
+    launch_gemm_site<T, double, double>(GS_Q1_GRAM, reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH,
+                            [&](int tl) { return gemm_tiles(2 * kx, 2 * kx, tl); }, st_, tileH);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uH), reinterpret_cast<double**>(dv + uOut), n,
                        4 * kx * kx, st_);
   launch_q1_gamma<T>(dctx, n, st_);

@@ -236,6 +236,82 @@ __global__ __launch_bounds__(GT) void k_q1_select(Ctx1<T>* ctxs, TruncParams tp)
   (void)sU;
 }
 
+// The one-site inner Gram on the vector units, for 2 kappa <= 32.  FP64
+// vector arithmetic has the rate of the FP64 matrix cores on this chip, and
+// this product is small in both output dimensions (16 x 16 over chi^2
+// terms): on 32- or 64-wide MFMA tiles most waves would idle.
+constexpr int Q1_RC = 64;  // r (right-bond index) per LDS chunk
+
+// H[a][a'] = sum_l lambda_l^2 sum_r conj(B[l][a][r]) B[l][a'][r] (the Gram
+// the descriptor dH describes), one workgroup per item and l-range (split
+// `split` of `splits`); each split's partial goes where the GEMM's split-K
+// partials go (C + split sSplit, leading dimension ldc), so the same
+// reduction adds them up.  FP64 accumulation.
+template <typename T>
+__global__ __launch_bounds__(GT) void k_q1_gram_v(Ctx1<T>* ctxs, int splits) {
+  __shared__ cpx<double> X[32][Q1_RC + 1];
+  const Ctx1<T>& c = ctxs[blockIdx.x / splits];
+  const int split = blockIdx.x % splits;
+  const GemmDesc& d = *c.dH;
+  if (!d.active) return;
+  const int k2 = d.M, cl = *c.chil, cr = *c.chir;
+  const int lper = (cl + splits - 1) / splits, l0 = split * lper, l1 = min(cl, l0 + lper);
+  const int tid = threadIdx.x, np = k2 * k2;
+  constexpr int PPT = 32 * 32 / GT;  // (a, a') pairs per thread
+  double ar[PPT], ai[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) ar[p] = ai[p] = 0.0;
+  // the (l, r-chunk) tiles in order, each thread's entries of the next tile
+  // loaded while the current one is summed
+  const int nrc = (cr + Q1_RC - 1) / Q1_RC, ntile = (l1 - l0) * nrc;
+  constexpr int EPT = 32 * Q1_RC / GT;  // tile entries per thread
+  cpx<T> nx[EPT];
+  auto fetch = [&](int t) {
+    const int l = l0 + t / nrc, r0 = (t % nrc) * Q1_RC, rn = min(Q1_RC, cr - r0);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + u * GT, a = e / Q1_RC, r = e % Q1_RC;
+      nx[u] = (a < k2 && r < rn) ? c.Bold[((long long)l * k2 + a) * cr + r0 + r] : mk<T>((T)0, (T)0);
+    }
+  };
+  if (ntile > 0) fetch(0);
+  for (int t = 0; t < ntile; ++t) {
+    const int l = l0 + t / nrc, r0 = (t % nrc) * Q1_RC, rn = min(Q1_RC, cr - r0);
+    const double w = c.laml2[l];
+    {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * GT, a = e / Q1_RC, r = e % Q1_RC;
+        if (a < k2) X[a][r] = mk((double)nx[u].re, (double)nx[u].im);
+      }
+      __syncthreads();
+      if (t + 1 < ntile) fetch(t + 1);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        const int q = tid + p * GT;
+        if (q < np) {
+          const int a = q / k2, b = q % k2;
+          double sr = 0.0, si = 0.0;
+          for (int r = 0; r < rn; ++r) {
+            const cpx<double> x = X[a][r], y = X[b][r];
+            sr += x.re * y.re + x.im * y.im;  // conj(x) y
+            si += x.re * y.im - x.im * y.re;
+          }
+          ar[p] += w * sr;
+          ai[p] += w * si;
+        }
+      }
+    }
+  }
+  cpx<double>* C = reinterpret_cast<cpx<double>*>(d.C) + (long long)split * d.sSplit;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const int q = tid + p * GT;
+    if (q < np) C[(long long)(q / k2) * d.ldc + q % k2] = mk(ar[p], ai[p]);
+  }
+}
+
 // ============================================================================
 // two-site noisy gate
 // ============================================================================
@@ -1665,6 +1741,9 @@ template <typename T> void launch_q1_gamma(Ctx1<T>* d, int n, hipStream_t s) {
 template <typename T> void launch_q1_select(Ctx1<T>* d, int n, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q1_select<T>, dim3(n), dim3(GT), 0, s, d, tp);
 }
+template <typename T> void launch_q1_gram_v(Ctx1<T>* d, int n, int splits, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_q1_gram_v<T>, dim3(n * splits), dim3(GT), 0, s, d, splits);
+}
 template <typename T> void launch_q2_prepare(Ctx2<T>* d, int n, int splitsE, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsE);
 }
@@ -1685,9 +1764,12 @@ void launch_q2_chol_e(Ctx2<T>* d, int n, int maxn, int splitsH, TruncParams tp, 
 
 namespace {
 bool g_e_chol = true;
+bool g_q1_vec = true;
 }
 void set_e_cholesky(bool on) { g_e_chol = on; }
 bool e_cholesky() { return g_e_chol; }
+void set_q1_vector(bool on) { g_q1_vec = on; }
+bool q1_vector() { return g_q1_vec; }
 template <typename T> void launch_q2_gamma(Ctx2<T>* d, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_gamma<T>, dim3(n, 4), dim3(GT), 0, s, d);
 }
@@ -1765,6 +1847,7 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_q1_prepare<T>(Ctx1<T>*, int, int, hipStream_t);                        \
   template void launch_q1_gamma<T>(Ctx1<T>*, int, hipStream_t);                               \
   template void launch_q1_select<T>(Ctx1<T>*, int, TruncParams, hipStream_t);                 \
+  template void launch_q1_gram_v<T>(Ctx1<T>*, int, int, hipStream_t);                         \
   template void launch_q2_prepare<T>(Ctx2<T>*, int, int, hipStream_t);                        \
   template void launch_q2_select_e<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_chol_e<T>(Ctx2<T>*, int, int, int, TruncParams, const EigDesc*, hipStream_t); \

@@ -84,6 +84,31 @@ def test_batch_equals_plain_and_oracle(prec):
         assert float(np.abs(got - ref).max()) < tol, (b, float(np.abs(got - ref).max()))
 
 
+@pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
+def test_one_site_gram_on_vector_units_matches_gemm_route(prec):
+    """The one-site inner Gram runs on the vector units when 2 kappa_max <=
+    32 (kappa_max 4 and 16 here); the MFMA GEMM route gives the same
+    observables to rounding (the default route is compared with the oracle
+    in the other tests)."""
+    require_gpu()
+    import torch
+    progs, P, obs = _instances()
+    chans = [M.Channel(W.chi_1q_default(), 1), M.Channel(W.chi_2q_default(), 2)]
+    pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
+    out = {}
+    for vec in (True, False):
+        prev = M.q1_vector(vec)
+        try:
+            for kap in (4, 16):
+                kw = dict(chi_max=16, kappa_max=kap, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
+                out[(vec, kap)] = M.batch_run(progs, pdev, chans, obs, use_graph=True, **kw).cpu().numpy()
+        finally:
+            M.q1_vector(prev)
+    tol = 1e-12 if prec == M.C128 else 1e-5
+    for kap in (4, 16):
+        assert float(np.abs(out[(True, kap)] - out[(False, kap)]).max()) < tol, kap
+
+
 def test_batch_graph_is_deterministic():
     require_gpu()
     import torch
