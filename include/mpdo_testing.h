@@ -96,12 +96,14 @@ mpdo_status mpdo_test_eig_band(int32_t on, int32_t* previous);
  * the call.  EINVAL unless on is 0 or 1. */
 mpdo_status mpdo_test_eig_coop(int32_t on, int32_t* previous);
 
-/* The one-site update's inner Gram (Eq. (9): the lambda^2-weighted Gram of
- * the site tensor over its bond indices) on the vector units when
- * 2 kappa_max <= 32 (on = 1, the default) or on the MFMA GEMM kernel
- * (on = 0).  Same results up to rounding order.  Process-wide; *previous (may be NULL) receives the
- * setting before the call.  EINVAL unless on is 0 or 1. */
-mpdo_status mpdo_test_q1_vector(int32_t on, int32_t* previous);
+/* The inner-index Grams of the one- and two-site updates (Eq. (9): the
+ * lambda^2-weighted Gram of the site tensor, or of the two-site block in the
+ * right factor's basis, over its bond indices) on the vector units when
+ * their size 2 kappa_max, 4 kappa_max is at most 16 (on = 1, the default),
+ * or on the MFMA GEMM kernel (on = 0).  Same results up to rounding order.
+ * Process-wide; *previous (may be NULL) receives the setting before the
+ * call.  EINVAL unless on is 0 or 1. */
+mpdo_status mpdo_test_gram_vector(int32_t on, int32_t* previous);
 
 /* The basis of the two-site update's right factor (E = F F^H, n = 2 chi <=
  * 128): a pivoted Cholesky factorisation of E (on = 1, the default) or its

@@ -1068,10 +1068,10 @@ extern "C" mpdo_status mpdo_test_eig_band(int32_t on, int32_t* previous) {
   return MPDO_OK;
 }
 
-extern "C" mpdo_status mpdo_test_q1_vector(int32_t on, int32_t* previous) {
+extern "C" mpdo_status mpdo_test_gram_vector(int32_t on, int32_t* previous) {
   if (on != 0 && on != 1) return fail(MPDO_EINVAL, "on must be 0 or 1");
-  if (previous) *previous = q1_vector() ? 1 : 0;
-  set_q1_vector(on != 0);
+  if (previous) *previous = gram_vector() ? 1 : 0;
+  set_gram_vector(on != 0);
   return MPDO_OK;
 }
 

@@ -387,11 +387,11 @@ void Engine<T>::run_1q(const std::vector<const GateOp*>& ops, Upload& up, bool f
   Ctx1<T>* dctx = reinterpret_cast<Ctx1<T>*>(dv + uCtx);
   TruncParams tp{cfg_.chi_max, cfg_.kap_max, cfg_.svd_cut, cfg_.kap_cut, cfg_.tolE};
   if (tpo) tp = *tpo;
-  // 2 kappa <= 32: the Gram on the vector units
-  const bool vec = q1_vector() && 2 * kx <= 32;
+  // at most GV_ROWS rows: the Gram on the vector units
+  const bool vec = gram_vector() && 2 * kx <= GV_ROWS;
   launch_q1_prepare<T>(dctx, n, splitsH, st_);
   if (vec)
-    launch_q1_gram_v<T>(dctx, n, splitsH, st_);
+    launch_gram_v<T>(reinterpret_cast<GemmDesc*>(dv + uH), n, splitsH, st_);
   else
     launch_gemm_site<T, double, double>(GS_Q1_GRAM, reinterpret_cast<GemmDesc*>(dv + uH), n, 1, splitsH,
                             [&](int tl) { return gemm_tiles(2 * kx, 2 * kx, tl); }, st_, tileH);
@@ -562,8 +562,11 @@ template <typename T> void Engine<T>::run_2q(const std::vector<const GateOp*>& o
   }
   launch_gemm_site<T, T, T>(GS_Q2_THETA, reinterpret_cast<GemmDesc*>(dv + uTh), n, 1, 1,
                           [&](int tl) { return gemm_tiles((int)thetaN, 4 * cx, tl); }, st_, 64);
-  launch_gemm_site<T, double, double>(GS_Q2_GRAM_H, reinterpret_cast<GemmDesc*>(dv + uGramH), n, 1, splitsH,
-                          [&](int tl) { return gemm_tiles(4 * kx, 4 * kx, tl); }, st_, tileH);
+  if (gram_vector() && 4 * kx <= GV_ROWS)  // the inner Gram on the vector units
+    launch_gram_v<T>(reinterpret_cast<GemmDesc*>(dv + uGramH), n, splitsH, st_);
+  else
+    launch_gemm_site<T, double, double>(GS_Q2_GRAM_H, reinterpret_cast<GemmDesc*>(dv + uGramH), n, 1, splitsH,
+                            [&](int tl) { return gemm_tiles(4 * kx, 4 * kx, tl); }, st_, tileH);
   launch_reduce_splits(reinterpret_cast<GemmDesc*>(dv + uGramH), reinterpret_cast<double**>(dv + uOutsH), n,
                        16 * kx * kx, st_);
   launch_q2_gamma<T>(dctx, n, st_);

@@ -244,9 +244,9 @@ struct TruncParams {
 template <typename T> void launch_q1_prepare(Ctx1<T>* d_ctx, int n, int splitsH, hipStream_t s);
 template <typename T> void launch_q1_gamma(Ctx1<T>* d_ctx, int n, hipStream_t s);
 template <typename T> void launch_q1_select(Ctx1<T>* d_ctx, int n, TruncParams tp, hipStream_t s);
-// the one-site Gram on the vector units (split partials where the GEMM site
-// writes them), for 2 kappa_max <= 32
-template <typename T> void launch_q1_gram_v(Ctx1<T>* d_ctx, int n, int splits, hipStream_t s);
+// a weighted Gram (A = B, opA = OP_C, opB = OP_T, two-level K) with M = N <=
+// GV_MAX = 32 on the vector units, split partials where the GEMM writes them
+template <typename T> void launch_gram_v(const GemmDesc* d_descs, int n, int splits, hipStream_t s);
 
 template <typename T> void launch_q2_prepare(Ctx2<T>* d_ctx, int n, int splitsE, hipStream_t s);
 template <typename T> void launch_q2_select_e(Ctx2<T>* d_ctx, int n, int splitsH, TruncParams tp, hipStream_t s);
@@ -261,10 +261,13 @@ void launch_q2_chol_e(Ctx2<T>* d_ctx, int n, int maxn, int splitsH, TruncParams 
 // Process-wide choice of that route (default on).
 void set_e_cholesky(bool on);
 bool e_cholesky();
-// the one-site Gram on the vector units when 2 kappa_max <= 32 (default on)
-// rather than on the GEMM kernel
-void set_q1_vector(bool on);
-bool q1_vector();
+// the one- and two-site inner Grams on the vector units when their size
+// (2 kappa_max, 4 kappa_max) is at most GV_ROWS (default on) rather than on
+// the GEMM kernel: a 16 x 16 Gram fills a quarter of the 32 x 32 MFMA tile
+// (vector units faster on the C2 step); a 32 x 32 one fills it (MFMA faster)
+constexpr int GV_ROWS = 16;
+void set_gram_vector(bool on);
+bool gram_vector();
 template <typename T> void launch_q2_gamma(Ctx2<T>* d_ctx, int n, hipStream_t s);
 template <typename T> void launch_q2_select_g(Ctx2<T>* d_ctx, int n, int splitsC, TruncParams tp, hipStream_t s);
 template <typename T> void launch_q2_select_b(Ctx2<T>* d_ctx, int n, TruncParams tp, hipStream_t s);

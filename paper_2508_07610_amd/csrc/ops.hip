@@ -236,71 +236,77 @@ __global__ __launch_bounds__(GT) void k_q1_select(Ctx1<T>* ctxs, TruncParams tp)
   (void)sU;
 }
 
-// The one-site inner Gram on the vector units, for 2 kappa <= 32.  FP64
+// Weighted Grams with a small output on the vector units: C = op(A)^H W op(A)
+// with M = N <= 32 over a long two-level K (the one-site inner Gram, 2 kappa
+// rows over (l, r); the two-site one, 4 kappa rows over (l, beta)).  FP64
 // vector arithmetic has the rate of the FP64 matrix cores on this chip, and
-// this product is small in both output dimensions (16 x 16 over chi^2
-// terms): on 32- or 64-wide MFMA tiles most waves would idle.
-constexpr int Q1_RC = 64;  // r (right-bond index) per LDS chunk
+// such an output leaves most waves of a 32- or 64-wide MFMA tile idle.
+constexpr int GV_RC = 64;  // inner K index per LDS tile
+constexpr int GV_MAX = 32; // largest M
 
-// H[a][a'] = sum_l lambda_l^2 sum_r conj(B[l][a][r]) B[l][a'][r] (the Gram
-// the descriptor dH describes), one workgroup per item and l-range (split
-// `split` of `splits`); each split's partial goes where the GEMM's split-K
-// partials go (C + split sSplit, leading dimension ldc), so the same
-// reduction adds them up.  FP64 accumulation.
+// The Gram a descriptor of the form A = B, opA = OP_C, opB = OP_T, K = L
+// kinner, weights w[k / wdiv] with wdiv a multiple of kinner (constant over
+// the inner index) describes: C[a][a'] = sum_k w conj(A(a, k)) A(a', k) with
+// A(a, k) at (k / kinner) kstride + a lda + k % kinner.  One
+// workgroup per item and range of the outer K index (split `split` of
+// `splits`); each split's partial goes where the GEMM's split-K partials go
+// (C + split sSplit, leading dimension ldc), so the same reduction adds them
+// up.  FP64 accumulation; the tiles of the range in order, each thread's
+// entries of the next tile loaded while the current one is summed.
 template <typename T>
-__global__ __launch_bounds__(GT) void k_q1_gram_v(Ctx1<T>* ctxs, int splits) {
-  __shared__ cpx<double> X[32][Q1_RC + 1];
-  const Ctx1<T>& c = ctxs[blockIdx.x / splits];
+__global__ __launch_bounds__(GT) void k_gram_v(const GemmDesc* __restrict__ descs, int splits) {
+  __shared__ cpx<double> X[GV_MAX][GV_RC + 1];
+  const GemmDesc& d = descs[blockIdx.x / splits];
   const int split = blockIdx.x % splits;
-  const GemmDesc& d = *c.dH;
   if (!d.active) return;
-  const int k2 = d.M, cl = *c.chil, cr = *c.chir;
-  const int lper = (cl + splits - 1) / splits, l0 = split * lper, l1 = min(cl, l0 + lper);
-  const int tid = threadIdx.x, np = k2 * k2;
-  constexpr int PPT = 32 * 32 / GT;  // (a, a') pairs per thread
+  const int m = d.M, kin = d.kinner > 0 ? d.kinner : d.K;
+  const int L = kin > 0 ? d.K / kin : 0;
+  const int lper = (L + splits - 1) / splits, l0 = split * lper, l1 = min(L, l0 + lper);
+  const long long kst = d.kinner > 0 ? d.kstride : 0;
+  const cpx<T>* A = reinterpret_cast<const cpx<T>*>(d.A);
+  const double* w = reinterpret_cast<const double*>(d.w);
+  const int wdiv = d.wdiv > 0 ? d.wdiv : 1;
+  const int tid = threadIdx.x, np = m * m;
+  constexpr int PPT = GV_MAX * GV_MAX / GT;  // (a, a') pairs per thread
   double ar[PPT], ai[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) ar[p] = ai[p] = 0.0;
-  // the (l, r-chunk) tiles in order, each thread's entries of the next tile
-  // loaded while the current one is summed
-  const int nrc = (cr + Q1_RC - 1) / Q1_RC, ntile = (l1 - l0) * nrc;
-  constexpr int EPT = 32 * Q1_RC / GT;  // tile entries per thread
+  const int nrc = (kin + GV_RC - 1) / GV_RC, ntile = (l1 - l0) * nrc;
+  constexpr int EPT = GV_MAX * GV_RC / GT;  // tile entries per thread
   cpx<T> nx[EPT];
   auto fetch = [&](int t) {
-    const int l = l0 + t / nrc, r0 = (t % nrc) * Q1_RC, rn = min(Q1_RC, cr - r0);
+    const int l = l0 + t / nrc, r0 = (t % nrc) * GV_RC, rn = min(GV_RC, kin - r0);
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      const int e = tid + u * GT, a = e / Q1_RC, r = e % Q1_RC;
-      nx[u] = (a < k2 && r < rn) ? c.Bold[((long long)l * k2 + a) * cr + r0 + r] : mk<T>((T)0, (T)0);
+      const int e = tid + u * GT, a = e / GV_RC, r = e % GV_RC;
+      nx[u] = (a < m && r < rn) ? A[(long long)l * kst + (long long)a * d.lda + r0 + r] : mk<T>((T)0, (T)0);
     }
   };
   if (ntile > 0) fetch(0);
   for (int t = 0; t < ntile; ++t) {
-    const int l = l0 + t / nrc, r0 = (t % nrc) * Q1_RC, rn = min(Q1_RC, cr - r0);
-    const double w = c.laml2[l];
-    {
-      __syncthreads();
+    const int l = l0 + t / nrc, r0 = (t % nrc) * GV_RC, rn = min(GV_RC, kin - r0);
+    __syncthreads();
 #pragma unroll
-      for (int u = 0; u < EPT; ++u) {
-        const int e = tid + u * GT, a = e / Q1_RC, r = e % Q1_RC;
-        if (a < k2) X[a][r] = mk((double)nx[u].re, (double)nx[u].im);
-      }
-      __syncthreads();
-      if (t + 1 < ntile) fetch(t + 1);
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + u * GT, a = e / GV_RC, r = e % GV_RC;
+      if (a < m) X[a][r] = mk((double)nx[u].re, (double)nx[u].im);
+    }
+    __syncthreads();
+    if (t + 1 < ntile) fetch(t + 1);
+    const double wt = w ? w[(long long)l * kin / wdiv] : 1.0;  // the tile's weight
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        const int q = tid + p * GT;
-        if (q < np) {
-          const int a = q / k2, b = q % k2;
-          double sr = 0.0, si = 0.0;
-          for (int r = 0; r < rn; ++r) {
-            const cpx<double> x = X[a][r], y = X[b][r];
-            sr += x.re * y.re + x.im * y.im;  // conj(x) y
-            si += x.re * y.im - x.im * y.re;
-          }
-          ar[p] += w * sr;
-          ai[p] += w * si;
+    for (int p = 0; p < PPT; ++p) {
+      const int q = tid + p * GT;
+      if (q < np) {
+        const int a = q / m, b = q % m;
+        double sr = 0.0, si = 0.0;
+        for (int r = 0; r < rn; ++r) {
+          const cpx<double> x = X[a][r], y = X[b][r];
+          sr += x.re * y.re + x.im * y.im;  // conj(x) y
+          si += x.re * y.im - x.im * y.re;
         }
+        ar[p] += wt * sr;
+        ai[p] += wt * si;
       }
     }
   }
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(GT) void k_q1_gram_v(Ctx1<T>* ctxs, int splits) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const int q = tid + p * GT;
-    if (q < np) C[(long long)(q / k2) * d.ldc + q % k2] = mk(ar[p], ai[p]);
+    if (q < np) C[(long long)(q / m) * d.ldc + q % m] = mk(ar[p], ai[p]);
   }
 }
 
@@ -1741,8 +1747,8 @@ template <typename T> void launch_q1_gamma(Ctx1<T>* d, int n, hipStream_t s) {
 template <typename T> void launch_q1_select(Ctx1<T>* d, int n, TruncParams tp, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q1_select<T>, dim3(n), dim3(GT), 0, s, d, tp);
 }
-template <typename T> void launch_q1_gram_v(Ctx1<T>* d, int n, int splits, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_q1_gram_v<T>, dim3(n * splits), dim3(GT), 0, s, d, splits);
+template <typename T> void launch_gram_v(const GemmDesc* d, int n, int splits, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gram_v<T>, dim3(n * splits), dim3(GT), 0, s, d, splits);
 }
 template <typename T> void launch_q2_prepare(Ctx2<T>* d, int n, int splitsE, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_prepare<T>, dim3(n), dim3(GT), 0, s, d, splitsE);
@@ -1764,12 +1770,12 @@ void launch_q2_chol_e(Ctx2<T>* d, int n, int maxn, int splitsH, TruncParams tp, 
 
 namespace {
 bool g_e_chol = true;
-bool g_q1_vec = true;
+bool g_gram_vec = true;
 }
 void set_e_cholesky(bool on) { g_e_chol = on; }
 bool e_cholesky() { return g_e_chol; }
-void set_q1_vector(bool on) { g_q1_vec = on; }
-bool q1_vector() { return g_q1_vec; }
+void set_gram_vector(bool on) { g_gram_vec = on; }
+bool gram_vector() { return g_gram_vec; }
 template <typename T> void launch_q2_gamma(Ctx2<T>* d, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_q2_gamma<T>, dim3(n, 4), dim3(GT), 0, s, d);
 }
@@ -1847,7 +1853,7 @@ template <typename T> void launch_copy_site(const cpx<T>* src, cpx<T>* dst, long
   template void launch_q1_prepare<T>(Ctx1<T>*, int, int, hipStream_t);                        \
   template void launch_q1_gamma<T>(Ctx1<T>*, int, hipStream_t);                               \
   template void launch_q1_select<T>(Ctx1<T>*, int, TruncParams, hipStream_t);                 \
-  template void launch_q1_gram_v<T>(Ctx1<T>*, int, int, hipStream_t);                         \
+  template void launch_gram_v<T>(const GemmDesc*, int, int, hipStream_t);                     \
   template void launch_q2_prepare<T>(Ctx2<T>*, int, int, hipStream_t);                        \
   template void launch_q2_select_e<T>(Ctx2<T>*, int, int, TruncParams, hipStream_t);          \
   template void launch_q2_chol_e<T>(Ctx2<T>*, int, int, int, TruncParams, const EigDesc*, hipStream_t); \

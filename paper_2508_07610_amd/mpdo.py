@@ -569,8 +569,8 @@ def _testing_lib():
         L.mpdo_test_eig_band.restype = ctypes.c_int
         L.mpdo_test_eig_coop.argtypes = [i32, ctypes.POINTER(i32)]
         L.mpdo_test_eig_coop.restype = ctypes.c_int
-        L.mpdo_test_q1_vector.argtypes = [i32, ctypes.POINTER(i32)]
-        L.mpdo_test_q1_vector.restype = ctypes.c_int
+        L.mpdo_test_gram_vector.argtypes = [i32, ctypes.POINTER(i32)]
+        L.mpdo_test_gram_vector.restype = ctypes.c_int
         L._testing_sig = True
     return L
 
@@ -629,12 +629,12 @@ def eig_coop(on: bool) -> bool:
     return bool(prev.value)
 
 
-def q1_vector(on: bool) -> bool:
-    """Run the one-site update's inner Gram on the vector units when
-    2 kappa_max <= 32 (True, the default) or on the MFMA GEMM kernel (False);
-    returns the previous setting."""
+def gram_vector(on: bool) -> bool:
+    """Run the one- and two-site inner Grams on the vector units when their
+    size (2 kappa_max, 4 kappa_max) is at most 16 (True, the default) or on
+    the MFMA GEMM kernel (False); returns the previous setting."""
     prev = ctypes.c_int32()
-    check(_testing_lib().mpdo_test_q1_vector(1 if on else 0, ctypes.byref(prev)))
+    check(_testing_lib().mpdo_test_gram_vector(1 if on else 0, ctypes.byref(prev)))
     return bool(prev.value)
 
 

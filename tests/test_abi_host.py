@@ -147,8 +147,8 @@ def test_eigensolver_switches_validate_and_restore():
     assert L.mpdo_test_eig_coop(1, ctypes.byref(prev)) == M.OK and prev.value == 0
     assert M.eig_coop(True) is True
     assert L.mpdo_test_eig_band(-1, None) == M.EINVAL
-    assert L.mpdo_test_q1_vector(3, None) == M.EINVAL
-    assert M.q1_vector(True) is True  # on by default
+    assert L.mpdo_test_gram_vector(3, None) == M.EINVAL
+    assert M.gram_vector(True) is True  # on by default
 
 
 def test_profile_read_rejects_unknown_class():

@@ -85,11 +85,12 @@ def test_batch_equals_plain_and_oracle(prec):
 
 
 @pytest.mark.parametrize("prec", [M.C128, M.C64_MIXED])
-def test_one_site_gram_on_vector_units_matches_gemm_route(prec):
-    """The one-site inner Gram runs on the vector units when 2 kappa_max <=
-    32 (kappa_max 4 and 16 here); the MFMA GEMM route gives the same
-    observables to rounding (the default route is compared with the oracle
-    in the other tests)."""
+def test_inner_grams_on_vector_units_match_gemm_route(prec):
+    """The one- and two-site inner Grams run on the vector units when their
+    size (2 kappa_max, 4 kappa_max) is at most 16 (kappa_max 4: both; 8: the
+    one-site Gram only); the MFMA GEMM route gives the same observables to
+    rounding (the default route is compared with the oracle in the other
+    tests)."""
     require_gpu()
     import torch
     progs, P, obs = _instances()
@@ -97,15 +98,15 @@ def test_one_site_gram_on_vector_units_matches_gemm_route(prec):
     pdev = torch.tensor(P, dtype=torch.float64, device="cuda")
     out = {}
     for vec in (True, False):
-        prev = M.q1_vector(vec)
+        prev = M.gram_vector(vec)
         try:
-            for kap in (4, 16):
+            for kap in (4, 8):
                 kw = dict(chi_max=16, kappa_max=kap, max_kraus=16, svd_cutoff=1e-10, kappa_cutoff=1e-10, prec=prec)
                 out[(vec, kap)] = M.batch_run(progs, pdev, chans, obs, use_graph=True, **kw).cpu().numpy()
         finally:
-            M.q1_vector(prev)
+            M.gram_vector(prev)
     tol = 1e-12 if prec == M.C128 else 1e-5
-    for kap in (4, 16):
+    for kap in (4, 8):
         assert float(np.abs(out[(True, kap)] - out[(False, kap)]).max()) < tol, kap
 
 
